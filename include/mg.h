@@ -1,0 +1,227 @@
+/*
+ * mg.h - C ABI of a matrix-free geometric-multigrid solver for periodic 3-D
+ * Poisson problems on one AMD Instinct MI355X (gfx950).
+ *
+ * Problems solved (paper: "Fast(er)PM and Moving Mesh: JAX-native Geometric
+ * Multigrid Methods"):
+ *   - the periodic particle-mesh Poisson equation discretised with the
+ *     second-order seven-point Laplacian, M phi = b (Sec. 2.1, eqs. poisson
+ *     and linsys; Sec. 2.3);
+ *   - the moving mesh's variable-coefficient operator in flux form,
+ *     M phi = div(C grad phi) = b with a symmetric positive-definite 3x3
+ *     coefficient C per cell (Sec. 4.3, eq. LB; Sec. 4.3.1).  C is the
+ *     paper's sqrt(g) g^{ab}; its 19-point discretisation averages the
+ *     diagonal coefficients onto faces and the tangential fluxes
+ *     C^{ab} D0_b phi onto faces, which keeps M symmetric and negative
+ *     semidefinite with the constants as null space.
+ *
+ * Method (Sec. 2.3, Fig. 1; Sec. 3.1; Sec. 3.4): V-cycles with
+ * degree-v Chebyshev-accelerated Jacobi smoothing on the interval
+ * [lmax/alpha, lmax] of D^-1 M (eq. flat_chebyshev; lmax = 2 for the
+ * seven-point operator, a Gershgorin bound per level otherwise, App. C eq.
+ * gersh), full-weighting restriction, trilinear prolongation and an exact
+ * coarsest-level solve; outer defect correction r = b - M phi, phi += V(r)
+ * warm-started from the caller's phi (Sec. 3.1, eq. kwarm).  In
+ * MG_MIXED precision the V-cycle runs in float while the outer residual, the
+ * update of phi and the coarsest solve run in double.
+ *
+ * Conventions shared by every entry point
+ *   - A field is n*n*n contiguous values indexed [z][y][x] (x fastest),
+ *     box length n*h, periodic in all three directions.
+ *   - Every field pointer is DEVICE memory owned by the caller (for example
+ *     a torch tensor), aligned to at least 16 bytes.  phi, b, lam and phibar
+ *     are double.  The library never frees caller memory.
+ *   - A coefficient field is 6 consecutive fields in the order
+ *     (xx, yy, zz, xy, xz, yz), float or double as its dtype argument says.
+ *   - All device work is ordered on the context's stream (hipStream_t passed
+ *     as void*, NULL = the legacy default stream).  Entry points that return
+ *     residual norms or status information synchronise that stream.
+ *   - No exception crosses the ABI.  Every call returns an mg_status; on an
+ *     error the context (if any) keeps a message for mg_last_error().
+ *   - A context is not thread safe; distinct contexts are independent.
+ */
+#ifndef MG_H
+#define MG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mg_status {
+    MG_OK = 0,
+    MG_ERR_INVALID = 1,        /* bad argument (sizes, levels, degree, null pointer, mode) */
+    MG_ERR_INVALID_COEFF = 2,  /* coefficient field not finite or with C^{aa} <= 0 */
+    MG_ERR_NOMEM = 3,          /* device allocation failed */
+    MG_ERR_HIP = 4,            /* a HIP runtime call failed */
+    MG_ERR_NONFINITE = 5,      /* NaN/Inf met in b, phi or a residual norm */
+    MG_ERR_NOT_CONVERGED = 6   /* tolerance not reached in max_cycles; outputs valid */
+} mg_status;
+
+enum mg_precision {
+    MG_FP64 = 0,   /* every step in double */
+    MG_MIXED = 1,  /* V-cycle in float; outer residual, phi update, coarsest solve in double */
+    MG_FP32 = 2    /* V-cycle and outer residual in float (phi is stored back as double) */
+};
+
+enum mg_smoother {
+    MG_CHEBYSHEV = 0,  /* degree-v Chebyshev acceleration of Jacobi (eq. flat_chebyshev) */
+    MG_JACOBI = 1      /* weighted Jacobi, omega and sweeps from mg_params (eq. flat_jacobi) */
+};
+
+enum mg_dtype {
+    MG_DTYPE_F32 = 0,
+    MG_DTYPE_F64 = 1
+};
+
+typedef struct mg_params {
+    int n;               /* points per side, power of two, 8 <= n <= 2048 */
+    int levels;          /* >= 1; the coarsest level has n >> (levels-1) >= 4 points per side */
+    int cheb_degree;     /* 1..8: operator applications per smoothing pass */
+    double cheb_alpha;   /* > 1: spectral interval [lmax/alpha, lmax] (paper: alpha ~ 8) */
+    double h;            /* fine-grid spacing > 0 (box length 1 <=> h = 1/n) */
+    int precision;       /* enum mg_precision */
+    int smoother;        /* enum mg_smoother */
+    double jacobi_omega; /* weighted-Jacobi factor (paper: 2/3) */
+    int jacobi_sweeps;   /* weighted-Jacobi sweeps per smoothing pass (paper: 2) */
+} mg_params;
+
+typedef struct mg_solve_info {
+    int cycles;          /* V-cycles (outer iterations) executed */
+    double rel_res0;     /* ||b - M phi0|| / ||b|| after projecting the mean out of b */
+    double rel_res;      /* final relative residual */
+    double* history;     /* optional HOST buffer: rel. residual before cycle 1, after each cycle */
+    int history_cap;     /* capacity of history; entries written = min(cycles + 1, cap) */
+} mg_solve_info;
+
+typedef struct mg_ctx mg_ctx;
+
+/* Fill *p with defaults for an n^3 grid: levels = log2(n) - 1 (coarsest 4^3,
+ * Sec. 4.3.3), degree 3, alpha 8, h = 1/n, MG_MIXED, Chebyshev, omega 2/3,
+ * 2 sweeps.  Host only. */
+mg_status mg_params_default(mg_params* p, int n);
+
+/* Check *p against the rules above without touching any device.  Returns
+ * MG_OK or MG_ERR_INVALID.  Host only. */
+mg_status mg_validate_params(const mg_params* p);
+
+/* Create a solver context (Sec. 2.3: hierarchy of spacings h, 2h, 4h, ...).
+ * coeff: NULL selects the constant-coefficient seven-point Laplacian;
+ * otherwise a device pointer to 6 n^3 fields (xx, yy, zz, xy, xz, yz) of dtype
+ * coeff_dtype, COPIED into the context (the caller may free it on return).
+ * Coarse-level coefficients are the componentwise full-weighting restriction
+ * of the fine ones (App. B restricts the geometry to every level).  The
+ * coarsest level of a variable-coefficient context may have at most 8^3
+ * points (it is solved with a dense pseudo-inverse).  stream: hipStream_t or
+ * NULL.  On success *out owns its device memory until mg_destroy.
+ * Errors: MG_ERR_INVALID (parameters), MG_ERR_INVALID_COEFF (coefficients not
+ * finite or a diagonal component <= 0), MG_ERR_NOMEM, MG_ERR_HIP. */
+mg_status mg_create(const mg_params* p, const void* coeff, int coeff_dtype,
+                    void* stream, mg_ctx** out);
+
+/* Free everything the context owns.  NULL is accepted. */
+mg_status mg_destroy(mg_ctx* ctx);
+
+/* Order all later work of the context on stream (hipStream_t, may be NULL). */
+mg_status mg_set_stream(mg_ctx* ctx, void* stream);
+
+/* One outer iteration in place: phi <- phi + V(b - M phi), the V-cycle of
+ * Sec. 2.3 applied to the defect (Sec. 3.1 defect correction).  b's mean is
+ * projected out first.  If rel_res_out is not NULL it receives
+ * ||b - M phi_new|| / ||b|| (host pointer; the call then synchronises).
+ * phi keeps whatever mean it had. */
+mg_status mg_vcycle(mg_ctx* ctx, double* phi, const double* b, double* rel_res_out);
+
+/* Solve M phi = b (Sec. 2.1, 2.3; warm start Sec. 3.1): project the mean out
+ * of b, start from phi (initial guess, e.g. the previous step's solution),
+ * test ||b - M phi|| / ||b|| <= tol before each cycle, run at most max_cycles
+ * cycles, then remove the mean of phi (gauge).  phi is overwritten with the
+ * solution.  If b is zero after projection, phi = 0 and rel_res = 0.
+ * The loop also stops when the residual has failed to decrease by 0.1% over
+ * two consecutive cycles (stagnation at the rounding floor of the precision).
+ * info may be NULL.  Returns MG_ERR_NOT_CONVERGED (phi still valid) when the
+ * tolerance is not reached, MG_ERR_NONFINITE on NaN/Inf.  Synchronises the
+ * stream once per cycle (one 8-byte norm read back). */
+mg_status mg_solve(mg_ctx* ctx, double* phi, const double* b, double tol,
+                   int max_cycles, mg_solve_info* info);
+
+/* Adjoint solve lam = M^+ phibar (Sec. 4.6, eq. adj_rhs): M is symmetric, so
+ * this is the forward machinery on the cotangent; lam holds the initial
+ * guess on entry and the zero-mean result on return.  With the paper's
+ * weighted operator A = W^-1 M (eq. curv_operator) and b = sqrt(g) f, the
+ * source cotangent is fbar = sqrt(g) * lam.  Same errors as mg_solve. */
+mg_status mg_solve_adjoint(mg_ctx* ctx, double* lam, const double* phibar,
+                           double tol, int max_cycles, mg_solve_info* info);
+
+/* Operator VJP at a converged solution (Sec. 4.6, eq. adj_op): overwrite cbar
+ * (device, 6 n^3 fields of dtype cbar_dtype) with dL/dC = -d(lam^T M(C) phi)/dC
+ * for L with dL/db = lam.  Diagonal components: mean over the two a-faces of
+ * (D+_a lam)(D+_a phi); off-diagonal (a,b): D0_a lam D0_b phi + D0_b lam D0_a phi
+ * (the stored component carries both (a,b) and (b,a)).  lam and phi are double
+ * device fields.  MG_ERR_INVALID for a seven-point (coeff == NULL) context. */
+mg_status mg_coeff_grad(mg_ctx* ctx, const double* lam, const double* phi,
+                        void* cbar, int cbar_dtype);
+
+/* Moving-mesh geometry (Sec. 4.2, eqs. map, triad, metric): from the
+ * deformation potential psi (device double n^3) compute the triad
+ * J = I + Hess psi with second-order central stencils, sqrt(g) = det J and
+ * C = det(J) J^-1 J^-T.  C_out: device, 6 n^3 fields of dtype (float or
+ * double); sqrtg_out: device double n^3 (may be NULL).  n power of two >= 4. */
+mg_status mg_geometry(int n, double h, const double* psi, void* C_out, int dtype,
+                      double* sqrtg_out, void* stream);
+
+/* Reverse mode of mg_geometry: psibar = (dC/dpsi)^T Cbar + (dsqrtg/dpsi)^T sqrtgbar.
+ * Cbar: device double 6 n^3 with the symmetric storage convention of
+ * mg_coeff_grad; sqrtgbar: device double n^3 or NULL (treated as zero);
+ * psibar: device double n^3, overwritten.  Allocates a temporary of 6 n^3
+ * doubles. */
+mg_status mg_geometry_bwd(int n, double h, const double* psi, const double* Cbar,
+                          const double* sqrtgbar, double* psibar, void* stream);
+
+/* ---- single steps of the V-cycle, for testing and composition ------------
+ * These act on caller double fields at level `level` of the context's
+ * hierarchy (level 0 = fine, n >> level points per side) with the context's
+ * operator, in double arithmetic.  They do not touch the context's solve
+ * state. */
+
+/* out = M_level u. */
+mg_status mg_apply(mg_ctx* ctx, int level, const double* u, double* out);
+
+/* One smoothing pass in place on level `level` (pre- and post-smoothing use
+ * the same pass): x <- S(x, b), Chebyshev of the context's degree or weighted
+ * Jacobi. */
+mg_status mg_smooth(mg_ctx* ctx, int level, double* x, const double* b);
+
+/* coarse = R(b - M_level x): residual and full-weighting restriction to
+ * level + 1.  x may be NULL (treated as zero: coarse = R b). */
+mg_status mg_residual_restrict(mg_ctx* ctx, int level, const double* x,
+                               const double* b, double* coarse);
+
+/* x += P e: trilinear prolongation from level + 1 to level, added to x. */
+mg_status mg_prolong_add(mg_ctx* ctx, int level, const double* e, double* x);
+
+/* e = zero-mean exact solution of M_c e = r - mean(r) on the coarsest level. */
+mg_status mg_coarse_solve(mg_ctx* ctx, const double* r, double* e);
+
+/* Gershgorin bound lmax of D^-1 M on each level (host array of `levels`
+ * doubles; 2 for the seven-point operator). */
+mg_status mg_level_lmax(const mg_ctx* ctx, double* lmax_out);
+
+/* ---- timing of the dominant kernel ---------------------------------------
+ * When enabled, every launch of the fine-level smoothing-step kernel inside
+ * mg_solve / mg_vcycle is bracketed by HIP events on the context's stream.
+ * mg_kernel_timing returns, since the previous call: the number of such
+ * launches, their summed duration in milliseconds and their summed
+ * algorithmic HBM bytes (every field element the launch reads or writes
+ * counted once: iterate, previous iterate, right-hand side, output and the
+ * six coefficient fields of a variable-coefficient operator).  It
+ * synchronises the stream.  Disabled by default. */
+mg_status mg_enable_kernel_timing(mg_ctx* ctx, int enable);
+mg_status mg_kernel_timing(mg_ctx* ctx, int* launches, double* total_ms, double* alg_bytes);
+
+const char* mg_status_string(mg_status s);
+const char* mg_last_error(const mg_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MG_H */

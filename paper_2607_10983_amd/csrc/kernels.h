@@ -1,0 +1,116 @@
+// Internal launch interface between the host orchestration (mg_api.cpp) and
+// the gfx950 kernels (kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+
+namespace mg {
+
+// Operator of one level: constant-coefficient seven-point Laplacian when
+// coeff == nullptr, otherwise the 19-point flux-form operator whose six
+// coefficient fields start at coeff (stride n^3 elements).
+template <typename TC>
+struct OpDesc {
+    int n;
+    double ih2;          // 1 / h^2 of this level
+    const TC* coeff;     // nullptr for the seven-point operator
+};
+
+// Number of thread blocks a stencil launch over an n^3 grid uses; partial
+// sums buffers must hold at least this many doubles.
+int stencil_blocks(int n);
+
+// ---- smoothing (Chebyshev / Jacobi step) ---------------------------------
+// out = x + a (x - xprev) + c D^-1 (b - M x)      (xprev == nullptr: xprev = 0;
+//                                                  x == nullptr: x = 0)
+// out may alias xprev but not x or b.
+template <typename T, typename TC>
+hipError_t launch_smooth_step(const OpDesc<TC>& op, const T* x, const T* xprev, const T* b,
+                              T* out, double a, double c, hipStream_t s);
+
+// ---- residual + full-weighting restriction ---------------------------------
+// coarse = R(b - M x) on the (n/2)^3 grid; x == nullptr means x = 0.
+template <typename T, typename TC>
+hipError_t launch_residual_restrict(const OpDesc<TC>& op, const T* x, const T* b, T* coarse,
+                                    hipStream_t s);
+
+// coarse = R(fine), componentwise for `ncomp` consecutive fields.
+template <typename T>
+hipError_t launch_restrict(int n, const T* fine, T* coarse, int ncomp, hipStream_t s);
+
+// ---- prolongation ------------------------------------------------------------
+// x (n^3) += P e ((n/2)^3), trilinear.
+template <typename T>
+hipError_t launch_prolong_add(int n, const T* e, T* x, hipStream_t s);
+
+// ---- operator application ----------------------------------------------------
+template <typename T, typename TC>
+hipError_t launch_apply(const OpDesc<TC>& op, const T* u, T* out, hipStream_t s);
+
+// ---- outer defect correction (double or float arithmetic TA) -----------------
+// If e != nullptr: phi_out = phi_in + e, else phi_out unused (may be nullptr)
+// and phi is phi_in.  r = (b - bmean) - M phi written as TR; per-block sums of
+// r^2 (in double) written to partials[block].  phi_out must not alias phi_in.
+template <typename TA, typename TR, typename TE, typename TC>
+hipError_t launch_outer_residual(const OpDesc<TC>& op, const double* phi_in, const TE* e,
+                                 double* phi_out, const double* b, double bmean, TR* r,
+                                 double* partials, hipStream_t s);
+
+// ---- reductions ----------------------------------------------------------------
+// partials[block] = sum over the block of (u - shift)^p, p in {1, 2}.
+hipError_t launch_block_sums(int n, const double* u, double shift, int p, double* partials,
+                             hipStream_t s);
+// out[slot] = sum_{i < count} partials[i] in a fixed order (one block).
+hipError_t launch_finalize_sum(const double* partials, int count, double* out, int slot,
+                               hipStream_t s);
+// out[slot] = max_{i < count} partials[i].
+hipError_t launch_finalize_max(const double* partials, int count, double* out, int slot,
+                               hipStream_t s);
+
+// ---- elementwise -----------------------------------------------------------------
+// dst = src - shift (double, may alias)
+hipError_t launch_shift(size_t count, const double* src, double shift, double* dst, hipStream_t s);
+// dst = src + e (double += T)
+template <typename T>
+hipError_t launch_add(size_t count, const double* src, const T* e, double* dst, hipStream_t s);
+template <typename TD, typename TS>
+hipError_t launch_convert(size_t count, const TS* src, TD* dst, hipStream_t s);
+template <typename T>
+hipError_t launch_fill(size_t count, T value, T* dst, hipStream_t s);
+
+// ---- coefficient hierarchy -------------------------------------------------------
+// partials[block] = max over the block of the Gershgorin bound of D^-1 M.
+template <typename TC>
+hipError_t launch_gershgorin(const OpDesc<TC>& op, double* partials, hipStream_t s);
+// partials[block] = number of cells with a non-finite component or C^{aa} <= 0.
+template <typename TC>
+hipError_t launch_coeff_check(int n, const TC* coeff, double* partials, hipStream_t s);
+
+// ---- coarsest level ----------------------------------------------------------------
+// Seven-point operator: e = Q diag(1/lambda) Q^T r with the separable real
+// Fourier basis Q (nc x nc, column-major basis vectors) and eigenvalues
+// lam1[nc] per axis (lambda = lam1[kx] + lam1[ky] + lam1[kz], the zero mode
+// dropped).  nc <= 16.  One block.
+template <typename T>
+hipError_t launch_coarse_flat(int nc, const double* Q, const double* lam1, const T* r, T* e,
+                              hipStream_t s);
+// Variable coefficients: e = G r with the dense symmetric pseudo-inverse G
+// (N x N, N = nc^3 <= 512).
+template <typename T>
+hipError_t launch_coarse_dense(int N, const double* G, const T* r, T* e, hipStream_t s);
+
+// ---- gradients and geometry ---------------------------------------------------------
+template <typename TO>
+hipError_t launch_coeff_grad(int n, double ih2, const double* lam, const double* phi, TO* cbar,
+                             hipStream_t s);
+template <typename TO>
+hipError_t launch_geometry(int n, double ih2, const double* psi, TO* C, double* sqrtg,
+                           hipStream_t s);
+// Jbar (6 n^3 doubles, symmetric storage: off-diagonal = Jbar_ab + Jbar_ba)
+hipError_t launch_geometry_bwd_cell(int n, double ih2, const double* psi, const double* Cbar,
+                                    const double* sqrtgbar, double* Jbar, hipStream_t s);
+// psibar = sum_ab Hess_ab(Jbar_ab)
+hipError_t launch_hessian_adjoint(int n, double ih2, const double* Jbar, double* psibar,
+                                  hipStream_t s);
+
+}  // namespace mg

@@ -1,0 +1,954 @@
+// gfx950 kernels of the matrix-free multigrid V-cycle.
+//
+// Every stencil kernel streams a periodic n^3 field (x fastest) with one
+// thread per (x, y) column marching `nz` planes in z; wave64 rows run along
+// the contiguous x axis so loads and stores are coalesced, and neighbour
+// values are served from the vector L1 / L2 caches.  Reductions are
+// per-block LDS trees in a fixed order followed by a single-block pass over
+// the partials, so every result is bitwise reproducible run to run.
+#include "kernels.h"
+
+#include <cmath>
+#include <cstdint>
+
+namespace mg {
+namespace {
+
+constexpr int kThreads = 256;
+
+struct Grid {
+    int n, mask;
+    __device__ __forceinline__ size_t operator()(int x, int y, int z) const {
+        return ((size_t)(z & mask) * (size_t)n + (size_t)(y & mask)) * (size_t)n + (size_t)(x & mask);
+    }
+};
+
+__device__ __forceinline__ int lin_tid() {
+    return threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+}
+__device__ __forceinline__ int lin_bid() {
+    return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+}
+
+// Fixed-order LDS tree over a power-of-two block; result valid in every thread.
+__device__ double block_sum(double v, double* sh) {
+    const int tid = lin_tid();
+    const int nt = blockDim.x * blockDim.y * blockDim.z;
+    sh[tid] = v;
+    __syncthreads();
+    for (int s = nt >> 1; s > 0; s >>= 1) {
+        if (tid < s) sh[tid] += sh[tid + s];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+__device__ double block_max(double v, double* sh) {
+    const int tid = lin_tid();
+    const int nt = blockDim.x * blockDim.y * blockDim.z;
+    sh[tid] = v;
+    __syncthreads();
+    for (int s = nt >> 1; s > 0; s >>= 1) {
+        if (tid < s) sh[tid] = fmax(sh[tid], sh[tid + s]);
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// ---- field accessors (value of the iterate at a linear index, in type T) ----
+template <typename T, typename TU>
+struct Plain {
+    const TU* p;
+    __device__ __forceinline__ T operator()(size_t i) const { return (T)p[i]; }
+};
+template <typename T, typename TE>
+struct PlusE {  // phi + e, formed in double
+    const double* p;
+    const TE* e;
+    __device__ __forceinline__ T operator()(size_t i) const { return (T)(p[i] + (double)e[i]); }
+};
+
+// ---- operators -------------------------------------------------------------------
+// Seven-point Laplacian: (sum of the six neighbours - 6 u) / h^2.
+template <typename T, typename F>
+__device__ __forceinline__ T flat_Mu(const F& u, const Grid& g, int x, int y, int z, T uc, T ih2) {
+    T s = u(g(x - 1, y, z)) + u(g(x + 1, y, z));
+    s += u(g(x, y - 1, z)) + u(g(x, y + 1, z));
+    s += u(g(x, y, z - 1)) + u(g(x, y, z + 1));
+    return (s - T(6) * uc) * ih2;
+}
+
+// Flux-form operator: face-averaged diagonal coefficients times compact
+// normal differences, plus D0_a (C^{ab} D0_b u) for the six ordered pairs.
+// Returns M u and the diagonal D (both scaled by 1/h^2).
+template <typename T, typename TC, typename F>
+__device__ __forceinline__ void var_Mu(const F& u, const TC* __restrict__ C, size_t N, const Grid& g,
+                                       int x, int y, int z, T uc, T ih2, T& Mu, T& D) {
+    const TC* Cxx = C;
+    const TC* Cyy = C + N;
+    const TC* Czz = C + 2 * N;
+    const TC* Cxy = C + 3 * N;
+    const TC* Cxz = C + 4 * N;
+    const TC* Cyz = C + 5 * N;
+    const size_t i0 = g(x, y, z);
+    T acc, dsum;
+    {
+        const T c0 = (T)Cxx[i0];
+        const T fp = T(0.5) * (c0 + (T)Cxx[g(x + 1, y, z)]);
+        const T fm = T(0.5) * (c0 + (T)Cxx[g(x - 1, y, z)]);
+        acc = fp * (u(g(x + 1, y, z)) - uc) - fm * (uc - u(g(x - 1, y, z)));
+        dsum = fp + fm;
+    }
+    {
+        const T c0 = (T)Cyy[i0];
+        const T fp = T(0.5) * (c0 + (T)Cyy[g(x, y + 1, z)]);
+        const T fm = T(0.5) * (c0 + (T)Cyy[g(x, y - 1, z)]);
+        acc += fp * (u(g(x, y + 1, z)) - uc) - fm * (uc - u(g(x, y - 1, z)));
+        dsum += fp + fm;
+    }
+    {
+        const T c0 = (T)Czz[i0];
+        const T fp = T(0.5) * (c0 + (T)Czz[g(x, y, z + 1)]);
+        const T fm = T(0.5) * (c0 + (T)Czz[g(x, y, z - 1)]);
+        acc += fp * (u(g(x, y, z + 1)) - uc) - fm * (uc - u(g(x, y, z - 1)));
+        dsum += fp + fm;
+    }
+    T cross;
+    {   // pairs (x,y) and (y,x)
+        const T upp = u(g(x + 1, y + 1, z)), upm = u(g(x + 1, y - 1, z));
+        const T ump = u(g(x - 1, y + 1, z)), umm = u(g(x - 1, y - 1, z));
+        cross = (T)Cxy[g(x + 1, y, z)] * (upp - upm) - (T)Cxy[g(x - 1, y, z)] * (ump - umm);
+        cross += (T)Cxy[g(x, y + 1, z)] * (upp - ump) - (T)Cxy[g(x, y - 1, z)] * (upm - umm);
+    }
+    {   // pairs (x,z) and (z,x)
+        const T upp = u(g(x + 1, y, z + 1)), upm = u(g(x + 1, y, z - 1));
+        const T ump = u(g(x - 1, y, z + 1)), umm = u(g(x - 1, y, z - 1));
+        cross += (T)Cxz[g(x + 1, y, z)] * (upp - upm) - (T)Cxz[g(x - 1, y, z)] * (ump - umm);
+        cross += (T)Cxz[g(x, y, z + 1)] * (upp - ump) - (T)Cxz[g(x, y, z - 1)] * (upm - umm);
+    }
+    {   // pairs (y,z) and (z,y)
+        const T upp = u(g(x, y + 1, z + 1)), upm = u(g(x, y + 1, z - 1));
+        const T ump = u(g(x, y - 1, z + 1)), umm = u(g(x, y - 1, z - 1));
+        cross += (T)Cyz[g(x, y + 1, z)] * (upp - upm) - (T)Cyz[g(x, y - 1, z)] * (ump - umm);
+        cross += (T)Cyz[g(x, y, z + 1)] * (upp - ump) - (T)Cyz[g(x, y, z - 1)] * (upm - umm);
+    }
+    Mu = (acc + T(0.25) * cross) * ih2;
+    D = -dsum * ih2;
+}
+
+template <typename T, typename TC>
+__device__ __forceinline__ T var_diag(const TC* __restrict__ C, size_t N, const Grid& g, int x, int y, int z,
+                                      T ih2) {
+    const size_t i0 = g(x, y, z);
+    T d = T(0);
+    for (int a = 0; a < 3; ++a) {
+        const TC* c = C + a * N;
+        const T c0 = (T)c[i0];
+        const int dx = a == 0, dy = a == 1, dz = a == 2;
+        d += T(0.5) * (c0 + (T)c[g(x + dx, y + dy, z + dz)]) + T(0.5) * (c0 + (T)c[g(x - dx, y - dy, z - dz)]);
+    }
+    return -d * ih2;
+}
+
+// ---- launch shape ------------------------------------------------------------------
+struct Shape {
+    dim3 grid, block;
+    int nz;
+};
+Shape stencil_shape(int n) {
+    const int bx = n < 64 ? n : 64;
+    int by = kThreads / bx;
+    if (by > n) by = n;
+    size_t pts = (size_t)n * n * n;
+    size_t want = pts / ((size_t)kThreads * 2048);
+    int nz = 1;
+    while ((size_t)nz * 2 <= want && nz < 32) nz *= 2;
+    if (nz > n) nz = n;
+    Shape s;
+    s.block = dim3(bx, by, 1);
+    s.grid = dim3(n / bx, n / by, n / nz);
+    s.nz = nz;
+    return s;
+}
+
+// =====================================================================================
+// smoothing step
+// =====================================================================================
+template <typename T, typename TC, bool HASX, bool HASPREV>
+__global__ __launch_bounds__(kThreads) void k_smooth(int n, T ih2, const TC* __restrict__ C,
+                                                     const T* __restrict__ x, const T* xprev,
+                                                     const T* __restrict__ b, T* out, T a, T c,
+                                                     int nz) {
+    const Grid g{n, n - 1};
+    const size_t N = (size_t)n * n * n;
+    const int xi = blockIdx.x * blockDim.x + threadIdx.x;
+    const int yi = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z0 = blockIdx.z * nz;
+    const Plain<T, T> u{x};
+    const T dflat = T(-6) * ih2;
+    for (int z = z0; z < z0 + nz; ++z) {
+        const size_t i = g(xi, yi, z);
+        const T bi = b[i];
+        T val;
+        if constexpr (HASX) {
+            const T uc = x[i];
+            T Mu, D;
+            if (C == nullptr) {
+                Mu = flat_Mu<T>(u, g, xi, yi, z, uc, ih2);
+                D = dflat;
+            } else {
+                var_Mu<T, TC>(u, C, N, g, xi, yi, z, uc, ih2, Mu, D);
+            }
+            T xp = T(0);
+            if constexpr (HASPREV) xp = xprev[i];
+            val = uc + a * (uc - xp) + c * (bi - Mu) / D;
+        } else {
+            const T D = C == nullptr ? dflat : var_diag<T, TC>(C, N, g, xi, yi, z, ih2);
+            val = c * bi / D;
+        }
+        out[i] = val;
+    }
+}
+
+// =====================================================================================
+// residual + full weighting
+// =====================================================================================
+template <typename T, typename TC, bool HASX>
+__global__ __launch_bounds__(kThreads) void k_resid_restrict(int n, T ih2, const TC* __restrict__ C,
+                                                             const T* __restrict__ x,
+                                                             const T* __restrict__ b,
+                                                             T* __restrict__ coarse, int nz) {
+    const int nc = n >> 1;
+    const Grid g{n, n - 1};
+    const Grid gc{nc, nc - 1};
+    const size_t N = (size_t)n * n * n;
+    const int X = blockIdx.x * blockDim.x + threadIdx.x;
+    const int Y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int Z0 = blockIdx.z * nz;
+    const Plain<T, T> u{x};
+    const T w1[3] = {T(0.25), T(0.5), T(0.25)};
+    for (int Z = Z0; Z < Z0 + nz; ++Z) {
+        T acc = T(0);
+        for (int dz = -1; dz <= 1; ++dz) {
+            T accy = T(0);
+            for (int dy = -1; dy <= 1; ++dy) {
+                T accx = T(0);
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int fx = 2 * X + dx, fy = 2 * Y + dy, fz = 2 * Z + dz;
+                    const size_t i = g(fx, fy, fz);
+                    T r = b[i];
+                    if constexpr (HASX) {
+                        const T uc = x[i];
+                        T Mu, D;
+                        if (C == nullptr) {
+                            Mu = flat_Mu<T>(u, g, fx, fy, fz, uc, ih2);
+                        } else {
+                            var_Mu<T, TC>(u, C, N, g, fx, fy, fz, uc, ih2, Mu, D);
+                        }
+                        r -= Mu;
+                    }
+                    accx += w1[dx + 1] * r;
+                }
+                accy += w1[dy + 1] * accx;
+            }
+            acc += w1[dz + 1] * accy;
+        }
+        coarse[gc(X, Y, Z)] = acc;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_restrict(int n, const T* __restrict__ fine,
+                                                       T* __restrict__ coarse, int nz) {
+    const int nc = n >> 1;
+    const Grid g{n, n - 1};
+    const Grid gc{nc, nc - 1};
+    const int X = blockIdx.x * blockDim.x + threadIdx.x;
+    const int Y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int Z0 = blockIdx.z * nz;
+    const T w1[3] = {T(0.25), T(0.5), T(0.25)};
+    for (int Z = Z0; Z < Z0 + nz; ++Z) {
+        T acc = T(0);
+        for (int dz = -1; dz <= 1; ++dz) {
+            T accy = T(0);
+            for (int dy = -1; dy <= 1; ++dy) {
+                T accx = T(0);
+                for (int dx = -1; dx <= 1; ++dx) accx += w1[dx + 1] * fine[g(2 * X + dx, 2 * Y + dy, 2 * Z + dz)];
+                accy += w1[dy + 1] * accx;
+            }
+            acc += w1[dz + 1] * accy;
+        }
+        coarse[gc(X, Y, Z)] = acc;
+    }
+}
+
+// =====================================================================================
+// trilinear prolongation + correction
+// =====================================================================================
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_prolong_add(int n, const T* __restrict__ e, T* x, int nz) {
+    const int nc = n >> 1;
+    const Grid g{n, n - 1};
+    const Grid gc{nc, nc - 1};
+    const int xi = blockIdx.x * blockDim.x + threadIdx.x;
+    const int yi = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z0 = blockIdx.z * nz;
+    const int X = xi >> 1, Y = yi >> 1;
+    const int ox = xi & 1, oy = yi & 1;
+    for (int z = z0; z < z0 + nz; ++z) {
+        const int Z = z >> 1, oz = z & 1;
+        // interpolate along x on the (up to) 4 coarse lines, then y, then z
+        T vz[2];
+        for (int kz = 0; kz <= oz; ++kz) {
+            T vy[2];
+            for (int ky = 0; ky <= oy; ++ky) {
+                const T a0 = e[gc(X, Y + ky, Z + kz)];
+                vy[ky] = ox ? T(0.5) * (a0 + e[gc(X + 1, Y + ky, Z + kz)]) : a0;
+            }
+            vz[kz] = oy ? T(0.5) * (vy[0] + vy[1]) : vy[0];
+        }
+        const T p = oz ? T(0.5) * (vz[0] + vz[1]) : vz[0];
+        const size_t i = g(xi, yi, z);
+        x[i] += p;
+    }
+}
+
+// =====================================================================================
+// operator application
+// =====================================================================================
+template <typename T, typename TC>
+__global__ __launch_bounds__(kThreads) void k_apply(int n, T ih2, const TC* __restrict__ C,
+                                                    const T* __restrict__ x, T* __restrict__ out, int nz) {
+    const Grid g{n, n - 1};
+    const size_t N = (size_t)n * n * n;
+    const int xi = blockIdx.x * blockDim.x + threadIdx.x;
+    const int yi = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z0 = blockIdx.z * nz;
+    const Plain<T, T> u{x};
+    for (int z = z0; z < z0 + nz; ++z) {
+        const size_t i = g(xi, yi, z);
+        const T uc = x[i];
+        T Mu, D;
+        if (C == nullptr) {
+            Mu = flat_Mu<T>(u, g, xi, yi, z, uc, ih2);
+        } else {
+            var_Mu<T, TC>(u, C, N, g, xi, yi, z, uc, ih2, Mu, D);
+        }
+        out[i] = Mu;
+    }
+}
+
+// =====================================================================================
+// outer defect correction: optional phi update, residual in TA, sum of r^2
+// =====================================================================================
+template <typename TA, typename TR, typename TE, typename TC, bool UPDATE>
+__global__ __launch_bounds__(kThreads) void k_outer_residual(int n, TA ih2, const TC* __restrict__ C,
+                                                             const double* __restrict__ phi_in,
+                                                             const TE* __restrict__ e,
+                                                             double* __restrict__ phi_out,
+                                                             const double* __restrict__ b, double bmean,
+                                                             TR* __restrict__ r, double* partials, int nz) {
+    __shared__ double sh[kThreads];
+    const Grid g{n, n - 1};
+    const size_t N = (size_t)n * n * n;
+    const int xi = blockIdx.x * blockDim.x + threadIdx.x;
+    const int yi = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z0 = blockIdx.z * nz;
+    double ss = 0.0;
+    for (int z = z0; z < z0 + nz; ++z) {
+        const size_t i = g(xi, yi, z);
+        TA Mu, D, uc;
+        if constexpr (UPDATE) {
+            const double pn = phi_in[i] + (double)e[i];
+            phi_out[i] = pn;
+            uc = (TA)pn;
+            const PlusE<TA, TE> u{phi_in, e};
+            if (C == nullptr) Mu = flat_Mu<TA>(u, g, xi, yi, z, uc, ih2);
+            else var_Mu<TA, TC>(u, C, N, g, xi, yi, z, uc, ih2, Mu, D);
+        } else {
+            uc = (TA)phi_in[i];
+            const Plain<TA, double> u{phi_in};
+            if (C == nullptr) Mu = flat_Mu<TA>(u, g, xi, yi, z, uc, ih2);
+            else var_Mu<TA, TC>(u, C, N, g, xi, yi, z, uc, ih2, Mu, D);
+        }
+        const TA ri = (TA)(b[i] - bmean) - Mu;
+        r[i] = (TR)ri;
+        ss += (double)ri * (double)ri;
+    }
+    const double tot = block_sum(ss, sh);
+    if (lin_tid() == 0) partials[lin_bid()] = tot;
+}
+
+// =====================================================================================
+// reductions
+// =====================================================================================
+__global__ __launch_bounds__(kThreads) void k_block_sums(int n, const double* __restrict__ u, double shift, int p,
+                                                         double* partials, int nz) {
+    __shared__ double sh[kThreads];
+    const Grid g{n, n - 1};
+    const int xi = blockIdx.x * blockDim.x + threadIdx.x;
+    const int yi = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z0 = blockIdx.z * nz;
+    double s = 0.0;
+    for (int z = z0; z < z0 + nz; ++z) {
+        const double v = u[g(xi, yi, z)] - shift;
+        s += p == 2 ? v * v : v;
+    }
+    const double tot = block_sum(s, sh);
+    if (lin_tid() == 0) partials[lin_bid()] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ partials, int count, double* out,
+                                                   int slot, int is_max) {
+    __shared__ double sh[1024];
+    const int tid = threadIdx.x;
+    double v = is_max ? -INFINITY : 0.0;
+    for (int i = tid; i < count; i += 1024) v = is_max ? fmax(v, partials[i]) : v + partials[i];
+    const double r = is_max ? block_max(v, sh) : block_sum(v, sh);
+    if (tid == 0) out[slot] = r;
+}
+
+// =====================================================================================
+// elementwise
+// =====================================================================================
+__global__ void k_shift(size_t count, const double* src, double shift, double* dst) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i] - shift;
+}
+template <typename T>
+__global__ void k_add(size_t count, const double* src, const T* e, double* dst) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i] + (double)e[i];
+}
+template <typename TD, typename TS>
+__global__ void k_convert(size_t count, const TS* src, TD* dst) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = (TD)src[i];
+}
+template <typename T>
+__global__ void k_fill(size_t count, T v, T* dst) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = v;
+}
+dim3 ew_grid(size_t count) {
+    size_t b = (count + kThreads - 1) / kThreads;
+    if (b > 65536) b = 65536;
+    if (b == 0) b = 1;
+    return dim3((unsigned)b);
+}
+
+// =====================================================================================
+// coefficient checks and Gershgorin bounds
+// =====================================================================================
+template <typename TC>
+__global__ __launch_bounds__(kThreads) void k_gershgorin(int n, const TC* __restrict__ C, double* partials, int nz) {
+    __shared__ double sh[kThreads];
+    const Grid g{n, n - 1};
+    const size_t N = (size_t)n * n * n;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z0 = blockIdx.z * nz;
+    double m = -INFINITY;
+    for (int z = z0; z < z0 + nz; ++z) {
+        const size_t i0 = g(x, y, z);
+        double face = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const TC* c = C + a * N;
+            const int dx = a == 0, dy = a == 1, dz = a == 2;
+            const double c0 = (double)c[i0];
+            face += 0.5 * (c0 + (double)c[g(x + dx, y + dy, z + dz)]) + 0.5 * (c0 + (double)c[g(x - dx, y - dy, z - dz)]);
+        }
+        double edge = 0.0;
+        const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+        for (int p = 0; p < 3; ++p) {
+            const TC* c = C + (3 + p) * N;
+            for (int sa = -1; sa <= 1; sa += 2)
+                for (int sb = -1; sb <= 1; sb += 2) {
+                    int ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0;
+                    (pa[p] == 0 ? ax : pa[p] == 1 ? ay : az) = sa;
+                    (pb[p] == 0 ? bx : pb[p] == 1 ? by : bz) = sb;
+                    edge += fabs((double)c[g(x + ax, y + ay, z + az)] + (double)c[g(x + bx, y + by, z + bz)]) * 0.25;
+                }
+        }
+        m = fmax(m, 1.0 + (face + edge) / face);
+    }
+    const double tot = block_max(m, sh);
+    if (lin_tid() == 0) partials[lin_bid()] = tot;
+}
+
+template <typename TC>
+__global__ __launch_bounds__(kThreads) void k_coeff_check(int n, const TC* __restrict__ C, double* partials, int nz) {
+    __shared__ double sh[kThreads];
+    const Grid g{n, n - 1};
+    const size_t N = (size_t)n * n * n;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z0 = blockIdx.z * nz;
+    double bad = 0.0;
+    for (int z = z0; z < z0 + nz; ++z) {
+        const size_t i = g(x, y, z);
+        bool ok = true;
+        for (int c = 0; c < 6; ++c) {
+            const double v = (double)C[c * N + i];
+            if (!isfinite(v)) ok = false;
+            if (c < 3 && !(v > 0.0)) ok = false;
+        }
+        bad += ok ? 0.0 : 1.0;
+    }
+    const double tot = block_sum(bad, sh);
+    if (lin_tid() == 0) partials[lin_bid()] = tot;
+}
+
+// =====================================================================================
+// coarsest level
+// =====================================================================================
+// Separable exact solve of the seven-point system: three 1-D basis changes,
+// division by the eigenvalue, three inverse basis changes, all in double in LDS.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_coarse_flat(int nc, const double* __restrict__ Q,
+                                                      const double* __restrict__ lam1, const T* __restrict__ r,
+                                                      T* __restrict__ e) {
+    __shared__ double A[4096];
+    __shared__ double B[4096];
+    __shared__ double q[256];
+    __shared__ double lam[16];
+    const int tid = threadIdx.x;
+    const int N = nc * nc * nc;
+    for (int i = tid; i < nc * nc; i += blockDim.x) q[i] = Q[i];
+    for (int i = tid; i < nc; i += blockDim.x) lam[i] = lam1[i];
+    for (int i = tid; i < N; i += blockDim.x) A[i] = (double)r[i];
+    __syncthreads();
+    // q[j + nc*k] = basis vector k at point j.  Forward: c_k = sum_j q[j,k] v_j.
+    auto pass = [&](const double* src, double* dst, int axis, bool forward) {
+        for (int i = tid; i < N; i += blockDim.x) {
+            const int x = i % nc, y = (i / nc) % nc, z = i / (nc * nc);
+            const int k = axis == 0 ? x : axis == 1 ? y : z;
+            const int stride = axis == 0 ? 1 : axis == 1 ? nc : nc * nc;
+            const int base = i - k * stride;
+            double acc = 0.0;
+            for (int j = 0; j < nc; ++j) {
+                const double w = forward ? q[j + nc * k] : q[k + nc * j];
+                acc += w * src[base + j * stride];
+            }
+            dst[i] = acc;
+        }
+        __syncthreads();
+    };
+    pass(A, B, 0, true);
+    pass(B, A, 1, true);
+    pass(A, B, 2, true);
+    for (int i = tid; i < N; i += blockDim.x) {
+        const int x = i % nc, y = (i / nc) % nc, z = i / (nc * nc);
+        const double l = lam[x] + lam[y] + lam[z];
+        B[i] = (x == 0 && y == 0 && z == 0) ? 0.0 : B[i] / l;
+    }
+    __syncthreads();
+    pass(B, A, 2, false);
+    pass(A, B, 1, false);
+    pass(B, A, 0, false);
+    for (int i = tid; i < N; i += blockDim.x) e[i] = (T)A[i];
+}
+
+// e = G r, 8 rows per block, 32 lanes per row, fixed-order sums.
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_dense(int N, const double* __restrict__ G, const T* __restrict__ r,
+                                                      T* __restrict__ e) {
+    __shared__ double sh[256];
+    const int row = blockIdx.x * 8 + (threadIdx.x >> 5);
+    const int lane = threadIdx.x & 31;
+    double acc = 0.0;
+    if (row < N)
+        for (int j = lane; j < N; j += 32) acc += G[(size_t)row * N + j] * (double)r[j];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 16; s > 0; s >>= 1) {
+        if (lane < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (lane == 0 && row < N) e[row] = (T)sh[threadIdx.x];
+}
+
+// =====================================================================================
+// coefficient gradient (operator VJP)
+// =====================================================================================
+template <typename TO>
+__global__ __launch_bounds__(kThreads) void k_coeff_grad(int n, double ih2, const double* __restrict__ lam,
+                                                         const double* __restrict__ phi, TO* __restrict__ out,
+                                                         int nz) {
+    const Grid g{n, n - 1};
+    const size_t N = (size_t)n * n * n;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z0 = blockIdx.z * nz;
+    for (int z = z0; z < z0 + nz; ++z) {
+        const size_t i = g(x, y, z);
+        const double l0 = lam[i], p0 = phi[i];
+        double lp[3], lm[3], pp[3], pm[3];
+        const int d[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+        for (int a = 0; a < 3; ++a) {
+            const size_t ip = g(x + d[a][0], y + d[a][1], z + d[a][2]);
+            const size_t im = g(x - d[a][0], y - d[a][1], z - d[a][2]);
+            lp[a] = lam[ip];
+            lm[a] = lam[im];
+            pp[a] = phi[ip];
+            pm[a] = phi[im];
+            const double gp = (lp[a] - l0) * (pp[a] - p0);
+            const double gm = (l0 - lm[a]) * (p0 - pm[a]);
+            out[a * N + i] = (TO)(0.5 * (gp + gm) * ih2);
+        }
+        const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+        for (int p = 0; p < 3; ++p) {
+            const int a = pa[p], b = pb[p];
+            const double dla = lp[a] - lm[a], dlb = lp[b] - lm[b];
+            const double dpa = pp[a] - pm[a], dpb = pp[b] - pm[b];
+            out[(3 + p) * N + i] = (TO)((dla * dpb + dlb * dpa) * 0.25 * ih2);
+        }
+    }
+}
+
+// =====================================================================================
+// moving-mesh geometry
+// =====================================================================================
+__device__ __forceinline__ void hess_at(const double* __restrict__ psi, const Grid& g, int x, int y, int z,
+                                        double ih2, double H[6]) {
+    const double c = psi[g(x, y, z)];
+    H[0] = (psi[g(x + 1, y, z)] - 2.0 * c + psi[g(x - 1, y, z)]) * ih2;
+    H[1] = (psi[g(x, y + 1, z)] - 2.0 * c + psi[g(x, y - 1, z)]) * ih2;
+    H[2] = (psi[g(x, y, z + 1)] - 2.0 * c + psi[g(x, y, z - 1)]) * ih2;
+    H[3] = (psi[g(x + 1, y + 1, z)] - psi[g(x + 1, y - 1, z)] - psi[g(x - 1, y + 1, z)] + psi[g(x - 1, y - 1, z)]) * 0.25 * ih2;
+    H[4] = (psi[g(x + 1, y, z + 1)] - psi[g(x + 1, y, z - 1)] - psi[g(x - 1, y, z + 1)] + psi[g(x - 1, y, z - 1)]) * 0.25 * ih2;
+    H[5] = (psi[g(x, y + 1, z + 1)] - psi[g(x, y + 1, z - 1)] - psi[g(x, y - 1, z + 1)] + psi[g(x, y - 1, z - 1)]) * 0.25 * ih2;
+}
+
+// Symmetric 3x3 (a,b,c,d,e,f) = (xx,yy,zz,xy,xz,yz): determinant and inverse.
+struct Sym3 {
+    double m[3][3];
+};
+__device__ __forceinline__ void sym_from6(const double s[6], Sym3& A) {
+    A.m[0][0] = s[0]; A.m[1][1] = s[1]; A.m[2][2] = s[2];
+    A.m[0][1] = A.m[1][0] = s[3];
+    A.m[0][2] = A.m[2][0] = s[4];
+    A.m[1][2] = A.m[2][1] = s[5];
+}
+__device__ __forceinline__ double inv3(const Sym3& J, Sym3& K) {
+    const double (*m)[3] = J.m;
+    const double c00 = m[1][1] * m[2][2] - m[1][2] * m[2][1];
+    const double c01 = m[1][2] * m[2][0] - m[1][0] * m[2][2];
+    const double c02 = m[1][0] * m[2][1] - m[1][1] * m[2][0];
+    const double det = m[0][0] * c00 + m[0][1] * c01 + m[0][2] * c02;
+    const double id = 1.0 / det;
+    K.m[0][0] = c00 * id;
+    K.m[0][1] = (m[0][2] * m[2][1] - m[0][1] * m[2][2]) * id;
+    K.m[0][2] = (m[0][1] * m[1][2] - m[0][2] * m[1][1]) * id;
+    K.m[1][0] = c01 * id;
+    K.m[1][1] = (m[0][0] * m[2][2] - m[0][2] * m[2][0]) * id;
+    K.m[1][2] = (m[0][2] * m[1][0] - m[0][0] * m[1][2]) * id;
+    K.m[2][0] = c02 * id;
+    K.m[2][1] = (m[0][1] * m[2][0] - m[0][0] * m[2][1]) * id;
+    K.m[2][2] = (m[0][0] * m[1][1] - m[0][1] * m[1][0]) * id;
+    return det;
+}
+__device__ __forceinline__ void mul3(const Sym3& A, const Sym3& B, Sym3& C) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) C.m[i][j] = A.m[i][0] * B.m[0][j] + A.m[i][1] * B.m[1][j] + A.m[i][2] * B.m[2][j];
+}
+
+template <typename TO>
+__global__ __launch_bounds__(kThreads) void k_geometry(int n, double ih2, const double* __restrict__ psi,
+                                                       TO* __restrict__ C, double* __restrict__ sqrtg, int nz) {
+    const Grid g{n, n - 1};
+    const size_t N = (size_t)n * n * n;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z0 = blockIdx.z * nz;
+    for (int z = z0; z < z0 + nz; ++z) {
+        double H[6];
+        hess_at(psi, g, x, y, z, ih2, H);
+        H[0] += 1.0; H[1] += 1.0; H[2] += 1.0;
+        Sym3 J, K, K2;
+        sym_from6(H, J);
+        const double det = inv3(J, K);
+        mul3(K, K, K2);   // J symmetric: J^-1 J^-T = K K
+        const size_t i = g(x, y, z);
+        C[i] = (TO)(det * K2.m[0][0]);
+        C[N + i] = (TO)(det * K2.m[1][1]);
+        C[2 * N + i] = (TO)(det * K2.m[2][2]);
+        C[3 * N + i] = (TO)(det * K2.m[0][1]);
+        C[4 * N + i] = (TO)(det * K2.m[0][2]);
+        C[5 * N + i] = (TO)(det * K2.m[1][2]);
+        if (sqrtg) sqrtg[i] = det;
+    }
+}
+
+// Per cell: Jbar = t K - d (P + P^T), P = K G K^2, t = d <G, K^2> + sqrtgbar d,
+// G the full symmetric cotangent of C (stored off-diagonals halved).
+__global__ __launch_bounds__(kThreads) void k_geometry_bwd_cell(int n, double ih2, const double* __restrict__ psi,
+                                                                const double* __restrict__ Cbar,
+                                                                const double* __restrict__ sbar,
+                                                                double* __restrict__ Jbar, int nz) {
+    const Grid g{n, n - 1};
+    const size_t N = (size_t)n * n * n;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z0 = blockIdx.z * nz;
+    for (int z = z0; z < z0 + nz; ++z) {
+        const size_t i = g(x, y, z);
+        double H[6];
+        hess_at(psi, g, x, y, z, ih2, H);
+        H[0] += 1.0; H[1] += 1.0; H[2] += 1.0;
+        Sym3 J, K, K2, G, KG, P;
+        sym_from6(H, J);
+        const double d = inv3(J, K);
+        mul3(K, K, K2);
+        double gs[6];
+        for (int c = 0; c < 6; ++c) gs[c] = Cbar[c * N + i] * (c < 3 ? 1.0 : 0.5);
+        sym_from6(gs, G);
+        double t = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) t += G.m[a][b] * K2.m[a][b];
+        t *= d;
+        if (sbar) t += sbar[i] * d;
+        mul3(K, G, KG);
+        mul3(KG, K2, P);
+        const int pa[6] = {0, 1, 2, 0, 0, 1}, pb[6] = {0, 1, 2, 1, 2, 2};
+        for (int c = 0; c < 6; ++c) {
+            const int a = pa[c], b = pb[c];
+            const double jab = t * K.m[a][b] - d * (P.m[a][b] + P.m[b][a]);
+            const double jba = t * K.m[b][a] - d * (P.m[b][a] + P.m[a][b]);
+            Jbar[c * N + i] = c < 3 ? jab : jab + jba;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_hessian_adjoint(int n, double ih2, const double* __restrict__ Jb,
+                                                              double* __restrict__ out, int nz) {
+    const Grid g{n, n - 1};
+    const size_t N = (size_t)n * n * n;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z0 = blockIdx.z * nz;
+    for (int z = z0; z < z0 + nz; ++z) {
+        double acc = 0.0;
+        for (int c = 0; c < 6; ++c) {
+            const double* u = Jb + c * N;
+            double H[6];
+            // only component c of the Hessian stencil applied to field c is needed
+            if (c < 3) {
+                const int dx = c == 0, dy = c == 1, dz = c == 2;
+                acc += (u[g(x + dx, y + dy, z + dz)] - 2.0 * u[g(x, y, z)] + u[g(x - dx, y - dy, z - dz)]) * ih2;
+            } else {
+                (void)H;
+                const int a = c == 5 ? 1 : 0, b = c == 3 ? 1 : 2;
+                int ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0;
+                (a == 0 ? ax : ay) = 1;
+                (b == 1 ? by : bz) = 1;
+                acc += (u[g(x + ax + bx, y + ay + by, z + az + bz)] - u[g(x + ax - bx, y + ay - by, z + az - bz)] -
+                        u[g(x - ax + bx, y - ay + by, z - az + bz)] + u[g(x - ax - bx, y - ay - by, z - az - bz)]) *
+                       0.25 * ih2;
+            }
+        }
+        out[g(x, y, z)] = acc;
+    }
+}
+
+}  // namespace
+
+// =====================================================================================
+// launchers
+// =====================================================================================
+int stencil_blocks(int n) {
+    Shape s = stencil_shape(n);
+    return (int)(s.grid.x * s.grid.y * s.grid.z);
+}
+
+template <typename T, typename TC>
+hipError_t launch_smooth_step(const OpDesc<TC>& op, const T* x, const T* xprev, const T* b, T* out, double a,
+                              double c, hipStream_t s) {
+    Shape sh = stencil_shape(op.n);
+    if (x == nullptr)
+        hipLaunchKernelGGL((k_smooth<T, TC, false, false>), sh.grid, sh.block, 0, s, op.n, (T)op.ih2, op.coeff, x,
+                           xprev, b, out, (T)a, (T)c, sh.nz);
+    else if (xprev == nullptr)
+        hipLaunchKernelGGL((k_smooth<T, TC, true, false>), sh.grid, sh.block, 0, s, op.n, (T)op.ih2, op.coeff, x,
+                           xprev, b, out, (T)a, (T)c, sh.nz);
+    else
+        hipLaunchKernelGGL((k_smooth<T, TC, true, true>), sh.grid, sh.block, 0, s, op.n, (T)op.ih2, op.coeff, x,
+                           xprev, b, out, (T)a, (T)c, sh.nz);
+    return hipGetLastError();
+}
+
+template <typename T, typename TC>
+hipError_t launch_residual_restrict(const OpDesc<TC>& op, const T* x, const T* b, T* coarse, hipStream_t s) {
+    Shape sh = stencil_shape(op.n / 2);
+    if (x)
+        hipLaunchKernelGGL((k_resid_restrict<T, TC, true>), sh.grid, sh.block, 0, s, op.n, (T)op.ih2, op.coeff, x, b,
+                           coarse, sh.nz);
+    else
+        hipLaunchKernelGGL((k_resid_restrict<T, TC, false>), sh.grid, sh.block, 0, s, op.n, (T)op.ih2, op.coeff, x, b,
+                           coarse, sh.nz);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_restrict(int n, const T* fine, T* coarse, int ncomp, hipStream_t s) {
+    Shape sh = stencil_shape(n / 2);
+    const size_t Nf = (size_t)n * n * n, Nc = Nf / 8;
+    for (int c = 0; c < ncomp; ++c)
+        hipLaunchKernelGGL((k_restrict<T>), sh.grid, sh.block, 0, s, n, fine + c * Nf, coarse + c * Nc, sh.nz);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prolong_add(int n, const T* e, T* x, hipStream_t s) {
+    Shape sh = stencil_shape(n);
+    hipLaunchKernelGGL((k_prolong_add<T>), sh.grid, sh.block, 0, s, n, e, x, sh.nz);
+    return hipGetLastError();
+}
+
+template <typename T, typename TC>
+hipError_t launch_apply(const OpDesc<TC>& op, const T* u, T* out, hipStream_t s) {
+    Shape sh = stencil_shape(op.n);
+    hipLaunchKernelGGL((k_apply<T, TC>), sh.grid, sh.block, 0, s, op.n, (T)op.ih2, op.coeff, u, out, sh.nz);
+    return hipGetLastError();
+}
+
+template <typename TA, typename TR, typename TE, typename TC>
+hipError_t launch_outer_residual(const OpDesc<TC>& op, const double* phi_in, const TE* e, double* phi_out,
+                                 const double* b, double bmean, TR* r, double* partials, hipStream_t s) {
+    Shape sh = stencil_shape(op.n);
+    if (e)
+        hipLaunchKernelGGL((k_outer_residual<TA, TR, TE, TC, true>), sh.grid, sh.block, 0, s, op.n, (TA)op.ih2,
+                           op.coeff, phi_in, e, phi_out, b, bmean, r, partials, sh.nz);
+    else
+        hipLaunchKernelGGL((k_outer_residual<TA, TR, TE, TC, false>), sh.grid, sh.block, 0, s, op.n, (TA)op.ih2,
+                           op.coeff, phi_in, e, phi_out, b, bmean, r, partials, sh.nz);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_sums(int n, const double* u, double shift, int p, double* partials, hipStream_t s) {
+    Shape sh = stencil_shape(n);
+    hipLaunchKernelGGL(k_block_sums, sh.grid, sh.block, 0, s, n, u, shift, p, partials, sh.nz);
+    return hipGetLastError();
+}
+hipError_t launch_finalize_sum(const double* partials, int count, double* out, int slot, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, partials, count, out, slot, 0);
+    return hipGetLastError();
+}
+hipError_t launch_finalize_max(const double* partials, int count, double* out, int slot, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, partials, count, out, slot, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_shift(size_t count, const double* src, double shift, double* dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_shift, ew_grid(count), dim3(kThreads), 0, s, count, src, shift, dst);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_add(size_t count, const double* src, const T* e, double* dst, hipStream_t s) {
+    hipLaunchKernelGGL((k_add<T>), ew_grid(count), dim3(kThreads), 0, s, count, src, e, dst);
+    return hipGetLastError();
+}
+template <typename TD, typename TS>
+hipError_t launch_convert(size_t count, const TS* src, TD* dst, hipStream_t s) {
+    hipLaunchKernelGGL((k_convert<TD, TS>), ew_grid(count), dim3(kThreads), 0, s, count, src, dst);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_fill(size_t count, T value, T* dst, hipStream_t s) {
+    hipLaunchKernelGGL((k_fill<T>), ew_grid(count), dim3(kThreads), 0, s, count, value, dst);
+    return hipGetLastError();
+}
+
+template <typename TC>
+hipError_t launch_gershgorin(const OpDesc<TC>& op, double* partials, hipStream_t s) {
+    Shape sh = stencil_shape(op.n);
+    hipLaunchKernelGGL((k_gershgorin<TC>), sh.grid, sh.block, 0, s, op.n, op.coeff, partials, sh.nz);
+    return hipGetLastError();
+}
+template <typename TC>
+hipError_t launch_coeff_check(int n, const TC* coeff, double* partials, hipStream_t s) {
+    Shape sh = stencil_shape(n);
+    hipLaunchKernelGGL((k_coeff_check<TC>), sh.grid, sh.block, 0, s, n, coeff, partials, sh.nz);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_coarse_flat(int nc, const double* Q, const double* lam1, const T* r, T* e, hipStream_t s) {
+    if (nc > 16) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_coarse_flat<T>), dim3(1), dim3(1024), 0, s, nc, Q, lam1, r, e);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_coarse_dense(int N, const double* G, const T* r, T* e, hipStream_t s) {
+    hipLaunchKernelGGL((k_coarse_dense<T>), dim3((N + 7) / 8), dim3(256), 0, s, N, G, r, e);
+    return hipGetLastError();
+}
+
+template <typename TO>
+hipError_t launch_coeff_grad(int n, double ih2, const double* lam, const double* phi, TO* cbar, hipStream_t s) {
+    Shape sh = stencil_shape(n);
+    hipLaunchKernelGGL((k_coeff_grad<TO>), sh.grid, sh.block, 0, s, n, ih2, lam, phi, cbar, sh.nz);
+    return hipGetLastError();
+}
+template <typename TO>
+hipError_t launch_geometry(int n, double ih2, const double* psi, TO* C, double* sqrtg, hipStream_t s) {
+    Shape sh = stencil_shape(n);
+    hipLaunchKernelGGL((k_geometry<TO>), sh.grid, sh.block, 0, s, n, ih2, psi, C, sqrtg, sh.nz);
+    return hipGetLastError();
+}
+hipError_t launch_geometry_bwd_cell(int n, double ih2, const double* psi, const double* Cbar, const double* sbar,
+                                    double* Jbar, hipStream_t s) {
+    Shape sh = stencil_shape(n);
+    hipLaunchKernelGGL(k_geometry_bwd_cell, sh.grid, sh.block, 0, s, n, ih2, psi, Cbar, sbar, Jbar, sh.nz);
+    return hipGetLastError();
+}
+hipError_t launch_hessian_adjoint(int n, double ih2, const double* Jbar, double* psibar, hipStream_t s) {
+    Shape sh = stencil_shape(n);
+    hipLaunchKernelGGL(k_hessian_adjoint, sh.grid, sh.block, 0, s, n, ih2, Jbar, psibar, sh.nz);
+    return hipGetLastError();
+}
+
+// ---- explicit instantiations ------------------------------------------------------
+#define INST_T_TC(T, TC)                                                                                         \
+    template hipError_t launch_smooth_step<T, TC>(const OpDesc<TC>&, const T*, const T*, const T*, T*, double,   \
+                                                  double, hipStream_t);                                          \
+    template hipError_t launch_residual_restrict<T, TC>(const OpDesc<TC>&, const T*, const T*, T*, hipStream_t); \
+    template hipError_t launch_apply<T, TC>(const OpDesc<TC>&, const T*, T*, hipStream_t);
+INST_T_TC(float, float)
+INST_T_TC(double, double)
+INST_T_TC(double, float)
+INST_T_TC(float, double)
+
+#define INST_T(T)                                                                                  \
+    template hipError_t launch_restrict<T>(int, const T*, T*, int, hipStream_t);                   \
+    template hipError_t launch_prolong_add<T>(int, const T*, T*, hipStream_t);                     \
+    template hipError_t launch_add<T>(size_t, const double*, const T*, double*, hipStream_t);      \
+    template hipError_t launch_fill<T>(size_t, T, T*, hipStream_t);                                \
+    template hipError_t launch_gershgorin<T>(const OpDesc<T>&, double*, hipStream_t);              \
+    template hipError_t launch_coeff_check<T>(int, const T*, double*, hipStream_t);                \
+    template hipError_t launch_coarse_flat<T>(int, const double*, const double*, const T*, T*, hipStream_t); \
+    template hipError_t launch_coarse_dense<T>(int, const double*, const T*, T*, hipStream_t);     \
+    template hipError_t launch_coeff_grad<T>(int, double, const double*, const double*, T*, hipStream_t); \
+    template hipError_t launch_geometry<T>(int, double, const double*, T*, double*, hipStream_t);
+INST_T(float)
+INST_T(double)
+
+template hipError_t launch_convert<float, double>(size_t, const double*, float*, hipStream_t);
+template hipError_t launch_convert<double, float>(size_t, const float*, double*, hipStream_t);
+template hipError_t launch_convert<double, double>(size_t, const double*, double*, hipStream_t);
+template hipError_t launch_convert<float, float>(size_t, const float*, float*, hipStream_t);
+
+#define INST_OUTER(TA, TR, TE, TC)                                                                                \
+    template hipError_t launch_outer_residual<TA, TR, TE, TC>(const OpDesc<TC>&, const double*, const TE*, double*, \
+                                                              const double*, double, TR*, double*, hipStream_t);
+INST_OUTER(double, double, double, double)
+INST_OUTER(double, double, double, float)
+INST_OUTER(double, float, float, float)
+INST_OUTER(double, float, float, double)
+INST_OUTER(float, float, float, float)
+INST_OUTER(float, float, float, double)
+
+}  // namespace mg

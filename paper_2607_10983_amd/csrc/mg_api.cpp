@@ -1,0 +1,878 @@
+// Host side of the C ABI declared in include/mg.h: parameter validation,
+// hierarchy allocation, Chebyshev schedules, coarsest-level solver setup and
+// the outer defect-correction loop.  All device work is issued on the
+// context's stream through the launchers of kernels.hip.
+#include "mg.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace mg;
+
+namespace {
+
+struct Level {
+    int n = 0;
+    size_t N = 0;
+    double h = 0, ih2 = 0;
+    void* x[2] = {nullptr, nullptr};  // inner iterates (ping-pong)
+    void* b = nullptr;                // inner right-hand side / restricted residual
+    void* coeff = nullptr;            // inner-precision coefficients (6 N), nullptr for 7-point
+    double lmax = 2.0;                // Gershgorin bound of D^-1 M
+    int cur = 0;                      // which x holds the current iterate
+    // smoothing schedule: step k computes x + a_k (x - x_prev) + c_k D^-1 (b - M x)
+    std::vector<double> a, c;
+};
+
+struct TimingPair {
+    hipEvent_t start, stop;
+};
+
+}  // namespace
+
+struct mg_ctx {
+    mg_params p{};
+    hipStream_t stream = nullptr;
+    bool var = false;
+    bool inner_double = true;   // inner V-cycle in double (MG_FP64) or float
+    std::vector<Level> lev;
+    // fine-level coefficients used by the outer residual
+    void* coeff_outer = nullptr;
+    bool coeff_outer_double = true;
+    bool coeff_outer_owned = false;
+    double* phi_tmp = nullptr;  // second buffer for the phi update
+    double* partials = nullptr;
+    int nparts = 0;
+    double* dscal = nullptr;    // device scalars
+    double* hscal = nullptr;    // pinned host mirror
+    double* Q = nullptr;        // coarsest seven-point basis and eigenvalues
+    double* lam1 = nullptr;
+    double* G = nullptr;        // coarsest variable-coefficient pseudo-inverse
+    double* scratch = nullptr;  // double scratch for the single-step entry points
+    size_t scratch_elems = 0;
+    std::string err;
+    // timing of the fine-level smoothing kernel
+    bool timing = false;
+    std::vector<TimingPair> events;
+    size_t events_used = 0;
+    int timed_launches = 0;
+    double timed_ms = 0.0;
+    double timed_bytes = 0.0;
+};
+
+namespace {
+
+const char* kStatus[] = {"MG_OK",
+                         "MG_ERR_INVALID: invalid argument",
+                         "MG_ERR_INVALID_COEFF: coefficient field not finite or with a non-positive diagonal component",
+                         "MG_ERR_NOMEM: device allocation failed",
+                         "MG_ERR_HIP: HIP runtime error",
+                         "MG_ERR_NONFINITE: NaN or Inf encountered",
+                         "MG_ERR_NOT_CONVERGED: tolerance not reached"};
+
+mg_status fail(mg_ctx* ctx, mg_status s, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    return s;
+}
+
+#define HIPCHK(ctx, ...)                                                                           \
+    do {                                                                                           \
+        hipError_t e_ = (__VA_ARGS__);                                                             \
+        if (e_ != hipSuccess)                                                                      \
+            return fail((ctx), MG_ERR_HIP, std::string(#__VA_ARGS__) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+mg_status dalloc(mg_ctx* ctx, void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) return MG_OK;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(ctx, MG_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    return MG_OK;
+}
+
+void dfree(void* p) {
+    if (p) (void)hipFree(p);
+}
+
+int coarsest_n(const mg_params& p) { return p.n >> (p.levels - 1); }
+
+// Chebyshev schedule on [lmax/alpha, lmax] (three-term recurrence, x_prev form).
+void make_schedule(const mg_params& p, Level& L) {
+    L.a.clear();
+    L.c.clear();
+    if (p.smoother == MG_JACOBI) {
+        for (int k = 0; k < p.jacobi_sweeps; ++k) {
+            L.a.push_back(0.0);
+            L.c.push_back(p.jacobi_omega);
+        }
+        return;
+    }
+    const double lmin = L.lmax / p.cheb_alpha;
+    const double theta = 0.5 * (L.lmax + lmin), delta = 0.5 * (L.lmax - lmin), sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    L.a.push_back(0.0);
+    L.c.push_back(1.0 / theta);
+    for (int k = 1; k < p.cheb_degree; ++k) {
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        L.a.push_back(rn * rho);
+        L.c.push_back(2.0 * rn / delta);
+        rho = rn;
+    }
+}
+
+// Real orthonormal Fourier basis of the periodic second difference on nc points.
+void flat_basis(int nc, double hc, std::vector<double>& Q, std::vector<double>& lam) {
+    Q.assign((size_t)nc * nc, 0.0);
+    lam.assign(nc, 0.0);
+    const double pi = std::acos(-1.0);
+    auto eig = [&](int m) { double s = std::sin(pi * m / nc); return -4.0 * s * s / (hc * hc); };
+    for (int j = 0; j < nc; ++j) Q[j + nc * 0] = 1.0 / std::sqrt((double)nc);
+    lam[0] = 0.0;
+    for (int m = 1; m < nc / 2; ++m) {
+        for (int j = 0; j < nc; ++j) {
+            Q[j + nc * (2 * m - 1)] = std::sqrt(2.0 / nc) * std::cos(2.0 * pi * m * j / nc);
+            Q[j + nc * (2 * m)] = std::sqrt(2.0 / nc) * std::sin(2.0 * pi * m * j / nc);
+        }
+        lam[2 * m - 1] = lam[2 * m] = eig(m);
+    }
+    for (int j = 0; j < nc; ++j) Q[j + nc * (nc - 1)] = (j % 2 ? -1.0 : 1.0) / std::sqrt((double)nc);
+    lam[nc - 1] = eig(nc / 2);
+}
+
+// Dense matrix of the 19-point operator on the coarsest level (host, double).
+void assemble_dense(int n, double ih2, const std::vector<double>& C, std::vector<double>& M) {
+    const int N = n * n * n;
+    M.assign((size_t)N * N, 0.0);
+    auto id = [n](int x, int y, int z) { return (((z % n + n) % n) * n + ((y % n + n) % n)) * n + ((x % n + n) % n); };
+    auto cc = [&](int c, int x, int y, int z) { return C[(size_t)c * N + id(x, y, z)]; };
+    for (int z = 0; z < n; ++z)
+        for (int y = 0; y < n; ++y)
+            for (int x = 0; x < n; ++x) {
+                const int i = id(x, y, z);
+                const int p[3] = {x, y, z};
+                for (int a = 0; a < 3; ++a)
+                    for (int s = -1; s <= 1; s += 2) {
+                        int q[3] = {p[0], p[1], p[2]};
+                        q[a] += s;
+                        const double cf = 0.5 * (cc(a, x, y, z) + cc(a, q[0], q[1], q[2]));
+                        M[(size_t)i * N + id(q[0], q[1], q[2])] += cf * ih2;
+                        M[(size_t)i * N + i] -= cf * ih2;
+                    }
+                const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+                for (int k = 0; k < 3; ++k) {
+                    const int a = pa[k], b = pb[k], comp = 3 + k;
+                    for (int sa = -1; sa <= 1; sa += 2)
+                        for (int sb = -1; sb <= 1; sb += 2) {
+                            int qa[3] = {p[0], p[1], p[2]}, qb[3] = {p[0], p[1], p[2]}, q[3] = {p[0], p[1], p[2]};
+                            qa[a] += sa;
+                            qb[b] += sb;
+                            q[a] += sa;
+                            q[b] += sb;
+                            const double v = sa * sb * (cc(comp, qa[0], qa[1], qa[2]) + cc(comp, qb[0], qb[1], qb[2])) * 0.25 * ih2;
+                            M[(size_t)i * N + id(q[0], q[1], q[2])] += v;
+                        }
+                }
+            }
+}
+
+// Zero-mean pseudo-inverse of a symmetric semidefinite M with null space span(1):
+// B = M - s 11^T / N is definite, and G = P B^-1 P with P = I - 11^T / N.
+bool pseudo_inverse(int N, const std::vector<double>& M, std::vector<double>& G) {
+    double s = 0.0;
+    for (int i = 0; i < N; ++i) s += std::fabs(M[(size_t)i * N + i]);
+    s /= N;
+    std::vector<double> A((size_t)N * 2 * N, 0.0);
+    for (int i = 0; i < N; ++i) {
+        for (int j = 0; j < N; ++j) A[(size_t)i * 2 * N + j] = M[(size_t)i * N + j] - s / N;
+        A[(size_t)i * 2 * N + N + i] = 1.0;
+    }
+    const int W = 2 * N;
+    for (int col = 0; col < N; ++col) {  // Gauss-Jordan with partial pivoting
+        int piv = col;
+        for (int r = col + 1; r < N; ++r)
+            if (std::fabs(A[(size_t)r * W + col]) > std::fabs(A[(size_t)piv * W + col])) piv = r;
+        if (A[(size_t)piv * W + col] == 0.0) return false;
+        if (piv != col)
+            for (int j = 0; j < W; ++j) std::swap(A[(size_t)piv * W + j], A[(size_t)col * W + j]);
+        const double inv = 1.0 / A[(size_t)col * W + col];
+        for (int j = 0; j < W; ++j) A[(size_t)col * W + j] *= inv;
+        for (int r = 0; r < N; ++r) {
+            if (r == col) continue;
+            const double f = A[(size_t)r * W + col];
+            if (f == 0.0) continue;
+            for (int j = 0; j < W; ++j) A[(size_t)r * W + j] -= f * A[(size_t)col * W + j];
+        }
+    }
+    std::vector<double> Bi((size_t)N * N);
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) Bi[(size_t)i * N + j] = A[(size_t)i * W + N + j];
+    // G = P Bi P
+    std::vector<double> rm(N, 0.0), cm(N, 0.0);
+    double tm = 0.0;
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+            rm[i] += Bi[(size_t)i * N + j] / N;
+            cm[j] += Bi[(size_t)i * N + j] / N;
+        }
+    for (int i = 0; i < N; ++i) tm += rm[i] / N;
+    G.assign((size_t)N * N, 0.0);
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) G[(size_t)i * N + j] = Bi[(size_t)i * N + j] - rm[i] - cm[j] + tm;
+    return true;
+}
+
+template <typename T>
+OpDesc<T> op_of(const Level& L) {
+    return OpDesc<T>{L.n, L.ih2, (const T*)L.coeff};
+}
+
+// ---- fine-level smoothing kernel timing ----------------------------------------------
+mg_status time_begin(mg_ctx* c, bool fine) {
+    if (!c->timing || !fine) return MG_OK;
+    if (c->events_used == c->events.size()) {
+        TimingPair tp;
+        HIPCHK(c, hipEventCreate(&tp.start));
+        HIPCHK(c, hipEventCreate(&tp.stop));
+        c->events.push_back(tp);
+    }
+    HIPCHK(c, hipEventRecord(c->events[c->events_used].start, c->stream));
+    return MG_OK;
+}
+mg_status time_end(mg_ctx* c, bool fine, double bytes) {
+    if (!c->timing || !fine) return MG_OK;
+    HIPCHK(c, hipEventRecord(c->events[c->events_used].stop, c->stream));
+    c->events_used++;
+    c->timed_launches++;
+    c->timed_bytes += bytes;
+    if (c->events_used >= 16384) {  // harvest to bound the pool
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (size_t i = 0; i < c->events_used; ++i) {
+            float ms = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&ms, c->events[i].start, c->events[i].stop));
+            c->timed_ms += ms;
+        }
+        c->events_used = 0;
+    }
+    return MG_OK;
+}
+
+// ---- inner V-cycle ----------------------------------------------------------------------
+// One smoothing pass on level l in inner precision T.  from_zero: the iterate is 0.
+template <typename T>
+mg_status smooth_level(mg_ctx* c, int l, bool from_zero) {
+    Level& L = c->lev[l];
+    const OpDesc<T> op = op_of<T>(L);
+    int cur = L.cur;
+    int prev = -1;  // buffer of x_{k-1}, -1 when x_{k-1} = 0 or not needed
+    const bool cheb = c->p.smoother == MG_CHEBYSHEV;
+    const bool fine = (l == 0);
+    const double fbytes = (double)L.N * sizeof(T);
+    const double cbytes = c->var ? 6.0 * (double)L.N * sizeof(T) : 0.0;
+    for (size_t k = 0; k < L.a.size(); ++k) {
+        double bytes = 0.0;
+        T* X0 = (T*)L.x[0];
+        T* X1 = (T*)L.x[1];
+        T* bufs[2] = {X0, X1};
+        mg_status st = time_begin(c, fine);
+        if (st != MG_OK) return st;
+        if (k == 0 && from_zero) {
+            HIPCHK(c, launch_smooth_step<T, T>(op, nullptr, nullptr, (const T*)L.b, bufs[0], 0.0, L.c[0], c->stream));
+            bytes = 2.0 * fbytes + cbytes;  // read b (and C for D), write x
+            cur = 0;
+            prev = -1;
+        } else {
+            const T* xp = (cheb && prev >= 0) ? bufs[prev] : nullptr;
+            const int out = (cheb && prev >= 0) ? prev : 1 - cur;
+            HIPCHK(c, launch_smooth_step<T, T>(op, bufs[cur], xp, (const T*)L.b, bufs[out], L.a[k], L.c[k],
+                                               c->stream));
+            bytes = (xp ? 4.0 : 3.0) * fbytes + cbytes;  // read x, [x_prev], b (, C); write out
+            prev = cur;
+            cur = out;
+        }
+        st = time_end(c, fine, bytes);
+        if (st != MG_OK) return st;
+    }
+    L.cur = cur;
+    return MG_OK;
+}
+
+template <typename T>
+mg_status coarse_level(mg_ctx* c, int l) {
+    Level& L = c->lev[l];
+    L.cur = 0;
+    if (!c->var)
+        HIPCHK(c, launch_coarse_flat<T>(L.n, c->Q, c->lam1, (const T*)L.b, (T*)L.x[0], c->stream));
+    else
+        HIPCHK(c, launch_coarse_dense<T>((int)L.N, c->G, (const T*)L.b, (T*)L.x[0], c->stream));
+    return MG_OK;
+}
+
+// x_l = V(0, b_l)
+template <typename T>
+mg_status vcycle_from_zero(mg_ctx* c, int l) {
+    const int last = (int)c->lev.size() - 1;
+    if (l == last) return coarse_level<T>(c, l);
+    Level& L = c->lev[l];
+    Level& Lc = c->lev[l + 1];
+    mg_status st = smooth_level<T>(c, l, true);
+    if (st != MG_OK) return st;
+    HIPCHK(c, launch_residual_restrict<T, T>(op_of<T>(L), (const T*)L.x[L.cur], (const T*)L.b, (T*)Lc.b, c->stream));
+    st = vcycle_from_zero<T>(c, l + 1);
+    if (st != MG_OK) return st;
+    HIPCHK(c, launch_prolong_add<T>(L.n, (const T*)Lc.x[Lc.cur], (T*)L.x[L.cur], c->stream));
+    return smooth_level<T>(c, l, false);
+}
+
+// ---- outer residual dispatch ---------------------------------------------------------------
+// r = (b - mean b) - M phi (phi = phi_in + e when e != null); per-block r^2 sums into partials.
+mg_status outer_residual(mg_ctx* c, const double* phi_in, const void* e, double* phi_out, const double* b,
+                         double bmean) {
+    Level& L = c->lev[0];
+    const int n = L.n;
+    const double ih2 = L.ih2;
+    hipError_t err;
+    if (c->p.precision == MG_FP64) {
+        OpDesc<double> op{n, ih2, (const double*)c->coeff_outer};
+        err = launch_outer_residual<double, double, double, double>(op, phi_in, (const double*)e, phi_out, b, bmean,
+                                                                    (double*)L.b, c->partials, c->stream);
+    } else if (c->p.precision == MG_MIXED) {
+        if (c->coeff_outer_double) {
+            OpDesc<double> op{n, ih2, (const double*)c->coeff_outer};
+            err = launch_outer_residual<double, float, float, double>(op, phi_in, (const float*)e, phi_out, b, bmean,
+                                                                      (float*)L.b, c->partials, c->stream);
+        } else {
+            OpDesc<float> op{n, ih2, (const float*)c->coeff_outer};
+            err = launch_outer_residual<double, float, float, float>(op, phi_in, (const float*)e, phi_out, b, bmean,
+                                                                     (float*)L.b, c->partials, c->stream);
+        }
+    } else {
+        OpDesc<float> op{n, ih2, (const float*)c->coeff_outer};
+        err = launch_outer_residual<float, float, float, float>(op, phi_in, (const float*)e, phi_out, b, bmean,
+                                                                (float*)L.b, c->partials, c->stream);
+    }
+    HIPCHK(c, err);
+    return MG_OK;
+}
+
+mg_status read_scalars(mg_ctx* c, int count) {
+    HIPCHK(c, hipMemcpyAsync(c->hscal, c->dscal, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return MG_OK;
+}
+
+mg_status inner_vcycle(mg_ctx* c) {
+    return c->inner_double ? vcycle_from_zero<double>(c, 0) : vcycle_from_zero<float>(c, 0);
+}
+
+const void* inner_e(mg_ctx* c) { return c->lev[0].x[c->lev[0].cur]; }
+
+mg_status check_ctx(mg_ctx* c) { return c ? MG_OK : MG_ERR_INVALID; }
+
+template <typename F>
+hipError_t with_op(mg_ctx* c, int level, F f) {
+    const Level& L = c->lev[level];
+    if (!c->var || c->inner_double) return f(OpDesc<double>{L.n, L.ih2, (const double*)L.coeff});
+    return f(OpDesc<float>{L.n, L.ih2, (const float*)L.coeff});
+}
+
+}  // namespace
+
+// =============================================================================================
+// C ABI
+// =============================================================================================
+extern "C" {
+
+const char* mg_status_string(mg_status s) {
+    if ((int)s < 0 || (int)s > 6) return "unknown mg_status";
+    return kStatus[(int)s];
+}
+
+const char* mg_last_error(const mg_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+mg_status mg_params_default(mg_params* p, int n) {
+    if (!p) return MG_ERR_INVALID;
+    p->n = n;
+    int lg = 0;
+    while ((1 << lg) < n) ++lg;
+    p->levels = lg - 1 > 1 ? lg - 1 : 1;
+    p->cheb_degree = 3;
+    p->cheb_alpha = 8.0;
+    p->h = n > 0 ? 1.0 / n : 0.0;
+    p->precision = MG_MIXED;
+    p->smoother = MG_CHEBYSHEV;
+    p->jacobi_omega = 2.0 / 3.0;
+    p->jacobi_sweeps = 2;
+    return MG_OK;
+}
+
+mg_status mg_validate_params(const mg_params* p) {
+    if (!p) return MG_ERR_INVALID;
+    if (!is_pow2(p->n) || p->n < 8 || p->n > 2048) return MG_ERR_INVALID;
+    if (p->levels < 1 || p->levels > 12) return MG_ERR_INVALID;
+    const int nc = coarsest_n(*p);
+    if (nc < 4 || nc > 16) return MG_ERR_INVALID;
+    if (p->cheb_degree < 1 || p->cheb_degree > 8) return MG_ERR_INVALID;
+    if (!(p->cheb_alpha > 1.0) || !std::isfinite(p->cheb_alpha)) return MG_ERR_INVALID;
+    if (!(p->h > 0.0) || !std::isfinite(p->h)) return MG_ERR_INVALID;
+    if (p->precision < MG_FP64 || p->precision > MG_FP32) return MG_ERR_INVALID;
+    if (p->smoother != MG_CHEBYSHEV && p->smoother != MG_JACOBI) return MG_ERR_INVALID;
+    if (p->smoother == MG_JACOBI) {
+        if (!(p->jacobi_omega > 0.0 && p->jacobi_omega < 2.0)) return MG_ERR_INVALID;
+        if (p->jacobi_sweeps < 1 || p->jacobi_sweeps > 16) return MG_ERR_INVALID;
+    }
+    return MG_OK;
+}
+
+mg_status mg_destroy(mg_ctx* c) {
+    if (!c) return MG_OK;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    for (auto& L : c->lev) {
+        dfree(L.x[0]);
+        dfree(L.x[1]);
+        dfree(L.b);
+        dfree(L.coeff);
+    }
+    if (c->coeff_outer_owned) dfree(c->coeff_outer);
+    dfree(c->phi_tmp);
+    dfree(c->partials);
+    dfree(c->dscal);
+    if (c->hscal) (void)hipHostFree(c->hscal);
+    dfree(c->Q);
+    dfree(c->lam1);
+    dfree(c->G);
+    dfree(c->scratch);
+    for (auto& e : c->events) {
+        (void)hipEventDestroy(e.start);
+        (void)hipEventDestroy(e.stop);
+    }
+    delete c;
+    return MG_OK;
+}
+
+static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype) {
+    const mg_params& p = c->p;
+    c->var = coeff != nullptr;
+    c->inner_double = p.precision == MG_FP64;
+    if (c->var && coarsest_n(p) > 8)
+        return fail(c, MG_ERR_INVALID, "variable-coefficient coarsest level must have at most 8^3 points");
+    const size_t Tsz = c->inner_double ? sizeof(double) : sizeof(float);
+    c->lev.resize(p.levels);
+    for (int l = 0; l < p.levels; ++l) {
+        Level& L = c->lev[l];
+        L.n = p.n >> l;
+        L.N = (size_t)L.n * L.n * L.n;
+        L.h = p.h * (double)(1 << l);
+        L.ih2 = 1.0 / (L.h * L.h);
+        mg_status st;
+        if ((st = dalloc(c, &L.x[0], L.N * Tsz)) != MG_OK) return st;
+        if ((st = dalloc(c, &L.x[1], L.N * Tsz)) != MG_OK) return st;
+        if ((st = dalloc(c, &L.b, L.N * Tsz)) != MG_OK) return st;
+    }
+    const size_t N0 = c->lev[0].N;
+    mg_status st;
+    if ((st = dalloc(c, (void**)&c->phi_tmp, N0 * sizeof(double))) != MG_OK) return st;
+    c->nparts = stencil_blocks(p.n);
+    if ((st = dalloc(c, (void**)&c->partials, (size_t)c->nparts * sizeof(double))) != MG_OK) return st;
+    if ((st = dalloc(c, (void**)&c->dscal, 16 * sizeof(double))) != MG_OK) return st;
+    HIPCHK(c, hipHostMalloc((void**)&c->hscal, 16 * sizeof(double), hipHostMallocDefault));
+
+    if (c->var) {
+        // fine coefficients in double, validated, restricted level by level
+        std::vector<double*> c64(p.levels, nullptr);
+        auto free64 = [&]() {
+            for (auto q : c64) dfree(q);
+        };
+        for (int l = 0; l < p.levels; ++l)
+            if ((st = dalloc(c, (void**)&c64[l], 6 * c->lev[l].N * sizeof(double))) != MG_OK) {
+                free64();
+                return st;
+            }
+        hipError_t e = coeff_dtype == MG_DTYPE_F64
+                           ? launch_convert<double, double>(6 * N0, (const double*)coeff, c64[0], c->stream)
+                           : launch_convert<double, float>(6 * N0, (const float*)coeff, c64[0], c->stream);
+        if (e != hipSuccess) { free64(); HIPCHK(c, e); }
+        e = launch_coeff_check<double>(p.n, c64[0], c->partials, c->stream);
+        if (e == hipSuccess) e = launch_finalize_sum(c->partials, c->nparts, c->dscal, 0, c->stream);
+        if (e != hipSuccess) { free64(); HIPCHK(c, e); }
+        if ((st = read_scalars(c, 1)) != MG_OK) { free64(); return st; }
+        if (c->hscal[0] != 0.0) {
+            free64();
+            return fail(c, MG_ERR_INVALID_COEFF,
+                        std::to_string((long long)c->hscal[0]) + " cells with non-finite or non-positive diagonal coefficients");
+        }
+        for (int l = 0; l + 1 < p.levels; ++l) {
+            e = launch_restrict<double>(c->lev[l].n, c64[l], c64[l + 1], 6, c->stream);
+            if (e != hipSuccess) { free64(); HIPCHK(c, e); }
+        }
+        for (int l = 0; l + 1 < p.levels; ++l) {
+            OpDesc<double> op{c->lev[l].n, c->lev[l].ih2, c64[l]};
+            e = launch_gershgorin<double>(op, c->partials, c->stream);
+            if (e == hipSuccess) e = launch_finalize_max(c->partials, stencil_blocks(c->lev[l].n), c->dscal, 0, c->stream);
+            if (e != hipSuccess) { free64(); HIPCHK(c, e); }
+            if ((st = read_scalars(c, 1)) != MG_OK) { free64(); return st; }
+            c->lev[l].lmax = c->hscal[0];
+        }
+        // coarsest dense pseudo-inverse (host, double)
+        {
+            Level& Lc = c->lev.back();
+            std::vector<double> hc(6 * Lc.N), M, G;
+            e = hipMemcpyAsync(hc.data(), c64.back(), hc.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) { free64(); HIPCHK(c, e); }
+            assemble_dense(Lc.n, Lc.ih2, hc, M);
+            if (!pseudo_inverse((int)Lc.N, M, G)) {
+                free64();
+                return fail(c, MG_ERR_INVALID_COEFF, "coarsest operator is singular beyond its constant null space");
+            }
+            if ((st = dalloc(c, (void**)&c->G, G.size() * sizeof(double))) != MG_OK) { free64(); return st; }
+            e = hipMemcpyAsync(c->G, G.data(), G.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) { free64(); HIPCHK(c, e); }
+        }
+        // level storage in inner precision; outer fine copy
+        if (c->inner_double) {
+            for (int l = 0; l < p.levels; ++l) {
+                c->lev[l].coeff = c64[l];
+                c64[l] = nullptr;
+            }
+            c->coeff_outer = c->lev[0].coeff;
+            c->coeff_outer_double = true;
+            c->coeff_outer_owned = false;
+        } else {
+            for (int l = 0; l < p.levels; ++l) {
+                if ((st = dalloc(c, &c->lev[l].coeff, 6 * c->lev[l].N * sizeof(float))) != MG_OK) { free64(); return st; }
+                e = launch_convert<float, double>(6 * c->lev[l].N, c64[l], (float*)c->lev[l].coeff, c->stream);
+                if (e != hipSuccess) { free64(); HIPCHK(c, e); }
+            }
+            if (p.precision == MG_MIXED && coeff_dtype == MG_DTYPE_F64) {
+                c->coeff_outer = c64[0];  // keep the caller's double values for the outer residual
+                c64[0] = nullptr;
+                c->coeff_outer_double = true;
+                c->coeff_outer_owned = true;
+            } else {
+                c->coeff_outer = c->lev[0].coeff;
+                c->coeff_outer_double = false;
+                c->coeff_outer_owned = false;
+            }
+        }
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        free64();
+    } else {
+        Level& Lc = c->lev.back();
+        std::vector<double> Q, lam;
+        flat_basis(Lc.n, Lc.h, Q, lam);
+        if ((st = dalloc(c, (void**)&c->Q, Q.size() * sizeof(double))) != MG_OK) return st;
+        if ((st = dalloc(c, (void**)&c->lam1, lam.size() * sizeof(double))) != MG_OK) return st;
+        HIPCHK(c, hipMemcpyAsync(c->Q, Q.data(), Q.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->lam1, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->coeff_outer = nullptr;
+    }
+    for (auto& L : c->lev) make_schedule(p, L);
+    return MG_OK;
+}
+
+mg_status mg_create(const mg_params* p, const void* coeff, int coeff_dtype, void* stream, mg_ctx** out) {
+    if (!out) return MG_ERR_INVALID;
+    *out = nullptr;
+    if (mg_validate_params(p) != MG_OK) return MG_ERR_INVALID;
+    if (coeff && coeff_dtype != MG_DTYPE_F32 && coeff_dtype != MG_DTYPE_F64) return MG_ERR_INVALID;
+    mg_ctx* c = new (std::nothrow) mg_ctx();
+    if (!c) return MG_ERR_NOMEM;
+    c->p = *p;
+    c->stream = (hipStream_t)stream;
+    mg_status st = create_impl(c, coeff, coeff_dtype);
+    if (st != MG_OK) {
+        std::fprintf(stderr, "mg_create: %s\n", c->err.c_str());
+        mg_destroy(c);
+        return st;
+    }
+    *out = c;
+    return MG_OK;
+}
+
+mg_status mg_set_stream(mg_ctx* c, void* stream) {
+    if (!c) return MG_ERR_INVALID;
+    c->stream = (hipStream_t)stream;
+    return MG_OK;
+}
+
+// mean of b into dscal[slot] (sum), then the caller divides
+static mg_status device_sum(mg_ctx* c, const double* u, double shift, int pw, int slot) {
+    HIPCHK(c, launch_block_sums(c->p.n, u, shift, pw, c->partials, c->stream));
+    HIPCHK(c, launch_finalize_sum(c->partials, c->nparts, c->dscal, slot, c->stream));
+    return MG_OK;
+}
+
+static mg_status solve_impl(mg_ctx* c, double* phi, const double* b, double tol, int max_cycles,
+                            mg_solve_info* info) {
+    const size_t N0 = c->lev[0].N;
+    const double invN = 1.0 / (double)N0;
+    mg_status st;
+    if ((st = device_sum(c, b, 0.0, 1, 0)) != MG_OK) return st;
+    if ((st = read_scalars(c, 1)) != MG_OK) return st;
+    const double bmean = c->hscal[0] * invN;
+    if (!std::isfinite(bmean)) return fail(c, MG_ERR_NONFINITE, "source contains NaN or Inf");
+    if ((st = device_sum(c, b, bmean, 2, 1)) != MG_OK) return st;
+    if ((st = outer_residual(c, phi, nullptr, nullptr, b, bmean)) != MG_OK) return st;
+    HIPCHK(c, launch_finalize_sum(c->partials, c->nparts, c->dscal, 2, c->stream));
+    if ((st = read_scalars(c, 3)) != MG_OK) return st;
+    const double nb = std::sqrt(c->hscal[1]);
+    if (info) {
+        info->cycles = 0;
+        info->rel_res0 = info->rel_res = 0.0;
+    }
+    if (nb == 0.0) {
+        HIPCHK(c, launch_fill<double>(N0, 0.0, phi, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (info && info->history && info->history_cap > 0) info->history[0] = 0.0;
+        return MG_OK;
+    }
+    double rel = std::sqrt(c->hscal[2]) / nb;
+    if (!std::isfinite(rel)) return fail(c, MG_ERR_NONFINITE, "initial residual is not finite (NaN/Inf in phi?)");
+    if (info) {
+        info->rel_res0 = rel;
+        if (info->history && info->history_cap > 0) info->history[0] = rel;
+    }
+    double* cur = phi;
+    double* other = c->phi_tmp;
+    int cycles = 0;
+    double prev1 = INFINITY, prev2 = INFINITY;
+    mg_status result = MG_OK;
+    while (rel > tol && cycles < max_cycles) {
+        if ((st = inner_vcycle(c)) != MG_OK) return st;
+        if ((st = outer_residual(c, cur, inner_e(c), other, b, bmean)) != MG_OK) return st;
+        HIPCHK(c, launch_finalize_sum(c->partials, c->nparts, c->dscal, 2, c->stream));
+        std::swap(cur, other);
+        if ((st = read_scalars(c, 3)) != MG_OK) return st;
+        prev2 = prev1;
+        prev1 = rel;
+        rel = std::sqrt(c->hscal[2]) / nb;
+        ++cycles;
+        if (info && info->history && cycles < info->history_cap) info->history[cycles] = rel;
+        if (!std::isfinite(rel)) {
+            result = fail(c, MG_ERR_NONFINITE, "residual became non-finite");
+            break;
+        }
+        // stagnation at the rounding floor: no decrease over two consecutive cycles
+        if (rel >= 0.999 * prev1 && prev1 >= 0.999 * prev2) break;
+    }
+    if (result == MG_OK && rel > tol) {
+        result = MG_ERR_NOT_CONVERGED;
+        c->err = "relative residual " + std::to_string(rel) + " > tol after " + std::to_string(cycles) + " cycles";
+    }
+    // gauge: phi <- cur - mean(cur)
+    if ((st = device_sum(c, cur, 0.0, 1, 3)) != MG_OK) return st;
+    if ((st = read_scalars(c, 4)) != MG_OK) return st;
+    HIPCHK(c, launch_shift(N0, cur, c->hscal[3] * invN, phi, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (info) {
+        info->cycles = cycles;
+        info->rel_res = rel;
+    }
+    return result;
+}
+
+mg_status mg_solve(mg_ctx* c, double* phi, const double* b, double tol, int max_cycles, mg_solve_info* info) {
+    if (!c || !phi || !b || max_cycles < 0 || !(tol >= 0.0)) return fail(c, MG_ERR_INVALID, "invalid solve arguments");
+    if (phi == b) return fail(c, MG_ERR_INVALID, "phi and b must not alias");
+    return solve_impl(c, phi, b, tol, max_cycles, info);
+}
+
+mg_status mg_solve_adjoint(mg_ctx* c, double* lam, const double* phibar, double tol, int max_cycles,
+                           mg_solve_info* info) {
+    if (!c || !lam || !phibar || max_cycles < 0 || !(tol >= 0.0))
+        return fail(c, MG_ERR_INVALID, "invalid adjoint-solve arguments");
+    if (lam == phibar) return fail(c, MG_ERR_INVALID, "lam and phibar must not alias");
+    // M = M^T: the adjoint system is the forward system with the cotangent as source.
+    return solve_impl(c, lam, phibar, tol, max_cycles, info);
+}
+
+mg_status mg_vcycle(mg_ctx* c, double* phi, const double* b, double* rel_res_out) {
+    if (!c || !phi || !b) return fail(c, MG_ERR_INVALID, "invalid vcycle arguments");
+    if (phi == b) return fail(c, MG_ERR_INVALID, "phi and b must not alias");
+    const size_t N0 = c->lev[0].N;
+    const double invN = 1.0 / (double)N0;
+    mg_status st;
+    if ((st = device_sum(c, b, 0.0, 1, 0)) != MG_OK) return st;
+    if ((st = read_scalars(c, 1)) != MG_OK) return st;
+    const double bmean = c->hscal[0] * invN;
+    if ((st = outer_residual(c, phi, nullptr, nullptr, b, bmean)) != MG_OK) return st;
+    if ((st = inner_vcycle(c)) != MG_OK) return st;
+    const void* e = inner_e(c);
+    if (c->inner_double) HIPCHK(c, launch_add<double>(N0, phi, (const double*)e, phi, c->stream));
+    else HIPCHK(c, launch_add<float>(N0, phi, (const float*)e, phi, c->stream));
+    if (rel_res_out) {
+        if ((st = device_sum(c, b, bmean, 2, 1)) != MG_OK) return st;
+        if ((st = outer_residual(c, phi, nullptr, nullptr, b, bmean)) != MG_OK) return st;
+        HIPCHK(c, launch_finalize_sum(c->partials, c->nparts, c->dscal, 2, c->stream));
+        if ((st = read_scalars(c, 3)) != MG_OK) return st;
+        const double nb = std::sqrt(c->hscal[1]);
+        *rel_res_out = nb > 0 ? std::sqrt(c->hscal[2]) / nb : 0.0;
+    }
+    return MG_OK;
+}
+
+mg_status mg_coeff_grad(mg_ctx* c, const double* lam, const double* phi, void* cbar, int cbar_dtype) {
+    if (!c || !lam || !phi || !cbar) return fail(c, MG_ERR_INVALID, "invalid coeff_grad arguments");
+    if (!c->var) return fail(c, MG_ERR_INVALID, "coefficient gradient needs a variable-coefficient context");
+    const Level& L = c->lev[0];
+    if (cbar_dtype == MG_DTYPE_F64)
+        HIPCHK(c, launch_coeff_grad<double>(L.n, L.ih2, lam, phi, (double*)cbar, c->stream));
+    else if (cbar_dtype == MG_DTYPE_F32)
+        HIPCHK(c, launch_coeff_grad<float>(L.n, L.ih2, lam, phi, (float*)cbar, c->stream));
+    else
+        return fail(c, MG_ERR_INVALID, "cbar_dtype must be MG_DTYPE_F32 or MG_DTYPE_F64");
+    return MG_OK;
+}
+
+mg_status mg_geometry(int n, double h, const double* psi, void* C_out, int dtype, double* sqrtg_out, void* stream) {
+    if (!is_pow2(n) || n < 4 || n > 2048 || !(h > 0) || !psi || !C_out) return MG_ERR_INVALID;
+    const double ih2 = 1.0 / (h * h);
+    hipError_t e;
+    if (dtype == MG_DTYPE_F64) e = launch_geometry<double>(n, ih2, psi, (double*)C_out, sqrtg_out, (hipStream_t)stream);
+    else if (dtype == MG_DTYPE_F32) e = launch_geometry<float>(n, ih2, psi, (float*)C_out, sqrtg_out, (hipStream_t)stream);
+    else return MG_ERR_INVALID;
+    return e == hipSuccess ? MG_OK : MG_ERR_HIP;
+}
+
+mg_status mg_geometry_bwd(int n, double h, const double* psi, const double* Cbar, const double* sqrtgbar,
+                          double* psibar, void* stream) {
+    if (!is_pow2(n) || n < 4 || n > 2048 || !(h > 0) || !psi || !Cbar || !psibar) return MG_ERR_INVALID;
+    const double ih2 = 1.0 / (h * h);
+    const size_t N = (size_t)n * n * n;
+    double* Jbar = nullptr;
+    if (hipMalloc((void**)&Jbar, 6 * N * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return MG_ERR_NOMEM;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_geometry_bwd_cell(n, ih2, psi, Cbar, sqrtgbar, Jbar, s);
+    if (e == hipSuccess) e = launch_hessian_adjoint(n, ih2, Jbar, psibar, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(Jbar);
+    return e == hipSuccess ? MG_OK : MG_ERR_HIP;
+}
+
+// ---- single steps (double arithmetic on caller fields) ---------------------------------------
+static mg_status level_check(mg_ctx* c, int level, bool need_coarser) {
+    if (!c) return MG_ERR_INVALID;
+    if (level < 0 || level >= (int)c->lev.size()) return fail(c, MG_ERR_INVALID, "level out of range");
+    if (need_coarser && level + 1 >= (int)c->lev.size()) return fail(c, MG_ERR_INVALID, "no coarser level");
+    return MG_OK;
+}
+
+static mg_status ensure_scratch(mg_ctx* c, size_t elems) {
+    if (c->scratch_elems >= elems) return MG_OK;
+    dfree(c->scratch);
+    c->scratch = nullptr;
+    c->scratch_elems = 0;
+    mg_status st = dalloc(c, (void**)&c->scratch, elems * sizeof(double));
+    if (st == MG_OK) c->scratch_elems = elems;
+    return st;
+}
+
+mg_status mg_apply(mg_ctx* c, int level, const double* u, double* out) {
+    mg_status st = level_check(c, level, false);
+    if (st != MG_OK) return st;
+    if (!u || !out || u == out) return fail(c, MG_ERR_INVALID, "invalid apply arguments");
+    HIPCHK(c, with_op(c, level, [&](auto op) { return launch_apply<double>(op, u, out, c->stream); }));
+    return MG_OK;
+}
+
+mg_status mg_smooth(mg_ctx* c, int level, double* x, const double* b) {
+    mg_status st = level_check(c, level, false);
+    if (st != MG_OK) return st;
+    if (!x || !b || x == b) return fail(c, MG_ERR_INVALID, "invalid smooth arguments");
+    const Level& L = c->lev[level];
+    if ((st = ensure_scratch(c, L.N)) != MG_OK) return st;
+    double* bufs[2] = {x, c->scratch};
+    const bool cheb = c->p.smoother == MG_CHEBYSHEV;
+    int cur = 0, prev = -1;
+    for (size_t k = 0; k < L.a.size(); ++k) {
+        const bool use_prev = cheb && prev >= 0;
+        const double* xp = use_prev ? bufs[prev] : nullptr;
+        const int out = use_prev ? prev : 1 - cur;
+        HIPCHK(c, with_op(c, level, [&](auto op) {
+                   return launch_smooth_step<double>(op, bufs[cur], xp, b, bufs[out], L.a[k], L.c[k], c->stream);
+               }));
+        prev = cur;
+        cur = out;
+    }
+    if (cur != 0) HIPCHK(c, hipMemcpyAsync(x, bufs[cur], L.N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    return MG_OK;
+}
+
+mg_status mg_residual_restrict(mg_ctx* c, int level, const double* x, const double* b, double* coarse) {
+    mg_status st = level_check(c, level, true);
+    if (st != MG_OK) return st;
+    if (!b || !coarse) return fail(c, MG_ERR_INVALID, "invalid residual_restrict arguments");
+    HIPCHK(c, with_op(c, level, [&](auto op) { return launch_residual_restrict<double>(op, x, b, coarse, c->stream); }));
+    return MG_OK;
+}
+
+mg_status mg_prolong_add(mg_ctx* c, int level, const double* e, double* x) {
+    mg_status st = level_check(c, level, true);
+    if (st != MG_OK) return st;
+    if (!e || !x) return fail(c, MG_ERR_INVALID, "invalid prolong arguments");
+    HIPCHK(c, launch_prolong_add<double>(c->lev[level].n, e, x, c->stream));
+    return MG_OK;
+}
+
+mg_status mg_coarse_solve(mg_ctx* c, const double* r, double* e) {
+    if (!c || !r || !e || r == e) return fail(c, MG_ERR_INVALID, "invalid coarse_solve arguments");
+    const Level& L = c->lev.back();
+    if (!c->var) HIPCHK(c, launch_coarse_flat<double>(L.n, c->Q, c->lam1, r, e, c->stream));
+    else HIPCHK(c, launch_coarse_dense<double>((int)L.N, c->G, r, e, c->stream));
+    return MG_OK;
+}
+
+mg_status mg_level_lmax(const mg_ctx* c, double* out) {
+    if (!c || !out) return MG_ERR_INVALID;
+    for (size_t l = 0; l < c->lev.size(); ++l) out[l] = c->lev[l].lmax;
+    return MG_OK;
+}
+
+mg_status mg_enable_kernel_timing(mg_ctx* c, int enable) {
+    if (!c) return MG_ERR_INVALID;
+    c->timing = enable != 0;
+    c->events_used = 0;
+    c->timed_launches = 0;
+    c->timed_ms = 0.0;
+    c->timed_bytes = 0.0;
+    return MG_OK;
+}
+
+mg_status mg_kernel_timing(mg_ctx* c, int* launches, double* total_ms, double* alg_bytes) {
+    if (!c || !launches || !total_ms || !alg_bytes) return MG_ERR_INVALID;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < c->events_used; ++i) {
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->events[i].start, c->events[i].stop));
+        c->timed_ms += ms;
+    }
+    c->events_used = 0;
+    *launches = c->timed_launches;
+    *total_ms = c->timed_ms;
+    *alg_bytes = c->timed_bytes;
+    c->timed_launches = 0;
+    c->timed_ms = 0.0;
+    c->timed_bytes = 0.0;
+    return MG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,374 @@
+"""Parity of the HIP path (through the C ABI) with the CPU float64 oracle.
+
+Floating-point bars: plain float64 path <= 1e-12 relative L2 against the
+oracle (residual histories <= 1e-12 absolute; histories are already divided
+by ||b||); mixed precision <= 1e-10 relative error against the exact
+discrete solution; pure float32 plateau <= 1e-5.  Single steps are compared
+element by element at sizes that span several thread blocks and wrap the
+periodic boundary.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import mg_oracle as O  # noqa: E402
+from workloads import flat_source, moving_mesh_field, psi_unit  # noqa: E402
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PSI_SCALE = json.load(open(os.path.join(ROOT, "tests", "golden", "psi_scale.json")))["scale"]
+RNG = np.random.default_rng(2024)
+
+
+@pytest.fixture(scope="module")
+def mgpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2607_10983_amd as m
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def moving_mesh_coeff(n, dtype=np.float64):
+    """C and sqrt(g) of the admissible moving-mesh deformation (oracle geometry)."""
+    psi = PSI_SCALE[str(n)] * psi_unit(n)
+    C, sg = O.geometry(psi, 1.0 / n)
+    return psi, C.astype(dtype), sg
+
+
+def random_spd(n, amp=0.3):
+    A = amp * RNG.standard_normal((n, n, n, 3, 3))
+    S = np.eye(3) + A @ np.swapaxes(A, -1, -2)
+    idx = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
+    return np.stack([S[..., a, b] for a, b in idx])
+
+
+# ------------------------------------------------------------------ single steps
+
+@pytest.mark.parametrize("n", [8, 16, 64])
+@pytest.mark.parametrize("var", [False, True])
+def test_apply(mgpu, n, var):
+    C = random_spd(n) if var else None
+    levels = max(1, int(math.log2(n)) - 2)
+    mg = mgpu.Multigrid(n, levels=levels, coeff=dev(C) if var else None, precision="fp64")
+    u = RNG.standard_normal((n, n, n))
+    ref = O.apply_var(u, C, 1.0 / n) if var else O.apply_flat(u, 1.0 / n)
+    out = host(mg.apply(dev(u)))
+    assert np.max(np.abs(out - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("var", [False, True])
+@pytest.mark.parametrize("degree", [1, 3, 4])
+def test_smooth(mgpu, var, degree):
+    n = 16
+    C = random_spd(n) if var else None
+    mg = mgpu.Multigrid(n, levels=2, degree=degree, coeff=dev(C) if var else None, precision="fp64")
+    H = O.build_hierarchy(n, 2, degree, C=C)
+    x = RNG.standard_normal((n, n, n))
+    b = RNG.standard_normal((n, n, n))
+    ref = O.smooth(H, H.levels[0], x, b)
+    out = host(mg.smooth(dev(x), dev(b)))
+    assert rel(out, ref) <= 1e-13
+    if var:
+        assert mg.level_lmax()[0] == pytest.approx(H.levels[0].cheb.lmax, rel=1e-14)
+    else:
+        assert mg.level_lmax()[0] == 2.0
+
+
+def test_smooth_jacobi(mgpu):
+    n = 16
+    mg = mgpu.Multigrid(n, levels=2, smoother="jacobi", precision="fp64")
+    H = O.build_hierarchy(n, 2, 3, smoother="jacobi")
+    x = RNG.standard_normal((n, n, n))
+    b = RNG.standard_normal((n, n, n))
+    assert rel(host(mg.smooth(dev(x), dev(b))), O.smooth(H, H.levels[0], x, b)) <= 1e-13
+
+
+@pytest.mark.parametrize("n", [8, 32, 128])
+@pytest.mark.parametrize("var", [False, True])
+def test_residual_restrict_and_prolong(mgpu, n, var):
+    if var and n > 32:
+        pytest.skip("coarse coefficient levels of a large variable context are not needed here")
+    C = random_spd(n) if var else None
+    levels = max(2, int(math.log2(n)) - 2)
+    mg = mgpu.Multigrid(n, levels=levels, coeff=dev(C) if var else None, precision="fp64")
+    h = 1.0 / n
+    x = RNG.standard_normal((n, n, n))
+    b = RNG.standard_normal((n, n, n))
+    Mx = O.apply_var(x, C, h) if var else O.apply_flat(x, h)
+    ref = O.restrict_fw(b - Mx)
+    out = host(mg.residual_restrict(dev(x), dev(b)))
+    assert np.max(np.abs(out - ref)) <= 1e-13 * np.max(np.abs(ref))
+    out0 = host(mg.residual_restrict(None, dev(b)))
+    assert np.max(np.abs(out0 - O.restrict_fw(b))) <= 1e-15 * 10
+    e = RNG.standard_normal((n // 2,) * 3)
+    outp = host(mg.prolong_add(dev(e), dev(x)))
+    assert np.max(np.abs(outp - (x + O.prolong(e)))) <= 1e-15 * 10
+
+
+@pytest.mark.parametrize("nc", [4, 8, 16])
+def test_coarse_solve_flat(mgpu, nc):
+    n = nc * 4
+    mg = mgpu.Multigrid(n, levels=3, precision="fp64")
+    r = RNG.standard_normal((nc, nc, nc))
+    hc = 4.0 / n
+    ref = O.fft_solve(r - r.mean(), hc)
+    out = host(mg.coarse_solve(dev(r)))
+    assert rel(out, ref) <= 1e-13
+
+
+def test_coarse_solve_var(mgpu):
+    n = 16
+    C = random_spd(n)
+    mg = mgpu.Multigrid(n, levels=3, coeff=dev(C), precision="fp64")
+    H = O.build_hierarchy(n, 3, 3, C=C)
+    r = RNG.standard_normal((4, 4, 4))
+    ref = O.coarse_solve(H.levels[-1], r - r.mean())
+    out = host(mg.coarse_solve(dev(r)))
+    assert rel(out, ref) <= 1e-12
+
+
+# ------------------------------------------------------------------ V-cycle and solve
+
+@pytest.mark.parametrize("var", [False, True])
+def test_single_vcycle(mgpu, var):
+    n = 32
+    levels = 4 if not var else 3
+    C = moving_mesh_coeff(n)[1] if var else None
+    mg = mgpu.Multigrid(n, levels=levels, coeff=dev(C) if var else None, precision="fp64")
+    H = O.build_hierarchy(n, levels, 3, C=C)
+    b = flat_source(n, 3)
+    b -= b.mean()
+    phi = RNG.standard_normal((n, n, n))
+    ref = O.vcycle(H, 0, phi, b)
+    p = dev(phi)
+    r = mg.vcycle(p, dev(b), rel_res=True)
+    assert rel(host(p), ref) <= 1e-12
+    Mref = O.apply_var(ref, C, 1.0 / n) if var else O.apply_flat(ref, 1.0 / n)
+    assert r == pytest.approx(np.linalg.norm(b - Mref) / np.linalg.norm(b), rel=1e-10)
+
+
+def test_config1_fp64_solution_and_history(mgpu):
+    """32^3, 4 levels, Chebyshev degree 3, zero guess, 10 V-cycles, float64."""
+    n = 32
+    b = flat_source(n, 0)
+    mg = mgpu.Multigrid(n, levels=4, degree=3, precision="fp64")
+    phi, info = mg.solve(dev(b), tol=0.0, max_cycles=10, raise_on_error=False)
+    ref = O.solve(O.build_hierarchy(n, 4, 3), b, tol=0.0, max_cycles=10)
+    assert info.cycles == 10
+    assert rel(host(phi), ref.phi) <= 1e-12
+    assert np.max(np.abs(np.array(info.history) - np.array(ref.history))) <= 1e-12
+    assert abs(host(phi).mean()) < 1e-15
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-12), ("mixed", 1e-10)])
+def test_flat_solve_reaches_exact_solution(mgpu, precision, bar):
+    n = 64
+    b = flat_source(n, 1)
+    mg = mgpu.Multigrid(n, levels=5, degree=4, precision=precision)
+    phi, info = mg.solve(dev(b), tol=1e-13 if precision == "fp64" else 1e-11, max_cycles=40,
+                         raise_on_error=False)
+    exact = O.fft_solve(b - b.mean(), 1.0 / n)
+    err = float(rel(host(phi), exact))
+    assert err <= bar, err
+    assert info.rel_res <= (2e-13 if precision == "fp64" else 1e-11)
+
+
+def test_mixed_history_tracks_fp64(mgpu):
+    n = 64
+    b = flat_source(n, 2)
+    h64 = mgpu.Multigrid(n, levels=5, precision="fp64").solve(dev(b), tol=0, max_cycles=8, raise_on_error=False)[1]
+    hmx = mgpu.Multigrid(n, levels=5, precision="mixed").solve(dev(b), tol=0, max_cycles=8, raise_on_error=False)[1]
+    a, m = np.array(h64.history), np.array(hmx.history)
+    assert np.all(np.abs(m - a) <= 1e-4 * a + 1e-12)
+
+
+def test_fp32_plateau(mgpu):
+    n = 64
+    b = flat_source(n, 0)
+    mg = mgpu.Multigrid(n, levels=5, precision="fp32")
+    phi, info = mg.solve(dev(b), tol=1e-12, max_cycles=30, raise_on_error=False)
+    exact = O.fft_solve(b - b.mean(), 1.0 / n)
+    assert rel(host(phi), exact) <= 1e-5
+
+
+def test_warm_start_saves_cycles(mgpu):
+    n = 64
+    from workloads import Spectrum, grf
+    delta = grf(n, Spectrum(-1.0), 0)
+    mg = mgpu.Multigrid(n, levels=5, precision="mixed")
+    phi, i0 = mg.solve(dev(delta), tol=1e-10)
+    b1 = 1.05 * delta + 0.02 * grf(n, Spectrum(-1.0), 101)
+    _, cold = mg.solve(dev(b1), tol=1e-10)
+    _, warm = mg.solve(dev(b1), phi0=phi, tol=1e-10)
+    assert warm.cycles < cold.cycles
+    ref = O.fft_solve(b1 - b1.mean(), 1.0 / n)
+    phi1, _ = mg.solve(dev(b1), phi0=phi, tol=1e-11)
+    assert rel(host(phi1), ref) <= 1e-10
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-12), ("mixed", 1e-10)])
+@pytest.mark.parametrize("cdtype", [np.float64, np.float32])
+def test_moving_mesh_solve(mgpu, precision, bar, cdtype):
+    n = 32
+    psi, C, sg = moving_mesh_coeff(n, cdtype)
+    g = moving_mesh_field(n, 0)
+    b = sg * (g - np.sum(g * sg) / np.sum(sg))
+    Cd = C.astype(np.float64)
+    H = O.build_hierarchy(n, 4, 3, C=Cd)
+    ref = O.solve(H, b, tol=1e-13, max_cycles=200)
+    mg = mgpu.Multigrid(n, levels=4, coeff=dev(C), precision=precision)
+    phi, info = mg.solve(dev(b), tol=1e-13 if precision == "fp64" else 1e-11, max_cycles=200,
+                         raise_on_error=False)
+    assert info.rel_res <= (2e-13 if precision == "fp64" else 1e-11)
+    assert rel(host(phi), ref.phi) <= bar
+    if precision == "fp64":
+        lm = O.gershgorin_lmax_var(Cd, 1.0 / n)
+        assert mg.level_lmax()[0] == pytest.approx(lm, rel=1e-13)
+
+
+def test_moving_mesh_fp64_history(mgpu):
+    n = 32
+    psi, C, sg = moving_mesh_coeff(n)
+    b = moving_mesh_field(n, 0) * sg
+    mg = mgpu.Multigrid(n, levels=4, coeff=dev(C), precision="fp64")
+    phi, info = mg.solve(dev(b), tol=0.0, max_cycles=6, raise_on_error=False)
+    ref = O.solve(O.build_hierarchy(n, 4, 3, C=C), b, tol=0.0, max_cycles=6)
+    assert rel(host(phi), ref.phi) <= 1e-12
+    assert np.max(np.abs(np.array(info.history) - np.array(ref.history))) <= 1e-12
+
+
+# ------------------------------------------------------------------ adjoint, gradients, geometry
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_geometry_forward(mgpu, n):
+    psi = PSI_SCALE[str(n)] * psi_unit(n)
+    Cref, sref = O.geometry(psi, 1.0 / n)
+    C, sg = mgpu.geometry(dev(psi))
+    assert rel(host(sg), sref) <= 1e-14
+    assert np.max(np.abs(host(C) - Cref)) <= 1e-13 * np.max(np.abs(Cref))
+    C32, _ = mgpu.geometry(dev(psi), dtype=torch.float32)
+    assert np.max(np.abs(host(C32) - Cref)) <= 1e-6 * np.max(np.abs(Cref))
+
+
+def test_geometry_backward(mgpu):
+    n = 16
+    psi = PSI_SCALE[str(n)] * psi_unit(n)
+    Cbar = RNG.standard_normal((6, n, n, n))
+    sbar = RNG.standard_normal((n, n, n))
+    ref = O.geometry_bwd(psi, Cbar, sbar, 1.0 / n)
+    out = host(mgpu.geometry_bwd(dev(psi), dev(Cbar), dev(sbar)))
+    assert rel(out, ref) <= 1e-12
+    out0 = host(mgpu.geometry_bwd(dev(psi), dev(Cbar), None))
+    assert rel(out0, O.geometry_bwd(psi, Cbar, np.zeros((n, n, n)), 1.0 / n)) <= 1e-12
+
+
+def test_coeff_grad(mgpu):
+    n = 16
+    C = random_spd(n)
+    mg = mgpu.Multigrid(n, levels=2, coeff=dev(C), precision="fp64")
+    lam = RNG.standard_normal((n, n, n))
+    phi = RNG.standard_normal((n, n, n))
+    ref = O.coeff_grad(lam, phi, 1.0 / n)
+    out = host(mg.coeff_grad(dev(lam), dev(phi)))
+    assert np.max(np.abs(out - ref)) <= 1e-13 * np.max(np.abs(ref))
+    with pytest.raises(mgpu.MGError):
+        mgpu.Multigrid(n, levels=2, precision="fp64").coeff_grad(dev(lam), dev(phi))
+
+
+def test_adjoint_solve(mgpu):
+    n = 32
+    psi, C, sg = moving_mesh_coeff(n)
+    w = RNG.standard_normal((n, n, n))
+    mg = mgpu.Multigrid(n, levels=4, coeff=dev(C), precision="fp64")
+    lam, info = mg.solve_adjoint(dev(w), tol=1e-12, max_cycles=100)
+    ref = O.solve_adjoint(O.build_hierarchy(n, 4, 3, C=C), w, tol=1e-13, max_cycles=200)
+    assert rel(host(lam), ref.phi) <= 1e-11
+
+
+def test_autograd_matches_oracle_gradient(mgpu):
+    """L = sum(w * phi), phi = solve(b(psi), C(psi)); dL/dpsi and dL/db vs the oracle."""
+    n = 16
+    h = 1.0 / n
+    psi = PSI_SCALE[str(n)] * psi_unit(n)
+    g = moving_mesh_field(n, 0)
+    w = RNG.standard_normal((n, n, n))
+    # GPU: differentiable geometry + torch-built source + differentiable solve
+    psi_t = dev(psi).requires_grad_(True)
+    g_t = dev(g)
+    C_t, sg_t = mgpu.geometry_fn(psi_t)
+    b_t = sg_t * (g_t - (g_t * sg_t).sum() / sg_t.sum())
+    phi_t = mgpu.solve(b_t, C_t, tol=1e-13, max_cycles=200, levels=3, precision="fp64")
+    L = (dev(w) * phi_t).sum()
+    L.backward()
+    gpu_grad = host(psi_t.grad)
+    # oracle: same chain written with oracle pieces
+    C, sg = O.geometry(psi, h)
+    m = np.sum(g * sg) / np.sum(sg)
+    b = sg * (g - m)
+    H = O.build_hierarchy(n, 3, 3, C=C)
+    phi = O.solve(H, b, tol=1e-14, max_cycles=300).phi
+    lam = O.solve(H, w, tol=1e-14, max_cycles=300).phi
+    Cbar = O.coeff_grad(lam, phi, h)
+    # b = sg (g - m), m = sum(g sg)/sum(sg):  d/dsg
+    S = np.sum(sg)
+    sbar = lam * (g - m) - (g - m) / S * np.sum(lam * sg)
+    ref = O.geometry_bwd(psi, Cbar, sbar, h)
+    assert rel(gpu_grad, ref) <= 1e-8
+    assert float(L) == pytest.approx(np.sum(w * phi), rel=1e-11)
+
+
+# ------------------------------------------------------------------ errors, determinism
+
+def test_invalid_coefficients_rejected(mgpu):
+    n = 16
+    C = random_spd(n)
+    C[1, 3, 4, 5] = -1.0
+    with pytest.raises(mgpu.MGError) as e:
+        mgpu.Multigrid(n, levels=2, coeff=dev(C), precision="fp64")
+    assert e.value.status == 2
+    C = random_spd(n)
+    C[4, 0, 0, 0] = np.nan
+    with pytest.raises(mgpu.MGError):
+        mgpu.Multigrid(n, levels=2, coeff=dev(C), precision="mixed")
+
+
+def test_nonfinite_source_and_not_converged(mgpu):
+    n = 16
+    mg = mgpu.Multigrid(n, levels=2, precision="fp64")
+    b = RNG.standard_normal((n, n, n))
+    bad = b.copy()
+    bad[1, 2, 3] = np.inf
+    with pytest.raises(mgpu.MGError) as e:
+        mg.solve(dev(bad))
+    assert e.value.status == 5
+    phi, info = mg.solve(dev(b), tol=1e-30, max_cycles=3, raise_on_error=False)
+    assert info.status == 6 and info.cycles == 3
+    z, info = mg.solve(dev(np.full((n, n, n), 2.5)))
+    assert info.cycles == 0 and float(z.abs().max()) == 0.0
+
+
+def test_bitwise_reproducible(mgpu):
+    n = 64
+    b = dev(flat_source(n, 5))
+    mg = mgpu.Multigrid(n, levels=5, precision="mixed")
+    p1, i1 = mg.solve(b, tol=1e-10)
+    p2, i2 = mg.solve(b, tol=1e-10)
+    assert torch.equal(p1, p2) and i1.history == i2.history
