@@ -5,7 +5,7 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmg.so")
+LIB_PATH = os.environ.get("MG_LIBRARY") or os.path.join(HERE, "libmg.so")
 
 MG_OK = 0
 MG_ERR_INVALID = 1

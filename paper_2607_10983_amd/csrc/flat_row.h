@@ -1,0 +1,25 @@
+// Seven-point row-wave kernels (flat_row.hip): one wavefront per full x-row,
+// used for levels with 64 <= n <= 1024.  Internal interface.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace mg {
+
+bool row_kernels_apply(int n);
+// number of per-block partial sums k_outer_row writes for an n^3 grid
+int row_outer_blocks(int n);
+// Tuning knob: target number of blocks per launch (default 8192).
+void set_row_target_blocks(int target);
+
+template <typename T>
+hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, const T* b, T* out, double a,
+                             double cd, hipStream_t s);
+template <typename TA, typename TR, typename TE>
+hipError_t launch_outer_row(int n, double ih2, const double* phi_in, const TE* e, double* phi_out, const double* b,
+                            double bmean, TR* r, double* partials, hipStream_t s);
+template <typename T>
+hipError_t launch_rr_row(int n, double ih2, const T* x, const T* b, T* coarse, hipStream_t s);
+template <typename T>
+hipError_t launch_prolong_row(int n, const T* e, T* x, hipStream_t s);
+
+}  // namespace mg

@@ -1,0 +1,548 @@
+// Seven-point "row-wave" kernels for levels with 64 <= n <= 1024.
+//
+// One wavefront owns one whole x-row of the level: lane l holds the VEC = n/64
+// contiguous elements [l*VEC, (l+1)*VEC) and moves them with 16-byte vector
+// loads/stores, so a wave reads or writes n*sizeof(T) contiguous bytes per
+// row.  Because the wave spans the full periodic row, the x-neighbours of a
+// lane's first and last element come from the neighbouring lanes by rotating
+// cross-lane moves (the wrap-around included) and no x-halo is ever loaded.
+// The y-neighbour rows are the rows of the adjacent waves (served by L1/L2),
+// and z-neighbours come from a register queue as the wave marches a chunk of
+// planes.  Blocks of four
+// waves are renumbered so that consecutive row blocks land on the same XCD
+// and share their halo rows through that XCD's L2.
+#include "flat_row.h"
+
+#include <cstdint>
+
+namespace mg {
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kBlock = 64 * kWaves;
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v2i __attribute__((ext_vector_type(2)));
+
+// Row segment of VEC contiguous elements through 16-byte (or 8/4-byte) vector
+// accesses.  Plain cached accesses: measured faster than non-temporal ones
+// here, since streaming hints keep the fields out of the Infinity Cache.
+template <typename T, int VEC>
+__device__ __forceinline__ void ldrow(T (&v)[VEC], const T* p) {
+    constexpr int B = VEC * (int)sizeof(T);
+    if constexpr (B >= 16) {
+#pragma unroll
+        for (int k = 0; k < B / 16; ++k) {
+            const v4i t = *(reinterpret_cast<const v4i*>(p) + k);
+            __builtin_memcpy(&v[k * 16 / (int)sizeof(T)], &t, 16);
+        }
+    } else if constexpr (B == 8) {
+        const v2i t = *reinterpret_cast<const v2i*>(p);
+        __builtin_memcpy(&v[0], &t, 8);
+    } else {
+        v[0] = p[0];
+    }
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void strow(T* p, const T (&v)[VEC]) {
+    constexpr int B = VEC * (int)sizeof(T);
+    if constexpr (B >= 16) {
+#pragma unroll
+        for (int k = 0; k < B / 16; ++k) {
+            v4i t;
+            __builtin_memcpy(&t, &v[k * 16 / (int)sizeof(T)], 16);
+            *(reinterpret_cast<v4i*>(p) + k) = t;
+        }
+    } else if constexpr (B == 8) {
+        v2i t;
+        __builtin_memcpy(&t, &v[0], 8);
+        *reinterpret_cast<v2i*>(p) = t;
+    } else {
+        p[0] = v[0];
+    }
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void copyrow(T (&d)[VEC], const T (&s)[VEC]) {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) d[e] = s[e];
+}
+
+// Rotating cross-lane move: value of lane (lane + delta) mod 64.
+template <typename T>
+__device__ __forceinline__ T lane_rot(T v, int delta) {
+    const int lane = threadIdx.x & 63;
+    return __shfl(v, (lane + delta) & 63, 64);
+}
+
+// M x on one row: c = centre row, ym/yp = rows y-1/y+1, zm/zp = planes z-1/z+1.
+template <typename T, int VEC>
+__device__ __forceinline__ void flat7_row(const T (&c)[VEC], const T (&ym)[VEC], const T (&yp)[VEC],
+                                          const T (&zm)[VEC], const T (&zp)[VEC], T ih2, T (&Mx)[VEC]) {
+    const T lft = lane_rot(c[VEC - 1], -1);
+    const T rgt = lane_rot(c[0], 1);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        const T l = e > 0 ? c[e - 1] : lft;
+        const T r = e < VEC - 1 ? c[e + 1] : rgt;
+        Mx[e] = (((l + r) + (ym[e] + yp[e])) + (zm[e] + zp[e]) - T(6) * c[e]) * ih2;
+    }
+}
+
+// Block id renumbering so that each XCD (blocks are dealt round-robin to the
+// eight XCDs) receives a contiguous range of logical blocks.
+__device__ __forceinline__ int xcd_logical(int bid, int nb) {
+    if (nb & 7) return bid;
+    return (bid & 7) * (nb >> 3) + (bid >> 3);
+}
+
+struct RowGrid {
+    int n, mask;
+    __device__ __forceinline__ size_t row(int y, int z) const {
+        return ((size_t)(z & mask) * (size_t)n + (size_t)(y & mask)) * (size_t)n;
+    }
+};
+
+// =====================================================================================
+// Chebyshev / Jacobi step: out = x + a (x - xprev) + cd (b - M x), cd = c / D
+// =====================================================================================
+template <typename T, int VEC, bool HASX, bool PREV>
+__global__ __launch_bounds__(kBlock) void k_smooth_row(int n, T ih2, const T* x, const T* xprev,
+                                                       const T* __restrict__ b, T* out, T a, T cd, int nz,
+                                                       int nyb) {
+    const RowGrid g{n, n - 1};
+    const int lb = xcd_logical(blockIdx.x, gridDim.x);
+    const int yb = lb % nyb, zc = lb / nyb;
+    const int y = yb * kWaves + (threadIdx.x >> 6);
+    const int z0 = zc * nz;
+    const size_t off = (size_t)(threadIdx.x & 63) * VEC;
+    if constexpr (!HASX) {
+        for (int k = 0; k < nz; ++k) {
+            const size_t r = g.row(y, z0 + k) + off;
+            T bb[VEC], o[VEC];
+            ldrow<T, VEC>(bb, b + r);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) o[e] = cd * bb[e];
+            strow<T, VEC>(out + r, o);
+        }
+        return;
+    } else {
+        T zm[VEC], c[VEC], zp[VEC], ym[VEC], yp[VEC], bb[VEC], pp[VEC];
+        ldrow<T, VEC>(zm, x + g.row(y, z0 - 1) + off);
+        ldrow<T, VEC>(c, x + g.row(y, z0) + off);
+        ldrow<T, VEC>(zp, x + g.row(y, z0 + 1) + off);
+        ldrow<T, VEC>(ym, x + g.row(y - 1, z0) + off);
+        ldrow<T, VEC>(yp, x + g.row(y + 1, z0) + off);
+        ldrow<T, VEC>(bb, b + g.row(y, z0) + off);
+        if constexpr (PREV) ldrow<T, VEC>(pp, xprev + g.row(y, z0) + off);
+        for (int k = 0; k < nz; ++k) {
+            const int z = z0 + k;
+            // prefetch the next plane's operands before any store of this plane
+            T zpp[VEC], ymn[VEC], ypn[VEC], bn[VEC], pn[VEC];
+            const bool more = k + 1 < nz;
+            if (more) {
+                ldrow<T, VEC>(zpp, x + g.row(y, z + 2) + off);
+                ldrow<T, VEC>(ymn, x + g.row(y - 1, z + 1) + off);
+                ldrow<T, VEC>(ypn, x + g.row(y + 1, z + 1) + off);
+                ldrow<T, VEC>(bn, b + g.row(y, z + 1) + off);
+                if constexpr (PREV) ldrow<T, VEC>(pn, xprev + g.row(y, z + 1) + off);
+            }
+            T Mx[VEC], o[VEC];
+            flat7_row<T, VEC>(c, ym, yp, zm, zp, ih2, Mx);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                const T xp = PREV ? pp[e] : T(0);
+                o[e] = c[e] + a * (c[e] - xp) + cd * (bb[e] - Mx[e]);
+            }
+            strow<T, VEC>(out + g.row(y, z) + off, o);
+            if (more) {
+                copyrow(zm, c);
+                copyrow(c, zp);
+                copyrow(zp, zpp);
+                copyrow(ym, ymn);
+                copyrow(yp, ypn);
+                copyrow(bb, bn);
+                if constexpr (PREV) copyrow(pp, pn);
+            }
+        }
+    }
+}
+
+// =====================================================================================
+// Outer defect correction: value = phi_in (+ e); r = (b - bmean) - M value
+// =====================================================================================
+template <typename TA, typename TR, typename TE, int VEC, bool UPDATE>
+__device__ __forceinline__ void ld_value(TA (&v)[VEC], const double* phi, const TE* e, size_t r) {
+    double p[VEC];
+    ldrow<double, VEC>(p, phi + r);
+    if constexpr (UPDATE) {
+        TE q[VEC];
+        ldrow<TE, VEC>(q, e + r);
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) v[k] = (TA)(p[k] + (double)q[k]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) v[k] = (TA)p[k];
+    }
+}
+
+template <typename TA, typename TR, typename TE, int VEC, bool UPDATE>
+__global__ __launch_bounds__(kBlock) void k_outer_row(int n, TA ih2, const double* __restrict__ phi_in,
+                                                      const TE* __restrict__ e, double* __restrict__ phi_out,
+                                                      const double* __restrict__ b, double bmean,
+                                                      TR* __restrict__ r, double* __restrict__ partials, int nz,
+                                                      int nyb) {
+    __shared__ double sh[kWaves];
+    const RowGrid g{n, n - 1};
+    const int lb = xcd_logical(blockIdx.x, gridDim.x);
+    const int yb = lb % nyb, zc = lb / nyb;
+    const int wave = threadIdx.x >> 6;
+    const int y = yb * kWaves + wave;
+    const int z0 = zc * nz;
+    const size_t off = (size_t)(threadIdx.x & 63) * VEC;
+    TA zm[VEC], c[VEC], zp[VEC], ym[VEC], yp[VEC];
+    double bb[VEC];
+    ld_value<TA, TR, TE, VEC, UPDATE>(zm, phi_in, e, g.row(y, z0 - 1) + off);
+    ld_value<TA, TR, TE, VEC, UPDATE>(c, phi_in, e, g.row(y, z0) + off);
+    ld_value<TA, TR, TE, VEC, UPDATE>(zp, phi_in, e, g.row(y, z0 + 1) + off);
+    ld_value<TA, TR, TE, VEC, UPDATE>(ym, phi_in, e, g.row(y - 1, z0) + off);
+    ld_value<TA, TR, TE, VEC, UPDATE>(yp, phi_in, e, g.row(y + 1, z0) + off);
+    ldrow<double, VEC>(bb, b + g.row(y, z0) + off);
+    double ss = 0.0;
+    for (int k = 0; k < nz; ++k) {
+        const int z = z0 + k;
+        TA zpp[VEC], ymn[VEC], ypn[VEC];
+        double bn[VEC];
+        const bool more = k + 1 < nz;
+        if (more) {
+            ld_value<TA, TR, TE, VEC, UPDATE>(zpp, phi_in, e, g.row(y, z + 2) + off);
+            ld_value<TA, TR, TE, VEC, UPDATE>(ymn, phi_in, e, g.row(y - 1, z + 1) + off);
+            ld_value<TA, TR, TE, VEC, UPDATE>(ypn, phi_in, e, g.row(y + 1, z + 1) + off);
+            ldrow<double, VEC>(bn, b + g.row(y, z + 1) + off);
+        }
+        TA Mx[VEC];
+        TR ro[VEC];
+        flat7_row<TA, VEC>(c, ym, yp, zm, zp, ih2, Mx);
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) {
+            const TA ri = (TA)(bb[q] - bmean) - Mx[q];
+            ro[q] = (TR)ri;
+            ss += (double)ri * (double)ri;
+        }
+        const size_t row = g.row(y, z) + off;
+        strow<TR, VEC>(r + row, ro);
+        if constexpr (UPDATE) {
+            double po[VEC];
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) po[q] = (double)c[q];
+            // phi_out keeps the double sum phi + e (c holds it rounded to TA)
+            if constexpr (sizeof(TA) != sizeof(double)) {
+                double p[VEC];
+                TE qv[VEC];
+                ldrow<double, VEC>(p, phi_in + row);
+                ldrow<TE, VEC>(qv, e + row);
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) po[q] = p[q] + (double)qv[q];
+            }
+            strow<double, VEC>(phi_out + row, po);
+        }
+        if (more) {
+            copyrow(zm, c);
+            copyrow(c, zp);
+            copyrow(zp, zpp);
+            copyrow(ym, ymn);
+            copyrow(yp, ypn);
+            copyrow(bb, bn);
+        }
+    }
+    // fixed-order block reduction: wave butterfly, then the four wave sums
+    for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[wave] = ss;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// =====================================================================================
+// Residual + full-weighting restriction: one wave per coarse row Y, marching
+// fine planes; fine rows 2Y-1, 2Y, 2Y+1 are formed, combined in y, then in x
+// across lanes, then accumulated in z.
+// =====================================================================================
+template <typename T, int VEC>
+__global__ __launch_bounds__(kBlock) void k_rr_row(int n, T ih2, const T* __restrict__ x,
+                                                   const T* __restrict__ b, T* __restrict__ coarse, int nzc,
+                                                   int nyb) {
+    constexpr int CV = VEC >= 2 ? VEC / 2 : 1;
+    const int nc = n >> 1;
+    const RowGrid g{n, n - 1};
+    const RowGrid gc{nc, nc - 1};
+    const int lb = xcd_logical(blockIdx.x, gridDim.x);
+    const int yb = lb % nyb, zc = lb / nyb;
+    const int lane = threadIdx.x & 63;
+    const int Y = yb * kWaves + (threadIdx.x >> 6);
+    const int Z0 = zc * nzc;
+    const int y1 = 2 * Y;
+    const size_t off = (size_t)lane * VEC;
+    // x rows 2Y-2 .. 2Y+2 at plane z (index 0..4) and rows 2Y-1..2Y+1 at z-1, z+1
+    T c0[VEC], c1[VEC], c2[VEC];     // rows 2Y-1, 2Y, 2Y+1 at plane z
+    T m0[VEC], m1[VEC], m2[VEC];     // same rows at z-1
+    T p0[VEC], p1[VEC], p2[VEC];     // same rows at z+1
+    T hm[VEC], hp[VEC];              // rows 2Y-2, 2Y+2 at plane z
+    int z = 2 * Z0 - 1;
+    ldrow<T, VEC>(m0, x + g.row(y1 - 1, z - 1) + off);
+    ldrow<T, VEC>(m1, x + g.row(y1, z - 1) + off);
+    ldrow<T, VEC>(m2, x + g.row(y1 + 1, z - 1) + off);
+    ldrow<T, VEC>(c0, x + g.row(y1 - 1, z) + off);
+    ldrow<T, VEC>(c1, x + g.row(y1, z) + off);
+    ldrow<T, VEC>(c2, x + g.row(y1 + 1, z) + off);
+    T acc[CV];
+    const int nf = 2 * nzc + 1;
+    for (int k = 0; k < nf; ++k, ++z) {
+        ldrow<T, VEC>(p0, x + g.row(y1 - 1, z + 1) + off);
+        ldrow<T, VEC>(p1, x + g.row(y1, z + 1) + off);
+        ldrow<T, VEC>(p2, x + g.row(y1 + 1, z + 1) + off);
+        ldrow<T, VEC>(hm, x + g.row(y1 - 2, z) + off);
+        ldrow<T, VEC>(hp, x + g.row(y1 + 2, z) + off);
+        T b0[VEC], b1[VEC], b2[VEC];
+        ldrow<T, VEC>(b0, b + g.row(y1 - 1, z) + off);
+        ldrow<T, VEC>(b1, b + g.row(y1, z) + off);
+        ldrow<T, VEC>(b2, b + g.row(y1 + 1, z) + off);
+        T M0[VEC], M1[VEC], M2[VEC], s[VEC];
+        flat7_row<T, VEC>(c0, hm, c1, m0, p0, ih2, M0);
+        flat7_row<T, VEC>(c1, c0, c2, m1, p1, ih2, M1);
+        flat7_row<T, VEC>(c2, c1, hp, m2, p2, ih2, M2);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+            s[e] = T(0.25) * (b0[e] - M0[e]) + T(0.5) * (b1[e] - M1[e]) + T(0.25) * (b2[e] - M2[e]);
+        // x: coarse element q <-> fine 2q; needs fine 2q-1 (previous lane's last for q = 0)
+        T sx[CV];
+        if constexpr (VEC >= 2) {
+            const T lft = lane_rot(s[VEC - 1], -1);
+#pragma unroll
+            for (int q = 0; q < CV; ++q) {
+                const T l = q > 0 ? s[2 * q - 1] : lft;
+                sx[q] = T(0.25) * l + T(0.5) * s[2 * q] + T(0.25) * s[2 * q + 1];
+            }
+        } else {
+            const T l = lane_rot(s[0], -1), r = lane_rot(s[0], 1);
+            sx[0] = T(0.25) * l + T(0.5) * s[0] + T(0.25) * r;
+        }
+        // z: odd fine plane 2Z-1 opens coarse plane Z, 2Z adds 1/2, 2Z+1 closes it
+        const bool odd = (k & 1) == 0;  // k = 0 <-> z = 2 Z0 - 1
+        if (k == 0) {
+#pragma unroll
+            for (int q = 0; q < CV; ++q) acc[q] = T(0.25) * sx[q];
+        } else if (!odd) {
+#pragma unroll
+            for (int q = 0; q < CV; ++q) acc[q] += T(0.5) * sx[q];
+        } else {
+            const int Z = (z - 1) >> 1;
+#pragma unroll
+            for (int q = 0; q < CV; ++q) acc[q] += T(0.25) * sx[q];
+            if constexpr (VEC >= 2) {
+                strow<T, CV>(coarse + gc.row(Y, Z) + (size_t)lane * CV, acc);
+            } else {
+                if ((lane & 1) == 0) coarse[gc.row(Y, Z) + (lane >> 1)] = acc[0];
+            }
+#pragma unroll
+            for (int q = 0; q < CV; ++q) acc[q] = T(0.25) * sx[q];
+        }
+        copyrow(m0, c0);
+        copyrow(m1, c1);
+        copyrow(m2, c2);
+        copyrow(c0, p0);
+        copyrow(c1, p1);
+        copyrow(c2, p2);
+    }
+}
+
+// =====================================================================================
+// Trilinear prolongation + correction: x (fine row y, plane z) += P e
+// =====================================================================================
+template <typename T, int VEC>
+__device__ __forceinline__ void coarse_seg(T (&v)[VEC / 2 + 1], const T* row, int lane) {
+    constexpr int CV = VEC / 2;
+    T t[CV];
+    ldrow<T, CV>(t, row + (size_t)lane * CV);
+#pragma unroll
+    for (int q = 0; q < CV; ++q) v[q] = t[q];
+    v[CV] = lane_rot(t[0], 1);
+}
+
+template <typename T, int VEC>
+__global__ __launch_bounds__(kBlock) void k_prolong_row(int n, const T* __restrict__ e, T* __restrict__ x, int nz,
+                                                        int nyb) {
+    const int nc = n >> 1;
+    const RowGrid g{n, n - 1};
+    const RowGrid gc{nc, nc - 1};
+    const int lb = xcd_logical(blockIdx.x, gridDim.x);
+    const int yb = lb % nyb, zc = lb / nyb;
+    const int lane = threadIdx.x & 63;
+    const int y = yb * kWaves + (threadIdx.x >> 6);
+    const int z0 = zc * nz;
+    const int Y = y >> 1, oy = y & 1;
+    const size_t off = (size_t)lane * VEC;
+    for (int k = 0; k < nz; ++k) {
+        const int z = z0 + k;
+        const int Z = z >> 1, oz = z & 1;
+        T xv[VEC], p[VEC];
+        ldrow<T, VEC>(xv, x + g.row(y, z) + off);
+        if constexpr (VEC >= 2) {
+            constexpr int CW = VEC / 2 + 1;
+            T r00[CW], r01[CW], r10[CW], r11[CW], w[CW];
+            coarse_seg<T, VEC>(r00, e + gc.row(Y, Z), lane);
+            if (oy) coarse_seg<T, VEC>(r01, e + gc.row(Y + 1, Z), lane);
+            if (oz) coarse_seg<T, VEC>(r10, e + gc.row(Y, Z + 1), lane);
+            if (oy && oz) coarse_seg<T, VEC>(r11, e + gc.row(Y + 1, Z + 1), lane);
+#pragma unroll
+            for (int q = 0; q < CW; ++q) {
+                T a0 = oy ? T(0.5) * (r00[q] + r01[q]) : r00[q];
+                if (oz) {
+                    const T a1 = oy ? T(0.5) * (r10[q] + r11[q]) : r10[q];
+                    a0 = T(0.5) * (a0 + a1);
+                }
+                w[q] = a0;
+            }
+#pragma unroll
+            for (int q = 0; q < VEC / 2; ++q) {
+                p[2 * q] = w[q];
+                p[2 * q + 1] = T(0.5) * (w[q] + w[q + 1]);
+            }
+        } else {
+            const int X = lane >> 1, ox = lane & 1;
+            auto at = [&](int yy, int zz, int xx) { return e[gc.row(yy, zz) + (size_t)(xx & (nc - 1))]; };
+            T a = at(Y, Z, X), a1 = ox ? at(Y, Z, X + 1) : T(0);
+            T v = ox ? T(0.5) * (a + a1) : a;
+            if (oy) {
+                const T b0 = at(Y + 1, Z, X), b1 = ox ? at(Y + 1, Z, X + 1) : T(0);
+                v = T(0.5) * (v + (ox ? T(0.5) * (b0 + b1) : b0));
+            }
+            if (oz) {
+                T c0 = at(Y, Z + 1, X), c1 = ox ? at(Y, Z + 1, X + 1) : T(0);
+                T u = ox ? T(0.5) * (c0 + c1) : c0;
+                if (oy) {
+                    const T d0 = at(Y + 1, Z + 1, X), d1 = ox ? at(Y + 1, Z + 1, X + 1) : T(0);
+                    u = T(0.5) * (u + (ox ? T(0.5) * (d0 + d1) : d0));
+                }
+                v = T(0.5) * (v + u);
+            }
+            p[0] = v;
+        }
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) xv[q] += p[q];
+        strow<T, VEC>(x + g.row(y, z) + off, xv);
+    }
+}
+
+// ---- launch shapes -------------------------------------------------------------------
+// rows of the (n x n) plane grouped four per block; z split into chunks of nz
+// planes so that about `target` blocks are launched.
+int g_target_blocks = 8192;
+
+void shape(int rows, int planes, int min_nz, int& nz, int& nyb, int& blocks) {
+    nyb = rows / kWaves;
+    const int target = g_target_blocks;
+    nz = planes;
+    while (nz > min_nz && (long)nyb * (planes / nz) < target) nz >>= 1;
+    blocks = nyb * (planes / nz);
+}
+
+template <typename T>
+struct VecDispatch;
+
+}  // namespace
+
+void set_row_target_blocks(int target) {
+    if (target >= 64) g_target_blocks = target;
+}
+
+bool row_kernels_apply(int n) { return n >= 64 && n <= 1024 && (n & (n - 1)) == 0; }
+
+int row_outer_blocks(int n) {
+    int nz, nyb, blocks;
+    shape(n, n, 4, nz, nyb, blocks);
+    return blocks;
+}
+
+#define DISPATCH_VEC(n, ...)                                  \
+    switch (n) {                                              \
+        case 64: { constexpr int VEC = 1; __VA_ARGS__; break; }   \
+        case 128: { constexpr int VEC = 2; __VA_ARGS__; break; }  \
+        case 256: { constexpr int VEC = 4; __VA_ARGS__; break; }  \
+        case 512: { constexpr int VEC = 8; __VA_ARGS__; break; }  \
+        case 1024: { constexpr int VEC = 16; __VA_ARGS__; break; } \
+        default: return hipErrorInvalidValue;                 \
+    }
+
+template <typename T>
+hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, const T* b, T* out, double a,
+                             double cd, hipStream_t s) {
+    int nz, nyb, blocks;
+    shape(n, n, 4, nz, nyb, blocks);
+    DISPATCH_VEC(n, {
+        if (x == nullptr)
+            hipLaunchKernelGGL((k_smooth_row<T, VEC, false, false>), dim3(blocks), dim3(kBlock), 0, s, n, (T)ih2, x,
+                               xprev, b, out, (T)a, (T)cd, nz, nyb);
+        else if (xprev == nullptr)
+            hipLaunchKernelGGL((k_smooth_row<T, VEC, true, false>), dim3(blocks), dim3(kBlock), 0, s, n, (T)ih2, x,
+                               xprev, b, out, (T)a, (T)cd, nz, nyb);
+        else
+            hipLaunchKernelGGL((k_smooth_row<T, VEC, true, true>), dim3(blocks), dim3(kBlock), 0, s, n, (T)ih2, x,
+                               xprev, b, out, (T)a, (T)cd, nz, nyb);
+    })
+    return hipGetLastError();
+}
+
+template <typename TA, typename TR, typename TE>
+hipError_t launch_outer_row(int n, double ih2, const double* phi_in, const TE* e, double* phi_out, const double* b,
+                            double bmean, TR* r, double* partials, hipStream_t s) {
+    int nz, nyb, blocks;
+    shape(n, n, 4, nz, nyb, blocks);
+    DISPATCH_VEC(n, {
+        if (e)
+            hipLaunchKernelGGL((k_outer_row<TA, TR, TE, VEC, true>), dim3(blocks), dim3(kBlock), 0, s, n, (TA)ih2,
+                               phi_in, e, phi_out, b, bmean, r, partials, nz, nyb);
+        else
+            hipLaunchKernelGGL((k_outer_row<TA, TR, TE, VEC, false>), dim3(blocks), dim3(kBlock), 0, s, n, (TA)ih2,
+                               phi_in, e, phi_out, b, bmean, r, partials, nz, nyb);
+    })
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rr_row(int n, double ih2, const T* x, const T* b, T* coarse, hipStream_t s) {
+    const int nc = n / 2;
+    int nzc, nyb, blocks;
+    shape(nc, nc, 2, nzc, nyb, blocks);
+    DISPATCH_VEC(n, {
+        hipLaunchKernelGGL((k_rr_row<T, VEC>), dim3(blocks), dim3(kBlock), 0, s, n, (T)ih2, x, b, coarse, nzc, nyb);
+    })
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prolong_row(int n, const T* e, T* x, hipStream_t s) {
+    int nz, nyb, blocks;
+    shape(n, n, 4, nz, nyb, blocks);
+    DISPATCH_VEC(n, {
+        hipLaunchKernelGGL((k_prolong_row<T, VEC>), dim3(blocks), dim3(kBlock), 0, s, n, e, x, nz, nyb);
+    })
+    return hipGetLastError();
+}
+
+template hipError_t launch_smooth_row<float>(int, double, const float*, const float*, const float*, float*, double,
+                                             double, hipStream_t);
+template hipError_t launch_smooth_row<double>(int, double, const double*, const double*, const double*, double*,
+                                              double, double, hipStream_t);
+template hipError_t launch_rr_row<float>(int, double, const float*, const float*, float*, hipStream_t);
+template hipError_t launch_rr_row<double>(int, double, const double*, const double*, double*, hipStream_t);
+template hipError_t launch_prolong_row<float>(int, const float*, float*, hipStream_t);
+template hipError_t launch_prolong_row<double>(int, const double*, double*, hipStream_t);
+template hipError_t launch_outer_row<double, double, double>(int, double, const double*, const double*, double*,
+                                                             const double*, double, double*, double*, hipStream_t);
+template hipError_t launch_outer_row<double, float, float>(int, double, const double*, const float*, double*,
+                                                           const double*, double, float*, double*, hipStream_t);
+template hipError_t launch_outer_row<float, float, float>(int, double, const double*, const float*, double*,
+                                                          const double*, double, float*, double*, hipStream_t);
+
+}  // namespace mg

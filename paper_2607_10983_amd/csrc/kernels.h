@@ -19,6 +19,9 @@ struct OpDesc {
 // Number of thread blocks a stencil launch over an n^3 grid uses; partial
 // sums buffers must hold at least this many doubles.
 int stencil_blocks(int n);
+// Number of per-block partial sums launch_outer_residual writes (seven-point
+// operator when flat is true).
+int outer_blocks(int n, bool flat);
 
 // ---- smoothing (Chebyshev / Jacobi step) ---------------------------------
 // out = x + a (x - xprev) + c D^-1 (b - M x)      (xprev == nullptr: xprev = 0;
@@ -29,10 +32,13 @@ hipError_t launch_smooth_step(const OpDesc<TC>& op, const T* x, const T* xprev, 
                               T* out, double a, double c, hipStream_t s);
 
 // ---- residual + full-weighting restriction ---------------------------------
-// coarse = R(b - M x) on the (n/2)^3 grid; x == nullptr means x = 0.
+// coarse = R(b - M x) on the (n/2)^3 grid; x == nullptr means x = 0.  When the
+// fused row kernel does not apply and `scratch` (n^3 elements, distinct from
+// x, b and coarse) is given, the residual is formed there first and then
+// restricted (two passes); without scratch a fused gather kernel is used.
 template <typename T, typename TC>
 hipError_t launch_residual_restrict(const OpDesc<TC>& op, const T* x, const T* b, T* coarse,
-                                    hipStream_t s);
+                                    T* scratch, hipStream_t s);
 
 // coarse = R(fine), componentwise for `ncomp` consecutive fields.
 template <typename T>

@@ -7,6 +7,7 @@
 // per-block LDS trees in a fixed order followed by a single-block pass over
 // the partials, so every result is bitwise reproducible run to run.
 #include "kernels.h"
+#include "flat_row.h"
 
 #include <cmath>
 #include <cstdint>
@@ -319,9 +320,11 @@ __global__ __launch_bounds__(kThreads) void k_prolong_add(int n, const T* __rest
 // =====================================================================================
 // operator application
 // =====================================================================================
+// out = M x, or out = b - M x when b is given
 template <typename T, typename TC>
 __global__ __launch_bounds__(kThreads) void k_apply(int n, T ih2, const TC* __restrict__ C,
-                                                    const T* __restrict__ x, T* __restrict__ out, int nz) {
+                                                    const T* __restrict__ x, const T* __restrict__ b,
+                                                    T* __restrict__ out, int nz) {
     const Grid g{n, n - 1};
     const size_t N = (size_t)n * n * n;
     const int xi = blockIdx.x * blockDim.x + threadIdx.x;
@@ -337,7 +340,7 @@ __global__ __launch_bounds__(kThreads) void k_apply(int n, T ih2, const TC* __re
         } else {
             var_Mu<T, TC>(u, C, N, g, xi, yi, z, uc, ih2, Mu, D);
         }
-        out[i] = Mu;
+        out[i] = b ? b[i] - Mu : Mu;
     }
 }
 
@@ -764,9 +767,13 @@ int stencil_blocks(int n) {
     return (int)(s.grid.x * s.grid.y * s.grid.z);
 }
 
+int outer_blocks(int n, bool flat) { return flat && row_kernels_apply(n) ? row_outer_blocks(n) : stencil_blocks(n); }
+
 template <typename T, typename TC>
 hipError_t launch_smooth_step(const OpDesc<TC>& op, const T* x, const T* xprev, const T* b, T* out, double a,
                               double c, hipStream_t s) {
+    if (op.coeff == nullptr && row_kernels_apply(op.n))
+        return launch_smooth_row<T>(op.n, op.ih2, x, xprev, b, out, a, c / (-6.0 * op.ih2), s);
     Shape sh = stencil_shape(op.n);
     if (x == nullptr)
         hipLaunchKernelGGL((k_smooth<T, TC, false, false>), sh.grid, sh.block, 0, s, op.n, (T)op.ih2, op.coeff, x,
@@ -781,7 +788,17 @@ hipError_t launch_smooth_step(const OpDesc<TC>& op, const T* x, const T* xprev, 
 }
 
 template <typename T, typename TC>
-hipError_t launch_residual_restrict(const OpDesc<TC>& op, const T* x, const T* b, T* coarse, hipStream_t s) {
+hipError_t launch_residual_restrict(const OpDesc<TC>& op, const T* x, const T* b, T* coarse, T* scratch,
+                                    hipStream_t s) {
+    if (op.coeff == nullptr && x != nullptr && row_kernels_apply(op.n))
+        return launch_rr_row<T>(op.n, op.ih2, x, b, coarse, s);
+    if (scratch != nullptr && x != nullptr) {
+        Shape sf = stencil_shape(op.n);
+        hipLaunchKernelGGL((k_apply<T, TC>), sf.grid, sf.block, 0, s, op.n, (T)op.ih2, op.coeff, x, b, scratch, sf.nz);
+        Shape sc = stencil_shape(op.n / 2);
+        hipLaunchKernelGGL((k_restrict<T>), sc.grid, sc.block, 0, s, op.n, (const T*)scratch, coarse, sc.nz);
+        return hipGetLastError();
+    }
     Shape sh = stencil_shape(op.n / 2);
     if (x)
         hipLaunchKernelGGL((k_resid_restrict<T, TC, true>), sh.grid, sh.block, 0, s, op.n, (T)op.ih2, op.coeff, x, b,
@@ -803,6 +820,7 @@ hipError_t launch_restrict(int n, const T* fine, T* coarse, int ncomp, hipStream
 
 template <typename T>
 hipError_t launch_prolong_add(int n, const T* e, T* x, hipStream_t s) {
+    if (row_kernels_apply(n)) return launch_prolong_row<T>(n, e, x, s);
     Shape sh = stencil_shape(n);
     hipLaunchKernelGGL((k_prolong_add<T>), sh.grid, sh.block, 0, s, n, e, x, sh.nz);
     return hipGetLastError();
@@ -811,13 +829,16 @@ hipError_t launch_prolong_add(int n, const T* e, T* x, hipStream_t s) {
 template <typename T, typename TC>
 hipError_t launch_apply(const OpDesc<TC>& op, const T* u, T* out, hipStream_t s) {
     Shape sh = stencil_shape(op.n);
-    hipLaunchKernelGGL((k_apply<T, TC>), sh.grid, sh.block, 0, s, op.n, (T)op.ih2, op.coeff, u, out, sh.nz);
+    hipLaunchKernelGGL((k_apply<T, TC>), sh.grid, sh.block, 0, s, op.n, (T)op.ih2, op.coeff, u, (const T*)nullptr,
+                       out, sh.nz);
     return hipGetLastError();
 }
 
 template <typename TA, typename TR, typename TE, typename TC>
 hipError_t launch_outer_residual(const OpDesc<TC>& op, const double* phi_in, const TE* e, double* phi_out,
                                  const double* b, double bmean, TR* r, double* partials, hipStream_t s) {
+    if (op.coeff == nullptr && row_kernels_apply(op.n))
+        return launch_outer_row<TA, TR, TE>(op.n, op.ih2, phi_in, e, phi_out, b, bmean, r, partials, s);
     Shape sh = stencil_shape(op.n);
     if (e)
         hipLaunchKernelGGL((k_outer_residual<TA, TR, TE, TC, true>), sh.grid, sh.block, 0, s, op.n, (TA)op.ih2,
@@ -915,7 +936,7 @@ hipError_t launch_hessian_adjoint(int n, double ih2, const double* Jbar, double*
 #define INST_T_TC(T, TC)                                                                                         \
     template hipError_t launch_smooth_step<T, TC>(const OpDesc<TC>&, const T*, const T*, const T*, T*, double,   \
                                                   double, hipStream_t);                                          \
-    template hipError_t launch_residual_restrict<T, TC>(const OpDesc<TC>&, const T*, const T*, T*, hipStream_t); \
+    template hipError_t launch_residual_restrict<T, TC>(const OpDesc<TC>&, const T*, const T*, T*, T*, hipStream_t); \
     template hipError_t launch_apply<T, TC>(const OpDesc<TC>&, const T*, T*, hipStream_t);
 INST_T_TC(float, float)
 INST_T_TC(double, double)

@@ -8,11 +8,14 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
 
+#include "flat_row.h"
 #include "kernels.h"
+#include "tail.h"
 
 using namespace mg;
 
@@ -49,12 +52,14 @@ struct mg_ctx {
     bool coeff_outer_owned = false;
     double* phi_tmp = nullptr;  // second buffer for the phi update
     double* partials = nullptr;
-    int nparts = 0;
+    int nparts = 0;        // partial sums written by launch_block_sums on the fine grid
+    int nparts_outer = 0;  // partial sums written by launch_outer_residual
     double* dscal = nullptr;    // device scalars
     double* hscal = nullptr;    // pinned host mirror
     double* Q = nullptr;        // coarsest seven-point basis and eigenvalues
     double* lam1 = nullptr;
     double* G = nullptr;        // coarsest variable-coefficient pseudo-inverse
+    int tail_start = -1;        // first level run by the single-workgroup tail kernel, -1 = none
     double* scratch = nullptr;  // double scratch for the single-step entry points
     size_t scratch_elems = 0;
     std::string err;
@@ -320,16 +325,51 @@ mg_status coarse_level(mg_ctx* c, int l) {
     return MG_OK;
 }
 
+template <typename T>
+mg_status tail_cycle(mg_ctx* c, int l0) {
+    TailArgs<T> a{};
+    const int L = (int)c->lev.size();
+    a.nlev = L - l0;
+    const bool cheb = c->p.smoother == MG_CHEBYSHEV;
+    a.sched.cheb = cheb ? 1 : 0;
+    a.sched.steps = (int)c->lev[l0].a.size();
+    for (int k = 0; k < a.nlev; ++k) {
+        Level& Lv = c->lev[l0 + k];
+        a.n[k] = Lv.n;
+        int lg = 0;
+        while ((1 << lg) < Lv.n) ++lg;
+        a.lg[k] = lg;
+        a.ih2[k] = Lv.ih2;
+        a.x0[k] = (T*)Lv.x[0];
+        a.x1[k] = (T*)Lv.x[1];
+        a.b[k] = (T*)Lv.b;
+        for (int j = 0; j < a.sched.steps; ++j) {
+            a.sched.a[k][j] = Lv.a[j];
+            a.sched.c[k][j] = Lv.c[j];
+        }
+    }
+    a.Q = c->Q;
+    a.lam1 = c->lam1;
+    HIPCHK(c, launch_tail<T>(a, c->stream));
+    // only the first tail level's iterate is read afterwards
+    const int down = tail_pass_cur(0, true, a.sched.steps, cheb);
+    c->lev[l0].cur = tail_pass_cur(down, false, a.sched.steps, cheb);
+    return MG_OK;
+}
+
 // x_l = V(0, b_l)
 template <typename T>
 mg_status vcycle_from_zero(mg_ctx* c, int l) {
     const int last = (int)c->lev.size() - 1;
+    if (l == c->tail_start) return tail_cycle<T>(c, l);
     if (l == last) return coarse_level<T>(c, l);
     Level& L = c->lev[l];
     Level& Lc = c->lev[l + 1];
     mg_status st = smooth_level<T>(c, l, true);
     if (st != MG_OK) return st;
-    HIPCHK(c, launch_residual_restrict<T, T>(op_of<T>(L), (const T*)L.x[L.cur], (const T*)L.b, (T*)Lc.b, c->stream));
+    // the buffer of the previous iterate is free here and serves as residual scratch
+    HIPCHK(c, launch_residual_restrict<T, T>(op_of<T>(L), (const T*)L.x[L.cur], (const T*)L.b, (T*)Lc.b,
+                                             (T*)L.x[1 - L.cur], c->stream));
     st = vcycle_from_zero<T>(c, l + 1);
     if (st != MG_OK) return st;
     HIPCHK(c, launch_prolong_add<T>(L.n, (const T*)Lc.x[Lc.cur], (T*)L.x[L.cur], c->stream));
@@ -485,8 +525,13 @@ static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype) {
     const size_t N0 = c->lev[0].N;
     mg_status st;
     if ((st = dalloc(c, (void**)&c->phi_tmp, N0 * sizeof(double))) != MG_OK) return st;
+    if (const char* t = std::getenv("MG_ROW_TARGET_BLOCKS")) set_row_target_blocks(std::atoi(t));
     c->nparts = stencil_blocks(p.n);
-    if ((st = dalloc(c, (void**)&c->partials, (size_t)c->nparts * sizeof(double))) != MG_OK) return st;
+    c->nparts_outer = outer_blocks(p.n, !c->var);
+    {
+        const int np = c->nparts > c->nparts_outer ? c->nparts : c->nparts_outer;
+        if ((st = dalloc(c, (void**)&c->partials, (size_t)np * sizeof(double))) != MG_OK) return st;
+    }
     if ((st = dalloc(c, (void**)&c->dscal, 16 * sizeof(double))) != MG_OK) return st;
     HIPCHK(c, hipHostMalloc((void**)&c->hscal, 16 * sizeof(double), hipHostMallocDefault));
 
@@ -581,6 +626,13 @@ static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype) {
         HIPCHK(c, hipMemcpyAsync(c->lam1, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         c->coeff_outer = nullptr;
+        // levels of at most 16^3 points down to a coarsest of at most 8^3 run in one kernel
+        const int steps = p.smoother == MG_JACOBI ? p.jacobi_sweeps : p.cheb_degree;
+        if (Lc.n <= 8 && steps <= kTailMaxSteps && !std::getenv("MG_NO_TAIL")) {
+            int l0 = p.levels - 1;
+            while (l0 > 0 && c->lev[l0 - 1].n <= 16 && p.levels - (l0 - 1) <= kTailMaxLevels) --l0;
+            if (p.levels - l0 >= 2) c->tail_start = l0;
+        }
     }
     for (auto& L : c->lev) make_schedule(p, L);
     return MG_OK;
@@ -629,7 +681,7 @@ static mg_status solve_impl(mg_ctx* c, double* phi, const double* b, double tol,
     if (!std::isfinite(bmean)) return fail(c, MG_ERR_NONFINITE, "source contains NaN or Inf");
     if ((st = device_sum(c, b, bmean, 2, 1)) != MG_OK) return st;
     if ((st = outer_residual(c, phi, nullptr, nullptr, b, bmean)) != MG_OK) return st;
-    HIPCHK(c, launch_finalize_sum(c->partials, c->nparts, c->dscal, 2, c->stream));
+    HIPCHK(c, launch_finalize_sum(c->partials, c->nparts_outer, c->dscal, 2, c->stream));
     if ((st = read_scalars(c, 3)) != MG_OK) return st;
     const double nb = std::sqrt(c->hscal[1]);
     if (info) {
@@ -656,7 +708,7 @@ static mg_status solve_impl(mg_ctx* c, double* phi, const double* b, double tol,
     while (rel > tol && cycles < max_cycles) {
         if ((st = inner_vcycle(c)) != MG_OK) return st;
         if ((st = outer_residual(c, cur, inner_e(c), other, b, bmean)) != MG_OK) return st;
-        HIPCHK(c, launch_finalize_sum(c->partials, c->nparts, c->dscal, 2, c->stream));
+        HIPCHK(c, launch_finalize_sum(c->partials, c->nparts_outer, c->dscal, 2, c->stream));
         std::swap(cur, other);
         if ((st = read_scalars(c, 3)) != MG_OK) return st;
         prev2 = prev1;
@@ -719,7 +771,7 @@ mg_status mg_vcycle(mg_ctx* c, double* phi, const double* b, double* rel_res_out
     if (rel_res_out) {
         if ((st = device_sum(c, b, bmean, 2, 1)) != MG_OK) return st;
         if ((st = outer_residual(c, phi, nullptr, nullptr, b, bmean)) != MG_OK) return st;
-        HIPCHK(c, launch_finalize_sum(c->partials, c->nparts, c->dscal, 2, c->stream));
+        HIPCHK(c, launch_finalize_sum(c->partials, c->nparts_outer, c->dscal, 2, c->stream));
         if ((st = read_scalars(c, 3)) != MG_OK) return st;
         const double nb = std::sqrt(c->hscal[1]);
         *rel_res_out = nb > 0 ? std::sqrt(c->hscal[2]) / nb : 0.0;
@@ -821,7 +873,10 @@ mg_status mg_residual_restrict(mg_ctx* c, int level, const double* x, const doub
     mg_status st = level_check(c, level, true);
     if (st != MG_OK) return st;
     if (!b || !coarse) return fail(c, MG_ERR_INVALID, "invalid residual_restrict arguments");
-    HIPCHK(c, with_op(c, level, [&](auto op) { return launch_residual_restrict<double>(op, x, b, coarse, c->stream); }));
+    if ((st = ensure_scratch(c, c->lev[level].N)) != MG_OK) return st;
+    HIPCHK(c, with_op(c, level, [&](auto op) {
+               return launch_residual_restrict<double>(op, x, b, coarse, c->scratch, c->stream);
+           }));
     return MG_OK;
 }
 

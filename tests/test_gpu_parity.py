@@ -74,13 +74,13 @@ def test_apply(mgpu, n, var):
     assert np.max(np.abs(out - ref)) <= 1e-13 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("var", [False, True])
+@pytest.mark.parametrize("var,n", [(False, 16), (True, 16), (False, 64), (False, 128), (False, 256)])
 @pytest.mark.parametrize("degree", [1, 3, 4])
-def test_smooth(mgpu, var, degree):
-    n = 16
+def test_smooth(mgpu, var, n, degree):
     C = random_spd(n) if var else None
-    mg = mgpu.Multigrid(n, levels=2, degree=degree, coeff=dev(C) if var else None, precision="fp64")
-    H = O.build_hierarchy(n, 2, degree, C=C)
+    levels = 2 if n == 16 else int(math.log2(n)) - 2
+    mg = mgpu.Multigrid(n, levels=levels, degree=degree, coeff=dev(C) if var else None, precision="fp64")
+    H = O.build_hierarchy(n, 2 if var else 1, degree, C=C)
     x = RNG.standard_normal((n, n, n))
     b = RNG.standard_normal((n, n, n))
     ref = O.smooth(H, H.levels[0], x, b)
@@ -101,7 +101,7 @@ def test_smooth_jacobi(mgpu):
     assert rel(host(mg.smooth(dev(x), dev(b))), O.smooth(H, H.levels[0], x, b)) <= 1e-13
 
 
-@pytest.mark.parametrize("n", [8, 32, 128])
+@pytest.mark.parametrize("n", [8, 32, 64, 128, 256])
 @pytest.mark.parametrize("var", [False, True])
 def test_residual_restrict_and_prolong(mgpu, n, var):
     if var and n > 32:
