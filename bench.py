@@ -32,17 +32,19 @@ HBM_PEAK_GBPS = 8000.0
 
 def model_bytes_per_cycle(n, levels, degree, precision):
     """Algorithmic bytes of one outer iteration (inner V-cycle + outer residual/update),
-    every field element each kernel reads or writes counted once."""
+    every field element each kernel reads or writes counted once.  The first
+    fine-level smoothing step from zero is written by the outer kernel (x1 = c0 D^-1 r)."""
     s = 8 if precision == "fp64" else 4
     tot = 0.0
     for l in range(levels - 1):
         N = (n >> l) ** 3
-        pre = 2 * s + (3 * s if degree >= 2 else 0) + 4 * s * max(degree - 2, 0)
+        first = 0 if l == 0 else 2 * s
+        pre = first + (3 * s if degree >= 2 else 0) + 4 * s * max(degree - 2, 0)
         post = 3 * s + 4 * s * (degree - 1)
         transfers = 2 * s + s / 8 + 2 * s + s / 8
         tot += N * (pre + post + transfers)
-    # outer: read phi, e, b; write phi, r  (e and r in the inner precision)
-    tot += n ** 3 * (8 + s + 8 + 8 + s)
+    # outer: read phi, e, b; write phi, r and the first smoothing step (e, r, x1 inner precision)
+    tot += n ** 3 * (8 + s + 8 + 8 + s + s)
     return tot
 
 

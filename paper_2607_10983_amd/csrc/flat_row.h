@@ -6,8 +6,9 @@
 namespace mg {
 
 bool row_kernels_apply(int n);
-// number of per-block partial sums k_outer_row writes for an n^3 grid
-int row_outer_blocks(int n);
+// number of per-block partial sums the outer-residual kernel writes for an
+// n^3 grid (double_arith: residual in double, otherwise float)
+int row_outer_blocks(int n, bool double_arith);
 // Tuning knob: target number of blocks per launch (default 8192).
 void set_row_target_blocks(int target);
 
@@ -16,7 +17,7 @@ hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, cons
                              double cd, hipStream_t s);
 template <typename TA, typename TR, typename TE>
 hipError_t launch_outer_row(int n, double ih2, const double* phi_in, const TE* e, double* phi_out, const double* b,
-                            double bmean, TR* r, double* partials, hipStream_t s);
+                            double bmean, TR* r, TR* x1, double cd0, double* partials, hipStream_t s);
 template <typename T>
 hipError_t launch_rr_row(int n, double ih2, const T* x, const T* b, T* coarse, hipStream_t s);
 template <typename T>

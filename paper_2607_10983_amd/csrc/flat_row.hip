@@ -191,8 +191,8 @@ template <typename TA, typename TR, typename TE, int VEC, bool UPDATE>
 __global__ __launch_bounds__(kBlock) void k_outer_row(int n, TA ih2, const double* __restrict__ phi_in,
                                                       const TE* __restrict__ e, double* __restrict__ phi_out,
                                                       const double* __restrict__ b, double bmean,
-                                                      TR* __restrict__ r, double* __restrict__ partials, int nz,
-                                                      int nyb) {
+                                                      TR* __restrict__ r, TR* __restrict__ x1, TA cd0,
+                                                      double* __restrict__ partials, int nz, int nyb) {
     __shared__ double sh[kWaves];
     const RowGrid g{n, n - 1};
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
@@ -232,6 +232,12 @@ __global__ __launch_bounds__(kBlock) void k_outer_row(int n, TA ih2, const doubl
         }
         const size_t row = g.row(y, z) + off;
         strow<TR, VEC>(r + row, ro);
+        if (x1) {
+            TR xo[VEC];
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) xo[q] = (TR)(cd0 * (TA)ro[q]);
+            strow<TR, VEC>(x1 + row, xo);
+        }
         if constexpr (UPDATE) {
             double po[VEC];
 #pragma unroll
@@ -261,6 +267,170 @@ __global__ __launch_bounds__(kBlock) void k_outer_row(int n, TA ih2, const doubl
     if ((threadIdx.x & 63) == 0) sh[wave] = ss;
     __syncthreads();
     if (threadIdx.x == 0) partials[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// =====================================================================================
+// LDS row-sharing variants: a block of W waves owns W consecutive rows; each
+// plane's rows (plus the two block-halo rows, loaded by the edge waves) are
+// published in LDS (double-buffered by plane parity, one barrier per plane),
+// so the y-neighbour rows come from LDS instead of L2/HBM.  Used where the
+// 2 (W + 2) rows fit in 80 KB of LDS.
+// =====================================================================================
+template <typename T, int VEC, int W, bool PREV>
+__global__ __launch_bounds__(64 * W) void k_smooth_lds(int n, T ih2, const T* x, const T* xprev,
+                                                       const T* __restrict__ b, T* out, T a, T cd, int nz,
+                                                       int nyb) {
+    constexpr int NR = 64 * VEC;
+    __shared__ T rows[2][W + 2][NR];
+    const RowGrid g{n, n - 1};
+    const int lb = xcd_logical(blockIdx.x, gridDim.x);
+    const int yb = lb % nyb, zc = lb / nyb;
+    const int w = threadIdx.x >> 6;
+    const int y0 = yb * W;
+    const int y = y0 + w;
+    const int z0 = zc * nz;
+    const int lane = threadIdx.x & 63;
+    const size_t off = (size_t)lane * VEC;
+    const bool lo = w == 0, hi = w == W - 1;
+    const int yh = lo ? y0 - 1 : y0 + W;  // halo row of the edge waves
+    T zm[VEC], c[VEC], zp[VEC], bb[VEC], pp[VEC], h[VEC];
+    ldrow<T, VEC>(zm, x + g.row(y, z0 - 1) + off);
+    ldrow<T, VEC>(c, x + g.row(y, z0) + off);
+    ldrow<T, VEC>(zp, x + g.row(y, z0 + 1) + off);
+    ldrow<T, VEC>(bb, b + g.row(y, z0) + off);
+    if constexpr (PREV) ldrow<T, VEC>(pp, xprev + g.row(y, z0) + off);
+    if (lo || hi) ldrow<T, VEC>(h, x + g.row(yh, z0) + off);
+    for (int k = 0; k < nz; ++k) {
+        const int z = z0 + k;
+        const int buf = k & 1;
+        T zpp[VEC], bn[VEC], pn[VEC], hn[VEC];
+        const bool more = k + 1 < nz;
+        if (more) {
+            ldrow<T, VEC>(zpp, x + g.row(y, z + 2) + off);
+            ldrow<T, VEC>(bn, b + g.row(y, z + 1) + off);
+            if constexpr (PREV) ldrow<T, VEC>(pn, xprev + g.row(y, z + 1) + off);
+            if (lo || hi) ldrow<T, VEC>(hn, x + g.row(yh, z + 1) + off);
+        }
+        strow<T, VEC>(&rows[buf][w + 1][off], c);
+        if (lo) strow<T, VEC>(&rows[buf][0][off], h);
+        if (hi) strow<T, VEC>(&rows[buf][W + 1][off], h);
+        __syncthreads();
+        T ym[VEC], yp[VEC];
+        ldrow<T, VEC>(ym, &rows[buf][w][off]);
+        ldrow<T, VEC>(yp, &rows[buf][w + 2][off]);
+        T Mx[VEC], o[VEC];
+        flat7_row<T, VEC>(c, ym, yp, zm, zp, ih2, Mx);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const T xp = PREV ? pp[e] : T(0);
+            o[e] = c[e] + a * (c[e] - xp) + cd * (bb[e] - Mx[e]);
+        }
+        strow<T, VEC>(out + g.row(y, z) + off, o);
+        if (more) {
+            copyrow(zm, c);
+            copyrow(c, zp);
+            copyrow(zp, zpp);
+            copyrow(bb, bn);
+            if constexpr (PREV) copyrow(pp, pn);
+            if (lo || hi) copyrow(h, hn);
+        }
+    }
+}
+
+template <typename TA, typename TR, typename TE, int VEC, int W, bool UPDATE>
+__global__ __launch_bounds__(64 * W) void k_outer_lds(int n, TA ih2, const double* __restrict__ phi_in,
+                                                      const TE* __restrict__ e, double* __restrict__ phi_out,
+                                                      const double* __restrict__ b, double bmean,
+                                                      TR* __restrict__ r, TR* __restrict__ x1, TA cd0,
+                                                      double* __restrict__ partials, int nz, int nyb) {
+    constexpr int NR = 64 * VEC;
+    __shared__ TA rows[2][W + 2][NR];
+    __shared__ double sh[W];
+    const RowGrid g{n, n - 1};
+    const int lb = xcd_logical(blockIdx.x, gridDim.x);
+    const int yb = lb % nyb, zc = lb / nyb;
+    const int w = threadIdx.x >> 6;
+    const int y0 = yb * W;
+    const int y = y0 + w;
+    const int z0 = zc * nz;
+    const int lane = threadIdx.x & 63;
+    const size_t off = (size_t)lane * VEC;
+    const bool lo = w == 0, hi = w == W - 1;
+    const int yh = lo ? y0 - 1 : y0 + W;
+    TA zm[VEC], c[VEC], zp[VEC], h[VEC];
+    double bb[VEC];
+    ld_value<TA, TR, TE, VEC, UPDATE>(zm, phi_in, e, g.row(y, z0 - 1) + off);
+    ld_value<TA, TR, TE, VEC, UPDATE>(c, phi_in, e, g.row(y, z0) + off);
+    ld_value<TA, TR, TE, VEC, UPDATE>(zp, phi_in, e, g.row(y, z0 + 1) + off);
+    ldrow<double, VEC>(bb, b + g.row(y, z0) + off);
+    if (lo || hi) ld_value<TA, TR, TE, VEC, UPDATE>(h, phi_in, e, g.row(yh, z0) + off);
+    double ss = 0.0;
+    for (int k = 0; k < nz; ++k) {
+        const int z = z0 + k;
+        const int buf = k & 1;
+        TA zpp[VEC], hn[VEC];
+        double bn[VEC];
+        const bool more = k + 1 < nz;
+        if (more) {
+            ld_value<TA, TR, TE, VEC, UPDATE>(zpp, phi_in, e, g.row(y, z + 2) + off);
+            ldrow<double, VEC>(bn, b + g.row(y, z + 1) + off);
+            if (lo || hi) ld_value<TA, TR, TE, VEC, UPDATE>(hn, phi_in, e, g.row(yh, z + 1) + off);
+        }
+        strow<TA, VEC>(&rows[buf][w + 1][off], c);
+        if (lo) strow<TA, VEC>(&rows[buf][0][off], h);
+        if (hi) strow<TA, VEC>(&rows[buf][W + 1][off], h);
+        __syncthreads();
+        TA ym[VEC], yp[VEC];
+        ldrow<TA, VEC>(ym, &rows[buf][w][off]);
+        ldrow<TA, VEC>(yp, &rows[buf][w + 2][off]);
+        TA Mx[VEC];
+        TR ro[VEC];
+        flat7_row<TA, VEC>(c, ym, yp, zm, zp, ih2, Mx);
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) {
+            const TA ri = (TA)(bb[q] - bmean) - Mx[q];
+            ro[q] = (TR)ri;
+            ss += (double)ri * (double)ri;
+        }
+        const size_t row = g.row(y, z) + off;
+        strow<TR, VEC>(r + row, ro);
+        if (x1) {
+            TR xo[VEC];
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) xo[q] = (TR)(cd0 * (TA)ro[q]);
+            strow<TR, VEC>(x1 + row, xo);
+        }
+        if constexpr (UPDATE) {
+            double po[VEC];
+            if constexpr (sizeof(TA) == sizeof(double)) {
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) po[q] = (double)c[q];
+            } else {  // keep the double sum phi + e (c holds it rounded to TA)
+                double p[VEC];
+                TE qv[VEC];
+                ldrow<double, VEC>(p, phi_in + row);
+                ldrow<TE, VEC>(qv, e + row);
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) po[q] = p[q] + (double)qv[q];
+            }
+            strow<double, VEC>(phi_out + row, po);
+        }
+        if (more) {
+            copyrow(zm, c);
+            copyrow(c, zp);
+            copyrow(zp, zpp);
+            copyrow(bb, bn);
+            if (lo || hi) copyrow(h, hn);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 64);
+    if (lane == 0) sh[w] = ss;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int q = 0; q < W; ++q) t += sh[q];
+        partials[blockIdx.x] = t;
+    }
 }
 
 // =====================================================================================
@@ -439,16 +609,24 @@ __global__ __launch_bounds__(kBlock) void k_prolong_row(int n, const T* __restri
 // planes so that about `target` blocks are launched.
 int g_target_blocks = 8192;
 
-void shape(int rows, int planes, int min_nz, int& nz, int& nyb, int& blocks) {
+// Kernels whose working set does not fit the Infinity Cache (the outer
+// residual with its double fields, residual + restriction) take longer z
+// chunks: each chunk re-reads the planes of its z-neighbour queue, and the
+// counters showed 36% extra fetch at the short chunk length.
+void shape(int rows, int planes, int min_nz, int& nz, int& nyb, int& blocks, int target = 0) {
     nyb = rows / kWaves;
-    const int target = g_target_blocks;
+    if (target == 0) target = g_target_blocks;
     nz = planes;
     while (nz > min_nz && (long)nyb * (planes / nz) < target) nz >>= 1;
     blocks = nyb * (planes / nz);
 }
 
+constexpr int kLdsWaves = 8;
+constexpr size_t kLdsBudget = 80 * 1024;
 template <typename T>
-struct VecDispatch;
+bool lds_rows_fit(int n) {
+    return 2ull * (kLdsWaves + 2) * (size_t)n * sizeof(T) <= kLdsBudget;
+}
 
 }  // namespace
 
@@ -458,9 +636,22 @@ void set_row_target_blocks(int target) {
 
 bool row_kernels_apply(int n) { return n >= 64 && n <= 1024 && (n & (n - 1)) == 0; }
 
-int row_outer_blocks(int n) {
+void outer_lds_shape(int n, int& nz, int& nyb, int& blocks) {
+    nyb = n / kLdsWaves;
+    nz = n;
+    while (nz > 16 && nyb * (n / nz) < 512) nz >>= 1;
+    blocks = nyb * (n / nz);
+}
+
+// The outer residual runs in double (TA) for MG_FP64/MG_MIXED and float for
+// MG_FP32; the block count must match what launch_outer_row uses.
+int row_outer_blocks(int n, bool double_arith) {
     int nz, nyb, blocks;
-    shape(n, n, 4, nz, nyb, blocks);
+    if (double_arith ? lds_rows_fit<double>(n) : lds_rows_fit<float>(n)) {
+        outer_lds_shape(n, nz, nyb, blocks);
+        return blocks;
+    }
+    shape(n, n, 16, nz, nyb, blocks, 1024);
     return blocks;
 }
 
@@ -478,6 +669,27 @@ template <typename T>
 hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, const T* b, T* out, double a,
                              double cd, hipStream_t s) {
     int nz, nyb, blocks;
+    // Row sharing through LDS pays where the level's fields exceed the 256 MB
+    // Infinity Cache (n >= 512); below that the y-halo rows already hit in
+    // cache and the per-plane barrier costs more than it saves (measured).
+    if (x != nullptr && n >= 512 && lds_rows_fit<T>(n)) {
+        constexpr int Wv = kLdsWaves;
+        nyb = n / Wv;
+        nz = n;
+        while (nz > 4 && nyb * (n / nz) < 2048) nz >>= 1;
+        blocks = nyb * (n / nz);
+        DISPATCH_VEC(n, {
+            if constexpr (2ull * (Wv + 2) * 64 * VEC * sizeof(T) <= kLdsBudget) {
+                if (xprev == nullptr)
+                    hipLaunchKernelGGL((k_smooth_lds<T, VEC, Wv, false>), dim3(blocks), dim3(64 * Wv), 0, s, n,
+                                       (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb);
+                else
+                    hipLaunchKernelGGL((k_smooth_lds<T, VEC, Wv, true>), dim3(blocks), dim3(64 * Wv), 0, s, n,
+                                       (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb);
+            }
+        })
+        return hipGetLastError();
+    }
     shape(n, n, 4, nz, nyb, blocks);
     DISPATCH_VEC(n, {
         if (x == nullptr)
@@ -495,16 +707,31 @@ hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, cons
 
 template <typename TA, typename TR, typename TE>
 hipError_t launch_outer_row(int n, double ih2, const double* phi_in, const TE* e, double* phi_out, const double* b,
-                            double bmean, TR* r, double* partials, hipStream_t s) {
+                            double bmean, TR* r, TR* x1, double cd0, double* partials, hipStream_t s) {
     int nz, nyb, blocks;
-    shape(n, n, 4, nz, nyb, blocks);
+    if (lds_rows_fit<TA>(n)) {
+        outer_lds_shape(n, nz, nyb, blocks);
+        constexpr int Wv = kLdsWaves;
+        DISPATCH_VEC(n, {
+            if constexpr (2ull * (Wv + 2) * 64 * VEC * sizeof(TA) <= kLdsBudget) {
+                if (e)
+                    hipLaunchKernelGGL((k_outer_lds<TA, TR, TE, VEC, Wv, true>), dim3(blocks), dim3(64 * Wv), 0, s,
+                                       n, (TA)ih2, phi_in, e, phi_out, b, bmean, r, x1, (TA)cd0, partials, nz, nyb);
+                else
+                    hipLaunchKernelGGL((k_outer_lds<TA, TR, TE, VEC, Wv, false>), dim3(blocks), dim3(64 * Wv), 0, s,
+                                       n, (TA)ih2, phi_in, e, phi_out, b, bmean, r, x1, (TA)cd0, partials, nz, nyb);
+            }
+        })
+        return hipGetLastError();
+    }
+    shape(n, n, 16, nz, nyb, blocks, 1024);
     DISPATCH_VEC(n, {
         if (e)
             hipLaunchKernelGGL((k_outer_row<TA, TR, TE, VEC, true>), dim3(blocks), dim3(kBlock), 0, s, n, (TA)ih2,
-                               phi_in, e, phi_out, b, bmean, r, partials, nz, nyb);
+                               phi_in, e, phi_out, b, bmean, r, x1, (TA)cd0, partials, nz, nyb);
         else
             hipLaunchKernelGGL((k_outer_row<TA, TR, TE, VEC, false>), dim3(blocks), dim3(kBlock), 0, s, n, (TA)ih2,
-                               phi_in, e, phi_out, b, bmean, r, partials, nz, nyb);
+                               phi_in, e, phi_out, b, bmean, r, x1, (TA)cd0, partials, nz, nyb);
     })
     return hipGetLastError();
 }
@@ -513,7 +740,7 @@ template <typename T>
 hipError_t launch_rr_row(int n, double ih2, const T* x, const T* b, T* coarse, hipStream_t s) {
     const int nc = n / 2;
     int nzc, nyb, blocks;
-    shape(nc, nc, 2, nzc, nyb, blocks);
+    shape(nc, nc, 4, nzc, nyb, blocks, 1024);
     DISPATCH_VEC(n, {
         hipLaunchKernelGGL((k_rr_row<T, VEC>), dim3(blocks), dim3(kBlock), 0, s, n, (T)ih2, x, b, coarse, nzc, nyb);
     })
@@ -539,10 +766,13 @@ template hipError_t launch_rr_row<double>(int, double, const double*, const doub
 template hipError_t launch_prolong_row<float>(int, const float*, float*, hipStream_t);
 template hipError_t launch_prolong_row<double>(int, const double*, double*, hipStream_t);
 template hipError_t launch_outer_row<double, double, double>(int, double, const double*, const double*, double*,
-                                                             const double*, double, double*, double*, hipStream_t);
+                                                             const double*, double, double*, double*, double,
+                                                             double*, hipStream_t);
 template hipError_t launch_outer_row<double, float, float>(int, double, const double*, const float*, double*,
-                                                           const double*, double, float*, double*, hipStream_t);
+                                                           const double*, double, float*, float*, double, double*,
+                                                           hipStream_t);
 template hipError_t launch_outer_row<float, float, float>(int, double, const double*, const float*, double*,
-                                                          const double*, double, float*, double*, hipStream_t);
+                                                          const double*, double, float*, float*, double, double*,
+                                                          hipStream_t);
 
 }  // namespace mg

@@ -20,8 +20,8 @@ struct OpDesc {
 // sums buffers must hold at least this many doubles.
 int stencil_blocks(int n);
 // Number of per-block partial sums launch_outer_residual writes (seven-point
-// operator when flat is true).
-int outer_blocks(int n, bool flat);
+// operator when flat is true; residual in double when double_arith is true).
+int outer_blocks(int n, bool flat, bool double_arith);
 
 // ---- smoothing (Chebyshev / Jacobi step) ---------------------------------
 // out = x + a (x - xprev) + c D^-1 (b - M x)      (xprev == nullptr: xprev = 0;
@@ -57,10 +57,12 @@ hipError_t launch_apply(const OpDesc<TC>& op, const T* u, T* out, hipStream_t s)
 // If e != nullptr: phi_out = phi_in + e, else phi_out unused (may be nullptr)
 // and phi is phi_in.  r = (b - bmean) - M phi written as TR; per-block sums of
 // r^2 (in double) written to partials[block].  phi_out must not alias phi_in.
+// If x1 != nullptr it also receives c0 D^-1 r, the first smoothing step of the
+// next V-cycle started from zero.
 template <typename TA, typename TR, typename TE, typename TC>
 hipError_t launch_outer_residual(const OpDesc<TC>& op, const double* phi_in, const TE* e,
                                  double* phi_out, const double* b, double bmean, TR* r,
-                                 double* partials, hipStream_t s);
+                                 TR* x1, double c0, double* partials, hipStream_t s);
 
 // ---- reductions ----------------------------------------------------------------
 // partials[block] = sum over the block of (u - shift)^p, p in {1, 2}.

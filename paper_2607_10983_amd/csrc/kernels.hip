@@ -353,7 +353,8 @@ __global__ __launch_bounds__(kThreads) void k_outer_residual(int n, TA ih2, cons
                                                              const TE* __restrict__ e,
                                                              double* __restrict__ phi_out,
                                                              const double* __restrict__ b, double bmean,
-                                                             TR* __restrict__ r, double* partials, int nz) {
+                                                             TR* __restrict__ r, TR* __restrict__ x1, TA c0,
+                                                             double* partials, int nz) {
     __shared__ double sh[kThreads];
     const Grid g{n, n - 1};
     const size_t N = (size_t)n * n * n;
@@ -379,6 +380,10 @@ __global__ __launch_bounds__(kThreads) void k_outer_residual(int n, TA ih2, cons
         }
         const TA ri = (TA)(b[i] - bmean) - Mu;
         r[i] = (TR)ri;
+        if (x1) {
+            if (C == nullptr) D = TA(-6) * ih2;
+            x1[i] = (TR)(c0 * (TA)(TR)ri / D);
+        }
         ss += (double)ri * (double)ri;
     }
     const double tot = block_sum(ss, sh);
@@ -767,7 +772,9 @@ int stencil_blocks(int n) {
     return (int)(s.grid.x * s.grid.y * s.grid.z);
 }
 
-int outer_blocks(int n, bool flat) { return flat && row_kernels_apply(n) ? row_outer_blocks(n) : stencil_blocks(n); }
+int outer_blocks(int n, bool flat, bool double_arith) {
+    return flat && row_kernels_apply(n) ? row_outer_blocks(n, double_arith) : stencil_blocks(n);
+}
 
 template <typename T, typename TC>
 hipError_t launch_smooth_step(const OpDesc<TC>& op, const T* x, const T* xprev, const T* b, T* out, double a,
@@ -836,16 +843,18 @@ hipError_t launch_apply(const OpDesc<TC>& op, const T* u, T* out, hipStream_t s)
 
 template <typename TA, typename TR, typename TE, typename TC>
 hipError_t launch_outer_residual(const OpDesc<TC>& op, const double* phi_in, const TE* e, double* phi_out,
-                                 const double* b, double bmean, TR* r, double* partials, hipStream_t s) {
+                                 const double* b, double bmean, TR* r, TR* x1, double c0, double* partials,
+                                 hipStream_t s) {
     if (op.coeff == nullptr && row_kernels_apply(op.n))
-        return launch_outer_row<TA, TR, TE>(op.n, op.ih2, phi_in, e, phi_out, b, bmean, r, partials, s);
+        return launch_outer_row<TA, TR, TE>(op.n, op.ih2, phi_in, e, phi_out, b, bmean, r, x1,
+                                            c0 / (-6.0 * op.ih2), partials, s);
     Shape sh = stencil_shape(op.n);
     if (e)
         hipLaunchKernelGGL((k_outer_residual<TA, TR, TE, TC, true>), sh.grid, sh.block, 0, s, op.n, (TA)op.ih2,
-                           op.coeff, phi_in, e, phi_out, b, bmean, r, partials, sh.nz);
+                           op.coeff, phi_in, e, phi_out, b, bmean, r, x1, (TA)c0, partials, sh.nz);
     else
         hipLaunchKernelGGL((k_outer_residual<TA, TR, TE, TC, false>), sh.grid, sh.block, 0, s, op.n, (TA)op.ih2,
-                           op.coeff, phi_in, e, phi_out, b, bmean, r, partials, sh.nz);
+                           op.coeff, phi_in, e, phi_out, b, bmean, r, x1, (TA)c0, partials, sh.nz);
     return hipGetLastError();
 }
 
@@ -964,7 +973,8 @@ template hipError_t launch_convert<float, float>(size_t, const float*, float*, h
 
 #define INST_OUTER(TA, TR, TE, TC)                                                                                \
     template hipError_t launch_outer_residual<TA, TR, TE, TC>(const OpDesc<TC>&, const double*, const TE*, double*, \
-                                                              const double*, double, TR*, double*, hipStream_t);
+                                                              const double*, double, TR*, TR*, double, double*,     \
+                                                              hipStream_t);
 INST_OUTER(double, double, double, double)
 INST_OUTER(double, double, double, float)
 INST_OUTER(double, float, float, float)

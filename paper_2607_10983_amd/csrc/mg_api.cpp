@@ -60,6 +60,7 @@ struct mg_ctx {
     double* lam1 = nullptr;
     double* G = nullptr;        // coarsest variable-coefficient pseudo-inverse
     int tail_start = -1;        // first level run by the single-workgroup tail kernel, -1 = none
+    bool x1_ready = false;      // the outer residual already wrote level 0's first smoothing step
     double* scratch = nullptr;  // double scratch for the single-step entry points
     size_t scratch_elems = 0;
     std::string err;
@@ -291,13 +292,19 @@ mg_status smooth_level(mg_ctx* c, int l, bool from_zero) {
         T* X0 = (T*)L.x[0];
         T* X1 = (T*)L.x[1];
         T* bufs[2] = {X0, X1};
+        if (k == 0 && from_zero && l == 0 && c->x1_ready) {  // formed by the outer residual kernel
+            c->x1_ready = false;
+            cur = 0;
+            prev = -1;
+            continue;
+        }
         mg_status st = time_begin(c, fine);
         if (st != MG_OK) return st;
         if (k == 0 && from_zero) {
-            HIPCHK(c, launch_smooth_step<T, T>(op, nullptr, nullptr, (const T*)L.b, bufs[0], 0.0, L.c[0], c->stream));
-            bytes = 2.0 * fbytes + cbytes;  // read b (and C for D), write x
             cur = 0;
             prev = -1;
+            HIPCHK(c, launch_smooth_step<T, T>(op, nullptr, nullptr, (const T*)L.b, bufs[0], 0.0, L.c[0], c->stream));
+            bytes = 2.0 * fbytes + cbytes;  // read b (and C for D), write x
         } else {
             const T* xp = (cheb && prev >= 0) ? bufs[prev] : nullptr;
             const int out = (cheb && prev >= 0) ? prev : 1 - cur;
@@ -351,9 +358,8 @@ mg_status tail_cycle(mg_ctx* c, int l0) {
     a.Q = c->Q;
     a.lam1 = c->lam1;
     HIPCHK(c, launch_tail<T>(a, c->stream));
-    // only the first tail level's iterate is read afterwards
-    const int down = tail_pass_cur(0, true, a.sched.steps, cheb);
-    c->lev[l0].cur = tail_pass_cur(down, false, a.sched.steps, cheb);
+    // the tail writes the first tail level's result to that level's buffer x0
+    c->lev[l0].cur = 0;
     return MG_OK;
 }
 
@@ -378,32 +384,40 @@ mg_status vcycle_from_zero(mg_ctx* c, int l) {
 
 // ---- outer residual dispatch ---------------------------------------------------------------
 // r = (b - mean b) - M phi (phi = phi_in + e when e != null); per-block r^2 sums into partials.
+// With next_cycle set, the kernel also writes the first smoothing step of the
+// V-cycle that follows (x = c0 D^-1 r on level 0).
 mg_status outer_residual(mg_ctx* c, const double* phi_in, const void* e, double* phi_out, const double* b,
-                         double bmean) {
+                         double bmean, bool next_cycle = false) {
     Level& L = c->lev[0];
     const int n = L.n;
     const double ih2 = L.ih2;
+    const bool x1 = next_cycle && c->tail_start != 0 && c->lev.size() > 1;
+    const double c0 = L.c.empty() ? 0.0 : L.c[0];
     hipError_t err;
     if (c->p.precision == MG_FP64) {
         OpDesc<double> op{n, ih2, (const double*)c->coeff_outer};
         err = launch_outer_residual<double, double, double, double>(op, phi_in, (const double*)e, phi_out, b, bmean,
-                                                                    (double*)L.b, c->partials, c->stream);
+                                                                    (double*)L.b, x1 ? (double*)L.x[0] : nullptr, c0,
+                                                                    c->partials, c->stream);
     } else if (c->p.precision == MG_MIXED) {
+        float* x1p = x1 ? (float*)L.x[0] : nullptr;
         if (c->coeff_outer_double) {
             OpDesc<double> op{n, ih2, (const double*)c->coeff_outer};
             err = launch_outer_residual<double, float, float, double>(op, phi_in, (const float*)e, phi_out, b, bmean,
-                                                                      (float*)L.b, c->partials, c->stream);
+                                                                      (float*)L.b, x1p, c0, c->partials, c->stream);
         } else {
             OpDesc<float> op{n, ih2, (const float*)c->coeff_outer};
             err = launch_outer_residual<double, float, float, float>(op, phi_in, (const float*)e, phi_out, b, bmean,
-                                                                     (float*)L.b, c->partials, c->stream);
+                                                                     (float*)L.b, x1p, c0, c->partials, c->stream);
         }
     } else {
         OpDesc<float> op{n, ih2, (const float*)c->coeff_outer};
         err = launch_outer_residual<float, float, float, float>(op, phi_in, (const float*)e, phi_out, b, bmean,
-                                                                (float*)L.b, c->partials, c->stream);
+                                                                (float*)L.b, x1 ? (float*)L.x[0] : nullptr, c0,
+                                                                c->partials, c->stream);
     }
     HIPCHK(c, err);
+    c->x1_ready = x1;
     return MG_OK;
 }
 
@@ -527,7 +541,7 @@ static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype) {
     if ((st = dalloc(c, (void**)&c->phi_tmp, N0 * sizeof(double))) != MG_OK) return st;
     if (const char* t = std::getenv("MG_ROW_TARGET_BLOCKS")) set_row_target_blocks(std::atoi(t));
     c->nparts = stencil_blocks(p.n);
-    c->nparts_outer = outer_blocks(p.n, !c->var);
+    c->nparts_outer = outer_blocks(p.n, !c->var, p.precision != MG_FP32);
     {
         const int np = c->nparts > c->nparts_outer ? c->nparts : c->nparts_outer;
         if ((st = dalloc(c, (void**)&c->partials, (size_t)np * sizeof(double))) != MG_OK) return st;
@@ -680,7 +694,7 @@ static mg_status solve_impl(mg_ctx* c, double* phi, const double* b, double tol,
     const double bmean = c->hscal[0] * invN;
     if (!std::isfinite(bmean)) return fail(c, MG_ERR_NONFINITE, "source contains NaN or Inf");
     if ((st = device_sum(c, b, bmean, 2, 1)) != MG_OK) return st;
-    if ((st = outer_residual(c, phi, nullptr, nullptr, b, bmean)) != MG_OK) return st;
+    if ((st = outer_residual(c, phi, nullptr, nullptr, b, bmean, true)) != MG_OK) return st;
     HIPCHK(c, launch_finalize_sum(c->partials, c->nparts_outer, c->dscal, 2, c->stream));
     if ((st = read_scalars(c, 3)) != MG_OK) return st;
     const double nb = std::sqrt(c->hscal[1]);
@@ -707,7 +721,7 @@ static mg_status solve_impl(mg_ctx* c, double* phi, const double* b, double tol,
     mg_status result = MG_OK;
     while (rel > tol && cycles < max_cycles) {
         if ((st = inner_vcycle(c)) != MG_OK) return st;
-        if ((st = outer_residual(c, cur, inner_e(c), other, b, bmean)) != MG_OK) return st;
+        if ((st = outer_residual(c, cur, inner_e(c), other, b, bmean, true)) != MG_OK) return st;
         HIPCHK(c, launch_finalize_sum(c->partials, c->nparts_outer, c->dscal, 2, c->stream));
         std::swap(cur, other);
         if ((st = read_scalars(c, 3)) != MG_OK) return st;
@@ -727,6 +741,7 @@ static mg_status solve_impl(mg_ctx* c, double* phi, const double* b, double tol,
         result = MG_ERR_NOT_CONVERGED;
         c->err = "relative residual " + std::to_string(rel) + " > tol after " + std::to_string(cycles) + " cycles";
     }
+    c->x1_ready = false;
     // gauge: phi <- cur - mean(cur)
     if ((st = device_sum(c, cur, 0.0, 1, 3)) != MG_OK) return st;
     if ((st = read_scalars(c, 4)) != MG_OK) return st;
@@ -763,7 +778,7 @@ mg_status mg_vcycle(mg_ctx* c, double* phi, const double* b, double* rel_res_out
     if ((st = device_sum(c, b, 0.0, 1, 0)) != MG_OK) return st;
     if ((st = read_scalars(c, 1)) != MG_OK) return st;
     const double bmean = c->hscal[0] * invN;
-    if ((st = outer_residual(c, phi, nullptr, nullptr, b, bmean)) != MG_OK) return st;
+    if ((st = outer_residual(c, phi, nullptr, nullptr, b, bmean, true)) != MG_OK) return st;
     if ((st = inner_vcycle(c)) != MG_OK) return st;
     const void* e = inner_e(c);
     if (c->inner_double) HIPCHK(c, launch_add<double>(N0, phi, (const double*)e, phi, c->stream));

@@ -16,6 +16,8 @@ struct TailSchedule {
     double c[kTailMaxLevels][kTailMaxSteps];
 };
 
+// Only x0[0] and b[0] (the first tail level) are accessed in global memory:
+// the tail reads b[0] and leaves the V-cycle result in x0[0].
 template <typename T>
 struct TailArgs {
     int nlev;                      // levels in the tail, the last one is the coarsest
@@ -29,10 +31,6 @@ struct TailArgs {
     const double* Q;               // coarsest separable basis (nc x nc)
     const double* lam1;            // its 1-D eigenvalues
 };
-
-// Buffer index holding the iterate after one smoothing pass that starts from
-// buffer `cur` (ignored when from_zero).
-int tail_pass_cur(int cur, bool from_zero, int steps, bool cheb);
 
 template <typename T>
 hipError_t launch_tail(const TailArgs<T>& args, hipStream_t s);

@@ -5,9 +5,12 @@
 // work.  This kernel runs the whole remaining V-cycle from a small level down
 // to the coarsest and back up inside ONE workgroup of 1024 threads: every
 // smoothing step, residual, restriction, coarsest solve and prolongation is
-// a phase of the same kernel, separated by workgroup barriers.  The level
-// fields stay in global memory (they fit in the CU's L1/L2); the coarsest
-// level's exact solve (separable real Fourier basis) runs in LDS in double.
+// a phase of the same kernel, separated by workgroup barriers.  All tail
+// level fields live in LDS (gfx950 gives a workgroup up to 160 KB: three
+// fields of 16^3 + 8^3 + 4^3 points take 56 KB in float, 112 KB in double);
+// only the first tail level's right-hand side is read from and its result
+// written back to global memory.  The coarsest level's exact solve
+// (separable real Fourier basis) also runs in LDS, in double.
 #include "tail.h"
 
 namespace mg {
@@ -54,30 +57,44 @@ __device__ __forceinline__ void phase(int N, F f, T* out) {
     __syncthreads();
 }
 
+constexpr int kTailElems = 3 * (4096 + 512 + 64);  // x0, x1, b of 16^3, 8^3, 4^3
+
+// LDS layout: level l's x0, x1, b follow those of levels 0..l-1.
 template <typename T>
-__device__ __forceinline__ T* xbuf(const TailArgs<T>& A, int l, int k) {
-    return k == 0 ? A.x0[l] : A.x1[l];
-}
+struct Fields {
+    T* base;
+    const TailArgs<T>* A;
+    __device__ __forceinline__ T* lev(int l) const {
+        int off = 0;
+        for (int k = 0; k < l; ++k) off += 3 * A->n[k] * A->n[k] * A->n[k];
+        return base + off;
+    }
+    __device__ __forceinline__ T* x(int l, int k) const {
+        const int N = A->n[l] * A->n[l] * A->n[l];
+        return lev(l) + k * N;
+    }
+    __device__ __forceinline__ T* b(int l) const { return x(l, 2); }
+};
 
 // One smoothing pass on tail level l (same buffer rotation as the multi-kernel path).
 template <typename T>
-__device__ int smooth_pass(const TailArgs<T>& A, int l, int cur, bool from_zero) {
+__device__ int smooth_pass(const TailArgs<T>& A, const Fields<T>& F, int l, int cur, bool from_zero) {
     const int n = A.n[l], lg = A.lg[l], N = n * n * n;
     const T ih2 = (T)A.ih2[l];
     const T dinv = T(1) / (T(-6) * ih2);
-    const T* b = A.b[l];
+    const T* b = F.b(l);
     int prev = -1;
     for (int k = 0; k < A.sched.steps; ++k) {
         const T a = (T)A.sched.a[l][k], c = (T)A.sched.c[l][k];
         if (k == 0 && from_zero) {
-            phase<T>(N, [&](int i) { return c * dinv * b[i]; }, xbuf(A, l, 0));
+            phase<T>(N, [&](int i) { return c * dinv * b[i]; }, F.x(l, 0));
             cur = 0;
             prev = -1;
         } else {
             const bool use_prev = A.sched.cheb && prev >= 0;
             const int o = use_prev ? prev : 1 - cur;
-            const T* xc = xbuf(A, l, cur);
-            const T* xp = use_prev ? xbuf(A, l, prev) : nullptr;
+            const T* xc = F.x(l, cur);
+            const T* xp = use_prev ? F.x(l, prev) : nullptr;
             phase<T>(N, [&](int i) {
                 int x, y, z;
                 coords(i, n, lg, x, y, z);
@@ -85,7 +102,7 @@ __device__ int smooth_pass(const TailArgs<T>& A, int l, int cur, bool from_zero)
                 const T xi = xc[i];
                 const T pv = use_prev ? xp[i] : T(0);
                 return xi + a * (xi - pv) + c * dinv * (b[i] - Mx);
-            }, xbuf(A, l, o));
+            }, F.x(l, o));
             prev = cur;
             cur = o;
         }
@@ -95,23 +112,31 @@ __device__ int smooth_pass(const TailArgs<T>& A, int l, int cur, bool from_zero)
 
 template <typename T>
 __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> A) {
+    __shared__ T fields[kTailElems];
     __shared__ double sA[512];
     __shared__ double sB[512];
     __shared__ double q[64];
     __shared__ double lam[8];
+    const Fields<T> F{fields, &A};
     unsigned curbits = 0;  // bit l: buffer holding level l's iterate (no private array)
     const int nl = A.nlev;
     const int tid = threadIdx.x;
+    {   // right-hand side of the first tail level from global memory
+        const int N0 = A.n[0] * A.n[0] * A.n[0];
+        T* b0 = F.b(0);
+        for (int i = tid; i < N0; i += kTailThreads) b0[i] = A.b[0][i];
+        __syncthreads();
+    }
     // ---------------- down leg
     for (int l = 0; l + 1 < nl; ++l) {
         const int n = A.n[l], lg = A.lg[l], N = n * n * n;
         const T ih2 = (T)A.ih2[l];
-        const int cl = smooth_pass(A, l, 0, true);
+        const int cl = smooth_pass(A, F, l, 0, true);
         curbits = (curbits & ~(1u << l)) | ((unsigned)cl << l);
         // residual into the free buffer, then full weighting into the coarse rhs
-        T* r = xbuf(A, l, 1 - cl);
-        const T* xc = xbuf(A, l, cl);
-        const T* b = A.b[l];
+        T* r = F.x(l, 1 - cl);
+        const T* xc = F.x(l, cl);
+        const T* b = F.b(l);
         phase<T>(N, [&](int i) {
             int x, y, z;
             coords(i, n, lg, x, y, z);
@@ -133,7 +158,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> A) {
                 acc += (dz == 0 ? T(0.5) : T(0.25)) * ay;
             }
             return acc;
-        }, A.b[l + 1]);
+        }, F.b(l + 1));
     }
     // ---------------- coarsest: exact zero-mean solve in double (separable basis)
     {
@@ -142,7 +167,8 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> A) {
         const int N = nc * nc * nc;
         for (int i = tid; i < nc * nc; i += kTailThreads) q[i] = A.Q[i];
         for (int i = tid; i < nc; i += kTailThreads) lam[i] = A.lam1[i];
-        for (int i = tid; i < N; i += kTailThreads) sA[i] = (double)A.b[l][i];
+        const T* bl = F.b(l);
+        for (int i = tid; i < N; i += kTailThreads) sA[i] = (double)bl[i];
         __syncthreads();
         auto pass = [&](const double* src, double* dst, int axis, bool forward) {
             for (int i = tid; i < N; i += kTailThreads) {
@@ -167,7 +193,8 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> A) {
         pass(sB, sA, 2, false);
         pass(sA, sB, 1, false);
         pass(sB, sA, 0, false);
-        for (int i = tid; i < N; i += kTailThreads) A.x0[l][i] = (T)sA[i];
+        T* xl = F.x(l, 0);
+        for (int i = tid; i < N; i += kTailThreads) xl[i] = (T)sA[i];
         curbits &= ~(1u << l);
         __syncthreads();
     }
@@ -175,9 +202,9 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> A) {
     for (int l = nl - 2; l >= 0; --l) {
         const int n = A.n[l], lg = A.lg[l], N = n * n * n;
         const int nc = A.n[l + 1], lgc = A.lg[l + 1];
-        const T* e = xbuf(A, l + 1, (curbits >> (l + 1)) & 1);
+        const T* e = F.x(l + 1, (curbits >> (l + 1)) & 1);
         const int cl = (curbits >> l) & 1;
-        T* xv = xbuf(A, l, cl);
+        T* xv = F.x(l, cl);
         phase<T>(N, [&](int i) {
             int x, y, z;
             coords(i, n, lg, x, y, z);
@@ -189,33 +216,25 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> A) {
                     for (int kx = 0; kx <= ox; ++kx) v += w * e[at(X + kx, Y + ky, Z + kz, nc, lgc)];
             return xv[i] + v;
         }, xv);
-        const int cn = smooth_pass(A, l, cl, false);
+        const int cn = smooth_pass(A, F, l, cl, false);
         curbits = (curbits & ~(1u << l)) | ((unsigned)cn << l);
+    }
+    {   // result of the first tail level to global memory (always its buffer x0)
+        const int N0 = A.n[0] * A.n[0] * A.n[0];
+        const T* x0 = F.x(0, curbits & 1);
+        for (int i = tid; i < N0; i += kTailThreads) A.x0[0][i] = x0[i];
     }
 }
 
 }  // namespace
 
-// Final buffer index of a smoothing pass (mirrors smooth_pass).
-int tail_pass_cur(int cur, bool from_zero, int steps, bool cheb) {
-    int prev = -1;
-    for (int k = 0; k < steps; ++k) {
-        if (k == 0 && from_zero) {
-            cur = 0;
-            prev = -1;
-        } else {
-            const bool use_prev = cheb && prev >= 0;
-            const int o = use_prev ? prev : 1 - cur;
-            prev = cur;
-            cur = o;
-        }
-    }
-    return cur;
-}
-
 template <typename T>
 hipError_t launch_tail(const TailArgs<T>& args, hipStream_t s) {
-    if (args.nlev < 2 || args.nlev > kTailMaxLevels || args.n[args.nlev - 1] > 8) return hipErrorInvalidValue;
+    if (args.nlev < 2 || args.nlev > kTailMaxLevels || args.n[0] > 16 || args.n[args.nlev - 1] > 8)
+        return hipErrorInvalidValue;
+    int elems = 0;
+    for (int l = 0; l < args.nlev; ++l) elems += 3 * args.n[l] * args.n[l] * args.n[l];
+    if (elems > kTailElems) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_tail<T>), dim3(1), dim3(kTailThreads), 0, s, args);
     return hipGetLastError();
 }
