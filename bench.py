@@ -29,6 +29,30 @@ sys.path.insert(0, ROOT)
 METRIC = "V-cycle Mpts/s + HBM GB/s; time to rel. residual 1e-10, mixed vs FP64"
 HBM_PEAK_GBPS = 8000.0
 
+# Measured HBM bytes per launch of the fine-level smoothing kernel on the
+# 256^3 / degree-3 workload: rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch
+# (profiles/hbm_bytes_smooth_outer_rr_prolong_256_512.md) scaled by the
+# copy-kernel factors 2.0 (fetch) and 1.0 (write), averaged over one V-cycle's
+# 3 launches with and 2 without the previous iterate.  Reported only while the
+# device code of the row kernels is the code the counters were taken on.
+TRAFFIC = {
+    "device_code_sha256": "0082d6d74fc5b8609c8c9d63eb5f23aba05832482716b4d67b6e5ac3e8344c58",
+    "n": 256,
+    "degree": 3,
+    "bytes_per_launch": (3 * (2 * 100560.6 + 65536.0) + 2 * (2 * 67953.1 + 65536.0)) / 5 * 1024,
+}
+
+
+def measured_traffic(n, degree):
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2607_10983_amd", "csrc", "flat_row.hip")).read()
+    dev = src[: src.index("\nint g_target_blocks")]
+    if hashlib.sha256(dev.encode()).hexdigest() != TRAFFIC["device_code_sha256"]:
+        return None
+    if (n, degree) != (TRAFFIC["n"], TRAFFIC["degree"]):
+        return None
+    return round(TRAFFIC["bytes_per_launch"])
+
 
 def model_bytes_per_cycle(n, levels, degree, precision):
     """Algorithmic bytes of one outer iteration (inner V-cycle + outer residual/update),
@@ -125,7 +149,8 @@ def main():
         "peak": HBM_PEAK_GBPS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBPS, 4) if achieved else None,
-        "traffic": None,
+        "traffic": measured_traffic(n, deg),
+        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE)",
         "launches": launches,
         "avg_launch_us": round(1e3 * k_ms / launches, 2) if launches else None,
         "alg_bytes_per_launch": k_bytes / launches if launches else None,

@@ -14,7 +14,7 @@ void set_row_target_blocks(int target);
 
 template <typename T>
 hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, const T* b, T* out, double a,
-                             double cd, hipStream_t s);
+                             double cd, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 template <typename TA, typename TR, typename TE>
 hipError_t launch_outer_row(int n, double ih2, const double* phi_in, const TE* e, double* phi_out, const double* b,
                             double bmean, TR* r, TR* x1, double cd0, double* partials, hipStream_t s);

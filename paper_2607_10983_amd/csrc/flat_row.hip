@@ -13,6 +13,8 @@
 // and share their halo rows through that XCD's L2.
 #include "flat_row.h"
 
+#include <hip/hip_ext.h>
+
 #include <cstdint>
 
 namespace mg {
@@ -667,7 +669,7 @@ int row_outer_blocks(int n, bool double_arith) {
 
 template <typename T>
 hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, const T* b, T* out, double a,
-                             double cd, hipStream_t s) {
+                             double cd, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     int nz, nyb, blocks;
     // Row sharing through LDS pays where the level's fields exceed the 256 MB
     // Infinity Cache (n >= 512); below that the y-halo rows already hit in
@@ -681,10 +683,10 @@ hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, cons
         DISPATCH_VEC(n, {
             if constexpr (2ull * (Wv + 2) * 64 * VEC * sizeof(T) <= kLdsBudget) {
                 if (xprev == nullptr)
-                    hipLaunchKernelGGL((k_smooth_lds<T, VEC, Wv, false>), dim3(blocks), dim3(64 * Wv), 0, s, n,
+                    hipExtLaunchKernelGGL((k_smooth_lds<T, VEC, Wv, false>), dim3(blocks), dim3(64 * Wv), 0, s, ev0, ev1, 0, n,
                                        (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb);
                 else
-                    hipLaunchKernelGGL((k_smooth_lds<T, VEC, Wv, true>), dim3(blocks), dim3(64 * Wv), 0, s, n,
+                    hipExtLaunchKernelGGL((k_smooth_lds<T, VEC, Wv, true>), dim3(blocks), dim3(64 * Wv), 0, s, ev0, ev1, 0, n,
                                        (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb);
             }
         })
@@ -693,13 +695,13 @@ hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, cons
     shape(n, n, 4, nz, nyb, blocks);
     DISPATCH_VEC(n, {
         if (x == nullptr)
-            hipLaunchKernelGGL((k_smooth_row<T, VEC, false, false>), dim3(blocks), dim3(kBlock), 0, s, n, (T)ih2, x,
+            hipExtLaunchKernelGGL((k_smooth_row<T, VEC, false, false>), dim3(blocks), dim3(kBlock), 0, s, ev0, ev1, 0, n, (T)ih2, x,
                                xprev, b, out, (T)a, (T)cd, nz, nyb);
         else if (xprev == nullptr)
-            hipLaunchKernelGGL((k_smooth_row<T, VEC, true, false>), dim3(blocks), dim3(kBlock), 0, s, n, (T)ih2, x,
+            hipExtLaunchKernelGGL((k_smooth_row<T, VEC, true, false>), dim3(blocks), dim3(kBlock), 0, s, ev0, ev1, 0, n, (T)ih2, x,
                                xprev, b, out, (T)a, (T)cd, nz, nyb);
         else
-            hipLaunchKernelGGL((k_smooth_row<T, VEC, true, true>), dim3(blocks), dim3(kBlock), 0, s, n, (T)ih2, x,
+            hipExtLaunchKernelGGL((k_smooth_row<T, VEC, true, true>), dim3(blocks), dim3(kBlock), 0, s, ev0, ev1, 0, n, (T)ih2, x,
                                xprev, b, out, (T)a, (T)cd, nz, nyb);
     })
     return hipGetLastError();
@@ -758,9 +760,9 @@ hipError_t launch_prolong_row(int n, const T* e, T* x, hipStream_t s) {
 }
 
 template hipError_t launch_smooth_row<float>(int, double, const float*, const float*, const float*, float*, double,
-                                             double, hipStream_t);
+                                             double, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_smooth_row<double>(int, double, const double*, const double*, const double*, double*,
-                                              double, double, hipStream_t);
+                                              double, double, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_rr_row<float>(int, double, const float*, const float*, float*, hipStream_t);
 template hipError_t launch_rr_row<double>(int, double, const double*, const double*, double*, hipStream_t);
 template hipError_t launch_prolong_row<float>(int, const float*, float*, hipStream_t);

@@ -26,10 +26,12 @@ int outer_blocks(int n, bool flat, bool double_arith);
 // ---- smoothing (Chebyshev / Jacobi step) ---------------------------------
 // out = x + a (x - xprev) + c D^-1 (b - M x)      (xprev == nullptr: xprev = 0;
 //                                                  x == nullptr: x = 0)
-// out may alias xprev but not x or b.
+// out may alias xprev but not x or b.  Non-null events ev0/ev1 are recorded
+// by the kernel's own dispatch (start and end of execution).
 template <typename T, typename TC>
 hipError_t launch_smooth_step(const OpDesc<TC>& op, const T* x, const T* xprev, const T* b,
-                              T* out, double a, double c, hipStream_t s);
+                              T* out, double a, double c, hipStream_t s, hipEvent_t ev0 = nullptr,
+                              hipEvent_t ev1 = nullptr);
 
 // ---- residual + full-weighting restriction ---------------------------------
 // coarse = R(b - M x) on the (n/2)^3 grid; x == nullptr means x = 0.  When the

@@ -9,6 +9,8 @@
 #include "kernels.h"
 #include "flat_row.h"
 
+#include <hip/hip_ext.h>
+
 #include <cmath>
 #include <cstdint>
 
@@ -778,18 +780,18 @@ int outer_blocks(int n, bool flat, bool double_arith) {
 
 template <typename T, typename TC>
 hipError_t launch_smooth_step(const OpDesc<TC>& op, const T* x, const T* xprev, const T* b, T* out, double a,
-                              double c, hipStream_t s) {
+                              double c, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (op.coeff == nullptr && row_kernels_apply(op.n))
-        return launch_smooth_row<T>(op.n, op.ih2, x, xprev, b, out, a, c / (-6.0 * op.ih2), s);
+        return launch_smooth_row<T>(op.n, op.ih2, x, xprev, b, out, a, c / (-6.0 * op.ih2), s, ev0, ev1);
     Shape sh = stencil_shape(op.n);
     if (x == nullptr)
-        hipLaunchKernelGGL((k_smooth<T, TC, false, false>), sh.grid, sh.block, 0, s, op.n, (T)op.ih2, op.coeff, x,
+        hipExtLaunchKernelGGL((k_smooth<T, TC, false, false>), sh.grid, sh.block, 0, s, ev0, ev1, 0, op.n, (T)op.ih2, op.coeff, x,
                            xprev, b, out, (T)a, (T)c, sh.nz);
     else if (xprev == nullptr)
-        hipLaunchKernelGGL((k_smooth<T, TC, true, false>), sh.grid, sh.block, 0, s, op.n, (T)op.ih2, op.coeff, x,
+        hipExtLaunchKernelGGL((k_smooth<T, TC, true, false>), sh.grid, sh.block, 0, s, ev0, ev1, 0, op.n, (T)op.ih2, op.coeff, x,
                            xprev, b, out, (T)a, (T)c, sh.nz);
     else
-        hipLaunchKernelGGL((k_smooth<T, TC, true, true>), sh.grid, sh.block, 0, s, op.n, (T)op.ih2, op.coeff, x,
+        hipExtLaunchKernelGGL((k_smooth<T, TC, true, true>), sh.grid, sh.block, 0, s, ev0, ev1, 0, op.n, (T)op.ih2, op.coeff, x,
                            xprev, b, out, (T)a, (T)c, sh.nz);
     return hipGetLastError();
 }
@@ -944,7 +946,7 @@ hipError_t launch_hessian_adjoint(int n, double ih2, const double* Jbar, double*
 // ---- explicit instantiations ------------------------------------------------------
 #define INST_T_TC(T, TC)                                                                                         \
     template hipError_t launch_smooth_step<T, TC>(const OpDesc<TC>&, const T*, const T*, const T*, T*, double,   \
-                                                  double, hipStream_t);                                          \
+                                                  double, hipStream_t, hipEvent_t, hipEvent_t);                  \
     template hipError_t launch_residual_restrict<T, TC>(const OpDesc<TC>&, const T*, const T*, T*, T*, hipStream_t); \
     template hipError_t launch_apply<T, TC>(const OpDesc<TC>&, const T*, T*, hipStream_t);
 INST_T_TC(float, float)

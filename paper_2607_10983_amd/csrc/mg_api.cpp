@@ -246,7 +246,10 @@ OpDesc<T> op_of(const Level& L) {
 }
 
 // ---- fine-level smoothing kernel timing ----------------------------------------------
-mg_status time_begin(mg_ctx* c, bool fine) {
+// The event pair travels with the kernel's own dispatch (hipExtLaunchKernel),
+// so the elapsed time is the kernel's execution time, as a profiler sees it.
+mg_status time_events(mg_ctx* c, bool fine, hipEvent_t* ev0, hipEvent_t* ev1) {
+    *ev0 = *ev1 = nullptr;
     if (!c->timing || !fine) return MG_OK;
     if (c->events_used == c->events.size()) {
         TimingPair tp;
@@ -254,12 +257,12 @@ mg_status time_begin(mg_ctx* c, bool fine) {
         HIPCHK(c, hipEventCreate(&tp.stop));
         c->events.push_back(tp);
     }
-    HIPCHK(c, hipEventRecord(c->events[c->events_used].start, c->stream));
+    *ev0 = c->events[c->events_used].start;
+    *ev1 = c->events[c->events_used].stop;
     return MG_OK;
 }
 mg_status time_end(mg_ctx* c, bool fine, double bytes) {
     if (!c->timing || !fine) return MG_OK;
-    HIPCHK(c, hipEventRecord(c->events[c->events_used].stop, c->stream));
     c->events_used++;
     c->timed_launches++;
     c->timed_bytes += bytes;
@@ -298,18 +301,20 @@ mg_status smooth_level(mg_ctx* c, int l, bool from_zero) {
             prev = -1;
             continue;
         }
-        mg_status st = time_begin(c, fine);
+        hipEvent_t ev0, ev1;
+        mg_status st = time_events(c, fine, &ev0, &ev1);
         if (st != MG_OK) return st;
         if (k == 0 && from_zero) {
             cur = 0;
             prev = -1;
-            HIPCHK(c, launch_smooth_step<T, T>(op, nullptr, nullptr, (const T*)L.b, bufs[0], 0.0, L.c[0], c->stream));
+            HIPCHK(c, launch_smooth_step<T, T>(op, nullptr, nullptr, (const T*)L.b, bufs[0], 0.0, L.c[0], c->stream,
+                                               ev0, ev1));
             bytes = 2.0 * fbytes + cbytes;  // read b (and C for D), write x
         } else {
             const T* xp = (cheb && prev >= 0) ? bufs[prev] : nullptr;
             const int out = (cheb && prev >= 0) ? prev : 1 - cur;
             HIPCHK(c, launch_smooth_step<T, T>(op, bufs[cur], xp, (const T*)L.b, bufs[out], L.a[k], L.c[k],
-                                               c->stream));
+                                               c->stream, ev0, ev1));
             bytes = (xp ? 4.0 : 3.0) * fbytes + cbytes;  // read x, [x_prev], b (, C); write out
             prev = cur;
             cur = out;
