@@ -222,15 +222,19 @@ def flat_eigenvalues(n: int, h: float) -> np.ndarray:
     return -(4.0 / (h * h)) * (s(m)[:, None, None] + s(m)[None, :, None] + s(mr)[None, None, :])
 
 
-def fft_solve(b: np.ndarray, h: float) -> np.ndarray:
-    """Exact zero-mean solution of the seven-point system by FFT diagonalisation."""
+def fft_solve(b: np.ndarray, h: float, workers: int = 1) -> np.ndarray:
+    """Exact zero-mean solution of the seven-point system by FFT diagonalisation
+    (``workers`` threads for the library FFT on large grids)."""
+    import scipy.fft as sfft
+
     n = b.shape[0]
     lam = flat_eigenvalues(n, h)
-    B = np.fft.rfftn(b)
+    B = sfft.rfftn(b, workers=workers)
     lam[0, 0, 0] = 1.0
-    E = B / lam
-    E[0, 0, 0] = 0.0
-    return np.fft.irfftn(E, s=b.shape, axes=(0, 1, 2))
+    B /= lam
+    B[0, 0, 0] = 0.0
+    del lam
+    return sfft.irfftn(B, s=b.shape, axes=(0, 1, 2), workers=workers)
 
 
 def dense_from_apply(apply, n: int) -> np.ndarray:
