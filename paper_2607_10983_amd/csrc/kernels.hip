@@ -8,6 +8,7 @@
 // the partials, so every result is bitwise reproducible run to run.
 #include "kernels.h"
 #include "flat_row.h"
+#include "var_row.h"
 
 #include <hip/hip_ext.h>
 
@@ -775,7 +776,8 @@ int stencil_blocks(int n) {
 }
 
 int outer_blocks(int n, bool flat, bool double_arith) {
-    return flat && row_kernels_apply(n) ? row_outer_blocks(n, double_arith) : stencil_blocks(n);
+    if (flat) return row_kernels_apply(n) ? row_outer_blocks(n, double_arith) : stencil_blocks(n);
+    return var_row_kernels_apply(n) ? var_row_blocks(n) : stencil_blocks(n);
 }
 
 template <typename T, typename TC>
@@ -783,6 +785,8 @@ hipError_t launch_smooth_step(const OpDesc<TC>& op, const T* x, const T* xprev, 
                               double c, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (op.coeff == nullptr && row_kernels_apply(op.n))
         return launch_smooth_row<T>(op.n, op.ih2, x, xprev, b, out, a, c / (-6.0 * op.ih2), s, ev0, ev1);
+    if (op.coeff != nullptr && var_row_kernels_apply(op.n))
+        return launch_var_smooth_row<T, TC>(op.n, op.ih2, op.coeff, x, xprev, b, out, a, c, s, ev0, ev1);
     Shape sh = stencil_shape(op.n);
     if (x == nullptr)
         hipExtLaunchKernelGGL((k_smooth<T, TC, false, false>), sh.grid, sh.block, 0, s, ev0, ev1, 0, op.n, (T)op.ih2, op.coeff, x,
@@ -802,8 +806,14 @@ hipError_t launch_residual_restrict(const OpDesc<TC>& op, const T* x, const T* b
     if (op.coeff == nullptr && x != nullptr && row_kernels_apply(op.n))
         return launch_rr_row<T>(op.n, op.ih2, x, b, coarse, s);
     if (scratch != nullptr && x != nullptr) {
-        Shape sf = stencil_shape(op.n);
-        hipLaunchKernelGGL((k_apply<T, TC>), sf.grid, sf.block, 0, s, op.n, (T)op.ih2, op.coeff, x, b, scratch, sf.nz);
+        if (op.coeff != nullptr && var_row_kernels_apply(op.n)) {
+            hipError_t e = launch_var_resid_row<T, TC>(op.n, op.ih2, op.coeff, x, b, scratch, s);
+            if (e != hipSuccess) return e;
+        } else {
+            Shape sf = stencil_shape(op.n);
+            hipLaunchKernelGGL((k_apply<T, TC>), sf.grid, sf.block, 0, s, op.n, (T)op.ih2, op.coeff, x, b, scratch,
+                               sf.nz);
+        }
         Shape sc = stencil_shape(op.n / 2);
         hipLaunchKernelGGL((k_restrict<T>), sc.grid, sc.block, 0, s, op.n, (const T*)scratch, coarse, sc.nz);
         return hipGetLastError();
@@ -837,6 +847,8 @@ hipError_t launch_prolong_add(int n, const T* e, T* x, hipStream_t s) {
 
 template <typename T, typename TC>
 hipError_t launch_apply(const OpDesc<TC>& op, const T* u, T* out, hipStream_t s) {
+    if (op.coeff != nullptr && var_row_kernels_apply(op.n))
+        return launch_var_resid_row<T, TC>(op.n, op.ih2, op.coeff, u, (const T*)nullptr, out, s);
     Shape sh = stencil_shape(op.n);
     hipLaunchKernelGGL((k_apply<T, TC>), sh.grid, sh.block, 0, s, op.n, (T)op.ih2, op.coeff, u, (const T*)nullptr,
                        out, sh.nz);
@@ -850,6 +862,9 @@ hipError_t launch_outer_residual(const OpDesc<TC>& op, const double* phi_in, con
     if (op.coeff == nullptr && row_kernels_apply(op.n))
         return launch_outer_row<TA, TR, TE>(op.n, op.ih2, phi_in, e, phi_out, b, bmean, r, x1,
                                             c0 / (-6.0 * op.ih2), partials, s);
+    if (op.coeff != nullptr && var_row_kernels_apply(op.n))
+        return launch_var_outer_row<TA, TR, TE, TC>(op.n, op.ih2, op.coeff, phi_in, e, phi_out, b, bmean, r, x1, c0,
+                                                    partials, s);
     Shape sh = stencil_shape(op.n);
     if (e)
         hipLaunchKernelGGL((k_outer_residual<TA, TR, TE, TC, true>), sh.grid, sh.block, 0, s, op.n, (TA)op.ih2,

@@ -1,0 +1,24 @@
+// 19-point flux-form operator, row-wave kernels (var_row.hip) for levels with
+// 64 <= n <= 1024.  Internal interface.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace mg {
+
+bool var_row_kernels_apply(int n);
+// number of per-block partial sums launch_var_outer_row writes
+int var_row_blocks(int n);
+
+// out = x + a (x - xprev) + c D^-1 (b - M x); x == nullptr: out = c D^-1 b
+template <typename T, typename TC>
+hipError_t launch_var_smooth_row(int n, double ih2, const TC* C, const T* x, const T* xprev, const T* b, T* out,
+                                 double a, double c, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+// out = b - M x (b != nullptr) or out = M x
+template <typename T, typename TC>
+hipError_t launch_var_resid_row(int n, double ih2, const TC* C, const T* x, const T* b, T* out, hipStream_t s);
+template <typename TA, typename TR, typename TE, typename TC>
+hipError_t launch_var_outer_row(int n, double ih2, const TC* C, const double* phi_in, const TE* e, double* phi_out,
+                                const double* b, double bmean, TR* r, TR* x1, double c0, double* partials,
+                                hipStream_t s);
+
+}  // namespace mg

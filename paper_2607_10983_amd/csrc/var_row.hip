@@ -1,0 +1,523 @@
+// 19-point flux-form operator, row-wave kernels for 64 <= n <= 1024.
+//
+// Same organisation as the seven-point row kernels: one wavefront owns one
+// whole x-row (lane l holds VEC = n/64 contiguous elements), x-shifted values
+// of any row come from rotating cross-lane moves (periodic wrap included),
+// and the wave marches a chunk of z-planes keeping the 3 x 3 (y, z) block of
+// iterate rows around its row in registers.  The six coefficient fields are
+// read row by row (the rows at y +- 1 and z +- 1 are re-reads served by
+// L1/L2).  The operator (Sec. 4.3.1, cross terms read as averaged fluxes):
+//   M u = sum_a [f_a+ (u_{+a} - u) - f_a- (u - u_{-a})] / h^2
+//       + 1/(4 h^2) sum_{a != b} [C^{ab}_{+a} (u_{+a+b} - u_{+a-b}) - C^{ab}_{-a} (u_{-a+b} - u_{-a-b})]
+// with f_a+- the mean of C^{aa} over the two cells of the face, and
+// D = -sum_a (f_a+ + f_a-) / h^2 its diagonal.
+#include "var_row.h"
+
+#include <hip/hip_ext.h>
+
+namespace mg {
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kBlock = 64 * kWaves;
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v2i __attribute__((ext_vector_type(2)));
+
+template <typename T, int VEC>
+__device__ __forceinline__ void ldrow(T (&v)[VEC], const T* p) {
+    constexpr int B = VEC * (int)sizeof(T);
+    if constexpr (B >= 16) {
+#pragma unroll
+        for (int k = 0; k < B / 16; ++k) {
+            const v4i t = *(reinterpret_cast<const v4i*>(p) + k);
+            __builtin_memcpy(&v[k * 16 / (int)sizeof(T)], &t, 16);
+        }
+    } else if constexpr (B == 8) {
+        const v2i t = *reinterpret_cast<const v2i*>(p);
+        __builtin_memcpy(&v[0], &t, 8);
+    } else {
+        v[0] = p[0];
+    }
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void strow(T* p, const T (&v)[VEC]) {
+    constexpr int B = VEC * (int)sizeof(T);
+    if constexpr (B >= 16) {
+#pragma unroll
+        for (int k = 0; k < B / 16; ++k) {
+            v4i t;
+            __builtin_memcpy(&t, &v[k * 16 / (int)sizeof(T)], 16);
+            *(reinterpret_cast<v4i*>(p) + k) = t;
+        }
+    } else if constexpr (B == 8) {
+        v2i t;
+        __builtin_memcpy(&t, &v[0], 8);
+        *reinterpret_cast<v2i*>(p) = t;
+    } else {
+        p[0] = v[0];
+    }
+}
+
+// coefficient row in compute precision T
+template <typename T, typename TC, int VEC>
+__device__ __forceinline__ void ldcrow(T (&v)[VEC], const TC* p) {
+    TC t[VEC];
+    ldrow<TC, VEC>(t, p);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) v[e] = (T)t[e];
+}
+
+template <typename T>
+__device__ __forceinline__ T lane_rot(T v, int delta) {
+    const int lane = threadIdx.x & 63;
+    return __shfl(v, (lane + delta) & 63, 64);
+}
+
+// Row shifted by +1 / -1 in x: element e of the result is row[e + 1] / row[e - 1].
+template <typename T, int VEC>
+__device__ __forceinline__ void shifts(const T (&r)[VEC], T (&p)[VEC], T (&m)[VEC]) {
+    const T first_next = lane_rot(r[0], 1);
+    const T last_prev = lane_rot(r[VEC - 1], -1);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        p[e] = e < VEC - 1 ? r[e + 1] : first_next;
+        m[e] = e > 0 ? r[e - 1] : last_prev;
+    }
+}
+
+__device__ __forceinline__ int xcd_logical(int bid, int nb) {
+    if (nb & 7) return bid;
+    return (bid & 7) * (nb >> 3) + (bid >> 3);
+}
+
+struct RowGrid {
+    int n, mask;
+    __device__ __forceinline__ size_t row(int y, int z) const {
+        return ((size_t)(z & mask) * (size_t)n + (size_t)(y & mask)) * (size_t)n;
+    }
+};
+
+// U[dy + 1][dz + 1] = iterate rows (y + dy, z + dz); returns M u and D of row (y, z).
+template <typename T, typename TC, int VEC>
+__device__ __forceinline__ void var19_row(const T (&U)[3][3][VEC], const TC* __restrict__ C, size_t N,
+                                          const RowGrid& g, int y, int z, size_t off, T ih2, T (&Mu)[VEC],
+                                          T (&D)[VEC]) {
+    const TC* Cxx = C;
+    const TC* Cyy = C + N;
+    const TC* Czz = C + 2 * N;
+    const TC* Cxy = C + 3 * N;
+    const TC* Cxz = C + 4 * N;
+    const TC* Cyz = C + 5 * N;
+    const size_t r0 = g.row(y, z) + off;
+    T acc[VEC], dsum[VEC], cross[VEC];
+    T up[VEC], um[VEC];
+    shifts<T, VEC>(U[1][1], up, um);
+    {   // x faces
+        T c[VEC], cp[VEC], cm[VEC];
+        ldcrow<T, TC, VEC>(c, Cxx + r0);
+        shifts<T, VEC>(c, cp, cm);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const T uc = U[1][1][e];
+            const T fp = T(0.5) * (c[e] + cp[e]), fm = T(0.5) * (c[e] + cm[e]);
+            acc[e] = fp * (up[e] - uc) - fm * (uc - um[e]);
+            dsum[e] = fp + fm;
+        }
+    }
+    {   // y faces
+        T c[VEC], cp[VEC], cm[VEC];
+        ldcrow<T, TC, VEC>(c, Cyy + r0);
+        ldcrow<T, TC, VEC>(cp, Cyy + g.row(y + 1, z) + off);
+        ldcrow<T, TC, VEC>(cm, Cyy + g.row(y - 1, z) + off);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const T uc = U[1][1][e];
+            const T fp = T(0.5) * (c[e] + cp[e]), fm = T(0.5) * (c[e] + cm[e]);
+            acc[e] += fp * (U[2][1][e] - uc) - fm * (uc - U[0][1][e]);
+            dsum[e] += fp + fm;
+        }
+    }
+    {   // z faces
+        T c[VEC], cp[VEC], cm[VEC];
+        ldcrow<T, TC, VEC>(c, Czz + r0);
+        ldcrow<T, TC, VEC>(cp, Czz + g.row(y, z + 1) + off);
+        ldcrow<T, TC, VEC>(cm, Czz + g.row(y, z - 1) + off);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const T uc = U[1][1][e];
+            const T fp = T(0.5) * (c[e] + cp[e]), fm = T(0.5) * (c[e] + cm[e]);
+            acc[e] += fp * (U[1][2][e] - uc) - fm * (uc - U[1][0][e]);
+            dsum[e] += fp + fm;
+        }
+    }
+    {   // pairs (x,y) and (y,x): C^{xy} at x+-1 (row y) and at y+-1
+        T c[VEC], cxp[VEC], cxm[VEC], cyp[VEC], cym[VEC];
+        ldcrow<T, TC, VEC>(c, Cxy + r0);
+        shifts<T, VEC>(c, cxp, cxm);
+        ldcrow<T, TC, VEC>(cyp, Cxy + g.row(y + 1, z) + off);
+        ldcrow<T, TC, VEC>(cym, Cxy + g.row(y - 1, z) + off);
+        T ypp[VEC], ypm[VEC], ymp[VEC], ymm[VEC];  // u(y+1, x+-1), u(y-1, x+-1)
+        shifts<T, VEC>(U[2][1], ypp, ypm);
+        shifts<T, VEC>(U[0][1], ymp, ymm);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            // upp = u(x+1,y+1), upm = u(x+1,y-1), ump = u(x-1,y+1), umm = u(x-1,y-1)
+            const T upp = ypp[e], upm = ymp[e], ump = ypm[e], umm = ymm[e];
+            cross[e] = cxp[e] * (upp - upm) - cxm[e] * (ump - umm) + cyp[e] * (upp - ump) - cym[e] * (upm - umm);
+        }
+    }
+    {   // pairs (x,z) and (z,x)
+        T c[VEC], cxp[VEC], cxm[VEC], czp[VEC], czm[VEC];
+        ldcrow<T, TC, VEC>(c, Cxz + r0);
+        shifts<T, VEC>(c, cxp, cxm);
+        ldcrow<T, TC, VEC>(czp, Cxz + g.row(y, z + 1) + off);
+        ldcrow<T, TC, VEC>(czm, Cxz + g.row(y, z - 1) + off);
+        T zpp[VEC], zpm[VEC], zmp[VEC], zmm[VEC];  // u(z+1, x+-1), u(z-1, x+-1)
+        shifts<T, VEC>(U[1][2], zpp, zpm);
+        shifts<T, VEC>(U[1][0], zmp, zmm);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const T upp = zpp[e], upm = zmp[e], ump = zpm[e], umm = zmm[e];
+            cross[e] += cxp[e] * (upp - upm) - cxm[e] * (ump - umm) + czp[e] * (upp - ump) - czm[e] * (upm - umm);
+        }
+    }
+    {   // pairs (y,z) and (z,y)
+        T cyp[VEC], cym[VEC], czp[VEC], czm[VEC];
+        ldcrow<T, TC, VEC>(cyp, Cyz + g.row(y + 1, z) + off);
+        ldcrow<T, TC, VEC>(cym, Cyz + g.row(y - 1, z) + off);
+        ldcrow<T, TC, VEC>(czp, Cyz + g.row(y, z + 1) + off);
+        ldcrow<T, TC, VEC>(czm, Cyz + g.row(y, z - 1) + off);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            // upp = u(y+1,z+1), upm = u(y+1,z-1), ump = u(y-1,z+1), umm = u(y-1,z-1)
+            const T upp = U[2][2][e], upm = U[2][0][e], ump = U[0][2][e], umm = U[0][0][e];
+            cross[e] += cyp[e] * (upp - upm) - cym[e] * (ump - umm) + czp[e] * (upp - ump) - czm[e] * (upm - umm);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        Mu[e] = (acc[e] + T(0.25) * cross[e]) * ih2;
+        D[e] = -dsum[e] * ih2;
+    }
+}
+
+// diagonal only (first smoothing step from zero)
+template <typename T, typename TC, int VEC>
+__device__ __forceinline__ void var19_diag(const TC* __restrict__ C, size_t N, const RowGrid& g, int y, int z,
+                                           size_t off, T ih2, T (&D)[VEC]) {
+    const size_t r0 = g.row(y, z) + off;
+    T c[VEC], cp[VEC], cm[VEC], d[VEC];
+    ldcrow<T, TC, VEC>(c, C + r0);
+    shifts<T, VEC>(c, cp, cm);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) d[e] = T(0.5) * (c[e] + cp[e]) + T(0.5) * (c[e] + cm[e]);
+    ldcrow<T, TC, VEC>(c, C + N + r0);
+    ldcrow<T, TC, VEC>(cp, C + N + g.row(y + 1, z) + off);
+    ldcrow<T, TC, VEC>(cm, C + N + g.row(y - 1, z) + off);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) d[e] += T(0.5) * (c[e] + cp[e]) + T(0.5) * (c[e] + cm[e]);
+    ldcrow<T, TC, VEC>(c, C + 2 * N + r0);
+    ldcrow<T, TC, VEC>(cp, C + 2 * N + g.row(y, z + 1) + off);
+    ldcrow<T, TC, VEC>(cm, C + 2 * N + g.row(y, z - 1) + off);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) D[e] = -(d[e] + T(0.5) * (c[e] + cp[e]) + T(0.5) * (c[e] + cm[e])) * ih2;
+}
+
+// value accessor of the iterate rows: plain field, or phi + e formed in double
+template <typename T, typename TU, int VEC>
+struct PlainRows {
+    const TU* u;
+    __device__ __forceinline__ void load(T (&v)[VEC], size_t r) const {
+        TU t[VEC];
+        ldrow<TU, VEC>(t, u + r);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) v[e] = (T)t[e];
+    }
+};
+template <typename T, typename TE, int VEC>
+struct SumRows {
+    const double* p;
+    const TE* e;
+    __device__ __forceinline__ void load(T (&v)[VEC], size_t r) const {
+        double a[VEC];
+        TE b[VEC];
+        ldrow<double, VEC>(a, p + r);
+        ldrow<TE, VEC>(b, e + r);
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) v[k] = (T)(a[k] + (double)b[k]);
+    }
+};
+
+template <typename T, int VEC, typename Src>
+__device__ __forceinline__ void load_plane3(T (&U)[3][3][VEC], int dz, const Src& src, const RowGrid& g, int y, int z,
+                                            size_t off) {
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) src.load(U[dy][dz], g.row(y + dy - 1, z) + off);
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void shift_queue(T (&U)[3][3][VEC]) {
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            U[dy][0][e] = U[dy][1][e];
+            U[dy][1][e] = U[dy][2][e];
+        }
+}
+
+// =====================================================================================
+// smoothing step: out = x + a (x - xprev) + c D^-1 (b - M x)
+// =====================================================================================
+template <typename T, typename TC, int VEC, bool HASX, bool PREV>
+__global__ __launch_bounds__(kBlock) void k_var_smooth_row(int n, T ih2, const TC* __restrict__ C, const T* x,
+                                                           const T* xprev, const T* __restrict__ b, T* out, T a, T c,
+                                                           int nz, int nyb) {
+    const RowGrid g{n, n - 1};
+    const size_t N = (size_t)n * n * n;
+    const int lb = xcd_logical(blockIdx.x, gridDim.x);
+    const int yb = lb % nyb, zc = lb / nyb;
+    const int y = yb * kWaves + (threadIdx.x >> 6);
+    const int z0 = zc * nz;
+    const size_t off = (size_t)(threadIdx.x & 63) * VEC;
+    if constexpr (!HASX) {
+        for (int k = 0; k < nz; ++k) {
+            const int z = z0 + k;
+            T D[VEC], bb[VEC], o[VEC];
+            var19_diag<T, TC, VEC>(C, N, g, y, z, off, ih2, D);
+            ldrow<T, VEC>(bb, b + g.row(y, z) + off);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) o[e] = c * bb[e] / D[e];
+            strow<T, VEC>(out + g.row(y, z) + off, o);
+        }
+    } else {
+        const PlainRows<T, T, VEC> src{x};
+        T U[3][3][VEC];
+        load_plane3<T, VEC>(U, 0, src, g, y, z0 - 1, off);
+        load_plane3<T, VEC>(U, 1, src, g, y, z0, off);
+        for (int k = 0; k < nz; ++k) {
+            const int z = z0 + k;
+            load_plane3<T, VEC>(U, 2, src, g, y, z + 1, off);
+            T bb[VEC], pp[VEC], Mu[VEC], D[VEC], o[VEC];
+            const size_t r = g.row(y, z) + off;
+            ldrow<T, VEC>(bb, b + r);
+            if constexpr (PREV) ldrow<T, VEC>(pp, xprev + r);
+            var19_row<T, TC, VEC>(U, C, N, g, y, z, off, ih2, Mu, D);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                const T xc = U[1][1][e];
+                const T xp = PREV ? pp[e] : T(0);
+                o[e] = xc + a * (xc - xp) + c * (bb[e] - Mu[e]) / D[e];
+            }
+            strow<T, VEC>(out + r, o);
+            shift_queue<T, VEC>(U);
+        }
+    }
+}
+
+// =====================================================================================
+// residual r = b - M x (scratch of the two-pass residual restriction) / apply
+// =====================================================================================
+template <typename T, typename TC, int VEC, bool WITHB>
+__global__ __launch_bounds__(kBlock) void k_var_resid_row(int n, T ih2, const TC* __restrict__ C,
+                                                          const T* __restrict__ x, const T* __restrict__ b,
+                                                          T* __restrict__ out, int nz, int nyb) {
+    const RowGrid g{n, n - 1};
+    const size_t N = (size_t)n * n * n;
+    const int lb = xcd_logical(blockIdx.x, gridDim.x);
+    const int yb = lb % nyb, zc = lb / nyb;
+    const int y = yb * kWaves + (threadIdx.x >> 6);
+    const int z0 = zc * nz;
+    const size_t off = (size_t)(threadIdx.x & 63) * VEC;
+    const PlainRows<T, T, VEC> src{x};
+    T U[3][3][VEC];
+    load_plane3<T, VEC>(U, 0, src, g, y, z0 - 1, off);
+    load_plane3<T, VEC>(U, 1, src, g, y, z0, off);
+    for (int k = 0; k < nz; ++k) {
+        const int z = z0 + k;
+        load_plane3<T, VEC>(U, 2, src, g, y, z + 1, off);
+        const size_t r = g.row(y, z) + off;
+        T Mu[VEC], D[VEC], o[VEC];
+        var19_row<T, TC, VEC>(U, C, N, g, y, z, off, ih2, Mu, D);
+        if constexpr (WITHB) {
+            T bb[VEC];
+            ldrow<T, VEC>(bb, b + r);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) o[e] = bb[e] - Mu[e];
+        } else {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) o[e] = Mu[e];
+        }
+        strow<T, VEC>(out + r, o);
+        shift_queue<T, VEC>(U);
+    }
+}
+
+// =====================================================================================
+// outer defect correction in TA: value = phi (+ e), r = (b - bmean) - M value,
+// optional x1 = c0 D^-1 r, partial sums of r^2
+// =====================================================================================
+template <typename TA, typename TR, typename TE, typename TC, int VEC, bool UPDATE>
+__global__ __launch_bounds__(kBlock) void k_var_outer_row(int n, TA ih2, const TC* __restrict__ C,
+                                                          const double* __restrict__ phi_in,
+                                                          const TE* __restrict__ e, double* __restrict__ phi_out,
+                                                          const double* __restrict__ b, double bmean,
+                                                          TR* __restrict__ r, TR* __restrict__ x1, TA c0,
+                                                          double* __restrict__ partials, int nz, int nyb) {
+    __shared__ double sh[kWaves];
+    const RowGrid g{n, n - 1};
+    const size_t N = (size_t)n * n * n;
+    const int lb = xcd_logical(blockIdx.x, gridDim.x);
+    const int yb = lb % nyb, zc = lb / nyb;
+    const int wave = threadIdx.x >> 6;
+    const int y = yb * kWaves + wave;
+    const int z0 = zc * nz;
+    const size_t off = (size_t)(threadIdx.x & 63) * VEC;
+    double ss = 0.0;
+    auto body = [&](const auto& src) {
+        TA U[3][3][VEC];
+        load_plane3<TA, VEC>(U, 0, src, g, y, z0 - 1, off);
+        load_plane3<TA, VEC>(U, 1, src, g, y, z0, off);
+        for (int k = 0; k < nz; ++k) {
+            const int z = z0 + k;
+            load_plane3<TA, VEC>(U, 2, src, g, y, z + 1, off);
+            const size_t row = g.row(y, z) + off;
+            double bb[VEC];
+            ldrow<double, VEC>(bb, b + row);
+            TA Mu[VEC], D[VEC];
+            TR ro[VEC];
+            var19_row<TA, TC, VEC>(U, C, N, g, y, z, off, ih2, Mu, D);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) {
+                const TA ri = (TA)(bb[q] - bmean) - Mu[q];
+                ro[q] = (TR)ri;
+                ss += (double)ri * (double)ri;
+            }
+            strow<TR, VEC>(r + row, ro);
+            if (x1) {
+                TR xo[VEC];
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) xo[q] = (TR)(c0 * (TA)ro[q] / D[q]);
+                strow<TR, VEC>(x1 + row, xo);
+            }
+            if constexpr (UPDATE) {
+                double p[VEC], po[VEC];
+                TE qv[VEC];
+                ldrow<double, VEC>(p, phi_in + row);
+                ldrow<TE, VEC>(qv, e + row);
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) po[q] = p[q] + (double)qv[q];
+                strow<double, VEC>(phi_out + row, po);
+            }
+            shift_queue<TA, VEC>(U);
+        }
+    };
+    if constexpr (UPDATE) body(SumRows<TA, TE, VEC>{phi_in, e});
+    else body(PlainRows<TA, double, VEC>{phi_in});
+    for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[wave] = ss;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+void shape(int n, int& nz, int& nyb, int& blocks) {
+    nyb = n / kWaves;
+    nz = n;
+    while (nz > 4 && nyb * (n / nz) < 2048) nz >>= 1;
+    blocks = nyb * (n / nz);
+}
+
+}  // namespace
+
+bool var_row_kernels_apply(int n) { return n >= 64 && n <= 1024 && (n & (n - 1)) == 0; }
+
+int var_row_blocks(int n) {
+    int nz, nyb, blocks;
+    shape(n, nz, nyb, blocks);
+    return blocks;
+}
+
+#define DISPATCH_VEC(n, ...)                                       \
+    switch (n) {                                                   \
+        case 64: { constexpr int VEC = 1; __VA_ARGS__; break; }    \
+        case 128: { constexpr int VEC = 2; __VA_ARGS__; break; }   \
+        case 256: { constexpr int VEC = 4; __VA_ARGS__; break; }   \
+        case 512: { constexpr int VEC = 8; __VA_ARGS__; break; }   \
+        case 1024: { constexpr int VEC = 16; __VA_ARGS__; break; } \
+        default: return hipErrorInvalidValue;                      \
+    }
+
+template <typename T, typename TC>
+hipError_t launch_var_smooth_row(int n, double ih2, const TC* C, const T* x, const T* xprev, const T* b, T* out,
+                                 double a, double c, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    int nz, nyb, blocks;
+    shape(n, nz, nyb, blocks);
+    DISPATCH_VEC(n, {
+        if (x == nullptr)
+            hipExtLaunchKernelGGL((k_var_smooth_row<T, TC, VEC, false, false>), dim3(blocks), dim3(kBlock), 0, s, ev0,
+                                  ev1, 0, n, (T)ih2, C, x, xprev, b, out, (T)a, (T)c, nz, nyb);
+        else if (xprev == nullptr)
+            hipExtLaunchKernelGGL((k_var_smooth_row<T, TC, VEC, true, false>), dim3(blocks), dim3(kBlock), 0, s, ev0,
+                                  ev1, 0, n, (T)ih2, C, x, xprev, b, out, (T)a, (T)c, nz, nyb);
+        else
+            hipExtLaunchKernelGGL((k_var_smooth_row<T, TC, VEC, true, true>), dim3(blocks), dim3(kBlock), 0, s, ev0,
+                                  ev1, 0, n, (T)ih2, C, x, xprev, b, out, (T)a, (T)c, nz, nyb);
+    })
+    return hipGetLastError();
+}
+
+template <typename T, typename TC>
+hipError_t launch_var_resid_row(int n, double ih2, const TC* C, const T* x, const T* b, T* out, hipStream_t s) {
+    int nz, nyb, blocks;
+    shape(n, nz, nyb, blocks);
+    DISPATCH_VEC(n, {
+        if (b)
+            hipLaunchKernelGGL((k_var_resid_row<T, TC, VEC, true>), dim3(blocks), dim3(kBlock), 0, s, n, (T)ih2, C, x,
+                               b, out, nz, nyb);
+        else
+            hipLaunchKernelGGL((k_var_resid_row<T, TC, VEC, false>), dim3(blocks), dim3(kBlock), 0, s, n, (T)ih2, C,
+                               x, b, out, nz, nyb);
+    })
+    return hipGetLastError();
+}
+
+template <typename TA, typename TR, typename TE, typename TC>
+hipError_t launch_var_outer_row(int n, double ih2, const TC* C, const double* phi_in, const TE* e, double* phi_out,
+                                const double* b, double bmean, TR* r, TR* x1, double c0, double* partials,
+                                hipStream_t s) {
+    int nz, nyb, blocks;
+    shape(n, nz, nyb, blocks);
+    DISPATCH_VEC(n, {
+        if (e)
+            hipLaunchKernelGGL((k_var_outer_row<TA, TR, TE, TC, VEC, true>), dim3(blocks), dim3(kBlock), 0, s, n,
+                               (TA)ih2, C, phi_in, e, phi_out, b, bmean, r, x1, (TA)c0, partials, nz, nyb);
+        else
+            hipLaunchKernelGGL((k_var_outer_row<TA, TR, TE, TC, VEC, false>), dim3(blocks), dim3(kBlock), 0, s, n,
+                               (TA)ih2, C, phi_in, e, phi_out, b, bmean, r, x1, (TA)c0, partials, nz, nyb);
+    })
+    return hipGetLastError();
+}
+
+#define INST_VAR(T, TC)                                                                                            \
+    template hipError_t launch_var_smooth_row<T, TC>(int, double, const TC*, const T*, const T*, const T*, T*,     \
+                                                     double, double, hipStream_t, hipEvent_t, hipEvent_t);         \
+    template hipError_t launch_var_resid_row<T, TC>(int, double, const TC*, const T*, const T*, T*, hipStream_t);
+INST_VAR(float, float)
+INST_VAR(double, double)
+INST_VAR(double, float)
+INST_VAR(float, double)
+
+#define INST_VOUT(TA, TR, TE, TC)                                                                                  \
+    template hipError_t launch_var_outer_row<TA, TR, TE, TC>(int, double, const TC*, const double*, const TE*,     \
+                                                             double*, const double*, double, TR*, TR*, double,     \
+                                                             double*, hipStream_t);
+INST_VOUT(double, double, double, double)
+INST_VOUT(double, double, double, float)
+INST_VOUT(double, float, float, float)
+INST_VOUT(double, float, float, double)
+INST_VOUT(float, float, float, float)
+INST_VOUT(float, float, float, double)
+
+}  // namespace mg

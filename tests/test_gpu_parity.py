@@ -74,13 +74,14 @@ def test_apply(mgpu, n, var):
     assert np.max(np.abs(out - ref)) <= 1e-13 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("var,n", [(False, 16), (True, 16), (False, 64), (False, 128), (False, 256)])
+@pytest.mark.parametrize("var,n", [(False, 16), (True, 16), (False, 64), (False, 128), (False, 256),
+                                   (True, 64), (True, 128)])
 @pytest.mark.parametrize("degree", [1, 3, 4])
 def test_smooth(mgpu, var, n, degree):
     C = random_spd(n) if var else None
     levels = 2 if n == 16 else int(math.log2(n)) - 2
     mg = mgpu.Multigrid(n, levels=levels, degree=degree, coeff=dev(C) if var else None, precision="fp64")
-    H = O.build_hierarchy(n, 2 if var else 1, degree, C=C)
+    H = O.build_hierarchy(n, levels if var else 1, degree, C=C)
     x = RNG.standard_normal((n, n, n))
     b = RNG.standard_normal((n, n, n))
     ref = O.smooth(H, H.levels[0], x, b)
@@ -104,8 +105,8 @@ def test_smooth_jacobi(mgpu):
 @pytest.mark.parametrize("n", [8, 32, 64, 128, 256])
 @pytest.mark.parametrize("var", [False, True])
 def test_residual_restrict_and_prolong(mgpu, n, var):
-    if var and n > 32:
-        pytest.skip("coarse coefficient levels of a large variable context are not needed here")
+    if var and n > 128:
+        pytest.skip("the 19-point oracle at 256^3 is covered by the full-size tests")
     C = random_spd(n) if var else None
     levels = max(2, int(math.log2(n)) - 2)
     mg = mgpu.Multigrid(n, levels=levels, coeff=dev(C) if var else None, precision="fp64")
@@ -242,6 +243,24 @@ def test_moving_mesh_solve(mgpu, precision, bar, cdtype):
     if precision == "fp64":
         lm = O.gershgorin_lmax_var(Cd, 1.0 / n)
         assert mg.level_lmax()[0] == pytest.approx(lm, rel=1e-13)
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-12), ("mixed", 1e-10)])
+def test_moving_mesh_solve_64(mgpu, precision, bar):
+    """64^3: the fine level runs the 19-point row kernels."""
+    n = 64
+    psi, C, sg = moving_mesh_coeff(n)
+    g = moving_mesh_field(n, 0)
+    b = sg * (g - np.sum(g * sg) / np.sum(sg))
+    ref = O.solve(O.build_hierarchy(n, 5, 3, C=C), b, tol=1e-13, max_cycles=60)
+    mg = mgpu.Multigrid(n, levels=5, coeff=dev(C), precision=precision)
+    phi, info = mg.solve(dev(b), tol=1e-13 if precision == "fp64" else 1e-11, max_cycles=60,
+                         raise_on_error=False)
+    assert rel(host(phi), ref.phi) <= bar
+    if precision == "fp64":
+        h6 = O.solve(O.build_hierarchy(n, 5, 3, C=C), b, tol=0.0, max_cycles=5).history
+        _, i5 = mg.solve(dev(b), tol=0.0, max_cycles=5, raise_on_error=False)
+        assert np.max(np.abs(np.array(i5.history) - np.array(h6))) <= 1e-12
 
 
 def test_moving_mesh_fp64_history(mgpu):
