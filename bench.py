@@ -11,9 +11,12 @@ All inputs are resident in HBM before timing starts.
 
 The JSON line reports V-cycle throughput of the mixed path (value), the same
 sequence in plain float64 (time-to-tolerance ratio), the roofline of the
-dominant kernel (fine-level smoothing step; HIP events around each launch,
-algorithmic bytes counted by the library), a 512^3 V-cycle leg, and the CPU
-oracle timed on a bounded sample.
+dominant kernel (fine-level smoothing step; in-dispatch HIP events around each
+launch, algorithmic bytes counted by the library), a size sweep 32^3 .. 1024^3
+(cold solves to the tolerance, mixed and float64, with the smoothing kernel's
+fraction of the HBM peak; 512^3 and 1024^3 are the large-mesh runs), the
+256^3 moving-mesh solve with its forward/backward timing, and the CPU oracle
+timed on a bounded sample.
 """
 import argparse
 import json
@@ -84,6 +87,96 @@ def run_sequence(mg, sources, phi, tol, max_cycles=60):
     return cycles
 
 
+def solve_timed(mg, torch, b, tol, max_cycles=60):
+    """Cold solve from zero: (cycles, ms, rel_res, kernel launches, kernel ms, kernel bytes)."""
+    phi = torch.zeros_like(b)
+    mg.solve(b, phi0=phi, out=phi, tol=tol, max_cycles=max_cycles, history=False, raise_on_error=False)
+    mg.enable_kernel_timing(True)
+    mg.kernel_timing()
+    phi.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info = mg.solve(b, phi0=phi, out=phi, tol=tol, max_cycles=max_cycles, history=False, raise_on_error=False)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    k, kms, kby = mg.kernel_timing()
+    mg.enable_kernel_timing(False)
+    return info, 1e3 * t, (k, kms, kby), phi
+
+
+def sweep_point(mgpu, torch, flat_source, n, tol):
+    """Cold solve of the k_c = (n/4) 2 pi source to `tol` in mixed and float64
+    precision.  32^3: 4 levels, degree 3; n >= 64: degree 4 with a 16^3
+    coarsest level."""
+    levels, deg = (4, 3) if n == 32 else (int(np.log2(n)) - 3, 4)
+    b = torch.from_numpy(flat_source(n, 0)).to("cuda")
+    out = {"levels": levels, "degree": deg}
+    for prec in ("mixed", "fp64"):
+        mg = mgpu.Multigrid(n, levels=levels, degree=deg, precision=prec)
+        info, ms, (k, kms, kby), phi = solve_timed(mg, torch, b, tol)
+        gbps = kby / (kms * 1e-3) / 1e9 if kms > 0 else None
+        out[prec] = {
+            "cycles": info.cycles,
+            "time_to_tol_ms": round(ms, 3),
+            "vcycle_mpts_per_s": round(info.cycles * n ** 3 / (ms * 1e-3) / 1e6, 1),
+            "rel_res": info.rel_res,
+            "smooth_kernel_GBps": round(gbps, 1) if gbps else None,
+            "smooth_kernel_frac": round(gbps / HBM_PEAK_GBPS, 4) if gbps else None,
+            "smooth_avg_launch_us": round(1e3 * kms / k, 2) if k else None,
+        }
+        del mg, phi
+        torch.cuda.empty_cache()
+    out["time_to_tol_ratio_fp64_over_mixed"] = round(out["fp64"]["time_to_tol_ms"] / out["mixed"]["time_to_tol_ms"], 3)
+    return out
+
+
+def moving_mesh_leg(mgpu, torch, n, tol):
+    """256^3 moving-mesh Poisson (float32 C, 19-point operator) to `tol`, mixed
+    vs float64; then forward and forward+backward of L = sum(w phi) through the
+    geometry, the source and the solve (implicit adjoint)."""
+    from workloads import loss_weight, moving_mesh_field, psi_unit
+
+    scale = json.load(open(os.path.join(ROOT, "tests", "golden", "psi_scale.json")))["scale"][str(n)]
+    psi = torch.from_numpy(scale * psi_unit(n)).to("cuda")
+    g = torch.from_numpy(moving_mesh_field(n, 0)).to("cuda")
+    w = torch.from_numpy(loss_weight(n, 2)).to("cuda")
+    C32, sg = mgpu.geometry(psi, dtype=torch.float32)
+    b = sg * (g - (g * sg).sum() / sg.sum())
+    out = {"n": n, "levels": int(np.log2(n)) - 1, "degree": 3, "psi_scale": scale,
+           "det_J": [round(float(sg.min()), 4), round(float(sg.max()), 4)]}
+    for prec in ("mixed", "fp64"):
+        mg = mgpu.Multigrid(n, coeff=C32, precision=prec)
+        info, ms, (k, kms, kby), phi = solve_timed(mg, torch, b, tol, max_cycles=100)
+        gbps = kby / (kms * 1e-3) / 1e9 if kms > 0 else None
+        out[prec] = {"cycles": info.cycles, "time_to_tol_ms": round(ms, 3), "rel_res": info.rel_res,
+                     "smooth_kernel_GBps": round(gbps, 1) if gbps else None}
+        del mg, phi
+    out["time_to_tol_ratio_fp64_over_mixed"] = round(out["fp64"]["time_to_tol_ms"] / out["mixed"]["time_to_tol_ms"], 3)
+
+    def fwd_bwd(prec, backward):
+        p = psi.clone().requires_grad_(backward)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        C, s = mgpu.geometry_fn(p)
+        bb = s * (g - (g * s).sum() / s.sum())
+        ph = mgpu.solve(bb, C, tol=tol, max_cycles=100, precision=prec)
+        L = (w * ph).sum()
+        if backward:
+            L.backward()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0)
+
+    grads = {}
+    for prec in ("mixed", "fp64"):
+        fwd_bwd(prec, True)
+        f = min(fwd_bwd(prec, False) for _ in range(2))
+        fb = min(fwd_bwd(prec, True) for _ in range(2))
+        grads[prec] = {"forward_ms": round(f, 2), "forward_backward_ms": round(fb, 2),
+                       "ratio": round(fb / f, 3)}
+    out["gradient"] = grads
+    return out
+
+
 def timed(fn, steps, torch):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -102,7 +195,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--degree", type=int, default=3)
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison sequence")
-    ap.add_argument("--no-b512", action="store_true", help="skip the 512^3 V-cycle leg")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the 32^3..1024^3 size sweep")
+    ap.add_argument("--sweep-max", type=int, default=1024, help="largest grid of the size sweep")
+    ap.add_argument("--no-mm", action="store_true", help="skip the moving-mesh and gradient leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     args = ap.parse_args()
 
@@ -176,40 +271,20 @@ def main():
         }
         del mg64
 
-    # ------------------------------------------------------------- 512^3 V-cycle leg
-    b512 = None
-    if not args.no_b512:
-        n5, lv5, d5 = 512, 6, 4
-        print("[bench] 512^3 leg: generating source", file=sys.stderr, flush=True)
-        b5 = torch.from_numpy(flat_source(n5, 0)).to(dev)
-        p5 = torch.zeros_like(b5)
-        m5 = mgpu.Multigrid(n5, levels=lv5, degree=d5, precision="mixed")
-        m5.solve(b5, phi0=p5, out=p5, tol=0.0, max_cycles=3, history=False, raise_on_error=False)
-        m5.enable_kernel_timing(True)
-        m5.kernel_timing()
-        p5.zero_()
-        ncyc = 20
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, info5 = m5.solve(b5, phi0=p5, out=p5, tol=0.0, max_cycles=ncyc, history=True, raise_on_error=False)
-        torch.cuda.synchronize()
-        t5 = time.perf_counter() - t0
-        l5, ms5, by5 = m5.kernel_timing()
-        bpc = model_bytes_per_cycle(n5, lv5, d5, "mixed")
-        b512 = {
-            "workload": "512^3 seven-point Poisson, GRF k^-1 exp(-(k/(128*2pi))^2), 6 levels, degree 4, "
-                        "mixed precision, 20 cycles from zero",
-            "cycles": info5.cycles,
-            "ms_per_cycle": round(1e3 * t5 / info5.cycles, 3),
-            "vcycle_mpts_per_s": round(info5.cycles * n5 ** 3 / t5 / 1e6, 1),
-            "model_bytes_per_cycle_per_pt": round(bpc / n5 ** 3, 2),
-            "model_GBps": round(info5.cycles * bpc / t5 / 1e9, 1),
-            "rel_res_final": info5.rel_res,
-            "smooth_kernel_GBps": round(by5 / (ms5 * 1e-3) / 1e9, 1) if ms5 else None,
-            "smooth_kernel_frac": round(by5 / (ms5 * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4) if ms5 else None,
-            "smooth_avg_launch_us": round(1e3 * ms5 / l5, 2) if l5 else None,
-        }
-        del m5, b5, p5
+    # ------------------------------------------------------------- size sweep 32^3 .. 1024^3
+    sweep = {}
+    if not args.no_sweep:
+        for ns in [m for m in (32, 64, 128, 256, 512, 1024) if m <= args.sweep_max]:
+            print(f"[bench] sweep {ns}^3", file=sys.stderr, flush=True)
+            sweep[str(ns)] = sweep_point(mgpu, torch, flat_source, ns, args.tol)
+            torch.cuda.empty_cache()
+
+    # ------------------------------------------------------------- moving mesh (19-point operator)
+    mm = None
+    if not args.no_mm:
+        print("[bench] moving-mesh leg", file=sys.stderr, flush=True)
+        mm = moving_mesh_leg(mgpu, torch, 256, args.tol)
+        torch.cuda.empty_cache()
 
     # ------------------------------------------------------------- CPU oracle baseline
     cpu = None
@@ -263,7 +338,9 @@ def main():
         "model_GBps": round(total_cycles * bytes_cycle / t_mixed / 1e9, 1),
         "roofline": roofline,
         "fp64": fp64,
-        "b512": b512,
+        "sweep": sweep,
+        "b512": sweep.get("512"),
+        "moving_mesh": mm,
         "cpu_baseline": cpu,
     }
     print(json.dumps(result), flush=True)
