@@ -13,7 +13,7 @@
 // and share their halo rows through that XCD's L2.
 #include "flat_row.h"
 
-#include <hip/hip_ext.h>
+#include "launch.h"
 
 #include <cstdint>
 
@@ -683,10 +683,10 @@ hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, cons
         DISPATCH_VEC(n, {
             if constexpr (2ull * (Wv + 2) * 64 * VEC * sizeof(T) <= kLdsBudget) {
                 if (xprev == nullptr)
-                    hipExtLaunchKernelGGL((k_smooth_lds<T, VEC, Wv, false>), dim3(blocks), dim3(64 * Wv), 0, s, ev0, ev1, 0, n,
+                    MG_LAUNCH((k_smooth_lds<T, VEC, Wv, false>), dim3(blocks), dim3(64 * Wv), s, ev0, ev1, n,
                                        (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb);
                 else
-                    hipExtLaunchKernelGGL((k_smooth_lds<T, VEC, Wv, true>), dim3(blocks), dim3(64 * Wv), 0, s, ev0, ev1, 0, n,
+                    MG_LAUNCH((k_smooth_lds<T, VEC, Wv, true>), dim3(blocks), dim3(64 * Wv), s, ev0, ev1, n,
                                        (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb);
             }
         })
@@ -695,13 +695,13 @@ hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, cons
     shape(n, n, 4, nz, nyb, blocks);
     DISPATCH_VEC(n, {
         if (x == nullptr)
-            hipExtLaunchKernelGGL((k_smooth_row<T, VEC, false, false>), dim3(blocks), dim3(kBlock), 0, s, ev0, ev1, 0, n, (T)ih2, x,
+            MG_LAUNCH((k_smooth_row<T, VEC, false, false>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (T)ih2, x,
                                xprev, b, out, (T)a, (T)cd, nz, nyb);
         else if (xprev == nullptr)
-            hipExtLaunchKernelGGL((k_smooth_row<T, VEC, true, false>), dim3(blocks), dim3(kBlock), 0, s, ev0, ev1, 0, n, (T)ih2, x,
+            MG_LAUNCH((k_smooth_row<T, VEC, true, false>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (T)ih2, x,
                                xprev, b, out, (T)a, (T)cd, nz, nyb);
         else
-            hipExtLaunchKernelGGL((k_smooth_row<T, VEC, true, true>), dim3(blocks), dim3(kBlock), 0, s, ev0, ev1, 0, n, (T)ih2, x,
+            MG_LAUNCH((k_smooth_row<T, VEC, true, true>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (T)ih2, x,
                                xprev, b, out, (T)a, (T)cd, nz, nyb);
     })
     return hipGetLastError();

@@ -10,7 +10,7 @@
 #include "flat_row.h"
 #include "var_row.h"
 
-#include <hip/hip_ext.h>
+#include "launch.h"
 
 #include <cmath>
 #include <cstdint>
@@ -789,13 +789,13 @@ hipError_t launch_smooth_step(const OpDesc<TC>& op, const T* x, const T* xprev, 
         return launch_var_smooth_row<T, TC>(op.n, op.ih2, op.coeff, x, xprev, b, out, a, c, s, ev0, ev1);
     Shape sh = stencil_shape(op.n);
     if (x == nullptr)
-        hipExtLaunchKernelGGL((k_smooth<T, TC, false, false>), sh.grid, sh.block, 0, s, ev0, ev1, 0, op.n, (T)op.ih2, op.coeff, x,
+        MG_LAUNCH((k_smooth<T, TC, false, false>), sh.grid, sh.block, s, ev0, ev1, op.n, (T)op.ih2, op.coeff, x,
                            xprev, b, out, (T)a, (T)c, sh.nz);
     else if (xprev == nullptr)
-        hipExtLaunchKernelGGL((k_smooth<T, TC, true, false>), sh.grid, sh.block, 0, s, ev0, ev1, 0, op.n, (T)op.ih2, op.coeff, x,
+        MG_LAUNCH((k_smooth<T, TC, true, false>), sh.grid, sh.block, s, ev0, ev1, op.n, (T)op.ih2, op.coeff, x,
                            xprev, b, out, (T)a, (T)c, sh.nz);
     else
-        hipExtLaunchKernelGGL((k_smooth<T, TC, true, true>), sh.grid, sh.block, 0, s, ev0, ev1, 0, op.n, (T)op.ih2, op.coeff, x,
+        MG_LAUNCH((k_smooth<T, TC, true, true>), sh.grid, sh.block, s, ev0, ev1, op.n, (T)op.ih2, op.coeff, x,
                            xprev, b, out, (T)a, (T)c, sh.nz);
     return hipGetLastError();
 }

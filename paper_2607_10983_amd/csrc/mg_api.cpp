@@ -6,6 +6,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -61,6 +62,16 @@ struct mg_ctx {
     double* G = nullptr;        // coarsest variable-coefficient pseudo-inverse
     int tail_start = -1;        // first level run by the single-workgroup tail kernel, -1 = none
     bool x1_ready = false;      // the outer residual already wrote level 0's first smoothing step
+    // The coarse sub-cycle (levels 1 .. coarsest) touches only context-owned
+    // buffers with fixed arguments, so it can be captured once into a HIP graph
+    // and replayed with one launch per V-cycle (MG_GRAPH set at creation).
+    bool use_graph = false;
+    bool capturing = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t coarse_graph = nullptr;
+    hipGraphExec_t coarse_exec = nullptr;
+    int coarse_cur = 0;
+    hipEvent_t norm_ev = nullptr;  // completion of the per-cycle norm readback
     double* scratch = nullptr;  // double scratch for the single-step entry points
     size_t scratch_elems = 0;
     std::string err;
@@ -368,10 +379,46 @@ mg_status tail_cycle(mg_ctx* c, int l0) {
     return MG_OK;
 }
 
+template <typename T>
+mg_status vcycle_from_zero(mg_ctx* c, int l);
+
+// Capture V(0, b_1) on level 1 and below into c->coarse_exec.
+template <typename T>
+mg_status capture_coarse(mg_ctx* c) {
+    if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipStream_t saved = c->stream;
+    c->stream = c->cap_stream;
+    c->capturing = true;
+    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    mg_status st = vcycle_from_zero<T>(c, 1);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    c->capturing = false;
+    c->stream = saved;
+    if (st != MG_OK) {
+        if (e == hipSuccess && g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    HIPCHK(c, e);
+    c->coarse_graph = g;
+    HIPCHK(c, hipGraphInstantiate(&c->coarse_exec, g, nullptr, nullptr, 0));
+    c->coarse_cur = c->lev[1].cur;
+    return MG_OK;
+}
+
 // x_l = V(0, b_l)
 template <typename T>
 mg_status vcycle_from_zero(mg_ctx* c, int l) {
     const int last = (int)c->lev.size() - 1;
+    if (l == 1 && last >= 2 && c->use_graph && !c->capturing) {
+        if (!c->coarse_exec) {
+            mg_status st = capture_coarse<T>(c);
+            if (st != MG_OK) return st;
+        }
+        HIPCHK(c, hipGraphLaunch(c->coarse_exec, c->stream));
+        c->lev[1].cur = c->coarse_cur;
+        return MG_OK;
+    }
     if (l == c->tail_start) return tail_cycle<T>(c, l);
     if (l == last) return coarse_level<T>(c, l);
     Level& L = c->lev[l];
@@ -518,6 +565,10 @@ mg_status mg_destroy(mg_ctx* c) {
         (void)hipEventDestroy(e.start);
         (void)hipEventDestroy(e.stop);
     }
+    if (c->coarse_exec) (void)hipGraphExecDestroy(c->coarse_exec);
+    if (c->coarse_graph) (void)hipGraphDestroy(c->coarse_graph);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->norm_ev) (void)hipEventDestroy(c->norm_ev);
     delete c;
     return MG_OK;
 }
@@ -545,6 +596,9 @@ static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype) {
     mg_status st;
     if ((st = dalloc(c, (void**)&c->phi_tmp, N0 * sizeof(double))) != MG_OK) return st;
     if (const char* t = std::getenv("MG_ROW_TARGET_BLOCKS")) set_row_target_blocks(std::atoi(t));
+    // replaying the coarse sub-cycle from a HIP graph measured slower than eager
+    // launches on this platform; it stays available for callers that want it
+    c->use_graph = std::getenv("MG_GRAPH") != nullptr;
     c->nparts = stencil_blocks(p.n);
     c->nparts_outer = outer_blocks(p.n, !c->var, p.precision != MG_FP32);
     {
@@ -553,6 +607,7 @@ static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype) {
     }
     if ((st = dalloc(c, (void**)&c->dscal, 16 * sizeof(double))) != MG_OK) return st;
     HIPCHK(c, hipHostMalloc((void**)&c->hscal, 16 * sizeof(double), hipHostMallocDefault));
+    HIPCHK(c, hipEventCreateWithFlags(&c->norm_ev, hipEventDisableTiming));
 
     if (c->var) {
         // fine coefficients in double, validated, restricted level by level
@@ -689,6 +744,18 @@ static mg_status device_sum(mg_ctx* c, const double* u, double shift, int pw, in
     return MG_OK;
 }
 
+// Readback of device scalars through an event, so the host can enqueue more
+// work before it waits for the values.
+static mg_status post_scalars(mg_ctx* c, int count) {
+    HIPCHK(c, hipMemcpyAsync(c->hscal, c->dscal, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipEventRecord(c->norm_ev, c->stream));
+    return MG_OK;
+}
+static mg_status wait_scalars(mg_ctx* c) {
+    HIPCHK(c, hipEventSynchronize(c->norm_ev));
+    return MG_OK;
+}
+
 static mg_status solve_impl(mg_ctx* c, double* phi, const double* b, double tol, int max_cycles,
                             mg_solve_info* info) {
     const size_t N0 = c->lev[0].N;
@@ -701,7 +768,14 @@ static mg_status solve_impl(mg_ctx* c, double* phi, const double* b, double tol,
     if ((st = device_sum(c, b, bmean, 2, 1)) != MG_OK) return st;
     if ((st = outer_residual(c, phi, nullptr, nullptr, b, bmean, true)) != MG_OK) return st;
     HIPCHK(c, launch_finalize_sum(c->partials, c->nparts_outer, c->dscal, 2, c->stream));
-    if ((st = read_scalars(c, 3)) != MG_OK) return st;
+    if ((st = post_scalars(c, 3)) != MG_OK) return st;
+    // Look-ahead: the next V-cycle depends only on device data (the residual
+    // just formed), so it is enqueued before the host waits for the norm; it
+    // is skipped when the measured contraction predicts convergence.  A
+    // look-ahead cycle that turns out unneeded only wrote hierarchy buffers.
+    bool ahead = max_cycles > 0;
+    if (ahead && (st = inner_vcycle(c)) != MG_OK) return st;
+    if ((st = wait_scalars(c)) != MG_OK) return st;
     const double nb = std::sqrt(c->hscal[1]);
     if (info) {
         info->cycles = 0;
@@ -710,11 +784,16 @@ static mg_status solve_impl(mg_ctx* c, double* phi, const double* b, double tol,
     if (nb == 0.0) {
         HIPCHK(c, launch_fill<double>(N0, 0.0, phi, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->x1_ready = false;
         if (info && info->history && info->history_cap > 0) info->history[0] = 0.0;
         return MG_OK;
     }
     double rel = std::sqrt(c->hscal[2]) / nb;
-    if (!std::isfinite(rel)) return fail(c, MG_ERR_NONFINITE, "initial residual is not finite (NaN/Inf in phi?)");
+    if (!std::isfinite(rel)) {
+        (void)hipStreamSynchronize(c->stream);
+        c->x1_ready = false;
+        return fail(c, MG_ERR_NONFINITE, "initial residual is not finite (NaN/Inf in phi?)");
+    }
     if (info) {
         info->rel_res0 = rel;
         if (info->history && info->history_cap > 0) info->history[0] = rel;
@@ -723,17 +802,22 @@ static mg_status solve_impl(mg_ctx* c, double* phi, const double* b, double tol,
     double* other = c->phi_tmp;
     int cycles = 0;
     double prev1 = INFINITY, prev2 = INFINITY;
+    double rho = 0.3;  // running estimate of the per-cycle residual reduction
     mg_status result = MG_OK;
     while (rel > tol && cycles < max_cycles) {
-        if ((st = inner_vcycle(c)) != MG_OK) return st;
+        if (!ahead && (st = inner_vcycle(c)) != MG_OK) return st;
         if ((st = outer_residual(c, cur, inner_e(c), other, b, bmean, true)) != MG_OK) return st;
         HIPCHK(c, launch_finalize_sum(c->partials, c->nparts_outer, c->dscal, 2, c->stream));
         std::swap(cur, other);
-        if ((st = read_scalars(c, 3)) != MG_OK) return st;
+        if ((st = post_scalars(c, 3)) != MG_OK) return st;
+        ahead = cycles + 1 < max_cycles && rho * rel > tol;
+        if (ahead && (st = inner_vcycle(c)) != MG_OK) return st;
+        if ((st = wait_scalars(c)) != MG_OK) return st;
         prev2 = prev1;
         prev1 = rel;
         rel = std::sqrt(c->hscal[2]) / nb;
         ++cycles;
+        if (prev1 > 0.0 && std::isfinite(rel)) rho = std::min(1.0, std::max(1e-3, rel / prev1));
         if (info && info->history && cycles < info->history_cap) info->history[cycles] = rel;
         if (!std::isfinite(rel)) {
             result = fail(c, MG_ERR_NONFINITE, "residual became non-finite");

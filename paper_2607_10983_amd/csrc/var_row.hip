@@ -13,7 +13,7 @@
 // D = -sum_a (f_a+ + f_a-) / h^2 its diagonal.
 #include "var_row.h"
 
-#include <hip/hip_ext.h>
+#include "launch.h"
 
 namespace mg {
 namespace {
@@ -456,14 +456,11 @@ hipError_t launch_var_smooth_row(int n, double ih2, const TC* C, const T* x, con
     shape(n, nz, nyb, blocks);
     DISPATCH_VEC(n, {
         if (x == nullptr)
-            hipExtLaunchKernelGGL((k_var_smooth_row<T, TC, VEC, false, false>), dim3(blocks), dim3(kBlock), 0, s, ev0,
-                                  ev1, 0, n, (T)ih2, C, x, xprev, b, out, (T)a, (T)c, nz, nyb);
+            MG_LAUNCH((k_var_smooth_row<T, TC, VEC, false, false>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (T)ih2, C, x, xprev, b, out, (T)a, (T)c, nz, nyb);
         else if (xprev == nullptr)
-            hipExtLaunchKernelGGL((k_var_smooth_row<T, TC, VEC, true, false>), dim3(blocks), dim3(kBlock), 0, s, ev0,
-                                  ev1, 0, n, (T)ih2, C, x, xprev, b, out, (T)a, (T)c, nz, nyb);
+            MG_LAUNCH((k_var_smooth_row<T, TC, VEC, true, false>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (T)ih2, C, x, xprev, b, out, (T)a, (T)c, nz, nyb);
         else
-            hipExtLaunchKernelGGL((k_var_smooth_row<T, TC, VEC, true, true>), dim3(blocks), dim3(kBlock), 0, s, ev0,
-                                  ev1, 0, n, (T)ih2, C, x, xprev, b, out, (T)a, (T)c, nz, nyb);
+            MG_LAUNCH((k_var_smooth_row<T, TC, VEC, true, true>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (T)ih2, C, x, xprev, b, out, (T)a, (T)c, nz, nyb);
     })
     return hipGetLastError();
 }
