@@ -289,15 +289,24 @@ class Hierarchy:
 def build_hierarchy(n: int, levels: int, degree: int = 3, h: Optional[float] = None,
                     C: Optional[np.ndarray] = None, alpha: float = 8.0,
                     smoother: str = "chebyshev", omega: float = 2.0 / 3.0,
-                    sweeps: int = 2) -> Hierarchy:
+                    sweeps: int = 2, psi: Optional[np.ndarray] = None) -> Hierarchy:
     """Levels ``0..levels-1``; the coefficients of level ``l+1`` are the
-    full-weighting restriction of those of level ``l`` (componentwise)."""
+    full-weighting restriction of those of level ``l`` (componentwise).
+
+    With ``psi`` (and no ``C``) every level is instead rediscretised from the
+    deformation potential restricted to it (Sec. 4.3; App. B):
+    ``psi_0 = psi``, ``psi_{l+1} = R psi_l`` and ``C_l = geometry(psi_l, h_l)``."""
     if h is None:
         h = 1.0 / n
     if n >> (levels - 1) < 2:
         raise ValueError("too many levels")
+    if psi is not None and C is not None:
+        raise ValueError("give C or psi, not both")
     out = []
+    psil = None if psi is None else np.asarray(psi, dtype=np.float64)
     Cl = None if C is None else np.asarray(C, dtype=np.float64)
+    if psil is not None:
+        Cl = geometry(psil, h)[0]
     for l in range(levels):
         nl = n >> l
         hl = h * (1 << l)
@@ -311,7 +320,10 @@ def build_hierarchy(n: int, levels: int, degree: int = 3, h: Optional[float] = N
         if l == levels - 1 and Cl is not None:
             lev.coarse_pinv = pinv_symmetric(dense_from_apply(lev.apply, nl))
         out.append(lev)
-        if Cl is not None and l + 1 < levels:
+        if l + 1 < levels and psil is not None:
+            psil = restrict_fw(psil)
+            Cl = geometry(psil, hl * 2.0)[0]
+        elif Cl is not None and l + 1 < levels:
             Cl = np.stack([restrict_fw(Cl[c]) for c in range(6)])
     return Hierarchy(out, degree, alpha, smoother, omega, sweeps)
 
@@ -372,6 +384,111 @@ def solve(H: Hierarchy, b: np.ndarray, phi0: Optional[np.ndarray] = None,
         hist.append(np.linalg.norm(b - lev.apply(phi)) / nb)
     phi = phi - phi.mean()
     return SolveResult(phi, cycles, hist)
+
+
+def solve_pcg(H: Hierarchy, b: np.ndarray, phi0: Optional[np.ndarray] = None,
+              tol: float = 1e-10, max_iter: int = 50) -> SolveResult:
+    """Multigrid-preconditioned conjugate gradients (Sec. 3.2): one V-cycle from
+    zero is the preconditioner ``B`` and ``phi0`` the first iterate.
+
+    Textbook preconditioned CG (Saad, Iterative Methods for Sparse Linear
+    Systems, Alg. 9.1) written directly in ``M`` and ``B``.  Both are negative
+    semidefinite on the same space, so every step size is that of CG on
+    ``-M`` preconditioned by ``-B``.  ``history`` holds the relative norm of the
+    recursively updated residual.  When the recursive residual meets ``tol`` the true
+    residual ``b - M phi`` is formed; if it misses ``tol`` the iteration
+    restarts from it.  ``cycles`` counts CG iterations; each applies the
+    preconditioner once."""
+    lev = H.levels[0]
+    b = b - b.mean()
+    nb = np.linalg.norm(b)
+    phi = np.zeros_like(b) if phi0 is None else np.array(phi0, dtype=np.float64)
+    if nb == 0.0:
+        return SolveResult(np.zeros_like(b), 0, [0.0])
+    precond = lambda r: vcycle(H, 0, np.zeros_like(r), r)
+    r = b - lev.apply(phi)
+    hist = [np.linalg.norm(r) / nb]
+    its = 0
+    while hist[-1] > tol and its < max_iter:
+        z = precond(r)
+        p = z
+        rz = np.vdot(r, z)
+        while its < max_iter:
+            q = lev.apply(p)
+            alpha = rz / np.vdot(p, q)
+            phi = phi + alpha * p
+            r = r - alpha * q
+            its += 1
+            hist.append(np.linalg.norm(r) / nb)
+            if hist[-1] <= tol:
+                break
+            z = precond(r)
+            rz_new = np.vdot(r, z)
+            p = z + (rz_new / rz) * p
+            rz = rz_new
+        r = b - lev.apply(phi)          # restart from the true residual
+        if np.linalg.norm(r) / nb > tol and its < max_iter:
+            hist[-1] = np.linalg.norm(r) / nb
+    phi = phi - phi.mean()
+    return SolveResult(phi, its, hist)
+
+
+def true_rel_residual(H: Hierarchy, b: np.ndarray, phi: np.ndarray) -> float:
+    b = b - b.mean()
+    return float(np.linalg.norm(b - H.levels[0].apply(phi)) / np.linalg.norm(b))
+
+
+# ---------------------------------------------------------------------------
+# Initial guesses (Sec. 3.2: recycling, eq. growth, polynomial extrapolation)
+# ---------------------------------------------------------------------------
+
+def predict(history: List[np.ndarray], kind: str, growth: float = 1.0) -> np.ndarray:
+    """Initial guess for step ``n`` from earlier solutions, newest first
+    (``history[0] = phi_{n-1}``, ``history[1] = phi_{n-2}``, ...):
+
+    * ``recycle``: ``phi_{n-1}``;
+    * ``growth``: ``(D_n / D_{n-1}) phi_{n-1}`` with ``growth = D_n / D_{n-1}``;
+    * ``linear``: ``2 phi_{n-1} - phi_{n-2}``;
+    * ``quadratic``: ``3 phi_{n-1} - 3 phi_{n-2} + phi_{n-3}``."""
+    if kind == "recycle":
+        return np.array(history[0], dtype=np.float64)
+    if kind == "growth":
+        return growth * history[0]
+    if kind == "linear":
+        return 2.0 * history[0] - history[1]
+    if kind == "quadratic":
+        return 3.0 * history[0] - 3.0 * history[1] + history[2]
+    raise ValueError(kind)
+
+
+# ---------------------------------------------------------------------------
+# Force readout (Sec. 3.4: fourth-order gradient; Sec. 4.5.1, eq. accel)
+# ---------------------------------------------------------------------------
+
+def gradient4(phi: np.ndarray, h: float) -> np.ndarray:
+    """Fourth-order central first differences along each direction,
+    ``(u_{i-2} - 8 u_{i-1} + 8 u_{i+1} - u_{i+2}) / (12 h)``; ``(3, n, n, n)``
+    in direction order (x, y, z)."""
+    out = np.empty((3,) + phi.shape)
+    for a in range(3):
+        out[a] = (_sh(phi, a, -2) - 8.0 * _sh(phi, a, -1)
+                  + 8.0 * _sh(phi, a, 1) - _sh(phi, a, 2)) / (12.0 * h)
+    return out
+
+
+def accel(phi: np.ndarray, h: float, psi: Optional[np.ndarray] = None,
+          scale: float = 1.0) -> np.ndarray:
+    """``a = -scale J^-1 grad phi`` (eq. accel; ``scale`` is the paper's
+    ``3/2 Omega_m``), ``grad`` the fourth-order difference and ``J = I + Hess psi``
+    (eq. triad).  Without ``psi`` the mesh is uniform (``J = I``) and ``a`` is
+    the plain force ``-scale grad phi``."""
+    g = gradient4(phi, h)
+    if psi is None:
+        return -scale * g
+    J = triad(psi, h)
+    gv = np.moveaxis(g, 0, -1)[..., None]            # (n, n, n, 3, 1)
+    a = np.linalg.solve(J, gv)[..., 0]
+    return -scale * np.moveaxis(a, -1, 0)
 
 
 # ---------------------------------------------------------------------------
