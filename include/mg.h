@@ -118,6 +118,19 @@ mg_status mg_validate_params(const mg_params* p);
 mg_status mg_create(const mg_params* p, const void* coeff, int coeff_dtype,
                     void* stream, mg_ctx** out);
 
+/* Variable-coefficient context rediscretised on every level from the
+ * deformation potential (Sec. 4.3; App. B restricts the deformation field to
+ * each coarse level): psi (device double n^3, read during the call only) is
+ * restricted by full weighting level by level, psi_{l+1} = R psi_l, and the
+ * coefficients of level l are C(psi_l) of mg_geometry at spacing 2^l h.
+ * The fine level's coefficients are exactly mg_geometry(psi); in MG_MIXED the
+ * outer residual uses them in double and the hierarchy in float.  Same
+ * parameter rules as mg_create (coarsest level at most 8^3 points).
+ * Errors as mg_create; MG_ERR_INVALID_COEFF also when the restricted
+ * potential folds a coarse level's mesh (a diagonal coefficient <= 0 or not
+ * finite there). */
+mg_status mg_create_psi(const mg_params* p, const double* psi, void* stream, mg_ctx** out);
+
 /* Free everything the context owns.  NULL is accepted. */
 mg_status mg_destroy(mg_ctx* ctx);
 
@@ -143,6 +156,24 @@ mg_status mg_vcycle(mg_ctx* ctx, double* phi, const double* b, double* rel_res_o
  * stream once per cycle (one 8-byte norm read back). */
 mg_status mg_solve(mg_ctx* ctx, double* phi, const double* b, double tol,
                    int max_cycles, mg_solve_info* info);
+
+/* Multigrid-preconditioned conjugate gradients (Sec. 3.2: the recycled
+ * potential seeds a CG iteration preconditioned by multigrid): one V-cycle
+ * from zero is the preconditioner B, phi the first iterate.  Flexible
+ * (Polak-Ribiere) step beta = (z_k, r_k - r_{k-1}) / (z_{k-1}, r_{k-1}),
+ * identical to textbook PCG for a fixed symmetric B and robust to the float
+ * rounding of an MG_MIXED or MG_FP32 preconditioner.  The recurrences (r, p,
+ * q = M p, phi) run in double in every precision mode.  Stops when the
+ * recursively updated residual meets tol and the true residual confirms it;
+ * if the true residual misses tol the iteration restarts from it, and stops
+ * at the rounding floor when a restart brings no 0.1% improvement.
+ * info->cycles counts CG iterations (one V-cycle each), history holds the
+ * recursive residuals (the true one where a restart happened) and rel_res
+ * the true final residual.  b's mean is projected out first and phi's mean
+ * removed at the end, as in mg_solve.  Allocates four n^3 double work fields
+ * in the context on first use.  Same errors as mg_solve. */
+mg_status mg_solve_pcg(mg_ctx* ctx, double* phi, const double* b, double tol,
+                       int max_iter, mg_solve_info* info);
 
 /* Adjoint solve lam = M^+ phibar (Sec. 4.6, eq. adj_rhs): M is symmetric, so
  * this is the forward machinery on the cotangent; lam holds the initial
@@ -176,6 +207,35 @@ mg_status mg_geometry(int n, double h, const double* psi, void* C_out, int dtype
  * doubles. */
 mg_status mg_geometry_bwd(int n, double h, const double* psi, const double* Cbar,
                           const double* sqrtgbar, double* psibar, void* stream);
+
+/* ---- initial guesses and force readout ----------------------------------- */
+
+enum mg_predictor {
+    MG_PREDICT_RECYCLE = 0,   /* out = phi1 */
+    MG_PREDICT_GROWTH = 1,    /* out = growth * phi1, growth = D(a_n) / D(a_{n-1}) (eq. growth) */
+    MG_PREDICT_LINEAR = 2,    /* out = 2 phi1 - phi2 */
+    MG_PREDICT_QUADRATIC = 3  /* out = 3 phi1 - 3 phi2 + phi3 */
+};
+
+/* Initial guess for the next solve from earlier solutions (Sec. 3.2:
+ * recycling, growth-scaled and polynomial-extrapolation predictors); phi1 is
+ * the newest (phi_{n-1}), phi2 = phi_{n-2}, phi3 = phi_{n-3}.  Device double
+ * n^3 fields; pointers the kind does not use may be NULL.  out may alias any
+ * input (elementwise).  Stream-ordered, no synchronisation.
+ * MG_ERR_INVALID for a bad n, kind, missing field or non-finite growth. */
+mg_status mg_predict(int n, int kind, const double* phi1, const double* phi2,
+                     const double* phi3, double growth, double* out, void* stream);
+
+/* Force readout after a solve (Sec. 3.4: fourth-order finite-difference
+ * gradient; Sec. 4.5.1, eq. accel): a = -scale J^-1 grad phi with
+ * grad_a phi = (phi_{i-2} - 8 phi_{i-1} + 8 phi_{i+1} - phi_{i+2}) / (12 h)
+ * along each axis and J = I + Hess psi (second-order stencils of
+ * mg_geometry).  psi == NULL: uniform mesh, a = -scale grad phi.  scale is
+ * the caller's normalisation (the paper's 3/2 Omega_m; 1 gives -grad phi).
+ * phi, psi: device double n^3; a_out: device, 3 n^3 values (x, y, z
+ * components, each an n^3 field) of dtype.  Stream-ordered. */
+mg_status mg_accel(int n, double h, const double* phi, const double* psi,
+                   double scale, void* a_out, int dtype, void* stream);
 
 /* ---- single steps of the V-cycle, for testing and composition ------------
  * These act on caller double fields at level `level` of the context's

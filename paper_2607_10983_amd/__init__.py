@@ -19,10 +19,13 @@ from typing import List, Optional, Tuple
 from . import _lib
 from ._lib import MGError
 
-__all__ = ["Multigrid", "SolveInfo", "geometry", "geometry_bwd", "solve", "MGError"]
+__all__ = ["Multigrid", "SolveInfo", "geometry", "geometry_bwd", "geometry_fn", "solve", "solve_fn",
+           "predict", "accel", "MGError"]
 
 _PRECISION = {"fp64": _lib.MG_FP64, "mixed": _lib.MG_MIXED, "fp32": _lib.MG_FP32}
 _SMOOTHER = {"chebyshev": _lib.MG_CHEBYSHEV, "jacobi": _lib.MG_JACOBI}
+_PREDICTOR = {"recycle": _lib.MG_PREDICT_RECYCLE, "growth": _lib.MG_PREDICT_GROWTH,
+              "linear": _lib.MG_PREDICT_LINEAR, "quadratic": _lib.MG_PREDICT_QUADRATIC}
 
 
 def _torch():
@@ -73,13 +76,16 @@ class Multigrid:
 
     ``coeff`` (optional) is a ``(6, n, n, n)`` float32/float64 GPU tensor of the
     symmetric coefficient ``C`` in order (xx, yy, zz, xy, xz, yz); it is copied.
+    ``psi`` (optional, instead of ``coeff``) is an ``(n, n, n)`` float64 GPU
+    deformation potential: every level is then rediscretised from the
+    potential restricted to it (``mg_create_psi``).
     ``precision``: "fp64", "mixed" (float V-cycle, double residual/update/coarsest
     solve) or "fp32".  ``levels`` defaults to ``log2(n) - 1`` (coarsest 4^3).
     """
 
     def __init__(self, n: int, levels: Optional[int] = None, degree: int = 3, coeff=None,
                  precision: str = "mixed", h: Optional[float] = None, alpha: float = 8.0,
-                 smoother: str = "chebyshev", omega: float = 2.0 / 3.0, sweeps: int = 2):
+                 smoother: str = "chebyshev", omega: float = 2.0 / 3.0, sweeps: int = 2, psi=None):
         torch = _torch()
         lib = _lib.load()
         p = _lib.MgParams()
@@ -99,7 +105,9 @@ class Multigrid:
         self.precision = precision
         self.levels = p.levels
         self.h = p.h
-        self.var = coeff is not None
+        self.var = coeff is not None or psi is not None
+        if coeff is not None and psi is not None:
+            raise ValueError("give coeff or psi, not both")
         cptr, cdt = None, _lib.MG_DTYPE_F64
         if coeff is not None:
             if coeff.dtype not in (torch.float32, torch.float64):
@@ -108,9 +116,15 @@ class Multigrid:
             cptr = _ptr(coeff)
             cdt = _lib.MG_DTYPE_F64 if coeff.dtype == torch.float64 else _lib.MG_DTYPE_F32
         h_ctx = ctypes.c_void_p()
-        st = lib.mg_create(ctypes.byref(p), cptr, cdt, _stream_ptr(), ctypes.byref(h_ctx))
-        if st != _lib.MG_OK:
-            raise MGError(st, "mg_create")
+        if psi is not None:
+            _check_field(psi, self.n, torch.float64, "psi")
+            st = lib.mg_create_psi(ctypes.byref(p), _ptr(psi), _stream_ptr(), ctypes.byref(h_ctx))
+            if st != _lib.MG_OK:
+                raise MGError(st, "mg_create_psi")
+        else:
+            st = lib.mg_create(ctypes.byref(p), cptr, cdt, _stream_ptr(), ctypes.byref(h_ctx))
+            if st != _lib.MG_OK:
+                raise MGError(st, "mg_create")
         self._ctx = h_ctx
 
     # ---------------------------------------------------------------- lifecycle
@@ -145,6 +159,19 @@ class Multigrid:
             out.copy_(phi0)
         _check_field(out, self.n, torch.float64, "phi")
         return out, self._run("mg_solve", out, b, tol, max_cycles, history, raise_on_error)
+
+    def solve_pcg(self, b, phi0=None, tol: float = 1e-10, max_iter: int = 50, history: bool = True,
+                  raise_on_error: bool = True, out=None) -> Tuple[object, SolveInfo]:
+        """Multigrid-preconditioned CG from ``phi0`` (``mg_solve_pcg``);
+        ``info.cycles`` counts CG iterations."""
+        torch = _torch()
+        _check_field(b, self.n, torch.float64, "b")
+        if out is None:
+            out = torch.zeros_like(b) if phi0 is None else phi0.clone()
+        elif phi0 is not None and phi0.data_ptr() != out.data_ptr():
+            out.copy_(phi0)
+        _check_field(out, self.n, torch.float64, "phi")
+        return out, self._run("mg_solve_pcg", out, b, tol, max_iter, history, raise_on_error)
 
     def solve_adjoint(self, phibar, lam0=None, tol: float = 1e-10, max_cycles: int = 50,
                       history: bool = True, raise_on_error: bool = True):
@@ -275,6 +302,45 @@ class Multigrid:
         return k.value, ms.value, by.value
 
 
+# ---------------------------------------------------------------------- predictors, forces
+def predict(kind: str, history, growth: float = 1.0, out=None):
+    """Initial guess from earlier solutions, newest first (``mg_predict``):
+    "recycle", "growth" (``growth * phi1``), "linear" or "quadratic"."""
+    torch = _torch()
+    need = {"recycle": 1, "growth": 1, "linear": 2, "quadratic": 3}[kind]
+    if len(history) < need:
+        raise ValueError(f"{kind} needs {need} earlier solutions")
+    n = history[0].shape[0]
+    for k, t in enumerate(history[:need]):
+        _check_field(t, n, torch.float64, f"history[{k}]")
+    out = torch.empty_like(history[0]) if out is None else out
+    _check_field(out, n, torch.float64, "out")
+    ptrs = [_ptr(history[k]) if k < need else None for k in range(3)]
+    st = _lib.load().mg_predict(n, _PREDICTOR[kind], ptrs[0], ptrs[1], ptrs[2], float(growth), _ptr(out),
+                                _stream_ptr())
+    if st != _lib.MG_OK:
+        raise MGError(st, "mg_predict")
+    return out
+
+
+def accel(phi, psi=None, scale: float = 1.0, h: Optional[float] = None, dtype=None):
+    """``a = -scale J^-1 grad phi`` as a ``(3, n, n, n)`` tensor (``mg_accel``)."""
+    torch = _torch()
+    n = phi.shape[0]
+    _check_field(phi, n, torch.float64, "phi")
+    if psi is not None:
+        _check_field(psi, n, torch.float64, "psi")
+    dtype = torch.float64 if dtype is None else dtype
+    h = 1.0 / n if h is None else h
+    a = torch.empty((3, n, n, n), dtype=dtype, device=phi.device)
+    dt = _lib.MG_DTYPE_F64 if dtype == torch.float64 else _lib.MG_DTYPE_F32
+    st = _lib.load().mg_accel(n, float(h), _ptr(phi), _ptr(psi) if psi is not None else None, float(scale),
+                              _ptr(a), dt, _stream_ptr())
+    if st != _lib.MG_OK:
+        raise MGError(st, "mg_accel")
+    return a
+
+
 # ---------------------------------------------------------------------- geometry
 def geometry(psi, h: Optional[float] = None, dtype=None):
     """``(C, sqrt_g)`` of the deformation potential ``psi`` (Sec. 4.2)."""
@@ -379,3 +445,6 @@ def solve(b, C=None, tol: float = 1e-10, max_cycles: int = 100, **ctx_opts):
     """Differentiable solve ``phi = M(C)^+ (b - mean b)`` with respect to ``b`` and ``C``."""
     opts = {"ctx": ctx_opts, "tol": tol, "max_cycles": max_cycles}
     return _fns()[1].apply(b, C, opts)
+
+
+solve_fn = solve

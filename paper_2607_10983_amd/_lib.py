@@ -18,6 +18,7 @@ MG_ERR_NOT_CONVERGED = 6
 MG_FP64, MG_MIXED, MG_FP32 = 0, 1, 2
 MG_CHEBYSHEV, MG_JACOBI = 0, 1
 MG_DTYPE_F32, MG_DTYPE_F64 = 0, 1
+MG_PREDICT_RECYCLE, MG_PREDICT_GROWTH, MG_PREDICT_LINEAR, MG_PREDICT_QUADRATIC = 0, 1, 2, 3
 
 
 class MgParams(ctypes.Structure):
@@ -55,14 +56,18 @@ SIGNATURES = {
     "mg_params_default": (_I, [ctypes.POINTER(MgParams), _I]),
     "mg_validate_params": (_I, [ctypes.POINTER(MgParams)]),
     "mg_create": (_I, [ctypes.POINTER(MgParams), _P, _I, _P, ctypes.POINTER(_P)]),
+    "mg_create_psi": (_I, [ctypes.POINTER(MgParams), _P, _P, ctypes.POINTER(_P)]),
     "mg_destroy": (_I, [_P]),
     "mg_set_stream": (_I, [_P, _P]),
     "mg_vcycle": (_I, [_P, _P, _P, _PD]),
     "mg_solve": (_I, [_P, _P, _P, _D, _I, ctypes.POINTER(MgSolveInfo)]),
     "mg_solve_adjoint": (_I, [_P, _P, _P, _D, _I, ctypes.POINTER(MgSolveInfo)]),
+    "mg_solve_pcg": (_I, [_P, _P, _P, _D, _I, ctypes.POINTER(MgSolveInfo)]),
     "mg_coeff_grad": (_I, [_P, _P, _P, _P, _I]),
     "mg_geometry": (_I, [_I, _D, _P, _P, _I, _P, _P]),
     "mg_geometry_bwd": (_I, [_I, _D, _P, _P, _P, _P, _P]),
+    "mg_predict": (_I, [_I, _I, _P, _P, _P, _D, _P, _P]),
+    "mg_accel": (_I, [_I, _D, _P, _P, _D, _P, _I, _P]),
     "mg_apply": (_I, [_P, _I, _P, _P]),
     "mg_smooth": (_I, [_P, _I, _P, _P]),
     "mg_residual_restrict": (_I, [_P, _I, _P, _P, _P]),

@@ -123,4 +123,45 @@ hipError_t launch_geometry_bwd_cell(int n, double ih2, const double* psi, const 
 hipError_t launch_hessian_adjoint(int n, double ih2, const double* Jbar, double* psibar,
                                   hipStream_t s);
 
+// ---- multigrid-preconditioned conjugate gradients (double recurrences) ----------
+// Scalars live in device memory so no pass waits for the host:
+enum PcgSlot { kPcgRz = 0, kPcgAlpha = 1, kPcgBeta = 2, kPcgRr = 3, kPcgPq = 4, kPcgSlots = 8 };
+// Per-block partial sums written by the passes below: `pcg_blocks(n)` per sum.
+int pcg_blocks(int n);
+// r = (b - bmean) - M phi (double), rin = r in the preconditioner's type TI;
+// partials[blk] = sum of r^2.
+template <typename TI, typename TC>
+hipError_t launch_pcg_residual(const OpDesc<TC>& op, const double* phi, const double* b, double bmean,
+                               double* r, TI* rin, double* partials, hipStream_t s);
+// partials[blk] = sum r z, partials[nb + blk] = sum z q (0 when q == nullptr).
+template <typename TI>
+hipError_t launch_pcg_dots(int n, const double* r, const TI* z, const double* q, double* partials,
+                           hipStream_t s);
+// p_new = z + beta p_old (p_old unread when restart), q = M p_new,
+// partials[blk] = sum p_new q.  beta = scal[kPcgBeta].
+template <typename TI, typename TC>
+hipError_t launch_pcg_direction(const OpDesc<TC>& op, const TI* z, const double* p_old, double* p_new,
+                                double* q, const double* scal, bool restart, double* partials,
+                                hipStream_t s);
+// phi += alpha p, r -= alpha q, rin = r; partials[blk] = sum r^2.  alpha = scal[kPcgAlpha].
+template <typename TI>
+hipError_t launch_pcg_update(int n, double* phi, const double* p, double* r, const double* q, TI* rin,
+                             const double* scal, double* partials, hipStream_t s);
+// Sums of the partials and the scalar recurrences, one block:
+//   kPcgBeta:  rz_new = sum r z; beta = restart ? 0 : -alpha (sum z q) / rz_old (flexible,
+//              Polak-Ribiere form); scal[kPcgRz] = rz_new
+//   kPcgAlpha: alpha = scal[kPcgRz] / sum p q
+//   kPcgRr:    scal[kPcgRr] = sum r^2
+hipError_t launch_pcg_scalars(const double* partials, int nb, double* scal, int which, bool restart,
+                              hipStream_t s);
+
+// ---- initial guesses and force readout ----------------------------------------------
+// out = c1 phi1 + c2 phi2 + c3 phi3 (terms with a zero coefficient are not read).
+hipError_t launch_combine3(size_t count, double c1, const double* phi1, double c2, const double* phi2,
+                           double c3, const double* phi3, double* out, hipStream_t s);
+// a = -scale J^-1 grad4 phi, J = I + Hess psi (psi == nullptr: J = I); a: 3 n^3 of TO.
+template <typename TO>
+hipError_t launch_accel(int n, double h, const double* phi, const double* psi, double scale, TO* a,
+                        hipStream_t s);
+
 }  // namespace mg

@@ -72,6 +72,12 @@ struct mg_ctx {
     hipGraphExec_t coarse_exec = nullptr;
     int coarse_cur = 0;
     hipEvent_t norm_ev = nullptr;  // completion of the per-cycle norm readback
+    // conjugate-gradient state (allocated by the first mg_solve_pcg)
+    double* pcg_r = nullptr;
+    double* pcg_p[2] = {nullptr, nullptr};
+    double* pcg_q = nullptr;
+    double* pcg_s = nullptr;
+    double* pcg_partials = nullptr;
     double* scratch = nullptr;  // double scratch for the single-step entry points
     size_t scratch_elems = 0;
     std::string err;
@@ -561,6 +567,12 @@ mg_status mg_destroy(mg_ctx* c) {
     dfree(c->lam1);
     dfree(c->G);
     dfree(c->scratch);
+    dfree(c->pcg_r);
+    dfree(c->pcg_p[0]);
+    dfree(c->pcg_p[1]);
+    dfree(c->pcg_q);
+    dfree(c->pcg_s);
+    dfree(c->pcg_partials);
     for (auto& e : c->events) {
         (void)hipEventDestroy(e.start);
         (void)hipEventDestroy(e.stop);
@@ -573,9 +585,9 @@ mg_status mg_destroy(mg_ctx* c) {
     return MG_OK;
 }
 
-static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype) {
+static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype, const double* psi = nullptr) {
     const mg_params& p = c->p;
-    c->var = coeff != nullptr;
+    c->var = coeff != nullptr || psi != nullptr;
     c->inner_double = p.precision == MG_FP64;
     if (c->var && coarsest_n(p) > 8)
         return fail(c, MG_ERR_INVALID, "variable-coefficient coarsest level must have at most 8^3 points");
@@ -620,22 +632,59 @@ static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype) {
                 free64();
                 return st;
             }
-        hipError_t e = coeff_dtype == MG_DTYPE_F64
-                           ? launch_convert<double, double>(6 * N0, (const double*)coeff, c64[0], c->stream)
-                           : launch_convert<double, float>(6 * N0, (const float*)coeff, c64[0], c->stream);
-        if (e != hipSuccess) { free64(); HIPCHK(c, e); }
-        e = launch_coeff_check<double>(p.n, c64[0], c->partials, c->stream);
-        if (e == hipSuccess) e = launch_finalize_sum(c->partials, c->nparts, c->dscal, 0, c->stream);
-        if (e != hipSuccess) { free64(); HIPCHK(c, e); }
-        if ((st = read_scalars(c, 1)) != MG_OK) { free64(); return st; }
-        if (c->hscal[0] != 0.0) {
-            free64();
-            return fail(c, MG_ERR_INVALID_COEFF,
-                        std::to_string((long long)c->hscal[0]) + " cells with non-finite or non-positive diagonal coefficients");
-        }
-        for (int l = 0; l + 1 < p.levels; ++l) {
-            e = launch_restrict<double>(c->lev[l].n, c64[l], c64[l + 1], 6, c->stream);
+        // count of invalid cells of level l into hscal[0]
+        auto check_level = [&](int l) -> hipError_t {
+            hipError_t e = launch_coeff_check<double>(c->lev[l].n, c64[l], c->partials, c->stream);
+            if (e == hipSuccess) e = launch_finalize_sum(c->partials, stencil_blocks(c->lev[l].n), c->dscal, 0, c->stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(c->hscal, c->dscal, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            return e;
+        };
+        hipError_t e = hipSuccess;
+        if (psi) {
+            // every level rediscretised from the potential restricted to it
+            std::vector<double*> pl(p.levels, nullptr);
+            auto freep = [&]() {
+                for (int l = 1; l < p.levels; ++l) dfree(pl[l]);
+            };
+            pl[0] = const_cast<double*>(psi);
+            for (int l = 1; l < p.levels; ++l)
+                if ((st = dalloc(c, (void**)&pl[l], c->lev[l].N * sizeof(double))) != MG_OK) {
+                    freep();
+                    free64();
+                    return st;
+                }
+            for (int l = 0; l < p.levels && e == hipSuccess; ++l) {
+                if (l > 0) e = launch_restrict<double>(c->lev[l - 1].n, pl[l - 1], pl[l], 1, c->stream);
+                if (e == hipSuccess) e = launch_geometry<double>(c->lev[l].n, c->lev[l].ih2, pl[l], c64[l], nullptr, c->stream);
+            }
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            freep();
             if (e != hipSuccess) { free64(); HIPCHK(c, e); }
+            for (int l = 0; l < p.levels; ++l) {
+                if ((e = check_level(l)) != hipSuccess) { free64(); HIPCHK(c, e); }
+                if (c->hscal[0] != 0.0) {
+                    free64();
+                    return fail(c, MG_ERR_INVALID_COEFF,
+                                std::to_string((long long)c->hscal[0]) + " cells of level " + std::to_string(l) +
+                                    " with a folded mesh (non-finite or non-positive diagonal coefficients)");
+                }
+            }
+        } else {
+            e = coeff_dtype == MG_DTYPE_F64
+                    ? launch_convert<double, double>(6 * N0, (const double*)coeff, c64[0], c->stream)
+                    : launch_convert<double, float>(6 * N0, (const float*)coeff, c64[0], c->stream);
+            if (e == hipSuccess) e = check_level(0);
+            if (e != hipSuccess) { free64(); HIPCHK(c, e); }
+            if (c->hscal[0] != 0.0) {
+                free64();
+                return fail(c, MG_ERR_INVALID_COEFF,
+                            std::to_string((long long)c->hscal[0]) + " cells with non-finite or non-positive diagonal coefficients");
+            }
+            for (int l = 0; l + 1 < p.levels; ++l) {
+                e = launch_restrict<double>(c->lev[l].n, c64[l], c64[l + 1], 6, c->stream);
+                if (e != hipSuccess) { free64(); HIPCHK(c, e); }
+            }
         }
         for (int l = 0; l + 1 < p.levels; ++l) {
             OpDesc<double> op{c->lev[l].n, c->lev[l].ih2, c64[l]};
@@ -677,8 +726,8 @@ static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype) {
                 e = launch_convert<float, double>(6 * c->lev[l].N, c64[l], (float*)c->lev[l].coeff, c->stream);
                 if (e != hipSuccess) { free64(); HIPCHK(c, e); }
             }
-            if (p.precision == MG_MIXED && coeff_dtype == MG_DTYPE_F64) {
-                c->coeff_outer = c64[0];  // keep the caller's double values for the outer residual
+            if (p.precision == MG_MIXED && (coeff_dtype == MG_DTYPE_F64 || psi)) {
+                c->coeff_outer = c64[0];  // keep the double values for the outer residual
                 c64[0] = nullptr;
                 c->coeff_outer_double = true;
                 c->coeff_outer_owned = true;
@@ -856,6 +905,219 @@ mg_status mg_solve_adjoint(mg_ctx* c, double* lam, const double* phibar, double 
     if (lam == phibar) return fail(c, MG_ERR_INVALID, "lam and phibar must not alias");
     // M = M^T: the adjoint system is the forward system with the cotangent as source.
     return solve_impl(c, lam, phibar, tol, max_cycles, info);
+}
+
+}  // extern "C"
+
+namespace {
+
+mg_status ensure_pcg(mg_ctx* c) {
+    if (c->pcg_r) return MG_OK;
+    const size_t bytes = c->lev[0].N * sizeof(double);
+    mg_status st;
+    if ((st = dalloc(c, (void**)&c->pcg_r, bytes)) != MG_OK) return st;
+    if ((st = dalloc(c, (void**)&c->pcg_p[0], bytes)) != MG_OK) return st;
+    if ((st = dalloc(c, (void**)&c->pcg_p[1], bytes)) != MG_OK) return st;
+    if ((st = dalloc(c, (void**)&c->pcg_q, bytes)) != MG_OK) return st;
+    if ((st = dalloc(c, (void**)&c->pcg_s, kPcgSlots * sizeof(double))) != MG_OK) return st;
+    return dalloc(c, (void**)&c->pcg_partials, 2 * (size_t)pcg_blocks(c->lev[0].n) * sizeof(double));
+}
+
+// Multigrid-preconditioned CG.  TI: type of the hierarchy (preconditioner
+// input r_in = level 0's right-hand side, output z = level 0's iterate);
+// TC: type of the fine coefficients used for q = M p.
+template <typename TI, typename TC>
+mg_status pcg_impl(mg_ctx* c, double* phi, const double* b, double tol, int max_iter, mg_solve_info* info) {
+    Level& L0 = c->lev[0];
+    const int n = L0.n;
+    const size_t N0 = L0.N;
+    const double invN = 1.0 / (double)N0;
+    const OpDesc<TC> op{n, L0.ih2, (const TC*)c->coeff_outer};
+    TI* rin = (TI*)L0.b;
+    double* r = c->pcg_r;
+    double* q = c->pcg_q;
+    double* S = c->pcg_s;
+    double* part = c->pcg_partials;
+    const int nb = pcg_blocks(n);
+    mg_status st;
+    c->x1_ready = false;
+    if ((st = device_sum(c, b, 0.0, 1, 0)) != MG_OK) return st;
+    if ((st = read_scalars(c, 1)) != MG_OK) return st;
+    const double bmean = c->hscal[0] * invN;
+    if (!std::isfinite(bmean)) return fail(c, MG_ERR_NONFINITE, "source contains NaN or Inf");
+    if ((st = device_sum(c, b, bmean, 2, 1)) != MG_OK) return st;
+    auto true_residual = [&]() -> mg_status {
+        HIPCHK(c, (launch_pcg_residual<TI, TC>(op, phi, b, bmean, r, rin, part, c->stream)));
+        HIPCHK(c, launch_finalize_sum(part, nb, c->dscal, 2, c->stream));
+        return MG_OK;
+    };
+    if ((st = true_residual()) != MG_OK) return st;
+    if ((st = post_scalars(c, 3)) != MG_OK) return st;
+    bool ahead = max_iter > 0;  // look-ahead preconditioner application, as in the defect-correction loop
+    if (ahead && (st = inner_vcycle(c)) != MG_OK) return st;
+    if ((st = wait_scalars(c)) != MG_OK) return st;
+    const double nbn = std::sqrt(c->hscal[1]);
+    if (info) {
+        info->cycles = 0;
+        info->rel_res0 = info->rel_res = 0.0;
+    }
+    if (nbn == 0.0) {
+        HIPCHK(c, launch_fill<double>(N0, 0.0, phi, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (info && info->history && info->history_cap > 0) info->history[0] = 0.0;
+        return MG_OK;
+    }
+    double rel = std::sqrt(c->hscal[2]) / nbn;
+    if (!std::isfinite(rel)) {
+        (void)hipStreamSynchronize(c->stream);
+        return fail(c, MG_ERR_NONFINITE, "initial residual is not finite (NaN/Inf in phi?)");
+    }
+    if (info) {
+        info->rel_res0 = rel;
+        if (info->history && info->history_cap > 0) info->history[0] = rel;
+    }
+    int its = 0, pc = 0;
+    bool restart = true;
+    double rho = 0.3, last_true = rel, true_rel = rel;
+    bool true_current = true;  // true_rel belongs to the current iterate
+    mg_status result = MG_OK;
+    while (rel > tol && its < max_iter) {
+        if (!ahead && (st = inner_vcycle(c)) != MG_OK) return st;
+        const TI* z = (const TI*)inner_e(c);
+        double* p_old = c->pcg_p[pc];
+        double* p_new = c->pcg_p[1 - pc];
+        HIPCHK(c, launch_pcg_dots<TI>(n, r, z, restart ? nullptr : q, part, c->stream));
+        HIPCHK(c, launch_pcg_scalars(part, nb, S, kPcgBeta, restart, c->stream));
+        HIPCHK(c, (launch_pcg_direction<TI, TC>(op, z, p_old, p_new, q, S, restart, part, c->stream)));
+        HIPCHK(c, launch_pcg_scalars(part, nb, S, kPcgAlpha, false, c->stream));
+        HIPCHK(c, launch_pcg_update<TI>(n, phi, p_new, r, q, rin, S, part, c->stream));
+        HIPCHK(c, launch_pcg_scalars(part, nb, S, kPcgRr, false, c->stream));
+        pc = 1 - pc;
+        restart = false;
+        true_current = false;
+        HIPCHK(c, hipMemcpyAsync(c->hscal, S + kPcgRr, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipEventRecord(c->norm_ev, c->stream));
+        ahead = its + 1 < max_iter && rho * rel > tol;
+        if (ahead && (st = inner_vcycle(c)) != MG_OK) return st;
+        if ((st = wait_scalars(c)) != MG_OK) return st;
+        const double prev = rel;
+        rel = std::sqrt(c->hscal[0]) / nbn;
+        ++its;
+        if (prev > 0.0 && std::isfinite(rel)) rho = std::min(1.0, std::max(1e-3, rel / prev));
+        if (info && info->history && its < info->history_cap) info->history[its] = rel;
+        if (!std::isfinite(rel)) {
+            result = fail(c, MG_ERR_NONFINITE, "residual became non-finite");
+            break;
+        }
+        if (rel <= tol) {
+            // the recursive residual met tol: confirm with the true residual
+            if ((st = true_residual()) != MG_OK) return st;
+            if ((st = read_scalars(c, 3)) != MG_OK) return st;
+            true_rel = std::sqrt(c->hscal[2]) / nbn;
+            true_current = true;
+            if (true_rel > tol && its < max_iter) {
+                if (true_rel >= 0.999 * last_true) {  // no progress since the last restart: rounding floor
+                    rel = true_rel;
+                    break;
+                }
+                last_true = true_rel;
+                rel = true_rel;
+                if (info && info->history && its < info->history_cap) info->history[its] = rel;
+                restart = true;  // r and r_in now hold the true residual
+                ahead = false;
+            }
+        }
+    }
+    if (!true_current && result == MG_OK) {
+        if ((st = true_residual()) != MG_OK) return st;
+        if ((st = read_scalars(c, 3)) != MG_OK) return st;
+        true_rel = std::sqrt(c->hscal[2]) / nbn;
+    }
+    if (result == MG_OK && true_rel > tol) {
+        result = MG_ERR_NOT_CONVERGED;
+        c->err = "relative residual " + std::to_string(true_rel) + " > tol after " + std::to_string(its) +
+                 " iterations";
+    }
+    // gauge: phi <- phi - mean(phi)
+    if ((st = device_sum(c, phi, 0.0, 1, 3)) != MG_OK) return st;
+    if ((st = read_scalars(c, 4)) != MG_OK) return st;
+    HIPCHK(c, launch_shift(N0, phi, c->hscal[3] * invN, phi, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (info) {
+        info->cycles = its;
+        info->rel_res = true_rel;
+    }
+    return result;
+}
+
+}  // namespace
+
+extern "C" {
+
+mg_status mg_solve_pcg(mg_ctx* c, double* phi, const double* b, double tol, int max_iter, mg_solve_info* info) {
+    if (!c || !phi || !b || max_iter < 0 || !(tol >= 0.0)) return fail(c, MG_ERR_INVALID, "invalid solve arguments");
+    if (phi == b) return fail(c, MG_ERR_INVALID, "phi and b must not alias");
+    mg_status st;
+    if ((st = ensure_pcg(c)) != MG_OK) return st;
+    const bool cd = !c->var || c->coeff_outer_double;
+    if (c->inner_double) return cd ? pcg_impl<double, double>(c, phi, b, tol, max_iter, info)
+                                   : pcg_impl<double, float>(c, phi, b, tol, max_iter, info);
+    return cd ? pcg_impl<float, double>(c, phi, b, tol, max_iter, info)
+              : pcg_impl<float, float>(c, phi, b, tol, max_iter, info);
+}
+
+mg_status mg_create_psi(const mg_params* p, const double* psi, void* stream, mg_ctx** out) {
+    if (!out) return MG_ERR_INVALID;
+    *out = nullptr;
+    if (!psi || mg_validate_params(p) != MG_OK) return MG_ERR_INVALID;
+    mg_ctx* c = new (std::nothrow) mg_ctx();
+    if (!c) return MG_ERR_NOMEM;
+    c->p = *p;
+    c->stream = (hipStream_t)stream;
+    mg_status st = create_impl(c, nullptr, MG_DTYPE_F64, psi);
+    if (st != MG_OK) {
+        std::fprintf(stderr, "mg_create_psi: %s\n", c->err.c_str());
+        mg_destroy(c);
+        return st;
+    }
+    *out = c;
+    return MG_OK;
+}
+
+mg_status mg_predict(int n, int kind, const double* phi1, const double* phi2, const double* phi3, double growth,
+                     double* out, void* stream) {
+    if (!is_pow2(n) || n < 4 || n > 2048 || !phi1 || !out) return MG_ERR_INVALID;
+    double c1, c2 = 0.0, c3 = 0.0;
+    switch (kind) {
+        case MG_PREDICT_RECYCLE: c1 = 1.0; break;
+        case MG_PREDICT_GROWTH:
+            if (!std::isfinite(growth)) return MG_ERR_INVALID;
+            c1 = growth;
+            break;
+        case MG_PREDICT_LINEAR:
+            if (!phi2) return MG_ERR_INVALID;
+            c1 = 2.0; c2 = -1.0;
+            break;
+        case MG_PREDICT_QUADRATIC:
+            if (!phi2 || !phi3) return MG_ERR_INVALID;
+            c1 = 3.0; c2 = -3.0; c3 = 1.0;
+            break;
+        default: return MG_ERR_INVALID;
+    }
+    const size_t N = (size_t)n * n * n;
+    return launch_combine3(N, c1, phi1, c2, phi2, c3, phi3, out, (hipStream_t)stream) == hipSuccess ? MG_OK
+                                                                                                   : MG_ERR_HIP;
+}
+
+mg_status mg_accel(int n, double h, const double* phi, const double* psi, double scale, void* a_out, int dtype,
+                   void* stream) {
+    if (!is_pow2(n) || n < 4 || n > 2048 || !(h > 0) || !phi || !a_out || !std::isfinite(scale))
+        return MG_ERR_INVALID;
+    hipError_t e;
+    if (dtype == MG_DTYPE_F64) e = launch_accel<double>(n, h, phi, psi, scale, (double*)a_out, (hipStream_t)stream);
+    else if (dtype == MG_DTYPE_F32) e = launch_accel<float>(n, h, phi, psi, scale, (float*)a_out, (hipStream_t)stream);
+    else return MG_ERR_INVALID;
+    return e == hipSuccess ? MG_OK : MG_ERR_HIP;
 }
 
 mg_status mg_vcycle(mg_ctx* c, double* phi, const double* b, double* rel_res_out) {
