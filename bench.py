@@ -15,8 +15,10 @@ dominant kernel (fine-level smoothing step; in-dispatch HIP events around each
 launch, algorithmic bytes counted by the library), a size sweep 32^3 .. 1024^3
 (cold solves to the tolerance, mixed and float64, with the smoothing kernel's
 fraction of the HBM peak; 512^3 and 1024^3 are the large-mesh runs), the
-256^3 moving-mesh solve with its forward/backward timing, and the CPU oracle
-timed on a bounded sample.
+256^3 moving-mesh solve with its forward/backward timing and the ablation of
+its smoother and coarse operators, the initial-guess predictors and
+multigrid-preconditioned CG on the warm-start sequence, the force readout
+kernel, and the CPU oracle timed on a bounded sample.
 """
 import argparse
 import json
@@ -174,6 +176,100 @@ def moving_mesh_leg(mgpu, torch, n, tol):
         grads[prec] = {"forward_ms": round(f, 2), "forward_backward_ms": round(fb, 2),
                        "ratio": round(fb / f, 3)}
     out["gradient"] = grads
+    print("[bench] moving-mesh smoother / coarse-operator ablation", file=sys.stderr, flush=True)
+    out["ablation"] = ablation_leg(mgpu, torch, psi, b, tol)
+    return out
+
+
+def predictor_leg(mgpu, torch, mg, sources, tol):
+    """Initial guesses on the warm-start sequence (Sec. 3.2): each step solved
+    to `tol` from the predictor's guess, with earlier solutions kept on the
+    device; the CG variant seeds multigrid-preconditioned CG with the recycled
+    potential.  Steps without enough history use the longest predictor they
+    can (t = 0 starts from zero)."""
+    n = sources[0].shape[0]
+    need = {"recycle": 1, "growth": 1, "linear": 2, "quadratic": 3}
+    out = {}
+    for variant in ("recycle", "growth", "linear", "quadratic", "pcg"):
+        kind = "recycle" if variant == "pcg" else variant
+        hist = []
+        cyc, res0 = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t, b in enumerate(sources):
+            if not hist:
+                guess = torch.zeros_like(b)
+            else:
+                k = kind if len(hist) >= need[kind] else ("linear" if len(hist) == 2 else "recycle")
+                g = (1.0 + 0.05 * t) / (1.0 + 0.05 * (t - 1))
+                guess = mgpu.predict(k, hist, growth=g if k == "growth" else 1.0)
+            fn = mg.solve_pcg if variant == "pcg" else mg.solve
+            kw = {"max_iter": 60} if variant == "pcg" else {"max_cycles": 60}
+            phi, info = fn(b, phi0=guess, out=guess, tol=tol, history=False, **kw)
+            cyc.append(info.cycles)
+            res0.append(info.rel_res0)
+            hist = [phi] + hist[:2]
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0)
+        out[variant] = {"cycles_per_step": cyc, "total_cycles": sum(cyc), "ms_per_sequence": round(ms, 3),
+                        "rel_res0_per_step": [float(f"{r:.3e}") for r in res0]}
+    return out
+
+
+def ablation_leg(mgpu, torch, psi, b, tol):
+    """Moving-mesh solver settings (Sec. 4.3, App. B): Chebyshev degree 3 with
+    Gershgorin bounds vs weighted Jacobi (omega = 2/3, 2 sweeps), coarse
+    coefficients by full weighting of C vs rediscretised from the restricted
+    deformation potential, and the potential-rediscretised hierarchy under CG.
+    The fine operator is the same float64 C(psi) in every variant; mixed
+    precision, cold solves to `tol`."""
+    C64, _ = mgpu.geometry(psi)
+    n = psi.shape[0]
+    out = {}
+    for smoother in ("chebyshev", "jacobi"):
+        for coarse in ("fw_coeff", "psi"):
+            kw = {"psi": psi} if coarse == "psi" else {"coeff": C64}
+            mg = mgpu.Multigrid(n, precision="mixed", smoother=smoother, **kw)
+            info, ms, _, phi = solve_timed(mg, torch, b, tol, max_cycles=100)
+            out[f"{smoother}+{coarse}"] = {"cycles": info.cycles, "time_to_tol_ms": round(ms, 3),
+                                           "rel_res": info.rel_res}
+            if smoother == "chebyshev" and coarse == "psi":
+                phi.zero_()
+                mg.solve_pcg(b, phi0=phi, out=phi, tol=tol, max_iter=100, history=False, raise_on_error=False)
+                phi.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, pinfo = mg.solve_pcg(b, phi0=phi, out=phi, tol=tol, max_iter=100, history=False,
+                                        raise_on_error=False)
+                torch.cuda.synchronize()
+                out["pcg+chebyshev+psi"] = {"cycles": pinfo.cycles,
+                                            "time_to_tol_ms": round(1e3 * (time.perf_counter() - t0), 3),
+                                            "rel_res": pinfo.rel_res}
+            del mg, phi
+    del C64
+    torch.cuda.empty_cache()
+    return out
+
+
+def accel_leg(mgpu, torch, phi, psi, reps=20):
+    """Force readout -s J^-1 grad phi after the solve: average kernel time and
+    algorithmic HBM rate (phi, psi read once; three components written)."""
+    n = phi.shape[0]
+    out = {}
+    for name, ps in (("flat", None), ("curvilinear", psi)):
+        for dt, sz in ((torch.float32, 4), (torch.float64, 8)):
+            a = mgpu.accel(phi, ps, scale=1.5 * 0.3, dtype=dt)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                a = mgpu.accel(phi, ps, scale=1.5 * 0.3, dtype=dt)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            by = n ** 3 * (8 + (8 if ps is not None else 0) + 3 * sz)
+            out[f"{name}_{'f32' if sz == 4 else 'f64'}"] = {"ms": round(ms, 4), "alg_bytes": by,
+                                                           "GBps": round(by / (ms * 1e-3) / 1e9, 1)}
+            del a
     return out
 
 
@@ -199,6 +295,7 @@ def main():
     ap.add_argument("--sweep-max", type=int, default=1024, help="largest grid of the size sweep")
     ap.add_argument("--no-mm", action="store_true", help="skip the moving-mesh and gradient leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-next", action="store_true", help="skip the predictor, CG and force-readout legs")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -271,6 +368,21 @@ def main():
         }
         del mg64
 
+    # ------------------------------------------------------------- predictors, CG, force readout
+    pred = accel = None
+    if not args.no_next:
+        print("[bench] predictor / CG leg", file=sys.stderr, flush=True)
+        pred = predictor_leg(mgpu, torch, mg, sources, args.tol)
+        psi_rf = None
+        from workloads import psi_unit
+        scale = json.load(open(os.path.join(ROOT, "tests", "golden", "psi_scale.json")))["scale"].get(str(n))
+        if scale is not None:
+            psi_rf = torch.from_numpy(scale * psi_unit(n)).to(dev)
+        accel = accel_leg(mgpu, torch, phi_mixed, psi_rf)
+        del psi_rf
+    del mg
+    torch.cuda.empty_cache()
+
     # ------------------------------------------------------------- size sweep 32^3 .. 1024^3
     sweep = {}
     if not args.no_sweep:
@@ -341,6 +453,8 @@ def main():
         "sweep": sweep,
         "b512": sweep.get("512"),
         "moving_mesh": mm,
+        "predictors": pred,
+        "accel": accel,
         "cpu_baseline": cpu,
     }
     print(json.dumps(result), flush=True)
