@@ -34,21 +34,20 @@ sys.path.insert(0, ROOT)
 METRIC = "V-cycle Mpts/s + HBM GB/s; time to rel. residual 1e-10, mixed vs FP64"
 HBM_PEAK_GBPS = 8000.0
 
-# Measured HBM bytes per launch of the fine-level smoothing kernel on the
+# Measured HBM bytes per launch of the fine-level smoothing kernels on the
 # 256^3 / degree-3 workload: rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch
-# (profiles/hbm_bytes_smooth_outer_rr_prolong_256_512.md) scaled by the
-# copy-kernel factors 2.0 (fetch) and 1.0 (write), averaged over one V-cycle's
-# 3 launches with and 2 without the previous iterate.  Reported only while the
-# device code of the row kernels is the code the counters were taken on.
+# (profiles/hbm_bytes_*.md) scaled by the copy-kernel factors 2.0 (fetch) and
+# 1.0 (write), averaged over the launches of one V-cycle.  Reported only while
+# the device code of the row kernels is the code the counters were taken on.
 TRAFFIC = {
-    "device_code_sha256": "0082d6d74fc5b8609c8c9d63eb5f23aba05832482716b4d67b6e5ac3e8344c58",
+    "device_code_sha256": None,
     "n": 256,
     "degree": 3,
-    "bytes_per_launch": (3 * (2 * 100560.6 + 65536.0) + 2 * (2 * 67953.1 + 65536.0)) / 5 * 1024,
+    "bytes_per_launch": {},
 }
 
 
-def measured_traffic(n, degree):
+def measured_traffic(n, degree, kernel):
     import hashlib
     src = open(os.path.join(ROOT, "paper_2607_10983_amd", "csrc", "flat_row.hip")).read()
     dev = src[: src.index("\nint g_target_blocks")]
@@ -56,22 +55,46 @@ def measured_traffic(n, degree):
         return None
     if (n, degree) != (TRAFFIC["n"], TRAFFIC["degree"]):
         return None
-    return round(TRAFFIC["bytes_per_launch"])
+    v = TRAFFIC["bytes_per_launch"].get(kernel)
+    return round(v) if v is not None else None
+
+
+def pass_bytes(v, from_zero, x1_fused, pairs, s):
+    """Algorithmic bytes per point of one smoothing pass of degree v, following
+    the library's schedule: steps pair up from the end of the pass where the
+    two-step kernel runs (a pair that is not the last writes its first step)."""
+    tot, prev, k = 0.0, False, 0
+    if from_zero and x1_fused:
+        k = 1
+    while k < v:
+        rem = v - k
+        need_y1 = rem > 2
+        if pairs and rem >= 2 and rem % 2 == 0 and not (k == 0 and from_zero) and not (need_y1 and prev):
+            tot += (3 + prev + need_y1) * s
+            prev, k = need_y1, k + 2
+        elif k == 0 and from_zero:
+            tot += 2 * s
+            prev, k = False, k + 1
+        else:
+            tot += (4 if prev else 3) * s
+            prev, k = True, k + 1
+    return tot
 
 
 def model_bytes_per_cycle(n, levels, degree, precision):
     """Algorithmic bytes of one outer iteration (inner V-cycle + outer residual/update),
     every field element each kernel reads or writes counted once.  The first
-    fine-level smoothing step from zero is written by the outer kernel (x1 = c0 D^-1 r)."""
+    fine-level smoothing step from zero is written by the outer kernel (x1 = c0 D^-1 r);
+    the two-step kernel runs on levels 64 <= n_l with rows of at most 1 KB."""
     s = 8 if precision == "fp64" else 4
     tot = 0.0
     for l in range(levels - 1):
-        N = (n >> l) ** 3
-        first = 0 if l == 0 else 2 * s
-        pre = first + (3 * s if degree >= 2 else 0) + 4 * s * max(degree - 2, 0)
-        post = 3 * s + 4 * s * (degree - 1)
+        nl = n >> l
+        pairs = nl >= 64 and nl * s <= 1024
+        pre = pass_bytes(degree, True, l == 0, pairs, s)
+        post = pass_bytes(degree, False, False, pairs, s)
         transfers = 2 * s + s / 8 + 2 * s + s / 8
-        tot += N * (pre + post + transfers)
+        tot += nl ** 3 * (pre + post + transfers)
     # outer: read phi, e, b; write phi, r and the first smoothing step (e, r, x1 inner precision)
     tot += n ** 3 * (8 + s + 8 + 8 + s + s)
     return tot
@@ -89,11 +112,19 @@ def run_sequence(mg, sources, phi, tol, max_cycles=60):
     return cycles
 
 
+MG_TIME_STEP, MG_TIME_PAIR = 1, 2
+
+
 def solve_timed(mg, torch, b, tol, max_cycles=60):
-    """Cold solve from zero: (cycles, ms, rel_res, kernel launches, kernel ms, kernel bytes)."""
+    """Cold solve from zero: (info, ms, one-step kernel (launches, ms, bytes), phi,
+    two-step kernel (launches, ms, bytes)).  The warm-up solve times the
+    two-step kernels, the timed solve the one-step kernels."""
     phi = torch.zeros_like(b)
+    mg.enable_kernel_timing(MG_TIME_PAIR)
+    mg.kernel_timing()
     mg.solve(b, phi0=phi, out=phi, tol=tol, max_cycles=max_cycles, history=False, raise_on_error=False)
-    mg.enable_kernel_timing(True)
+    pair = mg.kernel_timing()
+    mg.enable_kernel_timing(MG_TIME_STEP)
     mg.kernel_timing()
     phi.zero_()
     torch.cuda.synchronize()
@@ -102,8 +133,16 @@ def solve_timed(mg, torch, b, tol, max_cycles=60):
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     k, kms, kby = mg.kernel_timing()
-    mg.enable_kernel_timing(False)
-    return info, 1e3 * t, (k, kms, kby), phi
+    mg.enable_kernel_timing(0)
+    return info, 1e3 * t, (k, kms, kby), phi, pair
+
+
+def rate(kt):
+    """(GB/s, avg launch us) of a (launches, ms, bytes) triple, or Nones."""
+    k, ms, by = kt
+    if not k or ms <= 0:
+        return None, None
+    return round(by / (ms * 1e-3) / 1e9, 1), round(1e3 * ms / k, 2)
 
 
 def sweep_point(mgpu, torch, flat_source, n, tol):
@@ -115,16 +154,19 @@ def sweep_point(mgpu, torch, flat_source, n, tol):
     out = {"levels": levels, "degree": deg}
     for prec in ("mixed", "fp64"):
         mg = mgpu.Multigrid(n, levels=levels, degree=deg, precision=prec)
-        info, ms, (k, kms, kby), phi = solve_timed(mg, torch, b, tol)
-        gbps = kby / (kms * 1e-3) / 1e9 if kms > 0 else None
+        info, ms, kt, phi, pt = solve_timed(mg, torch, b, tol)
+        gbps, us = rate(kt)
+        pgbps, pus = rate(pt)
         out[prec] = {
             "cycles": info.cycles,
             "time_to_tol_ms": round(ms, 3),
             "vcycle_mpts_per_s": round(info.cycles * n ** 3 / (ms * 1e-3) / 1e6, 1),
             "rel_res": info.rel_res,
-            "smooth_kernel_GBps": round(gbps, 1) if gbps else None,
+            "smooth_kernel_GBps": gbps,
             "smooth_kernel_frac": round(gbps / HBM_PEAK_GBPS, 4) if gbps else None,
-            "smooth_avg_launch_us": round(1e3 * kms / k, 2) if k else None,
+            "smooth_avg_launch_us": us,
+            "pair_kernel_GBps": pgbps,
+            "pair_avg_launch_us": pus,
         }
         del mg, phi
         torch.cuda.empty_cache()
@@ -148,10 +190,10 @@ def moving_mesh_leg(mgpu, torch, n, tol):
            "det_J": [round(float(sg.min()), 4), round(float(sg.max()), 4)]}
     for prec in ("mixed", "fp64"):
         mg = mgpu.Multigrid(n, coeff=C32, precision=prec)
-        info, ms, (k, kms, kby), phi = solve_timed(mg, torch, b, tol, max_cycles=100)
-        gbps = kby / (kms * 1e-3) / 1e9 if kms > 0 else None
+        info, ms, kt, phi, _ = solve_timed(mg, torch, b, tol, max_cycles=100)
+        gbps, _ = rate(kt)
         out[prec] = {"cycles": info.cycles, "time_to_tol_ms": round(ms, 3), "rel_res": info.rel_res,
-                     "smooth_kernel_GBps": round(gbps, 1) if gbps else None}
+                     "smooth_kernel_GBps": gbps}
         del mg, phi
     out["time_to_tol_ratio_fp64_over_mixed"] = round(out["fp64"]["time_to_tol_ms"] / out["mixed"]["time_to_tol_ms"], 3)
 
@@ -230,7 +272,7 @@ def ablation_leg(mgpu, torch, psi, b, tol):
         for coarse in ("fw_coeff", "psi"):
             kw = {"psi": psi} if coarse == "psi" else {"coeff": C64}
             mg = mgpu.Multigrid(n, precision="mixed", smoother=smoother, **kw)
-            info, ms, _, phi = solve_timed(mg, torch, b, tol, max_cycles=100)
+            info, ms, _, phi, _ = solve_timed(mg, torch, b, tol, max_cycles=100)
             out[f"{smoother}+{coarse}"] = {"cycles": info.cycles, "time_to_tol_ms": round(ms, 3),
                                            "rel_res": info.rel_res}
             if smoother == "chebyshev" and coarse == "psi":
@@ -321,12 +363,20 @@ def main():
     mg = mgpu.Multigrid(n, levels=levels, degree=deg, precision="mixed")
     for _ in range(args.warmup):
         run_sequence(mg, sources, phi, args.tol)
-    mg.enable_kernel_timing(True)
+    # the dominant fine smoothing kernel: one-step or two-step kernel, by total time
+    kinds = {}
+    for kind in (MG_TIME_STEP, MG_TIME_PAIR):
+        mg.enable_kernel_timing(kind)
+        mg.kernel_timing()
+        run_sequence(mg, sources, phi, args.tol)
+        kinds[kind] = mg.kernel_timing()
+    dominant = max(kinds, key=lambda k: kinds[k][1])
+    mg.enable_kernel_timing(dominant)
     mg.kernel_timing()  # reset counters
     print(f"[bench] timing {args.steps} mixed steps", file=sys.stderr, flush=True)
     t_mixed, cyc = timed(lambda: run_sequence(mg, sources, phi, args.tol), args.steps, torch)
     launches, k_ms, k_bytes = mg.kernel_timing()
-    mg.enable_kernel_timing(False)
+    mg.enable_kernel_timing(0)
     phi_mixed = phi.clone()
     cycles_per_step = cyc[0]
     total_cycles = sum(sum(c) for c in cyc)
@@ -334,18 +384,29 @@ def main():
     mpts = total_cycles * n ** 3 / t_mixed / 1e6
     bytes_cycle = model_bytes_per_cycle(n, levels, deg, "mixed")
     achieved = k_bytes / (k_ms * 1e-3) / 1e9 if k_ms > 0 else None
+    names = {MG_TIME_STEP: "k_smooth_row (fine-level Chebyshev step, float)",
+             MG_TIME_PAIR: "k_smooth2_lds (two fused fine-level Chebyshev steps, float)"}
+    other = MG_TIME_PAIR if dominant == MG_TIME_STEP else MG_TIME_STEP
+    ogbps, ous = rate(kinds[other])
     roofline = {
-        "kernel": "k_smooth (fine-level Chebyshev step, float)",
+        "kernel": names[dominant],
         "bound": "hbm",
         "achieved": round(achieved, 1) if achieved else None,
         "peak": HBM_PEAK_GBPS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBPS, 4) if achieved else None,
-        "traffic": measured_traffic(n, deg),
+        "traffic": measured_traffic(n, deg, names[dominant].split()[0]),
         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE)",
         "launches": launches,
         "avg_launch_us": round(1e3 * k_ms / launches, 2) if launches else None,
         "alg_bytes_per_launch": k_bytes / launches if launches else None,
+        "share_of_step": round(k_ms / (1e3 * t_mixed), 4),
+        "other_fine_smoothing_kernel": {
+            "kernel": names[other], "achieved": ogbps, "avg_launch_us": ous,
+            "frac": round(ogbps / HBM_PEAK_GBPS, 4) if ogbps else None,
+            "launches_per_step": kinds[other][0],
+            "share_of_step": round(kinds[other][1] / ms_per_step, 4) if kinds[other][0] else None,
+        },
     }
 
     # ------------------------------------------------------------- float64 comparison

@@ -266,15 +266,22 @@ mg_status mg_coarse_solve(mg_ctx* ctx, const double* r, double* e);
  * doubles; 2 for the seven-point operator). */
 mg_status mg_level_lmax(const mg_ctx* ctx, double* lmax_out);
 
-/* ---- timing of the dominant kernel ---------------------------------------
- * When enabled, every launch of the fine-level smoothing-step kernel inside
- * mg_solve / mg_vcycle is bracketed by HIP events on the context's stream.
- * mg_kernel_timing returns, since the previous call: the number of such
- * launches, their summed duration in milliseconds and their summed
- * algorithmic HBM bytes (every field element the launch reads or writes
- * counted once: iterate, previous iterate, right-hand side, output and the
- * six coefficient fields of a variable-coefficient operator).  It
- * synchronises the stream.  Disabled by default. */
+/* ---- timing of the dominant kernels ---------------------------------------
+ * When enabled, every launch of a fine-level smoothing kernel inside mg_solve
+ * / mg_vcycle / mg_solve_pcg whose kind is in the mask is bracketed by HIP
+ * events recorded by the kernel's own dispatch on the context's stream.
+ * Kinds: MG_TIME_STEP, the one-step kernels; MG_TIME_PAIR, the kernels that
+ * apply two consecutive smoothing steps in one pass.  mg_kernel_timing
+ * returns, since the previous call: the number of such launches, their summed
+ * duration in milliseconds and their summed algorithmic HBM bytes (every
+ * field element the launch reads or writes counted once: iterate, previous
+ * iterate, right-hand side, outputs and the six coefficient fields of a
+ * variable-coefficient operator).  It synchronises the stream.  enable is the
+ * mask (0 disables, the default); other values give MG_ERR_INVALID. */
+enum mg_timing_kind {
+    MG_TIME_STEP = 1,
+    MG_TIME_PAIR = 2
+};
 mg_status mg_enable_kernel_timing(mg_ctx* ctx, int enable);
 mg_status mg_kernel_timing(mg_ctx* ctx, int* launches, double* total_ms, double* alg_bytes);
 

@@ -287,12 +287,17 @@ class Multigrid:
         return list(arr)
 
     # ---------------------------------------------------------------- timing
-    def enable_kernel_timing(self, on: bool = True):
-        _lib.load().mg_enable_kernel_timing(self._ctx, 1 if on else 0)
+    def enable_kernel_timing(self, mask: int = _lib.MG_TIME_STEP):
+        """Time fine-level smoothing kernels of the kinds in ``mask``
+        (MG_TIME_STEP one-step kernels, MG_TIME_PAIR two-step kernels; 0 or
+        False disables, True means MG_TIME_STEP)."""
+        st = _lib.load().mg_enable_kernel_timing(self._ctx, int(mask))
+        if st != _lib.MG_OK:
+            raise self._err(st, "mg_enable_kernel_timing")
 
     def kernel_timing(self):
-        """(launches, total_ms, algorithmic_bytes) of the fine-level smoothing
-        kernel since the last call."""
+        """(launches, total_ms, algorithmic_bytes) of the timed fine-level
+        smoothing kernels since the last call."""
         k = ctypes.c_int(0)
         ms = ctypes.c_double(0.0)
         by = ctypes.c_double(0.0)

@@ -79,17 +79,29 @@ __device__ __forceinline__ T lane_rot(T v, int delta) {
 }
 
 // M x on one row: c = centre row, ym/yp = rows y-1/y+1, zm/zp = planes z-1/z+1.
+// The rounding of the stencil and of the smoothing step below is written out
+// (no contraction left to the compiler), so every kernel that applies a step
+// -- single or fused -- produces the same bits.
 template <typename T, int VEC>
 __device__ __forceinline__ void flat7_row(const T (&c)[VEC], const T (&ym)[VEC], const T (&yp)[VEC],
                                           const T (&zm)[VEC], const T (&zp)[VEC], T ih2, T (&Mx)[VEC]) {
+#pragma clang fp contract(off)
     const T lft = lane_rot(c[VEC - 1], -1);
     const T rgt = lane_rot(c[0], 1);
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
         const T l = e > 0 ? c[e - 1] : lft;
         const T r = e < VEC - 1 ? c[e + 1] : rgt;
-        Mx[e] = (((l + r) + (ym[e] + yp[e])) + (zm[e] + zp[e]) - T(6) * c[e]) * ih2;
+        const T s = ((l + r) + (ym[e] + yp[e])) + (zm[e] + zp[e]);
+        Mx[e] = __builtin_fma(T(-6), c[e], s) * ih2;
     }
+}
+
+// One smoothing step at a point: x + a (x - xp) + cd (b - M x).
+template <typename T>
+__device__ __forceinline__ T cheb_step(T x, T xp, T b, T Mx, T a, T cd) {
+#pragma clang fp contract(off)
+    return __builtin_fma(cd, b - Mx, __builtin_fma(a, x - xp, x));
 }
 
 // Block id renumbering so that each XCD (blocks are dealt round-robin to the
@@ -125,7 +137,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_row(int n, T ih2, const T* x,
             T bb[VEC], o[VEC];
             ldrow<T, VEC>(bb, b + r);
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) o[e] = cd * bb[e];
+            for (int e = 0; e < VEC; ++e) o[e] = cd * bb[e];  // x = 0: the step is cd b
             strow<T, VEC>(out + r, o);
         }
         return;
@@ -153,10 +165,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_row(int n, T ih2, const T* x,
             T Mx[VEC], o[VEC];
             flat7_row<T, VEC>(c, ym, yp, zm, zp, ih2, Mx);
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                const T xp = PREV ? pp[e] : T(0);
-                o[e] = c[e] + a * (c[e] - xp) + cd * (bb[e] - Mx[e]);
-            }
+            for (int e = 0; e < VEC; ++e) o[e] = cheb_step<T>(c[e], PREV ? pp[e] : T(0), bb[e], Mx[e], a, cd);
             strow<T, VEC>(out + g.row(y, z) + off, o);
             if (more) {
                 copyrow(zm, c);
@@ -323,10 +332,7 @@ __global__ __launch_bounds__(64 * W) void k_smooth_lds(int n, T ih2, const T* x,
         T Mx[VEC], o[VEC];
         flat7_row<T, VEC>(c, ym, yp, zm, zp, ih2, Mx);
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) {
-            const T xp = PREV ? pp[e] : T(0);
-            o[e] = c[e] + a * (c[e] - xp) + cd * (bb[e] - Mx[e]);
-        }
+        for (int e = 0; e < VEC; ++e) o[e] = cheb_step<T>(c[e], PREV ? pp[e] : T(0), bb[e], Mx[e], a, cd);
         strow<T, VEC>(out + g.row(y, z) + off, o);
         if (more) {
             copyrow(zm, c);
@@ -335,6 +341,95 @@ __global__ __launch_bounds__(64 * W) void k_smooth_lds(int n, T ih2, const T* x,
             copyrow(bb, bn);
             if constexpr (PREV) copyrow(pp, pn);
             if (lo || hi) copyrow(h, hn);
+        }
+    }
+}
+
+// =====================================================================================
+// Two consecutive smoothing steps in one pass (temporal blocking in z):
+//   y1 = x  + a1 (x  - xp) + cd1 (b - M x)       (xp = 0 when PREV1 is false)
+//   y2 = y1 + a2 (y1 - x ) + cd2 (b - M y1)
+// Only y2 (and, with Y1OUT, y1) is written.  A block of NW waves owns rows
+// y0-1 .. y0+W (W = NW - 2 outputs): every wave forms y1 on its row one plane
+// ahead of the second step, the x rows y +- 1 coming from the caches; the y1
+// plane the second step needs is shared through LDS (double-buffered by plane
+// parity, one barrier per plane), with the two edge waves supplying the halo
+// rows.  A z chunk of nz output planes forms y1 on nz + 2 planes.  The
+// arithmetic of each step is that of k_smooth_row, in the same order.
+// =====================================================================================
+template <typename T, int VEC, int NW, bool PREV1, bool Y1OUT>
+__global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* __restrict__ x,
+                                                         const T* __restrict__ xp, const T* __restrict__ b,
+                                                         T* __restrict__ y2, T* __restrict__ y1o, T a1, T cd1, T a2,
+                                                         T cd2, int nz, int nyb) {
+    constexpr int NR = 64 * VEC;
+    constexpr int W = NW - 2;
+    __shared__ T rows[2][NW][NR];
+    const RowGrid g{n, n - 1};
+    const int lb = xcd_logical(blockIdx.x, gridDim.x);
+    const int yb = lb % nyb, zc = lb / nyb;
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int y = yb * W - 1 + w;  // rows outside [0, n) wrap for loads
+    const bool outw = w >= 1 && w <= W && y < n;
+    const int z0 = zc * nz;
+    const size_t off = (size_t)lane * VEC;
+    // first step: x on this row at planes z1-1, z1, z1+1, rows y-1 / y+1 at z1, b and xp at z1
+    T xm[VEC], xc[VEC], xq[VEC], ym[VEC], yp[VEC], b1[VEC], p1[VEC];
+    // second step: y1 on this row at z2-1 and z2 (z2 = z1 - 1) and b at z2; its
+    // x_prev is x at z2, i.e. xm
+    T sm[VEC], sc[VEC], b2[VEC];
+    int z1 = z0 - 1;
+    ldrow<T, VEC>(xm, x + g.row(y, z1 - 1) + off);
+    ldrow<T, VEC>(xc, x + g.row(y, z1) + off);
+    ldrow<T, VEC>(xq, x + g.row(y, z1 + 1) + off);
+    ldrow<T, VEC>(ym, x + g.row(y - 1, z1) + off);
+    ldrow<T, VEC>(yp, x + g.row(y + 1, z1) + off);
+    ldrow<T, VEC>(b1, b + g.row(y, z1) + off);
+    if constexpr (PREV1) ldrow<T, VEC>(p1, xp + g.row(y, z1) + off);
+    const int steps = nz + 2;
+    for (int j = 0; j < steps; ++j, ++z1) {
+        const bool more = j + 1 < steps;
+        T xn[VEC], ymn[VEC], ypn[VEC], bn[VEC], pn[VEC];
+        if (more) {
+            ldrow<T, VEC>(xn, x + g.row(y, z1 + 2) + off);
+            ldrow<T, VEC>(ymn, x + g.row(y - 1, z1 + 1) + off);
+            ldrow<T, VEC>(ypn, x + g.row(y + 1, z1 + 1) + off);
+            ldrow<T, VEC>(bn, b + g.row(y, z1 + 1) + off);
+            if constexpr (PREV1) ldrow<T, VEC>(pn, xp + g.row(y, z1 + 1) + off);
+        }
+        T M1[VEC], sp[VEC];
+        flat7_row<T, VEC>(xc, ym, yp, xm, xq, ih2, M1);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) sp[e] = cheb_step<T>(xc[e], PREV1 ? p1[e] : T(0), b1[e], M1[e], a1, cd1);
+        if constexpr (Y1OUT) {
+            if (outw && j >= 1 && j <= nz) strow<T, VEC>(y1o + g.row(y, z1) + off, sp);
+        }
+        if (j >= 2) {
+            const int buf = j & 1;
+            strow<T, VEC>(&rows[buf][w][off], sc);
+            __syncthreads();
+            if (outw) {
+                T nm[VEC], np[VEC], M2[VEC], o[VEC];
+                ldrow<T, VEC>(nm, &rows[buf][w - 1][off]);
+                ldrow<T, VEC>(np, &rows[buf][w + 1][off]);
+                flat7_row<T, VEC>(sc, nm, np, sm, sp, ih2, M2);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) o[e] = cheb_step<T>(sc[e], xm[e], b2[e], M2[e], a2, cd2);
+                strow<T, VEC>(y2 + g.row(y, z1 - 1) + off, o);
+            }
+        }
+        copyrow(sm, sc);
+        copyrow(sc, sp);
+        copyrow(b2, b1);
+        if (more) {
+            copyrow(xm, xc);
+            copyrow(xc, xq);
+            copyrow(xq, xn);
+            copyrow(ym, ymn);
+            copyrow(yp, ypn);
+            copyrow(b1, bn);
+            if constexpr (PREV1) copyrow(p1, pn);
         }
     }
 }
@@ -707,6 +802,70 @@ hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, cons
     return hipGetLastError();
 }
 
+// Waves per block of the two-step kernel (W = waves - 2 output rows): 16
+// by default, 8 or 12 selectable for measurement.
+constexpr int kPairWaves = 16;
+constexpr size_t kPairLdsBudget = 64 * 1024;
+int g_pair_nz = 0;  // z chunk of the two-step kernel; 0 = chosen from n
+int g_pair_waves = kPairWaves;
+
+// A 16-wave block leaves each wave 128 VGPRs; rows of more than 1 KB
+// (float n > 256, double n > 128) spill there, and the single-step kernels
+// are faster.
+bool pair_kernels_apply(int n, size_t elem) {
+    return row_kernels_apply(n) && (size_t)n * elem <= 1024 && 2ull * kPairWaves * (size_t)n * elem <= kPairLdsBudget;
+}
+
+void set_pair_nz(int nz) {
+    if (nz >= 0) g_pair_nz = nz;
+}
+void set_pair_waves(int waves) {
+    if (waves == 8 || waves == 12 || waves == 16) g_pair_waves = waves;
+}
+
+template <typename T, int NW>
+hipError_t launch_pair_nw(int n, double ih2, const T* x, const T* xp, const T* b, T* y2, T* y1, double a1, double cd1,
+                          double a2, double cd2, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    constexpr int W = NW - 2;
+    const int nyb = (n + W - 1) / W;
+    int nz = g_pair_nz;
+    if (nz <= 0 || nz > n || (n % nz) != 0) {
+        // about 1000 blocks, z chunks of at least 8 planes
+        nz = n;
+        while (nz > 8 && (long)nyb * (n / nz) < 1024) nz >>= 1;
+    }
+    const int blocks = nyb * (n / nz);
+    DISPATCH_VEC(n, {
+        if constexpr (64 * VEC * sizeof(T) <= 1024 && 2ull * NW * 64 * VEC * sizeof(T) <= kPairLdsBudget) {
+            if (xp == nullptr && y1 == nullptr)
+                MG_LAUNCH((k_smooth2_lds<T, VEC, NW, false, false>), dim3(blocks), dim3(64 * NW), s, ev0, ev1, n,
+                          (T)ih2, x, xp, b, y2, y1, (T)a1, (T)cd1, (T)a2, (T)cd2, nz, nyb);
+            else if (xp == nullptr)
+                MG_LAUNCH((k_smooth2_lds<T, VEC, NW, false, true>), dim3(blocks), dim3(64 * NW), s, ev0, ev1, n,
+                          (T)ih2, x, xp, b, y2, y1, (T)a1, (T)cd1, (T)a2, (T)cd2, nz, nyb);
+            else if (y1 == nullptr)
+                MG_LAUNCH((k_smooth2_lds<T, VEC, NW, true, false>), dim3(blocks), dim3(64 * NW), s, ev0, ev1, n,
+                          (T)ih2, x, xp, b, y2, y1, (T)a1, (T)cd1, (T)a2, (T)cd2, nz, nyb);
+            else
+                MG_LAUNCH((k_smooth2_lds<T, VEC, NW, true, true>), dim3(blocks), dim3(64 * NW), s, ev0, ev1, n,
+                          (T)ih2, x, xp, b, y2, y1, (T)a1, (T)cd1, (T)a2, (T)cd2, nz, nyb);
+        }
+    })
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_smooth_pair_row(int n, double ih2, const T* x, const T* xp, const T* b, T* y2, T* y1,
+                                  double a1, double cd1, double a2, double cd2, hipStream_t s, hipEvent_t ev0,
+                                  hipEvent_t ev1) {
+    if (!pair_kernels_apply(n, sizeof(T)) || x == nullptr) return hipErrorInvalidValue;
+    if (g_pair_waves == 8)
+        return launch_pair_nw<T, 8>(n, ih2, x, xp, b, y2, y1, a1, cd1, a2, cd2, s, ev0, ev1);
+    if (g_pair_waves == 12)
+        return launch_pair_nw<T, 12>(n, ih2, x, xp, b, y2, y1, a1, cd1, a2, cd2, s, ev0, ev1);
+    return launch_pair_nw<T, 16>(n, ih2, x, xp, b, y2, y1, a1, cd1, a2, cd2, s, ev0, ev1);
+}
+
 template <typename TA, typename TR, typename TE>
 hipError_t launch_outer_row(int n, double ih2, const double* phi_in, const TE* e, double* phi_out, const double* b,
                             double bmean, TR* r, TR* x1, double cd0, double* partials, hipStream_t s) {
@@ -763,6 +922,12 @@ template hipError_t launch_smooth_row<float>(int, double, const float*, const fl
                                              double, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_smooth_row<double>(int, double, const double*, const double*, const double*, double*,
                                               double, double, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_smooth_pair_row<float>(int, double, const float*, const float*, const float*, float*,
+                                                  float*, double, double, double, double, hipStream_t, hipEvent_t,
+                                                  hipEvent_t);
+template hipError_t launch_smooth_pair_row<double>(int, double, const double*, const double*, const double*,
+                                                   double*, double*, double, double, double, double, hipStream_t,
+                                                   hipEvent_t, hipEvent_t);
 template hipError_t launch_rr_row<float>(int, double, const float*, const float*, float*, hipStream_t);
 template hipError_t launch_rr_row<double>(int, double, const double*, const double*, double*, hipStream_t);
 template hipError_t launch_prolong_row<float>(int, const float*, float*, hipStream_t);

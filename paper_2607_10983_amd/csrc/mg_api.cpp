@@ -26,7 +26,7 @@ struct Level {
     int n = 0;
     size_t N = 0;
     double h = 0, ih2 = 0;
-    void* x[2] = {nullptr, nullptr};  // inner iterates (ping-pong)
+    void* x[3] = {nullptr, nullptr, nullptr};  // inner iterates; x[2] only where two-step kernels run
     void* b = nullptr;                // inner right-hand side / restricted residual
     void* coeff = nullptr;            // inner-precision coefficients (6 N), nullptr for 7-point
     double lmax = 2.0;                // Gershgorin bound of D^-1 M
@@ -62,6 +62,7 @@ struct mg_ctx {
     double* G = nullptr;        // coarsest variable-coefficient pseudo-inverse
     int tail_start = -1;        // first level run by the single-workgroup tail kernel, -1 = none
     bool x1_ready = false;      // the outer residual already wrote level 0's first smoothing step
+    int x1_buf = 0;             // ... into this level-0 iterate buffer
     // The coarse sub-cycle (levels 1 .. coarsest) touches only context-owned
     // buffers with fixed arguments, so it can be captured once into a HIP graph
     // and replayed with one launch per V-cycle (MG_GRAPH set at creation).
@@ -72,6 +73,7 @@ struct mg_ctx {
     hipGraphExec_t coarse_exec = nullptr;
     int coarse_cur = 0;
     hipEvent_t norm_ev = nullptr;  // completion of the per-cycle norm readback
+    bool use_pairs = true;         // last two steps of a smoothing pass in one two-step kernel
     // conjugate-gradient state (allocated by the first mg_solve_pcg)
     double* pcg_r = nullptr;
     double* pcg_p[2] = {nullptr, nullptr};
@@ -82,7 +84,7 @@ struct mg_ctx {
     size_t scratch_elems = 0;
     std::string err;
     // timing of the fine-level smoothing kernel
-    bool timing = false;
+    int timing = 0;  // mask of timed kernel kinds (MG_TIME_STEP, MG_TIME_PAIR)
     std::vector<TimingPair> events;
     size_t events_used = 0;
     int timed_launches = 0;
@@ -265,9 +267,9 @@ OpDesc<T> op_of(const Level& L) {
 // ---- fine-level smoothing kernel timing ----------------------------------------------
 // The event pair travels with the kernel's own dispatch (hipExtLaunchKernel),
 // so the elapsed time is the kernel's execution time, as a profiler sees it.
-mg_status time_events(mg_ctx* c, bool fine, hipEvent_t* ev0, hipEvent_t* ev1) {
+mg_status time_events(mg_ctx* c, bool fine, int kind, hipEvent_t* ev0, hipEvent_t* ev1) {
     *ev0 = *ev1 = nullptr;
-    if (!c->timing || !fine) return MG_OK;
+    if (!(c->timing & kind) || !fine) return MG_OK;
     if (c->events_used == c->events.size()) {
         TimingPair tp;
         HIPCHK(c, hipEventCreate(&tp.start));
@@ -278,8 +280,8 @@ mg_status time_events(mg_ctx* c, bool fine, hipEvent_t* ev0, hipEvent_t* ev1) {
     *ev1 = c->events[c->events_used].stop;
     return MG_OK;
 }
-mg_status time_end(mg_ctx* c, bool fine, double bytes) {
-    if (!c->timing || !fine) return MG_OK;
+mg_status time_end(mg_ctx* c, bool fine, int kind, double bytes) {
+    if (!(c->timing & kind) || !fine) return MG_OK;
     c->events_used++;
     c->timed_launches++;
     c->timed_bytes += bytes;
@@ -297,6 +299,9 @@ mg_status time_end(mg_ctx* c, bool fine, double bytes) {
 
 // ---- inner V-cycle ----------------------------------------------------------------------
 // One smoothing pass on level l in inner precision T.  from_zero: the iterate is 0.
+// index of an iterate buffer other than `cur` among x[0], x[1]
+inline int other(int cur) { return cur == 0 ? 1 : 0; }
+
 template <typename T>
 mg_status smooth_level(mg_ctx* c, int l, bool from_zero) {
     Level& L = c->lev[l];
@@ -307,21 +312,50 @@ mg_status smooth_level(mg_ctx* c, int l, bool from_zero) {
     const bool fine = (l == 0);
     const double fbytes = (double)L.N * sizeof(T);
     const double cbytes = c->var ? 6.0 * (double)L.N * sizeof(T) : 0.0;
-    for (size_t k = 0; k < L.a.size(); ++k) {
+    T* bufs[3] = {(T*)L.x[0], (T*)L.x[1], (T*)L.x[2]};
+    const int v = (int)L.a.size();
+    // the last two steps of the pass run as one two-step kernel where it exists
+    const bool pairs = c->use_pairs && L.x[2] != nullptr && !c->var;
+    for (int k = 0; k < v; ++k) {
         double bytes = 0.0;
-        T* X0 = (T*)L.x[0];
-        T* X1 = (T*)L.x[1];
-        T* bufs[2] = {X0, X1};
         if (k == 0 && from_zero && l == 0 && c->x1_ready) {  // formed by the outer residual kernel
             c->x1_ready = false;
-            cur = 0;
+            cur = c->x1_buf;
             prev = -1;
             continue;
         }
+        // Steps pair up from the end of the pass: an even number of remaining
+        // steps runs as two-step kernels.  A pair that is not the last one also
+        // writes its first step (the next pair's x_prev); that needs two free
+        // buffers, i.e. no x_prev of its own.
+        const int rem = v - k;
+        const bool has_prev = cheb && prev >= 0;
+        const bool need_y1 = cheb && rem > 2;
+        const bool pair = pairs && rem >= 2 && rem % 2 == 0 && !(k == 0 && from_zero) && !(need_y1 && has_prev);
+        const int kind = pair ? MG_TIME_PAIR : MG_TIME_STEP;
         hipEvent_t ev0, ev1;
-        mg_status st = time_events(c, fine, &ev0, &ev1);
+        mg_status st = time_events(c, fine, kind, &ev0, &ev1);
         if (st != MG_OK) return st;
-        if (k == 0 && from_zero) {
+        if (pair) {
+            const T* xp = has_prev ? bufs[prev] : nullptr;
+            int out, mid = -1;
+            if (has_prev) {
+                out = 3 - cur - prev;
+            } else {
+                const int f1 = cur == 0 ? 1 : 0;
+                const int f2 = 3 - cur - f1;
+                out = need_y1 ? f2 : f1;
+                mid = need_y1 ? f1 : -1;
+            }
+            const double D = -6.0 * L.ih2;  // c / D rounded as in the single-step launch
+            HIPCHK(c, launch_smooth_pair_row<T>(L.n, L.ih2, bufs[cur], xp, (const T*)L.b, bufs[out],
+                                                mid >= 0 ? bufs[mid] : nullptr, L.a[k], L.c[k] / D, L.a[k + 1],
+                                                L.c[k + 1] / D, c->stream, ev0, ev1));
+            bytes = (3.0 + (xp ? 1.0 : 0.0) + (mid >= 0 ? 1.0 : 0.0)) * fbytes;  // x, [x_prev], b; y2, [y1]
+            prev = mid;
+            cur = out;
+            ++k;  // the pair's second step
+        } else if (k == 0 && from_zero) {
             cur = 0;
             prev = -1;
             HIPCHK(c, launch_smooth_step<T, T>(op, nullptr, nullptr, (const T*)L.b, bufs[0], 0.0, L.c[0], c->stream,
@@ -329,14 +363,14 @@ mg_status smooth_level(mg_ctx* c, int l, bool from_zero) {
             bytes = 2.0 * fbytes + cbytes;  // read b (and C for D), write x
         } else {
             const T* xp = (cheb && prev >= 0) ? bufs[prev] : nullptr;
-            const int out = (cheb && prev >= 0) ? prev : 1 - cur;
+            const int out = (cheb && prev >= 0) ? prev : other(cur);
             HIPCHK(c, launch_smooth_step<T, T>(op, bufs[cur], xp, (const T*)L.b, bufs[out], L.a[k], L.c[k],
                                                c->stream, ev0, ev1));
             bytes = (xp ? 4.0 : 3.0) * fbytes + cbytes;  // read x, [x_prev], b (, C); write out
             prev = cur;
             cur = out;
         }
-        st = time_end(c, fine, bytes);
+        st = time_end(c, fine, kind, bytes);
         if (st != MG_OK) return st;
     }
     L.cur = cur;
@@ -433,7 +467,7 @@ mg_status vcycle_from_zero(mg_ctx* c, int l) {
     if (st != MG_OK) return st;
     // the buffer of the previous iterate is free here and serves as residual scratch
     HIPCHK(c, launch_residual_restrict<T, T>(op_of<T>(L), (const T*)L.x[L.cur], (const T*)L.b, (T*)Lc.b,
-                                             (T*)L.x[1 - L.cur], c->stream));
+                                             (T*)L.x[other(L.cur)], c->stream));
     st = vcycle_from_zero<T>(c, l + 1);
     if (st != MG_OK) return st;
     HIPCHK(c, launch_prolong_add<T>(L.n, (const T*)Lc.x[Lc.cur], (T*)L.x[L.cur], c->stream));
@@ -451,14 +485,16 @@ mg_status outer_residual(mg_ctx* c, const double* phi_in, const void* e, double*
     const double ih2 = L.ih2;
     const bool x1 = next_cycle && c->tail_start != 0 && c->lev.size() > 1;
     const double c0 = L.c.empty() ? 0.0 : L.c[0];
+    // x1 goes to a buffer other than the one holding e (the previous cycle's result)
+    const int xb = other(L.cur);
     hipError_t err;
     if (c->p.precision == MG_FP64) {
         OpDesc<double> op{n, ih2, (const double*)c->coeff_outer};
         err = launch_outer_residual<double, double, double, double>(op, phi_in, (const double*)e, phi_out, b, bmean,
-                                                                    (double*)L.b, x1 ? (double*)L.x[0] : nullptr, c0,
+                                                                    (double*)L.b, x1 ? (double*)L.x[xb] : nullptr, c0,
                                                                     c->partials, c->stream);
     } else if (c->p.precision == MG_MIXED) {
-        float* x1p = x1 ? (float*)L.x[0] : nullptr;
+        float* x1p = x1 ? (float*)L.x[xb] : nullptr;
         if (c->coeff_outer_double) {
             OpDesc<double> op{n, ih2, (const double*)c->coeff_outer};
             err = launch_outer_residual<double, float, float, double>(op, phi_in, (const float*)e, phi_out, b, bmean,
@@ -471,11 +507,12 @@ mg_status outer_residual(mg_ctx* c, const double* phi_in, const void* e, double*
     } else {
         OpDesc<float> op{n, ih2, (const float*)c->coeff_outer};
         err = launch_outer_residual<float, float, float, float>(op, phi_in, (const float*)e, phi_out, b, bmean,
-                                                                (float*)L.b, x1 ? (float*)L.x[0] : nullptr, c0,
+                                                                (float*)L.b, x1 ? (float*)L.x[xb] : nullptr, c0,
                                                                 c->partials, c->stream);
     }
     HIPCHK(c, err);
     c->x1_ready = x1;
+    c->x1_buf = xb;
     return MG_OK;
 }
 
@@ -555,6 +592,7 @@ mg_status mg_destroy(mg_ctx* c) {
     for (auto& L : c->lev) {
         dfree(L.x[0]);
         dfree(L.x[1]);
+        dfree(L.x[2]);
         dfree(L.b);
         dfree(L.coeff);
     }
@@ -602,12 +640,17 @@ static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype, cons
         mg_status st;
         if ((st = dalloc(c, &L.x[0], L.N * Tsz)) != MG_OK) return st;
         if ((st = dalloc(c, &L.x[1], L.N * Tsz)) != MG_OK) return st;
+        if (!c->var && pair_kernels_apply(L.n, Tsz) && (st = dalloc(c, &L.x[2], L.N * Tsz)) != MG_OK) return st;
         if ((st = dalloc(c, &L.b, L.N * Tsz)) != MG_OK) return st;
     }
     const size_t N0 = c->lev[0].N;
     mg_status st;
     if ((st = dalloc(c, (void**)&c->phi_tmp, N0 * sizeof(double))) != MG_OK) return st;
     if (const char* t = std::getenv("MG_ROW_TARGET_BLOCKS")) set_row_target_blocks(std::atoi(t));
+    if (const char* t = std::getenv("MG_PAIR_NZ")) set_pair_nz(std::atoi(t));
+    if (const char* t = std::getenv("MG_PAIR_WAVES")) set_pair_waves(std::atoi(t));
+    // two-step smoothing kernels; MG_NO_PAIR keeps every step a kernel of its own
+    c->use_pairs = std::getenv("MG_NO_PAIR") == nullptr;
     // replaying the coarse sub-cycle from a HIP graph measured slower than eager
     // launches on this platform; it stays available for callers that want it
     c->use_graph = std::getenv("MG_GRAPH") != nullptr;
@@ -1270,7 +1313,8 @@ mg_status mg_level_lmax(const mg_ctx* c, double* out) {
 
 mg_status mg_enable_kernel_timing(mg_ctx* c, int enable) {
     if (!c) return MG_ERR_INVALID;
-    c->timing = enable != 0;
+    if (enable < 0 || enable > (MG_TIME_STEP | MG_TIME_PAIR)) return fail(c, MG_ERR_INVALID, "timing mask out of range");
+    c->timing = enable;
     c->events_used = 0;
     c->timed_launches = 0;
     c->timed_ms = 0.0;

@@ -416,3 +416,26 @@ def test_graph_replay_matches_eager(mgpu, monkeypatch, var):
         assert float(junk) == float(junk)
         assert ig.cycles == ie.cycles and ig.history == ie.history
         assert torch.equal(pe, pg)
+
+
+@pytest.mark.parametrize("n,prec", [(64, "mixed"), (128, "fp64"), (256, "mixed"), (256, "fp64")])
+@pytest.mark.parametrize("degree,smoother", [(2, "chebyshev"), (3, "chebyshev"), (4, "chebyshev"), (6, "chebyshev"),
+                                             (3, "jacobi")])
+def test_two_step_kernel_matches_single_steps(mgpu, monkeypatch, n, prec, degree, smoother):
+    """The two-step smoothing kernel (last two steps of each pass in one
+    pass over memory) computes each step in the same order as the single-step
+    kernel: solves agree bitwise with MG_NO_PAIR, cycle by cycle."""
+    b = dev(flat_source(n, 3))
+    levels = int(math.log2(n)) - 1
+    kw = dict(levels=levels, degree=degree, precision=prec, smoother=smoother, sweeps=degree)
+    monkeypatch.setenv("MG_NO_PAIR", "1")
+    single = mgpu.Multigrid(n, **kw)
+    monkeypatch.delenv("MG_NO_PAIR")
+    fused = mgpu.Multigrid(n, **kw)
+    out = []
+    for mg in (single, fused):
+        phi, info = mg.solve(b, tol=1e-10, max_cycles=12, raise_on_error=False)
+        out.append((phi, info))
+    (ps, is_), (pf, if_) = out
+    assert is_.cycles == if_.cycles and is_.history == if_.history
+    assert torch.equal(ps, pf)
