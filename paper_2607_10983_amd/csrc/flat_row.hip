@@ -802,16 +802,17 @@ hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, cons
     return hipGetLastError();
 }
 
-// Waves per block of the two-step kernel (W = waves - 2 output rows): 16
-// by default, 8 or 12 selectable for measurement.
-constexpr int kPairWaves = 16;
+// Waves per block of the two-step kernel (W = waves - 2 output rows): 8 by
+// default (measured best of 8, 12 and 16 on the 256^3 sequence: 37.4 vs
+// 37.7 vs 38.0 ms), 12 or 16 selectable for measurement.
+constexpr int kPairWaves = 16;  // the largest block (LDS and register budget checks)
 constexpr size_t kPairLdsBudget = 64 * 1024;
 int g_pair_nz = 0;  // z chunk of the two-step kernel; 0 = chosen from n
-int g_pair_waves = kPairWaves;
+int g_pair_waves = 8;
 
-// A 16-wave block leaves each wave 128 VGPRs; rows of more than 1 KB
-// (float n > 256, double n > 128) spill there, and the single-step kernels
-// are faster.
+// Rows of more than 1 KB (float n > 256, double n > 128) need more
+// registers than a 16-wave block leaves a wave (128 VGPRs), and the
+// single-step kernels measured faster there.
 bool pair_kernels_apply(int n, size_t elem) {
     return row_kernels_apply(n) && (size_t)n * elem <= 1024 && 2ull * kPairWaves * (size_t)n * elem <= kPairLdsBudget;
 }
