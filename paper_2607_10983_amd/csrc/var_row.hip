@@ -4,9 +4,14 @@
 // whole x-row (lane l holds VEC = n/64 contiguous elements), x-shifted values
 // of any row come from rotating cross-lane moves (periodic wrap included),
 // and the wave marches a chunk of z-planes keeping the 3 x 3 (y, z) block of
-// iterate rows around its row in registers.  The six coefficient fields are
-// read row by row (the rows at y +- 1 and z +- 1 are re-reads served by
-// L1/L2).  The operator (Sec. 4.3.1, cross terms read as averaged fluxes):
+// iterate rows around its row in registers.  The coefficient components that
+// couple z (C^{zz}, C^{xz}, C^{yz}) ride in the same kind of z queue for the
+// wave's own row, so each of their rows is read once per pass; C^{xx},
+// C^{yy}, C^{xy} and the y-neighbour rows of C^{yy}, C^{xy}, C^{yz} are read
+// per plane (the y-neighbour rows are re-reads of the adjacent waves' rows).
+// Where the queue would cost occupancy (rows of more than 16 bytes per lane in
+// the smoothing kernel, VEC > 4 elsewhere) the z rows are re-read instead.
+// The operator (Sec. 4.3.1, cross terms read as averaged fluxes):
 //   M u = sum_a [f_a+ (u_{+a} - u) - f_a- (u - u_{-a})] / h^2
 //       + 1/(4 h^2) sum_{a != b} [C^{ab}_{+a} (u_{+a+b} - u_{+a-b}) - C^{ab}_{-a} (u_{-a+b} - u_{-a-b})]
 // with f_a+- the mean of C^{aa} over the two cells of the face, and
@@ -99,11 +104,40 @@ struct RowGrid {
     }
 };
 
-// U[dy + 1][dz + 1] = iterate rows (y + dy, z + dz); returns M u and D of row (y, z).
-template <typename T, typename TC, int VEC>
-__device__ __forceinline__ void var19_row(const T (&U)[3][3][VEC], const TC* __restrict__ C, size_t N,
-                                          const RowGrid& g, int y, int z, size_t off, T ih2, T (&Mu)[VEC],
-                                          T (&D)[VEC]) {
+// z queue of the own row's C^{zz}, C^{xz}, C^{yz} at planes z-1, z, z+1 (index 0, 1, 2)
+template <typename T, int VEC>
+struct CQueue {
+    T zz[3][VEC], xz[3][VEC], yz[3][VEC];
+};
+template <bool ZQ, typename T, typename TC, int VEC>
+__device__ __forceinline__ void cq_load(CQueue<T, VEC>& q, int slot, const TC* __restrict__ C, size_t N,
+                                        const RowGrid& g, int y, int z, size_t off) {
+    if constexpr (!ZQ) return;
+    const size_t r = g.row(y, z) + off;
+    ldcrow<T, TC, VEC>(q.zz[slot], C + 2 * N + r);
+    ldcrow<T, TC, VEC>(q.xz[slot], C + 4 * N + r);
+    ldcrow<T, TC, VEC>(q.yz[slot], C + 5 * N + r);
+}
+template <bool ZQ, typename T, int VEC>
+__device__ __forceinline__ void cq_shift(CQueue<T, VEC>& q) {
+    if constexpr (!ZQ) return;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        q.zz[0][e] = q.zz[1][e];
+        q.zz[1][e] = q.zz[2][e];
+        q.xz[0][e] = q.xz[1][e];
+        q.xz[1][e] = q.xz[2][e];
+        q.yz[0][e] = q.yz[1][e];
+        q.yz[1][e] = q.yz[2][e];
+    }
+}
+
+// U[dy + 1][dz + 1] = iterate rows (y + dy, z + dz), q the z queue of the row
+// (unused without ZQ); returns M u and D of row (y, z).
+template <bool ZQ, typename T, typename TC, int VEC>
+__device__ __forceinline__ void var19_row(const T (&U)[3][3][VEC], const CQueue<T, VEC>& q,
+                                          const TC* __restrict__ C, size_t N, const RowGrid& g, int y, int z,
+                                          size_t off, T ih2, T (&Mu)[VEC], T (&D)[VEC]) {
     const TC* Cxx = C;
     const TC* Cyy = C + N;
     const TC* Czz = C + 2 * N;
@@ -111,6 +145,21 @@ __device__ __forceinline__ void var19_row(const T (&U)[3][3][VEC], const TC* __r
     const TC* Cxz = C + 4 * N;
     const TC* Cyz = C + 5 * N;
     const size_t r0 = g.row(y, z) + off;
+    // z rows of C^{zz}, C^{xz}, C^{yz}: from the queue, or re-read
+    T lzz[3][VEC], lxz[3][VEC], lyz[3][VEC];
+    if constexpr (!ZQ) {
+        ldcrow<T, TC, VEC>(lzz[1], Czz + r0);
+        ldcrow<T, TC, VEC>(lzz[2], Czz + g.row(y, z + 1) + off);
+        ldcrow<T, TC, VEC>(lzz[0], Czz + g.row(y, z - 1) + off);
+        ldcrow<T, TC, VEC>(lxz[1], Cxz + r0);
+        ldcrow<T, TC, VEC>(lxz[2], Cxz + g.row(y, z + 1) + off);
+        ldcrow<T, TC, VEC>(lxz[0], Cxz + g.row(y, z - 1) + off);
+        ldcrow<T, TC, VEC>(lyz[2], Cyz + g.row(y, z + 1) + off);
+        ldcrow<T, TC, VEC>(lyz[0], Cyz + g.row(y, z - 1) + off);
+    }
+    const T(&zz)[3][VEC] = ZQ ? q.zz : lzz;
+    const T(&xz)[3][VEC] = ZQ ? q.xz : lxz;
+    const T(&yz)[3][VEC] = ZQ ? q.yz : lyz;
     T acc[VEC], dsum[VEC], cross[VEC];
     T up[VEC], um[VEC];
     shifts<T, VEC>(U[1][1], up, um);
@@ -140,10 +189,9 @@ __device__ __forceinline__ void var19_row(const T (&U)[3][3][VEC], const TC* __r
         }
     }
     {   // z faces
-        T c[VEC], cp[VEC], cm[VEC];
-        ldcrow<T, TC, VEC>(c, Czz + r0);
-        ldcrow<T, TC, VEC>(cp, Czz + g.row(y, z + 1) + off);
-        ldcrow<T, TC, VEC>(cm, Czz + g.row(y, z - 1) + off);
+        const T(&c)[VEC] = zz[1];
+        const T(&cp)[VEC] = zz[2];
+        const T(&cm)[VEC] = zz[0];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
             const T uc = U[1][1][e];
@@ -169,11 +217,10 @@ __device__ __forceinline__ void var19_row(const T (&U)[3][3][VEC], const TC* __r
         }
     }
     {   // pairs (x,z) and (z,x)
-        T c[VEC], cxp[VEC], cxm[VEC], czp[VEC], czm[VEC];
-        ldcrow<T, TC, VEC>(c, Cxz + r0);
-        shifts<T, VEC>(c, cxp, cxm);
-        ldcrow<T, TC, VEC>(czp, Cxz + g.row(y, z + 1) + off);
-        ldcrow<T, TC, VEC>(czm, Cxz + g.row(y, z - 1) + off);
+        T cxp[VEC], cxm[VEC];
+        shifts<T, VEC>(xz[1], cxp, cxm);
+        const T(&czp)[VEC] = xz[2];
+        const T(&czm)[VEC] = xz[0];
         T zpp[VEC], zpm[VEC], zmp[VEC], zmm[VEC];  // u(z+1, x+-1), u(z-1, x+-1)
         shifts<T, VEC>(U[1][2], zpp, zpm);
         shifts<T, VEC>(U[1][0], zmp, zmm);
@@ -184,11 +231,11 @@ __device__ __forceinline__ void var19_row(const T (&U)[3][3][VEC], const TC* __r
         }
     }
     {   // pairs (y,z) and (z,y)
-        T cyp[VEC], cym[VEC], czp[VEC], czm[VEC];
+        T cyp[VEC], cym[VEC];
         ldcrow<T, TC, VEC>(cyp, Cyz + g.row(y + 1, z) + off);
         ldcrow<T, TC, VEC>(cym, Cyz + g.row(y - 1, z) + off);
-        ldcrow<T, TC, VEC>(czp, Cyz + g.row(y, z + 1) + off);
-        ldcrow<T, TC, VEC>(czm, Cyz + g.row(y, z - 1) + off);
+        const T(&czp)[VEC] = yz[2];
+        const T(&czm)[VEC] = yz[0];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
             // upp = u(y+1,z+1), upm = u(y+1,z-1), ump = u(y-1,z+1), umm = u(y-1,z-1)
@@ -271,7 +318,7 @@ __device__ __forceinline__ void shift_queue(T (&U)[3][3][VEC]) {
 // =====================================================================================
 // smoothing step: out = x + a (x - xprev) + c D^-1 (b - M x)
 // =====================================================================================
-template <typename T, typename TC, int VEC, bool HASX, bool PREV>
+template <typename T, typename TC, int VEC, bool HASX, bool PREV, bool ZQ = (VEC * sizeof(T) <= 16)>
 __global__ __launch_bounds__(kBlock) void k_var_smooth_row(int n, T ih2, const TC* __restrict__ C, const T* x,
                                                            const T* xprev, const T* __restrict__ b, T* out, T a, T c,
                                                            int nz, int nyb) {
@@ -295,16 +342,20 @@ __global__ __launch_bounds__(kBlock) void k_var_smooth_row(int n, T ih2, const T
     } else {
         const PlainRows<T, T, VEC> src{x};
         T U[3][3][VEC];
+        CQueue<T, VEC> q;
         load_plane3<T, VEC>(U, 0, src, g, y, z0 - 1, off);
         load_plane3<T, VEC>(U, 1, src, g, y, z0, off);
+        cq_load<ZQ, T, TC, VEC>(q, 0, C, N, g, y, z0 - 1, off);
+        cq_load<ZQ, T, TC, VEC>(q, 1, C, N, g, y, z0, off);
         for (int k = 0; k < nz; ++k) {
             const int z = z0 + k;
             load_plane3<T, VEC>(U, 2, src, g, y, z + 1, off);
+            cq_load<ZQ, T, TC, VEC>(q, 2, C, N, g, y, z + 1, off);
             T bb[VEC], pp[VEC], Mu[VEC], D[VEC], o[VEC];
             const size_t r = g.row(y, z) + off;
             ldrow<T, VEC>(bb, b + r);
             if constexpr (PREV) ldrow<T, VEC>(pp, xprev + r);
-            var19_row<T, TC, VEC>(U, C, N, g, y, z, off, ih2, Mu, D);
+            var19_row<ZQ, T, TC, VEC>(U, q, C, N, g, y, z, off, ih2, Mu, D);
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
                 const T xc = U[1][1][e];
@@ -313,6 +364,7 @@ __global__ __launch_bounds__(kBlock) void k_var_smooth_row(int n, T ih2, const T
             }
             strow<T, VEC>(out + r, o);
             shift_queue<T, VEC>(U);
+            cq_shift<ZQ, T, VEC>(q);
         }
     }
 }
@@ -320,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_var_smooth_row(int n, T ih2, const T
 // =====================================================================================
 // residual r = b - M x (scratch of the two-pass residual restriction) / apply
 // =====================================================================================
-template <typename T, typename TC, int VEC, bool WITHB>
+template <typename T, typename TC, int VEC, bool WITHB, bool ZQ = (VEC <= 4)>
 __global__ __launch_bounds__(kBlock) void k_var_resid_row(int n, T ih2, const TC* __restrict__ C,
                                                           const T* __restrict__ x, const T* __restrict__ b,
                                                           T* __restrict__ out, int nz, int nyb) {
@@ -333,14 +385,18 @@ __global__ __launch_bounds__(kBlock) void k_var_resid_row(int n, T ih2, const TC
     const size_t off = (size_t)(threadIdx.x & 63) * VEC;
     const PlainRows<T, T, VEC> src{x};
     T U[3][3][VEC];
+    CQueue<T, VEC> q;
     load_plane3<T, VEC>(U, 0, src, g, y, z0 - 1, off);
     load_plane3<T, VEC>(U, 1, src, g, y, z0, off);
+    cq_load<ZQ, T, TC, VEC>(q, 0, C, N, g, y, z0 - 1, off);
+    cq_load<ZQ, T, TC, VEC>(q, 1, C, N, g, y, z0, off);
     for (int k = 0; k < nz; ++k) {
         const int z = z0 + k;
         load_plane3<T, VEC>(U, 2, src, g, y, z + 1, off);
+        cq_load<ZQ, T, TC, VEC>(q, 2, C, N, g, y, z + 1, off);
         const size_t r = g.row(y, z) + off;
         T Mu[VEC], D[VEC], o[VEC];
-        var19_row<T, TC, VEC>(U, C, N, g, y, z, off, ih2, Mu, D);
+        var19_row<ZQ, T, TC, VEC>(U, q, C, N, g, y, z, off, ih2, Mu, D);
         if constexpr (WITHB) {
             T bb[VEC];
             ldrow<T, VEC>(bb, b + r);
@@ -352,6 +408,7 @@ __global__ __launch_bounds__(kBlock) void k_var_resid_row(int n, T ih2, const TC
         }
         strow<T, VEC>(out + r, o);
         shift_queue<T, VEC>(U);
+        cq_shift<ZQ, T, VEC>(q);
     }
 }
 
@@ -359,7 +416,7 @@ __global__ __launch_bounds__(kBlock) void k_var_resid_row(int n, T ih2, const TC
 // outer defect correction in TA: value = phi (+ e), r = (b - bmean) - M value,
 // optional x1 = c0 D^-1 r, partial sums of r^2
 // =====================================================================================
-template <typename TA, typename TR, typename TE, typename TC, int VEC, bool UPDATE>
+template <typename TA, typename TR, typename TE, typename TC, int VEC, bool UPDATE, bool ZQ = (VEC <= 4)>
 __global__ __launch_bounds__(kBlock) void k_var_outer_row(int n, TA ih2, const TC* __restrict__ C,
                                                           const double* __restrict__ phi_in,
                                                           const TE* __restrict__ e, double* __restrict__ phi_out,
@@ -378,17 +435,21 @@ __global__ __launch_bounds__(kBlock) void k_var_outer_row(int n, TA ih2, const T
     double ss = 0.0;
     auto body = [&](const auto& src) {
         TA U[3][3][VEC];
+        CQueue<TA, VEC> q;
         load_plane3<TA, VEC>(U, 0, src, g, y, z0 - 1, off);
         load_plane3<TA, VEC>(U, 1, src, g, y, z0, off);
+        cq_load<ZQ, TA, TC, VEC>(q, 0, C, N, g, y, z0 - 1, off);
+        cq_load<ZQ, TA, TC, VEC>(q, 1, C, N, g, y, z0, off);
         for (int k = 0; k < nz; ++k) {
             const int z = z0 + k;
             load_plane3<TA, VEC>(U, 2, src, g, y, z + 1, off);
+            cq_load<ZQ, TA, TC, VEC>(q, 2, C, N, g, y, z + 1, off);
             const size_t row = g.row(y, z) + off;
             double bb[VEC];
             ldrow<double, VEC>(bb, b + row);
             TA Mu[VEC], D[VEC];
             TR ro[VEC];
-            var19_row<TA, TC, VEC>(U, C, N, g, y, z, off, ih2, Mu, D);
+            var19_row<ZQ, TA, TC, VEC>(U, q, C, N, g, y, z, off, ih2, Mu, D);
 #pragma unroll
             for (int q = 0; q < VEC; ++q) {
                 const TA ri = (TA)(bb[q] - bmean) - Mu[q];
@@ -412,6 +473,7 @@ __global__ __launch_bounds__(kBlock) void k_var_outer_row(int n, TA ih2, const T
                 strow<double, VEC>(phi_out + row, po);
             }
             shift_queue<TA, VEC>(U);
+            cq_shift<ZQ, TA, VEC>(q);
         }
     };
     if constexpr (UPDATE) body(SumRows<TA, TE, VEC>{phi_in, e});
