@@ -246,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_outer_row(int n, TA ih2, const doubl
         if (x1) {
             TR xo[VEC];
 #pragma unroll
-            for (int q = 0; q < VEC; ++q) xo[q] = (TR)(cd0 * (TA)ro[q]);
+            for (int q = 0; q < VEC; ++q) xo[q] = (TR)cd0 * ro[q];  // in the iterate's precision, as the first step from zero
             strow<TR, VEC>(x1 + row, xo);
         }
         if constexpr (UPDATE) {
@@ -356,12 +356,24 @@ __global__ __launch_bounds__(64 * W) void k_smooth_lds(int n, T ih2, const T* x,
 // parity, one barrier per plane), with the two edge waves supplying the halo
 // rows.  A z chunk of nz output planes forms y1 on nz + 2 planes.  The
 // arithmetic of each step is that of k_smooth_row, in the same order.
+//
+// FROMB: the first three steps of a pass from zero.  x is not read: it is
+// the pointwise first step x = cd0 b (cd0 = c0 / D), formed from the b rows
+// in T exactly as the single step from zero and the outer residual kernel
+// form it, and xp = 0.  One pass then reads b and writes the third step.
 // =====================================================================================
-template <typename T, int VEC, int NW, bool PREV1, bool Y1OUT>
+template <typename T, bool FROMB>
+__device__ __forceinline__ T first_step(T r, T cd0) {
+    if constexpr (FROMB) return cd0 * r;
+    return r;
+}
+
+template <typename T, int VEC, int NW, bool PREV1, bool Y1OUT, bool FROMB = false>
 __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* __restrict__ x,
                                                          const T* __restrict__ xp, const T* __restrict__ b,
                                                          T* __restrict__ y2, T* __restrict__ y1o, T a1, T cd1, T a2,
-                                                         T cd2, int nz, int nyb) {
+                                                         T cd2, int nz, int nyb, T cd0) {
+    static_assert(!(FROMB && PREV1), "a pass from zero has no x_prev");
     constexpr int NR = 64 * VEC;
     constexpr int W = NW - 2;
     __shared__ T rows[2][NW][NR];
@@ -375,33 +387,51 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
     const int z0 = zc * nz;
     const size_t off = (size_t)lane * VEC;
     // first step: x on this row at planes z1-1, z1, z1+1, rows y-1 / y+1 at z1, b and xp at z1
+    // (FROMB: these hold the b rows, x is formed from them, and b1 / b2 are
+    // the queue's own rows)
     T xm[VEC], xc[VEC], xq[VEC], ym[VEC], yp[VEC], b1[VEC], p1[VEC];
     // second step: y1 on this row at z2-1 and z2 (z2 = z1 - 1) and b at z2; its
     // x_prev is x at z2, i.e. xm
     T sm[VEC], sc[VEC], b2[VEC];
+    const T* src = FROMB ? b : x;
     int z1 = z0 - 1;
-    ldrow<T, VEC>(xm, x + g.row(y, z1 - 1) + off);
-    ldrow<T, VEC>(xc, x + g.row(y, z1) + off);
-    ldrow<T, VEC>(xq, x + g.row(y, z1 + 1) + off);
-    ldrow<T, VEC>(ym, x + g.row(y - 1, z1) + off);
-    ldrow<T, VEC>(yp, x + g.row(y + 1, z1) + off);
-    ldrow<T, VEC>(b1, b + g.row(y, z1) + off);
+    ldrow<T, VEC>(xm, src + g.row(y, z1 - 1) + off);
+    ldrow<T, VEC>(xc, src + g.row(y, z1) + off);
+    ldrow<T, VEC>(xq, src + g.row(y, z1 + 1) + off);
+    ldrow<T, VEC>(ym, src + g.row(y - 1, z1) + off);
+    ldrow<T, VEC>(yp, src + g.row(y + 1, z1) + off);
+    if constexpr (!FROMB) ldrow<T, VEC>(b1, b + g.row(y, z1) + off);
     if constexpr (PREV1) ldrow<T, VEC>(p1, xp + g.row(y, z1) + off);
     const int steps = nz + 2;
     for (int j = 0; j < steps; ++j, ++z1) {
         const bool more = j + 1 < steps;
         T xn[VEC], ymn[VEC], ypn[VEC], bn[VEC], pn[VEC];
         if (more) {
-            ldrow<T, VEC>(xn, x + g.row(y, z1 + 2) + off);
-            ldrow<T, VEC>(ymn, x + g.row(y - 1, z1 + 1) + off);
-            ldrow<T, VEC>(ypn, x + g.row(y + 1, z1 + 1) + off);
-            ldrow<T, VEC>(bn, b + g.row(y, z1 + 1) + off);
+            ldrow<T, VEC>(xn, src + g.row(y, z1 + 2) + off);
+            ldrow<T, VEC>(ymn, src + g.row(y - 1, z1 + 1) + off);
+            ldrow<T, VEC>(ypn, src + g.row(y + 1, z1 + 1) + off);
+            if constexpr (!FROMB) ldrow<T, VEC>(bn, b + g.row(y, z1 + 1) + off);
             if constexpr (PREV1) ldrow<T, VEC>(pn, xp + g.row(y, z1 + 1) + off);
         }
         T M1[VEC], sp[VEC];
-        flat7_row<T, VEC>(xc, ym, yp, xm, xq, ih2, M1);
+        if constexpr (FROMB) {
+            T fc[VEC], fm[VEC], fq[VEC], fym[VEC], fyp[VEC];
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) sp[e] = cheb_step<T>(xc[e], PREV1 ? p1[e] : T(0), b1[e], M1[e], a1, cd1);
+            for (int e = 0; e < VEC; ++e) {
+                fc[e] = first_step<T, FROMB>(xc[e], cd0);
+                fm[e] = first_step<T, FROMB>(xm[e], cd0);
+                fq[e] = first_step<T, FROMB>(xq[e], cd0);
+                fym[e] = first_step<T, FROMB>(ym[e], cd0);
+                fyp[e] = first_step<T, FROMB>(yp[e], cd0);
+            }
+            flat7_row<T, VEC>(fc, fym, fyp, fm, fq, ih2, M1);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) sp[e] = cheb_step<T>(fc[e], T(0), xc[e], M1[e], a1, cd1);
+        } else {
+            flat7_row<T, VEC>(xc, ym, yp, xm, xq, ih2, M1);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) sp[e] = cheb_step<T>(xc[e], PREV1 ? p1[e] : T(0), b1[e], M1[e], a1, cd1);
+        }
         if constexpr (Y1OUT) {
             if (outw && j >= 1 && j <= nz) strow<T, VEC>(y1o + g.row(y, z1) + off, sp);
         }
@@ -415,20 +445,25 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
                 ldrow<T, VEC>(np, &rows[buf][w + 1][off]);
                 flat7_row<T, VEC>(sc, nm, np, sm, sp, ih2, M2);
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) o[e] = cheb_step<T>(sc[e], xm[e], b2[e], M2[e], a2, cd2);
+                for (int e = 0; e < VEC; ++e) {
+                    if constexpr (FROMB)  // x_prev = first step at z2, b at z2 = the raw queue row
+                        o[e] = cheb_step<T>(sc[e], first_step<T, FROMB>(xm[e], cd0), xm[e], M2[e], a2, cd2);
+                    else
+                        o[e] = cheb_step<T>(sc[e], xm[e], b2[e], M2[e], a2, cd2);
+                }
                 strow<T, VEC>(y2 + g.row(y, z1 - 1) + off, o);
             }
         }
         copyrow(sm, sc);
         copyrow(sc, sp);
-        copyrow(b2, b1);
+        if constexpr (!FROMB) copyrow(b2, b1);
         if (more) {
             copyrow(xm, xc);
             copyrow(xc, xq);
             copyrow(xq, xn);
             copyrow(ym, ymn);
             copyrow(yp, ypn);
-            copyrow(b1, bn);
+            if constexpr (!FROMB) copyrow(b1, bn);
             if constexpr (PREV1) copyrow(p1, pn);
         }
     }
@@ -494,7 +529,7 @@ __global__ __launch_bounds__(64 * W) void k_outer_lds(int n, TA ih2, const doubl
         if (x1) {
             TR xo[VEC];
 #pragma unroll
-            for (int q = 0; q < VEC; ++q) xo[q] = (TR)(cd0 * (TA)ro[q]);
+            for (int q = 0; q < VEC; ++q) xo[q] = (TR)cd0 * ro[q];  // in the iterate's precision, as the first step from zero
             strow<TR, VEC>(x1 + row, xo);
         }
         if constexpr (UPDATE) {
@@ -824,9 +859,15 @@ void set_pair_waves(int waves) {
     if (waves == 8 || waves == 12 || waves == 16) g_pair_waves = waves;
 }
 
+// launch of one k_smooth2_lds variant inside launch_pair_nw (VEC from DISPATCH_VEC)
+#define MG_PAIR(PREV1, Y1OUT, FROMB)                                                                          \
+    MG_LAUNCH((k_smooth2_lds<T, VEC, NW, PREV1, Y1OUT, FROMB>), dim3(blocks), dim3(64 * NW), s, ev0, ev1, n, \
+              (T)ih2, x, xp, b, y2, y1, (T)a1, (T)cd1, (T)a2, (T)cd2, nz, nyb, (T)cd0)
+
 template <typename T, int NW>
 hipError_t launch_pair_nw(int n, double ih2, const T* x, const T* xp, const T* b, T* y2, T* y1, double a1, double cd1,
-                          double a2, double cd2, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                          double a2, double cd2, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, int x0_mode,
+                          double cd0) {
     constexpr int W = NW - 2;
     const int nyb = (n + W - 1) / W;
     int nz = g_pair_nz;
@@ -838,33 +879,36 @@ hipError_t launch_pair_nw(int n, double ih2, const T* x, const T* xp, const T* b
     const int blocks = nyb * (n / nz);
     DISPATCH_VEC(n, {
         if constexpr (64 * VEC * sizeof(T) <= 1024 && 2ull * NW * 64 * VEC * sizeof(T) <= kPairLdsBudget) {
-            if (xp == nullptr && y1 == nullptr)
-                MG_LAUNCH((k_smooth2_lds<T, VEC, NW, false, false>), dim3(blocks), dim3(64 * NW), s, ev0, ev1, n,
-                          (T)ih2, x, xp, b, y2, y1, (T)a1, (T)cd1, (T)a2, (T)cd2, nz, nyb);
-            else if (xp == nullptr)
-                MG_LAUNCH((k_smooth2_lds<T, VEC, NW, false, true>), dim3(blocks), dim3(64 * NW), s, ev0, ev1, n,
-                          (T)ih2, x, xp, b, y2, y1, (T)a1, (T)cd1, (T)a2, (T)cd2, nz, nyb);
-            else if (y1 == nullptr)
-                MG_LAUNCH((k_smooth2_lds<T, VEC, NW, true, false>), dim3(blocks), dim3(64 * NW), s, ev0, ev1, n,
-                          (T)ih2, x, xp, b, y2, y1, (T)a1, (T)cd1, (T)a2, (T)cd2, nz, nyb);
-            else
-                MG_LAUNCH((k_smooth2_lds<T, VEC, NW, true, true>), dim3(blocks), dim3(64 * NW), s, ev0, ev1, n,
-                          (T)ih2, x, xp, b, y2, y1, (T)a1, (T)cd1, (T)a2, (T)cd2, nz, nyb);
+            if (x0_mode != 0) {
+                if (y1 == nullptr) MG_PAIR(false, false, true);
+                else MG_PAIR(false, true, true);
+            } else if (xp == nullptr && y1 == nullptr) {
+                MG_PAIR(false, false, false);
+            } else if (xp == nullptr) {
+                MG_PAIR(false, true, false);
+            } else if (y1 == nullptr) {
+                MG_PAIR(true, false, false);
+            } else {
+                MG_PAIR(true, true, false);
+            }
         }
     })
     return hipGetLastError();
 }
+#undef MG_PAIR
 
 template <typename T>
 hipError_t launch_smooth_pair_row(int n, double ih2, const T* x, const T* xp, const T* b, T* y2, T* y1,
                                   double a1, double cd1, double a2, double cd2, hipStream_t s, hipEvent_t ev0,
-                                  hipEvent_t ev1) {
-    if (!pair_kernels_apply(n, sizeof(T)) || x == nullptr) return hipErrorInvalidValue;
+                                  hipEvent_t ev1, int x0_mode, double cd0) {
+    if (!pair_kernels_apply(n, sizeof(T))) return hipErrorInvalidValue;
+    if (x0_mode == 0 && x == nullptr) return hipErrorInvalidValue;
+    if (x0_mode != 0 && xp != nullptr) return hipErrorInvalidValue;
     if (g_pair_waves == 8)
-        return launch_pair_nw<T, 8>(n, ih2, x, xp, b, y2, y1, a1, cd1, a2, cd2, s, ev0, ev1);
+        return launch_pair_nw<T, 8>(n, ih2, x, xp, b, y2, y1, a1, cd1, a2, cd2, s, ev0, ev1, x0_mode, cd0);
     if (g_pair_waves == 12)
-        return launch_pair_nw<T, 12>(n, ih2, x, xp, b, y2, y1, a1, cd1, a2, cd2, s, ev0, ev1);
-    return launch_pair_nw<T, 16>(n, ih2, x, xp, b, y2, y1, a1, cd1, a2, cd2, s, ev0, ev1);
+        return launch_pair_nw<T, 12>(n, ih2, x, xp, b, y2, y1, a1, cd1, a2, cd2, s, ev0, ev1, x0_mode, cd0);
+    return launch_pair_nw<T, 16>(n, ih2, x, xp, b, y2, y1, a1, cd1, a2, cd2, s, ev0, ev1, x0_mode, cd0);
 }
 
 template <typename TA, typename TR, typename TE>
@@ -925,10 +969,10 @@ template hipError_t launch_smooth_row<double>(int, double, const double*, const 
                                               double, double, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_smooth_pair_row<float>(int, double, const float*, const float*, const float*, float*,
                                                   float*, double, double, double, double, hipStream_t, hipEvent_t,
-                                                  hipEvent_t);
+                                                  hipEvent_t, int, double);
 template hipError_t launch_smooth_pair_row<double>(int, double, const double*, const double*, const double*,
                                                    double*, double*, double, double, double, double, hipStream_t,
-                                                   hipEvent_t, hipEvent_t);
+                                                   hipEvent_t, hipEvent_t, int, double);
 template hipError_t launch_rr_row<float>(int, double, const float*, const float*, float*, hipStream_t);
 template hipError_t launch_rr_row<double>(int, double, const double*, const double*, double*, hipStream_t);
 template hipError_t launch_prolong_row<float>(int, const float*, float*, hipStream_t);

@@ -302,6 +302,17 @@ mg_status time_end(mg_ctx* c, bool fine, int kind, double bytes) {
 // index of an iterate buffer other than `cur` among x[0], x[1]
 inline int other(int cur) { return cur == 0 ? 1 : 0; }
 
+// The outer residual kernel can write level 0's first smoothing step (when
+// level 0 is not itself run by the tail kernel).
+inline bool x1_fusable(const mg_ctx* c) { return c->tail_start != 0 && c->lev.size() > 1; }
+
+// Level l runs its pass from zero as one three-step kernel (first step formed
+// from b on the fly): seven-point operator, two-step kernels available, and
+// at least three steps per pass.
+inline bool from_zero_triple(const mg_ctx* c, int l) {
+    return c->use_pairs && !c->var && c->lev[l].x[2] != nullptr && c->lev[l].a.size() >= 3;
+}
+
 template <typename T>
 mg_status smooth_level(mg_ctx* c, int l, bool from_zero) {
     Level& L = c->lev[l];
@@ -331,12 +342,26 @@ mg_status smooth_level(mg_ctx* c, int l, bool from_zero) {
         const int rem = v - k;
         const bool has_prev = cheb && prev >= 0;
         const bool need_y1 = cheb && rem > 2;
+        const bool triple = k == 0 && from_zero && from_zero_triple(c, l);
         const bool pair = pairs && rem >= 2 && rem % 2 == 0 && !(k == 0 && from_zero) && !(need_y1 && has_prev);
-        const int kind = pair ? MG_TIME_PAIR : MG_TIME_STEP;
+        const int kind = (pair || triple) ? MG_TIME_PAIR : MG_TIME_STEP;
         hipEvent_t ev0, ev1;
         mg_status st = time_events(c, fine, kind, &ev0, &ev1);
         if (st != MG_OK) return st;
-        if (pair) {
+        if (triple) {
+            // steps 0, 1, 2 of the pass from zero: reads b, writes x_3 (and x_2
+            // when a fourth step needs it as x_prev)
+            const bool y1 = cheb && v > 3;
+            const int out = 0, mid = y1 ? 1 : -1;
+            const double D = -6.0 * L.ih2;
+            HIPCHK(c, launch_smooth_pair_row<T>(L.n, L.ih2, nullptr, nullptr, (const T*)L.b, bufs[out],
+                                                mid >= 0 ? bufs[mid] : nullptr, L.a[1], L.c[1] / D, L.a[2],
+                                                L.c[2] / D, c->stream, ev0, ev1, 1, L.c[0] / D));
+            bytes = (2.0 + (mid >= 0 ? 1.0 : 0.0)) * fbytes;  // b; x_3 [, x_2]
+            prev = mid;
+            cur = out;
+            k = 2;  // three steps done
+        } else if (pair) {
             const T* xp = has_prev ? bufs[prev] : nullptr;
             int out, mid = -1;
             if (has_prev) {
@@ -483,7 +508,7 @@ mg_status outer_residual(mg_ctx* c, const double* phi_in, const void* e, double*
     Level& L = c->lev[0];
     const int n = L.n;
     const double ih2 = L.ih2;
-    const bool x1 = next_cycle && c->tail_start != 0 && c->lev.size() > 1;
+    const bool x1 = next_cycle && x1_fusable(c) && !from_zero_triple(c, 0);
     const double c0 = L.c.empty() ? 0.0 : L.c[0];
     // x1 goes to a buffer other than the one holding e (the previous cycle's result)
     const int xb = other(L.cur);
