@@ -845,11 +845,14 @@ constexpr size_t kPairLdsBudget = 64 * 1024;
 int g_pair_nz = 0;  // z chunk of the two-step kernel; 0 = chosen from n
 int g_pair_waves = 8;
 
-// Rows of more than 1 KB (float n > 256, double n > 128) need more
-// registers than a 16-wave block leaves a wave (128 VGPRs), and the
-// single-step kernels measured faster there.
+// Largest row (bytes) whose two-step kernel fits a wave's registers without
+// spilling: 8-wave blocks leave a wave 256 VGPRs (float n <= 512, double
+// n <= 256), 12- and 16-wave blocks 170 / 128 (float n <= 256, double n <= 128).
+constexpr size_t pair_max_row_bytes(int waves) { return waves <= 8 ? 2048 : 1024; }
+
 bool pair_kernels_apply(int n, size_t elem) {
-    return row_kernels_apply(n) && (size_t)n * elem <= 1024 && 2ull * kPairWaves * (size_t)n * elem <= kPairLdsBudget;
+    return row_kernels_apply(n) && (size_t)n * elem <= pair_max_row_bytes(g_pair_waves) &&
+           2ull * g_pair_waves * (size_t)n * elem <= kPairLdsBudget;
 }
 
 void set_pair_nz(int nz) {
@@ -878,7 +881,7 @@ hipError_t launch_pair_nw(int n, double ih2, const T* x, const T* xp, const T* b
     }
     const int blocks = nyb * (n / nz);
     DISPATCH_VEC(n, {
-        if constexpr (64 * VEC * sizeof(T) <= 1024 && 2ull * NW * 64 * VEC * sizeof(T) <= kPairLdsBudget) {
+        if constexpr (64 * VEC * sizeof(T) <= pair_max_row_bytes(NW) && 2ull * NW * 64 * VEC * sizeof(T) <= kPairLdsBudget) {
             if (x0_mode != 0) {
                 if (y1 == nullptr) MG_PAIR(false, false, true);
                 else MG_PAIR(false, true, true);

@@ -655,6 +655,11 @@ static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype, cons
     if (c->var && coarsest_n(p) > 8)
         return fail(c, MG_ERR_INVALID, "variable-coefficient coarsest level must have at most 8^3 points");
     const size_t Tsz = c->inner_double ? sizeof(double) : sizeof(float);
+    if (const char* t = std::getenv("MG_ROW_TARGET_BLOCKS")) set_row_target_blocks(std::atoi(t));
+    if (const char* t = std::getenv("MG_PAIR_NZ")) set_pair_nz(std::atoi(t));
+    if (const char* t = std::getenv("MG_PAIR_WAVES")) set_pair_waves(std::atoi(t));
+    // two-step smoothing kernels; MG_NO_PAIR keeps every step a kernel of its own
+    c->use_pairs = std::getenv("MG_NO_PAIR") == nullptr;
     c->lev.resize(p.levels);
     for (int l = 0; l < p.levels; ++l) {
         Level& L = c->lev[l];
@@ -665,17 +670,13 @@ static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype, cons
         mg_status st;
         if ((st = dalloc(c, &L.x[0], L.N * Tsz)) != MG_OK) return st;
         if ((st = dalloc(c, &L.x[1], L.N * Tsz)) != MG_OK) return st;
-        if (!c->var && pair_kernels_apply(L.n, Tsz) && (st = dalloc(c, &L.x[2], L.N * Tsz)) != MG_OK) return st;
+        if (!c->var && c->use_pairs && pair_kernels_apply(L.n, Tsz) && (st = dalloc(c, &L.x[2], L.N * Tsz)) != MG_OK)
+            return st;
         if ((st = dalloc(c, &L.b, L.N * Tsz)) != MG_OK) return st;
     }
     const size_t N0 = c->lev[0].N;
     mg_status st;
     if ((st = dalloc(c, (void**)&c->phi_tmp, N0 * sizeof(double))) != MG_OK) return st;
-    if (const char* t = std::getenv("MG_ROW_TARGET_BLOCKS")) set_row_target_blocks(std::atoi(t));
-    if (const char* t = std::getenv("MG_PAIR_NZ")) set_pair_nz(std::atoi(t));
-    if (const char* t = std::getenv("MG_PAIR_WAVES")) set_pair_waves(std::atoi(t));
-    // two-step smoothing kernels; MG_NO_PAIR keeps every step a kernel of its own
-    c->use_pairs = std::getenv("MG_NO_PAIR") == nullptr;
     // replaying the coarse sub-cycle from a HIP graph measured slower than eager
     // launches on this platform; it stays available for callers that want it
     c->use_graph = std::getenv("MG_GRAPH") != nullptr;
