@@ -368,7 +368,7 @@ __device__ __forceinline__ T first_step(T r, T cd0) {
     return r;
 }
 
-template <typename T, int VEC, int NW, bool PREV1, bool Y1OUT, bool FROMB = false>
+template <typename T, int VEC, int NW, bool PREV1, bool Y1OUT, bool FROMB = false, bool PF2 = false>
 __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* __restrict__ x,
                                                          const T* __restrict__ xp, const T* __restrict__ b,
                                                          T* __restrict__ y2, T* __restrict__ y1o, T a1, T cd1, T a2,
@@ -403,15 +403,27 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
     if constexpr (!FROMB) ldrow<T, VEC>(b1, b + g.row(y, z1) + off);
     if constexpr (PREV1) ldrow<T, VEC>(p1, xp + g.row(y, z1) + off);
     const int steps = nz + 2;
+    // PF2: operands of the plane after next are loaded one iteration earlier
+    // (a second register set), i.e. two planes ahead of their use
+    T xa[VEC], yma[VEC], ypa[VEC], ba[VEC], pa[VEC];
+    if constexpr (PF2) {
+        ldrow<T, VEC>(xa, src + g.row(y, z1 + 2) + off);
+        ldrow<T, VEC>(yma, src + g.row(y - 1, z1 + 1) + off);
+        ldrow<T, VEC>(ypa, src + g.row(y + 1, z1 + 1) + off);
+        if constexpr (!FROMB) ldrow<T, VEC>(ba, b + g.row(y, z1 + 1) + off);
+        if constexpr (PREV1) ldrow<T, VEC>(pa, xp + g.row(y, z1 + 1) + off);
+    }
     for (int j = 0; j < steps; ++j, ++z1) {
         const bool more = j + 1 < steps;
+        const int ahead = PF2 ? 1 : 0;  // the loads below are for plane z1 + 1 + ahead
+        const bool load = j + 1 + ahead < steps;
         T xn[VEC], ymn[VEC], ypn[VEC], bn[VEC], pn[VEC];
-        if (more) {
-            ldrow<T, VEC>(xn, src + g.row(y, z1 + 2) + off);
-            ldrow<T, VEC>(ymn, src + g.row(y - 1, z1 + 1) + off);
-            ldrow<T, VEC>(ypn, src + g.row(y + 1, z1 + 1) + off);
-            if constexpr (!FROMB) ldrow<T, VEC>(bn, b + g.row(y, z1 + 1) + off);
-            if constexpr (PREV1) ldrow<T, VEC>(pn, xp + g.row(y, z1 + 1) + off);
+        if (load) {
+            ldrow<T, VEC>(xn, src + g.row(y, z1 + 2 + ahead) + off);
+            ldrow<T, VEC>(ymn, src + g.row(y - 1, z1 + 1 + ahead) + off);
+            ldrow<T, VEC>(ypn, src + g.row(y + 1, z1 + 1 + ahead) + off);
+            if constexpr (!FROMB) ldrow<T, VEC>(bn, b + g.row(y, z1 + 1 + ahead) + off);
+            if constexpr (PREV1) ldrow<T, VEC>(pn, xp + g.row(y, z1 + 1 + ahead) + off);
         }
         T M1[VEC], sp[VEC];
         if constexpr (FROMB) {
@@ -460,11 +472,26 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
         if (more) {
             copyrow(xm, xc);
             copyrow(xc, xq);
-            copyrow(xq, xn);
-            copyrow(ym, ymn);
-            copyrow(yp, ypn);
-            if constexpr (!FROMB) copyrow(b1, bn);
-            if constexpr (PREV1) copyrow(p1, pn);
+            if constexpr (PF2) {
+                copyrow(xq, xa);
+                copyrow(ym, yma);
+                copyrow(yp, ypa);
+                if constexpr (!FROMB) copyrow(b1, ba);
+                if constexpr (PREV1) copyrow(p1, pa);
+                if (load) {
+                    copyrow(xa, xn);
+                    copyrow(yma, ymn);
+                    copyrow(ypa, ypn);
+                    if constexpr (!FROMB) copyrow(ba, bn);
+                    if constexpr (PREV1) copyrow(pa, pn);
+                }
+            } else {
+                copyrow(xq, xn);
+                copyrow(ym, ymn);
+                copyrow(yp, ypn);
+                if constexpr (!FROMB) copyrow(b1, bn);
+                if constexpr (PREV1) copyrow(p1, pn);
+            }
         }
     }
 }
@@ -844,6 +871,11 @@ constexpr int kPairWaves = 16;  // the largest block (LDS and register budget ch
 constexpr size_t kPairLdsBudget = 64 * 1024;
 int g_pair_nz = 0;  // z chunk of the two-step kernel; 0 = chosen from n
 int g_pair_waves = 8;
+// Prefetch depth of the two-step kernel: -1 = by row size (two planes ahead
+// for 2 KB rows, whose blocks run one per CU: 512^3 float 541 -> 498 us per
+// launch; one plane for smaller rows, where the extra registers cost
+// occupancy: 256^3 float 53 -> 61 us), 0 / 1 = one / two planes.
+int g_pair_pf2 = -1;
 
 // Largest row (bytes) whose two-step kernel fits a wave's registers without
 // spilling: 8-wave blocks leave a wave 256 VGPRs (float n <= 512, double
@@ -861,11 +893,19 @@ void set_pair_nz(int nz) {
 void set_pair_waves(int waves) {
     if (waves == 8 || waves == 12 || waves == 16) g_pair_waves = waves;
 }
+void set_pair_prefetch(int planes) {
+    if (planes == 1 || planes == 2) g_pair_pf2 = planes == 2 ? 1 : 0;
+}
 
 // launch of one k_smooth2_lds variant inside launch_pair_nw (VEC from DISPATCH_VEC)
-#define MG_PAIR(PREV1, Y1OUT, FROMB)                                                                          \
-    MG_LAUNCH((k_smooth2_lds<T, VEC, NW, PREV1, Y1OUT, FROMB>), dim3(blocks), dim3(64 * NW), s, ev0, ev1, n, \
-              (T)ih2, x, xp, b, y2, y1, (T)a1, (T)cd1, (T)a2, (T)cd2, nz, nyb, (T)cd0)
+#define MG_PAIR1(PREV1, Y1OUT, FROMB, PF2)                                                                      \
+    MG_LAUNCH((k_smooth2_lds<T, VEC, NW, PREV1, Y1OUT, FROMB, PF2>), dim3(blocks), dim3(64 * NW), s, ev0, ev1, \
+              n, (T)ih2, x, xp, b, y2, y1, (T)a1, (T)cd1, (T)a2, (T)cd2, nz, nyb, (T)cd0)
+#define MG_PAIR(PREV1, Y1OUT, FROMB)                  \
+    do {                                              \
+        if (pf2) MG_PAIR1(PREV1, Y1OUT, FROMB, true);  \
+        else MG_PAIR1(PREV1, Y1OUT, FROMB, false);    \
+    } while (0)
 
 template <typename T, int NW>
 hipError_t launch_pair_nw(int n, double ih2, const T* x, const T* xp, const T* b, T* y2, T* y1, double a1, double cd1,
@@ -880,6 +920,7 @@ hipError_t launch_pair_nw(int n, double ih2, const T* x, const T* xp, const T* b
         while (nz > 8 && (long)nyb * (n / nz) < 1024) nz >>= 1;
     }
     const int blocks = nyb * (n / nz);
+    const bool pf2 = g_pair_pf2 < 0 ? (size_t)n * sizeof(T) >= 2048 : g_pair_pf2 == 1;
     DISPATCH_VEC(n, {
         if constexpr (64 * VEC * sizeof(T) <= pair_max_row_bytes(NW) && 2ull * NW * 64 * VEC * sizeof(T) <= kPairLdsBudget) {
             if (x0_mode != 0) {
@@ -899,6 +940,7 @@ hipError_t launch_pair_nw(int n, double ih2, const T* x, const T* xp, const T* b
     return hipGetLastError();
 }
 #undef MG_PAIR
+#undef MG_PAIR1
 
 template <typename T>
 hipError_t launch_smooth_pair_row(int n, double ih2, const T* x, const T* xp, const T* b, T* y2, T* y1,

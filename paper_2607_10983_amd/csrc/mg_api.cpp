@@ -658,6 +658,7 @@ static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype, cons
     if (const char* t = std::getenv("MG_ROW_TARGET_BLOCKS")) set_row_target_blocks(std::atoi(t));
     if (const char* t = std::getenv("MG_PAIR_NZ")) set_pair_nz(std::atoi(t));
     if (const char* t = std::getenv("MG_PAIR_WAVES")) set_pair_waves(std::atoi(t));
+    if (const char* t = std::getenv("MG_PAIR_PREFETCH")) set_pair_prefetch(std::atoi(t));
     // two-step smoothing kernels; MG_NO_PAIR keeps every step a kernel of its own
     c->use_pairs = std::getenv("MG_NO_PAIR") == nullptr;
     c->lev.resize(p.levels);
