@@ -198,13 +198,37 @@ __device__ __forceinline__ void ld_value(TA (&v)[VEC], const double* phi, const 
     }
 }
 
+// Per-block partial sums of the outer kernels, three arrays of gridDim.x:
+// [0] sum (b - bmean)^2, [1] sum r^2, [2] sum phi (phi = the potential whose
+// residual is formed, in double).
+__device__ __forceinline__ void outer_partials(double* partials, double sb, double ss, double sp, double* sh,
+                                               int waves) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int o = 32; o > 0; o >>= 1) {
+        sb += __shfl_xor(sb, o, 64);
+        ss += __shfl_xor(ss, o, 64);
+        sp += __shfl_xor(sp, o, 64);
+    }
+    if (lane == 0) {
+        sh[wave] = sb;
+        sh[waves + wave] = ss;
+        sh[2 * waves + wave] = sp;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double t = 0.0;
+        for (int q = 0; q < waves; ++q) t += sh[threadIdx.x * waves + q];
+        partials[threadIdx.x * gridDim.x + blockIdx.x] = t;
+    }
+}
+
 template <typename TA, typename TR, typename TE, int VEC, bool UPDATE>
 __global__ __launch_bounds__(kBlock) void k_outer_row(int n, TA ih2, const double* __restrict__ phi_in,
                                                       const TE* __restrict__ e, double* __restrict__ phi_out,
                                                       const double* __restrict__ b, double bmean,
                                                       TR* __restrict__ r, TR* __restrict__ x1, TA cd0,
                                                       double* __restrict__ partials, int nz, int nyb) {
-    __shared__ double sh[kWaves];
+    __shared__ double sh[3 * kWaves];
     const RowGrid g{n, n - 1};
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int yb = lb % nyb, zc = lb / nyb;
@@ -220,7 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_outer_row(int n, TA ih2, const doubl
     ld_value<TA, TR, TE, VEC, UPDATE>(ym, phi_in, e, g.row(y - 1, z0) + off);
     ld_value<TA, TR, TE, VEC, UPDATE>(yp, phi_in, e, g.row(y + 1, z0) + off);
     ldrow<double, VEC>(bb, b + g.row(y, z0) + off);
-    double ss = 0.0;
+    double ss = 0.0, sb = 0.0, sp = 0.0;
     for (int k = 0; k < nz; ++k) {
         const int z = z0 + k;
         TA zpp[VEC], ymn[VEC], ypn[VEC];
@@ -237,9 +261,11 @@ __global__ __launch_bounds__(kBlock) void k_outer_row(int n, TA ih2, const doubl
         flat7_row<TA, VEC>(c, ym, yp, zm, zp, ih2, Mx);
 #pragma unroll
         for (int q = 0; q < VEC; ++q) {
-            const TA ri = (TA)(bb[q] - bmean) - Mx[q];
+            const double bq = bb[q] - bmean;
+            const TA ri = (TA)bq - Mx[q];
             ro[q] = (TR)ri;
             ss += (double)ri * (double)ri;
+            sb += bq * bq;
         }
         const size_t row = g.row(y, z) + off;
         strow<TR, VEC>(r + row, ro);
@@ -263,6 +289,16 @@ __global__ __launch_bounds__(kBlock) void k_outer_row(int n, TA ih2, const doubl
                 for (int q = 0; q < VEC; ++q) po[q] = p[q] + (double)qv[q];
             }
             strow<double, VEC>(phi_out + row, po);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) sp += po[q];
+        } else if constexpr (sizeof(TA) == sizeof(double)) {
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) sp += (double)c[q];
+        } else {
+            double p[VEC];
+            ldrow<double, VEC>(p, phi_in + row);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) sp += p[q];
         }
         if (more) {
             copyrow(zm, c);
@@ -273,11 +309,8 @@ __global__ __launch_bounds__(kBlock) void k_outer_row(int n, TA ih2, const doubl
             copyrow(bb, bn);
         }
     }
-    // fixed-order block reduction: wave butterfly, then the four wave sums
-    for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 64);
-    if ((threadIdx.x & 63) == 0) sh[wave] = ss;
-    __syncthreads();
-    if (threadIdx.x == 0) partials[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    // fixed-order block reduction: wave butterfly, then the wave sums in order
+    outer_partials(partials, sb, ss, sp, sh, kWaves);
 }
 
 // =====================================================================================
@@ -504,7 +537,7 @@ __global__ __launch_bounds__(64 * W) void k_outer_lds(int n, TA ih2, const doubl
                                                       double* __restrict__ partials, int nz, int nyb) {
     constexpr int NR = 64 * VEC;
     __shared__ TA rows[2][W + 2][NR];
-    __shared__ double sh[W];
+    __shared__ double sh[3 * W];
     const RowGrid g{n, n - 1};
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int yb = lb % nyb, zc = lb / nyb;
@@ -523,7 +556,7 @@ __global__ __launch_bounds__(64 * W) void k_outer_lds(int n, TA ih2, const doubl
     ld_value<TA, TR, TE, VEC, UPDATE>(zp, phi_in, e, g.row(y, z0 + 1) + off);
     ldrow<double, VEC>(bb, b + g.row(y, z0) + off);
     if (lo || hi) ld_value<TA, TR, TE, VEC, UPDATE>(h, phi_in, e, g.row(yh, z0) + off);
-    double ss = 0.0;
+    double ss = 0.0, sb = 0.0, sp = 0.0;
     for (int k = 0; k < nz; ++k) {
         const int z = z0 + k;
         const int buf = k & 1;
@@ -547,9 +580,11 @@ __global__ __launch_bounds__(64 * W) void k_outer_lds(int n, TA ih2, const doubl
         flat7_row<TA, VEC>(c, ym, yp, zm, zp, ih2, Mx);
 #pragma unroll
         for (int q = 0; q < VEC; ++q) {
-            const TA ri = (TA)(bb[q] - bmean) - Mx[q];
+            const double bq = bb[q] - bmean;
+            const TA ri = (TA)bq - Mx[q];
             ro[q] = (TR)ri;
             ss += (double)ri * (double)ri;
+            sb += bq * bq;
         }
         const size_t row = g.row(y, z) + off;
         strow<TR, VEC>(r + row, ro);
@@ -573,6 +608,16 @@ __global__ __launch_bounds__(64 * W) void k_outer_lds(int n, TA ih2, const doubl
                 for (int q = 0; q < VEC; ++q) po[q] = p[q] + (double)qv[q];
             }
             strow<double, VEC>(phi_out + row, po);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) sp += po[q];
+        } else if constexpr (sizeof(TA) == sizeof(double)) {
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) sp += (double)c[q];
+        } else {
+            double p[VEC];
+            ldrow<double, VEC>(p, phi_in + row);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) sp += p[q];
         }
         if (more) {
             copyrow(zm, c);
@@ -582,14 +627,7 @@ __global__ __launch_bounds__(64 * W) void k_outer_lds(int n, TA ih2, const doubl
             if (lo || hi) copyrow(h, hn);
         }
     }
-    for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 64);
-    if (lane == 0) sh[w] = ss;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int q = 0; q < W; ++q) t += sh[q];
-        partials[blockIdx.x] = t;
-    }
+    outer_partials(partials, sb, ss, sp, sh, W);
 }
 
 // =====================================================================================

@@ -61,6 +61,9 @@ hipError_t launch_apply(const OpDesc<TC>& op, const T* u, T* out, hipStream_t s)
 // r^2 (in double) written to partials[block].  phi_out must not alias phi_in.
 // If x1 != nullptr it also receives c0 D^-1 r, the first smoothing step of the
 // next V-cycle started from zero.
+// partials receives three arrays of outer_blocks() per-block sums: sum of
+// (b - bmean)^2, sum of r^2, and sum of the potential whose residual is formed
+// (phi_out when e != nullptr, else phi_in), all in double.
 template <typename TA, typename TR, typename TE, typename TC>
 hipError_t launch_outer_residual(const OpDesc<TC>& op, const double* phi_in, const TE* e,
                                  double* phi_out, const double* b, double bmean, TR* r,
@@ -70,6 +73,9 @@ hipError_t launch_outer_residual(const OpDesc<TC>& op, const double* phi_in, con
 // partials[block] = sum over the block of (u - shift)^p, p in {1, 2}.
 hipError_t launch_block_sums(int n, const double* u, double shift, int p, double* partials,
                              hipStream_t s);
+// out[slot + k] = sum_{i < count} partials[k * count + i], k < arrays (one block).
+hipError_t launch_finalize_sums(const double* partials, int count, int arrays, double* out, int slot,
+                                hipStream_t s);
 // out[slot] = sum_{i < count} partials[i] in a fixed order (one block).
 hipError_t launch_finalize_sum(const double* partials, int count, double* out, int slot,
                                hipStream_t s);

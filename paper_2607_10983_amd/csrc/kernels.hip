@@ -205,33 +205,45 @@ __global__ __launch_bounds__(kThreads) void k_outer_residual(int n, TA ih2, cons
     const int xi = blockIdx.x * blockDim.x + threadIdx.x;
     const int yi = blockIdx.y * blockDim.y + threadIdx.y;
     const int z0 = blockIdx.z * nz;
-    double ss = 0.0;
+    double ss = 0.0, sb = 0.0, sp = 0.0;
     for (int z = z0; z < z0 + nz; ++z) {
         const size_t i = g(xi, yi, z);
         TA Mu, D, uc;
         if constexpr (UPDATE) {
             const double pn = phi_in[i] + (double)e[i];
             phi_out[i] = pn;
+            sp += pn;
             uc = (TA)pn;
             const PlusE<TA, TE> u{phi_in, e};
             if (C == nullptr) Mu = flat_Mu<TA>(u, g, xi, yi, z, uc, ih2);
             else var_Mu<TA, TC>(u, C, N, g, xi, yi, z, uc, ih2, Mu, D);
         } else {
+            sp += phi_in[i];
             uc = (TA)phi_in[i];
             const Plain<TA, double> u{phi_in};
             if (C == nullptr) Mu = flat_Mu<TA>(u, g, xi, yi, z, uc, ih2);
             else var_Mu<TA, TC>(u, C, N, g, xi, yi, z, uc, ih2, Mu, D);
         }
-        const TA ri = (TA)(b[i] - bmean) - Mu;
+        const double bq = b[i] - bmean;
+        const TA ri = (TA)bq - Mu;
         r[i] = (TR)ri;
         if (x1) {
             if (C == nullptr) D = TA(-6) * ih2;
             x1[i] = (TR)(c0 * (TA)(TR)ri / D);
         }
         ss += (double)ri * (double)ri;
+        sb += bq * bq;
     }
-    const double tot = block_sum(ss, sh);
-    if (lin_tid() == 0) partials[lin_bid()] = tot;
+    // three partial sums, arrays of the block count: sum (b - bmean)^2, sum r^2, sum phi
+    const int nb = gridDim.x * gridDim.y * gridDim.z;
+    const double t0 = block_sum(sb, sh);
+    const double t1 = block_sum(ss, sh);
+    const double t2 = block_sum(sp, sh);
+    if (lin_tid() == 0) {
+        partials[lin_bid()] = t0;
+        partials[nb + lin_bid()] = t1;
+        partials[2 * nb + lin_bid()] = t2;
+    }
 }
 
 // =====================================================================================
@@ -261,6 +273,19 @@ __global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ pa
     for (int i = tid; i < count; i += 1024) v = is_max ? fmax(v, partials[i]) : v + partials[i];
     const double r = is_max ? block_max(v, sh) : block_sum(v, sh);
     if (tid == 0) out[slot] = r;
+}
+
+// out[slot + k] = sum of partials[k * count .. (k + 1) * count), k < arrays
+__global__ __launch_bounds__(1024) void k_finalize_multi(const double* __restrict__ partials, int count, int arrays,
+                                                         double* out, int slot) {
+    __shared__ double sh[1024];
+    const int tid = threadIdx.x;
+    for (int k = 0; k < arrays; ++k) {
+        double v = 0.0;
+        for (int i = tid; i < count; i += 1024) v += partials[(size_t)k * count + i];
+        const double r = block_sum(v, sh);
+        if (tid == 0) out[slot + k] = r;
+    }
 }
 
 // =====================================================================================
@@ -679,6 +704,11 @@ hipError_t launch_block_sums(int n, const double* u, double shift, int p, double
 }
 hipError_t launch_finalize_sum(const double* partials, int count, double* out, int slot, hipStream_t s) {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, partials, count, out, slot, 0);
+    return hipGetLastError();
+}
+hipError_t launch_finalize_sums(const double* partials, int count, int arrays, double* out, int slot,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_multi, dim3(1), dim3(1024), 0, s, partials, count, arrays, out, slot);
     return hipGetLastError();
 }
 hipError_t launch_finalize_max(const double* partials, int count, double* out, int slot, hipStream_t s) {

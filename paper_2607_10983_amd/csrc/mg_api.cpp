@@ -684,8 +684,9 @@ static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype, cons
     c->nparts = stencil_blocks(p.n);
     c->nparts_outer = outer_blocks(p.n, !c->var, p.precision != MG_FP32);
     {
+        // three arrays: the outer kernels write three partial sums per block
         const int np = c->nparts > c->nparts_outer ? c->nparts : c->nparts_outer;
-        if ((st = dalloc(c, (void**)&c->partials, (size_t)np * sizeof(double))) != MG_OK) return st;
+        if ((st = dalloc(c, (void**)&c->partials, 3 * (size_t)np * sizeof(double))) != MG_OK) return st;
     }
     if ((st = dalloc(c, (void**)&c->dscal, 16 * sizeof(double))) != MG_OK) return st;
     HIPCHK(c, hipHostMalloc((void**)&c->hscal, 16 * sizeof(double), hipHostMallocDefault));
@@ -884,10 +885,10 @@ static mg_status solve_impl(mg_ctx* c, double* phi, const double* b, double tol,
     if ((st = read_scalars(c, 1)) != MG_OK) return st;
     const double bmean = c->hscal[0] * invN;
     if (!std::isfinite(bmean)) return fail(c, MG_ERR_NONFINITE, "source contains NaN or Inf");
-    if ((st = device_sum(c, b, bmean, 2, 1)) != MG_OK) return st;
+    // the outer kernel also sums (b - bmean)^2 (slot 1) and phi (slot 3) beside r^2 (slot 2)
     if ((st = outer_residual(c, phi, nullptr, nullptr, b, bmean, true)) != MG_OK) return st;
-    HIPCHK(c, launch_finalize_sum(c->partials, c->nparts_outer, c->dscal, 2, c->stream));
-    if ((st = post_scalars(c, 3)) != MG_OK) return st;
+    HIPCHK(c, launch_finalize_sums(c->partials, c->nparts_outer, 3, c->dscal, 1, c->stream));
+    if ((st = post_scalars(c, 4)) != MG_OK) return st;
     // Look-ahead: the next V-cycle depends only on device data (the residual
     // just formed), so it is enqueued before the host waits for the norm; it
     // is skipped when the measured contraction predicts convergence.  A
@@ -926,9 +927,9 @@ static mg_status solve_impl(mg_ctx* c, double* phi, const double* b, double tol,
     while (rel > tol && cycles < max_cycles) {
         if (!ahead && (st = inner_vcycle(c)) != MG_OK) return st;
         if ((st = outer_residual(c, cur, inner_e(c), other, b, bmean, true)) != MG_OK) return st;
-        HIPCHK(c, launch_finalize_sum(c->partials, c->nparts_outer, c->dscal, 2, c->stream));
+        HIPCHK(c, launch_finalize_sums(c->partials, c->nparts_outer, 3, c->dscal, 1, c->stream));
         std::swap(cur, other);
-        if ((st = post_scalars(c, 3)) != MG_OK) return st;
+        if ((st = post_scalars(c, 4)) != MG_OK) return st;
         ahead = cycles + 1 < max_cycles && rho * rel > tol;
         if (ahead && (st = inner_vcycle(c)) != MG_OK) return st;
         if ((st = wait_scalars(c)) != MG_OK) return st;
@@ -950,9 +951,7 @@ static mg_status solve_impl(mg_ctx* c, double* phi, const double* b, double tol,
         c->err = "relative residual " + std::to_string(rel) + " > tol after " + std::to_string(cycles) + " cycles";
     }
     c->x1_ready = false;
-    // gauge: phi <- cur - mean(cur)
-    if ((st = device_sum(c, cur, 0.0, 1, 3)) != MG_OK) return st;
-    if ((st = read_scalars(c, 4)) != MG_OK) return st;
+    // gauge: phi <- cur - mean(cur); the sum of cur came with the last norm
     HIPCHK(c, launch_shift(N0, cur, c->hscal[3] * invN, phi, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (info) {
@@ -1205,9 +1204,8 @@ mg_status mg_vcycle(mg_ctx* c, double* phi, const double* b, double* rel_res_out
     if (c->inner_double) HIPCHK(c, launch_add<double>(N0, phi, (const double*)e, phi, c->stream));
     else HIPCHK(c, launch_add<float>(N0, phi, (const float*)e, phi, c->stream));
     if (rel_res_out) {
-        if ((st = device_sum(c, b, bmean, 2, 1)) != MG_OK) return st;
         if ((st = outer_residual(c, phi, nullptr, nullptr, b, bmean)) != MG_OK) return st;
-        HIPCHK(c, launch_finalize_sum(c->partials, c->nparts_outer, c->dscal, 2, c->stream));
+        HIPCHK(c, launch_finalize_sums(c->partials, c->nparts_outer, 3, c->dscal, 1, c->stream));
         if ((st = read_scalars(c, 3)) != MG_OK) return st;
         const double nb = std::sqrt(c->hscal[1]);
         *rel_res_out = nb > 0 ? std::sqrt(c->hscal[2]) / nb : 0.0;

@@ -423,7 +423,7 @@ __global__ __launch_bounds__(kBlock) void k_var_outer_row(int n, TA ih2, const T
                                                           const double* __restrict__ b, double bmean,
                                                           TR* __restrict__ r, TR* __restrict__ x1, TA c0,
                                                           double* __restrict__ partials, int nz, int nyb) {
-    __shared__ double sh[kWaves];
+    __shared__ double sh[3 * kWaves];
     const RowGrid g{n, n - 1};
     const size_t N = (size_t)n * n * n;
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
@@ -432,7 +432,7 @@ __global__ __launch_bounds__(kBlock) void k_var_outer_row(int n, TA ih2, const T
     const int y = yb * kWaves + wave;
     const int z0 = zc * nz;
     const size_t off = (size_t)(threadIdx.x & 63) * VEC;
-    double ss = 0.0;
+    double ss = 0.0, sb = 0.0, sp = 0.0;
     auto body = [&](const auto& src) {
         TA U[3][3][VEC];
         CQueue<TA, VEC> q;
@@ -452,9 +452,11 @@ __global__ __launch_bounds__(kBlock) void k_var_outer_row(int n, TA ih2, const T
             var19_row<ZQ, TA, TC, VEC>(U, q, C, N, g, y, z, off, ih2, Mu, D);
 #pragma unroll
             for (int q = 0; q < VEC; ++q) {
-                const TA ri = (TA)(bb[q] - bmean) - Mu[q];
+                const double bq = bb[q] - bmean;
+                const TA ri = (TA)bq - Mu[q];
                 ro[q] = (TR)ri;
                 ss += (double)ri * (double)ri;
+                sb += bq * bq;
             }
             strow<TR, VEC>(r + row, ro);
             if (x1) {
@@ -471,6 +473,13 @@ __global__ __launch_bounds__(kBlock) void k_var_outer_row(int n, TA ih2, const T
 #pragma unroll
                 for (int q = 0; q < VEC; ++q) po[q] = p[q] + (double)qv[q];
                 strow<double, VEC>(phi_out + row, po);
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) sp += po[q];
+            } else {
+                double p[VEC];
+                ldrow<double, VEC>(p, phi_in + row);
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) sp += p[q];
             }
             shift_queue<TA, VEC>(U);
             cq_shift<ZQ, TA, VEC>(q);
@@ -478,10 +487,23 @@ __global__ __launch_bounds__(kBlock) void k_var_outer_row(int n, TA ih2, const T
     };
     if constexpr (UPDATE) body(SumRows<TA, TE, VEC>{phi_in, e});
     else body(PlainRows<TA, double, VEC>{phi_in});
-    for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 64);
-    if ((threadIdx.x & 63) == 0) sh[wave] = ss;
+    // fixed-order block reduction of the three partial sums, arrays of gridDim.x:
+    // [0] sum (b - bmean)^2, [1] sum r^2, [2] sum phi
+    for (int o = 32; o > 0; o >>= 1) {
+        sb += __shfl_xor(sb, o, 64);
+        ss += __shfl_xor(ss, o, 64);
+        sp += __shfl_xor(sp, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sh[wave] = sb;
+        sh[kWaves + wave] = ss;
+        sh[2 * kWaves + wave] = sp;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) partials[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    if (threadIdx.x < 3) {
+        const double* t = sh + threadIdx.x * kWaves;
+        partials[threadIdx.x * gridDim.x + blockIdx.x] = (t[0] + t[1]) + (t[2] + t[3]);
+    }
 }
 
 void shape(int n, int& nz, int& nyb, int& blocks) {
