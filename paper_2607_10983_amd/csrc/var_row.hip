@@ -465,22 +465,25 @@ __global__ __launch_bounds__(kBlock) void k_var_outer_row(int n, TA ih2, const T
                 for (int q = 0; q < VEC; ++q) xo[q] = (TR)(c0 * (TA)ro[q] / D[q]);
                 strow<TR, VEC>(x1 + row, xo);
             }
-            if constexpr (UPDATE) {
-                double p[VEC], po[VEC];
+            // the row's value (phi or phi + e) in double: the queue's own row when
+            // TA is double, else read again
+            double po[VEC];
+            if constexpr (sizeof(TA) == sizeof(double)) {
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) po[q] = (double)U[1][1][q];
+            } else if constexpr (UPDATE) {
+                double p[VEC];
                 TE qv[VEC];
                 ldrow<double, VEC>(p, phi_in + row);
                 ldrow<TE, VEC>(qv, e + row);
 #pragma unroll
                 for (int q = 0; q < VEC; ++q) po[q] = p[q] + (double)qv[q];
-                strow<double, VEC>(phi_out + row, po);
-#pragma unroll
-                for (int q = 0; q < VEC; ++q) sp += po[q];
             } else {
-                double p[VEC];
-                ldrow<double, VEC>(p, phi_in + row);
-#pragma unroll
-                for (int q = 0; q < VEC; ++q) sp += p[q];
+                ldrow<double, VEC>(po, phi_in + row);
             }
+            if constexpr (UPDATE) strow<double, VEC>(phi_out + row, po);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) sp += po[q];
             shift_queue<TA, VEC>(U);
             cq_shift<ZQ, TA, VEC>(q);
         }
