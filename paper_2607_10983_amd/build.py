@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmg.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "flat_row.hip", "var_row.hip", "tail.hip", "pcg.hip", "readout.hip", "mg_api.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "flat_row.hip", "var_row.hip", "tail.hip", "visit.hip", "pcg.hip", "readout.hip", "mg_api.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -49,10 +49,10 @@ __global__ __launch_bounds__(kThreads) void k_smooth(int n, T ih2, const TC* __r
             }
             T xp = T(0);
             if constexpr (HASPREV) xp = xprev[i];
-            val = uc + a * (uc - xp) + c * (bi - Mu) / D;
+            // seven-point: c arrives as c / D (as in the row kernels)
+            val = C == nullptr ? step_pt<T>(uc, xp, bi, Mu, a, c) : uc + a * (uc - xp) + c * (bi - Mu) / D;
         } else {
-            const T D = C == nullptr ? dflat : var_diag<T, TC>(C, N, g, xi, yi, z, ih2);
-            val = c * bi / D;
+            val = C == nullptr ? c * bi : c * bi / var_diag<T, TC>(C, N, g, xi, yi, z, ih2);
         }
         out[i] = val;
     }
@@ -114,19 +114,12 @@ __global__ __launch_bounds__(kThreads) void k_restrict(int n, const T* __restric
     const int X = blockIdx.x * blockDim.x + threadIdx.x;
     const int Y = blockIdx.y * blockDim.y + threadIdx.y;
     const int Z0 = blockIdx.z * nz;
-    const T w1[3] = {T(0.25), T(0.5), T(0.25)};
     for (int Z = Z0; Z < Z0 + nz; ++Z) {
-        T acc = T(0);
-        for (int dz = -1; dz <= 1; ++dz) {
-            T accy = T(0);
-            for (int dy = -1; dy <= 1; ++dy) {
-                T accx = T(0);
-                for (int dx = -1; dx <= 1; ++dx) accx += w1[dx + 1] * fine[g(2 * X + dx, 2 * Y + dy, 2 * Z + dz)];
-                accy += w1[dy + 1] * accx;
-            }
-            acc += w1[dz + 1] * accy;
-        }
-        coarse[gc(X, Y, Z)] = acc;
+        T v[3][3][3];
+        for (int dz = 0; dz < 3; ++dz)
+            for (int dy = 0; dy < 3; ++dy)
+                for (int dx = 0; dx < 3; ++dx) v[dz][dy][dx] = fine[g(2 * X + dx - 1, 2 * Y + dy - 1, 2 * Z + dz - 1)];
+        coarse[gc(X, Y, Z)] = fw_pt<T>(v);
     }
 }
 
@@ -141,23 +134,12 @@ __global__ __launch_bounds__(kThreads) void k_prolong_add(int n, const T* __rest
     const int xi = blockIdx.x * blockDim.x + threadIdx.x;
     const int yi = blockIdx.y * blockDim.y + threadIdx.y;
     const int z0 = blockIdx.z * nz;
-    const int X = xi >> 1, Y = yi >> 1;
-    const int ox = xi & 1, oy = yi & 1;
+    auto ec = [&](int X, int Y, int Z) { return e[gc(X, Y, Z)]; };
     for (int z = z0; z < z0 + nz; ++z) {
-        const int Z = z >> 1, oz = z & 1;
         // interpolate along x on the (up to) 4 coarse lines, then y, then z
-        T vz[2];
-        for (int kz = 0; kz <= oz; ++kz) {
-            T vy[2];
-            for (int ky = 0; ky <= oy; ++ky) {
-                const T a0 = e[gc(X, Y + ky, Z + kz)];
-                vy[ky] = ox ? T(0.5) * (a0 + e[gc(X + 1, Y + ky, Z + kz)]) : a0;
-            }
-            vz[kz] = oy ? T(0.5) * (vy[0] + vy[1]) : vy[0];
-        }
-        const T p = oz ? T(0.5) * (vz[0] + vz[1]) : vz[0];
+        const T p = prolong_pt<T>(ec, xi, yi, z);
         const size_t i = g(xi, yi, z);
-        x[i] += p;
+        x[i] = add_pt<T>(x[i], p);
     }
 }
 
@@ -227,9 +209,9 @@ __global__ __launch_bounds__(kThreads) void k_outer_residual(int n, TA ih2, cons
         const double bq = b[i] - bmean;
         const TA ri = (TA)bq - Mu;
         r[i] = (TR)ri;
-        if (x1) {
-            if (C == nullptr) D = TA(-6) * ih2;
-            x1[i] = (TR)(c0 * (TA)(TR)ri / D);
+        if (x1) {  // first smoothing step from zero, rounded as the smoothing kernels round it
+            if (C == nullptr) x1[i] = (TR)c0 * (TR)ri;  // seven-point: c0 arrives as c0 / D
+            else x1[i] = (TR)(c0 * (TA)(TR)ri / D);
         }
         ss += (double)ri * (double)ri;
         sb += bq * bq;
@@ -610,6 +592,7 @@ hipError_t launch_smooth_step(const OpDesc<TC>& op, const T* x, const T* xprev, 
     if (op.coeff != nullptr && var_row_kernels_apply(op.n))
         return launch_var_smooth_row<T, TC>(op.n, op.ih2, op.coeff, x, xprev, b, out, a, c, s, ev0, ev1);
     Shape sh = stencil_shape(op.n);
+    if (op.coeff == nullptr) c = c / (-6.0 * op.ih2);  // the seven-point kernel takes c / D
     if (x == nullptr)
         MG_LAUNCH((k_smooth<T, TC, false, false>), sh.grid, sh.block, s, ev0, ev1, op.n, (T)op.ih2, op.coeff, x,
                            xprev, b, out, (T)a, (T)c, sh.nz);
@@ -688,6 +671,7 @@ hipError_t launch_outer_residual(const OpDesc<TC>& op, const double* phi_in, con
         return launch_var_outer_row<TA, TR, TE, TC>(op.n, op.ih2, op.coeff, phi_in, e, phi_out, b, bmean, r, x1, c0,
                                                     partials, s);
     Shape sh = stencil_shape(op.n);
+    if (op.coeff == nullptr) c0 = c0 / (-6.0 * op.ih2);
     if (e)
         hipLaunchKernelGGL((k_outer_residual<TA, TR, TE, TC, true>), sh.grid, sh.block, 0, s, op.n, (TA)op.ih2,
                            op.coeff, phi_in, e, phi_out, b, bmean, r, x1, (TA)c0, partials, sh.nz);

@@ -17,6 +17,9 @@
 #include "flat_row.h"
 #include "kernels.h"
 #include "tail.h"
+#include "visit.h"
+
+#include <type_traits>
 
 using namespace mg;
 
@@ -74,6 +77,7 @@ struct mg_ctx {
     int coarse_cur = 0;
     hipEvent_t norm_ev = nullptr;  // completion of the per-cycle norm readback
     bool use_pairs = true;         // last two steps of a smoothing pass in one two-step kernel
+    bool use_visits = true;        // fused visits of the 32^3 level (float hierarchy)
     // conjugate-gradient state (allocated by the first mg_solve_pcg)
     double* pcg_r = nullptr;
     double* pcg_p[2] = {nullptr, nullptr};
@@ -306,6 +310,14 @@ inline int other(int cur) { return cur == 0 ? 1 : 0; }
 // level 0 is not itself run by the tail kernel).
 inline bool x1_fusable(const mg_ctx* c) { return c->tail_start != 0 && c->lev.size() > 1; }
 
+// Level l (not the coarsest, not run by the tail kernel) is visited by the two
+// fused visit kernels: float hierarchy, seven-point operator, 32^3 points.
+inline bool visit_level(const mg_ctx* c, int l) {
+    return c->use_visits && !c->var && !c->inner_double && c->p.smoother == MG_CHEBYSHEV &&
+           l + 1 < (int)c->lev.size() && l != c->tail_start &&
+           visit_applies(c->lev[l].n, (int)c->lev[l].a.size());
+}
+
 // Level l runs its pass from zero as one three-step kernel (first step formed
 // from b on the fly): seven-point operator, two-step kernels available, and
 // at least three steps per pass.
@@ -488,6 +500,21 @@ mg_status vcycle_from_zero(mg_ctx* c, int l) {
     if (l == last) return coarse_level<T>(c, l);
     Level& L = c->lev[l];
     Level& Lc = c->lev[l + 1];
+    if constexpr (std::is_same<T, float>::value) {
+        if (visit_level(c, l)) {  // two launches for the whole visit of the 32^3 level
+            const int v = (int)L.a.size();
+            if (l == 0) c->x1_ready = false;
+            HIPCHK(c, launch_visit_pre(L.n, L.ih2, (const float*)L.b, (float*)L.x[0], (float*)Lc.b, L.a.data(),
+                                       L.c.data(), v, c->stream));
+            L.cur = 0;
+            mg_status st = vcycle_from_zero<T>(c, l + 1);
+            if (st != MG_OK) return st;
+            HIPCHK(c, launch_visit_post(L.n, L.ih2, (const float*)L.x[0], (const float*)Lc.x[Lc.cur],
+                                        (const float*)L.b, (float*)L.x[1], L.a.data(), L.c.data(), v, c->stream));
+            L.cur = 1;
+            return MG_OK;
+        }
+    }
     mg_status st = smooth_level<T>(c, l, true);
     if (st != MG_OK) return st;
     // the buffer of the previous iterate is free here and serves as residual scratch
@@ -508,7 +535,7 @@ mg_status outer_residual(mg_ctx* c, const double* phi_in, const void* e, double*
     Level& L = c->lev[0];
     const int n = L.n;
     const double ih2 = L.ih2;
-    const bool x1 = next_cycle && x1_fusable(c) && !from_zero_triple(c, 0);
+    const bool x1 = next_cycle && x1_fusable(c) && !from_zero_triple(c, 0) && !visit_level(c, 0);
     const double c0 = L.c.empty() ? 0.0 : L.c[0];
     // x1 goes to a buffer other than the one holding e (the previous cycle's result)
     const int xb = other(L.cur);
@@ -661,6 +688,7 @@ static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype, cons
     if (const char* t = std::getenv("MG_PAIR_PREFETCH")) set_pair_prefetch(std::atoi(t));
     // two-step smoothing kernels; MG_NO_PAIR keeps every step a kernel of its own
     c->use_pairs = std::getenv("MG_NO_PAIR") == nullptr;
+    c->use_visits = std::getenv("MG_NO_VISIT") == nullptr;
     c->lev.resize(p.levels);
     for (int l = 0; l < p.levels; ++l) {
         Level& L = c->lev[l];

@@ -69,11 +69,76 @@ struct PlusE {  // phi + e, formed in double
 // ---- operators -------------------------------------------------------------------
 // Seven-point Laplacian: (sum of the six neighbours - 6 u) / h^2.
 template <typename T, typename F>
+__device__ __forceinline__ T flat_Mu(const F& u, const Grid& g, int x, int y, int z, T uc, T ih2);
+
+// ---- point formulas with their rounding written out ------------------------------
+// Every seven-point kernel (row kernels, generic column kernels, fused level
+// visits) evaluates the stencil, the smoothing step, full weighting and the
+// prolongation through these, with no contraction left to the compiler, so
+// that fused and unfused paths produce the same bits.
+
+// (sum of the six neighbours - 6 c) / h^2
+template <typename T>
+__device__ __forceinline__ T flat7_pt(T xm, T xp, T ym, T yp, T zm, T zp, T c, T ih2) {
+#pragma clang fp contract(off)
+    const T s = ((xm + xp) + (ym + yp)) + (zm + zp);
+    return __builtin_fma(T(-6), c, s) * ih2;
+}
+
+// one smoothing step x + a (x - xp) + cd (b - M x), cd = c / D
+template <typename T>
+__device__ __forceinline__ T step_pt(T x, T xp, T b, T Mx, T a, T cd) {
+#pragma clang fp contract(off)
+    return __builtin_fma(cd, b - Mx, __builtin_fma(a, x - xp, x));
+}
+
+// full weighting of the 27 fine values v[dz][dy][dx] (offsets -1, 0, 1)
+template <typename T>
+__device__ __forceinline__ T fw_pt(const T (&v)[3][3][3]) {
+#pragma clang fp contract(off)
+    const T w1[3] = {T(0.25), T(0.5), T(0.25)};
+    T acc = T(0);
+    for (int dz = 0; dz < 3; ++dz) {
+        T accy = T(0);
+        for (int dy = 0; dy < 3; ++dy) {
+            T accx = T(0);
+            for (int dx = 0; dx < 3; ++dx) accx += w1[dx] * v[dz][dy][dx];
+            accy += w1[dy] * accx;
+        }
+        acc += w1[dz] * accy;
+    }
+    return acc;
+}
+
+// trilinear prolongation at fine point (x, y, z) of the coarse field read by
+// ec(X, Y, Z) (periodic indices)
+template <typename T, typename E>
+__device__ __forceinline__ T prolong_pt(const E& ec, int x, int y, int z) {
+#pragma clang fp contract(off)
+    const int X = x >> 1, Y = y >> 1, Z = z >> 1;
+    const int ox = x & 1, oy = y & 1, oz = z & 1;
+    T vz[2];
+    for (int kz = 0; kz <= oz; ++kz) {
+        T vy[2];
+        for (int ky = 0; ky <= oy; ++ky) {
+            const T a0 = ec(X, Y + ky, Z + kz);
+            vy[ky] = ox ? T(0.5) * (a0 + ec(X + 1, Y + ky, Z + kz)) : a0;
+        }
+        vz[kz] = oy ? T(0.5) * (vy[0] + vy[1]) : vy[0];
+    }
+    return oz ? T(0.5) * (vz[0] + vz[1]) : vz[0];
+}
+
+template <typename T>
+__device__ __forceinline__ T add_pt(T x, T p) {
+#pragma clang fp contract(off)
+    return x + p;
+}
+
+template <typename T, typename F>
 __device__ __forceinline__ T flat_Mu(const F& u, const Grid& g, int x, int y, int z, T uc, T ih2) {
-    T s = u(g(x - 1, y, z)) + u(g(x + 1, y, z));
-    s += u(g(x, y - 1, z)) + u(g(x, y + 1, z));
-    s += u(g(x, y, z - 1)) + u(g(x, y, z + 1));
-    return (s - T(6) * uc) * ih2;
+    return flat7_pt<T>(u(g(x - 1, y, z)), u(g(x + 1, y, z)), u(g(x, y - 1, z)), u(g(x, y + 1, z)),
+                       u(g(x, y, z - 1)), u(g(x, y, z + 1)), uc, ih2);
 }
 
 // Flux-form operator: face-averaged diagonal coefficients times compact

@@ -1,0 +1,218 @@
+// Fused level visits for the 32^3 level of the seven-point hierarchy.
+//
+// On a 32^3 level every kernel of a V-cycle visit is far too small to fill the
+// chip, and the visit costs its launch latencies (nine launches).  Here the
+// visit takes two launches.  Each workgroup (1024 threads, one per (x, y)
+// point of a 32 x 32 plane) owns one coarse plane Z, i.e. fine planes 2Z and
+// 2Z + 1, and recomputes what it needs of the neighbouring planes (a halo of
+// v + 1 planes shrinking by one per step), all of it in LDS:
+//
+//   pre:  x_1 = c_0 D^-1 b (pointwise), v - 1 further steps, r = b - M x_v,
+//         coarse rhs = R r; writes x_v on the owned planes and the coarse plane;
+//   post: x_0 = x + P e, v steps; writes x_v on the owned planes.
+//
+// This is the paper's fused wide-halo level visit (one exchange per visit
+// instead of one per step), used here to save launches instead of exchanges.
+// Every point formula is the shared one of the unfused kernels (stencil.h), so
+// the result is bitwise that of the separate smoothing, residual, restriction
+// and prolongation kernels.
+#include "visit.h"
+
+#include "stencil.h"
+
+namespace mg {
+namespace {
+
+constexpr int kN = 32;                // points per side
+constexpr int kP = kN * kN;           // points per plane = threads per workgroup
+constexpr int kMaxDeg = kVisitMaxDegree;
+constexpr int kPrePlanes = 2 * kMaxDeg + 3;   // planes of x_1 in the pre visit
+// b and three rotating iterate stacks of kPrePlanes planes: 144 KB of the 160 KB
+// a gfx950 workgroup may use
+constexpr int kLdsFloats = 4 * kPrePlanes * kP;
+
+struct VisitCoef {
+    float a[kMaxDeg], cd[kMaxDeg];  // step k: x + a_k (x - x_prev) + cd_k (b - M x)
+};
+
+__device__ __forceinline__ int wrap(int i) { return i & (kN - 1); }
+
+// seven-point stencil at (x, y) of plane p of an LDS stack of planes
+__device__ __forceinline__ float M_at(const float* st, int p, int x, int y, float ih2) {
+    const float* c = st + p * kP;
+    const float* m = c - kP;
+    const float* q = c + kP;
+    return flat7_pt<float>(c[y * kN + wrap(x - 1)], c[y * kN + wrap(x + 1)], c[wrap(y - 1) * kN + x],
+                           c[wrap(y + 1) * kN + x], m[y * kN + x], q[y * kN + x], c[y * kN + x], ih2);
+}
+
+// Plane stacks: every stack holds the planes [lo, lo + NP) of a field, and
+// the three iterate stacks rotate so that x_k, x_{k-1} and a free one are at
+// hand.  V (the step count) is a template parameter so that every plane loop
+// unrolls and the global loads of the staging loops are all in flight at once.
+template <int V>
+__global__ __launch_bounds__(kP) void k_visit_pre(const float* __restrict__ b, float* __restrict__ xout,
+                                                  float* __restrict__ coarse_b, float ih2, VisitCoef coef) {
+    constexpr int NP = 2 * V + 3;  // planes of x_1: z0 - 1 - V .. z0 + 1 + V
+    __shared__ float lds[kLdsFloats];
+    const int t = threadIdx.x;
+    const int x = t & (kN - 1), y = t >> 5;
+    const int Z = blockIdx.x;
+    const int z0 = 2 * Z;
+    const int lo = z0 - 1 - V;
+    float* sb = lds;  // b on the x_1 planes
+    float* buf[3] = {lds + NP * kP, lds + 2 * NP * kP, lds + 3 * NP * kP};
+    // b and x_1 = c_0 D^-1 b on every plane of the stack
+    float bv[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) bv[p] = b[(size_t)wrap(lo + p) * kP + t];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        sb[p * kP + t] = bv[p];
+        buf[0][p * kP + t] = coef.cd[0] * bv[p];
+    }
+    __syncthreads();
+    // step k makes x_{k+1} on planes lo + k .. z0 + 1 + V - k (one fewer per side each step)
+    int cur = 0, prv = -1;
+#pragma unroll
+    for (int k = 1; k < V; ++k) {
+        const int out = prv >= 0 ? prv : 1;
+#pragma unroll
+        for (int p = k; p <= NP - 1 - k; ++p) {
+            const float xc = buf[cur][p * kP + t];
+            const float xp = prv >= 0 ? buf[prv][p * kP + t] : 0.0f;
+            const float Mx = M_at(buf[cur], p, x, y, ih2);
+            buf[out][p * kP + t] = step_pt<float>(xc, xp, sb[p * kP + t], Mx, coef.a[k], coef.cd[k]);
+        }
+        __syncthreads();
+        prv = cur;
+        cur = out;
+    }
+    // residual on planes z0 - 1 .. z0 + 1 (stack planes V .. V + 2) into the free buffer
+    const int rb = prv >= 0 ? 3 - cur - prv : 1;
+#pragma unroll
+    for (int p = V; p <= V + 2; ++p) buf[rb][p * kP + t] = sb[p * kP + t] - M_at(buf[cur], p, x, y, ih2);
+    // the smoothed iterate on the owned planes
+#pragma unroll
+    for (int p = V + 1; p <= V + 2; ++p) xout[(size_t)(lo + p) * kP + t] = buf[cur][p * kP + t];
+    __syncthreads();
+    // full weighting onto coarse plane Z (16 x 16 points)
+    if (t < kP / 4) {
+        const int X = t & (kN / 2 - 1), Y = t >> 4;
+        float vv[3][3][3];
+#pragma unroll
+        for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx)
+                    vv[dz][dy][dx] = buf[rb][(V + dz) * kP + wrap(2 * Y + dy - 1) * kN + wrap(2 * X + dx - 1)];
+        coarse_b[(size_t)Z * (kP / 4) + t] = fw_pt<float>(vv);
+    }
+}
+
+template <int V>
+__global__ __launch_bounds__(kP) void k_visit_post(const float* __restrict__ xin, const float* __restrict__ e,
+                                                   const float* __restrict__ b, float* __restrict__ xout, float ih2,
+                                                   VisitCoef coef) {
+    constexpr int NP = 2 * V + 2;              // planes of x_0: z0 - V .. z0 + 1 + V
+    constexpr int NC = 2 * ((V + 1) / 2) + 2;  // coarse planes the prolongation reads
+    constexpr int nc = kN / 2, pc = nc * nc;
+    __shared__ float lds[kLdsFloats];
+    const int t = threadIdx.x;
+    const int x = t & (kN - 1), y = t >> 5;
+    const int Z = blockIdx.x;
+    const int z0 = 2 * Z;
+    const int lo = z0 - V;
+    const int zlo = Z - (V + 1) / 2;  // first staged coarse plane
+    float* sb = lds;
+    float* buf[3] = {lds + NP * kP, lds + 2 * NP * kP, lds + 3 * NP * kP};
+    float* se = lds + 4 * NP * kP;  // coarse planes zlo .. zlo + NC - 1
+    static_assert(4 * NP * kP + NC * pc <= kLdsFloats, "post visit stacks exceed LDS");
+    float bv[NP], xv[NP], ev[(NC * pc + kP - 1) / kP];
+#pragma unroll
+    for (int j = 0; j < (NC * pc + kP - 1) / kP; ++j) {
+        const int q = j * kP + t;
+        ev[j] = q < NC * pc ? e[(size_t)((zlo + q / pc) & (nc - 1)) * pc + (q % pc)] : 0.0f;
+    }
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        bv[p] = b[(size_t)wrap(lo + p) * kP + t];
+        xv[p] = xin[(size_t)wrap(lo + p) * kP + t];
+    }
+#pragma unroll
+    for (int j = 0; j < (NC * pc + kP - 1) / kP; ++j)
+        if (j * kP + t < NC * pc) se[j * kP + t] = ev[j];
+    __syncthreads();
+    // coarse value at periodic (X, Y, Zc); Zc is unwrapped, within the staged planes
+    auto ec = [&](int X, int Y, int Zc) { return se[(Zc - zlo) * pc + (Y & (nc - 1)) * nc + (X & (nc - 1))]; };
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        sb[p * kP + t] = bv[p];
+        buf[0][p * kP + t] = add_pt<float>(xv[p], prolong_pt<float>(ec, x, y, lo + p));
+    }
+    __syncthreads();
+    int cur = 0, prv = -1;
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        const int out = prv >= 0 ? prv : 1;
+#pragma unroll
+        for (int p = k + 1; p <= NP - 2 - k; ++p) {
+            const float xc = buf[cur][p * kP + t];
+            const float xp = prv >= 0 ? buf[prv][p * kP + t] : 0.0f;
+            const float Mx = M_at(buf[cur], p, x, y, ih2);
+            buf[out][p * kP + t] = step_pt<float>(xc, xp, sb[p * kP + t], Mx, coef.a[k], coef.cd[k]);
+        }
+        __syncthreads();
+        prv = cur;
+        cur = out;
+    }
+#pragma unroll
+    for (int p = V; p <= V + 1; ++p) xout[(size_t)(lo + p) * kP + t] = buf[cur][p * kP + t];
+}
+
+// step coefficients in the kernels' precision, c_k / D rounded as in the
+// single-step launches
+VisitCoef visit_coef(double ih2, const double* a, const double* c, int degree) {
+    VisitCoef coef{};
+    const double D = -6.0 * ih2;
+    for (int k = 0; k < degree; ++k) {
+        coef.a[k] = (float)a[k];
+        coef.cd[k] = (float)(c[k] / D);
+    }
+    return coef;
+}
+
+}  // namespace
+
+bool visit_applies(int n, int degree) { return n == kN && degree >= 1 && degree <= kMaxDeg; }
+
+hipError_t launch_visit_pre(int n, double ih2, const float* b, float* xout, float* coarse_b, const double* a,
+                            const double* c, int degree, hipStream_t s) {
+    if (!visit_applies(n, degree)) return hipErrorInvalidValue;
+    const VisitCoef coef = visit_coef(ih2, a, c, degree);
+    const dim3 grid(kN / 2), block(kP);
+    const float fih2 = (float)ih2;
+    switch (degree) {
+    case 1: hipLaunchKernelGGL(k_visit_pre<1>, grid, block, 0, s, b, xout, coarse_b, fih2, coef); break;
+    case 2: hipLaunchKernelGGL(k_visit_pre<2>, grid, block, 0, s, b, xout, coarse_b, fih2, coef); break;
+    default: hipLaunchKernelGGL(k_visit_pre<3>, grid, block, 0, s, b, xout, coarse_b, fih2, coef); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_visit_post(int n, double ih2, const float* xin, const float* e, const float* b, float* xout,
+                             const double* a, const double* c, int degree, hipStream_t s) {
+    if (!visit_applies(n, degree) || xout == xin) return hipErrorInvalidValue;
+    const VisitCoef coef = visit_coef(ih2, a, c, degree);
+    const dim3 grid(kN / 2), block(kP);
+    const float fih2 = (float)ih2;
+    switch (degree) {
+    case 1: hipLaunchKernelGGL(k_visit_post<1>, grid, block, 0, s, xin, e, b, xout, fih2, coef); break;
+    case 2: hipLaunchKernelGGL(k_visit_post<2>, grid, block, 0, s, xin, e, b, xout, fih2, coef); break;
+    default: hipLaunchKernelGGL(k_visit_post<3>, grid, block, 0, s, xin, e, b, xout, fih2, coef); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mg

@@ -439,3 +439,25 @@ def test_two_step_kernel_matches_single_steps(mgpu, monkeypatch, n, prec, degree
     (ps, is_), (pf, if_) = out
     assert is_.cycles == if_.cycles and is_.history == if_.history
     assert torch.equal(ps, pf)
+
+
+@pytest.mark.parametrize("n,levels", [(32, 4), (32, 2), (64, 5), (256, 7)])
+@pytest.mark.parametrize("degree", [1, 2, 3])
+def test_level_visit_matches_unfused(mgpu, monkeypatch, n, levels, degree):
+    """The fused visit of the 32^3 level (smoothing from zero, residual and
+    full weighting in one launch; prolongation and smoothing in another) uses
+    the point formulas of the separate kernels: mixed-precision solves agree
+    bitwise with MG_NO_VISIT, cycle by cycle."""
+    b = dev(flat_source(n, 5))
+    kw = dict(levels=levels, degree=degree, precision="mixed")
+    monkeypatch.setenv("MG_NO_VISIT", "1")
+    plain = mgpu.Multigrid(n, **kw)
+    monkeypatch.delenv("MG_NO_VISIT")
+    fused = mgpu.Multigrid(n, **kw)
+    out = []
+    for mg in (plain, fused):
+        phi, info = mg.solve(b, tol=1e-10, max_cycles=10, raise_on_error=False)
+        out.append((phi, info))
+    (pp, ip), (pf, if_) = out
+    assert ip.cycles == if_.cycles and ip.history == if_.history
+    assert torch.equal(pp, pf)
