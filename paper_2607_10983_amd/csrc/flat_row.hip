@@ -13,6 +13,7 @@
 // and share their halo rows through that XCD's L2.
 #include "flat_row.h"
 
+#include "fma.h"
 #include "launch.h"
 
 #include <cstdint>
@@ -93,7 +94,7 @@ __device__ __forceinline__ void flat7_row(const T (&c)[VEC], const T (&ym)[VEC],
         const T l = e > 0 ? c[e - 1] : lft;
         const T r = e < VEC - 1 ? c[e + 1] : rgt;
         const T s = ((l + r) + (ym[e] + yp[e])) + (zm[e] + zp[e]);
-        Mx[e] = __builtin_fma(T(-6), c[e], s) * ih2;
+        Mx[e] = fma_rn(T(-6), c[e], s) * ih2;
     }
 }
 
@@ -101,7 +102,7 @@ __device__ __forceinline__ void flat7_row(const T (&c)[VEC], const T (&ym)[VEC],
 template <typename T>
 __device__ __forceinline__ T cheb_step(T x, T xp, T b, T Mx, T a, T cd) {
 #pragma clang fp contract(off)
-    return __builtin_fma(cd, b - Mx, __builtin_fma(a, x - xp, x));
+    return fma_rn(cd, b - Mx, fma_rn(a, x - xp, x));
 }
 
 // Block id renumbering so that each XCD (blocks are dealt round-robin to the

@@ -4,6 +4,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "fma.h"
+
 #include <cstddef>
 
 namespace mg {
@@ -82,14 +84,14 @@ template <typename T>
 __device__ __forceinline__ T flat7_pt(T xm, T xp, T ym, T yp, T zm, T zp, T c, T ih2) {
 #pragma clang fp contract(off)
     const T s = ((xm + xp) + (ym + yp)) + (zm + zp);
-    return __builtin_fma(T(-6), c, s) * ih2;
+    return fma_rn(T(-6), c, s) * ih2;
 }
 
 // one smoothing step x + a (x - xp) + cd (b - M x), cd = c / D
 template <typename T>
 __device__ __forceinline__ T step_pt(T x, T xp, T b, T Mx, T a, T cd) {
 #pragma clang fp contract(off)
-    return __builtin_fma(cd, b - Mx, __builtin_fma(a, x - xp, x));
+    return fma_rn(cd, b - Mx, fma_rn(a, x - xp, x));
 }
 
 // full weighting of the 27 fine values v[dz][dy][dx] (offsets -1, 0, 1)
