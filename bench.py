@@ -40,14 +40,14 @@ HBM_PEAK_GBPS = 8000.0
 # 1.0 (write), averaged over the launches of one V-cycle.  Reported only while
 # the device code of the row kernels is the code the counters were taken on.
 TRAFFIC = {
-    "device_code_sha256": "907bc4031a085762294b61d905e548950714131cab566115b009772655122d07",
+    "device_code_sha256": "eda75e3472ad1488e7e9b51df5e38abee893afc9f2ef560281fd3f88ed36e71d",
     "n": 256,
     "degree": 3,
     "bytes_per_launch": {
         # pre-smoothing from zero (b -> x3) and post-smoothing pair (x, x_prev, b -> y2)
-        "k_smooth2_lds": ((73.6 + 64.0) + (229.7 + 64.0)) / 2 * 1024 * 1024,
+        "k_smooth2_lds": ((74.2 + 64.0) + (232.7 + 64.0)) / 2 * 1024 * 1024,
         # the one remaining fine single step (x, b -> out)
-        "k_smooth_row": (132.5 + 64.0) * 1024 * 1024,
+        "k_smooth_row": (132.1 + 64.0) * 1024 * 1024,
     },
 }
 

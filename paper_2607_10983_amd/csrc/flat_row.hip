@@ -402,7 +402,7 @@ __device__ __forceinline__ T first_step(T r, T cd0) {
     return r;
 }
 
-template <typename T, int VEC, int NW, bool PREV1, bool Y1OUT, bool FROMB = false, bool PF2 = false>
+template <typename T, int VEC, int NW, bool PREV1, bool Y1OUT, bool FROMB = false, bool PF2 = false, int NZC = 0>
 __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* __restrict__ x,
                                                          const T* __restrict__ xp, const T* __restrict__ b,
                                                          T* __restrict__ y2, T* __restrict__ y1o, T a1, T cd1, T a2,
@@ -436,7 +436,11 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
     ldrow<T, VEC>(yp, src + g.row(y + 1, z1) + off);
     if constexpr (!FROMB) ldrow<T, VEC>(b1, b + g.row(y, z1) + off);
     if constexpr (PREV1) ldrow<T, VEC>(p1, xp + g.row(y, z1) + off);
-    const int steps = nz + 2;
+    // NZC > 0: the chunk height is a compile-time constant and the plane loop
+    // unrolls completely, so the row queues are renamed instead of copied and
+    // each prefetched row is waited for where it is first used, not at the end
+    // of the iteration that issued it.
+    const int steps = (NZC > 0 ? NZC : nz) + 2;
     // PF2: operands of the plane after next are loaded one iteration earlier
     // (a second register set), i.e. two planes ahead of their use
     T xa[VEC], yma[VEC], ypa[VEC], ba[VEC], pa[VEC];
@@ -447,7 +451,7 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
         if constexpr (!FROMB) ldrow<T, VEC>(ba, b + g.row(y, z1 + 1) + off);
         if constexpr (PREV1) ldrow<T, VEC>(pa, xp + g.row(y, z1 + 1) + off);
     }
-    for (int j = 0; j < steps; ++j, ++z1) {
+    auto plane = [&](const int j) {
         const bool more = j + 1 < steps;
         const int ahead = PF2 ? 1 : 0;  // the loads below are for plane z1 + 1 + ahead
         const bool load = j + 1 + ahead < steps;
@@ -527,6 +531,12 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
                 if constexpr (PREV1) copyrow(p1, pn);
             }
         }
+    };
+    if constexpr (NZC > 0) {
+#pragma unroll
+        for (int j = 0; j < NZC + 2; ++j, ++z1) plane(j);
+    } else {
+        for (int j = 0; j < steps; ++j, ++z1) plane(j);
     }
 }
 
@@ -908,6 +918,7 @@ hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, cons
 // 37.7 vs 38.0 ms), 12 or 16 selectable for measurement.
 constexpr int kPairWaves = 16;  // the largest block (LDS and register budget checks)
 constexpr size_t kPairLdsBudget = 64 * 1024;
+constexpr int kPairUnrollNz = 8;  // chunk height of the fully unrolled two-step variant
 int g_pair_nz = 0;  // z chunk of the two-step kernel; 0 = chosen from n
 int g_pair_waves = 8;
 // Prefetch depth of the two-step kernel: -1 = by row size (two planes ahead
@@ -915,6 +926,7 @@ int g_pair_waves = 8;
 // launch; one plane for smaller rows, where the extra registers cost
 // occupancy: 256^3 float 53 -> 61 us), 0 / 1 = one / two planes.
 int g_pair_pf2 = -1;
+bool g_pair_unroll = true;  // fully unrolled variant for chunks of kPairUnrollNz planes
 
 // Largest row (bytes) whose two-step kernel fits a wave's registers without
 // spilling: 8-wave blocks leave a wave 256 VGPRs (float n <= 512, double
@@ -932,18 +944,20 @@ void set_pair_nz(int nz) {
 void set_pair_waves(int waves) {
     if (waves == 8 || waves == 12 || waves == 16) g_pair_waves = waves;
 }
+void set_pair_unroll(bool on) { g_pair_unroll = on; }
 void set_pair_prefetch(int planes) {
     if (planes == 1 || planes == 2) g_pair_pf2 = planes == 2 ? 1 : 0;
 }
 
 // launch of one k_smooth2_lds variant inside launch_pair_nw (VEC from DISPATCH_VEC)
-#define MG_PAIR1(PREV1, Y1OUT, FROMB, PF2)                                                                      \
-    MG_LAUNCH((k_smooth2_lds<T, VEC, NW, PREV1, Y1OUT, FROMB, PF2>), dim3(blocks), dim3(64 * NW), s, ev0, ev1, \
+#define MG_PAIR1(PREV1, Y1OUT, FROMB, PF2, NZC)                                                                 \
+    MG_LAUNCH((k_smooth2_lds<T, VEC, NW, PREV1, Y1OUT, FROMB, PF2, NZC>), dim3(blocks), dim3(64 * NW), s, ev0, ev1, \
               n, (T)ih2, x, xp, b, y2, y1, (T)a1, (T)cd1, (T)a2, (T)cd2, nz, nyb, (T)cd0)
-#define MG_PAIR(PREV1, Y1OUT, FROMB)                  \
-    do {                                              \
-        if (pf2) MG_PAIR1(PREV1, Y1OUT, FROMB, true);  \
-        else MG_PAIR1(PREV1, Y1OUT, FROMB, false);    \
+#define MG_PAIR(PREV1, Y1OUT, FROMB)                                          \
+    do {                                                                      \
+        if (pf2) MG_PAIR1(PREV1, Y1OUT, FROMB, true, 0);                      \
+        else if (g_pair_unroll && nz == kPairUnrollNz) MG_PAIR1(PREV1, Y1OUT, FROMB, false, kPairUnrollNz); \
+        else MG_PAIR1(PREV1, Y1OUT, FROMB, false, 0);                         \
     } while (0)
 
 template <typename T, int NW>
