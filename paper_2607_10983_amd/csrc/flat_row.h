@@ -11,6 +11,7 @@ bool row_kernels_apply(int n);
 int row_outer_blocks(int n, bool double_arith);
 // Tuning knob: target number of blocks per launch (default 8192).
 void set_row_target_blocks(int target);
+void set_small_nz(int nz, int pair_nz);
 
 template <typename T>
 hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, const T* b, T* out, double a,

@@ -683,6 +683,8 @@ static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype, cons
         return fail(c, MG_ERR_INVALID, "variable-coefficient coarsest level must have at most 8^3 points");
     const size_t Tsz = c->inner_double ? sizeof(double) : sizeof(float);
     if (const char* t = std::getenv("MG_ROW_TARGET_BLOCKS")) set_row_target_blocks(std::atoi(t));
+    if (const char* t = std::getenv("MG_SMALL_NZ")) set_small_nz(std::atoi(t), -1);
+    if (const char* t = std::getenv("MG_PAIR_SMALL_NZ")) set_small_nz(-1, std::atoi(t));
     if (const char* t = std::getenv("MG_PAIR_NZ")) set_pair_nz(std::atoi(t));
     if (const char* t = std::getenv("MG_PAIR_WAVES")) set_pair_waves(std::atoi(t));
     if (const char* t = std::getenv("MG_PAIR_PREFETCH")) set_pair_prefetch(std::atoi(t));
