@@ -73,9 +73,11 @@ hipError_t launch_outer_residual(const OpDesc<TC>& op, const double* phi_in, con
 // partials[block] = sum over the block of (u - shift)^p, p in {1, 2}.
 hipError_t launch_block_sums(int n, const double* u, double shift, int p, double* partials,
                              hipStream_t s);
-// out[slot + k] = sum_{i < count} partials[k * count + i], k < arrays (one block).
+// out[slot + k] = sum_{i < count} partials[k * count + i], k < arrays (one block);
+// also into host_out[slot + k] (pinned host memory, visible to the host once an
+// event recorded after the launch has completed) when host_out is not null.
 hipError_t launch_finalize_sums(const double* partials, int count, int arrays, double* out, int slot,
-                                hipStream_t s);
+                                hipStream_t s, double* host_out = nullptr);
 // out[slot] = sum_{i < count} partials[i] in a fixed order (one block).
 hipError_t launch_finalize_sum(const double* partials, int count, double* out, int slot,
                                hipStream_t s);

@@ -720,7 +720,8 @@ static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype, cons
         if ((st = dalloc(c, (void**)&c->partials, 3 * (size_t)np * sizeof(double))) != MG_OK) return st;
     }
     if ((st = dalloc(c, (void**)&c->dscal, 16 * sizeof(double))) != MG_OK) return st;
-    HIPCHK(c, hipHostMalloc((void**)&c->hscal, 16 * sizeof(double), hipHostMallocDefault));
+    // coherent: the finalize kernel writes the outer sums into it directly
+    HIPCHK(c, hipHostMalloc((void**)&c->hscal, 16 * sizeof(double), hipHostMallocCoherent));
     HIPCHK(c, hipEventCreateWithFlags(&c->norm_ev, hipEventDisableTiming));
 
     if (c->var) {
@@ -902,6 +903,20 @@ static mg_status post_scalars(mg_ctx* c, int count) {
     HIPCHK(c, hipEventRecord(c->norm_ev, c->stream));
     return MG_OK;
 }
+// The three outer sums (slots 1..3), finalized straight into the pinned host
+// mirror as well; the event marks when the host may read them.
+static mg_status post_outer_sums(mg_ctx* c) {
+    HIPCHK(c, launch_finalize_sums(c->partials, c->nparts_outer, 3, c->dscal, 1, c->stream, c->hscal));
+    HIPCHK(c, hipEventRecord(c->norm_ev, c->stream));
+    return MG_OK;
+}
+// Outer residual of the solve loop and its three sums.
+static mg_status outer_with_sums(mg_ctx* c, const double* phi_in, const void* e, double* phi_out, const double* b,
+                                 double bmean) {
+    mg_status st = outer_residual(c, phi_in, e, phi_out, b, bmean, true);
+    if (st != MG_OK) return st;
+    return post_outer_sums(c);
+}
 static mg_status wait_scalars(mg_ctx* c) {
     HIPCHK(c, hipEventSynchronize(c->norm_ev));
     return MG_OK;
@@ -917,9 +932,7 @@ static mg_status solve_impl(mg_ctx* c, double* phi, const double* b, double tol,
     const double bmean = c->hscal[0] * invN;
     if (!std::isfinite(bmean)) return fail(c, MG_ERR_NONFINITE, "source contains NaN or Inf");
     // the outer kernel also sums (b - bmean)^2 (slot 1) and phi (slot 3) beside r^2 (slot 2)
-    if ((st = outer_residual(c, phi, nullptr, nullptr, b, bmean, true)) != MG_OK) return st;
-    HIPCHK(c, launch_finalize_sums(c->partials, c->nparts_outer, 3, c->dscal, 1, c->stream));
-    if ((st = post_scalars(c, 4)) != MG_OK) return st;
+    if ((st = outer_with_sums(c, phi, nullptr, nullptr, b, bmean)) != MG_OK) return st;
     // Look-ahead: the next V-cycle depends only on device data (the residual
     // just formed), so it is enqueued before the host waits for the norm; it
     // is skipped when the measured contraction predicts convergence.  A
@@ -957,10 +970,8 @@ static mg_status solve_impl(mg_ctx* c, double* phi, const double* b, double tol,
     mg_status result = MG_OK;
     while (rel > tol && cycles < max_cycles) {
         if (!ahead && (st = inner_vcycle(c)) != MG_OK) return st;
-        if ((st = outer_residual(c, cur, inner_e(c), other, b, bmean, true)) != MG_OK) return st;
-        HIPCHK(c, launch_finalize_sums(c->partials, c->nparts_outer, 3, c->dscal, 1, c->stream));
+        if ((st = outer_with_sums(c, cur, inner_e(c), other, b, bmean)) != MG_OK) return st;
         std::swap(cur, other);
-        if ((st = post_scalars(c, 4)) != MG_OK) return st;
         ahead = cycles + 1 < max_cycles && rho * rel > tol;
         if (ahead && (st = inner_vcycle(c)) != MG_OK) return st;
         if ((st = wait_scalars(c)) != MG_OK) return st;
