@@ -18,41 +18,53 @@ namespace {
 
 constexpr int kTailThreads = 1024;
 
-constexpr int kMaxPts = 4;  // 16^3 points / 1024 threads
+// Level geometry as compile-time constants: the tail's levels have 16^3, 8^3
+// or 4^3 points, and with the sizes fixed every neighbour index reduces to a
+// few masks and the per-thread point loops unroll.
+template <int N>
+struct Geo {
+    static constexpr int n = N;
+    static constexpr int lg = N == 16 ? 4 : N == 8 ? 3 : 2;
+    static constexpr int P = N * N * N;
+    static constexpr int m = N - 1;
+    static constexpr int pts = (P + kTailThreads - 1) / kTailThreads;  // points per thread
+    static_assert(N == 4 || N == 8 || N == 16, "tail levels have 4^3, 8^3 or 16^3 points");
+    __device__ static __forceinline__ void coords(int i, int& x, int& y, int& z) {
+        x = i & m;
+        y = (i >> lg) & m;
+        z = i >> (2 * lg);
+    }
+    __device__ static __forceinline__ int at(int x, int y, int z) {
+        return ((((z & m) << lg) | (y & m)) << lg) | (x & m);
+    }
+};
 
-__device__ __forceinline__ void coords(int i, int n, int lg, int& x, int& y, int& z) {
-    x = i & (n - 1);
-    y = (i >> lg) & (n - 1);
-    z = i >> (2 * lg);
-}
-__device__ __forceinline__ int at(int x, int y, int z, int n, int lg) {
-    const int m = n - 1;
-    return ((((z & m) << lg) | (y & m)) << lg) | (x & m);
-}
-
-template <typename T>
-__device__ __forceinline__ T Mx_at(const T* u, int x, int y, int z, int n, int lg, T ih2) {
-    const T c = u[at(x, y, z, n, lg)];
-    T s = u[at(x - 1, y, z, n, lg)] + u[at(x + 1, y, z, n, lg)];
-    s += u[at(x, y - 1, z, n, lg)] + u[at(x, y + 1, z, n, lg)];
-    s += u[at(x, y, z - 1, n, lg)] + u[at(x, y, z + 1, n, lg)];
+template <typename T, int N>
+__device__ __forceinline__ T Mx_at(const T* u, int i, T ih2) {
+    using G = Geo<N>;
+    constexpr int mx = G::m, my = G::m << G::lg, pz = N * N;
+    const T c = u[i];
+    T s = u[(i & ~mx) | ((i - 1) & mx)] + u[(i & ~mx) | ((i + 1) & mx)];
+    s += u[(i & ~my) | ((i - N) & my)] + u[(i & ~my) | ((i + N) & my)];
+    s += u[(i - pz) & (G::P - 1)] + u[(i + pz) & (G::P - 1)];
     return (s - T(6) * c) * ih2;
 }
 
-// Every phase computes the thread's (at most kMaxPts) points with all loads
-// issued before any store, then stores them, then waits at the barrier.
-template <typename T, typename F>
-__device__ __forceinline__ void phase(int N, F f, T* out) {
-    T v[kMaxPts];
+// Every phase computes the thread's points with all loads issued before any
+// store, then stores them, then waits at the barrier.
+template <typename T, int P, typename F>
+__device__ __forceinline__ void phase(F f, T* out) {
+    constexpr int K = (P + kTailThreads - 1) / kTailThreads;
+    T v[K];
 #pragma unroll
-    for (int k = 0; k < kMaxPts; ++k) {
+    for (int k = 0; k < K; ++k) {
         const int i = threadIdx.x + k * kTailThreads;
-        if (i < N) v[k] = f(i);
+        if (P % kTailThreads == 0 || i < P) v[k] = f(i);
     }
 #pragma unroll
-    for (int k = 0; k < kMaxPts; ++k) {
+    for (int k = 0; k < K; ++k) {
         const int i = threadIdx.x + k * kTailThreads;
-        if (i < N) out[i] = v[k];
+        if (P % kTailThreads == 0 || i < P) out[i] = v[k];
     }
     __syncthreads();
 }
@@ -76,10 +88,11 @@ struct Fields {
     __device__ __forceinline__ T* b(int l) const { return x(l, 2); }
 };
 
-// One smoothing pass on tail level l (same buffer rotation as the multi-kernel path).
-template <typename T>
+// One smoothing pass on tail level l of N^3 points (same buffer rotation as
+// the multi-kernel path).
+template <typename T, int N>
 __device__ int smooth_pass(const TailArgs<T>& A, const Fields<T>& F, int l, int cur, bool from_zero) {
-    const int n = A.n[l], lg = A.lg[l], N = n * n * n;
+    constexpr int P = Geo<N>::P;
     const T ih2 = (T)A.ih2[l];
     const T dinv = T(1) / (T(-6) * ih2);
     const T* b = F.b(l);
@@ -87,7 +100,7 @@ __device__ int smooth_pass(const TailArgs<T>& A, const Fields<T>& F, int l, int 
     for (int k = 0; k < A.sched.steps; ++k) {
         const T a = (T)A.sched.a[l][k], c = (T)A.sched.c[l][k];
         if (k == 0 && from_zero) {
-            phase<T>(N, [&](int i) { return c * dinv * b[i]; }, F.x(l, 0));
+            phase<T, P>([&](int i) { return c * dinv * b[i]; }, F.x(l, 0));
             cur = 0;
             prev = -1;
         } else {
@@ -95,10 +108,8 @@ __device__ int smooth_pass(const TailArgs<T>& A, const Fields<T>& F, int l, int 
             const int o = use_prev ? prev : 1 - cur;
             const T* xc = F.x(l, cur);
             const T* xp = use_prev ? F.x(l, prev) : nullptr;
-            phase<T>(N, [&](int i) {
-                int x, y, z;
-                coords(i, n, lg, x, y, z);
-                const T Mx = Mx_at(xc, x, y, z, n, lg, ih2);
+            phase<T, P>([&](int i) {
+                const T Mx = Mx_at<T, N>(xc, i, ih2);
                 const T xi = xc[i];
                 const T pv = use_prev ? xp[i] : T(0);
                 return xi + a * (xi - pv) + c * dinv * (b[i] - Mx);
@@ -108,6 +119,96 @@ __device__ int smooth_pass(const TailArgs<T>& A, const Fields<T>& F, int l, int 
         }
     }
     return cur;
+}
+
+// Down leg on level l (N^3 points): smoothing from zero, residual into the
+// free buffer, full weighting into the coarse right-hand side.  Returns the
+// buffer holding the smoothed iterate.
+template <typename T, int N>
+__device__ int down_level(const TailArgs<T>& A, const Fields<T>& F, int l) {
+    using G = Geo<N>;
+    using Gc = Geo<N / 2>;
+    const T ih2 = (T)A.ih2[l];
+    const int cl = smooth_pass<T, N>(A, F, l, 0, true);
+    T* r = F.x(l, 1 - cl);
+    const T* xc = F.x(l, cl);
+    const T* b = F.b(l);
+    phase<T, G::P>([&](int i) { return b[i] - Mx_at<T, N>(xc, i, ih2); }, r);
+    phase<T, Gc::P>([&](int i) {
+        int X, Y, Z;
+        Gc::coords(i, X, Y, Z);
+        T acc = T(0);
+        for (int dz = -1; dz <= 1; ++dz) {
+            T ay = T(0);
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int fy = 2 * Y + dy, fz = 2 * Z + dz;
+                const T ax = T(0.25) * r[G::at(2 * X - 1, fy, fz)] + T(0.5) * r[G::at(2 * X, fy, fz)] +
+                             T(0.25) * r[G::at(2 * X + 1, fy, fz)];
+                ay += (dy == 0 ? T(0.5) : T(0.25)) * ax;
+            }
+            acc += (dz == 0 ? T(0.5) : T(0.25)) * ay;
+        }
+        return acc;
+    }, F.b(l + 1));
+    return cl;
+}
+
+// Up leg on level l (N^3 points): x += P e, then post-smoothing.  Returns the
+// buffer holding the result.
+template <typename T, int N>
+__device__ int up_level(const TailArgs<T>& A, const Fields<T>& F, int l, int cl, const T* e) {
+    using G = Geo<N>;
+    using Gc = Geo<N / 2>;
+    T* xv = F.x(l, cl);
+    phase<T, G::P>([&](int i) {
+        int x, y, z;
+        G::coords(i, x, y, z);
+        const int X = x >> 1, Y = y >> 1, Z = z >> 1, ox = x & 1, oy = y & 1, oz = z & 1;
+        const T w = (ox ? T(0.5) : T(1)) * (oy ? T(0.5) : T(1)) * (oz ? T(0.5) : T(1));
+        T v = T(0);
+        for (int kz = 0; kz <= oz; ++kz)
+            for (int ky = 0; ky <= oy; ++ky)
+                for (int kx = 0; kx <= ox; ++kx) v += w * e[Gc::at(X + kx, Y + ky, Z + kz)];
+        return xv[i] + v;
+    }, xv);
+    return smooth_pass<T, N>(A, F, l, cl, false);
+}
+
+// Exact zero-mean solve on the coarsest level (NC^3 points) in double with the
+// separable basis: three forward passes, the division by the eigenvalue sums,
+// three backward passes.  The basis q and eigenvalues lam are in LDS.
+template <typename T, int NC>
+__device__ void coarsest(const T* bl, T* xl, double* sA, double* sB, const double* q, const double* lam) {
+    constexpr int N = NC * NC * NC;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < N; i += kTailThreads) sA[i] = (double)bl[i];
+    __syncthreads();
+    auto pass = [&](const double* src, double* dst, int axis, bool forward) {
+        for (int i = tid; i < N; i += kTailThreads) {
+            const int x = i % NC, y = (i / NC) % NC, z = i / (NC * NC);
+            const int k = axis == 0 ? x : axis == 1 ? y : z;
+            const int stride = axis == 0 ? 1 : axis == 1 ? NC : NC * NC;
+            const int base = i - k * stride;
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < NC; ++j) acc += (forward ? q[j + NC * k] : q[k + NC * j]) * src[base + j * stride];
+            dst[i] = acc;
+        }
+        __syncthreads();
+    };
+    pass(sA, sB, 0, true);
+    pass(sB, sA, 1, true);
+    pass(sA, sB, 2, true);
+    for (int i = tid; i < N; i += kTailThreads) {
+        const int x = i % NC, y = (i / NC) % NC, z = i / (NC * NC);
+        sB[i] = (x == 0 && y == 0 && z == 0) ? 0.0 : sB[i] / (lam[x] + lam[y] + lam[z]);
+    }
+    __syncthreads();
+    pass(sB, sA, 2, false);
+    pass(sA, sB, 1, false);
+    pass(sB, sA, 0, false);
+    for (int i = tid; i < N; i += kTailThreads) xl[i] = (T)sA[i];
+    __syncthreads();
 }
 
 template <typename T>
@@ -121,102 +222,33 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> A) {
     unsigned curbits = 0;  // bit l: buffer holding level l's iterate (no private array)
     const int nl = A.nlev;
     const int tid = threadIdx.x;
-    {   // right-hand side of the first tail level from global memory
+    const int ncst = A.n[nl - 1];
+    {   // right-hand side of the first tail level and the coarsest basis from
+        // global memory, all loads in flight together
         const int N0 = A.n[0] * A.n[0] * A.n[0];
         T* b0 = F.b(0);
         for (int i = tid; i < N0; i += kTailThreads) b0[i] = A.b[0][i];
+        if (tid < ncst * ncst) q[tid] = A.Q[tid];
+        if (tid < ncst) lam[tid] = A.lam1[tid];
         __syncthreads();
     }
     // ---------------- down leg
     for (int l = 0; l + 1 < nl; ++l) {
-        const int n = A.n[l], lg = A.lg[l], N = n * n * n;
-        const T ih2 = (T)A.ih2[l];
-        const int cl = smooth_pass(A, F, l, 0, true);
+        const int cl = A.n[l] == 16 ? down_level<T, 16>(A, F, l) : down_level<T, 8>(A, F, l);
         curbits = (curbits & ~(1u << l)) | ((unsigned)cl << l);
-        // residual into the free buffer, then full weighting into the coarse rhs
-        T* r = F.x(l, 1 - cl);
-        const T* xc = F.x(l, cl);
-        const T* b = F.b(l);
-        phase<T>(N, [&](int i) {
-            int x, y, z;
-            coords(i, n, lg, x, y, z);
-            return b[i] - Mx_at(xc, x, y, z, n, lg, ih2);
-        }, r);
-        const int nc = A.n[l + 1], lgc = A.lg[l + 1], Nc = nc * nc * nc;
-        phase<T>(Nc, [&](int i) {
-            int X, Y, Z;
-            coords(i, nc, lgc, X, Y, Z);
-            T acc = T(0);
-            for (int dz = -1; dz <= 1; ++dz) {
-                T ay = T(0);
-                for (int dy = -1; dy <= 1; ++dy) {
-                    const int fy = 2 * Y + dy, fz = 2 * Z + dz;
-                    const T ax = T(0.25) * r[at(2 * X - 1, fy, fz, n, lg)] + T(0.5) * r[at(2 * X, fy, fz, n, lg)] +
-                                 T(0.25) * r[at(2 * X + 1, fy, fz, n, lg)];
-                    ay += (dy == 0 ? T(0.5) : T(0.25)) * ax;
-                }
-                acc += (dz == 0 ? T(0.5) : T(0.25)) * ay;
-            }
-            return acc;
-        }, F.b(l + 1));
     }
     // ---------------- coarsest: exact zero-mean solve in double (separable basis)
     {
         const int l = nl - 1;
-        const int nc = A.n[l];
-        const int N = nc * nc * nc;
-        for (int i = tid; i < nc * nc; i += kTailThreads) q[i] = A.Q[i];
-        for (int i = tid; i < nc; i += kTailThreads) lam[i] = A.lam1[i];
-        const T* bl = F.b(l);
-        for (int i = tid; i < N; i += kTailThreads) sA[i] = (double)bl[i];
-        __syncthreads();
-        auto pass = [&](const double* src, double* dst, int axis, bool forward) {
-            for (int i = tid; i < N; i += kTailThreads) {
-                const int x = i % nc, y = (i / nc) % nc, z = i / (nc * nc);
-                const int k = axis == 0 ? x : axis == 1 ? y : z;
-                const int stride = axis == 0 ? 1 : axis == 1 ? nc : nc * nc;
-                const int base = i - k * stride;
-                double acc = 0.0;
-                for (int j = 0; j < nc; ++j) acc += (forward ? q[j + nc * k] : q[k + nc * j]) * src[base + j * stride];
-                dst[i] = acc;
-            }
-            __syncthreads();
-        };
-        pass(sA, sB, 0, true);
-        pass(sB, sA, 1, true);
-        pass(sA, sB, 2, true);
-        for (int i = tid; i < N; i += kTailThreads) {
-            const int x = i % nc, y = (i / nc) % nc, z = i / (nc * nc);
-            sB[i] = (x == 0 && y == 0 && z == 0) ? 0.0 : sB[i] / (lam[x] + lam[y] + lam[z]);
-        }
-        __syncthreads();
-        pass(sB, sA, 2, false);
-        pass(sA, sB, 1, false);
-        pass(sB, sA, 0, false);
-        T* xl = F.x(l, 0);
-        for (int i = tid; i < N; i += kTailThreads) xl[i] = (T)sA[i];
+        if (ncst == 8) coarsest<T, 8>(F.b(l), F.x(l, 0), sA, sB, q, lam);
+        else coarsest<T, 4>(F.b(l), F.x(l, 0), sA, sB, q, lam);
         curbits &= ~(1u << l);
-        __syncthreads();
     }
     // ---------------- up leg
     for (int l = nl - 2; l >= 0; --l) {
-        const int n = A.n[l], lg = A.lg[l], N = n * n * n;
-        const int nc = A.n[l + 1], lgc = A.lg[l + 1];
         const T* e = F.x(l + 1, (curbits >> (l + 1)) & 1);
         const int cl = (curbits >> l) & 1;
-        T* xv = F.x(l, cl);
-        phase<T>(N, [&](int i) {
-            int x, y, z;
-            coords(i, n, lg, x, y, z);
-            const int X = x >> 1, Y = y >> 1, Z = z >> 1, ox = x & 1, oy = y & 1, oz = z & 1;
-            const T w = (ox ? T(0.5) : T(1)) * (oy ? T(0.5) : T(1)) * (oz ? T(0.5) : T(1));
-            T v = T(0);
-            for (int kz = 0; kz <= oz; ++kz)
-                for (int ky = 0; ky <= oy; ++ky)
-                    for (int kx = 0; kx <= ox; ++kx) v += w * e[at(X + kx, Y + ky, Z + kz, nc, lgc)];
-            return xv[i] + v;
-        }, xv);
-        const int cn = smooth_pass(A, F, l, cl, false);
+        const int cn = A.n[l] == 16 ? up_level<T, 16>(A, F, l, cl, e) : up_level<T, 8>(A, F, l, cl, e);
         curbits = (curbits & ~(1u << l)) | ((unsigned)cn << l);
     }
     {   // result of the first tail level to global memory (always its buffer x0)
@@ -230,8 +262,14 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> A) {
 
 template <typename T>
 hipError_t launch_tail(const TailArgs<T>& args, hipStream_t s) {
-    if (args.nlev < 2 || args.nlev > kTailMaxLevels || args.n[0] > 16 || args.n[args.nlev - 1] > 8)
-        return hipErrorInvalidValue;
+    // levels of 16^3 or 8^3 points down to a coarsest of 8^3 or 4^3, halving each time
+    if (args.nlev < 2 || args.nlev > kTailMaxLevels) return hipErrorInvalidValue;
+    for (int l = 0; l < args.nlev; ++l) {
+        const int nl = args.n[l];
+        const bool coarsest = l == args.nlev - 1;
+        if (coarsest ? (nl != 8 && nl != 4) : (nl != 16 && nl != 8)) return hipErrorInvalidValue;
+        if (l > 0 && nl * 2 != args.n[l - 1]) return hipErrorInvalidValue;
+    }
     int elems = 0;
     for (int l = 0; l < args.nlev; ++l) elems += 3 * args.n[l] * args.n[l] * args.n[l];
     if (elems > kTailElems) return hipErrorInvalidValue;
