@@ -44,10 +44,10 @@ TRAFFIC = {
     "n": 256,
     "degree": 3,
     "bytes_per_launch": {
-        # pre-smoothing from zero (b -> x3) and post-smoothing pair (x, x_prev, b -> y2)
-        "k_smooth2_lds": ((74.2 + 64.0) + (232.7 + 64.0)) / 2 * 1024 * 1024,
+        # pre-smoothing from zero (b -> x3, two-plane prefetch) and post-smoothing pair (x, x_prev, b -> y2)
+        "k_smooth2_lds": ((74.3 + 64.0) + (232.2 + 64.0)) / 2 * 1024 * 1024,
         # the one remaining fine single step (x, b -> out)
-        "k_smooth_row": (132.1 + 64.0) * 1024 * 1024,
+        "k_smooth_row": (132.2 + 64.0) * 1024 * 1024,
     },
 }
 

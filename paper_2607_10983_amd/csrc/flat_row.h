@@ -27,6 +27,7 @@ void set_pair_nz(int nz);
 void set_pair_waves(int waves);
 void set_pair_prefetch(int planes);
 void set_pair_unroll(bool on);
+void set_fromb_pf2(bool on);
 template <typename T>
 hipError_t launch_smooth_pair_row(int n, double ih2, const T* x, const T* xp, const T* b, T* y2, T* y1,
                                   double a1, double cd1, double a2, double cd2, hipStream_t s,

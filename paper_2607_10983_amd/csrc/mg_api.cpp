@@ -689,6 +689,7 @@ static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype, cons
     if (const char* t = std::getenv("MG_PAIR_WAVES")) set_pair_waves(std::atoi(t));
     if (const char* t = std::getenv("MG_PAIR_PREFETCH")) set_pair_prefetch(std::atoi(t));
     if (const char* t = std::getenv("MG_PAIR_UNROLL")) set_pair_unroll(std::atoi(t) != 0);
+    if (const char* t = std::getenv("MG_FROMB_PF2")) set_fromb_pf2(std::atoi(t) != 0);
     // two-step smoothing kernels; MG_NO_PAIR keeps every step a kernel of its own
     c->use_pairs = std::getenv("MG_NO_PAIR") == nullptr;
     c->use_visits = std::getenv("MG_NO_VISIT") == nullptr;
