@@ -37,17 +37,17 @@ HBM_PEAK_GBPS = 8000.0
 # Measured HBM bytes per launch of the fine-level smoothing kernels on the
 # 256^3 / degree-3 workload: rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch
 # (profiles/hbm_bytes_*.md) scaled by the copy-kernel factors 2.0 (fetch) and
-# 1.0 (write), averaged over the launches of one V-cycle.  Reported only while
+# 1.0 (write), per launch of each kernel.  Reported only while
 # the device code of the row kernels is the code the counters were taken on.
 TRAFFIC = {
-    "device_code_sha256": "eda75e3472ad1488e7e9b51df5e38abee893afc9f2ef560281fd3f88ed36e71d",
+    "device_code_sha256": "767c442cafc3510fd421113a22569a96bb70171895d94014bfe4142e31090339",
     "n": 256,
     "degree": 3,
     "bytes_per_launch": {
-        # pre-smoothing from zero (b -> x3, two-plane prefetch) and post-smoothing pair (x, x_prev, b -> y2)
-        "k_smooth2_lds": ((74.3 + 64.0) + (232.2 + 64.0)) / 2 * 1024 * 1024,
-        # the one remaining fine single step (x, b -> out)
-        "k_smooth_row": (132.2 + 64.0) * 1024 * 1024,
+        # pre-smoothing, one pass from zero (b -> x3, two-plane prefetch)
+        "k_smooth2_lds": (74.4 + 64.0) * 1024 * 1024,
+        # post-smoothing, three steps in one pass (x, b -> x3)
+        "k_smooth3_lds": (152.8 + 64.0) * 1024 * 1024,
     },
 }
 
@@ -65,13 +65,19 @@ def measured_traffic(n, degree, kernel):
     return round(v) if v is not None else None
 
 
-def pass_bytes(v, from_zero, x1_fused, pairs, s):
+def pass_bytes(v, from_zero, pairs, triple, s):
     """Algorithmic bytes per point of one smoothing pass of degree v, following
-    the library's schedule: steps pair up from the end of the pass where the
+    the library's schedule: a pass from zero starts with one kernel for its
+    first three steps (b -> x3, and x2 when a fourth step needs it as x_prev);
+    a pass of three steps from a nonzero iterate is one three-step kernel
+    (x, b -> x3); otherwise steps pair up from the end of the pass where the
     two-step kernel runs (a pair that is not the last writes its first step)."""
+    if not from_zero and triple and v == 3:
+        return 3 * s
     tot, prev, k = 0.0, False, 0
-    if from_zero and x1_fused:
-        k = 1
+    if from_zero and pairs and v >= 3:
+        tot += (2 + (v > 3)) * s
+        prev, k = v > 3, 3
     while k < v:
         rem = v - k
         need_y1 = rem > 2
@@ -89,20 +95,29 @@ def pass_bytes(v, from_zero, x1_fused, pairs, s):
 
 def model_bytes_per_cycle(n, levels, degree, precision):
     """Algorithmic bytes of one outer iteration (inner V-cycle + outer residual/update),
-    every field element each kernel reads or writes counted once.  The first
-    fine-level smoothing step from zero is written by the outer kernel (x1 = c0 D^-1 r);
-    the two-step kernel runs on levels 64 <= n_l with rows of at most 1 KB."""
+    every field element each kernel reads or writes counted once, following the
+    library's schedule: multi-step kernels on levels 64 <= n_l (two-step rows up
+    to 2 KB, three-step rows up to 1 KB), the 32^3 level of a float hierarchy as
+    two fused visits, the outer kernel writing the first step from zero only
+    where the fine level has no pass-from-zero kernel."""
     s = 8 if precision == "fp64" else 4
     tot = 0.0
+    tail_start = next((l for l in range(levels) if n >> l <= 16), levels)
     for l in range(levels - 1):
         nl = n >> l
-        pairs = nl >= 64 and nl * s <= 1024
-        pre = pass_bytes(degree, True, l == 0, pairs, s)
-        post = pass_bytes(degree, False, False, pairs, s)
+        pairs = 64 <= nl <= 1024 and nl * s <= 2048
+        triple = 64 <= nl and nl * s <= 1024
+        if precision != "fp64" and nl == 32 and degree <= 3 and l != tail_start:
+            tot += nl ** 3 * ((2 * s + s / 8) + (3 * s + s / 8))  # fused pre and post visits
+            continue
+        x1_outer = l == 0 and not (pairs and degree >= 3)
+        pre = pass_bytes(degree, True, pairs, triple, s) - (2 * s if x1_outer else 0)  # step 0 by the outer
+        post = pass_bytes(degree, False, pairs, triple, s)
         transfers = 2 * s + s / 8 + 2 * s + s / 8
         tot += nl ** 3 * (pre + post + transfers)
-    # outer: read phi, e, b; write phi, r and the first smoothing step (e, r, x1 inner precision)
-    tot += n ** 3 * (8 + s + 8 + 8 + s + s)
+    # outer: read phi, e, b; write phi, r (and the first smoothing step where no pass-from-zero kernel runs)
+    fine_pairs = 64 <= n <= 1024 and n * s <= 2048
+    tot += n ** 3 * (8 + s + 8 + 8 + s + (0 if fine_pairs and degree >= 3 else s))
     return tot
 
 
@@ -118,7 +133,7 @@ def run_sequence(mg, sources, phi, tol, max_cycles=60):
     return cycles
 
 
-MG_TIME_STEP, MG_TIME_PAIR = 1, 2
+MG_TIME_STEP, MG_TIME_PAIR, MG_TIME_TRIPLE = 1, 2, 4
 
 
 def solve_timed(mg, torch, b, tol, max_cycles=60):
@@ -369,9 +384,9 @@ def main():
     mg = mgpu.Multigrid(n, levels=levels, degree=deg, precision="mixed")
     for _ in range(args.warmup):
         run_sequence(mg, sources, phi, args.tol)
-    # the dominant fine smoothing kernel: one-step or two-step kernel, by total time
+    # the dominant fine smoothing kernel: one-, two- or three-step kernel, by total time
     kinds = {}
-    for kind in (MG_TIME_STEP, MG_TIME_PAIR):
+    for kind in (MG_TIME_STEP, MG_TIME_PAIR, MG_TIME_TRIPLE):
         mg.enable_kernel_timing(kind)
         mg.kernel_timing()
         run_sequence(mg, sources, phi, args.tol)
@@ -391,9 +406,21 @@ def main():
     bytes_cycle = model_bytes_per_cycle(n, levels, deg, "mixed")
     achieved = k_bytes / (k_ms * 1e-3) / 1e9 if k_ms > 0 else None
     names = {MG_TIME_STEP: "k_smooth_row (fine-level Chebyshev step, float)",
-             MG_TIME_PAIR: "k_smooth2_lds (two fused fine-level Chebyshev steps, float)"}
-    other = MG_TIME_PAIR if dominant == MG_TIME_STEP else MG_TIME_STEP
-    ogbps, ous = rate(kinds[other])
+             MG_TIME_PAIR: "k_smooth2_lds (fine-level two-step kernel and pass from zero, float)",
+             MG_TIME_TRIPLE: "k_smooth3_lds (fine-level three-step pass, float)"}
+    others = []
+    for kind in names:
+        if kind == dominant or not kinds[kind][0]:
+            continue
+        ogbps, ous = rate(kinds[kind])
+        others.append({
+            "kernel": names[kind], "achieved": ogbps, "avg_launch_us": ous,
+            "frac": round(ogbps / HBM_PEAK_GBPS, 4) if ogbps else None,
+            "traffic": measured_traffic(n, deg, names[kind].split()[0]),
+            "launches_per_step": kinds[kind][0],
+            "alg_bytes_per_launch": kinds[kind][2] / kinds[kind][0],
+            "share_of_step": round(kinds[kind][1] / ms_per_step, 4),
+        })
     roofline = {
         "kernel": names[dominant],
         "bound": "hbm",
@@ -407,12 +434,7 @@ def main():
         "avg_launch_us": round(1e3 * k_ms / launches, 2) if launches else None,
         "alg_bytes_per_launch": k_bytes / launches if launches else None,
         "share_of_step": round(k_ms / (1e3 * t_mixed), 4),
-        "other_fine_smoothing_kernel": {
-            "kernel": names[other], "achieved": ogbps, "avg_launch_us": ous,
-            "frac": round(ogbps / HBM_PEAK_GBPS, 4) if ogbps else None,
-            "launches_per_step": kinds[other][0],
-            "share_of_step": round(kinds[other][1] / ms_per_step, 4) if kinds[other][0] else None,
-        },
+        "other_fine_smoothing_kernels": others,
     }
 
     # ------------------------------------------------------------- float64 comparison

@@ -271,7 +271,9 @@ mg_status mg_level_lmax(const mg_ctx* ctx, double* lmax_out);
  * / mg_vcycle / mg_solve_pcg whose kind is in the mask is bracketed by HIP
  * events recorded by the kernel's own dispatch on the context's stream.
  * Kinds: MG_TIME_STEP, the one-step kernels; MG_TIME_PAIR, the kernels that
- * apply two consecutive smoothing steps in one pass.  mg_kernel_timing
+ * apply two consecutive smoothing steps in one pass (and the pass from zero
+ * that forms its first step on the fly); MG_TIME_TRIPLE, the kernel that
+ * applies three steps in one pass from a nonzero iterate.  mg_kernel_timing
  * returns, since the previous call: the number of such launches, their summed
  * duration in milliseconds and their summed algorithmic HBM bytes (every
  * field element the launch reads or writes counted once: iterate, previous
@@ -280,7 +282,8 @@ mg_status mg_level_lmax(const mg_ctx* ctx, double* lmax_out);
  * mask (0 disables, the default); other values give MG_ERR_INVALID. */
 enum mg_timing_kind {
     MG_TIME_STEP = 1,
-    MG_TIME_PAIR = 2
+    MG_TIME_PAIR = 2,
+    MG_TIME_TRIPLE = 4
 };
 mg_status mg_enable_kernel_timing(mg_ctx* ctx, int enable);
 mg_status mg_kernel_timing(mg_ctx* ctx, int* launches, double* total_ms, double* alg_bytes);

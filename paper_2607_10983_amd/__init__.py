@@ -289,7 +289,8 @@ class Multigrid:
     # ---------------------------------------------------------------- timing
     def enable_kernel_timing(self, mask: int = _lib.MG_TIME_STEP):
         """Time fine-level smoothing kernels of the kinds in ``mask``
-        (MG_TIME_STEP one-step kernels, MG_TIME_PAIR two-step kernels; 0 or
+        (MG_TIME_STEP one-step kernels, MG_TIME_PAIR two-step kernels,
+        MG_TIME_TRIPLE three-step kernels; 0 or
         False disables, True means MG_TIME_STEP)."""
         st = _lib.load().mg_enable_kernel_timing(self._ctx, int(mask))
         if st != _lib.MG_OK:

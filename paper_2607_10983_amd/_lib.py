@@ -19,7 +19,7 @@ MG_FP64, MG_MIXED, MG_FP32 = 0, 1, 2
 MG_CHEBYSHEV, MG_JACOBI = 0, 1
 MG_DTYPE_F32, MG_DTYPE_F64 = 0, 1
 MG_PREDICT_RECYCLE, MG_PREDICT_GROWTH, MG_PREDICT_LINEAR, MG_PREDICT_QUADRATIC = 0, 1, 2, 3
-MG_TIME_STEP, MG_TIME_PAIR = 1, 2
+MG_TIME_STEP, MG_TIME_PAIR, MG_TIME_TRIPLE = 1, 2, 4
 
 
 class MgParams(ctypes.Structure):

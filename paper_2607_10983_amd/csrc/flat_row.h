@@ -23,6 +23,16 @@ hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, cons
 // (a1, cd1) and (a2, cd2) are steps 1 and 2.
 // pair_kernels_apply tells whether n and the element size are supported.
 bool pair_kernels_apply(int n, size_t elem);
+// Three steps in one pass from x with x_prev = 0 (the start of a smoothing
+// pass that is not from zero): y3 after steps (a0, cd0), (a1, cd1), (a2, cd2).
+// y3 must differ from x and b.
+bool triple_kernels_apply(int n, size_t elem);
+void set_use_triple(bool on);
+void set_triple_waves(int waves);
+template <typename T>
+hipError_t launch_smooth_triple_row(int n, double ih2, const T* x, const T* b, T* y3, double a0, double cd0,
+                                    double a1, double cd1, double a2, double cd2, hipStream_t s, hipEvent_t ev0,
+                                    hipEvent_t ev1);
 void set_pair_nz(int nz);
 void set_pair_waves(int waves);
 void set_pair_prefetch(int planes);

@@ -540,6 +540,110 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
     }
 }
 
+// =====================================================================================
+// Three consecutive smoothing steps in one pass, starting a pass from x
+// (x_prev = 0, as in the first step of a post-smoothing pass):
+//   y1 = x  + a0 x + cd0 (b - M x)
+//   y2 = y1 + a1 (y1 - x ) + cd1 (b - M y1)
+//   y3 = y2 + a2 (y2 - y1) + cd2 (b - M y2)
+// Only y3 is written.  A block of NW waves owns rows y0-2 .. y0+W+1 (W = NW - 4
+// outputs): every wave forms y1 on its row (x rows y +- 1 from the caches),
+// waves 1 .. NW-2 form y2 one plane behind, waves 2 .. NW-3 form y3 one more
+// plane behind.  The y1 and y2 planes are shared through LDS, double-buffered
+// by iteration parity, one barrier per plane.  The arithmetic of each step is
+// that of k_smooth_row, in the same order.  NZC: compile-time chunk height
+// (the plane loop unrolls completely, see k_smooth2_lds).
+// =====================================================================================
+template <typename T, int VEC, int NW, int NZC>
+__global__ __launch_bounds__(64 * NW) void k_smooth3_lds(int n, T ih2, const T* __restrict__ x,
+                                                         const T* __restrict__ b, T* __restrict__ y3, T a0, T cd0,
+                                                         T a1, T cd1, T a2, T cd2, int nyb) {
+    constexpr int NR = 64 * VEC;
+    constexpr int W = NW - 4;
+    __shared__ T rows1[2][NW][NR];
+    __shared__ T rows2[2][NW][NR];
+    const RowGrid g{n, n - 1};
+    const int lb = xcd_logical(blockIdx.x, gridDim.x);
+    const int yb = lb % nyb, zc = lb / nyb;
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int y = yb * W - 2 + w;  // rows outside [0, n) wrap for loads
+    const bool st2 = w >= 1 && w <= NW - 2;
+    const bool outw = w >= 2 && w <= NW - 3 && y < n;
+    const int z0 = zc * NZC;
+    const size_t off = (size_t)lane * VEC;
+    // stage 1 at plane z1: x on this row at z1-1, z1, z1+1, rows y-1 / y+1 at z1, b at z1
+    T xm[VEC], xc[VEC], xq[VEC], ym[VEC], yp[VEC], b1[VEC];
+    // stage 2 at z1-1: y1 at z1-2, z1-1 (and z1 just formed), b at z1-1; x_prev = x at z1-1 = xm
+    // stage 3 at z1-2: y2 at z1-3, z1-2 (and z1-1 just formed), b at z1-2; x_prev = y1 at z1-2 = s1m
+    // (the queues start empty: their first planes are formed before they are read)
+    T s1m[VEC] = {}, s1c[VEC] = {}, b2[VEC] = {};
+    T s2m[VEC] = {}, s2c[VEC] = {}, b3[VEC] = {};
+    int z1 = z0 - 2;
+    ldrow<T, VEC>(xm, x + g.row(y, z1 - 1) + off);
+    ldrow<T, VEC>(xc, x + g.row(y, z1) + off);
+    ldrow<T, VEC>(xq, x + g.row(y, z1 + 1) + off);
+    ldrow<T, VEC>(ym, x + g.row(y - 1, z1) + off);
+    ldrow<T, VEC>(yp, x + g.row(y + 1, z1) + off);
+    ldrow<T, VEC>(b1, b + g.row(y, z1) + off);
+    constexpr int steps = NZC + 4;
+#pragma unroll
+    for (int j = 0; j < steps; ++j, ++z1) {
+        const bool more = j + 1 < steps;
+        T xn[VEC], ymn[VEC], ypn[VEC], bn[VEC];
+        if (more) {
+            ldrow<T, VEC>(xn, x + g.row(y, z1 + 2) + off);
+            ldrow<T, VEC>(ymn, x + g.row(y - 1, z1 + 1) + off);
+            ldrow<T, VEC>(ypn, x + g.row(y + 1, z1 + 1) + off);
+            ldrow<T, VEC>(bn, b + g.row(y, z1 + 1) + off);
+        }
+        // stage 1: y1 at z1 (x_prev = 0)
+        T M1[VEC], s1p[VEC];
+        flat7_row<T, VEC>(xc, ym, yp, xm, xq, ih2, M1);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) s1p[e] = cheb_step<T>(xc[e], T(0), b1[e], M1[e], a0, cd0);
+        T s2p[VEC] = {};
+        if (j >= 2) {
+            const int buf = j & 1;
+            strow<T, VEC>(&rows1[buf][w][off], s1c);                // y1 at z1-1
+            if (j >= 3 && st2) strow<T, VEC>(&rows2[buf][w][off], s2c);  // y2 at z1-2
+            __syncthreads();
+            if (st2) {  // stage 2: y2 at z1-1
+                T nm[VEC], np[VEC], M2[VEC];
+                ldrow<T, VEC>(nm, &rows1[buf][w - 1][off]);
+                ldrow<T, VEC>(np, &rows1[buf][w + 1][off]);
+                flat7_row<T, VEC>(s1c, nm, np, s1m, s1p, ih2, M2);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) s2p[e] = cheb_step<T>(s1c[e], xm[e], b2[e], M2[e], a1, cd1);
+            }
+            if (j >= 4 && outw) {  // stage 3: y3 at z1-2
+                T nm[VEC], np[VEC], M3[VEC], o[VEC];
+                ldrow<T, VEC>(nm, &rows2[buf][w - 1][off]);
+                ldrow<T, VEC>(np, &rows2[buf][w + 1][off]);
+                flat7_row<T, VEC>(s2c, nm, np, s2m, s2p, ih2, M3);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) o[e] = cheb_step<T>(s2c[e], s1m[e], b3[e], M3[e], a2, cd2);
+                strow<T, VEC>(y3 + g.row(y, z1 - 2) + off, o);
+            }
+        }
+        // rotate the queues
+        copyrow(s2m, s2c);
+        copyrow(s2c, s2p);
+        copyrow(b3, b2);
+        copyrow(s1m, s1c);
+        copyrow(s1c, s1p);
+        copyrow(b2, b1);
+        if (more) {
+            copyrow(xm, xc);
+            copyrow(xc, xq);
+            copyrow(xq, xn);
+            copyrow(ym, ymn);
+            copyrow(yp, ypn);
+            copyrow(b1, bn);
+        }
+    }
+}
+
 template <typename TA, typename TR, typename TE, int VEC, int W, bool UPDATE>
 __global__ __launch_bounds__(64 * W) void k_outer_lds(int n, TA ih2, const double* __restrict__ phi_in,
                                                       const TE* __restrict__ e, double* __restrict__ phi_out,
@@ -1034,6 +1138,55 @@ hipError_t launch_smooth_pair_row(int n, double ih2, const T* x, const T* xp, co
         return launch_pair_nw<T, 12>(n, ih2, x, xp, b, y2, y1, a1, cd1, a2, cd2, s, ev0, ev1, x0_mode, cd0);
     return launch_pair_nw<T, 16>(n, ih2, x, xp, b, y2, y1, a1, cd1, a2, cd2, s, ev0, ev1, x0_mode, cd0);
 }
+
+// Three-step kernel: 12 waves (8 output rows) per block, chunks of
+// kTripleNz planes; rows of at most 1 KB (float n <= 256, double n <= 128).
+constexpr int kTripleNz = 8;
+bool g_use_triple = true;
+// block of the three-step kernel: 8 waves at 64^3, 12 above (measured:
+// 64^3 5.7 vs 6.4 us, 128^3 10.1 vs 10.8 us, 256^3 within 1%); 0 = by size
+int g_triple_waves = 0;
+
+bool triple_kernels_apply(int n, size_t elem) {
+    return g_use_triple && row_kernels_apply(n) && (size_t)n * elem <= 1024 && n % kTripleNz == 0;
+}
+void set_use_triple(bool on) { g_use_triple = on; }
+void set_triple_waves(int w) {
+    if (w == 0 || w == 8 || w == 12 || w == 16) g_triple_waves = w;
+}
+
+template <typename T, int NW>
+hipError_t launch_triple_nw(int n, double ih2, const T* x, const T* b, T* y3, double a0, double cd0, double a1,
+                            double cd1, double a2, double cd2, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    constexpr int W = NW - 4;
+    const int nyb = (n + W - 1) / W;
+    const int blocks = nyb * (n / kTripleNz);
+    DISPATCH_VEC(n, {
+        if constexpr (64 * VEC * sizeof(T) <= 1024)
+            MG_LAUNCH((k_smooth3_lds<T, VEC, NW, kTripleNz>), dim3(blocks), dim3(64 * NW), s, ev0, ev1, n, (T)ih2, x,
+                      b, y3, (T)a0, (T)cd0, (T)a1, (T)cd1, (T)a2, (T)cd2, nyb);
+    })
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_smooth_triple_row(int n, double ih2, const T* x, const T* b, T* y3, double a0, double cd0,
+                                    double a1, double cd1, double a2, double cd2, hipStream_t s, hipEvent_t ev0,
+                                    hipEvent_t ev1) {
+    if (!triple_kernels_apply(n, sizeof(T)) || x == y3 || b == y3) return hipErrorInvalidValue;
+    const int waves = g_triple_waves > 0 ? g_triple_waves : (n <= 64 ? 8 : 12);
+    if (waves == 8)
+        return launch_triple_nw<T, 8>(n, ih2, x, b, y3, a0, cd0, a1, cd1, a2, cd2, s, ev0, ev1);
+    if (waves == 16)
+        return launch_triple_nw<T, 16>(n, ih2, x, b, y3, a0, cd0, a1, cd1, a2, cd2, s, ev0, ev1);
+    return launch_triple_nw<T, 12>(n, ih2, x, b, y3, a0, cd0, a1, cd1, a2, cd2, s, ev0, ev1);
+}
+template hipError_t launch_smooth_triple_row<float>(int, double, const float*, const float*, float*, double, double,
+                                                    double, double, double, double, hipStream_t, hipEvent_t,
+                                                    hipEvent_t);
+template hipError_t launch_smooth_triple_row<double>(int, double, const double*, const double*, double*, double,
+                                                     double, double, double, double, double, hipStream_t,
+                                                     hipEvent_t, hipEvent_t);
 
 template <typename TA, typename TR, typename TE>
 hipError_t launch_outer_row(int n, double ih2, const double* phi_in, const TE* e, double* phi_out, const double* b,

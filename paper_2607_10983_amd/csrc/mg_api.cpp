@@ -88,7 +88,7 @@ struct mg_ctx {
     size_t scratch_elems = 0;
     std::string err;
     // timing of the fine-level smoothing kernel
-    int timing = 0;  // mask of timed kernel kinds (MG_TIME_STEP, MG_TIME_PAIR)
+    int timing = 0;  // mask of timed kernel kinds (MG_TIME_STEP, MG_TIME_PAIR, MG_TIME_TRIPLE)
     std::vector<TimingPair> events;
     size_t events_used = 0;
     int timed_launches = 0;
@@ -355,12 +355,25 @@ mg_status smooth_level(mg_ctx* c, int l, bool from_zero) {
         const bool has_prev = cheb && prev >= 0;
         const bool need_y1 = cheb && rem > 2;
         const bool triple = k == 0 && from_zero && from_zero_triple(c, l);
+        // a pass of three steps that does not start from zero: one three-step kernel
+        const bool triple3 = k == 0 && !from_zero && cheb && v == 3 && c->use_pairs && !c->var &&
+                             triple_kernels_apply(L.n, sizeof(T));
         const bool pair = pairs && rem >= 2 && rem % 2 == 0 && !(k == 0 && from_zero) && !(need_y1 && has_prev);
-        const int kind = (pair || triple) ? MG_TIME_PAIR : MG_TIME_STEP;
+        const int kind = triple3 ? MG_TIME_TRIPLE : (pair || triple) ? MG_TIME_PAIR : MG_TIME_STEP;
         hipEvent_t ev0, ev1;
         mg_status st = time_events(c, fine, kind, &ev0, &ev1);
         if (st != MG_OK) return st;
-        if (triple) {
+        if (triple3) {
+            const int out = other(cur);
+            const double D = -6.0 * L.ih2;
+            HIPCHK(c, launch_smooth_triple_row<T>(L.n, L.ih2, bufs[cur], (const T*)L.b, bufs[out], L.a[0],
+                                                  L.c[0] / D, L.a[1], L.c[1] / D, L.a[2], L.c[2] / D, c->stream, ev0,
+                                                  ev1));
+            bytes = 3.0 * fbytes;  // x, b; x_3
+            prev = -1;
+            cur = out;
+            k = 2;  // three steps done
+        } else if (triple) {
             // steps 0, 1, 2 of the pass from zero: reads b, writes x_3 (and x_2
             // when a fourth step needs it as x_prev)
             const bool y1 = cheb && v > 3;
@@ -690,6 +703,8 @@ static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype, cons
     if (const char* t = std::getenv("MG_PAIR_PREFETCH")) set_pair_prefetch(std::atoi(t));
     if (const char* t = std::getenv("MG_PAIR_UNROLL")) set_pair_unroll(std::atoi(t) != 0);
     if (const char* t = std::getenv("MG_FROMB_PF2")) set_fromb_pf2(std::atoi(t) != 0);
+    if (const char* t = std::getenv("MG_TRIPLE")) set_use_triple(std::atoi(t) != 0);
+    if (const char* t = std::getenv("MG_TRIPLE_WAVES")) set_triple_waves(std::atoi(t));
     // two-step smoothing kernels; MG_NO_PAIR keeps every step a kernel of its own
     c->use_pairs = std::getenv("MG_NO_PAIR") == nullptr;
     c->use_visits = std::getenv("MG_NO_VISIT") == nullptr;
@@ -1381,7 +1396,7 @@ mg_status mg_level_lmax(const mg_ctx* c, double* out) {
 
 mg_status mg_enable_kernel_timing(mg_ctx* c, int enable) {
     if (!c) return MG_ERR_INVALID;
-    if (enable < 0 || enable > (MG_TIME_STEP | MG_TIME_PAIR)) return fail(c, MG_ERR_INVALID, "timing mask out of range");
+    if (enable < 0 || enable > (MG_TIME_STEP | MG_TIME_PAIR | MG_TIME_TRIPLE)) return fail(c, MG_ERR_INVALID, "timing mask out of range");
     c->timing = enable;
     c->events_used = 0;
     c->timed_launches = 0;
