@@ -11,6 +11,8 @@ bool row_kernels_apply(int n);
 int row_outer_blocks(int n, bool double_arith);
 // Tuning knob: target number of blocks per launch (default 8192).
 void set_row_target_blocks(int target);
+void set_outer_shape(int waves, int nz);
+void set_rr_target(int blocks);
 void set_small_nz(int nz, int pair_nz);
 
 template <typename T>

@@ -962,10 +962,35 @@ inline void small_chunk(int n, int planes, int nzs, int nyb, int& nz, int& block
 
 bool row_kernels_apply(int n) { return n >= 64 && n <= 1024 && (n & (n - 1)) == 0; }
 
-void outer_lds_shape(int n, int& nz, int& nyb, int& blocks) {
-    nyb = n / kLdsWaves;
+// block count the residual + restriction kernel's chunks aim for on levels of
+// 256^3 and more (256^3: 512 blocks 22.6 us, 1024 blocks 25.2 us, 256 blocks 28.9 us)
+int g_rr_target = 512;
+int g_outer_waves = 8;  // waves (rows) per block of the outer LDS kernel
+int g_outer_nz = 0;     // its z chunk, 0 = by the block-count rule
+
+void set_rr_target(int blocks) {
+    if (blocks >= 64) g_rr_target = blocks;
+}
+void set_outer_shape(int waves, int nz) {
+    if (waves == 8 || waves == 16) g_outer_waves = waves;
+    if (nz >= 0) g_outer_nz = nz;
+}
+
+// Waves of the outer LDS kernel at size n and element size elem (8 unless the
+// larger block's two planes of rows fit the LDS budget).
+int outer_waves(int n, size_t elem) {
+    const int w = g_outer_waves;
+    return 2ull * (w + 2) * (size_t)n * elem <= kLdsBudget ? w : kLdsWaves;
+}
+
+// Longest z chunks that still give one block per CU: the outer kernel is
+// bound by its bytes, and a chunk re-reads its two halo planes (256^3: chunks
+// of 32 planes 103.6 us against 107.8 us for 16; 16-wave blocks measured slower).
+void outer_lds_shape(int n, int waves, int& nz, int& nyb, int& blocks) {
+    nyb = n / waves;
     nz = n;
-    while (nz > 16 && nyb * (n / nz) < 512) nz >>= 1;
+    while (nz > 16 && nyb * (n / nz) < 256) nz >>= 1;
+    if (g_outer_nz > 0 && g_outer_nz <= n && n % g_outer_nz == 0) nz = g_outer_nz;
     blocks = nyb * (n / nz);
 }
 
@@ -974,7 +999,7 @@ void outer_lds_shape(int n, int& nz, int& nyb, int& blocks) {
 int row_outer_blocks(int n, bool double_arith) {
     int nz, nyb, blocks;
     if (double_arith ? lds_rows_fit<double>(n) : lds_rows_fit<float>(n)) {
-        outer_lds_shape(n, nz, nyb, blocks);
+        outer_lds_shape(n, outer_waves(n, double_arith ? sizeof(double) : sizeof(float)), nz, nyb, blocks);
         return blocks;
     }
     shape(n, n, 16, nz, nyb, blocks, 1024);
@@ -1193,18 +1218,25 @@ hipError_t launch_outer_row(int n, double ih2, const double* phi_in, const TE* e
                             double bmean, TR* r, TR* x1, double cd0, double* partials, hipStream_t s) {
     int nz, nyb, blocks;
     if (lds_rows_fit<TA>(n)) {
-        outer_lds_shape(n, nz, nyb, blocks);
-        constexpr int Wv = kLdsWaves;
-        DISPATCH_VEC(n, {
-            if constexpr (2ull * (Wv + 2) * 64 * VEC * sizeof(TA) <= kLdsBudget) {
-                if (e)
-                    hipLaunchKernelGGL((k_outer_lds<TA, TR, TE, VEC, Wv, true>), dim3(blocks), dim3(64 * Wv), 0, s,
-                                       n, (TA)ih2, phi_in, e, phi_out, b, bmean, r, x1, (TA)cd0, partials, nz, nyb);
-                else
-                    hipLaunchKernelGGL((k_outer_lds<TA, TR, TE, VEC, Wv, false>), dim3(blocks), dim3(64 * Wv), 0, s,
-                                       n, (TA)ih2, phi_in, e, phi_out, b, bmean, r, x1, (TA)cd0, partials, nz, nyb);
-            }
-        })
+        const int waves = outer_waves(n, sizeof(TA));
+        outer_lds_shape(n, waves, nz, nyb, blocks);
+#define MG_OUTER_LDS(Wv)                                                                                           \
+    DISPATCH_VEC(n, {                                                                                              \
+        if constexpr (2ull * (Wv + 2) * 64 * VEC * sizeof(TA) <= kLdsBudget) {                                     \
+            if (e)                                                                                                 \
+                hipLaunchKernelGGL((k_outer_lds<TA, TR, TE, VEC, Wv, true>), dim3(blocks), dim3(64 * Wv), 0, s, n, \
+                                   (TA)ih2, phi_in, e, phi_out, b, bmean, r, x1, (TA)cd0, partials, nz, nyb);     \
+            else                                                                                                   \
+                hipLaunchKernelGGL((k_outer_lds<TA, TR, TE, VEC, Wv, false>), dim3(blocks), dim3(64 * Wv), 0, s, n, \
+                                   (TA)ih2, phi_in, e, phi_out, b, bmean, r, x1, (TA)cd0, partials, nz, nyb);     \
+        }                                                                                                          \
+    })
+        if (waves == 16) {
+            MG_OUTER_LDS(16)
+        } else {
+            MG_OUTER_LDS(8)
+        }
+#undef MG_OUTER_LDS
         return hipGetLastError();
     }
     shape(n, n, 16, nz, nyb, blocks, 1024);
@@ -1225,7 +1257,7 @@ hipError_t launch_rr_row(int n, double ih2, const T* x, const T* b, T* coarse, h
     int nzc, nyb, blocks;
     // small levels are latency chains: chunks of 2 coarse planes (128^3: 7.7 -> 5.7 us,
     // 64^3: 6.8 -> 4.8 us per launch)
-    shape(nc, nc, n <= 128 ? 2 : 4, nzc, nyb, blocks, 1024);
+    shape(nc, nc, n <= 128 ? 2 : 4, nzc, nyb, blocks, n >= 256 ? g_rr_target : 1024);
     small_chunk(n, nc, g_small_nz, nyb, nzc, blocks);
     DISPATCH_VEC(n, {
         hipLaunchKernelGGL((k_rr_row<T, VEC>), dim3(blocks), dim3(kBlock), 0, s, n, (T)ih2, x, b, coarse, nzc, nyb);

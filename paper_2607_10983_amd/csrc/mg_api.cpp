@@ -704,6 +704,9 @@ static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype, cons
     if (const char* t = std::getenv("MG_PAIR_UNROLL")) set_pair_unroll(std::atoi(t) != 0);
     if (const char* t = std::getenv("MG_FROMB_PF2")) set_fromb_pf2(std::atoi(t) != 0);
     if (const char* t = std::getenv("MG_TRIPLE")) set_use_triple(std::atoi(t) != 0);
+    if (const char* t = std::getenv("MG_OUTER_WAVES")) set_outer_shape(std::atoi(t), -1);
+    if (const char* t = std::getenv("MG_OUTER_NZ")) set_outer_shape(0, std::atoi(t));
+    if (const char* t = std::getenv("MG_RR_TARGET")) set_rr_target(std::atoi(t));
     if (const char* t = std::getenv("MG_TRIPLE_WAVES")) set_triple_waves(std::atoi(t));
     // two-step smoothing kernels; MG_NO_PAIR keeps every step a kernel of its own
     c->use_pairs = std::getenv("MG_NO_PAIR") == nullptr;
