@@ -40,14 +40,14 @@ HBM_PEAK_GBPS = 8000.0
 # 1.0 (write), per launch of each kernel.  Reported only while
 # the device code of the row kernels is the code the counters were taken on.
 TRAFFIC = {
-    "device_code_sha256": "767c442cafc3510fd421113a22569a96bb70171895d94014bfe4142e31090339",
+    "device_code_sha256": "42f986852f6e23c9013e3aa1262fb0872a9365eba7ba7fe7fddd14edf2d644b1",
     "n": 256,
     "degree": 3,
     "bytes_per_launch": {
-        # pre-smoothing, one pass from zero (b -> x3, two-plane prefetch)
-        "k_smooth2_lds": (74.4 + 64.0) * 1024 * 1024,
-        # post-smoothing, three steps in one pass (x, b -> x3)
-        "k_smooth3_lds": (152.8 + 64.0) * 1024 * 1024,
+        # pre-smoothing, one pass from zero (b -> x3, two-plane prefetch, 16-wave blocks)
+        "k_smooth2_lds": (79.1 + 64.0) * 1024 * 1024,
+        # prolongation + post-smoothing, three steps in one pass (x, e, b -> x3)
+        "k_smooth3p_lds": (175.4 + 64.0) * 1024 * 1024,
     },
 }
 
@@ -97,9 +97,10 @@ def model_bytes_per_cycle(n, levels, degree, precision):
     """Algorithmic bytes of one outer iteration (inner V-cycle + outer residual/update),
     every field element each kernel reads or writes counted once, following the
     library's schedule: multi-step kernels on levels 64 <= n_l (two-step rows up
-    to 2 KB, three-step rows up to 1 KB), the 32^3 level of a float hierarchy as
-    two fused visits, the outer kernel writing the first step from zero only
-    where the fine level has no pass-from-zero kernel."""
+    to 2 KB, three-step rows up to 1 KB; from 128^3 the three-step pass forms
+    x + P e itself, so the prolongation writes nothing), the 32^3 level of a
+    float hierarchy as two fused visits, the outer kernel writing the first step
+    from zero only where the fine level has no pass-from-zero kernel."""
     s = 8 if precision == "fp64" else 4
     tot = 0.0
     tail_start = next((l for l in range(levels) if n >> l <= 16), levels)
@@ -113,7 +114,8 @@ def model_bytes_per_cycle(n, levels, degree, precision):
         x1_outer = l == 0 and not (pairs and degree >= 3)
         pre = pass_bytes(degree, True, pairs, triple, s) - (2 * s if x1_outer else 0)  # step 0 by the outer
         post = pass_bytes(degree, False, pairs, triple, s)
-        transfers = 2 * s + s / 8 + 2 * s + s / 8
+        fused_prolong = triple and nl >= 128 and degree == 3
+        transfers = 2 * s + s / 8 + (s / 8 if fused_prolong else 2 * s + s / 8)
         tot += nl ** 3 * (pre + post + transfers)
     # outer: read phi, e, b; write phi, r (and the first smoothing step where no pass-from-zero kernel runs)
     fine_pairs = 64 <= n <= 1024 and n * s <= 2048
@@ -407,7 +409,8 @@ def main():
     achieved = k_bytes / (k_ms * 1e-3) / 1e9 if k_ms > 0 else None
     names = {MG_TIME_STEP: "k_smooth_row (fine-level Chebyshev step, float)",
              MG_TIME_PAIR: "k_smooth2_lds (fine-level two-step kernel and pass from zero, float)",
-             MG_TIME_TRIPLE: "k_smooth3_lds (fine-level three-step pass, float)"}
+             MG_TIME_TRIPLE: ("k_smooth3p_lds (fine-level prolongation + three-step pass, float)" if n >= 128
+                              else "k_smooth3_lds (fine-level three-step pass, float)")}
     others = []
     for kind in names:
         if kind == dominant or not kinds[kind][0]:

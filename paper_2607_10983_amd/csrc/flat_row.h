@@ -31,6 +31,14 @@ bool pair_kernels_apply(int n, size_t elem);
 bool triple_kernels_apply(int n, size_t elem);
 void set_use_triple(bool on);
 void set_triple_waves(int waves);
+// The same pass starting from x0 = x + P e (e on the (n/2)^3 grid), x0 formed
+// on the fly and never written: y3 after three steps from x0.  n >= 128.
+bool triple_pro_applies(int n, size_t elem);
+void set_use_triple_pro(bool on);
+template <typename T>
+hipError_t launch_prolong_triple_row(int n, double ih2, const T* x, const T* e, const T* b, T* y3, double a0,
+                                     double cd0, double a1, double cd1, double a2, double cd2, hipStream_t s,
+                                     hipEvent_t ev0, hipEvent_t ev1);
 template <typename T>
 hipError_t launch_smooth_triple_row(int n, double ih2, const T* x, const T* b, T* y3, double a0, double cd0,
                                     double a1, double cd1, double a2, double cd2, hipStream_t s, hipEvent_t ev0,

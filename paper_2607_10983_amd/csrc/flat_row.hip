@@ -540,6 +540,54 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
     }
 }
 
+// The coarse rows the trilinear prolongation of fine row (y, z) reads (VEC >= 2):
+// (Y, Z), and (Y+1, Z), (Y, Z+1), (Y+1, Z+1) where y, z are odd; loaded raw so
+// that a prefetch is not waited for until the values are combined.
+template <typename T, int VEC>
+struct CoarseRows {
+    T t00[VEC / 2], t01[VEC / 2], t10[VEC / 2], t11[VEC / 2];
+};
+template <typename T, int VEC>
+__device__ __forceinline__ void coarse_load(CoarseRows<T, VEC>& c, const T* e, const RowGrid& gc, int y, int z,
+                                            int lane) {
+    constexpr int CV = VEC / 2;
+    const int Y = y >> 1, Z = z >> 1, oy = y & 1, oz = z & 1;
+    const size_t off = (size_t)lane * CV;
+    ldrow<T, CV>(c.t00, e + gc.row(Y, Z) + off);
+    if (oy) ldrow<T, CV>(c.t01, e + gc.row(Y + 1, Z) + off);
+    if (oz) ldrow<T, CV>(c.t10, e + gc.row(Y, Z + 1) + off);
+    if (oy && oz) ldrow<T, CV>(c.t11, e + gc.row(Y + 1, Z + 1) + off);
+}
+// xv += P e on fine row (y, z): interpolate in y, then z, then x (the x + 1
+// coarse value from the next lane).  Rounding written out: every kernel that
+// prolongs (the prolongation kernel, the fused post-smoothing pass) gets the
+// same bits.
+template <typename T, int VEC>
+__device__ __forceinline__ void prolong_add(T (&xv)[VEC], const CoarseRows<T, VEC>& c, int y, int z) {
+#pragma clang fp contract(off)
+    constexpr int CV = VEC / 2, CW = CV + 1;
+    const int oy = y & 1, oz = z & 1;
+    T w[CW];
+    auto seg = [&](const T (&t)[CV], int q) { return q < CV ? t[q] : lane_rot(t[0], 1); };
+#pragma unroll
+    for (int q = 0; q < CW; ++q) {
+        const T r00 = seg(c.t00, q);
+        T a0 = r00;
+        if (oy) a0 = T(0.5) * (r00 + seg(c.t01, q));
+        if (oz) {
+            const T r10 = seg(c.t10, q);
+            const T a1 = oy ? T(0.5) * (r10 + seg(c.t11, q)) : r10;
+            a0 = T(0.5) * (a0 + a1);
+        }
+        w[q] = a0;
+    }
+#pragma unroll
+    for (int q = 0; q < CV; ++q) {
+        xv[2 * q] = xv[2 * q] + w[q];
+        xv[2 * q + 1] = xv[2 * q + 1] + T(0.5) * (w[q] + w[q + 1]);
+    }
+}
+
 // =====================================================================================
 // Three consecutive smoothing steps in one pass, starting a pass from x
 // (x_prev = 0, as in the first step of a post-smoothing pass):
@@ -639,6 +687,126 @@ __global__ __launch_bounds__(64 * NW) void k_smooth3_lds(int n, T ih2, const T* 
             copyrow(xq, xn);
             copyrow(ym, ymn);
             copyrow(yp, ypn);
+            copyrow(b1, bn);
+        }
+    }
+}
+
+// =====================================================================================
+// The three-step pass fused with the prolongation before it: the pass starts
+// from x0 = x + P e, formed row by row as x and the coarse rows arrive, never
+// written.  Each wave forms x0 on its own row (z queue) and the two edge waves
+// also on one halo row each; the x0 plane is shared through LDS like the y1
+// and y2 planes, so stage 1 reads its y-neighbours there instead of from the
+// caches.  Same three steps as k_smooth3_lds, same bits as prolongation
+// followed by three single steps.  VEC >= 2 (n >= 128).
+// =====================================================================================
+template <typename T, int VEC, int NW, int NZC>
+__global__ __launch_bounds__(64 * NW) void k_smooth3p_lds(int n, T ih2, const T* __restrict__ x,
+                                                          const T* __restrict__ e, const T* __restrict__ b,
+                                                          T* __restrict__ y3, T a0, T cd0, T a1, T cd1, T a2, T cd2,
+                                                          int nyb) {
+    static_assert(VEC >= 2, "the fused prolongation needs two fine points per coarse point and lane");
+    constexpr int NR = 64 * VEC;
+    constexpr int W = NW - 4;
+    __shared__ T rows0[2][NW + 2][NR];  // x0: slot w + 1 = wave w's row, slots 0 / NW + 1 the halo rows
+    __shared__ T rows1[2][NW][NR];
+    __shared__ T rows2[2][NW][NR];
+    const RowGrid g{n, n - 1};
+    const RowGrid gc{n >> 1, (n >> 1) - 1};
+    const int lb = xcd_logical(blockIdx.x, gridDim.x);
+    const int yb = lb % nyb, zc = lb / nyb;
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int y = yb * W - 2 + w;  // rows outside [0, n) wrap for loads (parity and coarse row wrap alike)
+    const bool lo = w == 0, hi = w == NW - 1;
+    const int yh = lo ? y - 1 : y + 1;  // halo row of an edge wave
+    const bool st2 = w >= 1 && w <= NW - 2;
+    const bool outw = w >= 2 && w <= NW - 3 && y < n;
+    const int z0 = zc * NZC;
+    const size_t off = (size_t)lane * VEC;
+    auto load_x0 = [&](T (&v)[VEC], int yy, int zz) {
+        CoarseRows<T, VEC> c;
+        ldrow<T, VEC>(v, x + g.row(yy, zz) + off);
+        coarse_load<T, VEC>(c, e, gc, yy, zz, lane);
+        prolong_add<T, VEC>(v, c, yy, zz);
+    };
+    // x0 on this row at z1-1, z1, z1+1 and on the halo row at z1; b at z1
+    T xm[VEC], xc[VEC], xq[VEC], h[VEC] = {}, b1[VEC];
+    T s1m[VEC] = {}, s1c[VEC] = {}, b2[VEC] = {};
+    T s2m[VEC] = {}, s2c[VEC] = {}, b3[VEC] = {};
+    int z1 = z0 - 2;
+    load_x0(xm, y, z1 - 1);
+    load_x0(xc, y, z1);
+    load_x0(xq, y, z1 + 1);
+    if (lo || hi) load_x0(h, yh, z1);
+    ldrow<T, VEC>(b1, b + g.row(y, z1) + off);
+    constexpr int steps = NZC + 4;
+#pragma unroll
+    for (int j = 0; j < steps; ++j, ++z1) {
+        const bool more = j + 1 < steps;
+        // raw operands of the next plane: this row at z1+2, the halo row at z1+1, b at z1+1
+        T xr[VEC], hr[VEC], bn[VEC];
+        CoarseRows<T, VEC> cr, chr;
+        if (more) {
+            ldrow<T, VEC>(xr, x + g.row(y, z1 + 2) + off);
+            coarse_load<T, VEC>(cr, e, gc, y, z1 + 2, lane);
+            if (lo || hi) {
+                ldrow<T, VEC>(hr, x + g.row(yh, z1 + 1) + off);
+                coarse_load<T, VEC>(chr, e, gc, yh, z1 + 1, lane);
+            }
+            ldrow<T, VEC>(bn, b + g.row(y, z1 + 1) + off);
+        }
+        const int buf = j & 1;
+        strow<T, VEC>(&rows0[buf][w + 1][off], xc);
+        if (lo) strow<T, VEC>(&rows0[buf][0][off], h);
+        if (hi) strow<T, VEC>(&rows0[buf][NW + 1][off], h);
+        if (j >= 2) strow<T, VEC>(&rows1[buf][w][off], s1c);                 // y1 at z1-1
+        if (j >= 3 && st2) strow<T, VEC>(&rows2[buf][w][off], s2c);          // y2 at z1-2
+        __syncthreads();
+        // stage 1: y1 at z1 (x_prev = 0)
+        T s1p[VEC];
+        {
+            T ym[VEC], yp[VEC], M1[VEC];
+            ldrow<T, VEC>(ym, &rows0[buf][w][off]);
+            ldrow<T, VEC>(yp, &rows0[buf][w + 2][off]);
+            flat7_row<T, VEC>(xc, ym, yp, xm, xq, ih2, M1);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) s1p[q] = cheb_step<T>(xc[q], T(0), b1[q], M1[q], a0, cd0);
+        }
+        T s2p[VEC] = {};
+        if (j >= 2 && st2) {  // stage 2: y2 at z1-1, x_prev = x0 at z1-1
+            T nm[VEC], np[VEC], M2[VEC];
+            ldrow<T, VEC>(nm, &rows1[buf][w - 1][off]);
+            ldrow<T, VEC>(np, &rows1[buf][w + 1][off]);
+            flat7_row<T, VEC>(s1c, nm, np, s1m, s1p, ih2, M2);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) s2p[q] = cheb_step<T>(s1c[q], xm[q], b2[q], M2[q], a1, cd1);
+        }
+        if (j >= 4 && outw) {  // stage 3: y3 at z1-2, x_prev = y1 at z1-2
+            T nm[VEC], np[VEC], M3[VEC], o[VEC];
+            ldrow<T, VEC>(nm, &rows2[buf][w - 1][off]);
+            ldrow<T, VEC>(np, &rows2[buf][w + 1][off]);
+            flat7_row<T, VEC>(s2c, nm, np, s2m, s2p, ih2, M3);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) o[q] = cheb_step<T>(s2c[q], s1m[q], b3[q], M3[q], a2, cd2);
+            strow<T, VEC>(y3 + g.row(y, z1 - 2) + off, o);
+        }
+        copyrow(s2m, s2c);
+        copyrow(s2c, s2p);
+        copyrow(b3, b2);
+        copyrow(s1m, s1c);
+        copyrow(s1c, s1p);
+        copyrow(b2, b1);
+        if (more) {
+            copyrow(xm, xc);
+            copyrow(xc, xq);
+            prolong_add<T, VEC>(xr, cr, y, z1 + 2);
+            copyrow(xq, xr);
+            if (lo || hi) {
+                prolong_add<T, VEC>(hr, chr, yh, z1 + 1);
+                copyrow(h, hr);
+            }
             copyrow(b1, bn);
         }
     }
@@ -867,30 +1035,14 @@ __global__ __launch_bounds__(kBlock) void k_prolong_row(int n, const T* __restri
     for (int k = 0; k < nz; ++k) {
         const int z = z0 + k;
         const int Z = z >> 1, oz = z & 1;
-        T xv[VEC], p[VEC];
+        T xv[VEC];
         ldrow<T, VEC>(xv, x + g.row(y, z) + off);
         if constexpr (VEC >= 2) {
-            constexpr int CW = VEC / 2 + 1;
-            T r00[CW], r01[CW], r10[CW], r11[CW], w[CW];
-            coarse_seg<T, VEC>(r00, e + gc.row(Y, Z), lane);
-            if (oy) coarse_seg<T, VEC>(r01, e + gc.row(Y + 1, Z), lane);
-            if (oz) coarse_seg<T, VEC>(r10, e + gc.row(Y, Z + 1), lane);
-            if (oy && oz) coarse_seg<T, VEC>(r11, e + gc.row(Y + 1, Z + 1), lane);
-#pragma unroll
-            for (int q = 0; q < CW; ++q) {
-                T a0 = oy ? T(0.5) * (r00[q] + r01[q]) : r00[q];
-                if (oz) {
-                    const T a1 = oy ? T(0.5) * (r10[q] + r11[q]) : r10[q];
-                    a0 = T(0.5) * (a0 + a1);
-                }
-                w[q] = a0;
-            }
-#pragma unroll
-            for (int q = 0; q < VEC / 2; ++q) {
-                p[2 * q] = w[q];
-                p[2 * q + 1] = T(0.5) * (w[q] + w[q + 1]);
-            }
+            CoarseRows<T, VEC> c;
+            coarse_load<T, VEC>(c, e, gc, y, z, lane);
+            prolong_add<T, VEC>(xv, c, y, z);
         } else {
+            T p[VEC];
             const int X = lane >> 1, ox = lane & 1;
             auto at = [&](int yy, int zz, int xx) { return e[gc.row(yy, zz) + (size_t)(xx & (nc - 1))]; };
             T a = at(Y, Z, X), a1 = ox ? at(Y, Z, X + 1) : T(0);
@@ -909,9 +1061,9 @@ __global__ __launch_bounds__(kBlock) void k_prolong_row(int n, const T* __restri
                 v = T(0.5) * (v + u);
             }
             p[0] = v;
-        }
 #pragma unroll
-        for (int q = 0; q < VEC; ++q) xv[q] += p[q];
+            for (int q = 0; q < VEC; ++q) xv[q] += p[q];
+        }
         strow<T, VEC>(x + g.row(y, z) + off, xv);
     }
 }
@@ -1065,6 +1217,7 @@ constexpr size_t kPairLdsBudget = 64 * 1024;
 constexpr int kPairUnrollNz = 8;  // chunk height of the fully unrolled two-step variant
 int g_pair_nz = 0;  // z chunk of the two-step kernel; 0 = chosen from n
 int g_pair_waves = 8;
+bool g_pair_waves_set = false;  // waves chosen explicitly (then also for the pass from zero)
 // Prefetch depth of the two-step kernel: -1 = by row size (two planes ahead
 // for 2 KB rows, whose blocks run one per CU: 512^3 float 541 -> 498 us per
 // launch; one plane for smaller rows, where the extra registers cost
@@ -1090,7 +1243,10 @@ void set_pair_nz(int nz) {
     if (nz >= 0) g_pair_nz = nz;
 }
 void set_pair_waves(int waves) {
-    if (waves == 8 || waves == 12 || waves == 16) g_pair_waves = waves;
+    if (waves == 8 || waves == 12 || waves == 16) {
+        g_pair_waves = waves;
+        g_pair_waves_set = true;
+    }
 }
 void set_pair_unroll(bool on) { g_pair_unroll = on; }
 void set_fromb_pf2(bool on) { g_fromb_pf2 = on; }
@@ -1157,9 +1313,18 @@ hipError_t launch_smooth_pair_row(int n, double ih2, const T* x, const T* xp, co
     if (!pair_kernels_apply(n, sizeof(T))) return hipErrorInvalidValue;
     if (x0_mode == 0 && x == nullptr) return hipErrorInvalidValue;
     if (x0_mode != 0 && xp != nullptr) return hipErrorInvalidValue;
-    if (g_pair_waves == 8)
+    int waves = g_pair_waves;
+    // The pass from zero (one field read) runs best in larger blocks where the
+    // row fits their register budget: 256^3 16 waves 33.8 us (8: 35.4, 12: 38.3),
+    // 128^3 12 waves 7.8 us (8: 8.6), 64^3 8 waves.
+    if (x0_mode != 0 && !g_pair_waves_set) {
+        const size_t row = (size_t)n * sizeof(T);
+        waves = (n >= 256 && row <= pair_max_row_bytes(16)) ? 16 : (n >= 128 && row <= pair_max_row_bytes(12)) ? 12 : 8;
+        if (2ull * waves * row > kPairLdsBudget) waves = 8;
+    }
+    if (waves == 8)
         return launch_pair_nw<T, 8>(n, ih2, x, xp, b, y2, y1, a1, cd1, a2, cd2, s, ev0, ev1, x0_mode, cd0);
-    if (g_pair_waves == 12)
+    if (waves == 12)
         return launch_pair_nw<T, 12>(n, ih2, x, xp, b, y2, y1, a1, cd1, a2, cd2, s, ev0, ev1, x0_mode, cd0);
     return launch_pair_nw<T, 16>(n, ih2, x, xp, b, y2, y1, a1, cd1, a2, cd2, s, ev0, ev1, x0_mode, cd0);
 }
@@ -1168,6 +1333,7 @@ hipError_t launch_smooth_pair_row(int n, double ih2, const T* x, const T* xp, co
 // kTripleNz planes; rows of at most 1 KB (float n <= 256, double n <= 128).
 constexpr int kTripleNz = 8;
 bool g_use_triple = true;
+bool g_use_triple_pro = true;  // post-smoothing pass fused with the prolongation before it
 // block of the three-step kernel: 8 waves at 64^3, 12 above (measured:
 // 64^3 5.7 vs 6.4 us, 128^3 10.1 vs 10.8 us, 256^3 within 1%); 0 = by size
 int g_triple_waves = 0;
@@ -1206,6 +1372,45 @@ hipError_t launch_smooth_triple_row(int n, double ih2, const T* x, const T* b, T
         return launch_triple_nw<T, 16>(n, ih2, x, b, y3, a0, cd0, a1, cd1, a2, cd2, s, ev0, ev1);
     return launch_triple_nw<T, 12>(n, ih2, x, b, y3, a0, cd0, a1, cd1, a2, cd2, s, ev0, ev1);
 }
+template <typename T, int NW>
+hipError_t launch_triple_pro_nw(int n, double ih2, const T* x, const T* e, const T* b, T* y3, double a0, double cd0,
+                                double a1, double cd1, double a2, double cd2, hipStream_t s, hipEvent_t ev0,
+                                hipEvent_t ev1) {
+    constexpr int W = NW - 4;
+    const int nyb = (n + W - 1) / W;
+    const int blocks = nyb * (n / kTripleNz);
+    DISPATCH_VEC(n, {
+        if constexpr (VEC >= 2 && 64 * VEC * sizeof(T) <= 1024)
+            MG_LAUNCH((k_smooth3p_lds<T, VEC, NW, kTripleNz>), dim3(blocks), dim3(64 * NW), s, ev0, ev1, n, (T)ih2,
+                      x, e, b, y3, (T)a0, (T)cd0, (T)a1, (T)cd1, (T)a2, (T)cd2, nyb);
+        else
+            return hipErrorInvalidValue;
+    })
+    return hipGetLastError();
+}
+
+bool triple_pro_applies(int n, size_t elem) { return g_use_triple_pro && n >= 128 && triple_kernels_apply(n, elem); }
+void set_use_triple_pro(bool on) { g_use_triple_pro = on; }
+
+template <typename T>
+hipError_t launch_prolong_triple_row(int n, double ih2, const T* x, const T* e, const T* b, T* y3, double a0,
+                                     double cd0, double a1, double cd1, double a2, double cd2, hipStream_t s,
+                                     hipEvent_t ev0, hipEvent_t ev1) {
+    if (!triple_pro_applies(n, sizeof(T)) || y3 == x || y3 == b || y3 == e) return hipErrorInvalidValue;
+    const int waves = g_triple_waves > 0 ? g_triple_waves : 12;
+    if (waves == 8)
+        return launch_triple_pro_nw<T, 8>(n, ih2, x, e, b, y3, a0, cd0, a1, cd1, a2, cd2, s, ev0, ev1);
+    if (waves == 16)
+        return launch_triple_pro_nw<T, 16>(n, ih2, x, e, b, y3, a0, cd0, a1, cd1, a2, cd2, s, ev0, ev1);
+    return launch_triple_pro_nw<T, 12>(n, ih2, x, e, b, y3, a0, cd0, a1, cd1, a2, cd2, s, ev0, ev1);
+}
+template hipError_t launch_prolong_triple_row<float>(int, double, const float*, const float*, const float*, float*,
+                                                     double, double, double, double, double, double, hipStream_t,
+                                                     hipEvent_t, hipEvent_t);
+template hipError_t launch_prolong_triple_row<double>(int, double, const double*, const double*, const double*,
+                                                      double*, double, double, double, double, double, double,
+                                                      hipStream_t, hipEvent_t, hipEvent_t);
+
 template hipError_t launch_smooth_triple_row<float>(int, double, const float*, const float*, float*, double, double,
                                                     double, double, double, double, hipStream_t, hipEvent_t,
                                                     hipEvent_t);

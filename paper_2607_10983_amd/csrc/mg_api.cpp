@@ -318,6 +318,14 @@ inline bool visit_level(const mg_ctx* c, int l) {
            visit_applies(c->lev[l].n, (int)c->lev[l].a.size());
 }
 
+// Level l's post-smoothing pass (three Chebyshev steps) runs fused with the
+// prolongation before it.
+inline bool post_fused(const mg_ctx* c, int l, size_t elem) {
+    const Level& L = c->lev[l];
+    return c->p.smoother == MG_CHEBYSHEV && L.a.size() == 3 && c->use_pairs && !c->var &&
+           triple_pro_applies(L.n, elem);
+}
+
 // Level l runs its pass from zero as one three-step kernel (first step formed
 // from b on the fly): seven-point operator, two-step kernels available, and
 // at least three steps per pass.
@@ -535,6 +543,19 @@ mg_status vcycle_from_zero(mg_ctx* c, int l) {
                                              (T*)L.x[other(L.cur)], c->stream));
     st = vcycle_from_zero<T>(c, l + 1);
     if (st != MG_OK) return st;
+    if (post_fused(c, l, sizeof(T))) {  // prolongation and the three-step post-smoothing pass in one kernel
+        const bool fine = (l == 0);
+        hipEvent_t ev0, ev1;
+        if ((st = time_events(c, fine, MG_TIME_TRIPLE, &ev0, &ev1)) != MG_OK) return st;
+        const double D = -6.0 * L.ih2;  // c / D rounded as in the single-step launch
+        const int out = other(L.cur);
+        HIPCHK(c, launch_prolong_triple_row<T>(L.n, L.ih2, (const T*)L.x[L.cur], (const T*)Lc.x[Lc.cur],
+                                               (const T*)L.b, (T*)L.x[out], L.a[0], L.c[0] / D, L.a[1],
+                                               L.c[1] / D, L.a[2], L.c[2] / D, c->stream, ev0, ev1));
+        L.cur = out;
+        // x, b read, x_3 written, e read once per coarse point
+        return time_end(c, fine, MG_TIME_TRIPLE, (3.0 + 1.0 / 8.0) * (double)L.N * sizeof(T));
+    }
     HIPCHK(c, launch_prolong_add<T>(L.n, (const T*)Lc.x[Lc.cur], (T*)L.x[L.cur], c->stream));
     return smooth_level<T>(c, l, false);
 }
@@ -704,6 +725,7 @@ static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype, cons
     if (const char* t = std::getenv("MG_PAIR_UNROLL")) set_pair_unroll(std::atoi(t) != 0);
     if (const char* t = std::getenv("MG_FROMB_PF2")) set_fromb_pf2(std::atoi(t) != 0);
     if (const char* t = std::getenv("MG_TRIPLE")) set_use_triple(std::atoi(t) != 0);
+    if (const char* t = std::getenv("MG_TRIPLE_PRO")) set_use_triple_pro(std::atoi(t) != 0);
     if (const char* t = std::getenv("MG_OUTER_WAVES")) set_outer_shape(std::atoi(t), -1);
     if (const char* t = std::getenv("MG_OUTER_NZ")) set_outer_shape(0, std::atoi(t));
     if (const char* t = std::getenv("MG_RR_TARGET")) set_rr_target(std::atoi(t));
