@@ -543,20 +543,48 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
 // The coarse rows the trilinear prolongation of fine row (y, z) reads (VEC >= 2):
 // (Y, Z), and (Y+1, Z), (Y, Z+1), (Y+1, Z+1) where y, z are odd; loaded raw so
 // that a prefetch is not waited for until the values are combined.
+// VEC == 1 (64^3): lane l holds fine x = l, i.e. coarse X = l / 2, and reads
+// the coarse values X and X + 1 of each row itself.
 template <typename T, int VEC>
 struct CoarseRows {
     T t00[VEC / 2], t01[VEC / 2], t10[VEC / 2], t11[VEC / 2];
 };
+template <typename T>
+struct CoarseRows<T, 1> {
+    T a, a1, b0, b1, c0, c1, d0, d1;  // rows (Y, Z), (Y+1, Z), (Y, Z+1), (Y+1, Z+1) at X, X + 1
+};
 template <typename T, int VEC>
 __device__ __forceinline__ void coarse_load(CoarseRows<T, VEC>& c, const T* e, const RowGrid& gc, int y, int z,
                                             int lane) {
-    constexpr int CV = VEC / 2;
     const int Y = y >> 1, Z = z >> 1, oy = y & 1, oz = z & 1;
-    const size_t off = (size_t)lane * CV;
-    ldrow<T, CV>(c.t00, e + gc.row(Y, Z) + off);
-    if (oy) ldrow<T, CV>(c.t01, e + gc.row(Y + 1, Z) + off);
-    if (oz) ldrow<T, CV>(c.t10, e + gc.row(Y, Z + 1) + off);
-    if (oy && oz) ldrow<T, CV>(c.t11, e + gc.row(Y + 1, Z + 1) + off);
+    if constexpr (VEC == 1) {
+        const int X = lane >> 1, ox = lane & 1, m = gc.mask;
+        const T* r0 = e + gc.row(Y, Z);
+        c.a = r0[X & m];
+        if (ox) c.a1 = r0[(X + 1) & m];
+        if (oy) {
+            const T* r1 = e + gc.row(Y + 1, Z);
+            c.b0 = r1[X & m];
+            if (ox) c.b1 = r1[(X + 1) & m];
+        }
+        if (oz) {
+            const T* r2 = e + gc.row(Y, Z + 1);
+            c.c0 = r2[X & m];
+            if (ox) c.c1 = r2[(X + 1) & m];
+            if (oy) {
+                const T* r3 = e + gc.row(Y + 1, Z + 1);
+                c.d0 = r3[X & m];
+                if (ox) c.d1 = r3[(X + 1) & m];
+            }
+        }
+    } else {
+        constexpr int CV = VEC / 2;
+        const size_t off = (size_t)lane * CV;
+        ldrow<T, CV>(c.t00, e + gc.row(Y, Z) + off);
+        if (oy) ldrow<T, CV>(c.t01, e + gc.row(Y + 1, Z) + off);
+        if (oz) ldrow<T, CV>(c.t10, e + gc.row(Y, Z + 1) + off);
+        if (oy && oz) ldrow<T, CV>(c.t11, e + gc.row(Y + 1, Z + 1) + off);
+    }
 }
 // xv += P e on fine row (y, z): interpolate in y, then z, then x (the x + 1
 // coarse value from the next lane).  Rounding written out: every kernel that
@@ -565,26 +593,38 @@ __device__ __forceinline__ void coarse_load(CoarseRows<T, VEC>& c, const T* e, c
 template <typename T, int VEC>
 __device__ __forceinline__ void prolong_add(T (&xv)[VEC], const CoarseRows<T, VEC>& c, int y, int z) {
 #pragma clang fp contract(off)
-    constexpr int CV = VEC / 2, CW = CV + 1;
     const int oy = y & 1, oz = z & 1;
-    T w[CW];
-    auto seg = [&](const T (&t)[CV], int q) { return q < CV ? t[q] : lane_rot(t[0], 1); };
-#pragma unroll
-    for (int q = 0; q < CW; ++q) {
-        const T r00 = seg(c.t00, q);
-        T a0 = r00;
-        if (oy) a0 = T(0.5) * (r00 + seg(c.t01, q));
+    if constexpr (VEC == 1) {  // interpolate in x, then y, then z
+        const int ox = threadIdx.x & 1;
+        T v = ox ? T(0.5) * (c.a + c.a1) : c.a;
+        if (oy) v = T(0.5) * (v + (ox ? T(0.5) * (c.b0 + c.b1) : c.b0));
         if (oz) {
-            const T r10 = seg(c.t10, q);
-            const T a1 = oy ? T(0.5) * (r10 + seg(c.t11, q)) : r10;
-            a0 = T(0.5) * (a0 + a1);
+            T u = ox ? T(0.5) * (c.c0 + c.c1) : c.c0;
+            if (oy) u = T(0.5) * (u + (ox ? T(0.5) * (c.d0 + c.d1) : c.d0));
+            v = T(0.5) * (v + u);
         }
-        w[q] = a0;
-    }
+        xv[0] = xv[0] + v;
+    } else {
+        constexpr int CV = VEC / 2, CW = CV + 1;
+        T w[CW];
+        auto seg = [&](const T (&t)[CV], int q) { return q < CV ? t[q] : lane_rot(t[0], 1); };
 #pragma unroll
-    for (int q = 0; q < CV; ++q) {
-        xv[2 * q] = xv[2 * q] + w[q];
-        xv[2 * q + 1] = xv[2 * q + 1] + T(0.5) * (w[q] + w[q + 1]);
+        for (int q = 0; q < CW; ++q) {
+            const T r00 = seg(c.t00, q);
+            T a0 = r00;
+            if (oy) a0 = T(0.5) * (r00 + seg(c.t01, q));
+            if (oz) {
+                const T r10 = seg(c.t10, q);
+                const T a1 = oy ? T(0.5) * (r10 + seg(c.t11, q)) : r10;
+                a0 = T(0.5) * (a0 + a1);
+            }
+            w[q] = a0;
+        }
+#pragma unroll
+        for (int q = 0; q < CV; ++q) {
+            xv[2 * q] = xv[2 * q] + w[q];
+            xv[2 * q + 1] = xv[2 * q + 1] + T(0.5) * (w[q] + w[q + 1]);
+        }
     }
 }
 
@@ -699,14 +739,13 @@ __global__ __launch_bounds__(64 * NW) void k_smooth3_lds(int n, T ih2, const T* 
 // also on one halo row each; the x0 plane is shared through LDS like the y1
 // and y2 planes, so stage 1 reads its y-neighbours there instead of from the
 // caches.  Same three steps as k_smooth3_lds, same bits as prolongation
-// followed by three single steps.  VEC >= 2 (n >= 128).
+// followed by three single steps.
 // =====================================================================================
 template <typename T, int VEC, int NW, int NZC>
 __global__ __launch_bounds__(64 * NW) void k_smooth3p_lds(int n, T ih2, const T* __restrict__ x,
                                                           const T* __restrict__ e, const T* __restrict__ b,
                                                           T* __restrict__ y3, T a0, T cd0, T a1, T cd1, T a2, T cd2,
                                                           int nyb) {
-    static_assert(VEC >= 2, "the fused prolongation needs two fine points per coarse point and lane");
     constexpr int NR = 64 * VEC;
     constexpr int W = NW - 4;
     __shared__ T rows0[2][NW + 2][NR];  // x0: slot w + 1 = wave w's row, slots 0 / NW + 1 the halo rows
@@ -1030,40 +1069,14 @@ __global__ __launch_bounds__(kBlock) void k_prolong_row(int n, const T* __restri
     const int lane = threadIdx.x & 63;
     const int y = yb * kWaves + (threadIdx.x >> 6);
     const int z0 = zc * nz;
-    const int Y = y >> 1, oy = y & 1;
     const size_t off = (size_t)lane * VEC;
     for (int k = 0; k < nz; ++k) {
         const int z = z0 + k;
-        const int Z = z >> 1, oz = z & 1;
         T xv[VEC];
         ldrow<T, VEC>(xv, x + g.row(y, z) + off);
-        if constexpr (VEC >= 2) {
-            CoarseRows<T, VEC> c;
-            coarse_load<T, VEC>(c, e, gc, y, z, lane);
-            prolong_add<T, VEC>(xv, c, y, z);
-        } else {
-            T p[VEC];
-            const int X = lane >> 1, ox = lane & 1;
-            auto at = [&](int yy, int zz, int xx) { return e[gc.row(yy, zz) + (size_t)(xx & (nc - 1))]; };
-            T a = at(Y, Z, X), a1 = ox ? at(Y, Z, X + 1) : T(0);
-            T v = ox ? T(0.5) * (a + a1) : a;
-            if (oy) {
-                const T b0 = at(Y + 1, Z, X), b1 = ox ? at(Y + 1, Z, X + 1) : T(0);
-                v = T(0.5) * (v + (ox ? T(0.5) * (b0 + b1) : b0));
-            }
-            if (oz) {
-                T c0 = at(Y, Z + 1, X), c1 = ox ? at(Y, Z + 1, X + 1) : T(0);
-                T u = ox ? T(0.5) * (c0 + c1) : c0;
-                if (oy) {
-                    const T d0 = at(Y + 1, Z + 1, X), d1 = ox ? at(Y + 1, Z + 1, X + 1) : T(0);
-                    u = T(0.5) * (u + (ox ? T(0.5) * (d0 + d1) : d0));
-                }
-                v = T(0.5) * (v + u);
-            }
-            p[0] = v;
-#pragma unroll
-            for (int q = 0; q < VEC; ++q) xv[q] += p[q];
-        }
+        CoarseRows<T, VEC> c;
+        coarse_load<T, VEC>(c, e, gc, y, z, lane);
+        prolong_add<T, VEC>(xv, c, y, z);
         strow<T, VEC>(x + g.row(y, z) + off, xv);
     }
 }
@@ -1380,7 +1393,7 @@ hipError_t launch_triple_pro_nw(int n, double ih2, const T* x, const T* e, const
     const int nyb = (n + W - 1) / W;
     const int blocks = nyb * (n / kTripleNz);
     DISPATCH_VEC(n, {
-        if constexpr (VEC >= 2 && 64 * VEC * sizeof(T) <= 1024)
+        if constexpr (64 * VEC * sizeof(T) <= 1024)
             MG_LAUNCH((k_smooth3p_lds<T, VEC, NW, kTripleNz>), dim3(blocks), dim3(64 * NW), s, ev0, ev1, n, (T)ih2,
                       x, e, b, y3, (T)a0, (T)cd0, (T)a1, (T)cd1, (T)a2, (T)cd2, nyb);
         else
@@ -1389,6 +1402,8 @@ hipError_t launch_triple_pro_nw(int n, double ih2, const T* x, const T* e, const
     return hipGetLastError();
 }
 
+// From 128^3: at 64^3 the fused pass (11.1 us) is no faster than the
+// prolongation and the three-step pass apart (5.0 + 5.8 us).
 bool triple_pro_applies(int n, size_t elem) { return g_use_triple_pro && n >= 128 && triple_kernels_apply(n, elem); }
 void set_use_triple_pro(bool on) { g_use_triple_pro = on; }
 
@@ -1397,7 +1412,7 @@ hipError_t launch_prolong_triple_row(int n, double ih2, const T* x, const T* e, 
                                      double cd0, double a1, double cd1, double a2, double cd2, hipStream_t s,
                                      hipEvent_t ev0, hipEvent_t ev1) {
     if (!triple_pro_applies(n, sizeof(T)) || y3 == x || y3 == b || y3 == e) return hipErrorInvalidValue;
-    const int waves = g_triple_waves > 0 ? g_triple_waves : 12;
+    const int waves = g_triple_waves > 0 ? g_triple_waves : (n <= 64 ? 8 : 12);
     if (waves == 8)
         return launch_triple_pro_nw<T, 8>(n, ih2, x, e, b, y3, a0, cd0, a1, cd1, a2, cd2, s, ev0, ev1);
     if (waves == 16)
