@@ -3,6 +3,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "sums.h"
+
 namespace mg {
 
 bool row_kernels_apply(int n);
@@ -22,7 +24,8 @@ hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, cons
 // xp may be nullptr for x_prev = 0).  y2 and y1 must not alias x, xp or b.
 // x0_mode != 0: the first three steps of a pass from zero instead; x and xp
 // are not read, the first step x = cd0 * b is formed on the fly in T, and
-// (a1, cd1) and (a2, cd2) are steps 1 and 2.
+// (a1, cd1) and (a2, cd2) are steps 1 and 2.  sums (pass from zero only):
+// an extra block also finishes those partial sums (sums.h).
 // pair_kernels_apply tells whether n and the element size are supported.
 bool pair_kernels_apply(int n, size_t elem);
 // Three steps in one pass from x with x_prev = 0 (the start of a smoothing
@@ -52,7 +55,7 @@ template <typename T>
 hipError_t launch_smooth_pair_row(int n, double ih2, const T* x, const T* xp, const T* b, T* y2, T* y1,
                                   double a1, double cd1, double a2, double cd2, hipStream_t s,
                                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, int x0_mode = 0,
-                                  double cd0 = 0.0);
+                                  double cd0 = 0.0, const SumsJob* sums = nullptr);
 template <typename TA, typename TR, typename TE>
 hipError_t launch_outer_row(int n, double ih2, const double* phi_in, const TE* e, double* phi_out, const double* b,
                             double bmean, TR* r, TR* x1, double cd0, double* partials, hipStream_t s);

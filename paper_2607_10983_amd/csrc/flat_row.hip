@@ -15,6 +15,7 @@
 
 #include "fma.h"
 #include "launch.h"
+#include "sums.h"
 
 #include <cstdint>
 
@@ -395,6 +396,9 @@ __global__ __launch_bounds__(64 * W) void k_smooth_lds(int n, T ih2, const T* x,
 // the pointwise first step x = cd0 b (cd0 = c0 / D), formed from the b rows
 // in T exactly as the single step from zero and the outer residual kernel
 // form it, and xp = 0.  One pass then reads b and writes the third step.
+// With a sums job (job.count > 0), one extra block (the last) finishes the
+// partial sums of the outer residual launch that produced b, instead of a
+// launch of its own.
 // =====================================================================================
 template <typename T, bool FROMB>
 __device__ __forceinline__ T first_step(T r, T cd0) {
@@ -406,13 +410,24 @@ template <typename T, int VEC, int NW, bool PREV1, bool Y1OUT, bool FROMB = fals
 __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* __restrict__ x,
                                                          const T* __restrict__ xp, const T* __restrict__ b,
                                                          T* __restrict__ y2, T* __restrict__ y1o, T a1, T cd1, T a2,
-                                                         T cd2, int nz, int nyb, T cd0) {
+                                                         T cd2, int nz, int nyb, T cd0, SumsJob job) {
     static_assert(!(FROMB && PREV1), "a pass from zero has no x_prev");
     constexpr int NR = 64 * VEC;
     constexpr int W = NW - 2;
     __shared__ T rows[2][NW][NR];
     const RowGrid g{n, n - 1};
-    const int lb = xcd_logical(blockIdx.x, gridDim.x);
+    int nb = gridDim.x;
+    if constexpr (FROMB) {
+        if (job.count > 0) {
+            nb -= 1;
+            if ((int)blockIdx.x == nb) {
+                __shared__ double sh[kSumLanes];
+                finish_sums(job, sh);
+                return;
+            }
+        }
+    }
+    const int lb = xcd_logical(blockIdx.x, nb);
     const int yb = lb % nyb, zc = lb / nyb;
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -1269,8 +1284,9 @@ void set_pair_prefetch(int planes) {
 
 // launch of one k_smooth2_lds variant inside launch_pair_nw (VEC from DISPATCH_VEC)
 #define MG_PAIR1(PREV1, Y1OUT, FROMB, PF2, NZC)                                                                 \
-    MG_LAUNCH((k_smooth2_lds<T, VEC, NW, PREV1, Y1OUT, FROMB, PF2, NZC>), dim3(blocks), dim3(64 * NW), s, ev0, ev1, \
-              n, (T)ih2, x, xp, b, y2, y1, (T)a1, (T)cd1, (T)a2, (T)cd2, nz, nyb, (T)cd0)
+    MG_LAUNCH((k_smooth2_lds<T, VEC, NW, PREV1, Y1OUT, FROMB, PF2, NZC>), dim3(blocks + (FROMB ? extra : 0)),      \
+              dim3(64 * NW), s, ev0, ev1, n, (T)ih2, x, xp, b, y2, y1, (T)a1, (T)cd1, (T)a2, (T)cd2, nz, nyb,     \
+              (T)cd0, FROMB ? sums : SumsJob{})
 #define MG_PAIR(PREV1, Y1OUT, FROMB)                                          \
     do {                                                                      \
         if (pf2) MG_PAIR1(PREV1, Y1OUT, FROMB, true, 0);                      \
@@ -1281,7 +1297,8 @@ void set_pair_prefetch(int planes) {
 template <typename T, int NW>
 hipError_t launch_pair_nw(int n, double ih2, const T* x, const T* xp, const T* b, T* y2, T* y1, double a1, double cd1,
                           double a2, double cd2, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, int x0_mode,
-                          double cd0) {
+                          double cd0, const SumsJob& sums) {
+    const int extra = sums.count > 0 ? 1 : 0;  // the block that finishes the sums (pass from zero only)
     constexpr int W = NW - 2;
     const int nyb = (n + W - 1) / W;
     int nz = g_pair_nz;
@@ -1322,8 +1339,10 @@ hipError_t launch_pair_nw(int n, double ih2, const T* x, const T* xp, const T* b
 template <typename T>
 hipError_t launch_smooth_pair_row(int n, double ih2, const T* x, const T* xp, const T* b, T* y2, T* y1,
                                   double a1, double cd1, double a2, double cd2, hipStream_t s, hipEvent_t ev0,
-                                  hipEvent_t ev1, int x0_mode, double cd0) {
+                                  hipEvent_t ev1, int x0_mode, double cd0, const SumsJob* sums_job) {
     if (!pair_kernels_apply(n, sizeof(T))) return hipErrorInvalidValue;
+    const SumsJob sums = sums_job ? *sums_job : SumsJob{};
+    if (sums.count > 0 && x0_mode == 0) return hipErrorInvalidValue;
     if (x0_mode == 0 && x == nullptr) return hipErrorInvalidValue;
     if (x0_mode != 0 && xp != nullptr) return hipErrorInvalidValue;
     int waves = g_pair_waves;
@@ -1336,10 +1355,10 @@ hipError_t launch_smooth_pair_row(int n, double ih2, const T* x, const T* xp, co
         if (2ull * waves * row > kPairLdsBudget) waves = 8;
     }
     if (waves == 8)
-        return launch_pair_nw<T, 8>(n, ih2, x, xp, b, y2, y1, a1, cd1, a2, cd2, s, ev0, ev1, x0_mode, cd0);
+        return launch_pair_nw<T, 8>(n, ih2, x, xp, b, y2, y1, a1, cd1, a2, cd2, s, ev0, ev1, x0_mode, cd0, sums);
     if (waves == 12)
-        return launch_pair_nw<T, 12>(n, ih2, x, xp, b, y2, y1, a1, cd1, a2, cd2, s, ev0, ev1, x0_mode, cd0);
-    return launch_pair_nw<T, 16>(n, ih2, x, xp, b, y2, y1, a1, cd1, a2, cd2, s, ev0, ev1, x0_mode, cd0);
+        return launch_pair_nw<T, 12>(n, ih2, x, xp, b, y2, y1, a1, cd1, a2, cd2, s, ev0, ev1, x0_mode, cd0, sums);
+    return launch_pair_nw<T, 16>(n, ih2, x, xp, b, y2, y1, a1, cd1, a2, cd2, s, ev0, ev1, x0_mode, cd0, sums);
 }
 
 // Three-step kernel: 12 waves (8 output rows) per block, chunks of
@@ -1502,10 +1521,10 @@ template hipError_t launch_smooth_row<double>(int, double, const double*, const 
                                               double, double, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_smooth_pair_row<float>(int, double, const float*, const float*, const float*, float*,
                                                   float*, double, double, double, double, hipStream_t, hipEvent_t,
-                                                  hipEvent_t, int, double);
+                                                  hipEvent_t, int, double, const SumsJob*);
 template hipError_t launch_smooth_pair_row<double>(int, double, const double*, const double*, const double*,
                                                    double*, double*, double, double, double, double, hipStream_t,
-                                                   hipEvent_t, hipEvent_t, int, double);
+                                                   hipEvent_t, hipEvent_t, int, double, const SumsJob*);
 template hipError_t launch_rr_row<float>(int, double, const float*, const float*, float*, hipStream_t);
 template hipError_t launch_rr_row<double>(int, double, const double*, const double*, double*, hipStream_t);
 template hipError_t launch_prolong_row<float>(int, const float*, float*, hipStream_t);

@@ -12,6 +12,7 @@
 
 #include "launch.h"
 #include "stencil.h"
+#include "sums.h"
 
 #include <cmath>
 #include <cstdint>
@@ -258,19 +259,10 @@ __global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ pa
 }
 
 // out[slot + k] = sum of partials[k * count .. (k + 1) * count), k < arrays
-__global__ __launch_bounds__(1024) void k_finalize_multi(const double* __restrict__ partials, int count, int arrays,
-                                                         double* out, int slot, double* host_out) {
-    __shared__ double sh[1024];
-    const int tid = threadIdx.x;
-    for (int k = 0; k < arrays; ++k) {
-        double v = 0.0;
-        for (int i = tid; i < count; i += 1024) v += partials[(size_t)k * count + i];
-        const double r = block_sum(v, sh);
-        if (tid == 0) {
-            out[slot + k] = r;
-            if (host_out) host_out[slot + k] = r;  // pinned host mirror: no separate copy
-        }
-    }
+// (host_out: pinned host mirror, no separate copy)
+__global__ __launch_bounds__(kSumLanes) void k_finalize_multi(SumsJob job) {
+    __shared__ double sh[kSumLanes];
+    finish_sums(job, sh);
 }
 
 // =====================================================================================
@@ -695,7 +687,8 @@ hipError_t launch_finalize_sum(const double* partials, int count, double* out, i
 }
 hipError_t launch_finalize_sums(const double* partials, int count, int arrays, double* out, int slot,
                                 hipStream_t s, double* host_out) {
-    hipLaunchKernelGGL(k_finalize_multi, dim3(1), dim3(1024), 0, s, partials, count, arrays, out, slot, host_out);
+    const SumsJob job{partials, count, arrays, out, slot, host_out};
+    hipLaunchKernelGGL(k_finalize_multi, dim3(1), dim3(kSumLanes), 0, s, job);
     return hipGetLastError();
 }
 hipError_t launch_finalize_max(const double* partials, int count, double* out, int slot, hipStream_t s) {

@@ -60,6 +60,10 @@ struct mg_ctx {
     int nparts_outer = 0;  // partial sums written by launch_outer_residual
     double* dscal = nullptr;    // device scalars
     double* hscal = nullptr;    // pinned host mirror
+    // The outer sums wait to be finished by the next pass from zero on level 0
+    // (an extra block of that kernel) instead of a finalize launch.
+    bool pending_sums = false;
+    bool fuse_sums = true;
     double* Q = nullptr;        // coarsest seven-point basis and eigenvalues
     double* lam1 = nullptr;
     double* G = nullptr;        // coarsest variable-coefficient pseudo-inverse
@@ -387,9 +391,17 @@ mg_status smooth_level(mg_ctx* c, int l, bool from_zero) {
             const bool y1 = cheb && v > 3;
             const int out = 0, mid = y1 ? 1 : -1;
             const double D = -6.0 * L.ih2;
+            // on level 0 the pending outer sums are finished by an extra block
+            const bool sums = l == 0 && c->pending_sums;
+            const SumsJob job{c->partials, c->nparts_outer, 3, c->dscal, 1, c->hscal};
             HIPCHK(c, launch_smooth_pair_row<T>(L.n, L.ih2, nullptr, nullptr, (const T*)L.b, bufs[out],
                                                 mid >= 0 ? bufs[mid] : nullptr, L.a[1], L.c[1] / D, L.a[2],
-                                                L.c[2] / D, c->stream, ev0, ev1, 1, L.c[0] / D));
+                                                L.c[2] / D, c->stream, ev0, ev1, 1, L.c[0] / D,
+                                                sums ? &job : nullptr));
+            if (sums) {
+                HIPCHK(c, hipEventRecord(c->norm_ev, c->stream));
+                c->pending_sums = false;
+            }
             bytes = (2.0 + (mid >= 0 ? 1.0 : 0.0)) * fbytes;  // b; x_3 [, x_2]
             prev = mid;
             cur = out;
@@ -733,6 +745,7 @@ static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype, cons
     // two-step smoothing kernels; MG_NO_PAIR keeps every step a kernel of its own
     c->use_pairs = std::getenv("MG_NO_PAIR") == nullptr;
     c->use_visits = std::getenv("MG_NO_VISIT") == nullptr;
+    c->fuse_sums = std::getenv("MG_NO_FUSED_SUMS") == nullptr;
     c->lev.resize(p.levels);
     for (int l = 0; l < p.levels; ++l) {
         Level& L = c->lev[l];
@@ -951,11 +964,28 @@ static mg_status post_outer_sums(mg_ctx* c) {
     HIPCHK(c, hipEventRecord(c->norm_ev, c->stream));
     return MG_OK;
 }
-// Outer residual of the solve loop and its three sums.
+// Level 0's inner V-cycle starts with the pass-from-zero kernel, which can
+// finish the outer sums in an extra block.
+static bool sums_in_pass_from_zero(const mg_ctx* c) {
+    return c->fuse_sums && c->lev.size() > 1 && c->tail_start != 0 && !visit_level(c, 0) && from_zero_triple(c, 0);
+}
+// Outer residual of the solve loop and its three sums.  When a V-cycle is
+// enqueued right after it (cycle_follows) and starts with the pass from zero,
+// the sums are left pending for that kernel; flush_sums finishes them
+// otherwise.  Either way norm_ev marks when the host may read them.
 static mg_status outer_with_sums(mg_ctx* c, const double* phi_in, const void* e, double* phi_out, const double* b,
-                                 double bmean) {
+                                 double bmean, bool cycle_follows) {
     mg_status st = outer_residual(c, phi_in, e, phi_out, b, bmean, true);
     if (st != MG_OK) return st;
+    if (cycle_follows && sums_in_pass_from_zero(c)) {
+        c->pending_sums = true;
+        return MG_OK;
+    }
+    return post_outer_sums(c);
+}
+static mg_status flush_sums(mg_ctx* c) {
+    if (!c->pending_sums) return MG_OK;
+    c->pending_sums = false;
     return post_outer_sums(c);
 }
 static mg_status wait_scalars(mg_ctx* c) {
@@ -973,13 +1003,15 @@ static mg_status solve_impl(mg_ctx* c, double* phi, const double* b, double tol,
     const double bmean = c->hscal[0] * invN;
     if (!std::isfinite(bmean)) return fail(c, MG_ERR_NONFINITE, "source contains NaN or Inf");
     // the outer kernel also sums (b - bmean)^2 (slot 1) and phi (slot 3) beside r^2 (slot 2)
-    if ((st = outer_with_sums(c, phi, nullptr, nullptr, b, bmean)) != MG_OK) return st;
     // Look-ahead: the next V-cycle depends only on device data (the residual
     // just formed), so it is enqueued before the host waits for the norm; it
     // is skipped when the measured contraction predicts convergence.  A
     // look-ahead cycle that turns out unneeded only wrote hierarchy buffers.
+    c->pending_sums = false;
     bool ahead = max_cycles > 0;
+    if ((st = outer_with_sums(c, phi, nullptr, nullptr, b, bmean, ahead)) != MG_OK) return st;
     if (ahead && (st = inner_vcycle(c)) != MG_OK) return st;
+    if ((st = flush_sums(c)) != MG_OK) return st;
     if ((st = wait_scalars(c)) != MG_OK) return st;
     const double nb = std::sqrt(c->hscal[1]);
     if (info) {
@@ -1011,10 +1043,11 @@ static mg_status solve_impl(mg_ctx* c, double* phi, const double* b, double tol,
     mg_status result = MG_OK;
     while (rel > tol && cycles < max_cycles) {
         if (!ahead && (st = inner_vcycle(c)) != MG_OK) return st;
-        if ((st = outer_with_sums(c, cur, inner_e(c), other, b, bmean)) != MG_OK) return st;
-        std::swap(cur, other);
         ahead = cycles + 1 < max_cycles && rho * rel > tol;
+        if ((st = outer_with_sums(c, cur, inner_e(c), other, b, bmean, ahead)) != MG_OK) return st;
+        std::swap(cur, other);
         if (ahead && (st = inner_vcycle(c)) != MG_OK) return st;
+        if ((st = flush_sums(c)) != MG_OK) return st;
         if ((st = wait_scalars(c)) != MG_OK) return st;
         prev2 = prev1;
         prev1 = rel;
