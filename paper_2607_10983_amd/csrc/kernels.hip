@@ -240,6 +240,9 @@ __global__ __launch_bounds__(kThreads) void k_block_sums(int n, const double* __
     const int yi = blockIdx.y * blockDim.y + threadIdx.y;
     const int z0 = blockIdx.z * nz;
     double s = 0.0;
+    // unrolled so that several planes' loads are in flight (39 -> 35 us at 256^3);
+    // the sum keeps its z order
+#pragma unroll 8
     for (int z = z0; z < z0 + nz; ++z) {
         const double v = u[g(xi, yi, z)] - shift;
         s += p == 2 ? v * v : v;
