@@ -99,9 +99,10 @@ def model_bytes_per_cycle(n, levels, degree, precision):
     every field element each kernel reads or writes counted once, following the
     library's schedule: multi-step kernels on levels 64 <= n_l (two-step rows up
     to 2 KB, three-step rows up to 1 KB; from 128^3 the three-step pass forms
-    x + P e itself, so the prolongation writes nothing), the 32^3 level of a
-    float hierarchy as two fused visits, the outer kernel writing the first step
-    from zero only where the fine level has no pass-from-zero kernel."""
+    x + P e itself, so the prolongation writes nothing), the 32^3 and 64^3
+    levels of a float hierarchy as two fused visits each, the outer kernel
+    writing the first step from zero only where the fine level has no
+    pass-from-zero kernel."""
     s = 8 if precision == "fp64" else 4
     tot = 0.0
     tail_start = next((l for l in range(levels) if n >> l <= 16), levels)
@@ -109,7 +110,7 @@ def model_bytes_per_cycle(n, levels, degree, precision):
         nl = n >> l
         pairs = 64 <= nl <= 1024 and nl * s <= 2048
         triple = 64 <= nl and nl * s <= 1024
-        if precision != "fp64" and nl == 32 and degree <= 3 and l != tail_start:
+        if precision != "fp64" and nl in (32, 64) and degree <= 3 and l != tail_start:
             tot += nl ** 3 * ((2 * s + s / 8) + (3 * s + s / 8))  # fused pre and post visits
             continue
         x1_outer = l == 0 and not (pairs and degree >= 3)

@@ -970,12 +970,13 @@ __global__ __launch_bounds__(64 * W) void k_outer_lds(int n, TA ih2, const doubl
 // =====================================================================================
 // Residual + full-weighting restriction: one wave per coarse row Y, marching
 // fine planes; fine rows 2Y-1, 2Y, 2Y+1 are formed, combined in y, then in x
-// across lanes, then accumulated in z.
+// across lanes, then accumulated in z, each with fw3's rounding.
 // =====================================================================================
 template <typename T, int VEC>
 __global__ __launch_bounds__(kBlock) void k_rr_row(int n, T ih2, const T* __restrict__ x,
                                                    const T* __restrict__ b, T* __restrict__ coarse, int nzc,
                                                    int nyb) {
+#pragma clang fp contract(off)  // full weighting in y, then x, then z, as fw3 rounds it
     constexpr int CV = VEC >= 2 ? VEC / 2 : 1;
     const int nc = n >> 1;
     const RowGrid g{n, n - 1};
@@ -1017,7 +1018,7 @@ __global__ __launch_bounds__(kBlock) void k_rr_row(int n, T ih2, const T* __rest
         flat7_row<T, VEC>(c2, c1, hp, m2, p2, ih2, M2);
 #pragma unroll
         for (int e = 0; e < VEC; ++e)
-            s[e] = T(0.25) * (b0[e] - M0[e]) + T(0.5) * (b1[e] - M1[e]) + T(0.25) * (b2[e] - M2[e]);
+            s[e] = fw3<T>(b0[e] - M0[e], b1[e] - M1[e], b2[e] - M2[e]);
         // x: coarse element q <-> fine 2q; needs fine 2q-1 (previous lane's last for q = 0)
         T sx[CV];
         if constexpr (VEC >= 2) {
@@ -1025,11 +1026,11 @@ __global__ __launch_bounds__(kBlock) void k_rr_row(int n, T ih2, const T* __rest
 #pragma unroll
             for (int q = 0; q < CV; ++q) {
                 const T l = q > 0 ? s[2 * q - 1] : lft;
-                sx[q] = T(0.25) * l + T(0.5) * s[2 * q] + T(0.25) * s[2 * q + 1];
+                sx[q] = fw3<T>(l, s[2 * q], s[2 * q + 1]);
             }
         } else {
             const T l = lane_rot(s[0], -1), r = lane_rot(s[0], 1);
-            sx[0] = T(0.25) * l + T(0.5) * s[0] + T(0.25) * r;
+            sx[0] = fw3<T>(l, s[0], r);
         }
         // z: odd fine plane 2Z-1 opens coarse plane Z, 2Z adds 1/2, 2Z+1 closes it
         const bool odd = (k & 1) == 0;  // k = 0 <-> z = 2 Z0 - 1

@@ -1,5 +1,5 @@
-// Fused level visits of the 32^3 seven-point level with Chebyshev smoothing
-// (visit.hip).  Internal interface.
+// Fused level visits of the 32^3 and 64^3 seven-point levels with Chebyshev
+// smoothing (visit.hip).  Internal interface.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -8,7 +8,8 @@ namespace mg {
 // Largest smoothing degree a fused visit handles (its plane stacks must fit LDS).
 constexpr int kVisitMaxDegree = 3;
 
-// True when the level (n^3 points, smoothing degree) can be visited fused.
+// True when the level (n^3 points, n = 32 or 64, smoothing degree) can be
+// visited fused.
 bool visit_applies(int n, int degree);
 
 // Pre-smoothing from zero, residual and full weighting in one launch:

@@ -441,13 +441,13 @@ def test_two_step_kernel_matches_single_steps(mgpu, monkeypatch, n, prec, degree
     assert torch.equal(ps, pf)
 
 
-@pytest.mark.parametrize("n,levels", [(32, 4), (32, 2), (64, 5), (256, 7)])
+@pytest.mark.parametrize("n,levels", [(32, 4), (32, 2), (64, 5), (64, 3), (128, 6), (256, 7)])
 @pytest.mark.parametrize("degree", [1, 2, 3])
 def test_level_visit_matches_unfused(mgpu, monkeypatch, n, levels, degree):
-    """The fused visit of the 32^3 level (smoothing from zero, residual and
-    full weighting in one launch; prolongation and smoothing in another) uses
-    the point formulas of the separate kernels: mixed-precision solves agree
-    bitwise with MG_NO_VISIT, cycle by cycle."""
+    """The fused visits of the 32^3 and 64^3 levels (smoothing from zero,
+    residual and full weighting in one launch; prolongation and smoothing in
+    another) use the point formulas of the separate kernels: mixed-precision
+    solves agree bitwise with MG_NO_VISIT, cycle by cycle."""
     b = dev(flat_source(n, 5))
     kw = dict(levels=levels, degree=degree, precision="mixed")
     monkeypatch.setenv("MG_NO_VISIT", "1")
