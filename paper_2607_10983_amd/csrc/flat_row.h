@@ -34,6 +34,7 @@ bool pair_kernels_apply(int n, size_t elem);
 bool triple_kernels_apply(int n, size_t elem);
 void set_use_triple(bool on);
 void set_triple_waves(int waves);
+void set_fromb_waves(int waves);
 // The same pass starting from x0 = x + P e (e on the (n/2)^3 grid), x0 formed
 // on the fly and never written: y3 after three steps from x0.  n >= 128.
 bool triple_pro_applies(int n, size_t elem);

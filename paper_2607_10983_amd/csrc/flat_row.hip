@@ -73,11 +73,24 @@ __device__ __forceinline__ void copyrow(T (&d)[VEC], const T (&s)[VEC]) {
     for (int e = 0; e < VEC; ++e) d[e] = s[e];
 }
 
-// Rotating cross-lane move: value of lane (lane + delta) mod 64.
+// Rotating cross-lane move: value of lane (lane + delta) mod 64, delta = +1
+// or -1.  A DPP move across the whole wave (wave_rol:1 brings lane + 1,
+// wave_ror:1 lane - 1): plain VALU, no trip through the LDS crossbar.
+__device__ __forceinline__ int lane_rot32(int v, int delta) {
+    return delta > 0 ? __builtin_amdgcn_update_dpp(0, v, 0x134, 0xF, 0xF, false)
+                     : __builtin_amdgcn_update_dpp(0, v, 0x13C, 0xF, 0xF, false);
+}
 template <typename T>
 __device__ __forceinline__ T lane_rot(T v, int delta) {
-    const int lane = threadIdx.x & 63;
-    return __shfl(v, (lane + delta) & 63, 64);
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, lane_rot32(__builtin_bit_cast(int, v), delta));
+    } else {
+        v2i h = __builtin_bit_cast(v2i, v);
+        h.x = lane_rot32(h.x, delta);
+        h.y = lane_rot32(h.y, delta);
+        return __builtin_bit_cast(T, h);
+    }
 }
 
 // M x on one row: c = centre row, ym/yp = rows y-1/y+1, zm/zp = planes z-1/z+1.
@@ -113,6 +126,13 @@ __device__ __forceinline__ int xcd_logical(int bid, int nb) {
     return (bid & 7) * (nb >> 3) + (bid >> 3);
 }
 
+// Index of the calling wave in its block, as a wave-uniform (scalar) value:
+// row and plane offsets derived from it are then formed by the scalar unit.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+// Row addressing of a periodic n^3 level.  Every row kernel is instantiated
+// for n = 64 * VEC (a lane holds VEC points of a row), so the kernels build
+// it from VEC and its sizes are compile-time constants.
 struct RowGrid {
     int n, mask;
     __device__ __forceinline__ size_t row(int y, int z) const {
@@ -127,10 +147,10 @@ template <typename T, int VEC, bool HASX, bool PREV>
 __global__ __launch_bounds__(kBlock) void k_smooth_row(int n, T ih2, const T* x, const T* xprev,
                                                        const T* __restrict__ b, T* out, T a, T cd, int nz,
                                                        int nyb) {
-    const RowGrid g{n, n - 1};
+    const RowGrid g{64 * VEC, 64 * VEC - 1};
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int yb = lb % nyb, zc = lb / nyb;
-    const int y = yb * kWaves + (threadIdx.x >> 6);
+    const int y = yb * kWaves + wave_id();
     const int z0 = zc * nz;
     const size_t off = (size_t)(threadIdx.x & 63) * VEC;
     if constexpr (!HASX) {
@@ -231,10 +251,10 @@ __global__ __launch_bounds__(kBlock) void k_outer_row(int n, TA ih2, const doubl
                                                       TR* __restrict__ r, TR* __restrict__ x1, TA cd0,
                                                       double* __restrict__ partials, int nz, int nyb) {
     __shared__ double sh[3 * kWaves];
-    const RowGrid g{n, n - 1};
+    const RowGrid g{64 * VEC, 64 * VEC - 1};
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int yb = lb % nyb, zc = lb / nyb;
-    const int wave = threadIdx.x >> 6;
+    const int wave = wave_id();
     const int y = yb * kWaves + wave;
     const int z0 = zc * nz;
     const size_t off = (size_t)(threadIdx.x & 63) * VEC;
@@ -328,10 +348,10 @@ __global__ __launch_bounds__(64 * W) void k_smooth_lds(int n, T ih2, const T* x,
                                                        int nyb) {
     constexpr int NR = 64 * VEC;
     __shared__ T rows[2][W + 2][NR];
-    const RowGrid g{n, n - 1};
+    const RowGrid g{64 * VEC, 64 * VEC - 1};
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int yb = lb % nyb, zc = lb / nyb;
-    const int w = threadIdx.x >> 6;
+    const int w = wave_id();
     const int y0 = yb * W;
     const int y = y0 + w;
     const int z0 = zc * nz;
@@ -415,7 +435,7 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
     constexpr int NR = 64 * VEC;
     constexpr int W = NW - 2;
     __shared__ T rows[2][NW][NR];
-    const RowGrid g{n, n - 1};
+    const RowGrid g{64 * VEC, 64 * VEC - 1};
     int nb = gridDim.x;
     if constexpr (FROMB) {
         if (job.count > 0) {
@@ -429,7 +449,7 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
     }
     const int lb = xcd_logical(blockIdx.x, nb);
     const int yb = lb % nyb, zc = lb / nyb;
-    const int w = threadIdx.x >> 6;
+    const int w = wave_id();
     const int lane = threadIdx.x & 63;
     const int y = yb * W - 1 + w;  // rows outside [0, n) wrap for loads
     const bool outw = w >= 1 && w <= W && y < n;
@@ -665,10 +685,10 @@ __global__ __launch_bounds__(64 * NW) void k_smooth3_lds(int n, T ih2, const T* 
     constexpr int W = NW - 4;
     __shared__ T rows1[2][NW][NR];
     __shared__ T rows2[2][NW][NR];
-    const RowGrid g{n, n - 1};
+    const RowGrid g{64 * VEC, 64 * VEC - 1};
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int yb = lb % nyb, zc = lb / nyb;
-    const int w = threadIdx.x >> 6;
+    const int w = wave_id();
     const int lane = threadIdx.x & 63;
     const int y = yb * W - 2 + w;  // rows outside [0, n) wrap for loads
     const bool st2 = w >= 1 && w <= NW - 2;
@@ -766,11 +786,11 @@ __global__ __launch_bounds__(64 * NW) void k_smooth3p_lds(int n, T ih2, const T*
     __shared__ T rows0[2][NW + 2][NR];  // x0: slot w + 1 = wave w's row, slots 0 / NW + 1 the halo rows
     __shared__ T rows1[2][NW][NR];
     __shared__ T rows2[2][NW][NR];
-    const RowGrid g{n, n - 1};
-    const RowGrid gc{n >> 1, (n >> 1) - 1};
+    const RowGrid g{64 * VEC, 64 * VEC - 1};
+    const RowGrid gc{32 * VEC, 32 * VEC - 1};
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int yb = lb % nyb, zc = lb / nyb;
-    const int w = threadIdx.x >> 6;
+    const int w = wave_id();
     const int lane = threadIdx.x & 63;
     const int y = yb * W - 2 + w;  // rows outside [0, n) wrap for loads (parity and coarse row wrap alike)
     const bool lo = w == 0, hi = w == NW - 1;
@@ -875,10 +895,10 @@ __global__ __launch_bounds__(64 * W) void k_outer_lds(int n, TA ih2, const doubl
     constexpr int NR = 64 * VEC;
     __shared__ TA rows[2][W + 2][NR];
     __shared__ double sh[3 * W];
-    const RowGrid g{n, n - 1};
+    const RowGrid g{64 * VEC, 64 * VEC - 1};
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int yb = lb % nyb, zc = lb / nyb;
-    const int w = threadIdx.x >> 6;
+    const int w = wave_id();
     const int y0 = yb * W;
     const int y = y0 + w;
     const int z0 = zc * nz;
@@ -978,13 +998,13 @@ __global__ __launch_bounds__(kBlock) void k_rr_row(int n, T ih2, const T* __rest
                                                    int nyb) {
 #pragma clang fp contract(off)  // full weighting in y, then x, then z, as fw3 rounds it
     constexpr int CV = VEC >= 2 ? VEC / 2 : 1;
-    const int nc = n >> 1;
-    const RowGrid g{n, n - 1};
+    constexpr int nc = 32 * VEC;
+    const RowGrid g{64 * VEC, 64 * VEC - 1};
     const RowGrid gc{nc, nc - 1};
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int yb = lb % nyb, zc = lb / nyb;
     const int lane = threadIdx.x & 63;
-    const int Y = yb * kWaves + (threadIdx.x >> 6);
+    const int Y = yb * kWaves + wave_id();
     const int Z0 = zc * nzc;
     const int y1 = 2 * Y;
     const size_t off = (size_t)lane * VEC;
@@ -1077,13 +1097,13 @@ __device__ __forceinline__ void coarse_seg(T (&v)[VEC / 2 + 1], const T* row, in
 template <typename T, int VEC>
 __global__ __launch_bounds__(kBlock) void k_prolong_row(int n, const T* __restrict__ e, T* __restrict__ x, int nz,
                                                         int nyb) {
-    const int nc = n >> 1;
-    const RowGrid g{n, n - 1};
+    constexpr int nc = 32 * VEC;
+    const RowGrid g{64 * VEC, 64 * VEC - 1};
     const RowGrid gc{nc, nc - 1};
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int yb = lb % nyb, zc = lb / nyb;
     const int lane = threadIdx.x & 63;
-    const int y = yb * kWaves + (threadIdx.x >> 6);
+    const int y = yb * kWaves + wave_id();
     const int z0 = zc * nz;
     const size_t off = (size_t)lane * VEC;
     for (int k = 0; k < nz; ++k) {
@@ -1277,6 +1297,12 @@ void set_pair_waves(int waves) {
         g_pair_waves_set = true;
     }
 }
+// block of the pass from zero; 0 = by size (measured at 256^3 with 88 VGPRs:
+// 16 waves 36.5 us, 12 waves 39.2, 10 waves 39.0, 8 waves 37.7)
+int g_fromb_waves = 0;
+void set_fromb_waves(int waves) {
+    if (waves == 0 || waves == 8 || waves == 12 || waves == 16) g_fromb_waves = waves;
+}
 void set_pair_unroll(bool on) { g_pair_unroll = on; }
 void set_fromb_pf2(bool on) { g_fromb_pf2 = on; }
 void set_pair_prefetch(int planes) {
@@ -1350,7 +1376,9 @@ hipError_t launch_smooth_pair_row(int n, double ih2, const T* x, const T* xp, co
     // The pass from zero (one field read) runs best in larger blocks where the
     // row fits their register budget: 256^3 16 waves 33.8 us (8: 35.4, 12: 38.3),
     // 128^3 12 waves 7.8 us (8: 8.6), 64^3 8 waves.
-    if (x0_mode != 0 && !g_pair_waves_set) {
+    if (x0_mode != 0 && g_fromb_waves > 0) {
+        waves = g_fromb_waves;
+    } else if (x0_mode != 0 && !g_pair_waves_set) {
         const size_t row = (size_t)n * sizeof(T);
         waves = (n >= 256 && row <= pair_max_row_bytes(16)) ? 16 : (n >= 128 && row <= pair_max_row_bytes(12)) ? 12 : 8;
         if (2ull * waves * row > kPairLdsBudget) waves = 8;

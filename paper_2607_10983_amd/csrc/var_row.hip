@@ -74,11 +74,27 @@ __device__ __forceinline__ void ldcrow(T (&v)[VEC], const TC* p) {
     for (int e = 0; e < VEC; ++e) v[e] = (T)t[e];
 }
 
+// Rotating cross-lane move: value of lane (lane + delta) mod 64, delta = +1
+// or -1, as a DPP move across the whole wave (wave_rol:1 / wave_ror:1).
+__device__ __forceinline__ int lane_rot32(int v, int delta) {
+    return delta > 0 ? __builtin_amdgcn_update_dpp(0, v, 0x134, 0xF, 0xF, false)
+                     : __builtin_amdgcn_update_dpp(0, v, 0x13C, 0xF, 0xF, false);
+}
 template <typename T>
 __device__ __forceinline__ T lane_rot(T v, int delta) {
-    const int lane = threadIdx.x & 63;
-    return __shfl(v, (lane + delta) & 63, 64);
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, lane_rot32(__builtin_bit_cast(int, v), delta));
+    } else {
+        v2i h = __builtin_bit_cast(v2i, v);
+        h.x = lane_rot32(h.x, delta);
+        h.y = lane_rot32(h.y, delta);
+        return __builtin_bit_cast(T, h);
+    }
 }
+
+// Index of the calling wave in its block as a wave-uniform (scalar) value.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // Row shifted by +1 / -1 in x: element e of the result is row[e + 1] / row[e - 1].
 template <typename T, int VEC>
@@ -97,6 +113,8 @@ __device__ __forceinline__ int xcd_logical(int bid, int nb) {
     return (bid & 7) * (nb >> 3) + (bid >> 3);
 }
 
+// Row addressing of a periodic n^3 level; the kernels are instantiated for
+// n = 64 * VEC and build it from VEC, so its sizes are compile-time constants.
 struct RowGrid {
     int n, mask;
     __device__ __forceinline__ size_t row(int y, int z) const {
@@ -322,11 +340,11 @@ template <typename T, typename TC, int VEC, bool HASX, bool PREV, bool ZQ = (VEC
 __global__ __launch_bounds__(kBlock) void k_var_smooth_row(int n, T ih2, const TC* __restrict__ C, const T* x,
                                                            const T* xprev, const T* __restrict__ b, T* out, T a, T c,
                                                            int nz, int nyb) {
-    const RowGrid g{n, n - 1};
-    const size_t N = (size_t)n * n * n;
+    const RowGrid g{64 * VEC, 64 * VEC - 1};
+    constexpr size_t N = (size_t)(64 * VEC) * (64 * VEC) * (64 * VEC);
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int yb = lb % nyb, zc = lb / nyb;
-    const int y = yb * kWaves + (threadIdx.x >> 6);
+    const int y = yb * kWaves + wave_id();
     const int z0 = zc * nz;
     const size_t off = (size_t)(threadIdx.x & 63) * VEC;
     if constexpr (!HASX) {
@@ -376,11 +394,11 @@ template <typename T, typename TC, int VEC, bool WITHB, bool ZQ = (VEC <= 4)>
 __global__ __launch_bounds__(kBlock) void k_var_resid_row(int n, T ih2, const TC* __restrict__ C,
                                                           const T* __restrict__ x, const T* __restrict__ b,
                                                           T* __restrict__ out, int nz, int nyb) {
-    const RowGrid g{n, n - 1};
-    const size_t N = (size_t)n * n * n;
+    const RowGrid g{64 * VEC, 64 * VEC - 1};
+    constexpr size_t N = (size_t)(64 * VEC) * (64 * VEC) * (64 * VEC);
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int yb = lb % nyb, zc = lb / nyb;
-    const int y = yb * kWaves + (threadIdx.x >> 6);
+    const int y = yb * kWaves + wave_id();
     const int z0 = zc * nz;
     const size_t off = (size_t)(threadIdx.x & 63) * VEC;
     const PlainRows<T, T, VEC> src{x};
@@ -424,11 +442,11 @@ __global__ __launch_bounds__(kBlock) void k_var_outer_row(int n, TA ih2, const T
                                                           TR* __restrict__ r, TR* __restrict__ x1, TA c0,
                                                           double* __restrict__ partials, int nz, int nyb) {
     __shared__ double sh[3 * kWaves];
-    const RowGrid g{n, n - 1};
-    const size_t N = (size_t)n * n * n;
+    const RowGrid g{64 * VEC, 64 * VEC - 1};
+    constexpr size_t N = (size_t)(64 * VEC) * (64 * VEC) * (64 * VEC);
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int yb = lb % nyb, zc = lb / nyb;
-    const int wave = threadIdx.x >> 6;
+    const int wave = wave_id();
     const int y = yb * kWaves + wave;
     const int z0 = zc * nz;
     const size_t off = (size_t)(threadIdx.x & 63) * VEC;
