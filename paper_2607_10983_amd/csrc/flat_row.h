@@ -35,6 +35,7 @@ bool triple_kernels_apply(int n, size_t elem);
 void set_use_triple(bool on);
 void set_triple_waves(int waves);
 void set_fromb_waves(int waves);
+void set_triple_nz(int nz);
 // The same pass starting from x0 = x + P e (e on the (n/2)^3 grid), x0 formed
 // on the fly and never written: y3 after three steps from x0.  n >= 128.
 bool triple_pro_applies(int n, size_t elem);

@@ -67,6 +67,42 @@ __device__ __forceinline__ void strow(T* p, const T (&v)[VEC]) {
     }
 }
 
+// A row's copy in LDS.  Rows of at most 16 bytes per lane keep the global
+// layout (lane l at element l * VEC).  Longer rows are stored in 16-byte
+// pieces with piece j of every lane together (lane l's piece j at element
+// (j * 64 + l) * P), so that every 16-byte LDS access of a wave covers
+// consecutive addresses instead of a lane stride of VEC elements, which
+// conflicts on the LDS banks.
+template <typename T, int VEC>
+__device__ __forceinline__ void lds_strow(T* row, int lane, const T (&v)[VEC]) {
+    constexpr int B = VEC * (int)sizeof(T);
+    if constexpr (B <= 16) {
+        strow<T, VEC>(row + (size_t)lane * VEC, v);
+    } else {
+        constexpr int P = 16 / (int)sizeof(T);
+#pragma unroll
+        for (int j = 0; j < VEC / P; ++j) {
+            v4i t;
+            __builtin_memcpy(&t, &v[j * P], 16);
+            *reinterpret_cast<v4i*>(row + (size_t)(j * 64 + lane) * P) = t;
+        }
+    }
+}
+template <typename T, int VEC>
+__device__ __forceinline__ void lds_ldrow(T (&v)[VEC], const T* row, int lane) {
+    constexpr int B = VEC * (int)sizeof(T);
+    if constexpr (B <= 16) {
+        ldrow<T, VEC>(v, row + (size_t)lane * VEC);
+    } else {
+        constexpr int P = 16 / (int)sizeof(T);
+#pragma unroll
+        for (int j = 0; j < VEC / P; ++j) {
+            const v4i t = *reinterpret_cast<const v4i*>(row + (size_t)(j * 64 + lane) * P);
+            __builtin_memcpy(&v[j * P], &t, 16);
+        }
+    }
+}
+
 template <typename T, int VEC>
 __device__ __forceinline__ void copyrow(T (&d)[VEC], const T (&s)[VEC]) {
 #pragma unroll
@@ -377,13 +413,13 @@ __global__ __launch_bounds__(64 * W) void k_smooth_lds(int n, T ih2, const T* x,
             if constexpr (PREV) ldrow<T, VEC>(pn, xprev + g.row(y, z + 1) + off);
             if (lo || hi) ldrow<T, VEC>(hn, x + g.row(yh, z + 1) + off);
         }
-        strow<T, VEC>(&rows[buf][w + 1][off], c);
-        if (lo) strow<T, VEC>(&rows[buf][0][off], h);
-        if (hi) strow<T, VEC>(&rows[buf][W + 1][off], h);
+        lds_strow<T, VEC>(rows[buf][w + 1], lane, c);
+        if (lo) lds_strow<T, VEC>(rows[buf][0], lane, h);
+        if (hi) lds_strow<T, VEC>(rows[buf][W + 1], lane, h);
         __syncthreads();
         T ym[VEC], yp[VEC];
-        ldrow<T, VEC>(ym, &rows[buf][w][off]);
-        ldrow<T, VEC>(yp, &rows[buf][w + 2][off]);
+        lds_ldrow<T, VEC>(ym, rows[buf][w], lane);
+        lds_ldrow<T, VEC>(yp, rows[buf][w + 2], lane);
         T Mx[VEC], o[VEC];
         flat7_row<T, VEC>(c, ym, yp, zm, zp, ih2, Mx);
 #pragma unroll
@@ -522,12 +558,12 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
         }
         if (j >= 2) {
             const int buf = j & 1;
-            strow<T, VEC>(&rows[buf][w][off], sc);
+            lds_strow<T, VEC>(rows[buf][w], lane, sc);
             __syncthreads();
             if (outw) {
                 T nm[VEC], np[VEC], M2[VEC], o[VEC];
-                ldrow<T, VEC>(nm, &rows[buf][w - 1][off]);
-                ldrow<T, VEC>(np, &rows[buf][w + 1][off]);
+                lds_ldrow<T, VEC>(nm, rows[buf][w - 1], lane);
+                lds_ldrow<T, VEC>(np, rows[buf][w + 1], lane);
                 flat7_row<T, VEC>(sc, nm, np, sm, sp, ih2, M2);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) {
@@ -728,21 +764,21 @@ __global__ __launch_bounds__(64 * NW) void k_smooth3_lds(int n, T ih2, const T* 
         T s2p[VEC] = {};
         if (j >= 2) {
             const int buf = j & 1;
-            strow<T, VEC>(&rows1[buf][w][off], s1c);                // y1 at z1-1
-            if (j >= 3 && st2) strow<T, VEC>(&rows2[buf][w][off], s2c);  // y2 at z1-2
+            lds_strow<T, VEC>(rows1[buf][w], lane, s1c);                // y1 at z1-1
+            if (j >= 3 && st2) lds_strow<T, VEC>(rows2[buf][w], lane, s2c);  // y2 at z1-2
             __syncthreads();
             if (st2) {  // stage 2: y2 at z1-1
                 T nm[VEC], np[VEC], M2[VEC];
-                ldrow<T, VEC>(nm, &rows1[buf][w - 1][off]);
-                ldrow<T, VEC>(np, &rows1[buf][w + 1][off]);
+                lds_ldrow<T, VEC>(nm, rows1[buf][w - 1], lane);
+                lds_ldrow<T, VEC>(np, rows1[buf][w + 1], lane);
                 flat7_row<T, VEC>(s1c, nm, np, s1m, s1p, ih2, M2);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) s2p[e] = cheb_step<T>(s1c[e], xm[e], b2[e], M2[e], a1, cd1);
             }
             if (j >= 4 && outw) {  // stage 3: y3 at z1-2
                 T nm[VEC], np[VEC], M3[VEC], o[VEC];
-                ldrow<T, VEC>(nm, &rows2[buf][w - 1][off]);
-                ldrow<T, VEC>(np, &rows2[buf][w + 1][off]);
+                lds_ldrow<T, VEC>(nm, rows2[buf][w - 1], lane);
+                lds_ldrow<T, VEC>(np, rows2[buf][w + 1], lane);
                 flat7_row<T, VEC>(s2c, nm, np, s2m, s2p, ih2, M3);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) o[e] = cheb_step<T>(s2c[e], s1m[e], b3[e], M3[e], a2, cd2);
@@ -832,18 +868,18 @@ __global__ __launch_bounds__(64 * NW) void k_smooth3p_lds(int n, T ih2, const T*
             ldrow<T, VEC>(bn, b + g.row(y, z1 + 1) + off);
         }
         const int buf = j & 1;
-        strow<T, VEC>(&rows0[buf][w + 1][off], xc);
-        if (lo) strow<T, VEC>(&rows0[buf][0][off], h);
-        if (hi) strow<T, VEC>(&rows0[buf][NW + 1][off], h);
-        if (j >= 2) strow<T, VEC>(&rows1[buf][w][off], s1c);                 // y1 at z1-1
-        if (j >= 3 && st2) strow<T, VEC>(&rows2[buf][w][off], s2c);          // y2 at z1-2
+        lds_strow<T, VEC>(rows0[buf][w + 1], lane, xc);
+        if (lo) lds_strow<T, VEC>(rows0[buf][0], lane, h);
+        if (hi) lds_strow<T, VEC>(rows0[buf][NW + 1], lane, h);
+        if (j >= 2) lds_strow<T, VEC>(rows1[buf][w], lane, s1c);                 // y1 at z1-1
+        if (j >= 3 && st2) lds_strow<T, VEC>(rows2[buf][w], lane, s2c);          // y2 at z1-2
         __syncthreads();
         // stage 1: y1 at z1 (x_prev = 0)
         T s1p[VEC];
         {
             T ym[VEC], yp[VEC], M1[VEC];
-            ldrow<T, VEC>(ym, &rows0[buf][w][off]);
-            ldrow<T, VEC>(yp, &rows0[buf][w + 2][off]);
+            lds_ldrow<T, VEC>(ym, rows0[buf][w], lane);
+            lds_ldrow<T, VEC>(yp, rows0[buf][w + 2], lane);
             flat7_row<T, VEC>(xc, ym, yp, xm, xq, ih2, M1);
 #pragma unroll
             for (int q = 0; q < VEC; ++q) s1p[q] = cheb_step<T>(xc[q], T(0), b1[q], M1[q], a0, cd0);
@@ -851,16 +887,16 @@ __global__ __launch_bounds__(64 * NW) void k_smooth3p_lds(int n, T ih2, const T*
         T s2p[VEC] = {};
         if (j >= 2 && st2) {  // stage 2: y2 at z1-1, x_prev = x0 at z1-1
             T nm[VEC], np[VEC], M2[VEC];
-            ldrow<T, VEC>(nm, &rows1[buf][w - 1][off]);
-            ldrow<T, VEC>(np, &rows1[buf][w + 1][off]);
+            lds_ldrow<T, VEC>(nm, rows1[buf][w - 1], lane);
+            lds_ldrow<T, VEC>(np, rows1[buf][w + 1], lane);
             flat7_row<T, VEC>(s1c, nm, np, s1m, s1p, ih2, M2);
 #pragma unroll
             for (int q = 0; q < VEC; ++q) s2p[q] = cheb_step<T>(s1c[q], xm[q], b2[q], M2[q], a1, cd1);
         }
         if (j >= 4 && outw) {  // stage 3: y3 at z1-2, x_prev = y1 at z1-2
             T nm[VEC], np[VEC], M3[VEC], o[VEC];
-            ldrow<T, VEC>(nm, &rows2[buf][w - 1][off]);
-            ldrow<T, VEC>(np, &rows2[buf][w + 1][off]);
+            lds_ldrow<T, VEC>(nm, rows2[buf][w - 1], lane);
+            lds_ldrow<T, VEC>(np, rows2[buf][w + 1], lane);
             flat7_row<T, VEC>(s2c, nm, np, s2m, s2p, ih2, M3);
 #pragma unroll
             for (int q = 0; q < VEC; ++q) o[q] = cheb_step<T>(s2c[q], s1m[q], b3[q], M3[q], a2, cd2);
@@ -925,13 +961,13 @@ __global__ __launch_bounds__(64 * W) void k_outer_lds(int n, TA ih2, const doubl
             ldrow<double, VEC>(bn, b + g.row(y, z + 1) + off);
             if (lo || hi) ld_value<TA, TR, TE, VEC, UPDATE>(hn, phi_in, e, g.row(yh, z + 1) + off);
         }
-        strow<TA, VEC>(&rows[buf][w + 1][off], c);
-        if (lo) strow<TA, VEC>(&rows[buf][0][off], h);
-        if (hi) strow<TA, VEC>(&rows[buf][W + 1][off], h);
+        lds_strow<TA, VEC>(rows[buf][w + 1], lane, c);
+        if (lo) lds_strow<TA, VEC>(rows[buf][0], lane, h);
+        if (hi) lds_strow<TA, VEC>(rows[buf][W + 1], lane, h);
         __syncthreads();
         TA ym[VEC], yp[VEC];
-        ldrow<TA, VEC>(ym, &rows[buf][w][off]);
-        ldrow<TA, VEC>(yp, &rows[buf][w + 2][off]);
+        lds_ldrow<TA, VEC>(ym, rows[buf][w], lane);
+        lds_ldrow<TA, VEC>(yp, rows[buf][w + 2], lane);
         TA Mx[VEC];
         TR ro[VEC];
         flat7_row<TA, VEC>(c, ym, yp, zm, zp, ih2, Mx);
@@ -1393,6 +1429,15 @@ hipError_t launch_smooth_pair_row(int n, double ih2, const T* x, const T* xp, co
 // Three-step kernel: 12 waves (8 output rows) per block, chunks of
 // kTripleNz planes; rows of at most 1 KB (float n <= 256, double n <= 128).
 constexpr int kTripleNz = 8;
+// z chunk of the fused post-smoothing pass in 12-wave blocks from 256^3: 8, 16
+// or 32 planes; 0 = 16.  Below 256^3 the chunk is kTripleNz.  A chunk forms
+// step 0 on NZC + 4 planes for NZC outputs, and each plane costs a barrier
+// round whatever its share of useful work: 256^3 with 12-wave blocks,
+// 8 planes 56.1 us, 16 planes 48.5 us, 32 planes 47.5 us.
+int g_triple_nz = 0;
+void set_triple_nz(int nz) {
+    if (nz == 0 || nz == 8 || nz == 16 || nz == 32) g_triple_nz = nz;
+}
 bool g_use_triple = true;
 bool g_use_triple_pro = true;  // post-smoothing pass fused with the prolongation before it
 // block of the three-step kernel: 8 waves at 64^3, 12 above (measured:
@@ -1439,14 +1484,27 @@ hipError_t launch_triple_pro_nw(int n, double ih2, const T* x, const T* e, const
                                 hipEvent_t ev1) {
     constexpr int W = NW - 4;
     const int nyb = (n + W - 1) / W;
-    const int blocks = nyb * (n / kTripleNz);
+    int nzc = kTripleNz;
+    if (NW == 12 && n >= 256) nzc = g_triple_nz > 0 ? g_triple_nz : 16;
+    if (n % nzc != 0) nzc = kTripleNz;
+    const int blocks = nyb * (n / nzc);
+#define MG_TRIPLE_PRO(NZC)                                                                                       \
+    MG_LAUNCH((k_smooth3p_lds<T, VEC, NW, NZC>), dim3(blocks), dim3(64 * NW), s, ev0, ev1, n, (T)ih2, x, e, b, y3, \
+              (T)a0, (T)cd0, (T)a1, (T)cd1, (T)a2, (T)cd2, nyb)
     DISPATCH_VEC(n, {
-        if constexpr (64 * VEC * sizeof(T) <= 1024)
-            MG_LAUNCH((k_smooth3p_lds<T, VEC, NW, kTripleNz>), dim3(blocks), dim3(64 * NW), s, ev0, ev1, n, (T)ih2,
-                      x, e, b, y3, (T)a0, (T)cd0, (T)a1, (T)cd1, (T)a2, (T)cd2, nyb);
-        else
+        if constexpr (64 * VEC * sizeof(T) <= 1024) {
+            if constexpr (NW == 12) {
+                if (nzc == 32) MG_TRIPLE_PRO(32);
+                else if (nzc == 16) MG_TRIPLE_PRO(16);
+                else MG_TRIPLE_PRO(kTripleNz);
+            } else {
+                MG_TRIPLE_PRO(kTripleNz);
+            }
+        } else {
             return hipErrorInvalidValue;
+        }
     })
+#undef MG_TRIPLE_PRO
     return hipGetLastError();
 }
 

@@ -743,6 +743,7 @@ static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype, cons
     if (const char* t = std::getenv("MG_RR_TARGET")) set_rr_target(std::atoi(t));
     if (const char* t = std::getenv("MG_TRIPLE_WAVES")) set_triple_waves(std::atoi(t));
     if (const char* t = std::getenv("MG_FROMB_WAVES")) set_fromb_waves(std::atoi(t));
+    if (const char* t = std::getenv("MG_TRIPLE_NZ")) set_triple_nz(std::atoi(t));
     // two-step smoothing kernels; MG_NO_PAIR keeps every step a kernel of its own
     c->use_pairs = std::getenv("MG_NO_PAIR") == nullptr;
     c->use_visits = std::getenv("MG_NO_VISIT") == nullptr;
