@@ -452,7 +452,7 @@ __global__ __launch_bounds__(64 * W) void k_smooth_lds(int n, T ih2, const T* x,
 // the pointwise first step x = cd0 b (cd0 = c0 / D), formed from the b rows
 // in T exactly as the single step from zero and the outer residual kernel
 // form it, and xp = 0.  One pass then reads b and writes the third step.
-// With a sums job (job.count > 0), one extra block (the last) finishes the
+// With a sums job (job.count > 0), one extra block (block 0, dispatched first) finishes the
 // partial sums of the outer residual launch that produced b, instead of a
 // launch of its own.
 // =====================================================================================
@@ -472,18 +472,19 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
     constexpr int W = NW - 2;
     __shared__ T rows[2][NW][NR];
     const RowGrid g{64 * VEC, 64 * VEC - 1};
-    int nb = gridDim.x;
+    int nb = gridDim.x, bid = blockIdx.x;
     if constexpr (FROMB) {
-        if (job.count > 0) {
+        if (job.count > 0) {  // block 0 finishes the sums, dispatched first
             nb -= 1;
-            if ((int)blockIdx.x == nb) {
+            bid -= 1;
+            if (bid < 0) {
                 __shared__ double sh[kSumLanes];
                 finish_sums(job, sh);
                 return;
             }
         }
     }
-    const int lb = xcd_logical(blockIdx.x, nb);
+    const int lb = xcd_logical(bid, nb);
     const int yb = lb % nyb, zc = lb / nyb;
     const int w = wave_id();
     const int lane = threadIdx.x & 63;

@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -80,6 +82,13 @@ struct mg_ctx {
     hipGraphExec_t coarse_exec = nullptr;
     int coarse_cur = 0;
     hipEvent_t norm_ev = nullptr;  // completion of the per-cycle norm readback
+    // The sums finished inside the pass from zero need no event: the block
+    // that writes them to the pinned mirror makes them visible at system
+    // scope and then writes sums_seq to hscal[kHostFlagSlot], which the host
+    // polls.  An event there cost a 5.6 us stall between the pass from zero
+    // and the next kernel at 256^3 (4.6 us without its system-scope release).
+    double sums_seq = 0.0;
+    bool scal_flag = false;  // the pending readback is the flag, not norm_ev
     bool use_pairs = true;         // last two steps of a smoothing pass in one two-step kernel
     bool use_visits = true;        // fused visits of the 32^3 level (float hierarchy)
     // conjugate-gradient state (allocated by the first mg_solve_pcg)
@@ -280,8 +289,10 @@ mg_status time_events(mg_ctx* c, bool fine, int kind, hipEvent_t* ev0, hipEvent_
     if (!(c->timing & kind) || !fine) return MG_OK;
     if (c->events_used == c->events.size()) {
         TimingPair tp;
-        HIPCHK(c, hipEventCreate(&tp.start));
-        HIPCHK(c, hipEventCreate(&tp.stop));
+        // timing only: no system-scope release (an L2 writeback of every XCD,
+        // 4-6 us of stall around the timed kernel)
+        HIPCHK(c, hipEventCreateWithFlags(&tp.start, hipEventDisableSystemFence));
+        HIPCHK(c, hipEventCreateWithFlags(&tp.stop, hipEventDisableSystemFence));
         c->events.push_back(tp);
     }
     *ev0 = c->events[c->events_used].start;
@@ -393,13 +404,14 @@ mg_status smooth_level(mg_ctx* c, int l, bool from_zero) {
             const double D = -6.0 * L.ih2;
             // on level 0 the pending outer sums are finished by an extra block
             const bool sums = l == 0 && c->pending_sums;
-            const SumsJob job{c->partials, c->nparts_outer, 3, c->dscal, 1, c->hscal};
+            const SumsJob job{c->partials, c->nparts_outer, 3, c->dscal, 1, c->hscal, sums ? c->sums_seq + 1.0 : 0.0};
             HIPCHK(c, launch_smooth_pair_row<T>(L.n, L.ih2, nullptr, nullptr, (const T*)L.b, bufs[out],
                                                 mid >= 0 ? bufs[mid] : nullptr, L.a[1], L.c[1] / D, L.a[2],
                                                 L.c[2] / D, c->stream, ev0, ev1, 1, L.c[0] / D,
                                                 sums ? &job : nullptr));
             if (sums) {
-                HIPCHK(c, hipEventRecord(c->norm_ev, c->stream));
+                c->sums_seq += 1.0;
+                c->scal_flag = true;
                 c->pending_sums = false;
             }
             bytes = (2.0 + (mid >= 0 ? 1.0 : 0.0)) * fbytes;  // b; x_3 [, x_2]
@@ -779,6 +791,7 @@ static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype, cons
     // coherent: the finalize kernel writes the outer sums into it directly
     HIPCHK(c, hipHostMalloc((void**)&c->hscal, 16 * sizeof(double), hipHostMallocCoherent));
     HIPCHK(c, hipEventCreateWithFlags(&c->norm_ev, hipEventDisableTiming));
+    c->hscal[kHostFlagSlot] = 0.0;
 
     if (c->var) {
         // fine coefficients in double, validated, restricted level by level
@@ -957,6 +970,7 @@ static mg_status device_sum(mg_ctx* c, const double* u, double shift, int pw, in
 static mg_status post_scalars(mg_ctx* c, int count) {
     HIPCHK(c, hipMemcpyAsync(c->hscal, c->dscal, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipEventRecord(c->norm_ev, c->stream));
+    c->scal_flag = false;
     return MG_OK;
 }
 // The three outer sums (slots 1..3), finalized straight into the pinned host
@@ -964,6 +978,7 @@ static mg_status post_scalars(mg_ctx* c, int count) {
 static mg_status post_outer_sums(mg_ctx* c) {
     HIPCHK(c, launch_finalize_sums(c->partials, c->nparts_outer, 3, c->dscal, 1, c->stream, c->hscal));
     HIPCHK(c, hipEventRecord(c->norm_ev, c->stream));
+    c->scal_flag = false;
     return MG_OK;
 }
 // Level 0's inner V-cycle starts with the pass-from-zero kernel, which can
@@ -991,7 +1006,27 @@ static mg_status flush_sums(mg_ctx* c) {
     return post_outer_sums(c);
 }
 static mg_status wait_scalars(mg_ctx* c) {
-    HIPCHK(c, hipEventSynchronize(c->norm_ev));
+    if (!c->scal_flag) {
+        HIPCHK(c, hipEventSynchronize(c->norm_ev));
+        return MG_OK;
+    }
+    // Poll the flag.  Only after 50 ms of waiting is the stream asked whether
+    // it still runs: a stream query enqueues a marker, which costs a
+    // 5.8 us stall in front of the next kernel.
+    const volatile double* flag = c->hscal + kHostFlagSlot;
+    auto last = std::chrono::steady_clock::now();
+    for (unsigned i = 1;; ++i) {
+        if (*flag == c->sums_seq) break;
+        if ((i & 4095) != 0) continue;
+        const auto now = std::chrono::steady_clock::now();
+        if (now - last < std::chrono::milliseconds(50)) continue;
+        last = now;
+        const hipError_t e = hipStreamQuery(c->stream);
+        if (e != hipSuccess && e != hipErrorNotReady) HIPCHK(c, e);
+        if (e == hipSuccess && *flag != c->sums_seq) return fail(c, MG_ERR_HIP, "outer sums flag not raised");
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    c->scal_flag = false;
     return MG_OK;
 }
 
@@ -1184,6 +1219,7 @@ mg_status pcg_impl(mg_ctx* c, double* phi, const double* b, double tol, int max_
         true_current = false;
         HIPCHK(c, hipMemcpyAsync(c->hscal, S + kPcgRr, sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipEventRecord(c->norm_ev, c->stream));
+        c->scal_flag = false;
         ahead = its + 1 < max_iter && rho * rel > tol;
         if (ahead && (st = inner_vcycle(c)) != MG_OK) return st;
         if ((st = wait_scalars(c)) != MG_OK) return st;

@@ -21,7 +21,11 @@ struct SumsJob {
     double* out;             // out[slot + k], k < arrays
     int slot;
     double* host_out;        // pinned host mirror, or null
+    double seq;              // nonzero: written to host_out[kHostFlagSlot] once the sums are visible
 };
+
+// Slot of the pinned host mirror that receives SumsJob::seq.
+constexpr int kHostFlagSlot = 15;
 
 // Every thread of the block calls it; sh holds kSumLanes doubles.
 __device__ __forceinline__ void finish_sums(const SumsJob& job, double* sh) {
@@ -44,6 +48,15 @@ __device__ __forceinline__ void finish_sums(const SumsJob& job, double* sh) {
             if (job.host_out) job.host_out[job.slot + k] = sh[0];
         }
         __syncthreads();
+    }
+    // The host may read the mirror without a stream event: make the sums
+    // visible at system scope, then raise the flag the host polls.
+    if (job.host_out && tid == 0) {
+        __threadfence_system();
+        if (job.seq != 0.0) {
+            *reinterpret_cast<volatile double*>(job.host_out + kHostFlagSlot) = job.seq;
+            __threadfence_system();
+        }
     }
 }
 
