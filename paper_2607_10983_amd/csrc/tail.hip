@@ -69,6 +69,54 @@ __device__ __forceinline__ void phase(F f, T* out) {
     __syncthreads();
 }
 
+// 16^3 stencil phases: thread t owns the 4 consecutive x points 4t .. 4t+3
+// (a quarter of an x row), so its own points and the y and z neighbour
+// segments come with one 16-byte LDS access each, and only the two x
+// neighbours beyond the segment are single loads: 7 LDS reads for 4 points
+// instead of 28.  Same expression as Mx_at, point by point.
+template <typename T>
+__device__ __forceinline__ void seg4(T (&v)[4], const T* p) {
+    if constexpr (sizeof(T) == 4) {
+        const float4 t = *reinterpret_cast<const float4*>(p);
+        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    } else {
+        const double2 a = *reinterpret_cast<const double2*>(p);
+        const double2 b = *reinterpret_cast<const double2*>(p + 2);
+        v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    }
+}
+template <typename T>
+__device__ __forceinline__ void put4(T* p, const T (&v)[4]) {
+    if constexpr (sizeof(T) == 4) {
+        *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+    } else {
+        *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+        *reinterpret_cast<double2*>(p + 2) = make_double2(v[2], v[3]);
+    }
+}
+// M u at the 4 points i0 .. i0+3 of a 16^3 level (i0 a multiple of 4); c = u there
+template <typename T>
+__device__ __forceinline__ void Mx16_seg(const T* u, int i0, T ih2, T (&c)[4], T (&Mx)[4]) {
+    constexpr int N = 16, P = N * N * N, mx = N - 1, my = (N - 1) * N, pz = N * N;
+    T ym[4], yp[4], zm[4], zp[4];
+    seg4<T>(c, u + i0);
+    seg4<T>(ym, u + ((i0 & ~my) | ((i0 - N) & my)));
+    seg4<T>(yp, u + ((i0 & ~my) | ((i0 + N) & my)));
+    seg4<T>(zm, u + ((i0 - pz) & (P - 1)));
+    seg4<T>(zp, u + ((i0 + pz) & (P - 1)));
+    const T lft = u[(i0 & ~mx) | ((i0 - 1) & mx)];
+    const T rgt = u[(i0 & ~mx) | ((i0 + 4) & mx)];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const T l = e > 0 ? c[e - 1] : lft;
+        const T r = e < 3 ? c[e + 1] : rgt;
+        T s = l + r;
+        s += ym[e] + yp[e];
+        s += zm[e] + zp[e];
+        Mx[e] = (s - T(6) * c[e]) * ih2;
+    }
+}
+
 constexpr int kTailElems = 3 * (4096 + 512 + 64);  // x0, x1, b of 16^3, 8^3, 4^3
 
 // LDS layout: level l's x0, x1, b follow those of levels 0..l-1.
@@ -108,12 +156,24 @@ __device__ int smooth_pass(const TailArgs<T>& A, const Fields<T>& F, int l, int 
             const int o = use_prev ? prev : 1 - cur;
             const T* xc = F.x(l, cur);
             const T* xp = use_prev ? F.x(l, prev) : nullptr;
-            phase<T, P>([&](int i) {
-                const T Mx = Mx_at<T, N>(xc, i, ih2);
-                const T xi = xc[i];
-                const T pv = use_prev ? xp[i] : T(0);
-                return xi + a * (xi - pv) + c * dinv * (b[i] - Mx);
-            }, F.x(l, o));
+            if constexpr (N == 16 && P == 4 * kTailThreads) {
+                const int i0 = 4 * threadIdx.x;
+                T xi[4], Mx[4], bb[4], pv[4] = {T(0), T(0), T(0), T(0)}, v[4];
+                Mx16_seg<T>(xc, i0, ih2, xi, Mx);
+                seg4<T>(bb, b + i0);
+                if (use_prev) seg4<T>(pv, xp + i0);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = xi[e] + a * (xi[e] - pv[e]) + c * dinv * (bb[e] - Mx[e]);
+                put4<T>(F.x(l, o) + i0, v);
+                __syncthreads();
+            } else {
+                phase<T, P>([&](int i) {
+                    const T Mx = Mx_at<T, N>(xc, i, ih2);
+                    const T xi = xc[i];
+                    const T pv = use_prev ? xp[i] : T(0);
+                    return xi + a * (xi - pv) + c * dinv * (b[i] - Mx);
+                }, F.x(l, o));
+            }
             prev = cur;
             cur = o;
         }
@@ -133,7 +193,18 @@ __device__ int down_level(const TailArgs<T>& A, const Fields<T>& F, int l) {
     T* r = F.x(l, 1 - cl);
     const T* xc = F.x(l, cl);
     const T* b = F.b(l);
-    phase<T, G::P>([&](int i) { return b[i] - Mx_at<T, N>(xc, i, ih2); }, r);
+    if constexpr (N == 16 && G::P == 4 * kTailThreads) {
+        const int i0 = 4 * threadIdx.x;
+        T xi[4], Mx[4], bb[4], v[4];
+        Mx16_seg<T>(xc, i0, ih2, xi, Mx);
+        seg4<T>(bb, b + i0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = bb[e] - Mx[e];
+        put4<T>(r + i0, v);
+        __syncthreads();
+    } else {
+        phase<T, G::P>([&](int i) { return b[i] - Mx_at<T, N>(xc, i, ih2); }, r);
+    }
     phase<T, Gc::P>([&](int i) {
         int X, Y, Z;
         Gc::coords(i, X, Y, Z);
@@ -213,7 +284,7 @@ __device__ void coarsest(const T* bl, T* xl, double* sA, double* sB, const doubl
 
 template <typename T>
 __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> A) {
-    __shared__ T fields[kTailElems];
+    __shared__ __align__(16) T fields[kTailElems];
     __shared__ double sA[512];
     __shared__ double sB[512];
     __shared__ double q[64];
