@@ -282,6 +282,38 @@ __device__ void coarsest(const T* bl, T* xl, double* sA, double* sB, const doubl
     __syncthreads();
 }
 
+// The same solve on a 4^3 coarsest level by one wave: lane i owns point
+// i = x + 4 y + 16 z and takes the other points of its line from their lanes
+// by cross-lane moves, so the six passes need no workgroup barrier.  Same
+// sums in the same order as the workgroup version.
+template <typename T>
+__device__ void coarsest4(const T* bl, T* xl, const double* q, const double* lam) {
+    constexpr int NC = 4;
+    if (threadIdx.x < 64) {
+        const int i = threadIdx.x, x = i & 3, y = (i >> 2) & 3, z = i >> 4;
+        auto pass = [&](double u, int axis, bool forward) {
+            const int k = axis == 0 ? x : axis == 1 ? y : z;
+            const int stride = axis == 0 ? 1 : axis == 1 ? NC : NC * NC;
+            const int base = i - k * stride;
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < NC; ++j)
+                acc += (forward ? q[j + NC * k] : q[k + NC * j]) * __shfl(u, base + j * stride, 64);
+            return acc;
+        };
+        double v = (double)bl[i];
+        v = pass(v, 0, true);
+        v = pass(v, 1, true);
+        v = pass(v, 2, true);
+        v = (x == 0 && y == 0 && z == 0) ? 0.0 : v / (lam[x] + lam[y] + lam[z]);
+        v = pass(v, 2, false);
+        v = pass(v, 1, false);
+        v = pass(v, 0, false);
+        xl[i] = (T)v;
+    }
+    __syncthreads();
+}
+
 template <typename T>
 __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> A) {
     __shared__ __align__(16) T fields[kTailElems];
@@ -312,7 +344,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> A) {
     {
         const int l = nl - 1;
         if (ncst == 8) coarsest<T, 8>(F.b(l), F.x(l, 0), sA, sB, q, lam);
-        else coarsest<T, 4>(F.b(l), F.x(l, 0), sA, sB, q, lam);
+        else coarsest4<T>(F.b(l), F.x(l, 0), q, lam);
         curbits &= ~(1u << l);
     }
     // ---------------- up leg
