@@ -11,12 +11,15 @@ All inputs are resident in HBM before timing starts.
 
 The JSON line reports V-cycle throughput of the mixed path (value), the same
 sequence in plain float64 (time-to-tolerance ratio), the roofline of the
-dominant kernel (fine-level smoothing step; in-dispatch HIP events around each
-launch, algorithmic bytes counted by the library), a size sweep 32^3 .. 1024^3
-(cold solves to the tolerance, mixed and float64, with the smoothing kernel's
-fraction of the HBM peak; 512^3 and 1024^3 are the large-mesh runs), the
-256^3 moving-mesh solve with its forward/backward timing and the ablation of
-its smoother and coarse operators, the initial-guess predictors and
+dominant kernel of the step (the fine-level kernel kind with the largest
+share of the step's time; in-dispatch HIP events around each launch,
+algorithmic bytes counted by the library) with every other fine-level kernel
+beside it, the 512^3 V-cycle (20 event-timed warm cycles, median of 5, whole
+cycle against the HBM roofline, and every fine kernel's rate), a size sweep
+32^3 .. 1024^3 (cold solves to the tolerance in mixed, float64 and pure
+float32, with the whole-cycle fraction of the HBM peak), the 256^3
+moving-mesh solve with its forward/backward timing and the ablation of its
+smoother and coarse operators, the initial-guess predictors and
 multigrid-preconditioned CG on the warm-start sequence, the force readout
 kernel, and the CPU oracle timed on a bounded sample.
 """
@@ -137,29 +140,72 @@ def run_sequence(mg, sources, phi, tol, max_cycles=60):
     return cycles
 
 
-MG_TIME_STEP, MG_TIME_PAIR, MG_TIME_TRIPLE = 1, 2, 4
+MG_TIME_STEP, MG_TIME_PAIR, MG_TIME_TRIPLE, MG_TIME_OUTER, MG_TIME_TRANSFER = 1, 2, 4, 8, 16
+KINDS = (MG_TIME_STEP, MG_TIME_PAIR, MG_TIME_TRIPLE, MG_TIME_OUTER, MG_TIME_TRANSFER)
 
 
-def solve_timed(mg, torch, b, tol, max_cycles=60):
-    """Cold solve from zero: (info, ms, one-step kernel (launches, ms, bytes), phi,
-    two-step kernel (launches, ms, bytes)).  The warm-up solve times the
-    two-step kernels, the timed solve the one-step kernels."""
+def kernel_name(kind, n, precision, var=False):
+    t = "double" if precision == "fp64" else "float"
+    if var:
+        return {MG_TIME_STEP: f"k_var_smooth_row (fine-level 19-point Chebyshev step, {t})",
+                MG_TIME_OUTER: "k_var_outer_row (19-point outer defect correction: phi += e, FP64 residual, norms)",
+                MG_TIME_TRANSFER: f"k_var_resid_row / k_prolong_row (fine-level 19-point residual, prolongation, {t})",
+                }.get(kind, f"kind {kind}")
+    return {MG_TIME_STEP: f"k_smooth_row / k_smooth_lds (fine-level single Chebyshev step, {t})",
+            MG_TIME_PAIR: f"k_smooth2_lds (fine-level two-step pass and pass from zero, {t})",
+            MG_TIME_TRIPLE: (f"k_smooth3p_lds (fine-level prolongation + three-step pass, {t})" if n >= 128
+                             else f"k_smooth3_lds (fine-level three-step pass, {t})"),
+            MG_TIME_OUTER: "k_outer_lds (outer defect correction: phi += e, FP64 residual r, norms, r cast "
+                           "to the inner precision)",
+            MG_TIME_TRANSFER: f"k_rr_row / k_prolong_row (fine-level residual + restriction, prolongation, {t})",
+            }[kind]
+
+
+def breakdown(mg, run):
+    """{kind: (launches, ms, alg_bytes)} of the fine-level kernels, one call of
+    run() per kind with that kind's in-dispatch events enabled."""
+    out = {}
+    for kind in KINDS:
+        mg.enable_kernel_timing(kind)
+        mg.kernel_timing()
+        run()
+        out[kind] = mg.kernel_timing()
+    mg.enable_kernel_timing(0)
+    return out
+
+
+def kernel_entry(kind, kt, n, precision, step_ms, deg=None, var=False, per="step"):
+    gbps, us = rate(kt)
+    k, ms, by = kt
+    return {"kernel": kernel_name(kind, n, precision, var), "achieved": gbps,
+            "frac": round(gbps / HBM_PEAK_GBPS, 4) if gbps else None, "avg_launch_us": us,
+            f"launches_per_{per}": k, "alg_bytes_per_launch": by / k if k else None,
+            f"share_of_{per}": round(ms / step_ms, 4) if step_ms else None,
+            "traffic": measured_traffic(n, deg, kernel_name(kind, n, precision, var).split()[0])
+            if deg is not None and not var and precision != "fp64" else None}
+
+
+def solve_timed(mg, torch, b, tol, max_cycles=60, kernels=False):
+    """Cold solve from zero, after one untimed warm-up solve: (info, ms, phi,
+    per-kernel breakdown of one more solve or None)."""
     phi = torch.zeros_like(b)
-    mg.enable_kernel_timing(MG_TIME_PAIR)
-    mg.kernel_timing()
     mg.solve(b, phi0=phi, out=phi, tol=tol, max_cycles=max_cycles, history=False, raise_on_error=False)
-    pair = mg.kernel_timing()
-    mg.enable_kernel_timing(MG_TIME_STEP)
-    mg.kernel_timing()
     phi.zero_()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, info = mg.solve(b, phi0=phi, out=phi, tol=tol, max_cycles=max_cycles, history=False, raise_on_error=False)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
-    k, kms, kby = mg.kernel_timing()
-    mg.enable_kernel_timing(0)
-    return info, 1e3 * t, (k, kms, kby), phi, pair
+    kt = None
+    if kernels:
+        tmp = torch.zeros_like(b)
+
+        def run():
+            tmp.zero_()
+            mg.solve(b, phi0=tmp, out=tmp, tol=tol, max_cycles=max_cycles, history=False, raise_on_error=False)
+        kt = breakdown(mg, run)
+        del tmp
+    return info, 1e3 * t, phi, kt
 
 
 def rate(kt):
@@ -172,30 +218,88 @@ def rate(kt):
 
 def sweep_point(mgpu, torch, flat_source, n, tol):
     """Cold solve of the k_c = (n/4) 2 pi source to `tol` in mixed and float64
-    precision.  32^3: 4 levels, degree 3; n >= 64: degree 4 with a 16^3
-    coarsest level."""
+    precision, and in pure float32 to its rounding plateau (stagnation).
+    32^3: 4 levels, degree 3; n >= 64: degree 4 with a 16^3 coarsest level.
+    Whole-cycle rate: the model's algorithmic bytes of the cycles run over the
+    time to tolerance (host round trips and the setup of the solve included)."""
     levels, deg = (4, 3) if n == 32 else (int(np.log2(n)) - 3, 4)
     b = torch.from_numpy(flat_source(n, 0)).to("cuda")
     out = {"levels": levels, "degree": deg}
-    for prec in ("mixed", "fp64"):
+    phis = {}
+    for prec in ("mixed", "fp64", "fp32"):
         mg = mgpu.Multigrid(n, levels=levels, degree=deg, precision=prec)
-        info, ms, kt, phi, pt = solve_timed(mg, torch, b, tol)
-        gbps, us = rate(kt)
-        pgbps, pus = rate(pt)
+        info, ms, phi, kt = solve_timed(mg, torch, b, tol if prec != "fp32" else 0.0,
+                                        max_cycles=60 if prec != "fp32" else 30, kernels=n >= 256 and prec != "fp32")
+        mb = model_bytes_per_cycle(n, levels, deg, prec)
+        gbps = info.cycles * mb / (ms * 1e-3) / 1e9
         out[prec] = {
             "cycles": info.cycles,
             "time_to_tol_ms": round(ms, 3),
+            "ms_per_cycle": round(ms / max(info.cycles, 1), 4),
             "vcycle_mpts_per_s": round(info.cycles * n ** 3 / (ms * 1e-3) / 1e6, 1),
             "rel_res": info.rel_res,
-            "smooth_kernel_GBps": gbps,
-            "smooth_kernel_frac": round(gbps / HBM_PEAK_GBPS, 4) if gbps else None,
-            "smooth_avg_launch_us": us,
-            "pair_kernel_GBps": pgbps,
-            "pair_avg_launch_us": pus,
+            "model_bytes_per_cycle_per_pt": round(mb / n ** 3, 2),
+            "cycle_GBps": round(gbps, 1),
+            "cycle_frac": round(gbps / HBM_PEAK_GBPS, 4),
+        }
+        if kt is not None:
+            out[prec]["fine_kernels"] = [kernel_entry(k, kt[k], n, prec, ms, per="solve")
+                                         for k in KINDS if kt[k][0]]
+        if prec == "fp32":
+            out[prec]["note"] = "tolerance disabled: runs to its float32 rounding plateau (stagnation guard)"
+            out[prec]["rel_diff_vs_mixed"] = float(torch.linalg.norm(phi - phis["mixed"]) /
+                                                   torch.linalg.norm(phis["mixed"]))
+        else:
+            phis[prec] = phi
+        del mg
+        torch.cuda.empty_cache()
+    out["time_to_tol_ratio_fp64_over_mixed"] = round(out["fp64"]["time_to_tol_ms"] / out["mixed"]["time_to_tol_ms"], 3)
+    return out
+
+
+def b512_leg(mgpu, torch, flat_source, n=512, levels=6, deg=4, cycles=20, reps=5):
+    """The 512^3 V-cycle (one GPU's share of 1024^3 on eight GPUs): from a
+    warm iterate (the source solved to 1e-10), 3 warm-up cycles, then
+    `cycles` defect-correction cycles (mg_cycles: no host wait between
+    cycles) timed with HIP events on the solver's stream, median of `reps`.
+    Whole-cycle rate = the model's algorithmic bytes of the call over its
+    time; then each fine-level kernel kind's in-dispatch rate over one more
+    call."""
+    b = torch.from_numpy(flat_source(n, 0)).to("cuda")
+    out = {"n": n, "levels": levels, "degree": deg, "cycles_timed": cycles, "repeats": reps}
+    for prec in ("mixed", "fp64"):
+        mg = mgpu.Multigrid(n, levels=levels, degree=deg, precision=prec)
+        phi = torch.zeros_like(b)
+        mg.solve(b, phi0=phi, out=phi, tol=1e-10, max_cycles=40, history=False, raise_on_error=False)
+        mg.cycles(phi, b, 3)
+        times = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            rel = mg.cycles(phi, b, cycles)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = float(np.median(times))
+        s = 8 if prec == "fp64" else 4
+        N = n ** 3
+        # `cycles` model cycles, plus the call's first outer pass (no e), the
+        # mean of b and the final gauge shift
+        by = cycles * model_bytes_per_cycle(n, levels, deg, prec) + N * ((8 + 8 + s) + 8 + 16)
+        gbps = by / (ms * 1e-3) / 1e9
+        kt = breakdown(mg, lambda: mg.cycles(phi, b, cycles))
+        out[prec] = {
+            "ms_per_call": round(ms, 3), "ms_per_cycle": round(ms / cycles, 4),
+            "times_ms": [round(t, 3) for t in times],
+            "vcycle_mpts_per_s": round(cycles * N / (ms * 1e-3) / 1e6, 1),
+            "model_bytes_per_cycle_per_pt": round(model_bytes_per_cycle(n, levels, deg, prec) / N, 2),
+            "cycle_GBps": round(gbps, 1), "cycle_frac": round(gbps / HBM_PEAK_GBPS, 4),
+            "rel_res_after": rel,
+            "fine_kernels": [kernel_entry(k, kt[k], n, prec, ms, per="call") for k in KINDS if kt[k][0]],
         }
         del mg, phi
         torch.cuda.empty_cache()
-    out["time_to_tol_ratio_fp64_over_mixed"] = round(out["fp64"]["time_to_tol_ms"] / out["mixed"]["time_to_tol_ms"], 3)
+    out["time_ratio_fp64_over_mixed"] = round(out["fp64"]["ms_per_call"] / out["mixed"]["ms_per_call"], 3)
     return out
 
 
@@ -215,10 +319,10 @@ def moving_mesh_leg(mgpu, torch, n, tol):
            "det_J": [round(float(sg.min()), 4), round(float(sg.max()), 4)]}
     for prec in ("mixed", "fp64"):
         mg = mgpu.Multigrid(n, coeff=C32, precision=prec)
-        info, ms, kt, phi, _ = solve_timed(mg, torch, b, tol, max_cycles=100)
-        gbps, _ = rate(kt)
+        info, ms, phi, kt = solve_timed(mg, torch, b, tol, max_cycles=100, kernels=True)
         out[prec] = {"cycles": info.cycles, "time_to_tol_ms": round(ms, 3), "rel_res": info.rel_res,
-                     "smooth_kernel_GBps": gbps}
+                     "fine_kernels": [kernel_entry(k, kt[k], n, prec, ms, var=True, per="solve")
+                                      for k in KINDS if kt[k][0]]}
         del mg, phi
     out["time_to_tol_ratio_fp64_over_mixed"] = round(out["fp64"]["time_to_tol_ms"] / out["mixed"]["time_to_tol_ms"], 3)
 
@@ -297,7 +401,7 @@ def ablation_leg(mgpu, torch, psi, b, tol):
         for coarse in ("fw_coeff", "psi"):
             kw = {"psi": psi} if coarse == "psi" else {"coeff": C64}
             mg = mgpu.Multigrid(n, precision="mixed", smoother=smoother, **kw)
-            info, ms, _, phi, _ = solve_timed(mg, torch, b, tol, max_cycles=100)
+            info, ms, phi, _ = solve_timed(mg, torch, b, tol, max_cycles=100)
             out[f"{smoother}+{coarse}"] = {"cycles": info.cycles, "time_to_tol_ms": round(ms, 3),
                                            "rel_res": info.rel_res}
             if smoother == "chebyshev" and coarse == "psi":
@@ -340,6 +444,105 @@ def accel_leg(mgpu, torch, phi, psi, reps=20):
     return out
 
 
+def host_cpu():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "cpus_available": avail}
+
+
+def cpu_leg(src_np, n, levels, deg, phi_mixed, phi_fp32, fp32_info, c2_cycles, c4_cycles):
+    """The oracle (NumPy float64, one thread: roll, ufuncs and the FFT run
+    single-threaded) on a bounded sample of the benchmark's work: one warm-up
+    V-cycle, then the median of 3 timed V-cycles at 256^3 on source t = 0
+    (seven-point), and one V-cycle of the 19-point moving-mesh operator after
+    a warm-up cycle.  Time to 1e-10 is estimated from these as the cycle
+    count the solve needs (measured on the GPU, same arithmetic) times one
+    cycle plus one residual evaluation.  Also the accuracy of the timed mixed
+    path and the pure-float32 plateau against the oracle's exact
+    FFT-diagonalised solve."""
+    import json as _json
+
+    from oracle import mg_oracle as O
+    from workloads import moving_mesh_field, psi_unit
+
+    N = n ** 3
+    h = 1.0 / n
+    H = O.build_hierarchy(n, levels, deg)
+    b0 = src_np[0] - src_np[0].mean()
+    x = O.vcycle(H, 0, np.zeros_like(b0), b0)  # warm-up
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        x = O.vcycle(H, 0, x, b0)
+        times.append(time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    float(np.linalg.norm(b0 - H.levels[0].apply(x)))
+    t_res = time.perf_counter() - t0
+    med = float(np.median(times))
+    # 19-point operator: moving-mesh coefficients (float32 values, as on the GPU)
+    scale = _json.load(open(os.path.join(ROOT, "tests", "golden", "psi_scale.json")))["scale"][str(n)]
+    t0 = time.perf_counter()
+    C, sg = O.geometry(scale * psi_unit(n), h)
+    C = C.astype(np.float32).astype(np.float64)
+    g = moving_mesh_field(n, 0)
+    bm = sg * (g - np.sum(g * sg) / np.sum(sg))
+    bm -= bm.mean()
+    Hv = O.build_hierarchy(n, levels, deg, C=C)
+    t_setup_var = time.perf_counter() - t0
+    xv = O.vcycle(Hv, 0, np.zeros_like(bm), bm)  # warm-up
+    t0 = time.perf_counter()
+    xv = O.vcycle(Hv, 0, xv, bm)
+    t_var = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    float(np.linalg.norm(bm - Hv.levels[0].apply(xv)))
+    t_res_var = time.perf_counter() - t0
+    del Hv, C, sg, g, bm, xv
+    # accuracy against the exact discrete solve
+    last = src_np[-1]
+    exact = O.fft_solve(last - last.mean(), h)
+    err = float(np.linalg.norm(phi_mixed.cpu().numpy() - exact) / np.linalg.norm(exact))
+    out = {
+        "value": round(N / med / 1e6, 3),
+        "unit": "Mpts/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"NumPy float64 oracle at {n}^3, one thread: median of 3 seven-point V-cycles after a "
+                   f"warm-up cycle (source t=0; {', '.join(f'{t:.2f}' for t in times)} s), and one "
+                   f"19-point moving-mesh V-cycle after a warm-up cycle ({t_var:.2f} s)"),
+        **host_cpu(),
+        "vcycle_s_median": round(med, 3),
+        "residual_eval_s": round(t_res, 3),
+        "vcycle_19pt_s": round(t_var, 3),
+        "vcycle_19pt_mpts_per_s": round(N / t_var / 1e6, 3),
+        "setup_19pt_s": round(t_setup_var, 2),
+        "est_time_to_1e-10_s": {
+            "c2_first_source": round(c2_cycles[0] * (med + t_res) + t_res, 1),
+            "c2_cycles": c2_cycles[0],
+            "c4_moving_mesh": round(c4_cycles * (t_var + t_res_var) + t_res_var, 1) if c4_cycles else None,
+            "c4_cycles": c4_cycles,
+        },
+        "mixed_final_rel_err_vs_oracle_exact": err,
+    }
+    if phi_fp32 is not None:
+        b0e = O.fft_solve(b0, h)
+        out["fp32_plateau"] = {
+            "source": "warm-start sequence t=0, cold, tolerance disabled (stops at stagnation)",
+            "cycles": fp32_info["cycles"], "rel_res": fp32_info["rel_res"],
+            "rel_err_vs_oracle_exact": float(np.linalg.norm(phi_fp32.cpu().numpy() - b0e) / np.linalg.norm(b0e)),
+        }
+    return out
+
+
 def timed(fn, steps, torch):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -359,6 +562,7 @@ def main():
     ap.add_argument("--degree", type=int, default=3)
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison sequence")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 32^3..1024^3 size sweep")
+    ap.add_argument("--no-b512", action="store_true", help="skip the 512^3 V-cycle leg")
     ap.add_argument("--sweep-max", type=int, default=1024, help="largest grid of the size sweep")
     ap.add_argument("--no-mm", action="store_true", help="skip the moving-mesh and gradient leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -388,13 +592,9 @@ def main():
     mg = mgpu.Multigrid(n, levels=levels, degree=deg, precision="mixed")
     for _ in range(args.warmup):
         run_sequence(mg, sources, phi, args.tol)
-    # the dominant fine smoothing kernel: one-, two- or three-step kernel, by total time
-    kinds = {}
-    for kind in (MG_TIME_STEP, MG_TIME_PAIR, MG_TIME_TRIPLE):
-        mg.enable_kernel_timing(kind)
-        mg.kernel_timing()
-        run_sequence(mg, sources, phi, args.tol)
-        kinds[kind] = mg.kernel_timing()
+    # the dominant kernel of the step: the fine-level kernel kind with the
+    # largest total time over one untimed sequence per kind
+    kinds = breakdown(mg, lambda: run_sequence(mg, sources, phi, args.tol))
     dominant = max(kinds, key=lambda k: kinds[k][1])
     mg.enable_kernel_timing(dominant)
     mg.kernel_timing()  # reset counters
@@ -409,37 +609,22 @@ def main():
     mpts = total_cycles * n ** 3 / t_mixed / 1e6
     bytes_cycle = model_bytes_per_cycle(n, levels, deg, "mixed")
     achieved = k_bytes / (k_ms * 1e-3) / 1e9 if k_ms > 0 else None
-    names = {MG_TIME_STEP: "k_smooth_row (fine-level Chebyshev step, float)",
-             MG_TIME_PAIR: "k_smooth2_lds (fine-level two-step kernel and pass from zero, float)",
-             MG_TIME_TRIPLE: ("k_smooth3p_lds (fine-level prolongation + three-step pass, float)" if n >= 128
-                              else "k_smooth3_lds (fine-level three-step pass, float)")}
-    others = []
-    for kind in names:
-        if kind == dominant or not kinds[kind][0]:
-            continue
-        ogbps, ous = rate(kinds[kind])
-        others.append({
-            "kernel": names[kind], "achieved": ogbps, "avg_launch_us": ous,
-            "frac": round(ogbps / HBM_PEAK_GBPS, 4) if ogbps else None,
-            "traffic": measured_traffic(n, deg, names[kind].split()[0]),
-            "launches_per_step": kinds[kind][0],
-            "alg_bytes_per_launch": kinds[kind][2] / kinds[kind][0],
-            "share_of_step": round(kinds[kind][1] / ms_per_step, 4),
-        })
+    others = [kernel_entry(kind, kinds[kind], n, "mixed", ms_per_step, deg)
+              for kind in KINDS if kind != dominant and kinds[kind][0]]
     roofline = {
-        "kernel": names[dominant],
+        "kernel": kernel_name(dominant, n, "mixed"),
         "bound": "hbm",
         "achieved": round(achieved, 1) if achieved else None,
         "peak": HBM_PEAK_GBPS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBPS, 4) if achieved else None,
-        "traffic": measured_traffic(n, deg, names[dominant].split()[0]),
+        "traffic": measured_traffic(n, deg, kernel_name(dominant, n, "mixed").split()[0]),
         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE)",
         "launches": launches,
         "avg_launch_us": round(1e3 * k_ms / launches, 2) if launches else None,
         "alg_bytes_per_launch": k_bytes / launches if launches else None,
         "share_of_step": round(k_ms / (1e3 * t_mixed), 4),
-        "other_fine_smoothing_kernels": others,
+        "other_fine_kernels": others,
     }
 
     # ------------------------------------------------------------- float64 comparison
@@ -477,6 +662,13 @@ def main():
     del mg
     torch.cuda.empty_cache()
 
+    # ------------------------------------------------------------- 512^3 V-cycle
+    b512 = None
+    if not args.no_b512:
+        print("[bench] 512^3 V-cycle", file=sys.stderr, flush=True)
+        b512 = b512_leg(mgpu, torch, flat_source)
+        torch.cuda.empty_cache()
+
     # ------------------------------------------------------------- size sweep 32^3 .. 1024^3
     sweep = {}
     if not args.no_sweep:
@@ -492,33 +684,20 @@ def main():
         mm = moving_mesh_leg(mgpu, torch, 256, args.tol)
         torch.cuda.empty_cache()
 
+    # ------------------------------------------------------------- pure float32 plateau (C2 t = 0)
+    plateau_phi = None
+    if not args.no_cpu:
+        mg32 = mgpu.Multigrid(n, levels=levels, degree=deg, precision="fp32")
+        plateau_phi, p32 = mg32.solve(sources[0], tol=0.0, max_cycles=40, history=False, raise_on_error=False)
+        plateau_info = {"cycles": p32.cycles, "rel_res": p32.rel_res}
+        del mg32
+
     # ------------------------------------------------------------- CPU oracle baseline
     cpu = None
     if not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
-        from oracle import mg_oracle as O
-
-        H = O.build_hierarchy(n, levels, deg)
-        b0 = src_np[0] - src_np[0].mean()
-        x = np.zeros_like(b0)
-        k = 2
-        t0 = time.perf_counter()
-        for _ in range(k):
-            x = O.vcycle(H, 0, x, b0)
-        tc = time.perf_counter() - t0
-        # accuracy of the timed mixed path against the oracle's exact discrete solve
-        last = src_np[-1]
-        exact = O.fft_solve(last - last.mean(), 1.0 / n)
-        err = float(np.linalg.norm(phi_mixed.cpu().numpy() - exact) / np.linalg.norm(exact))
-        cpu = {
-            "value": round(k * n ** 3 / tc / 1e6, 3),
-            "unit": "Mpts/s",
-            "cores": 1,
-            "kind": "oracle",
-            "sample": f"{k} float64 V-cycles of the NumPy oracle at {n}^3 on source t=0 "
-                      f"({tc:.1f} s, single thread)",
-            "mixed_final_rel_err_vs_oracle_exact": err,
-        }
+        cpu = cpu_leg(src_np, n, levels, deg, phi_mixed, plateau_phi, plateau_info, cycles_per_step,
+                      mm["fp64"]["cycles"] if mm else None)
 
     result = {
         "metric": METRIC,
@@ -545,7 +724,7 @@ def main():
         "roofline": roofline,
         "fp64": fp64,
         "sweep": sweep,
-        "b512": sweep.get("512"),
+        "b512": b512,
         "moving_mesh": mm,
         "predictors": pred,
         "accel": accel,

@@ -73,6 +73,20 @@ enum mg_dtype {
     MG_DTYPE_F64 = 1
 };
 
+/* Reference switches (mg_params.options).  0, the default, runs every fused
+ * kernel; each bit replaces one fusion by the plain sequence of single-step
+ * kernels it stands for, so that fused and plain paths can be compared bit
+ * for bit and timed against each other.  They change no arithmetic. */
+enum mg_option {
+    MG_OPT_NO_PAIR = 1,        /* every smoothing step its own kernel (no two- or three-step passes,
+                                  no prolongation fused into post-smoothing) */
+    MG_OPT_NO_VISIT = 2,       /* no fused visits of the 32^3 and 64^3 float levels */
+    MG_OPT_NO_TAIL = 4,        /* levels of at most 16^3 points as separate kernels, not one workgroup */
+    MG_OPT_NO_FUSED_SUMS = 8,  /* outer residual norms finished by their own kernel */
+    MG_OPT_GRAPH = 16,         /* coarse sub-cycle replayed from a captured HIP graph */
+    MG_OPT_ALL = 31
+};
+
 typedef struct mg_params {
     int n;               /* points per side, power of two, 8 <= n <= 2048 */
     int levels;          /* >= 1; the coarsest level has n >> (levels-1) >= 4 points per side */
@@ -83,6 +97,7 @@ typedef struct mg_params {
     int smoother;        /* enum mg_smoother */
     double jacobi_omega; /* weighted-Jacobi factor (paper: 2/3) */
     int jacobi_sweeps;   /* weighted-Jacobi sweeps per smoothing pass (paper: 2) */
+    int options;         /* bit mask of enum mg_option; 0 = every fused kernel */
 } mg_params;
 
 typedef struct mg_solve_info {
@@ -97,7 +112,7 @@ typedef struct mg_ctx mg_ctx;
 
 /* Fill *p with defaults for an n^3 grid: levels = log2(n) - 1 (coarsest 4^3,
  * Sec. 4.3.3), degree 3, alpha 8, h = 1/n, MG_MIXED, Chebyshev, omega 2/3,
- * 2 sweeps.  Host only. */
+ * 2 sweeps, options 0.  Host only. */
 mg_status mg_params_default(mg_params* p, int n);
 
 /* Check *p against the rules above without touching any device.  Returns
@@ -157,6 +172,21 @@ mg_status mg_vcycle(mg_ctx* ctx, double* phi, const double* b, double* rel_res_o
 mg_status mg_solve(mg_ctx* ctx, double* phi, const double* b, double tol,
                    int max_cycles, mg_solve_info* info);
 
+/* A fixed number of warm-started cycles (Sec. 3.1: after an accurate first
+ * solve, each time step runs a small, fixed number of defect-correction
+ * cycles from the previous potential; the results section times warm solves
+ * of one to four cycles).  Projects the mean out of b, runs exactly `cycles`
+ * iterations phi <- phi + V(b - M phi) from the caller's phi with no
+ * convergence test and no host wait between them, then removes the mean of
+ * phi (gauge) as mg_solve does.  cycles >= 0 (0 only evaluates the residual
+ * and gauge-fixes).  rel_res_out (host pointer, may be NULL) receives
+ * ||b - M phi|| / ||b|| of the returned phi (0 if b is zero after
+ * projection, in which case phi = 0).  Synchronises the stream twice: for
+ * the mean of b at the start and for the final norms at the end.  Errors:
+ * MG_ERR_INVALID, MG_ERR_NONFINITE (NaN/Inf in b or in the final residual),
+ * MG_ERR_HIP. */
+mg_status mg_cycles(mg_ctx* ctx, double* phi, const double* b, int cycles, double* rel_res_out);
+
 /* Multigrid-preconditioned conjugate gradients (Sec. 3.2: the recycled
  * potential seeds a CG iteration preconditioned by multigrid): one V-cycle
  * from zero is the preconditioner B, phi the first iterate.  Flexible
@@ -175,7 +205,7 @@ mg_status mg_solve(mg_ctx* ctx, double* phi, const double* b, double tol,
 mg_status mg_solve_pcg(mg_ctx* ctx, double* phi, const double* b, double tol,
                        int max_iter, mg_solve_info* info);
 
-/* Adjoint solve lam = M^+ phibar (Sec. 4.6, eq. adj_rhs): M is symmetric, so
+/* Adjoint solve lam = M^+ phibar (Sec. 4.8, eq. adj_rhs): M is symmetric, so
  * this is the forward machinery on the cotangent; lam holds the initial
  * guess on entry and the zero-mean result on return.  With the paper's
  * weighted operator A = W^-1 M (eq. curv_operator) and b = sqrt(g) f, the
@@ -183,7 +213,7 @@ mg_status mg_solve_pcg(mg_ctx* ctx, double* phi, const double* b, double tol,
 mg_status mg_solve_adjoint(mg_ctx* ctx, double* lam, const double* phibar,
                            double tol, int max_cycles, mg_solve_info* info);
 
-/* Operator VJP at a converged solution (Sec. 4.6, eq. adj_op): overwrite cbar
+/* Operator VJP at a converged solution (Sec. 4.8, eq. adj_op): overwrite cbar
  * (device, 6 n^3 fields of dtype cbar_dtype) with dL/dC = -d(lam^T M(C) phi)/dC
  * for L with dL/db = lam.  Diagonal components: mean over the two a-faces of
  * (D+_a lam)(D+_a phi); off-diagonal (a,b): D0_a lam D0_b phi + D0_b lam D0_a phi
@@ -266,14 +296,54 @@ mg_status mg_coarse_solve(mg_ctx* ctx, const double* r, double* e);
  * doubles; 2 for the seven-point operator). */
 mg_status mg_level_lmax(const mg_ctx* ctx, double* lmax_out);
 
+/* ---- steps of the inner V-cycle in the context's own precision -------------
+ * One step of the V-cycle on level `level`, run through exactly the kernels
+ * mg_solve launches there (row-wave, two- and three-step passes, the pass
+ * from zero, the prolongation fused into post-smoothing, the fused 32^3 and
+ * 64^3 visits and the single-workgroup tail kernel), in the context's inner
+ * precision: float for MG_MIXED and MG_FP32, double for MG_FP64.  The double
+ * inputs are rounded to that precision on entry and the result is widened to
+ * double on exit, so a float step can be compared point by point with a
+ * double reference.  Operations (Sec. 2.3, Fig. 1; eq. flat_chebyshev):
+ *   MG_STEP_SMOOTH          out = S(x, b), one smoothing pass from x
+ *   MG_STEP_SMOOTH_ZERO     out = S(0, b), the pass from zero (x unused)
+ *   MG_STEP_PROLONG_SMOOTH  out = S(x + P e, b), prolongation of the coarse
+ *                           correction e then the post-smoothing pass
+ *   MG_STEP_RESIDUAL_RESTRICT  out = R(b - M x) on level + 1 (x, b unused: e)
+ *   MG_STEP_PROLONG         out = x + P e
+ *   MG_STEP_VCYCLE          out = V(0, b), the inner cycle from zero on
+ *                           levels level .. coarsest (level 0: the cycle
+ *                           that each defect-correction iteration applies to
+ *                           its residual)
+ * x, b, out: level-`level` fields (out on level + 1 for the restriction);
+ * e: level-(level + 1) field; pointers an operation does not use may be
+ * NULL.  All are caller-owned double device fields; out may alias an input.
+ * The step works in the context's hierarchy buffers, so it must not overlap
+ * a solve on the same context.  Stream-ordered, no synchronisation.
+ * Errors: MG_ERR_INVALID (operation, level, missing pointer). */
+enum mg_step {
+    MG_STEP_SMOOTH = 0,
+    MG_STEP_SMOOTH_ZERO = 1,
+    MG_STEP_PROLONG_SMOOTH = 2,
+    MG_STEP_RESIDUAL_RESTRICT = 3,
+    MG_STEP_PROLONG = 4,
+    MG_STEP_VCYCLE = 5
+};
+mg_status mg_inner_step(mg_ctx* ctx, int step, int level, const double* x, const double* e,
+                        const double* b, double* out);
+
 /* ---- timing of the dominant kernels ---------------------------------------
- * When enabled, every launch of a fine-level smoothing kernel inside mg_solve
- * / mg_vcycle / mg_solve_pcg whose kind is in the mask is bracketed by HIP
- * events recorded by the kernel's own dispatch on the context's stream.
- * Kinds: MG_TIME_STEP, the one-step kernels; MG_TIME_PAIR, the kernels that
- * apply two consecutive smoothing steps in one pass (and the pass from zero
- * that forms its first step on the fly); MG_TIME_TRIPLE, the kernel that
- * applies three steps in one pass from a nonzero iterate.  mg_kernel_timing
+ * When enabled, every launch of a fine-level kernel inside mg_solve /
+ * mg_cycles / mg_vcycle / mg_solve_pcg whose kind is in the mask is bracketed
+ * by HIP events recorded by the kernel's own dispatch on the context's
+ * stream.  Kinds: MG_TIME_STEP, the one-step smoothing kernels; MG_TIME_PAIR,
+ * the kernels that apply two consecutive smoothing steps in one pass (and
+ * the pass from zero that forms its first step on the fly); MG_TIME_TRIPLE,
+ * the kernels that apply three steps in one pass from a nonzero iterate (with
+ * the prolongation fused in front where it is); MG_TIME_OUTER, the outer
+ * defect-correction kernel (phi update, FP64 residual, norms); MG_TIME_TRANSFER,
+ * the fine level's residual + restriction and its separate prolongation.
+ * mg_kernel_timing
  * returns, since the previous call: the number of such launches, their summed
  * duration in milliseconds and their summed algorithmic HBM bytes (every
  * field element the launch reads or writes counted once: iterate, previous
@@ -283,7 +353,9 @@ mg_status mg_level_lmax(const mg_ctx* ctx, double* lmax_out);
 enum mg_timing_kind {
     MG_TIME_STEP = 1,
     MG_TIME_PAIR = 2,
-    MG_TIME_TRIPLE = 4
+    MG_TIME_TRIPLE = 4,
+    MG_TIME_OUTER = 8,
+    MG_TIME_TRANSFER = 16
 };
 mg_status mg_enable_kernel_timing(mg_ctx* ctx, int enable);
 mg_status mg_kernel_timing(mg_ctx* ctx, int* launches, double* total_ms, double* alg_bytes);

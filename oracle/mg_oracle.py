@@ -492,7 +492,7 @@ def accel(phi: np.ndarray, h: float, psi: Optional[np.ndarray] = None,
 
 
 # ---------------------------------------------------------------------------
-# Adjoint and gradients (Sec. 4.6, eqs. adj_rhs and adj_op)
+# Adjoint and gradients (Sec. 4.8, eqs. adj_rhs and adj_op)
 # ---------------------------------------------------------------------------
 
 def solve_adjoint(H: Hierarchy, phibar: np.ndarray, tol: float = 1e-10,

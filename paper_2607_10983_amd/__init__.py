@@ -8,7 +8,7 @@ is missing or no GPU is present, the calls raise.
 
 Paper: "Fast(er)PM and Moving Mesh: JAX-native Geometric Multigrid Methods"
 (Sec. 2.3 V-cycle, Sec. 3 warm-started defect correction, Sec. 4.3 curvilinear
-operator, Sec. 4.6 implicit adjoint).
+operator, Sec. 4.8 implicit adjoint).
 """
 from __future__ import annotations
 
@@ -81,11 +81,14 @@ class Multigrid:
     potential restricted to it (``mg_create_psi``).
     ``precision``: "fp64", "mixed" (float V-cycle, double residual/update/coarsest
     solve) or "fp32".  ``levels`` defaults to ``log2(n) - 1`` (coarsest 4^3).
+    ``options`` is the ``mg_params.options`` mask of reference switches
+    (``MG_OPT_*``; 0 runs every fused kernel).
     """
 
     def __init__(self, n: int, levels: Optional[int] = None, degree: int = 3, coeff=None,
                  precision: str = "mixed", h: Optional[float] = None, alpha: float = 8.0,
-                 smoother: str = "chebyshev", omega: float = 2.0 / 3.0, sweeps: int = 2, psi=None):
+                 smoother: str = "chebyshev", omega: float = 2.0 / 3.0, sweeps: int = 2, psi=None,
+                 options: int = 0):
         torch = _torch()
         lib = _lib.load()
         p = _lib.MgParams()
@@ -100,6 +103,7 @@ class Multigrid:
         p.smoother = _SMOOTHER[smoother]
         p.jacobi_omega = float(omega)
         p.jacobi_sweeps = int(sweeps)
+        p.options = int(options)
         self.n = int(n)
         self.params = p
         self.precision = precision
@@ -195,6 +199,43 @@ class Multigrid:
             raise self._err(st, fname)
         return res
 
+    def cycles(self, phi, b, cycles: int) -> float:
+        """Exactly ``cycles`` warm defect-correction cycles on ``phi`` in place
+        (``mg_cycles``), then the gauge; returns the final relative residual."""
+        torch = _torch()
+        _check_field(phi, self.n, torch.float64, "phi")
+        _check_field(b, self.n, torch.float64, "b")
+        self._sync_stream()
+        out = ctypes.c_double(0.0)
+        st = _lib.load().mg_cycles(self._ctx, _ptr(phi), _ptr(b), int(cycles), ctypes.byref(out))
+        if st != _lib.MG_OK:
+            raise self._err(st, "mg_cycles")
+        return out.value
+
+    _STEPS = {"smooth": _lib.MG_STEP_SMOOTH, "smooth_zero": _lib.MG_STEP_SMOOTH_ZERO,
+              "prolong_smooth": _lib.MG_STEP_PROLONG_SMOOTH, "residual_restrict": _lib.MG_STEP_RESIDUAL_RESTRICT,
+              "prolong": _lib.MG_STEP_PROLONG, "vcycle": _lib.MG_STEP_VCYCLE}
+
+    def inner_step(self, step: str, level: int = 0, x=None, e=None, b=None):
+        """One V-cycle step in the context's inner precision through the
+        kernels the solver itself launches (``mg_inner_step``); double in and
+        out.  ``step``: smooth, smooth_zero, prolong_smooth, residual_restrict,
+        prolong or vcycle."""
+        torch = _torch()
+        nl = self._level_n(level)
+        for name, t, m in (("x", x, nl), ("b", b, nl), ("e", e, nl // 2)):
+            if t is not None:
+                _check_field(t, m, torch.float64, name)
+        ref = b if b is not None else x
+        shape = (nl // 2,) * 3 if step == "residual_restrict" else (nl,) * 3
+        out = torch.empty(shape, dtype=torch.float64, device=ref.device)
+        self._sync_stream()
+        p = lambda t: _ptr(t) if t is not None else None  # noqa: E731
+        st = _lib.load().mg_inner_step(self._ctx, self._STEPS[step], int(level), p(x), p(e), p(b), _ptr(out))
+        if st != _lib.MG_OK:
+            raise self._err(st, "mg_inner_step")
+        return out
+
     def vcycle(self, phi, b, rel_res: bool = False):
         """One defect-correction cycle in place: ``phi <- phi + V(b - M phi)``."""
         torch = _torch()
@@ -288,17 +329,18 @@ class Multigrid:
 
     # ---------------------------------------------------------------- timing
     def enable_kernel_timing(self, mask: int = _lib.MG_TIME_STEP):
-        """Time fine-level smoothing kernels of the kinds in ``mask``
-        (MG_TIME_STEP one-step kernels, MG_TIME_PAIR two-step kernels,
-        MG_TIME_TRIPLE three-step kernels; 0 or
-        False disables, True means MG_TIME_STEP)."""
+        """Time fine-level kernels of the kinds in ``mask`` (MG_TIME_STEP
+        one-step smoothing, MG_TIME_PAIR two-step passes, MG_TIME_TRIPLE
+        three-step passes, MG_TIME_OUTER the outer defect kernel,
+        MG_TIME_TRANSFER residual + restriction and prolongation; 0 or False
+        disables, True means MG_TIME_STEP)."""
         st = _lib.load().mg_enable_kernel_timing(self._ctx, int(mask))
         if st != _lib.MG_OK:
             raise self._err(st, "mg_enable_kernel_timing")
 
     def kernel_timing(self):
         """(launches, total_ms, algorithmic_bytes) of the timed fine-level
-        smoothing kernels since the last call."""
+        kernels since the last call."""
         k = ctypes.c_int(0)
         ms = ctypes.c_double(0.0)
         by = ctypes.c_double(0.0)
@@ -403,13 +445,14 @@ def _autograd():
 
     class SolveFn(torch.autograd.Function):
         """phi = M(C)^+ (b - mean b): implicit adjoint, differentiated at the
-        converged solution rather than through the cycles (Sec. 4.6)."""
+        converged solution rather than through the cycles (Sec. 4.8).  The
+        implicit gradient holds only at a converged solve, so a forward or
+        adjoint solve that misses its tolerance raises MGError."""
 
         @staticmethod
         def forward(ctx, b, C, opts):
-            mg = Multigrid(b.shape[0], coeff=C, **opts["ctx"])
-            phi, info = mg.solve(b.detach().contiguous(), tol=opts["tol"], max_cycles=opts["max_cycles"],
-                                 raise_on_error=False)
+            mg = _solve_context(b.shape[0], C, opts["ctx"])
+            phi, info = mg.solve(b.detach().contiguous(), tol=opts["tol"], max_cycles=opts["max_cycles"])
             ctx.mg = mg
             ctx.opts = opts
             ctx.c_dtype = None if C is None else C.dtype
@@ -421,7 +464,7 @@ def _autograd():
             (phi,) = ctx.saved_tensors
             mg = ctx.mg
             lam, _ = mg.solve_adjoint(phibar.contiguous().to(torch.float64), tol=ctx.opts["tol"],
-                                      max_cycles=ctx.opts["max_cycles"], raise_on_error=False)
+                                      max_cycles=ctx.opts["max_cycles"])
             Cbar = None
             if ctx.c_dtype is not None and ctx.needs_input_grad[1]:
                 Cbar = mg.coeff_grad(lam, phi, dtype=ctx.c_dtype)
@@ -431,6 +474,26 @@ def _autograd():
 
 
 _FNS = None
+# Contexts of the differentiable solve, reused while the coefficient tensor is
+# the same object with an unchanged version counter (setup restricts C to
+# every level, bounds the spectra and factors the coarsest operator).
+_SOLVE_CTX = []
+_SOLVE_CTX_MAX = 2
+
+
+def _solve_context(n, C, ctx_opts):
+    import weakref
+
+    key = (int(n), tuple(sorted(ctx_opts.items())),
+           None if C is None else (C.data_ptr(), C.dtype, tuple(C.shape), C._version))
+    for i, (k, ref, mg) in enumerate(_SOLVE_CTX):
+        if k == key and (C is None or ref() is C):
+            _SOLVE_CTX.insert(0, _SOLVE_CTX.pop(i))
+            return mg
+    mg = Multigrid(n, coeff=None if C is None else C.detach(), **ctx_opts)
+    _SOLVE_CTX.insert(0, (key, None if C is None else weakref.ref(C), mg))
+    del _SOLVE_CTX[_SOLVE_CTX_MAX:]
+    return mg
 
 
 def _fns():

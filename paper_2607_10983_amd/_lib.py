@@ -19,7 +19,10 @@ MG_FP64, MG_MIXED, MG_FP32 = 0, 1, 2
 MG_CHEBYSHEV, MG_JACOBI = 0, 1
 MG_DTYPE_F32, MG_DTYPE_F64 = 0, 1
 MG_PREDICT_RECYCLE, MG_PREDICT_GROWTH, MG_PREDICT_LINEAR, MG_PREDICT_QUADRATIC = 0, 1, 2, 3
-MG_TIME_STEP, MG_TIME_PAIR, MG_TIME_TRIPLE = 1, 2, 4
+MG_TIME_STEP, MG_TIME_PAIR, MG_TIME_TRIPLE, MG_TIME_OUTER, MG_TIME_TRANSFER = 1, 2, 4, 8, 16
+MG_OPT_NO_PAIR, MG_OPT_NO_VISIT, MG_OPT_NO_TAIL, MG_OPT_NO_FUSED_SUMS, MG_OPT_GRAPH = 1, 2, 4, 8, 16
+(MG_STEP_SMOOTH, MG_STEP_SMOOTH_ZERO, MG_STEP_PROLONG_SMOOTH, MG_STEP_RESIDUAL_RESTRICT, MG_STEP_PROLONG,
+ MG_STEP_VCYCLE) = range(6)
 
 
 class MgParams(ctypes.Structure):
@@ -33,6 +36,7 @@ class MgParams(ctypes.Structure):
         ("smoother", ctypes.c_int),
         ("jacobi_omega", ctypes.c_double),
         ("jacobi_sweeps", ctypes.c_int),
+        ("options", ctypes.c_int),
     ]
 
 
@@ -64,6 +68,8 @@ SIGNATURES = {
     "mg_solve": (_I, [_P, _P, _P, _D, _I, ctypes.POINTER(MgSolveInfo)]),
     "mg_solve_adjoint": (_I, [_P, _P, _P, _D, _I, ctypes.POINTER(MgSolveInfo)]),
     "mg_solve_pcg": (_I, [_P, _P, _P, _D, _I, ctypes.POINTER(MgSolveInfo)]),
+    "mg_cycles": (_I, [_P, _P, _P, _I, _PD]),
+    "mg_inner_step": (_I, [_P, _I, _I, _P, _P, _P, _P]),
     "mg_coeff_grad": (_I, [_P, _P, _P, _P, _I]),
     "mg_geometry": (_I, [_I, _D, _P, _P, _I, _P, _P]),
     "mg_geometry_bwd": (_I, [_I, _D, _P, _P, _P, _P, _P]),

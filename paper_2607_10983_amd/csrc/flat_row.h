@@ -11,11 +11,6 @@ bool row_kernels_apply(int n);
 // number of per-block partial sums the outer-residual kernel writes for an
 // n^3 grid (double_arith: residual in double, otherwise float)
 int row_outer_blocks(int n, bool double_arith);
-// Tuning knob: target number of blocks per launch (default 8192).
-void set_row_target_blocks(int target);
-void set_outer_shape(int waves, int nz);
-void set_rr_target(int blocks);
-void set_small_nz(int nz, int pair_nz);
 
 template <typename T>
 hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, const T* b, T* out, double a,
@@ -32,14 +27,9 @@ bool pair_kernels_apply(int n, size_t elem);
 // pass that is not from zero): y3 after steps (a0, cd0), (a1, cd1), (a2, cd2).
 // y3 must differ from x and b.
 bool triple_kernels_apply(int n, size_t elem);
-void set_use_triple(bool on);
-void set_triple_waves(int waves);
-void set_fromb_waves(int waves);
-void set_triple_nz(int nz);
 // The same pass starting from x0 = x + P e (e on the (n/2)^3 grid), x0 formed
 // on the fly and never written: y3 after three steps from x0.  n >= 128.
 bool triple_pro_applies(int n, size_t elem);
-void set_use_triple_pro(bool on);
 template <typename T>
 hipError_t launch_prolong_triple_row(int n, double ih2, const T* x, const T* e, const T* b, T* y3, double a0,
                                      double cd0, double a1, double cd1, double a2, double cd2, hipStream_t s,
@@ -48,11 +38,6 @@ template <typename T>
 hipError_t launch_smooth_triple_row(int n, double ih2, const T* x, const T* b, T* y3, double a0, double cd0,
                                     double a1, double cd1, double a2, double cd2, hipStream_t s, hipEvent_t ev0,
                                     hipEvent_t ev1);
-void set_pair_nz(int nz);
-void set_pair_waves(int waves);
-void set_pair_prefetch(int planes);
-void set_pair_unroll(bool on);
-void set_fromb_pf2(bool on);
 template <typename T>
 hipError_t launch_smooth_pair_row(int n, double ih2, const T* x, const T* xp, const T* b, T* y2, T* y1,
                                   double a1, double cd1, double a2, double cd2, hipStream_t s,
@@ -60,10 +45,13 @@ hipError_t launch_smooth_pair_row(int n, double ih2, const T* x, const T* xp, co
                                   double cd0 = 0.0, const SumsJob* sums = nullptr);
 template <typename TA, typename TR, typename TE>
 hipError_t launch_outer_row(int n, double ih2, const double* phi_in, const TE* e, double* phi_out, const double* b,
-                            double bmean, TR* r, TR* x1, double cd0, double* partials, hipStream_t s);
+                            double bmean, TR* r, TR* x1, double cd0, double* partials, hipStream_t s,
+                            hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 template <typename T>
-hipError_t launch_rr_row(int n, double ih2, const T* x, const T* b, T* coarse, hipStream_t s);
+hipError_t launch_rr_row(int n, double ih2, const T* x, const T* b, T* coarse, hipStream_t s,
+                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 template <typename T>
-hipError_t launch_prolong_row(int n, const T* e, T* x, hipStream_t s);
+hipError_t launch_prolong_row(int n, const T* e, T* x, hipStream_t s, hipEvent_t ev0 = nullptr,
+                              hipEvent_t ev1 = nullptr);
 
 }  // namespace mg

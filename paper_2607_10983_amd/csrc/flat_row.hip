@@ -1156,10 +1156,10 @@ __global__ __launch_bounds__(kBlock) void k_prolong_row(int n, const T* __restri
 
 // ---- launch shapes -------------------------------------------------------------------
 // rows of the (n x n) plane grouped four per block; z split into chunks of nz
-// planes so that about `target` blocks are launched.
-int g_target_blocks = 8192;
-int g_small_nz = 0;       // z chunk of the single-step, restriction and prolongation kernels for n <= 128
-int g_pair_small_nz = 0;  // z chunk of the two-step kernel for n <= 128 (0 = by the rule for all sizes)
+// planes so that about `target` blocks are launched.  Every launch shape is a
+// function of n and the element size only, so two contexts in one process
+// never see different shapes.
+constexpr int kTargetBlocks = 8192;
 
 // Kernels whose working set does not fit the Infinity Cache (the outer
 // residual with its double fields, residual + restriction) take longer z
@@ -1167,7 +1167,7 @@ int g_pair_small_nz = 0;  // z chunk of the two-step kernel for n <= 128 (0 = by
 // counters showed 36% extra fetch at the short chunk length.
 void shape(int rows, int planes, int min_nz, int& nz, int& nyb, int& blocks, int target = 0) {
     nyb = rows / kWaves;
-    if (target == 0) target = g_target_blocks;
+    if (target == 0) target = kTargetBlocks;
     nz = planes;
     while (nz > min_nz && (long)nyb * (planes / nz) < target) nz >>= 1;
     blocks = nyb * (planes / nz);
@@ -1182,53 +1182,20 @@ bool lds_rows_fit(int n) {
 
 }  // namespace
 
-void set_row_target_blocks(int target) {
-    if (target >= 64) g_target_blocks = target;
-}
-void set_small_nz(int nz, int pair_nz) {
-    if (nz >= 0) g_small_nz = nz;
-    if (pair_nz >= 0) g_pair_small_nz = pair_nz;
-}
-
-// Chunk override for the small levels: planes / nz blocks per row block.
-inline void small_chunk(int n, int planes, int nzs, int nyb, int& nz, int& blocks) {
-    if (nzs > 0 && n <= 128 && nzs <= planes && planes % nzs == 0) {
-        nz = nzs;
-        blocks = nyb * (planes / nz);
-    }
-}
-
 bool row_kernels_apply(int n) { return n >= 64 && n <= 1024 && (n & (n - 1)) == 0; }
 
 // block count the residual + restriction kernel's chunks aim for on levels of
 // 256^3 and more (256^3: 512 blocks 22.6 us, 1024 blocks 25.2 us, 256 blocks 28.9 us)
-int g_rr_target = 512;
-int g_outer_waves = 8;  // waves (rows) per block of the outer LDS kernel
-int g_outer_nz = 0;     // its z chunk, 0 = by the block-count rule
+constexpr int kRrTarget = 512;
 
-void set_rr_target(int blocks) {
-    if (blocks >= 64) g_rr_target = blocks;
-}
-void set_outer_shape(int waves, int nz) {
-    if (waves == 8 || waves == 16) g_outer_waves = waves;
-    if (nz >= 0) g_outer_nz = nz;
-}
-
-// Waves of the outer LDS kernel at size n and element size elem (8 unless the
-// larger block's two planes of rows fit the LDS budget).
-int outer_waves(int n, size_t elem) {
-    const int w = g_outer_waves;
-    return 2ull * (w + 2) * (size_t)n * elem <= kLdsBudget ? w : kLdsWaves;
-}
-
-// Longest z chunks that still give one block per CU: the outer kernel is
-// bound by its bytes, and a chunk re-reads its two halo planes (256^3: chunks
-// of 32 planes 103.6 us against 107.8 us for 16; 16-wave blocks measured slower).
+// Longest z chunks that still give one block of kLdsWaves waves per CU: the
+// outer kernel is bound by its bytes, and a chunk re-reads its two halo planes
+// (256^3: chunks of 32 planes 103.6 us against 107.8 us for 16; 16-wave
+// blocks measured slower).
 void outer_lds_shape(int n, int waves, int& nz, int& nyb, int& blocks) {
     nyb = n / waves;
     nz = n;
     while (nz > 16 && nyb * (n / nz) < 256) nz >>= 1;
-    if (g_outer_nz > 0 && g_outer_nz <= n && n % g_outer_nz == 0) nz = g_outer_nz;
     blocks = nyb * (n / nz);
 }
 
@@ -1237,7 +1204,7 @@ void outer_lds_shape(int n, int waves, int& nz, int& nyb, int& blocks) {
 int row_outer_blocks(int n, bool double_arith) {
     int nz, nyb, blocks;
     if (double_arith ? lds_rows_fit<double>(n) : lds_rows_fit<float>(n)) {
-        outer_lds_shape(n, outer_waves(n, double_arith ? sizeof(double) : sizeof(float)), nz, nyb, blocks);
+        outer_lds_shape(n, kLdsWaves, nz, nyb, blocks);
         return blocks;
     }
     shape(n, n, 16, nz, nyb, blocks, 1024);
@@ -1280,7 +1247,6 @@ hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, cons
         return hipGetLastError();
     }
     shape(n, n, 4, nz, nyb, blocks);
-    small_chunk(n, n, g_small_nz, nyb, nz, blocks);
     DISPATCH_VEC(n, {
         if (x == nullptr)
             MG_LAUNCH((k_smooth_row<T, VEC, false, false>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (T)ih2, x,
@@ -1295,25 +1261,18 @@ hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, cons
     return hipGetLastError();
 }
 
-// Waves per block of the two-step kernel (W = waves - 2 output rows): 8 by
-// default (measured best of 8, 12 and 16 on the 256^3 sequence: 37.4 vs
-// 37.7 vs 38.0 ms), 12 or 16 selectable for measurement.
-constexpr int kPairWaves = 16;  // the largest block (LDS and register budget checks)
+// Waves per block of the two-step kernel (W = waves - 2 output rows): 8
+// (measured best of 8, 12 and 16 on the 256^3 sequence: 37.4 vs 37.7 vs
+// 38.0 ms).  The pass from zero picks its own block by row size.
+constexpr int kPairWavesDefault = 8;
 constexpr size_t kPairLdsBudget = 64 * 1024;
 constexpr int kPairUnrollNz = 8;  // chunk height of the fully unrolled two-step variant
-int g_pair_nz = 0;  // z chunk of the two-step kernel; 0 = chosen from n
-int g_pair_waves = 8;
-bool g_pair_waves_set = false;  // waves chosen explicitly (then also for the pass from zero)
-// Prefetch depth of the two-step kernel: -1 = by row size (two planes ahead
-// for 2 KB rows, whose blocks run one per CU: 512^3 float 541 -> 498 us per
-// launch; one plane for smaller rows, where the extra registers cost
-// occupancy: 256^3 float 53 -> 61 us), 0 / 1 = one / two planes.
-int g_pair_pf2 = -1;
-bool g_pair_unroll = true;
-// The pass from zero reads one field (b), so its unrolled variant can afford
-// prefetching two planes ahead at the same occupancy (256^3: 40.3 -> 37.7 us,
-// 128^3: 9.5 -> 8.7 us per launch).
-bool g_fromb_pf2 = true;  // fully unrolled variant for chunks of kPairUnrollNz planes
+// Prefetch depth of the two-step kernel: two planes ahead for 2 KB rows,
+// whose blocks run one per CU (512^3 float 541 -> 498 us per launch); one
+// plane for smaller rows, where the extra registers cost occupancy (256^3
+// float 53 -> 61 us).  The pass from zero reads one field (b), so its
+// unrolled variant prefetches two planes ahead at the same occupancy
+// (256^3: 40.3 -> 37.7 us, 128^3: 9.5 -> 8.7 us per launch).
 
 // Largest row (bytes) whose two-step kernel fits a wave's registers without
 // spilling: 8-wave blocks leave a wave 256 VGPRs (float n <= 512, double
@@ -1321,29 +1280,8 @@ bool g_fromb_pf2 = true;  // fully unrolled variant for chunks of kPairUnrollNz 
 constexpr size_t pair_max_row_bytes(int waves) { return waves <= 8 ? 2048 : 1024; }
 
 bool pair_kernels_apply(int n, size_t elem) {
-    return row_kernels_apply(n) && (size_t)n * elem <= pair_max_row_bytes(g_pair_waves) &&
-           2ull * g_pair_waves * (size_t)n * elem <= kPairLdsBudget;
-}
-
-void set_pair_nz(int nz) {
-    if (nz >= 0) g_pair_nz = nz;
-}
-void set_pair_waves(int waves) {
-    if (waves == 8 || waves == 12 || waves == 16) {
-        g_pair_waves = waves;
-        g_pair_waves_set = true;
-    }
-}
-// block of the pass from zero; 0 = by size (measured at 256^3 with 88 VGPRs:
-// 16 waves 36.5 us, 12 waves 39.2, 10 waves 39.0, 8 waves 37.7)
-int g_fromb_waves = 0;
-void set_fromb_waves(int waves) {
-    if (waves == 0 || waves == 8 || waves == 12 || waves == 16) g_fromb_waves = waves;
-}
-void set_pair_unroll(bool on) { g_pair_unroll = on; }
-void set_fromb_pf2(bool on) { g_fromb_pf2 = on; }
-void set_pair_prefetch(int planes) {
-    if (planes == 1 || planes == 2) g_pair_pf2 = planes == 2 ? 1 : 0;
+    return row_kernels_apply(n) && (size_t)n * elem <= pair_max_row_bytes(kPairWavesDefault) &&
+           2ull * kPairWavesDefault * (size_t)n * elem <= kPairLdsBudget;
 }
 
 // launch of one k_smooth2_lds variant inside launch_pair_nw (VEC from DISPATCH_VEC)
@@ -1354,7 +1292,7 @@ void set_pair_prefetch(int planes) {
 #define MG_PAIR(PREV1, Y1OUT, FROMB)                                          \
     do {                                                                      \
         if (pf2) MG_PAIR1(PREV1, Y1OUT, FROMB, true, 0);                      \
-        else if (g_pair_unroll && nz == kPairUnrollNz) MG_PAIR1(PREV1, Y1OUT, FROMB, false, kPairUnrollNz); \
+        else if (nz == kPairUnrollNz) MG_PAIR1(PREV1, Y1OUT, FROMB, false, kPairUnrollNz); \
         else MG_PAIR1(PREV1, Y1OUT, FROMB, false, 0);                         \
     } while (0)
 
@@ -1365,21 +1303,17 @@ hipError_t launch_pair_nw(int n, double ih2, const T* x, const T* xp, const T* b
     const int extra = sums.count > 0 ? 1 : 0;  // the block that finishes the sums (pass from zero only)
     constexpr int W = NW - 2;
     const int nyb = (n + W - 1) / W;
-    int nz = g_pair_nz;
-    if (nz <= 0 || nz > n || (n % nz) != 0) {
-        // about 1000 blocks, z chunks of at least 8 planes
-        nz = n;
-        // 64^3: chunks of 4 planes (pass from zero 6.1 -> 5.0 us per launch)
-        const int min_nz = n <= 64 ? 4 : 8;
-        while (nz > min_nz && (long)nyb * (n / nz) < 1024) nz >>= 1;
-        if (g_pair_small_nz > 0 && n <= 128 && n % g_pair_small_nz == 0) nz = g_pair_small_nz;
-    }
+    // about 1000 blocks, z chunks of at least 8 planes; 64^3: chunks of 4
+    // planes (pass from zero 6.1 -> 5.0 us per launch)
+    int nz = n;
+    const int min_nz = n <= 64 ? 4 : 8;
+    while (nz > min_nz && (long)nyb * (n / nz) < 1024) nz >>= 1;
     const int blocks = nyb * (n / nz);
-    const bool pf2 = g_pair_pf2 < 0 ? (size_t)n * sizeof(T) >= 2048 : g_pair_pf2 == 1;
+    const bool pf2 = (size_t)n * sizeof(T) >= 2048;
     DISPATCH_VEC(n, {
         if constexpr (64 * VEC * sizeof(T) <= pair_max_row_bytes(NW) && 2ull * NW * 64 * VEC * sizeof(T) <= kPairLdsBudget) {
             if (x0_mode != 0) {
-                if (g_fromb_pf2 && !pf2 && g_pair_unroll && nz == kPairUnrollNz) {
+                if (!pf2 && nz == kPairUnrollNz) {
                     if (y1 == nullptr) MG_PAIR1(false, false, true, true, kPairUnrollNz);
                     else MG_PAIR1(false, true, true, true, kPairUnrollNz);
                 } else if (y1 == nullptr) MG_PAIR(false, false, true);
@@ -1393,6 +1327,8 @@ hipError_t launch_pair_nw(int n, double ih2, const T* x, const T* xp, const T* b
             } else {
                 MG_PAIR(true, true, false);
             }
+        } else {
+            return hipErrorInvalidValue;  // row does not fit this block's register or LDS budget
         }
     })
     return hipGetLastError();
@@ -1409,13 +1345,11 @@ hipError_t launch_smooth_pair_row(int n, double ih2, const T* x, const T* xp, co
     if (sums.count > 0 && x0_mode == 0) return hipErrorInvalidValue;
     if (x0_mode == 0 && x == nullptr) return hipErrorInvalidValue;
     if (x0_mode != 0 && xp != nullptr) return hipErrorInvalidValue;
-    int waves = g_pair_waves;
+    int waves = kPairWavesDefault;
     // The pass from zero (one field read) runs best in larger blocks where the
     // row fits their register budget: 256^3 16 waves 33.8 us (8: 35.4, 12: 38.3),
     // 128^3 12 waves 7.8 us (8: 8.6), 64^3 8 waves.
-    if (x0_mode != 0 && g_fromb_waves > 0) {
-        waves = g_fromb_waves;
-    } else if (x0_mode != 0 && !g_pair_waves_set) {
+    if (x0_mode != 0) {
         const size_t row = (size_t)n * sizeof(T);
         waves = (n >= 256 && row <= pair_max_row_bytes(16)) ? 16 : (n >= 128 && row <= pair_max_row_bytes(12)) ? 12 : 8;
         if (2ull * waves * row > kPairLdsBudget) waves = 8;
@@ -1430,27 +1364,19 @@ hipError_t launch_smooth_pair_row(int n, double ih2, const T* x, const T* xp, co
 // Three-step kernel: 12 waves (8 output rows) per block, chunks of
 // kTripleNz planes; rows of at most 1 KB (float n <= 256, double n <= 128).
 constexpr int kTripleNz = 8;
-// z chunk of the fused post-smoothing pass in 12-wave blocks from 256^3: 8, 16
-// or 32 planes; 0 = 16.  Below 256^3 the chunk is kTripleNz.  A chunk forms
-// step 0 on NZC + 4 planes for NZC outputs, and each plane costs a barrier
-// round whatever its share of useful work: 256^3 with 12-wave blocks,
-// 8 planes 56.1 us, 16 planes 48.5 us, 32 planes 47.5 us.
-int g_triple_nz = 0;
-void set_triple_nz(int nz) {
-    if (nz == 0 || nz == 8 || nz == 16 || nz == 32) g_triple_nz = nz;
-}
-bool g_use_triple = true;
-bool g_use_triple_pro = true;  // post-smoothing pass fused with the prolongation before it
-// block of the three-step kernel: 8 waves at 64^3, 12 above (measured:
-// 64^3 5.7 vs 6.4 us, 128^3 10.1 vs 10.8 us, 256^3 within 1%); 0 = by size
-int g_triple_waves = 0;
+// z chunk of the fused post-smoothing pass in 12-wave blocks from 256^3: 16
+// planes.  Below 256^3 the chunk is kTripleNz.  A chunk forms step 0 on
+// NZC + 4 planes for NZC outputs, and each plane costs a barrier round
+// whatever its share of useful work: 256^3 with 12-wave blocks, 8 planes
+// 56.1 us, 16 planes 48.5 us, 32 planes 47.5 us (32 planes gave fewer blocks
+// than CUs at 128 rows of 8 and measured no better over the whole sequence).
+constexpr int kTripleProNzLarge = 16;
+// block of the three-step kernels: 8 waves at 64^3, 12 above (measured:
+// 64^3 5.7 vs 6.4 us, 128^3 10.1 vs 10.8 us, 256^3 within 1%)
+inline int triple_waves(int n) { return n <= 64 ? 8 : 12; }
 
 bool triple_kernels_apply(int n, size_t elem) {
-    return g_use_triple && row_kernels_apply(n) && (size_t)n * elem <= 1024 && n % kTripleNz == 0;
-}
-void set_use_triple(bool on) { g_use_triple = on; }
-void set_triple_waves(int w) {
-    if (w == 0 || w == 8 || w == 12 || w == 16) g_triple_waves = w;
+    return row_kernels_apply(n) && (size_t)n * elem <= 1024 && n % kTripleNz == 0;
 }
 
 template <typename T, int NW>
@@ -1472,11 +1398,8 @@ hipError_t launch_smooth_triple_row(int n, double ih2, const T* x, const T* b, T
                                     double a1, double cd1, double a2, double cd2, hipStream_t s, hipEvent_t ev0,
                                     hipEvent_t ev1) {
     if (!triple_kernels_apply(n, sizeof(T)) || x == y3 || b == y3) return hipErrorInvalidValue;
-    const int waves = g_triple_waves > 0 ? g_triple_waves : (n <= 64 ? 8 : 12);
-    if (waves == 8)
+    if (triple_waves(n) == 8)
         return launch_triple_nw<T, 8>(n, ih2, x, b, y3, a0, cd0, a1, cd1, a2, cd2, s, ev0, ev1);
-    if (waves == 16)
-        return launch_triple_nw<T, 16>(n, ih2, x, b, y3, a0, cd0, a1, cd1, a2, cd2, s, ev0, ev1);
     return launch_triple_nw<T, 12>(n, ih2, x, b, y3, a0, cd0, a1, cd1, a2, cd2, s, ev0, ev1);
 }
 template <typename T, int NW>
@@ -1486,7 +1409,7 @@ hipError_t launch_triple_pro_nw(int n, double ih2, const T* x, const T* e, const
     constexpr int W = NW - 4;
     const int nyb = (n + W - 1) / W;
     int nzc = kTripleNz;
-    if (NW == 12 && n >= 256) nzc = g_triple_nz > 0 ? g_triple_nz : 16;
+    if (NW == 12 && n >= 256) nzc = kTripleProNzLarge;
     if (n % nzc != 0) nzc = kTripleNz;
     const int blocks = nyb * (n / nzc);
 #define MG_TRIPLE_PRO(NZC)                                                                                       \
@@ -1495,8 +1418,7 @@ hipError_t launch_triple_pro_nw(int n, double ih2, const T* x, const T* e, const
     DISPATCH_VEC(n, {
         if constexpr (64 * VEC * sizeof(T) <= 1024) {
             if constexpr (NW == 12) {
-                if (nzc == 32) MG_TRIPLE_PRO(32);
-                else if (nzc == 16) MG_TRIPLE_PRO(16);
+                if (nzc == kTripleProNzLarge) MG_TRIPLE_PRO(kTripleProNzLarge);
                 else MG_TRIPLE_PRO(kTripleNz);
             } else {
                 MG_TRIPLE_PRO(kTripleNz);
@@ -1511,19 +1433,15 @@ hipError_t launch_triple_pro_nw(int n, double ih2, const T* x, const T* e, const
 
 // From 128^3: at 64^3 the fused pass (11.1 us) is no faster than the
 // prolongation and the three-step pass apart (5.0 + 5.8 us).
-bool triple_pro_applies(int n, size_t elem) { return g_use_triple_pro && n >= 128 && triple_kernels_apply(n, elem); }
-void set_use_triple_pro(bool on) { g_use_triple_pro = on; }
+bool triple_pro_applies(int n, size_t elem) { return n >= 128 && triple_kernels_apply(n, elem); }
 
 template <typename T>
 hipError_t launch_prolong_triple_row(int n, double ih2, const T* x, const T* e, const T* b, T* y3, double a0,
                                      double cd0, double a1, double cd1, double a2, double cd2, hipStream_t s,
                                      hipEvent_t ev0, hipEvent_t ev1) {
     if (!triple_pro_applies(n, sizeof(T)) || y3 == x || y3 == b || y3 == e) return hipErrorInvalidValue;
-    const int waves = g_triple_waves > 0 ? g_triple_waves : (n <= 64 ? 8 : 12);
-    if (waves == 8)
+    if (triple_waves(n) == 8)
         return launch_triple_pro_nw<T, 8>(n, ih2, x, e, b, y3, a0, cd0, a1, cd1, a2, cd2, s, ev0, ev1);
-    if (waves == 16)
-        return launch_triple_pro_nw<T, 16>(n, ih2, x, e, b, y3, a0, cd0, a1, cd1, a2, cd2, s, ev0, ev1);
     return launch_triple_pro_nw<T, 12>(n, ih2, x, e, b, y3, a0, cd0, a1, cd1, a2, cd2, s, ev0, ev1);
 }
 template hipError_t launch_prolong_triple_row<float>(int, double, const float*, const float*, const float*, float*,
@@ -1542,63 +1460,58 @@ template hipError_t launch_smooth_triple_row<double>(int, double, const double*,
 
 template <typename TA, typename TR, typename TE>
 hipError_t launch_outer_row(int n, double ih2, const double* phi_in, const TE* e, double* phi_out, const double* b,
-                            double bmean, TR* r, TR* x1, double cd0, double* partials, hipStream_t s) {
+                            double bmean, TR* r, TR* x1, double cd0, double* partials, hipStream_t s,
+                            hipEvent_t ev0, hipEvent_t ev1) {
     int nz, nyb, blocks;
     if (lds_rows_fit<TA>(n)) {
-        const int waves = outer_waves(n, sizeof(TA));
-        outer_lds_shape(n, waves, nz, nyb, blocks);
+        outer_lds_shape(n, kLdsWaves, nz, nyb, blocks);
 #define MG_OUTER_LDS(Wv)                                                                                           \
     DISPATCH_VEC(n, {                                                                                              \
         if constexpr (2ull * (Wv + 2) * 64 * VEC * sizeof(TA) <= kLdsBudget) {                                     \
             if (e)                                                                                                 \
-                hipLaunchKernelGGL((k_outer_lds<TA, TR, TE, VEC, Wv, true>), dim3(blocks), dim3(64 * Wv), 0, s, n, \
+                MG_LAUNCH((k_outer_lds<TA, TR, TE, VEC, Wv, true>), dim3(blocks), dim3(64 * Wv), s, ev0, ev1, n, \
                                    (TA)ih2, phi_in, e, phi_out, b, bmean, r, x1, (TA)cd0, partials, nz, nyb);     \
             else                                                                                                   \
-                hipLaunchKernelGGL((k_outer_lds<TA, TR, TE, VEC, Wv, false>), dim3(blocks), dim3(64 * Wv), 0, s, n, \
+                MG_LAUNCH((k_outer_lds<TA, TR, TE, VEC, Wv, false>), dim3(blocks), dim3(64 * Wv), s, ev0, ev1, n, \
                                    (TA)ih2, phi_in, e, phi_out, b, bmean, r, x1, (TA)cd0, partials, nz, nyb);     \
         }                                                                                                          \
     })
-        if (waves == 16) {
-            MG_OUTER_LDS(16)
-        } else {
-            MG_OUTER_LDS(8)
-        }
+        MG_OUTER_LDS(kLdsWaves)
 #undef MG_OUTER_LDS
         return hipGetLastError();
     }
     shape(n, n, 16, nz, nyb, blocks, 1024);
     DISPATCH_VEC(n, {
         if (e)
-            hipLaunchKernelGGL((k_outer_row<TA, TR, TE, VEC, true>), dim3(blocks), dim3(kBlock), 0, s, n, (TA)ih2,
+            MG_LAUNCH((k_outer_row<TA, TR, TE, VEC, true>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (TA)ih2,
                                phi_in, e, phi_out, b, bmean, r, x1, (TA)cd0, partials, nz, nyb);
         else
-            hipLaunchKernelGGL((k_outer_row<TA, TR, TE, VEC, false>), dim3(blocks), dim3(kBlock), 0, s, n, (TA)ih2,
+            MG_LAUNCH((k_outer_row<TA, TR, TE, VEC, false>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (TA)ih2,
                                phi_in, e, phi_out, b, bmean, r, x1, (TA)cd0, partials, nz, nyb);
     })
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_rr_row(int n, double ih2, const T* x, const T* b, T* coarse, hipStream_t s) {
+hipError_t launch_rr_row(int n, double ih2, const T* x, const T* b, T* coarse, hipStream_t s, hipEvent_t ev0,
+                         hipEvent_t ev1) {
     const int nc = n / 2;
     int nzc, nyb, blocks;
     // small levels are latency chains: chunks of 2 coarse planes (128^3: 7.7 -> 5.7 us,
     // 64^3: 6.8 -> 4.8 us per launch)
-    shape(nc, nc, n <= 128 ? 2 : 4, nzc, nyb, blocks, n >= 256 ? g_rr_target : 1024);
-    small_chunk(n, nc, g_small_nz, nyb, nzc, blocks);
+    shape(nc, nc, n <= 128 ? 2 : 4, nzc, nyb, blocks, n >= 256 ? kRrTarget : 1024);
     DISPATCH_VEC(n, {
-        hipLaunchKernelGGL((k_rr_row<T, VEC>), dim3(blocks), dim3(kBlock), 0, s, n, (T)ih2, x, b, coarse, nzc, nyb);
+        MG_LAUNCH((k_rr_row<T, VEC>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (T)ih2, x, b, coarse, nzc, nyb);
     })
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_prolong_row(int n, const T* e, T* x, hipStream_t s) {
+hipError_t launch_prolong_row(int n, const T* e, T* x, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     int nz, nyb, blocks;
     shape(n, n, 4, nz, nyb, blocks);
-    small_chunk(n, n, g_small_nz, nyb, nz, blocks);
     DISPATCH_VEC(n, {
-        hipLaunchKernelGGL((k_prolong_row<T, VEC>), dim3(blocks), dim3(kBlock), 0, s, n, e, x, nz, nyb);
+        MG_LAUNCH((k_prolong_row<T, VEC>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, e, x, nz, nyb);
     })
     return hipGetLastError();
 }
@@ -1613,18 +1526,20 @@ template hipError_t launch_smooth_pair_row<float>(int, double, const float*, con
 template hipError_t launch_smooth_pair_row<double>(int, double, const double*, const double*, const double*,
                                                    double*, double*, double, double, double, double, hipStream_t,
                                                    hipEvent_t, hipEvent_t, int, double, const SumsJob*);
-template hipError_t launch_rr_row<float>(int, double, const float*, const float*, float*, hipStream_t);
-template hipError_t launch_rr_row<double>(int, double, const double*, const double*, double*, hipStream_t);
-template hipError_t launch_prolong_row<float>(int, const float*, float*, hipStream_t);
-template hipError_t launch_prolong_row<double>(int, const double*, double*, hipStream_t);
+template hipError_t launch_rr_row<float>(int, double, const float*, const float*, float*, hipStream_t, hipEvent_t,
+                                         hipEvent_t);
+template hipError_t launch_rr_row<double>(int, double, const double*, const double*, double*, hipStream_t, hipEvent_t,
+                                          hipEvent_t);
+template hipError_t launch_prolong_row<float>(int, const float*, float*, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_prolong_row<double>(int, const double*, double*, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_outer_row<double, double, double>(int, double, const double*, const double*, double*,
                                                              const double*, double, double*, double*, double,
-                                                             double*, hipStream_t);
+                                                             double*, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_outer_row<double, float, float>(int, double, const double*, const float*, double*,
                                                            const double*, double, float*, float*, double, double*,
-                                                           hipStream_t);
+                                                           hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_outer_row<float, float, float>(int, double, const double*, const float*, double*,
                                                           const double*, double, float*, float*, double, double*,
-                                                          hipStream_t);
+                                                          hipStream_t, hipEvent_t, hipEvent_t);
 
 }  // namespace mg

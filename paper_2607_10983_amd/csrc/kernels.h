@@ -40,7 +40,8 @@ hipError_t launch_smooth_step(const OpDesc<TC>& op, const T* x, const T* xprev, 
 // restricted (two passes); without scratch a fused gather kernel is used.
 template <typename T, typename TC>
 hipError_t launch_residual_restrict(const OpDesc<TC>& op, const T* x, const T* b, T* coarse,
-                                    T* scratch, hipStream_t s);
+                                    T* scratch, hipStream_t s, hipEvent_t ev0 = nullptr,
+                                    hipEvent_t ev1 = nullptr);
 
 // coarse = R(fine), componentwise for `ncomp` consecutive fields.
 template <typename T>
@@ -49,7 +50,8 @@ hipError_t launch_restrict(int n, const T* fine, T* coarse, int ncomp, hipStream
 // ---- prolongation ------------------------------------------------------------
 // x (n^3) += P e ((n/2)^3), trilinear.
 template <typename T>
-hipError_t launch_prolong_add(int n, const T* e, T* x, hipStream_t s);
+hipError_t launch_prolong_add(int n, const T* e, T* x, hipStream_t s, hipEvent_t ev0 = nullptr,
+                              hipEvent_t ev1 = nullptr);
 
 // ---- operator application ----------------------------------------------------
 template <typename T, typename TC>
@@ -67,7 +69,8 @@ hipError_t launch_apply(const OpDesc<TC>& op, const T* u, T* out, hipStream_t s)
 template <typename TA, typename TR, typename TE, typename TC>
 hipError_t launch_outer_residual(const OpDesc<TC>& op, const double* phi_in, const TE* e,
                                  double* phi_out, const double* b, double bmean, TR* r,
-                                 TR* x1, double c0, double* partials, hipStream_t s);
+                                 TR* x1, double c0, double* partials, hipStream_t s,
+                                 hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // ---- reductions ----------------------------------------------------------------
 // partials[block] = sum over the block of (u - shift)^p, p in {1, 2}.

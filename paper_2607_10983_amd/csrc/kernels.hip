@@ -605,12 +605,12 @@ hipError_t launch_smooth_step(const OpDesc<TC>& op, const T* x, const T* xprev, 
 
 template <typename T, typename TC>
 hipError_t launch_residual_restrict(const OpDesc<TC>& op, const T* x, const T* b, T* coarse, T* scratch,
-                                    hipStream_t s) {
+                                    hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (op.coeff == nullptr && x != nullptr && row_kernels_apply(op.n))
-        return launch_rr_row<T>(op.n, op.ih2, x, b, coarse, s);
+        return launch_rr_row<T>(op.n, op.ih2, x, b, coarse, s, ev0, ev1);
     if (scratch != nullptr && x != nullptr) {
         if (op.coeff != nullptr && var_row_kernels_apply(op.n)) {
-            hipError_t e = launch_var_resid_row<T, TC>(op.n, op.ih2, op.coeff, x, b, scratch, s);
+            hipError_t e = launch_var_resid_row<T, TC>(op.n, op.ih2, op.coeff, x, b, scratch, s, ev0, ev1);
             if (e != hipSuccess) return e;
         } else {
             Shape sf = stencil_shape(op.n);
@@ -641,10 +641,10 @@ hipError_t launch_restrict(int n, const T* fine, T* coarse, int ncomp, hipStream
 }
 
 template <typename T>
-hipError_t launch_prolong_add(int n, const T* e, T* x, hipStream_t s) {
-    if (row_kernels_apply(n)) return launch_prolong_row<T>(n, e, x, s);
+hipError_t launch_prolong_add(int n, const T* e, T* x, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (row_kernels_apply(n)) return launch_prolong_row<T>(n, e, x, s, ev0, ev1);
     Shape sh = stencil_shape(n);
-    hipLaunchKernelGGL((k_prolong_add<T>), sh.grid, sh.block, 0, s, n, e, x, sh.nz);
+    MG_LAUNCH((k_prolong_add<T>), sh.grid, sh.block, s, ev0, ev1, n, e, x, sh.nz);
     return hipGetLastError();
 }
 
@@ -661,21 +661,21 @@ hipError_t launch_apply(const OpDesc<TC>& op, const T* u, T* out, hipStream_t s)
 template <typename TA, typename TR, typename TE, typename TC>
 hipError_t launch_outer_residual(const OpDesc<TC>& op, const double* phi_in, const TE* e, double* phi_out,
                                  const double* b, double bmean, TR* r, TR* x1, double c0, double* partials,
-                                 hipStream_t s) {
+                                 hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (op.coeff == nullptr && row_kernels_apply(op.n))
         return launch_outer_row<TA, TR, TE>(op.n, op.ih2, phi_in, e, phi_out, b, bmean, r, x1,
-                                            c0 / (-6.0 * op.ih2), partials, s);
+                                            c0 / (-6.0 * op.ih2), partials, s, ev0, ev1);
     if (op.coeff != nullptr && var_row_kernels_apply(op.n))
         return launch_var_outer_row<TA, TR, TE, TC>(op.n, op.ih2, op.coeff, phi_in, e, phi_out, b, bmean, r, x1, c0,
-                                                    partials, s);
+                                                    partials, s, ev0, ev1);
     Shape sh = stencil_shape(op.n);
     if (op.coeff == nullptr) c0 = c0 / (-6.0 * op.ih2);
     if (e)
-        hipLaunchKernelGGL((k_outer_residual<TA, TR, TE, TC, true>), sh.grid, sh.block, 0, s, op.n, (TA)op.ih2,
-                           op.coeff, phi_in, e, phi_out, b, bmean, r, x1, (TA)c0, partials, sh.nz);
+        MG_LAUNCH((k_outer_residual<TA, TR, TE, TC, true>), sh.grid, sh.block, s, ev0, ev1, op.n, (TA)op.ih2,
+                  op.coeff, phi_in, e, phi_out, b, bmean, r, x1, (TA)c0, partials, sh.nz);
     else
-        hipLaunchKernelGGL((k_outer_residual<TA, TR, TE, TC, false>), sh.grid, sh.block, 0, s, op.n, (TA)op.ih2,
-                           op.coeff, phi_in, e, phi_out, b, bmean, r, x1, (TA)c0, partials, sh.nz);
+        MG_LAUNCH((k_outer_residual<TA, TR, TE, TC, false>), sh.grid, sh.block, s, ev0, ev1, op.n, (TA)op.ih2,
+                  op.coeff, phi_in, e, phi_out, b, bmean, r, x1, (TA)c0, partials, sh.nz);
     return hipGetLastError();
 }
 
@@ -772,7 +772,8 @@ hipError_t launch_hessian_adjoint(int n, double ih2, const double* Jbar, double*
 #define INST_T_TC(T, TC)                                                                                         \
     template hipError_t launch_smooth_step<T, TC>(const OpDesc<TC>&, const T*, const T*, const T*, T*, double,   \
                                                   double, hipStream_t, hipEvent_t, hipEvent_t);                  \
-    template hipError_t launch_residual_restrict<T, TC>(const OpDesc<TC>&, const T*, const T*, T*, T*, hipStream_t); \
+    template hipError_t launch_residual_restrict<T, TC>(const OpDesc<TC>&, const T*, const T*, T*, T*, hipStream_t, \
+                                                        hipEvent_t, hipEvent_t);                                  \
     template hipError_t launch_apply<T, TC>(const OpDesc<TC>&, const T*, T*, hipStream_t);
 INST_T_TC(float, float)
 INST_T_TC(double, double)
@@ -781,7 +782,7 @@ INST_T_TC(float, double)
 
 #define INST_T(T)                                                                                  \
     template hipError_t launch_restrict<T>(int, const T*, T*, int, hipStream_t);                   \
-    template hipError_t launch_prolong_add<T>(int, const T*, T*, hipStream_t);                     \
+    template hipError_t launch_prolong_add<T>(int, const T*, T*, hipStream_t, hipEvent_t, hipEvent_t); \
     template hipError_t launch_add<T>(size_t, const double*, const T*, double*, hipStream_t);      \
     template hipError_t launch_fill<T>(size_t, T, T*, hipStream_t);                                \
     template hipError_t launch_gershgorin<T>(const OpDesc<T>&, double*, hipStream_t);              \
@@ -801,7 +802,7 @@ template hipError_t launch_convert<float, float>(size_t, const float*, float*, h
 #define INST_OUTER(TA, TR, TE, TC)                                                                                \
     template hipError_t launch_outer_residual<TA, TR, TE, TC>(const OpDesc<TC>&, const double*, const TE*, double*, \
                                                               const double*, double, TR*, TR*, double, double*,     \
-                                                              hipStream_t);
+                                                              hipStream_t, hipEvent_t, hipEvent_t);
 INST_OUTER(double, double, double, double)
 INST_OUTER(double, double, double, float)
 INST_OUTER(double, float, float, float)

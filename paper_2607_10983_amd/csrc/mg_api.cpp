@@ -90,7 +90,8 @@ struct mg_ctx {
     double sums_seq = 0.0;
     bool scal_flag = false;  // the pending readback is the flag, not norm_ev
     bool use_pairs = true;         // last two steps of a smoothing pass in one two-step kernel
-    bool use_visits = true;        // fused visits of the 32^3 level (float hierarchy)
+    bool use_visits = true;        // fused visits of the 32^3 and 64^3 levels (float hierarchy)
+    bool use_tail = true;          // levels of at most 16^3 points in one workgroup
     // conjugate-gradient state (allocated by the first mg_solve_pcg)
     double* pcg_r = nullptr;
     double* pcg_p[2] = {nullptr, nullptr};
@@ -504,6 +505,51 @@ mg_status tail_cycle(mg_ctx* c, int l0) {
 template <typename T>
 mg_status vcycle_from_zero(mg_ctx* c, int l);
 
+// r_{l+1} = R(b_l - M_l x_l) into level l+1's right-hand side; the buffer of
+// the previous iterate is free here and serves as residual scratch.
+template <typename T>
+mg_status residual_restrict_level(mg_ctx* c, int l) {
+    Level& L = c->lev[l];
+    Level& Lc = c->lev[l + 1];
+    const bool fine = (l == 0);
+    hipEvent_t ev0, ev1;
+    mg_status st = time_events(c, fine, MG_TIME_TRANSFER, &ev0, &ev1);
+    if (st != MG_OK) return st;
+    HIPCHK(c, launch_residual_restrict<T, T>(op_of<T>(L), (const T*)L.x[L.cur], (const T*)L.b, (T*)Lc.b,
+                                             (T*)L.x[other(L.cur)], c->stream, ev0, ev1));
+    // seven-point: x, b read, r_{l+1} written; 19-point: the timed pass forms
+    // the fine residual (x, b, C read, r written) and a second pass restricts it
+    const double N = (double)L.N, s = sizeof(T);
+    const double bytes = c->var ? N * (3.0 * s + 6.0 * s) : N * (2.0 + 1.0 / 8.0) * s;
+    return time_end(c, fine, MG_TIME_TRANSFER, bytes);
+}
+
+// Up-leg of level l: x_l += P e_{l+1}, then the post-smoothing pass (one
+// kernel for both where the prolongation is fused into the three-step pass).
+template <typename T>
+mg_status post_level(mg_ctx* c, int l) {
+    Level& L = c->lev[l];
+    Level& Lc = c->lev[l + 1];
+    const bool fine = (l == 0);
+    hipEvent_t ev0, ev1;
+    mg_status st;
+    if (post_fused(c, l, sizeof(T))) {  // prolongation and the three-step post-smoothing pass in one kernel
+        if ((st = time_events(c, fine, MG_TIME_TRIPLE, &ev0, &ev1)) != MG_OK) return st;
+        const double D = -6.0 * L.ih2;  // c / D rounded as in the single-step launch
+        const int out = other(L.cur);
+        HIPCHK(c, launch_prolong_triple_row<T>(L.n, L.ih2, (const T*)L.x[L.cur], (const T*)Lc.x[Lc.cur],
+                                               (const T*)L.b, (T*)L.x[out], L.a[0], L.c[0] / D, L.a[1],
+                                               L.c[1] / D, L.a[2], L.c[2] / D, c->stream, ev0, ev1));
+        L.cur = out;
+        // x, b read, x_3 written, e read once per coarse point
+        return time_end(c, fine, MG_TIME_TRIPLE, (3.0 + 1.0 / 8.0) * (double)L.N * sizeof(T));
+    }
+    if ((st = time_events(c, fine, MG_TIME_TRANSFER, &ev0, &ev1)) != MG_OK) return st;
+    HIPCHK(c, launch_prolong_add<T>(L.n, (const T*)Lc.x[Lc.cur], (T*)L.x[L.cur], c->stream, ev0, ev1));
+    if ((st = time_end(c, fine, MG_TIME_TRANSFER, (2.0 + 1.0 / 8.0) * (double)L.N * sizeof(T))) != MG_OK) return st;
+    return smooth_level<T>(c, l, false);
+}
+
 // Capture V(0, b_1) on level 1 and below into c->coarse_exec.
 template <typename T>
 mg_status capture_coarse(mg_ctx* c) {
@@ -562,26 +608,10 @@ mg_status vcycle_from_zero(mg_ctx* c, int l) {
     }
     mg_status st = smooth_level<T>(c, l, true);
     if (st != MG_OK) return st;
-    // the buffer of the previous iterate is free here and serves as residual scratch
-    HIPCHK(c, launch_residual_restrict<T, T>(op_of<T>(L), (const T*)L.x[L.cur], (const T*)L.b, (T*)Lc.b,
-                                             (T*)L.x[other(L.cur)], c->stream));
+    if ((st = residual_restrict_level<T>(c, l)) != MG_OK) return st;
     st = vcycle_from_zero<T>(c, l + 1);
     if (st != MG_OK) return st;
-    if (post_fused(c, l, sizeof(T))) {  // prolongation and the three-step post-smoothing pass in one kernel
-        const bool fine = (l == 0);
-        hipEvent_t ev0, ev1;
-        if ((st = time_events(c, fine, MG_TIME_TRIPLE, &ev0, &ev1)) != MG_OK) return st;
-        const double D = -6.0 * L.ih2;  // c / D rounded as in the single-step launch
-        const int out = other(L.cur);
-        HIPCHK(c, launch_prolong_triple_row<T>(L.n, L.ih2, (const T*)L.x[L.cur], (const T*)Lc.x[Lc.cur],
-                                               (const T*)L.b, (T*)L.x[out], L.a[0], L.c[0] / D, L.a[1],
-                                               L.c[1] / D, L.a[2], L.c[2] / D, c->stream, ev0, ev1));
-        L.cur = out;
-        // x, b read, x_3 written, e read once per coarse point
-        return time_end(c, fine, MG_TIME_TRIPLE, (3.0 + 1.0 / 8.0) * (double)L.N * sizeof(T));
-    }
-    HIPCHK(c, launch_prolong_add<T>(L.n, (const T*)Lc.x[Lc.cur], (T*)L.x[L.cur], c->stream));
-    return smooth_level<T>(c, l, false);
+    return post_level<T>(c, l);
 }
 
 // ---- outer residual dispatch ---------------------------------------------------------------
@@ -597,33 +627,42 @@ mg_status outer_residual(mg_ctx* c, const double* phi_in, const void* e, double*
     const double c0 = L.c.empty() ? 0.0 : L.c[0];
     // x1 goes to a buffer other than the one holding e (the previous cycle's result)
     const int xb = other(L.cur);
+    hipEvent_t ev0, ev1;
+    mg_status st = time_events(c, true, MG_TIME_OUTER, &ev0, &ev1);
+    if (st != MG_OK) return st;
     hipError_t err;
     if (c->p.precision == MG_FP64) {
         OpDesc<double> op{n, ih2, (const double*)c->coeff_outer};
         err = launch_outer_residual<double, double, double, double>(op, phi_in, (const double*)e, phi_out, b, bmean,
                                                                     (double*)L.b, x1 ? (double*)L.x[xb] : nullptr, c0,
-                                                                    c->partials, c->stream);
+                                                                    c->partials, c->stream, ev0, ev1);
     } else if (c->p.precision == MG_MIXED) {
         float* x1p = x1 ? (float*)L.x[xb] : nullptr;
         if (c->coeff_outer_double) {
             OpDesc<double> op{n, ih2, (const double*)c->coeff_outer};
             err = launch_outer_residual<double, float, float, double>(op, phi_in, (const float*)e, phi_out, b, bmean,
-                                                                      (float*)L.b, x1p, c0, c->partials, c->stream);
+                                                                      (float*)L.b, x1p, c0, c->partials, c->stream,
+                                                                      ev0, ev1);
         } else {
             OpDesc<float> op{n, ih2, (const float*)c->coeff_outer};
             err = launch_outer_residual<double, float, float, float>(op, phi_in, (const float*)e, phi_out, b, bmean,
-                                                                     (float*)L.b, x1p, c0, c->partials, c->stream);
+                                                                     (float*)L.b, x1p, c0, c->partials, c->stream,
+                                                                     ev0, ev1);
         }
     } else {
         OpDesc<float> op{n, ih2, (const float*)c->coeff_outer};
         err = launch_outer_residual<float, float, float, float>(op, phi_in, (const float*)e, phi_out, b, bmean,
                                                                 (float*)L.b, x1 ? (float*)L.x[xb] : nullptr, c0,
-                                                                c->partials, c->stream);
+                                                                c->partials, c->stream, ev0, ev1);
     }
     HIPCHK(c, err);
     c->x1_ready = x1;
     c->x1_buf = xb;
-    return MG_OK;
+    // phi (and e, phi_out) and b in their storage types, r (and x1) in the inner type, C once
+    const double si = c->inner_double ? 8.0 : 4.0;
+    const double sc = c->var ? 6.0 * (c->coeff_outer_double ? 8.0 : 4.0) : 0.0;
+    const double per_pt = 8.0 + 8.0 + si + (e ? si + 8.0 : 0.0) + (x1 ? si : 0.0) + sc;
+    return time_end(c, true, MG_TIME_OUTER, per_pt * (double)L.N);
 }
 
 mg_status read_scalars(mg_ctx* c, int count) {
@@ -674,6 +713,7 @@ mg_status mg_params_default(mg_params* p, int n) {
     p->smoother = MG_CHEBYSHEV;
     p->jacobi_omega = 2.0 / 3.0;
     p->jacobi_sweeps = 2;
+    p->options = 0;
     return MG_OK;
 }
 
@@ -688,6 +728,7 @@ mg_status mg_validate_params(const mg_params* p) {
     if (!(p->h > 0.0) || !std::isfinite(p->h)) return MG_ERR_INVALID;
     if (p->precision < MG_FP64 || p->precision > MG_FP32) return MG_ERR_INVALID;
     if (p->smoother != MG_CHEBYSHEV && p->smoother != MG_JACOBI) return MG_ERR_INVALID;
+    if ((p->options & ~MG_OPT_ALL) != 0) return MG_ERR_INVALID;
     if (p->smoother == MG_JACOBI) {
         if (!(p->jacobi_omega > 0.0 && p->jacobi_omega < 2.0)) return MG_ERR_INVALID;
         if (p->jacobi_sweeps < 1 || p->jacobi_sweeps > 16) return MG_ERR_INVALID;
@@ -740,26 +781,12 @@ static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype, cons
     if (c->var && coarsest_n(p) > 8)
         return fail(c, MG_ERR_INVALID, "variable-coefficient coarsest level must have at most 8^3 points");
     const size_t Tsz = c->inner_double ? sizeof(double) : sizeof(float);
-    if (const char* t = std::getenv("MG_ROW_TARGET_BLOCKS")) set_row_target_blocks(std::atoi(t));
-    if (const char* t = std::getenv("MG_SMALL_NZ")) set_small_nz(std::atoi(t), -1);
-    if (const char* t = std::getenv("MG_PAIR_SMALL_NZ")) set_small_nz(-1, std::atoi(t));
-    if (const char* t = std::getenv("MG_PAIR_NZ")) set_pair_nz(std::atoi(t));
-    if (const char* t = std::getenv("MG_PAIR_WAVES")) set_pair_waves(std::atoi(t));
-    if (const char* t = std::getenv("MG_PAIR_PREFETCH")) set_pair_prefetch(std::atoi(t));
-    if (const char* t = std::getenv("MG_PAIR_UNROLL")) set_pair_unroll(std::atoi(t) != 0);
-    if (const char* t = std::getenv("MG_FROMB_PF2")) set_fromb_pf2(std::atoi(t) != 0);
-    if (const char* t = std::getenv("MG_TRIPLE")) set_use_triple(std::atoi(t) != 0);
-    if (const char* t = std::getenv("MG_TRIPLE_PRO")) set_use_triple_pro(std::atoi(t) != 0);
-    if (const char* t = std::getenv("MG_OUTER_WAVES")) set_outer_shape(std::atoi(t), -1);
-    if (const char* t = std::getenv("MG_OUTER_NZ")) set_outer_shape(0, std::atoi(t));
-    if (const char* t = std::getenv("MG_RR_TARGET")) set_rr_target(std::atoi(t));
-    if (const char* t = std::getenv("MG_TRIPLE_WAVES")) set_triple_waves(std::atoi(t));
-    if (const char* t = std::getenv("MG_FROMB_WAVES")) set_fromb_waves(std::atoi(t));
-    if (const char* t = std::getenv("MG_TRIPLE_NZ")) set_triple_nz(std::atoi(t));
-    // two-step smoothing kernels; MG_NO_PAIR keeps every step a kernel of its own
-    c->use_pairs = std::getenv("MG_NO_PAIR") == nullptr;
-    c->use_visits = std::getenv("MG_NO_VISIT") == nullptr;
-    c->fuse_sums = std::getenv("MG_NO_FUSED_SUMS") == nullptr;
+    // reference switches of this context (mg_params.options)
+    c->use_pairs = (p.options & MG_OPT_NO_PAIR) == 0;
+    c->use_visits = (p.options & MG_OPT_NO_VISIT) == 0;
+    c->fuse_sums = (p.options & MG_OPT_NO_FUSED_SUMS) == 0;
+    c->use_tail = (p.options & MG_OPT_NO_TAIL) == 0;
+    c->use_graph = (p.options & MG_OPT_GRAPH) != 0;
     c->lev.resize(p.levels);
     for (int l = 0; l < p.levels; ++l) {
         Level& L = c->lev[l];
@@ -778,8 +805,7 @@ static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype, cons
     mg_status st;
     if ((st = dalloc(c, (void**)&c->phi_tmp, N0 * sizeof(double))) != MG_OK) return st;
     // replaying the coarse sub-cycle from a HIP graph measured slower than eager
-    // launches on this platform; it stays available for callers that want it
-    c->use_graph = std::getenv("MG_GRAPH") != nullptr;
+    // launches on this platform; MG_OPT_GRAPH keeps it available
     c->nparts = stencil_blocks(p.n);
     c->nparts_outer = outer_blocks(p.n, !c->var, p.precision != MG_FP32);
     {
@@ -923,7 +949,7 @@ static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype, cons
         c->coeff_outer = nullptr;
         // levels of at most 16^3 points down to a coarsest of at most 8^3 run in one kernel
         const int steps = p.smoother == MG_JACOBI ? p.jacobi_sweeps : p.cheb_degree;
-        if (Lc.n <= 8 && steps <= kTailMaxSteps && !std::getenv("MG_NO_TAIL")) {
+        if (Lc.n <= 8 && steps <= kTailMaxSteps && c->use_tail) {
             int l0 = p.levels - 1;
             while (l0 > 0 && c->lev[l0 - 1].n <= 16 && p.levels - (l0 - 1) <= kTailMaxLevels) --l0;
             if (p.levels - l0 >= 2) c->tail_start = l0;
@@ -1127,6 +1153,43 @@ mg_status mg_solve_adjoint(mg_ctx* c, double* lam, const double* phibar, double 
     if (lam == phibar) return fail(c, MG_ERR_INVALID, "lam and phibar must not alias");
     // M = M^T: the adjoint system is the forward system with the cotangent as source.
     return solve_impl(c, lam, phibar, tol, max_cycles, info);
+}
+
+// A fixed number of defect-correction cycles with no host wait between them:
+// every outer kernel is followed by the next inner V-cycle at once, and the
+// outer sums are read once, after the last update.
+mg_status mg_cycles(mg_ctx* c, double* phi, const double* b, int cycles, double* rel_res_out) {
+    if (!c || !phi || !b || cycles < 0) return fail(c, MG_ERR_INVALID, "invalid cycles arguments");
+    if (phi == b) return fail(c, MG_ERR_INVALID, "phi and b must not alias");
+    const size_t N0 = c->lev[0].N;
+    const double invN = 1.0 / (double)N0;
+    mg_status st;
+    if ((st = device_sum(c, b, 0.0, 1, 0)) != MG_OK) return st;
+    if ((st = read_scalars(c, 1)) != MG_OK) return st;
+    const double bmean = c->hscal[0] * invN;
+    if (!std::isfinite(bmean)) return fail(c, MG_ERR_NONFINITE, "source contains NaN or Inf");
+    c->pending_sums = false;
+    double* cur = phi;
+    double* other = c->phi_tmp;
+    for (int k = 0; k <= cycles; ++k) {
+        const bool follows = k < cycles;
+        if (k == 0) st = outer_with_sums(c, phi, nullptr, nullptr, b, bmean, follows);
+        else st = outer_with_sums(c, cur, inner_e(c), other, b, bmean, follows);
+        if (st != MG_OK) return st;
+        if (k > 0) std::swap(cur, other);
+        if (follows && (st = inner_vcycle(c)) != MG_OK) return st;
+    }
+    if ((st = flush_sums(c)) != MG_OK) return st;
+    if ((st = wait_scalars(c)) != MG_OK) return st;
+    c->x1_ready = false;
+    const double nb = std::sqrt(c->hscal[1]);
+    const double rel = nb > 0.0 ? std::sqrt(c->hscal[2]) / nb : 0.0;
+    if (nb == 0.0) HIPCHK(c, launch_fill<double>(N0, 0.0, phi, c->stream));
+    else HIPCHK(c, launch_shift(N0, cur, c->hscal[3] * invN, phi, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (rel_res_out) *rel_res_out = rel;
+    if (!std::isfinite(rel)) return fail(c, MG_ERR_NONFINITE, "residual is not finite");
+    return MG_OK;
 }
 
 }  // extern "C"
@@ -1484,6 +1547,97 @@ mg_status mg_coarse_solve(mg_ctx* c, const double* r, double* e) {
     return MG_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// One V-cycle step of level l in the inner type T on the context's buffers;
+// the caller's double fields are rounded to T on entry and out is widened.
+template <typename T>
+mg_status inner_step_impl(mg_ctx* c, int step, int l, const double* x, const double* e, const double* b,
+                          double* out) {
+    Level& L = c->lev[l];
+    Level* Lc = l + 1 < (int)c->lev.size() ? &c->lev[l + 1] : nullptr;
+    hipStream_t s = c->stream;
+    c->x1_ready = false;
+    c->pending_sums = false;
+    auto in = [&](size_t count, const double* src, void* dst) -> hipError_t {
+        return launch_convert<T, double>(count, src, (T*)dst, s);
+    };
+    const T* res = nullptr;
+    size_t count = L.N;
+    mg_status st = MG_OK;
+    switch (step) {
+        case MG_STEP_SMOOTH:
+            HIPCHK(c, in(L.N, x, L.x[0]));
+            HIPCHK(c, in(L.N, b, L.b));
+            L.cur = 0;
+            st = smooth_level<T>(c, l, false);
+            res = (const T*)L.x[L.cur];
+            break;
+        case MG_STEP_SMOOTH_ZERO:
+            HIPCHK(c, in(L.N, b, L.b));
+            st = smooth_level<T>(c, l, true);
+            res = (const T*)L.x[L.cur];
+            break;
+        case MG_STEP_PROLONG_SMOOTH:
+            HIPCHK(c, in(L.N, x, L.x[0]));
+            HIPCHK(c, in(Lc->N, e, Lc->x[0]));
+            HIPCHK(c, in(L.N, b, L.b));
+            L.cur = 0;
+            Lc->cur = 0;
+            st = post_level<T>(c, l);
+            res = (const T*)L.x[L.cur];
+            break;
+        case MG_STEP_RESIDUAL_RESTRICT:
+            HIPCHK(c, in(L.N, x, L.x[0]));
+            HIPCHK(c, in(L.N, b, L.b));
+            L.cur = 0;
+            st = residual_restrict_level<T>(c, l);
+            res = (const T*)Lc->b;
+            count = Lc->N;
+            break;
+        case MG_STEP_PROLONG:
+            HIPCHK(c, in(L.N, x, L.x[0]));
+            HIPCHK(c, in(Lc->N, e, Lc->x[0]));
+            HIPCHK(c, launch_prolong_add<T>(L.n, (const T*)Lc->x[0], (T*)L.x[0], s));
+            L.cur = 0;
+            res = (const T*)L.x[0];
+            break;
+        case MG_STEP_VCYCLE:
+            HIPCHK(c, in(L.N, b, L.b));
+            st = vcycle_from_zero<T>(c, l);
+            res = (const T*)L.x[L.cur];
+            break;
+        default:
+            return fail(c, MG_ERR_INVALID, "unknown step");
+    }
+    if (st != MG_OK) return st;
+    HIPCHK(c, (launch_convert<double, T>(count, res, out, s)));
+    return MG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mg_status mg_inner_step(mg_ctx* c, int step, int level, const double* x, const double* e, const double* b,
+                        double* out) {
+    if (!c) return MG_ERR_INVALID;
+    if (step < MG_STEP_SMOOTH || step > MG_STEP_VCYCLE) return fail(c, MG_ERR_INVALID, "unknown step");
+    const bool coarser = step == MG_STEP_PROLONG_SMOOTH || step == MG_STEP_RESIDUAL_RESTRICT || step == MG_STEP_PROLONG;
+    mg_status st = level_check(c, level, coarser);
+    if (st != MG_OK) return st;
+    const bool need_x = step == MG_STEP_SMOOTH || step == MG_STEP_PROLONG_SMOOTH ||
+                        step == MG_STEP_RESIDUAL_RESTRICT || step == MG_STEP_PROLONG;
+    const bool need_e = step == MG_STEP_PROLONG_SMOOTH || step == MG_STEP_PROLONG;
+    const bool need_b = step != MG_STEP_PROLONG;
+    if (!out || (need_x && !x) || (need_e && !e) || (need_b && !b))
+        return fail(c, MG_ERR_INVALID, "missing field for this step");
+    return c->inner_double ? inner_step_impl<double>(c, step, level, x, e, b, out)
+                           : inner_step_impl<float>(c, step, level, x, e, b, out);
+}
+
 mg_status mg_level_lmax(const mg_ctx* c, double* out) {
     if (!c || !out) return MG_ERR_INVALID;
     for (size_t l = 0; l < c->lev.size(); ++l) out[l] = c->lev[l].lmax;
@@ -1492,7 +1646,8 @@ mg_status mg_level_lmax(const mg_ctx* c, double* out) {
 
 mg_status mg_enable_kernel_timing(mg_ctx* c, int enable) {
     if (!c) return MG_ERR_INVALID;
-    if (enable < 0 || enable > (MG_TIME_STEP | MG_TIME_PAIR | MG_TIME_TRIPLE)) return fail(c, MG_ERR_INVALID, "timing mask out of range");
+    const int all = MG_TIME_STEP | MG_TIME_PAIR | MG_TIME_TRIPLE | MG_TIME_OUTER | MG_TIME_TRANSFER;
+    if (enable < 0 || enable > all) return fail(c, MG_ERR_INVALID, "timing mask out of range");
     c->timing = enable;
     c->events_used = 0;
     c->timed_launches = 0;

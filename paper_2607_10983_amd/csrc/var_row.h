@@ -15,10 +15,11 @@ hipError_t launch_var_smooth_row(int n, double ih2, const TC* C, const T* x, con
                                  double a, double c, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 // out = b - M x (b != nullptr) or out = M x
 template <typename T, typename TC>
-hipError_t launch_var_resid_row(int n, double ih2, const TC* C, const T* x, const T* b, T* out, hipStream_t s);
+hipError_t launch_var_resid_row(int n, double ih2, const TC* C, const T* x, const T* b, T* out, hipStream_t s,
+                                hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 template <typename TA, typename TR, typename TE, typename TC>
 hipError_t launch_var_outer_row(int n, double ih2, const TC* C, const double* phi_in, const TE* e, double* phi_out,
                                 const double* b, double bmean, TR* r, TR* x1, double c0, double* partials,
-                                hipStream_t s);
+                                hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 }  // namespace mg

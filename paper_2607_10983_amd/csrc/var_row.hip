@@ -571,16 +571,17 @@ hipError_t launch_var_smooth_row(int n, double ih2, const TC* C, const T* x, con
 }
 
 template <typename T, typename TC>
-hipError_t launch_var_resid_row(int n, double ih2, const TC* C, const T* x, const T* b, T* out, hipStream_t s) {
+hipError_t launch_var_resid_row(int n, double ih2, const TC* C, const T* x, const T* b, T* out, hipStream_t s,
+                                hipEvent_t ev0, hipEvent_t ev1) {
     int nz, nyb, blocks;
     shape(n, nz, nyb, blocks);
     DISPATCH_VEC(n, {
         if (b)
-            hipLaunchKernelGGL((k_var_resid_row<T, TC, VEC, true>), dim3(blocks), dim3(kBlock), 0, s, n, (T)ih2, C, x,
-                               b, out, nz, nyb);
+            MG_LAUNCH((k_var_resid_row<T, TC, VEC, true>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (T)ih2, C, x,
+                      b, out, nz, nyb);
         else
-            hipLaunchKernelGGL((k_var_resid_row<T, TC, VEC, false>), dim3(blocks), dim3(kBlock), 0, s, n, (T)ih2, C,
-                               x, b, out, nz, nyb);
+            MG_LAUNCH((k_var_resid_row<T, TC, VEC, false>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (T)ih2, C,
+                      x, b, out, nz, nyb);
     })
     return hipGetLastError();
 }
@@ -588,16 +589,16 @@ hipError_t launch_var_resid_row(int n, double ih2, const TC* C, const T* x, cons
 template <typename TA, typename TR, typename TE, typename TC>
 hipError_t launch_var_outer_row(int n, double ih2, const TC* C, const double* phi_in, const TE* e, double* phi_out,
                                 const double* b, double bmean, TR* r, TR* x1, double c0, double* partials,
-                                hipStream_t s) {
+                                hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     int nz, nyb, blocks;
     shape(n, nz, nyb, blocks);
     DISPATCH_VEC(n, {
         if (e)
-            hipLaunchKernelGGL((k_var_outer_row<TA, TR, TE, TC, VEC, true>), dim3(blocks), dim3(kBlock), 0, s, n,
-                               (TA)ih2, C, phi_in, e, phi_out, b, bmean, r, x1, (TA)c0, partials, nz, nyb);
+            MG_LAUNCH((k_var_outer_row<TA, TR, TE, TC, VEC, true>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n,
+                      (TA)ih2, C, phi_in, e, phi_out, b, bmean, r, x1, (TA)c0, partials, nz, nyb);
         else
-            hipLaunchKernelGGL((k_var_outer_row<TA, TR, TE, TC, VEC, false>), dim3(blocks), dim3(kBlock), 0, s, n,
-                               (TA)ih2, C, phi_in, e, phi_out, b, bmean, r, x1, (TA)c0, partials, nz, nyb);
+            MG_LAUNCH((k_var_outer_row<TA, TR, TE, TC, VEC, false>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n,
+                      (TA)ih2, C, phi_in, e, phi_out, b, bmean, r, x1, (TA)c0, partials, nz, nyb);
     })
     return hipGetLastError();
 }
@@ -605,7 +606,8 @@ hipError_t launch_var_outer_row(int n, double ih2, const TC* C, const double* ph
 #define INST_VAR(T, TC)                                                                                            \
     template hipError_t launch_var_smooth_row<T, TC>(int, double, const TC*, const T*, const T*, const T*, T*,     \
                                                      double, double, hipStream_t, hipEvent_t, hipEvent_t);         \
-    template hipError_t launch_var_resid_row<T, TC>(int, double, const TC*, const T*, const T*, T*, hipStream_t);
+    template hipError_t launch_var_resid_row<T, TC>(int, double, const TC*, const T*, const T*, T*, hipStream_t,   \
+                                                    hipEvent_t, hipEvent_t);
 INST_VAR(float, float)
 INST_VAR(double, double)
 INST_VAR(double, float)
@@ -614,7 +616,7 @@ INST_VAR(float, double)
 #define INST_VOUT(TA, TR, TE, TC)                                                                                  \
     template hipError_t launch_var_outer_row<TA, TR, TE, TC>(int, double, const TC*, const double*, const TE*,     \
                                                              double*, const double*, double, TR*, TR*, double,     \
-                                                             double*, hipStream_t);
+                                                             double*, hipStream_t, hipEvent_t, hipEvent_t);
 INST_VOUT(double, double, double, double)
 INST_VOUT(double, double, double, float)
 INST_VOUT(double, float, float, float)

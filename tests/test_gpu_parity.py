@@ -105,8 +105,6 @@ def test_smooth_jacobi(mgpu):
 @pytest.mark.parametrize("n", [8, 32, 64, 128, 256])
 @pytest.mark.parametrize("var", [False, True])
 def test_residual_restrict_and_prolong(mgpu, n, var):
-    if var and n > 128:
-        pytest.skip("the 19-point oracle at 256^3 is covered by the full-size tests")
     C = random_spd(n) if var else None
     levels = max(2, int(math.log2(n)) - 2)
     mg = mgpu.Multigrid(n, levels=levels, coeff=dev(C) if var else None, precision="fp64")
@@ -354,6 +352,46 @@ def test_autograd_matches_oracle_gradient(mgpu):
     assert float(L) == pytest.approx(np.sum(w * phi), rel=1e-11)
 
 
+def test_solve_fn_raises_when_not_converged(mgpu):
+    """The implicit adjoint is valid only at a converged solve: the
+    differentiable solve raises instead of returning silent gradients."""
+    n = 16
+    psi, C, sg = moving_mesh_coeff(n)
+    b = dev(moving_mesh_field(n, 0) * sg).requires_grad_(True)
+    with pytest.raises(mgpu.MGError) as e:
+        mgpu.solve(b, dev(C), tol=1e-30, max_cycles=2, levels=2, precision="fp64")
+    assert e.value.status == 6
+    # converged: the context built for C is reused by the next call with the same tensor
+    Ct = dev(C)
+    p1 = mgpu.solve(b, Ct, tol=1e-12, max_cycles=100, levels=2, precision="fp64")
+    p2 = mgpu.solve(b, Ct, tol=1e-12, max_cycles=100, levels=2, precision="fp64")
+    assert torch.equal(p1, p2)
+    (p2 * p2).sum().backward()
+    assert b.grad is not None and torch.isfinite(b.grad).all()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_fixed_cycles_match_solve(mgpu, precision):
+    """mg_cycles (a fixed number of warm cycles, no host wait between them)
+    launches the same kernels in the same order as mg_solve with the
+    tolerance disabled: bitwise the same potential and final residual."""
+    n = 64
+    b = dev(flat_source(n, 6))
+    mg = mgpu.Multigrid(n, levels=5, degree=3, precision=precision)
+    phi_s, info = mg.solve(b, tol=0.0, max_cycles=4, raise_on_error=False)
+    phi_c = torch.zeros_like(phi_s)
+    r = mg.cycles(phi_c, b, 4)
+    assert info.cycles == 4
+    assert torch.equal(phi_s, phi_c)
+    assert r == info.rel_res
+    # warm continuation: two more cycles from the result equal a 6-cycle solve
+    mg.cycles(phi_c, b, 2)
+    phi_6, info6 = mg.solve(b, tol=0.0, max_cycles=6, raise_on_error=False)
+    assert rel(host(phi_c), host(phi_6)) <= 1e-13
+    z = torch.zeros_like(phi_c)
+    assert mg.cycles(z, dev(np.full((n, n, n), 1.5)), 3) == 0.0 and float(z.abs().max()) == 0.0
+
+
 # ------------------------------------------------------------------ errors, determinism
 
 def test_invalid_coefficients_rejected(mgpu):
@@ -394,17 +432,14 @@ def test_bitwise_reproducible(mgpu):
 
 
 @pytest.mark.parametrize("var", [False, True])
-def test_graph_replay_matches_eager(mgpu, monkeypatch, var):
+def test_graph_replay_matches_eager(mgpu, var):
     """The coarse sub-cycle replayed from a captured HIP graph gives bitwise the
     same iterates as eager launches, replay after replay, with unrelated eager
     GPU work and synchronisations between the replays."""
     n = 64
     C = dev(moving_mesh_coeff(n)[1]) if var else None
-    monkeypatch.delenv("MG_GRAPH", raising=False)
     eager = mgpu.Multigrid(n, levels=5, coeff=C, precision="mixed")
-    monkeypatch.setenv("MG_GRAPH", "1")
-    graph = mgpu.Multigrid(n, levels=5, coeff=C, precision="mixed")
-    monkeypatch.delenv("MG_GRAPH")
+    graph = mgpu.Multigrid(n, levels=5, coeff=C, precision="mixed", options=mgpu._lib.MG_OPT_GRAPH)
     pe = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
     pg = torch.zeros_like(pe)
     for seed in (11, 12, 13, 14):
@@ -421,16 +456,14 @@ def test_graph_replay_matches_eager(mgpu, monkeypatch, var):
 @pytest.mark.parametrize("n,prec", [(64, "mixed"), (128, "fp64"), (256, "mixed"), (256, "fp64")])
 @pytest.mark.parametrize("degree,smoother", [(2, "chebyshev"), (3, "chebyshev"), (4, "chebyshev"), (6, "chebyshev"),
                                              (3, "jacobi")])
-def test_two_step_kernel_matches_single_steps(mgpu, monkeypatch, n, prec, degree, smoother):
+def test_two_step_kernel_matches_single_steps(mgpu, n, prec, degree, smoother):
     """The two-step smoothing kernel (last two steps of each pass in one
     pass over memory) computes each step in the same order as the single-step
-    kernel: solves agree bitwise with MG_NO_PAIR, cycle by cycle."""
+    kernel: solves agree bitwise with MG_OPT_NO_PAIR, cycle by cycle."""
     b = dev(flat_source(n, 3))
     levels = int(math.log2(n)) - 1
     kw = dict(levels=levels, degree=degree, precision=prec, smoother=smoother, sweeps=degree)
-    monkeypatch.setenv("MG_NO_PAIR", "1")
-    single = mgpu.Multigrid(n, **kw)
-    monkeypatch.delenv("MG_NO_PAIR")
+    single = mgpu.Multigrid(n, options=mgpu._lib.MG_OPT_NO_PAIR, **kw)
     fused = mgpu.Multigrid(n, **kw)
     out = []
     for mg in (single, fused):
@@ -443,16 +476,14 @@ def test_two_step_kernel_matches_single_steps(mgpu, monkeypatch, n, prec, degree
 
 @pytest.mark.parametrize("n,levels", [(32, 4), (32, 2), (64, 5), (64, 3), (128, 6), (256, 7)])
 @pytest.mark.parametrize("degree", [1, 2, 3])
-def test_level_visit_matches_unfused(mgpu, monkeypatch, n, levels, degree):
+def test_level_visit_matches_unfused(mgpu, n, levels, degree):
     """The fused visits of the 32^3 and 64^3 levels (smoothing from zero,
     residual and full weighting in one launch; prolongation and smoothing in
     another) use the point formulas of the separate kernels: mixed-precision
-    solves agree bitwise with MG_NO_VISIT, cycle by cycle."""
+    solves agree bitwise with MG_OPT_NO_VISIT, cycle by cycle."""
     b = dev(flat_source(n, 5))
     kw = dict(levels=levels, degree=degree, precision="mixed")
-    monkeypatch.setenv("MG_NO_VISIT", "1")
-    plain = mgpu.Multigrid(n, **kw)
-    monkeypatch.delenv("MG_NO_VISIT")
+    plain = mgpu.Multigrid(n, options=mgpu._lib.MG_OPT_NO_VISIT, **kw)
     fused = mgpu.Multigrid(n, **kw)
     out = []
     for mg in (plain, fused):
