@@ -15,57 +15,17 @@
 
 #include "fma.h"
 #include "launch.h"
+#include "row.h"
 #include "sums.h"
 
 #include <cstdint>
+#include <type_traits>
 
 namespace mg {
 namespace {
 
 constexpr int kWaves = 4;
 constexpr int kBlock = 64 * kWaves;
-
-typedef int v4i __attribute__((ext_vector_type(4)));
-typedef int v2i __attribute__((ext_vector_type(2)));
-
-// Row segment of VEC contiguous elements through 16-byte (or 8/4-byte) vector
-// accesses.  Plain cached accesses: measured faster than non-temporal ones
-// here, since streaming hints keep the fields out of the Infinity Cache.
-template <typename T, int VEC>
-__device__ __forceinline__ void ldrow(T (&v)[VEC], const T* p) {
-    constexpr int B = VEC * (int)sizeof(T);
-    if constexpr (B >= 16) {
-#pragma unroll
-        for (int k = 0; k < B / 16; ++k) {
-            const v4i t = *(reinterpret_cast<const v4i*>(p) + k);
-            __builtin_memcpy(&v[k * 16 / (int)sizeof(T)], &t, 16);
-        }
-    } else if constexpr (B == 8) {
-        const v2i t = *reinterpret_cast<const v2i*>(p);
-        __builtin_memcpy(&v[0], &t, 8);
-    } else {
-        v[0] = p[0];
-    }
-}
-
-template <typename T, int VEC>
-__device__ __forceinline__ void strow(T* p, const T (&v)[VEC]) {
-    constexpr int B = VEC * (int)sizeof(T);
-    if constexpr (B >= 16) {
-#pragma unroll
-        for (int k = 0; k < B / 16; ++k) {
-            v4i t;
-            __builtin_memcpy(&t, &v[k * 16 / (int)sizeof(T)], 16);
-            *(reinterpret_cast<v4i*>(p) + k) = t;
-        }
-    } else if constexpr (B == 8) {
-        v2i t;
-        __builtin_memcpy(&t, &v[0], 8);
-        *reinterpret_cast<v2i*>(p) = t;
-    } else {
-        p[0] = v[0];
-    }
-}
 
 // A row's copy in LDS.  Rows of at most 16 bytes per lane keep the global
 // layout (lane l at element l * VEC).  Longer rows are stored in 16-byte
@@ -109,26 +69,6 @@ __device__ __forceinline__ void copyrow(T (&d)[VEC], const T (&s)[VEC]) {
     for (int e = 0; e < VEC; ++e) d[e] = s[e];
 }
 
-// Rotating cross-lane move: value of lane (lane + delta) mod 64, delta = +1
-// or -1.  A DPP move across the whole wave (wave_rol:1 brings lane + 1,
-// wave_ror:1 lane - 1): plain VALU, no trip through the LDS crossbar.
-__device__ __forceinline__ int lane_rot32(int v, int delta) {
-    return delta > 0 ? __builtin_amdgcn_update_dpp(0, v, 0x134, 0xF, 0xF, false)
-                     : __builtin_amdgcn_update_dpp(0, v, 0x13C, 0xF, 0xF, false);
-}
-template <typename T>
-__device__ __forceinline__ T lane_rot(T v, int delta) {
-    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
-    if constexpr (sizeof(T) == 4) {
-        return __builtin_bit_cast(T, lane_rot32(__builtin_bit_cast(int, v), delta));
-    } else {
-        v2i h = __builtin_bit_cast(v2i, v);
-        h.x = lane_rot32(h.x, delta);
-        h.y = lane_rot32(h.y, delta);
-        return __builtin_bit_cast(T, h);
-    }
-}
-
 // M x on one row: c = centre row, ym/yp = rows y-1/y+1, zm/zp = planes z-1/z+1.
 // The rounding of the stencil and of the smoothing step below is written out
 // (no contraction left to the compiler), so every kernel that applies a step
@@ -148,33 +88,46 @@ __device__ __forceinline__ void flat7_row(const T (&c)[VEC], const T (&ym)[VEC],
     }
 }
 
+// flat7_row for a row split into segments held by several waves: the
+// x-neighbours beyond the segment (lane 0's left, lane 63's right) are the
+// lane's halo value hx instead of the wrapped-around lanes of its own wave.
+// Same arithmetic as flat7_row.
+template <typename T, int VEC, int S>
+__device__ __forceinline__ void flat7_row_seg(const T (&c)[VEC], const T (&ym)[VEC], const T (&yp)[VEC],
+                                              const T (&zm)[VEC], const T (&zp)[VEC], T ih2, T (&Mx)[VEC], T hx) {
+#pragma clang fp contract(off)
+    T lft = lane_rot(c[VEC - 1], -1);
+    T rgt = lane_rot(c[0], 1);
+    if constexpr (S > 1) {
+        const int lane = threadIdx.x & 63;
+        if (lane == 0) lft = hx;
+        if (lane == 63) rgt = hx;
+    }
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        const T l = e > 0 ? c[e - 1] : lft;
+        const T r = e < VEC - 1 ? c[e + 1] : rgt;
+        const T s = ((l + r) + (ym[e] + yp[e])) + (zm[e] + zp[e]);
+        Mx[e] = fma_rn(T(-6), c[e], s) * ih2;
+    }
+}
+
+// Element of a full row (length S * 64 * VEC) that lane `lane` of the wave
+// holding segment `seg` needs beyond its segment: the one before the segment
+// for the lower half of the wave (lane 0 uses it), the one after it for the
+// upper half (lane 63 uses it).  Periodic in x.
+template <int VEC, int S>
+__device__ __forceinline__ int seg_halo(int seg, int lane) {
+    constexpr int NR = 64 * VEC, NF = NR * S;
+    return lane < 32 ? (seg * NR - 1) & (NF - 1) : ((seg + 1) * NR) & (NF - 1);
+}
+
 // One smoothing step at a point: x + a (x - xp) + cd (b - M x).
 template <typename T>
 __device__ __forceinline__ T cheb_step(T x, T xp, T b, T Mx, T a, T cd) {
 #pragma clang fp contract(off)
     return fma_rn(cd, b - Mx, fma_rn(a, x - xp, x));
 }
-
-// Block id renumbering so that each XCD (blocks are dealt round-robin to the
-// eight XCDs) receives a contiguous range of logical blocks.
-__device__ __forceinline__ int xcd_logical(int bid, int nb) {
-    if (nb & 7) return bid;
-    return (bid & 7) * (nb >> 3) + (bid >> 3);
-}
-
-// Index of the calling wave in its block, as a wave-uniform (scalar) value:
-// row and plane offsets derived from it are then formed by the scalar unit.
-__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
-
-// Row addressing of a periodic n^3 level.  Every row kernel is instantiated
-// for n = 64 * VEC (a lane holds VEC points of a row), so the kernels build
-// it from VEC and its sizes are compile-time constants.
-struct RowGrid {
-    int n, mask;
-    __device__ __forceinline__ size_t row(int y, int z) const {
-        return ((size_t)(z & mask) * (size_t)n + (size_t)(y & mask)) * (size_t)n;
-    }
-};
 
 // =====================================================================================
 // Chebyshev / Jacobi step: out = x + a (x - xprev) + cd (b - M x), cd = c / D
@@ -462,16 +415,24 @@ __device__ __forceinline__ T first_step(T r, T cd0) {
     return r;
 }
 
-template <typename T, int VEC, int NW, bool PREV1, bool Y1OUT, bool FROMB = false, bool PF2 = false, int NZC = 0>
+// S > 1: each row is split into S segments of 64 VEC elements, one per wave
+// (S consecutive waves hold one row), so that long rows keep few values per
+// lane; the x-neighbours across segment ends come from a halo element loaded
+// with each row of the first step's z queue, and from the neighbouring
+// segment's slot in LDS for the second step.
+template <typename T, int VEC, int NW, bool PREV1, bool Y1OUT, bool FROMB = false, bool PF2 = false, int NZC = 0,
+          int S = 1>
 __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* __restrict__ x,
                                                          const T* __restrict__ xp, const T* __restrict__ b,
                                                          T* __restrict__ y2, T* __restrict__ y1o, T a1, T cd1, T a2,
                                                          T cd2, int nz, int nyb, T cd0, SumsJob job) {
     static_assert(!(FROMB && PREV1), "a pass from zero has no x_prev");
+    static_assert(S == 1 || VEC * sizeof(T) <= 16, "split rows keep the plain LDS row layout");
+    static_assert(NW % S == 0, "a block holds whole rows");
     constexpr int NR = 64 * VEC;
-    constexpr int W = NW - 2;
+    constexpr int W = NW / S - 2;
     __shared__ T rows[2][NW][NR];
-    const RowGrid g{64 * VEC, 64 * VEC - 1};
+    const RowGrid g{NR * S, NR * S - 1};
     int nb = gridDim.x, bid = blockIdx.x;
     if constexpr (FROMB) {
         if (job.count > 0) {  // block 0 finishes the sums, dispatched first
@@ -487,11 +448,15 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
     const int lb = xcd_logical(bid, nb);
     const int yb = lb % nyb, zc = lb / nyb;
     const int w = wave_id();
+    const int wr = w / S, seg = w - wr * S;  // row of the block and segment of the row
     const int lane = threadIdx.x & 63;
-    const int y = yb * W - 1 + w;  // rows outside [0, n) wrap for loads
-    const bool outw = w >= 1 && w <= W && y < n;
+    const int y = yb * W - 1 + wr;  // rows outside [0, n) wrap for loads
+    const bool outw = wr >= 1 && wr <= W && y < n;
     const int z0 = zc * nz;
-    const size_t off = (size_t)lane * VEC;
+    const size_t off = (size_t)seg * NR + (size_t)lane * VEC;
+    const int hoff = S > 1 ? seg_halo<VEC, S>(seg, lane) : 0;
+    // LDS slots of the same row's previous / next segment (second-step halo)
+    const int wprev = wr * S + (seg + S - 1) % S, wnext = wr * S + (seg + 1) % S;
     // first step: x on this row at planes z1-1, z1, z1+1, rows y-1 / y+1 at z1, b and xp at z1
     // (FROMB: these hold the b rows, x is formed from them, and b1 / b2 are
     // the queue's own rows)
@@ -499,11 +464,17 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
     // second step: y1 on this row at z2-1 and z2 (z2 = z1 - 1) and b at z2; its
     // x_prev is x at z2, i.e. xm
     T sm[VEC], sc[VEC], b2[VEC];
+    // S > 1: x-halo elements of the centre rows xc, xq (and xa) of the first step
+    T hc = T(0), hq = T(0), ha = T(0);
     const T* src = FROMB ? b : x;
     int z1 = z0 - 1;
     ldrow<T, VEC>(xm, src + g.row(y, z1 - 1) + off);
     ldrow<T, VEC>(xc, src + g.row(y, z1) + off);
     ldrow<T, VEC>(xq, src + g.row(y, z1 + 1) + off);
+    if constexpr (S > 1) {
+        hc = src[g.row(y, z1) + hoff];
+        hq = src[g.row(y, z1 + 1) + hoff];
+    }
     ldrow<T, VEC>(ym, src + g.row(y - 1, z1) + off);
     ldrow<T, VEC>(yp, src + g.row(y + 1, z1) + off);
     if constexpr (!FROMB) ldrow<T, VEC>(b1, b + g.row(y, z1) + off);
@@ -518,6 +489,7 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
     T xa[VEC], yma[VEC], ypa[VEC], ba[VEC], pa[VEC];
     if constexpr (PF2) {
         ldrow<T, VEC>(xa, src + g.row(y, z1 + 2) + off);
+        if constexpr (S > 1) ha = src[g.row(y, z1 + 2) + hoff];
         ldrow<T, VEC>(yma, src + g.row(y - 1, z1 + 1) + off);
         ldrow<T, VEC>(ypa, src + g.row(y + 1, z1 + 1) + off);
         if constexpr (!FROMB) ldrow<T, VEC>(ba, b + g.row(y, z1 + 1) + off);
@@ -528,8 +500,10 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
         const int ahead = PF2 ? 1 : 0;  // the loads below are for plane z1 + 1 + ahead
         const bool load = j + 1 + ahead < steps;
         T xn[VEC], ymn[VEC], ypn[VEC], bn[VEC], pn[VEC];
+        T hn = T(0);
         if (load) {
             ldrow<T, VEC>(xn, src + g.row(y, z1 + 2 + ahead) + off);
+            if constexpr (S > 1) hn = src[g.row(y, z1 + 2 + ahead) + hoff];
             ldrow<T, VEC>(ymn, src + g.row(y - 1, z1 + 1 + ahead) + off);
             ldrow<T, VEC>(ypn, src + g.row(y + 1, z1 + 1 + ahead) + off);
             if constexpr (!FROMB) ldrow<T, VEC>(bn, b + g.row(y, z1 + 1 + ahead) + off);
@@ -546,11 +520,11 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
                 fym[e] = first_step<T, FROMB>(ym[e], cd0);
                 fyp[e] = first_step<T, FROMB>(yp[e], cd0);
             }
-            flat7_row<T, VEC>(fc, fym, fyp, fm, fq, ih2, M1);
+            flat7_row_seg<T, VEC, S>(fc, fym, fyp, fm, fq, ih2, M1, first_step<T, FROMB>(hc, cd0));
 #pragma unroll
             for (int e = 0; e < VEC; ++e) sp[e] = cheb_step<T>(fc[e], T(0), xc[e], M1[e], a1, cd1);
         } else {
-            flat7_row<T, VEC>(xc, ym, yp, xm, xq, ih2, M1);
+            flat7_row_seg<T, VEC, S>(xc, ym, yp, xm, xq, ih2, M1, hc);
 #pragma unroll
             for (int e = 0; e < VEC; ++e) sp[e] = cheb_step<T>(xc[e], PREV1 ? p1[e] : T(0), b1[e], M1[e], a1, cd1);
         }
@@ -563,9 +537,11 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
             __syncthreads();
             if (outw) {
                 T nm[VEC], np[VEC], M2[VEC], o[VEC];
-                lds_ldrow<T, VEC>(nm, rows[buf][w - 1], lane);
-                lds_ldrow<T, VEC>(np, rows[buf][w + 1], lane);
-                flat7_row<T, VEC>(sc, nm, np, sm, sp, ih2, M2);
+                lds_ldrow<T, VEC>(nm, rows[buf][w - S], lane);
+                lds_ldrow<T, VEC>(np, rows[buf][w + S], lane);
+                T hs = T(0);
+                if constexpr (S > 1) hs = lane < 32 ? rows[buf][wprev][NR - 1] : rows[buf][wnext][0];
+                flat7_row_seg<T, VEC, S>(sc, nm, np, sm, sp, ih2, M2, hs);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) {
                     if constexpr (FROMB)  // x_prev = first step at z2, b at z2 = the raw queue row
@@ -582,7 +558,10 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
         if (more) {
             copyrow(xm, xc);
             copyrow(xc, xq);
+            hc = hq;
             if constexpr (PF2) {
+                hq = ha;
+                if (load) ha = hn;
                 copyrow(xq, xa);
                 copyrow(ym, yma);
                 copyrow(yp, ypa);
@@ -596,6 +575,7 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
                     if constexpr (PREV1) copyrow(pa, pn);
                 }
             } else {
+                hq = hn;
                 copyrow(xq, xn);
                 copyrow(ym, ymn);
                 copyrow(yp, ypn);
@@ -1336,6 +1316,58 @@ hipError_t launch_pair_nw(int n, double ih2, const T* x, const T* xp, const T* b
 #undef MG_PAIR
 #undef MG_PAIR1
 
+// Rows longer than kPairSegBytes run the two-step kernels split into segments
+// of that many bytes, one wave each, with the block shape and chunk length of
+// the 1 KB rows of 256^3 float (16 waves = 8 rows, chunks of 8 planes): a
+// lane then holds 16 bytes of a row, and the register budget of 16-wave
+// blocks holds the fully unrolled variants.
+constexpr size_t kPairSegBytes = 1024;
+inline int pair_segments(int n, size_t elem) {
+    const size_t row = (size_t)n * elem;
+    return row > kPairSegBytes ? (int)(row / kPairSegBytes) : 1;
+}
+
+#define MG_PAIRS(PREV1, Y1OUT, FROMB, PF2)                                                                         \
+    MG_LAUNCH((k_smooth2_lds<T, VEC, NW, PREV1, Y1OUT, FROMB, PF2, kPairUnrollNz, S>),                          \
+              dim3(blocks + (FROMB ? extra : 0)), dim3(64 * NW), s, ev0, ev1, n, (T)ih2, x, xp, b, y2, y1, (T)a1, \
+              (T)cd1, (T)a2, (T)cd2, kPairUnrollNz, nyb, (T)cd0, FROMB ? sums : SumsJob{})
+template <typename T, int NW, int S>
+hipError_t launch_pair_seg(int n, double ih2, const T* x, const T* xp, const T* b, T* y2, T* y1, double a1,
+                           double cd1, double a2, double cd2, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
+                           int x0_mode, double cd0, const SumsJob& sums) {
+    constexpr int W = NW / S - 2;
+    const int extra = sums.count > 0 ? 1 : 0;  // the block that finishes the sums (pass from zero only)
+    const int nyb = (n + W - 1) / W;
+    if (n % kPairUnrollNz != 0) return hipErrorInvalidValue;
+    const int blocks = nyb * (n / kPairUnrollNz);
+    const int vec = n / (64 * S);
+    auto go = [&](auto vtag) -> hipError_t {
+        constexpr int VEC = decltype(vtag)::value;
+        if constexpr (VEC * sizeof(T) <= 16 && 2ull * NW * 64 * VEC * sizeof(T) <= kPairLdsBudget) {
+            if (x0_mode != 0) {
+                if (y1 == nullptr) MG_PAIRS(false, false, true, true);
+                else MG_PAIRS(false, true, true, true);
+            } else if (xp == nullptr && y1 == nullptr) {
+                MG_PAIRS(false, false, false, false);
+            } else if (xp == nullptr) {
+                MG_PAIRS(false, true, false, false);
+            } else if (y1 == nullptr) {
+                MG_PAIRS(true, false, false, false);
+            } else {
+                MG_PAIRS(true, true, false, false);
+            }
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    };
+    switch (vec) {
+        case 2: return go(std::integral_constant<int, 2>{});
+        case 4: return go(std::integral_constant<int, 4>{});
+        default: return hipErrorInvalidValue;
+    }
+}
+#undef MG_PAIRS
+
 template <typename T>
 hipError_t launch_smooth_pair_row(int n, double ih2, const T* x, const T* xp, const T* b, T* y2, T* y1,
                                   double a1, double cd1, double a2, double cd2, hipStream_t s, hipEvent_t ev0,
@@ -1345,6 +1377,13 @@ hipError_t launch_smooth_pair_row(int n, double ih2, const T* x, const T* xp, co
     if (sums.count > 0 && x0_mode == 0) return hipErrorInvalidValue;
     if (x0_mode == 0 && x == nullptr) return hipErrorInvalidValue;
     if (x0_mode != 0 && xp != nullptr) return hipErrorInvalidValue;
+    switch (pair_segments(n, sizeof(T))) {
+        case 1: break;
+        case 2:
+            return launch_pair_seg<T, 16, 2>(n, ih2, x, xp, b, y2, y1, a1, cd1, a2, cd2, s, ev0, ev1, x0_mode, cd0,
+                                             sums);
+        default: return hipErrorInvalidValue;
+    }
     int waves = kPairWavesDefault;
     // The pass from zero (one field read) runs best in larger blocks where the
     // row fits their register budget: 256^3 16 waves 33.8 us (8: 35.4, 12: 38.3),

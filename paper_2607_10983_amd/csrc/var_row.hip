@@ -19,51 +19,13 @@
 #include "var_row.h"
 
 #include "launch.h"
+#include "row.h"
 
 namespace mg {
 namespace {
 
 constexpr int kWaves = 4;
 constexpr int kBlock = 64 * kWaves;
-
-typedef int v4i __attribute__((ext_vector_type(4)));
-typedef int v2i __attribute__((ext_vector_type(2)));
-
-template <typename T, int VEC>
-__device__ __forceinline__ void ldrow(T (&v)[VEC], const T* p) {
-    constexpr int B = VEC * (int)sizeof(T);
-    if constexpr (B >= 16) {
-#pragma unroll
-        for (int k = 0; k < B / 16; ++k) {
-            const v4i t = *(reinterpret_cast<const v4i*>(p) + k);
-            __builtin_memcpy(&v[k * 16 / (int)sizeof(T)], &t, 16);
-        }
-    } else if constexpr (B == 8) {
-        const v2i t = *reinterpret_cast<const v2i*>(p);
-        __builtin_memcpy(&v[0], &t, 8);
-    } else {
-        v[0] = p[0];
-    }
-}
-
-template <typename T, int VEC>
-__device__ __forceinline__ void strow(T* p, const T (&v)[VEC]) {
-    constexpr int B = VEC * (int)sizeof(T);
-    if constexpr (B >= 16) {
-#pragma unroll
-        for (int k = 0; k < B / 16; ++k) {
-            v4i t;
-            __builtin_memcpy(&t, &v[k * 16 / (int)sizeof(T)], 16);
-            *(reinterpret_cast<v4i*>(p) + k) = t;
-        }
-    } else if constexpr (B == 8) {
-        v2i t;
-        __builtin_memcpy(&t, &v[0], 8);
-        *reinterpret_cast<v2i*>(p) = t;
-    } else {
-        p[0] = v[0];
-    }
-}
 
 // coefficient row in compute precision T
 template <typename T, typename TC, int VEC>
@@ -73,28 +35,6 @@ __device__ __forceinline__ void ldcrow(T (&v)[VEC], const TC* p) {
 #pragma unroll
     for (int e = 0; e < VEC; ++e) v[e] = (T)t[e];
 }
-
-// Rotating cross-lane move: value of lane (lane + delta) mod 64, delta = +1
-// or -1, as a DPP move across the whole wave (wave_rol:1 / wave_ror:1).
-__device__ __forceinline__ int lane_rot32(int v, int delta) {
-    return delta > 0 ? __builtin_amdgcn_update_dpp(0, v, 0x134, 0xF, 0xF, false)
-                     : __builtin_amdgcn_update_dpp(0, v, 0x13C, 0xF, 0xF, false);
-}
-template <typename T>
-__device__ __forceinline__ T lane_rot(T v, int delta) {
-    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
-    if constexpr (sizeof(T) == 4) {
-        return __builtin_bit_cast(T, lane_rot32(__builtin_bit_cast(int, v), delta));
-    } else {
-        v2i h = __builtin_bit_cast(v2i, v);
-        h.x = lane_rot32(h.x, delta);
-        h.y = lane_rot32(h.y, delta);
-        return __builtin_bit_cast(T, h);
-    }
-}
-
-// Index of the calling wave in its block as a wave-uniform (scalar) value.
-__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // Row shifted by +1 / -1 in x: element e of the result is row[e + 1] / row[e - 1].
 template <typename T, int VEC>
@@ -107,20 +47,6 @@ __device__ __forceinline__ void shifts(const T (&r)[VEC], T (&p)[VEC], T (&m)[VE
         m[e] = e > 0 ? r[e - 1] : last_prev;
     }
 }
-
-__device__ __forceinline__ int xcd_logical(int bid, int nb) {
-    if (nb & 7) return bid;
-    return (bid & 7) * (nb >> 3) + (bid >> 3);
-}
-
-// Row addressing of a periodic n^3 level; the kernels are instantiated for
-// n = 64 * VEC and build it from VEC, so its sizes are compile-time constants.
-struct RowGrid {
-    int n, mask;
-    __device__ __forceinline__ size_t row(int y, int z) const {
-        return ((size_t)(z & mask) * (size_t)n + (size_t)(y & mask)) * (size_t)n;
-    }
-};
 
 // z queue of the own row's C^{zz}, C^{xz}, C^{yz} at planes z-1, z, z+1 (index 0, 1, 2)
 template <typename T, int VEC>

@@ -289,8 +289,9 @@ def test_19_point_steps_256(mgpu, precision):
     print(f"19-point residual_restrict 256^3 {precision}: {err:.2e}", flush=True)
     assert err <= bar
     del Mx, out, ref
-    H = O.build_hierarchy(n, 1, 3, C=C)
-    ref = O.smooth(H, H.levels[0], x, b)
+    # one level of the oracle's hierarchy (its coarsest-level dense solver is not needed)
+    lev = O.Level(n, h, C, 1.0 / O.diag_var(C, h), O.cheb_coeffs(O.gershgorin_lmax_var(C, h), 8.0))
+    ref = O.smooth(O.Hierarchy([lev], 3, 8.0), lev, x, b)
     out = host(mg.inner_step("smooth", 0, x=dev(x), b=dev(b)))
     err = np.max(np.abs(out - ref)) / np.max(np.abs(ref))
     print(f"19-point smoothing pass 256^3 {precision}: {err:.2e}", flush=True)

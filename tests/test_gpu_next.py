@@ -223,15 +223,17 @@ def test_predict_growth_beats_recycling(mgpu):
 
 # ------------------------------------------------ force readout
 
-@pytest.mark.parametrize("n", [4, 8, 32])
+@pytest.mark.parametrize("n", [4, 8, 32, 64, 128, 256])
 @pytest.mark.parametrize("curv", [False, True])
 def test_accel(mgpu, n, curv):
+    """Element-wise against the oracle: the column kernel below 64^3, the
+    row-wave kernel (x-neighbours by lane rotation, z queue) from 64^3."""
     h = 1.0 / n
     phi = RNG.standard_normal((n, n, n))
     psi = None
     if curv:
         psi = psi_unit(n)
-        psi *= 0.5 * O.admissible_scale(psi, h)
+        psi *= 0.5 * (PSI_SCALE[str(n)] if str(n) in PSI_SCALE else O.admissible_scale(psi, h))
     ref = O.accel(phi, h, psi, 0.45)
     out = host(mgpu.accel(dev(phi), dev(psi) if curv else None, scale=0.45))
     assert np.max(np.abs(out - ref)) <= 1e-13 * np.max(np.abs(ref))

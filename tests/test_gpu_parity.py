@@ -384,10 +384,12 @@ def test_fixed_cycles_match_solve(mgpu, precision):
     assert info.cycles == 4
     assert torch.equal(phi_s, phi_c)
     assert r == info.rel_res
-    # warm continuation: two more cycles from the result equal a 6-cycle solve
+    # warm continuation: two more cycles from the gauge-fixed result equal a
+    # 6-cycle solve up to rounding (the float inner cycle of mixed precision
+    # sees the shifted iterate's residual rounded differently)
     mg.cycles(phi_c, b, 2)
     phi_6, info6 = mg.solve(b, tol=0.0, max_cycles=6, raise_on_error=False)
-    assert rel(host(phi_c), host(phi_6)) <= 1e-13
+    assert rel(host(phi_c), host(phi_6)) <= (1e-13 if precision == "fp64" else 1e-11)
     z = torch.zeros_like(phi_c)
     assert mg.cycles(z, dev(np.full((n, n, n), 1.5)), 3) == 0.0 and float(z.abs().max()) == 0.0
 
@@ -453,13 +455,15 @@ def test_graph_replay_matches_eager(mgpu, var):
         assert torch.equal(pe, pg)
 
 
-@pytest.mark.parametrize("n,prec", [(64, "mixed"), (128, "fp64"), (256, "mixed"), (256, "fp64")])
+@pytest.mark.parametrize("n,prec", [(64, "mixed"), (128, "fp64"), (256, "mixed"), (256, "fp64"), (512, "mixed")])
 @pytest.mark.parametrize("degree,smoother", [(2, "chebyshev"), (3, "chebyshev"), (4, "chebyshev"), (6, "chebyshev"),
                                              (3, "jacobi")])
 def test_two_step_kernel_matches_single_steps(mgpu, n, prec, degree, smoother):
     """The two-step smoothing kernel (last two steps of each pass in one
     pass over memory) computes each step in the same order as the single-step
-    kernel: solves agree bitwise with MG_OPT_NO_PAIR, cycle by cycle."""
+    kernel: solves agree bitwise with MG_OPT_NO_PAIR, cycle by cycle.  Rows
+    of more than 1 KB (512^3 float, 256^3 double) run the two-step kernels
+    split over two waves per row."""
     b = dev(flat_source(n, 3))
     levels = int(math.log2(n)) - 1
     kw = dict(levels=levels, degree=degree, precision=prec, smoother=smoother, sweeps=degree)
