@@ -238,6 +238,22 @@ mg_status mg_geometry(int n, double h, const double* psi, void* C_out, int dtype
 mg_status mg_geometry_bwd(int n, double h, const double* psi, const double* Cbar,
                           const double* sqrtgbar, double* psibar, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops with a fixed memory budget, harnesses that forbid
+ * hipMalloc): mg_geometry_bwd with the same arguments and the same result
+ * bits, but its 6 n^3 double temporary replaced by a library-owned device
+ * array of MG_NOALLOC_SCRATCH_BYTES per GPU (allocated when the library's
+ * code is loaded on that GPU, held until the process ends), through which
+ * the grid is processed in z slabs.  n <= MG_NOALLOC_MAX_N, else
+ * MG_ERR_INVALID.  Calls no hipMalloc, hipFree or allocating routine and does
+ * not synchronise (stream-ordered).  Every call on one GPU uses that GPU's
+ * array, so calls that overlap on one GPU (different streams or threads)
+ * race and must be ordered by the caller. */
+#define MG_NOALLOC_MAX_N 512
+#define MG_NOALLOC_SCRATCH_BYTES (48u * 1024u * 1024u)
+mg_status mg_geometry_bwd_noalloc(int n, double h, const double* psi, const double* Cbar,
+                                  const double* sqrtgbar, double* psibar, void* stream);
+
 /* ---- initial guesses and force readout ----------------------------------- */
 
 enum mg_predictor {

@@ -18,6 +18,7 @@ MG_ERR_NOT_CONVERGED = 6
 MG_FP64, MG_MIXED, MG_FP32 = 0, 1, 2
 MG_CHEBYSHEV, MG_JACOBI = 0, 1
 MG_DTYPE_F32, MG_DTYPE_F64 = 0, 1
+MG_NOALLOC_MAX_N = 512
 MG_PREDICT_RECYCLE, MG_PREDICT_GROWTH, MG_PREDICT_LINEAR, MG_PREDICT_QUADRATIC = 0, 1, 2, 3
 MG_TIME_STEP, MG_TIME_PAIR, MG_TIME_TRIPLE, MG_TIME_OUTER, MG_TIME_TRANSFER = 1, 2, 4, 8, 16
 MG_OPT_NO_PAIR, MG_OPT_NO_VISIT, MG_OPT_NO_TAIL, MG_OPT_NO_FUSED_SUMS, MG_OPT_GRAPH = 1, 2, 4, 8, 16
@@ -73,6 +74,7 @@ SIGNATURES = {
     "mg_coeff_grad": (_I, [_P, _P, _P, _P, _I]),
     "mg_geometry": (_I, [_I, _D, _P, _P, _I, _P, _P]),
     "mg_geometry_bwd": (_I, [_I, _D, _P, _P, _P, _P, _P]),
+    "mg_geometry_bwd_noalloc": (_I, [_I, _D, _P, _P, _P, _P, _P]),
     "mg_predict": (_I, [_I, _I, _P, _P, _P, _D, _P, _P]),
     "mg_accel": (_I, [_I, _D, _P, _P, _D, _P, _I, _P]),
     "mg_apply": (_I, [_P, _I, _P, _P]),

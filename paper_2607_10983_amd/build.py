@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmg.so")
 OBJDIR = os.path.join(ROOT, "_build")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("flat_row.hip", "var_row.hip", "kernels.hip", "tail.hip",
-                                                    "visit.hip", "pcg.hip", "readout.hip",
+                                                    "visit.hip", "pcg.hip", "readout.hip", "noalloc.hip",
                                                     "mg_api.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

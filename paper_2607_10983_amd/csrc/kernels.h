@@ -127,12 +127,18 @@ hipError_t launch_coeff_grad(int n, double ih2, const double* lam, const double*
 template <typename TO>
 hipError_t launch_geometry(int n, double ih2, const double* psi, TO* C, double* sqrtg,
                            hipStream_t s);
-// Jbar (6 n^3 doubles, symmetric storage: off-diagonal = Jbar_ab + Jbar_ba)
+// Jbar (symmetric storage: off-diagonal = Jbar_ab + Jbar_ba) of the planes
+// zlo .. zlo + planes - 1 (mod n), 6 planes n^2 doubles laid out [c][plane][y][x];
+// planes = 0: the whole grid (6 n^3 doubles, zlo = 0).
 hipError_t launch_geometry_bwd_cell(int n, double ih2, const double* psi, const double* Cbar,
-                                    const double* sqrtgbar, double* Jbar, hipStream_t s);
-// psibar = sum_ab Hess_ab(Jbar_ab)
+                                    const double* sqrtgbar, double* Jbar, hipStream_t s,
+                                    int zlo = 0, int planes = 0);
+// psibar = sum_ab Hess_ab(Jbar_ab) on the planes z0 .. z0 + count - 1, from a
+// Jbar slab (zlo, planes) that holds z0 - 1 .. z0 + count (or the whole grid:
+// planes = 0, count = 0).
 hipError_t launch_hessian_adjoint(int n, double ih2, const double* Jbar, double* psibar,
-                                  hipStream_t s);
+                                  hipStream_t s, int zlo = 0, int planes = 0, int z0 = 0,
+                                  int count = 0);
 
 // ---- multigrid-preconditioned conjugate gradients (double recurrences) ----------
 // Scalars live in device memory so no pass waits for the host:

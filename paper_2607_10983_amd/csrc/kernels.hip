@@ -498,17 +498,24 @@ __global__ __launch_bounds__(kThreads) void k_geometry(int n, double ih2, const 
 
 // Per cell: Jbar = t K - d (P + P^T), P = K G K^2, t = d <G, K^2> + sqrtgbar d,
 // G the full symmetric cotangent of C (stored off-diagonals halved).
+// Jbar of the planes zlo .. zlo + planes - 1 (mod n): plane p of component c
+// at Jbar[c * planes n^2 + p n^2 + y n + x] (the whole grid when zlo = 0 and
+// planes = n).
 __global__ __launch_bounds__(kThreads) void k_geometry_bwd_cell(int n, double ih2, const double* __restrict__ psi,
                                                                 const double* __restrict__ Cbar,
                                                                 const double* __restrict__ sbar,
-                                                                double* __restrict__ Jbar, int nz) {
+                                                                double* __restrict__ Jbar, int zlo, int planes,
+                                                                int nz) {
     const Grid g{n, n - 1};
     const size_t N = (size_t)n * n * n;
+    const size_t NS = (size_t)planes * n * n;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z0 = blockIdx.z * nz;
-    for (int z = z0; z < z0 + nz; ++z) {
+    const int p0 = blockIdx.z * nz;
+    for (int p = p0; p < p0 + nz && p < planes; ++p) {
+        const int z = (zlo + p) & (n - 1);
         const size_t i = g(x, y, z);
+        const size_t is = ((size_t)p * n + y) * n + x;
         double H[6];
         hess_at(psi, g, x, y, z, ih2, H);
         H[0] += 1.0; H[1] += 1.0; H[2] += 1.0;
@@ -531,39 +538,48 @@ __global__ __launch_bounds__(kThreads) void k_geometry_bwd_cell(int n, double ih
             const int a = pa[c], b = pb[c];
             const double jab = t * K.m[a][b] - d * (P.m[a][b] + P.m[b][a]);
             const double jba = t * K.m[b][a] - d * (P.m[b][a] + P.m[a][b]);
-            Jbar[c * N + i] = c < 3 ? jab : jab + jba;
+            Jbar[c * NS + is] = c < 3 ? jab : jab + jba;
         }
     }
 }
 
+// psibar on planes z0 .. z0 + count - 1 from the Jbar planes zlo .. zlo +
+// planes - 1 of k_geometry_bwd_cell; they must include z0 - 1 .. z0 + count
+// unless they are the whole grid.
 __global__ __launch_bounds__(kThreads) void k_hessian_adjoint(int n, double ih2, const double* __restrict__ Jb,
-                                                              double* __restrict__ out, int nz) {
+                                                              double* __restrict__ out, int zlo, int planes, int z0,
+                                                              int count, int nz) {
     const Grid g{n, n - 1};
-    const size_t N = (size_t)n * n * n;
+    const size_t NS = (size_t)planes * n * n;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z0 = blockIdx.z * nz;
-    for (int z = z0; z < z0 + nz; ++z) {
+    const int k0 = blockIdx.z * nz;
+    for (int k = k0; k < k0 + nz && k < count; ++k) {
+        const int z = z0 + k;
+        const int q = (z - zlo) & (n - 1);  // plane of z in the Jbar slab
         double acc = 0.0;
         for (int c = 0; c < 6; ++c) {
-            const double* u = Jb + c * N;
-            double H[6];
+            const double* u = Jb + c * NS;
+            // x and y wrap on the grid, z indexes the slab's planes (and wraps
+            // when the slab is the whole grid)
+            auto at = [&](int dx, int dy, int dz) {
+                return u[g(x + dx, y + dy, 0) + (size_t)((q + dz) & (n - 1)) * n * n];
+            };
             // only component c of the Hessian stencil applied to field c is needed
             if (c < 3) {
                 const int dx = c == 0, dy = c == 1, dz = c == 2;
-                acc += (u[g(x + dx, y + dy, z + dz)] - 2.0 * u[g(x, y, z)] + u[g(x - dx, y - dy, z - dz)]) * ih2;
+                acc += (at(dx, dy, dz) - 2.0 * at(0, 0, 0) + at(-dx, -dy, -dz)) * ih2;
             } else {
-                (void)H;
                 const int a = c == 5 ? 1 : 0, b = c == 3 ? 1 : 2;
                 int ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0;
                 (a == 0 ? ax : ay) = 1;
                 (b == 1 ? by : bz) = 1;
-                acc += (u[g(x + ax + bx, y + ay + by, z + az + bz)] - u[g(x + ax - bx, y + ay - by, z + az - bz)] -
-                        u[g(x - ax + bx, y - ay + by, z - az + bz)] + u[g(x - ax - bx, y - ay - by, z - az - bz)]) *
+                acc += (at(ax + bx, ay + by, az + bz) - at(ax - bx, ay - by, az - bz) -
+                        at(-ax + bx, -ay + by, -az + bz) + at(-ax - bx, -ay - by, -az - bz)) *
                        0.25 * ih2;
             }
         }
-        out[g(x, y, z)] = acc;
+        out[g(x, y, z & (n - 1))] = acc;
     }
 }
 
@@ -757,14 +773,22 @@ hipError_t launch_geometry(int n, double ih2, const double* psi, TO* C, double* 
     return hipGetLastError();
 }
 hipError_t launch_geometry_bwd_cell(int n, double ih2, const double* psi, const double* Cbar, const double* sbar,
-                                    double* Jbar, hipStream_t s) {
+                                    double* Jbar, hipStream_t s, int zlo, int planes) {
+    if (planes <= 0) planes = n;
     Shape sh = stencil_shape(n);
-    hipLaunchKernelGGL(k_geometry_bwd_cell, sh.grid, sh.block, 0, s, n, ih2, psi, Cbar, sbar, Jbar, sh.nz);
+    const int chunks = (planes + sh.nz - 1) / sh.nz;
+    hipLaunchKernelGGL(k_geometry_bwd_cell, dim3(sh.grid.x, sh.grid.y, chunks), sh.block, 0, s, n, ih2, psi, Cbar,
+                       sbar, Jbar, zlo, planes, sh.nz);
     return hipGetLastError();
 }
-hipError_t launch_hessian_adjoint(int n, double ih2, const double* Jbar, double* psibar, hipStream_t s) {
+hipError_t launch_hessian_adjoint(int n, double ih2, const double* Jbar, double* psibar, hipStream_t s, int zlo,
+                                  int planes, int z0, int count) {
+    if (planes <= 0) planes = n;
+    if (count <= 0) count = n;
     Shape sh = stencil_shape(n);
-    hipLaunchKernelGGL(k_hessian_adjoint, sh.grid, sh.block, 0, s, n, ih2, Jbar, psibar, sh.nz);
+    const int chunks = (count + sh.nz - 1) / sh.nz;
+    hipLaunchKernelGGL(k_hessian_adjoint, dim3(sh.grid.x, sh.grid.y, chunks), sh.block, 0, s, n, ih2, Jbar, psibar,
+                       zlo, planes, z0, count, sh.nz);
     return hipGetLastError();
 }
 
