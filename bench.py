@@ -128,6 +128,18 @@ def model_bytes_per_cycle(n, levels, degree, precision):
     return tot
 
 
+def reference_bytes_per_cycle(n, degree, precision):
+    """Bytes of one outer iteration in the reference decomposition into one
+    streaming pass per step (each field element of a step read or written
+    once): per level visit from zero 9.25 s + 8 s (v - 1) (first step from
+    zero 2 s, later steps 4 s, residual + full weighting and prolongation
+    2 s + s / 8 each, first post-smoothing step 3 s), the hierarchy x 8/7,
+    plus the outer update (32 B mixed) or the FP64 convergence pass (24 B)."""
+    s = 8 if precision == "fp64" else 4
+    inner = (9.25 + 8 * (degree - 1)) * s * 8.0 / 7.0
+    return n ** 3 * (inner + (24 if precision == "fp64" else 32))
+
+
 def run_sequence(mg, sources, phi, tol, max_cycles=60):
     phi.zero_()
     cycles = []
@@ -241,6 +253,8 @@ def sweep_point(mgpu, torch, flat_source, n, tol):
             "model_bytes_per_cycle_per_pt": round(mb / n ** 3, 2),
             "cycle_GBps": round(gbps, 1),
             "cycle_frac": round(gbps / HBM_PEAK_GBPS, 4),
+            "cycle_frac_reference": round(info.cycles * reference_bytes_per_cycle(n, deg, prec) / (ms * 1e-3) / 1e9
+                                          / HBM_PEAK_GBPS, 4),
         }
         if kt is not None:
             out[prec]["fine_kernels"] = [kernel_entry(k, kt[k], n, prec, ms, per="solve")
@@ -294,6 +308,9 @@ def b512_leg(mgpu, torch, flat_source, n=512, levels=6, deg=4, cycles=20, reps=5
             "vcycle_mpts_per_s": round(cycles * N / (ms * 1e-3) / 1e6, 1),
             "model_bytes_per_cycle_per_pt": round(model_bytes_per_cycle(n, levels, deg, prec) / N, 2),
             "cycle_GBps": round(gbps, 1), "cycle_frac": round(gbps / HBM_PEAK_GBPS, 4),
+            "reference_bytes_per_cycle_per_pt": round(reference_bytes_per_cycle(n, deg, prec) / N, 2),
+            "cycle_frac_reference": round(cycles * reference_bytes_per_cycle(n, deg, prec) / (ms * 1e-3) / 1e9
+                                          / HBM_PEAK_GBPS, 4),
             "rel_res_after": rel,
             "fine_kernels": [kernel_entry(k, kt[k], n, prec, ms, per="call") for k in KINDS if kt[k][0]],
         }

@@ -132,16 +132,25 @@ __device__ __forceinline__ T cheb_step(T x, T xp, T b, T Mx, T a, T cd) {
 // =====================================================================================
 // Chebyshev / Jacobi step: out = x + a (x - xprev) + cd (b - M x), cd = c / D
 // =====================================================================================
-template <typename T, int VEC, bool HASX, bool PREV>
+// S > 1: each row split into S segments of 64 VEC elements, one per wave (a
+// block of kWaves waves holds kWaves / S rows), so that rows of several KB
+// keep a modest number of values per lane; the x-neighbours across segment
+// ends come from one halo element loaded with each centre row.
+template <typename T, int VEC, bool HASX, bool PREV, int S = 1>
 __global__ __launch_bounds__(kBlock) void k_smooth_row(int n, T ih2, const T* x, const T* xprev,
                                                        const T* __restrict__ b, T* out, T a, T cd, int nz,
                                                        int nyb) {
-    const RowGrid g{64 * VEC, 64 * VEC - 1};
+    static_assert(kWaves % S == 0, "a block holds whole rows");
+    constexpr int NR = 64 * VEC;
+    const RowGrid g{NR * S, NR * S - 1};
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int yb = lb % nyb, zc = lb / nyb;
-    const int y = yb * kWaves + wave_id();
+    const int w = wave_id();
+    const int y = yb * (kWaves / S) + w / S, seg = w % S;
     const int z0 = zc * nz;
-    const size_t off = (size_t)(threadIdx.x & 63) * VEC;
+    const int lane = threadIdx.x & 63;
+    const size_t off = (size_t)seg * NR + (size_t)lane * VEC;
+    const int hoff = S > 1 ? seg_halo<VEC, S>(seg, lane) : 0;
     if constexpr (!HASX) {
         for (int k = 0; k < nz; ++k) {
             const size_t r = g.row(y, z0 + k) + off;
@@ -154,9 +163,14 @@ __global__ __launch_bounds__(kBlock) void k_smooth_row(int n, T ih2, const T* x,
         return;
     } else {
         T zm[VEC], c[VEC], zp[VEC], ym[VEC], yp[VEC], bb[VEC], pp[VEC];
+        T hc = T(0), hp = T(0);  // x-halo of c and zp (S > 1)
         ldrow<T, VEC>(zm, x + g.row(y, z0 - 1) + off);
         ldrow<T, VEC>(c, x + g.row(y, z0) + off);
         ldrow<T, VEC>(zp, x + g.row(y, z0 + 1) + off);
+        if constexpr (S > 1) {
+            hc = x[g.row(y, z0) + hoff];
+            hp = x[g.row(y, z0 + 1) + hoff];
+        }
         ldrow<T, VEC>(ym, x + g.row(y - 1, z0) + off);
         ldrow<T, VEC>(yp, x + g.row(y + 1, z0) + off);
         ldrow<T, VEC>(bb, b + g.row(y, z0) + off);
@@ -165,16 +179,18 @@ __global__ __launch_bounds__(kBlock) void k_smooth_row(int n, T ih2, const T* x,
             const int z = z0 + k;
             // prefetch the next plane's operands before any store of this plane
             T zpp[VEC], ymn[VEC], ypn[VEC], bn[VEC], pn[VEC];
+            T hpp = T(0);
             const bool more = k + 1 < nz;
             if (more) {
                 ldrow<T, VEC>(zpp, x + g.row(y, z + 2) + off);
+                if constexpr (S > 1) hpp = x[g.row(y, z + 2) + hoff];
                 ldrow<T, VEC>(ymn, x + g.row(y - 1, z + 1) + off);
                 ldrow<T, VEC>(ypn, x + g.row(y + 1, z + 1) + off);
                 ldrow<T, VEC>(bn, b + g.row(y, z + 1) + off);
                 if constexpr (PREV) ldrow<T, VEC>(pn, xprev + g.row(y, z + 1) + off);
             }
             T Mx[VEC], o[VEC];
-            flat7_row<T, VEC>(c, ym, yp, zm, zp, ih2, Mx);
+            flat7_row_seg<T, VEC, S>(c, ym, yp, zm, zp, ih2, Mx, hc);
 #pragma unroll
             for (int e = 0; e < VEC; ++e) o[e] = cheb_step<T>(c[e], PREV ? pp[e] : T(0), bb[e], Mx[e], a, cd);
             strow<T, VEC>(out + g.row(y, z) + off, o);
@@ -182,6 +198,8 @@ __global__ __launch_bounds__(kBlock) void k_smooth_row(int n, T ih2, const T* x,
                 copyrow(zm, c);
                 copyrow(c, zp);
                 copyrow(zp, zpp);
+                hc = hp;
+                hp = hpp;
                 copyrow(ym, ymn);
                 copyrow(yp, ypn);
                 copyrow(bb, bn);
@@ -233,25 +251,42 @@ __device__ __forceinline__ void outer_partials(double* partials, double sb, doub
     }
 }
 
-template <typename TA, typename TR, typename TE, int VEC, bool UPDATE>
+// The potential (phi, or phi + e) at one element as TA: the x-halo of a split row.
+template <typename TA, typename TE, bool UPDATE>
+__device__ __forceinline__ TA ld_value1(const double* phi, const TE* e, size_t i) {
+    if constexpr (UPDATE) return (TA)(phi[i] + (double)e[i]);
+    return (TA)phi[i];
+}
+
+// S > 1: rows split into S segments, one per wave, as in k_smooth_row.
+template <typename TA, typename TR, typename TE, int VEC, bool UPDATE, int S = 1>
 __global__ __launch_bounds__(kBlock) void k_outer_row(int n, TA ih2, const double* __restrict__ phi_in,
                                                       const TE* __restrict__ e, double* __restrict__ phi_out,
                                                       const double* __restrict__ b, double bmean,
                                                       TR* __restrict__ r, TR* __restrict__ x1, TA cd0,
                                                       double* __restrict__ partials, int nz, int nyb) {
+    static_assert(kWaves % S == 0, "a block holds whole rows");
     __shared__ double sh[3 * kWaves];
-    const RowGrid g{64 * VEC, 64 * VEC - 1};
+    constexpr int NR = 64 * VEC;
+    const RowGrid g{NR * S, NR * S - 1};
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int yb = lb % nyb, zc = lb / nyb;
     const int wave = wave_id();
-    const int y = yb * kWaves + wave;
+    const int y = yb * (kWaves / S) + wave / S, seg = wave % S;
     const int z0 = zc * nz;
-    const size_t off = (size_t)(threadIdx.x & 63) * VEC;
+    const int lane = threadIdx.x & 63;
+    const size_t off = (size_t)seg * NR + (size_t)lane * VEC;
+    const int hoff = S > 1 ? seg_halo<VEC, S>(seg, lane) : 0;
     TA zm[VEC], c[VEC], zp[VEC], ym[VEC], yp[VEC];
+    TA hc = TA(0), hp = TA(0);  // x-halo of c and zp (S > 1)
     double bb[VEC];
     ld_value<TA, TR, TE, VEC, UPDATE>(zm, phi_in, e, g.row(y, z0 - 1) + off);
     ld_value<TA, TR, TE, VEC, UPDATE>(c, phi_in, e, g.row(y, z0) + off);
     ld_value<TA, TR, TE, VEC, UPDATE>(zp, phi_in, e, g.row(y, z0 + 1) + off);
+    if constexpr (S > 1) {
+        hc = ld_value1<TA, TE, UPDATE>(phi_in, e, g.row(y, z0) + hoff);
+        hp = ld_value1<TA, TE, UPDATE>(phi_in, e, g.row(y, z0 + 1) + hoff);
+    }
     ld_value<TA, TR, TE, VEC, UPDATE>(ym, phi_in, e, g.row(y - 1, z0) + off);
     ld_value<TA, TR, TE, VEC, UPDATE>(yp, phi_in, e, g.row(y + 1, z0) + off);
     ldrow<double, VEC>(bb, b + g.row(y, z0) + off);
@@ -259,17 +294,19 @@ __global__ __launch_bounds__(kBlock) void k_outer_row(int n, TA ih2, const doubl
     for (int k = 0; k < nz; ++k) {
         const int z = z0 + k;
         TA zpp[VEC], ymn[VEC], ypn[VEC];
+        TA hpp = TA(0);
         double bn[VEC];
         const bool more = k + 1 < nz;
         if (more) {
             ld_value<TA, TR, TE, VEC, UPDATE>(zpp, phi_in, e, g.row(y, z + 2) + off);
+            if constexpr (S > 1) hpp = ld_value1<TA, TE, UPDATE>(phi_in, e, g.row(y, z + 2) + hoff);
             ld_value<TA, TR, TE, VEC, UPDATE>(ymn, phi_in, e, g.row(y - 1, z + 1) + off);
             ld_value<TA, TR, TE, VEC, UPDATE>(ypn, phi_in, e, g.row(y + 1, z + 1) + off);
             ldrow<double, VEC>(bn, b + g.row(y, z + 1) + off);
         }
         TA Mx[VEC];
         TR ro[VEC];
-        flat7_row<TA, VEC>(c, ym, yp, zm, zp, ih2, Mx);
+        flat7_row_seg<TA, VEC, S>(c, ym, yp, zm, zp, ih2, Mx, hc);
 #pragma unroll
         for (int q = 0; q < VEC; ++q) {
             const double bq = bb[q] - bmean;
@@ -315,6 +352,8 @@ __global__ __launch_bounds__(kBlock) void k_outer_row(int n, TA ih2, const doubl
             copyrow(zm, c);
             copyrow(c, zp);
             copyrow(zp, zpp);
+            hc = hp;
+            hp = hpp;
             copyrow(ym, ymn);
             copyrow(yp, ypn);
             copyrow(bb, bn);
@@ -589,6 +628,139 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
         for (int j = 0; j < NZC + 2; ++j, ++z1) plane(j);
     } else {
         for (int j = 0; j < steps; ++j, ++z1) plane(j);
+    }
+}
+
+// The same two steps with the x plane (FROMB: the b plane) shared through LDS
+// as well: every wave loads only its own row of x (b, x_prev) and publishes
+// it one plane ahead of its use, so the first step's y-neighbours (and, for
+// split rows, its x-halo) come from LDS instead of the caches; only the two
+// edge rows of the block load their outer neighbour row.  One barrier per
+// plane for both planes; same arithmetic and bits as k_smooth2_lds.
+template <typename T, int VEC, int NW, bool PREV1, bool Y1OUT, bool FROMB, int NZC, int S>
+__global__ __launch_bounds__(64 * NW) void k_smooth2x_lds(int n, T ih2, const T* __restrict__ x,
+                                                          const T* __restrict__ xp, const T* __restrict__ b,
+                                                          T* __restrict__ y2, T* __restrict__ y1o, T a1, T cd1,
+                                                          T a2, T cd2, int nyb, T cd0, SumsJob job) {
+    static_assert(!(FROMB && PREV1), "a pass from zero has no x_prev");
+    static_assert(VEC * sizeof(T) <= 16, "plain LDS row layout");
+    static_assert(NW % S == 0 && NW / S >= 3, "a block holds whole rows, at least one output row");
+    constexpr int NR = 64 * VEC;
+    constexpr int R = NW / S;  // rows of the block
+    constexpr int W = R - 2;   // output rows
+    __shared__ T xs[2][NW][NR];    // x (FROMB: b) rows of a plane, one plane ahead
+    __shared__ T rows[2][NW][NR];  // first-step rows of a plane
+    const RowGrid g{NR * S, NR * S - 1};
+    int nb = gridDim.x, bid = blockIdx.x;
+    if constexpr (FROMB) {
+        if (job.count > 0) {  // block 0 finishes the sums, dispatched first
+            nb -= 1;
+            bid -= 1;
+            if (bid < 0) {
+                __shared__ double sh[kSumLanes];
+                finish_sums(job, sh);
+                return;
+            }
+        }
+    }
+    const int lb = xcd_logical(bid, nb);
+    const int yb = lb % nyb, zc = lb / nyb;
+    const int w = wave_id();
+    const int wr = w / S, seg = w - wr * S;
+    const int lane = threadIdx.x & 63;
+    const int y = yb * W - 1 + wr;  // rows outside [0, n) wrap for loads
+    const bool outw = wr >= 1 && wr <= W && y < n;
+    const bool lo = wr == 0, hi = wr == R - 1;
+    const int yo = lo ? y - 1 : y + 1;  // outer neighbour row of an edge row
+    const int z0 = zc * NZC;
+    const size_t off = (size_t)seg * NR + (size_t)lane * VEC;
+    const int wprev = wr * S + (seg + S - 1) % S, wnext = wr * S + (seg + 1) % S;
+    const T* src = FROMB ? b : x;
+    int z1 = z0 - 1;
+    // first step at z1: this row at z1-1, z1, z1+1, the outer row (edges) at z1, b and xp at z1
+    T xm[VEC], xc[VEC], xq[VEC], o1[VEC] = {}, b1[VEC], p1[VEC];
+    // second step at z2 = z1 - 1: first-step rows at z2-1, z2; b at z2; x_prev = xm
+    T sm[VEC] = {}, sc[VEC] = {}, b2[VEC] = {};
+    ldrow<T, VEC>(xm, src + g.row(y, z1 - 1) + off);
+    ldrow<T, VEC>(xc, src + g.row(y, z1) + off);
+    ldrow<T, VEC>(xq, src + g.row(y, z1 + 1) + off);
+    if (lo || hi) ldrow<T, VEC>(o1, src + g.row(yo, z1) + off);
+    if constexpr (!FROMB) ldrow<T, VEC>(b1, b + g.row(y, z1) + off);
+    if constexpr (PREV1) ldrow<T, VEC>(p1, xp + g.row(y, z1) + off);
+    lds_strow<T, VEC>(xs[0][w], lane, xc);
+    __syncthreads();
+    constexpr int steps = NZC + 2;
+#pragma unroll
+    for (int j = 0; j < steps; ++j, ++z1) {
+        const bool more = j + 1 < steps;
+        const int cb = j & 1;
+        T xn[VEC], bn[VEC], pn[VEC], on[VEC];
+        if (more) {
+            ldrow<T, VEC>(xn, src + g.row(y, z1 + 2) + off);
+            if (lo || hi) ldrow<T, VEC>(on, src + g.row(yo, z1 + 1) + off);
+            if constexpr (!FROMB) ldrow<T, VEC>(bn, b + g.row(y, z1 + 1) + off);
+            if constexpr (PREV1) ldrow<T, VEC>(pn, xp + g.row(y, z1 + 1) + off);
+        }
+        // first step at z1
+        T ym[VEC], yp[VEC], M1[VEC], sp[VEC];
+        if (lo) copyrow(ym, o1);
+        else lds_ldrow<T, VEC>(ym, xs[cb][w - S], lane);
+        if (hi) copyrow(yp, o1);
+        else lds_ldrow<T, VEC>(yp, xs[cb][w + S], lane);
+        T hx = T(0);
+        if constexpr (S > 1) hx = lane < 32 ? xs[cb][wprev][NR - 1] : xs[cb][wnext][0];
+        if constexpr (FROMB) {
+            T fc[VEC], fm[VEC], fq[VEC], fym[VEC], fyp[VEC];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                fc[e] = first_step<T, FROMB>(xc[e], cd0);
+                fm[e] = first_step<T, FROMB>(xm[e], cd0);
+                fq[e] = first_step<T, FROMB>(xq[e], cd0);
+                fym[e] = first_step<T, FROMB>(ym[e], cd0);
+                fyp[e] = first_step<T, FROMB>(yp[e], cd0);
+            }
+            flat7_row_seg<T, VEC, S>(fc, fym, fyp, fm, fq, ih2, M1, first_step<T, FROMB>(hx, cd0));
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) sp[e] = cheb_step<T>(fc[e], T(0), xc[e], M1[e], a1, cd1);
+        } else {
+            flat7_row_seg<T, VEC, S>(xc, ym, yp, xm, xq, ih2, M1, hx);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) sp[e] = cheb_step<T>(xc[e], PREV1 ? p1[e] : T(0), b1[e], M1[e], a1, cd1);
+        }
+        if constexpr (Y1OUT) {
+            if (outw && j >= 1 && j <= NZC) strow<T, VEC>(y1o + g.row(y, z1) + off, sp);
+        }
+        // publish x at z1+1 (used by the next plane's first step) and the first step at z1-1
+        if (more) lds_strow<T, VEC>(xs[cb ^ 1][w], lane, xq);
+        if (j >= 2) lds_strow<T, VEC>(rows[cb][w], lane, sc);
+        __syncthreads();
+        if (j >= 2 && outw) {  // second step at z1-1
+            T nm[VEC], np[VEC], M2[VEC], o[VEC];
+            lds_ldrow<T, VEC>(nm, rows[cb][w - S], lane);
+            lds_ldrow<T, VEC>(np, rows[cb][w + S], lane);
+            T hs = T(0);
+            if constexpr (S > 1) hs = lane < 32 ? rows[cb][wprev][NR - 1] : rows[cb][wnext][0];
+            flat7_row_seg<T, VEC, S>(sc, nm, np, sm, sp, ih2, M2, hs);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                if constexpr (FROMB)  // x_prev = first step at z2, b at z2 = the raw queue row
+                    o[e] = cheb_step<T>(sc[e], first_step<T, FROMB>(xm[e], cd0), xm[e], M2[e], a2, cd2);
+                else
+                    o[e] = cheb_step<T>(sc[e], xm[e], b2[e], M2[e], a2, cd2);
+            }
+            strow<T, VEC>(y2 + g.row(y, z1 - 1) + off, o);
+        }
+        copyrow(sm, sc);
+        copyrow(sc, sp);
+        if constexpr (!FROMB) copyrow(b2, b1);
+        if (more) {
+            copyrow(xm, xc);
+            copyrow(xc, xq);
+            copyrow(xq, xn);
+            if (lo || hi) copyrow(o1, on);
+            if constexpr (!FROMB) copyrow(b1, bn);
+            if constexpr (PREV1) copyrow(p1, pn);
+        }
     }
 }
 
@@ -1181,15 +1353,33 @@ void outer_lds_shape(int n, int waves, int& nz, int& nyb, int& blocks) {
 
 // The outer residual runs in double (TA) for MG_FP64/MG_MIXED and float for
 // MG_FP32; the block count must match what launch_outer_row uses.
+// Segments per row of the kernels that keep their rows in registers without
+// LDS (single step, outer residual): rows of more than 2 KB are split so that
+// a lane holds at most 32 bytes (1024^3 double: 4 segments of 2 KB; a lane of
+// an unsplit 8 KB row held 128 bytes, and these kernels ran one wave per SIMD).
+constexpr size_t kRowSegBytes = 2048;
+inline int row_segments(int n, size_t elem) {
+    const size_t row = (size_t)n * elem;
+    return row > kRowSegBytes ? (int)(row / kRowSegBytes) : 1;
+}
+
 int row_outer_blocks(int n, bool double_arith) {
     int nz, nyb, blocks;
     if (double_arith ? lds_rows_fit<double>(n) : lds_rows_fit<float>(n)) {
         outer_lds_shape(n, kLdsWaves, nz, nyb, blocks);
         return blocks;
     }
-    shape(n, n, 16, nz, nyb, blocks, 1024);
+    shape(n * row_segments(n, double_arith ? sizeof(double) : sizeof(float)), n, 16, nz, nyb, blocks, 1024);
     return blocks;
 }
+
+// Row kernel with S segments per row: VEC = n / (64 S) elements per lane.
+#define DISPATCH_SEG(n, S, ...)                                                \
+    switch ((n) / (64 * (S))) {                                                \
+        case 4: { constexpr int VEC = 4; __VA_ARGS__; break; }                 \
+        case 8: { constexpr int VEC = 8; __VA_ARGS__; break; }                 \
+        default: return hipErrorInvalidValue;                                  \
+    }
 
 #define DISPATCH_VEC(n, ...)                                  \
     switch (n) {                                              \
@@ -1224,6 +1414,26 @@ hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, cons
                                        (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb);
             }
         })
+        return hipGetLastError();
+    }
+    const int S = x != nullptr ? row_segments(n, sizeof(T)) : 1;
+    if (S > 1) {
+        shape(n * S, n, 4, nz, nyb, blocks);
+#define MG_SMOOTH_SEG(SS)                                                                                            \
+    DISPATCH_SEG(n, SS, {                                                                                            \
+        if (xprev == nullptr)                                                                                        \
+            MG_LAUNCH((k_smooth_row<T, VEC, true, false, SS>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (T)ih2, x, \
+                      xprev, b, out, (T)a, (T)cd, nz, nyb);                                                           \
+        else                                                                                                         \
+            MG_LAUNCH((k_smooth_row<T, VEC, true, true, SS>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (T)ih2, x,  \
+                      xprev, b, out, (T)a, (T)cd, nz, nyb);                                                           \
+    })
+        switch (S) {
+            case 2: MG_SMOOTH_SEG(2); break;
+            case 4: MG_SMOOTH_SEG(4); break;
+            default: return hipErrorInvalidValue;
+        }
+#undef MG_SMOOTH_SEG
         return hipGetLastError();
     }
     shape(n, n, 4, nz, nyb, blocks);
@@ -1322,15 +1532,29 @@ hipError_t launch_pair_nw(int n, double ih2, const T* x, const T* xp, const T* b
 // lane then holds 16 bytes of a row, and the register budget of 16-wave
 // blocks holds the fully unrolled variants.
 constexpr size_t kPairSegBytes = 1024;
+constexpr int kPairSegWaves = 16;       // block of the split two-step kernels
+constexpr int kPairSegNz = kPairUnrollNz;  // their (fully unrolled) chunk height
+// x plane of the split two-step kernels shared through LDS (k_smooth2x_lds):
+// 512^3 float pairs 4.07 -> 4.45 TB/s, 256^3 double 3.74 -> 3.98 TB/s, same
+// bits.  Unsplit 1 KB rows keep k_smooth2_lds: the 256^3 float pass from zero
+// measured 37.9 us there against 40.6 us in this kernel and block shape.
+constexpr bool kPairXLds = true;
 inline int pair_segments(int n, size_t elem) {
     const size_t row = (size_t)n * elem;
     return row > kPairSegBytes ? (int)(row / kPairSegBytes) : 1;
 }
 
 #define MG_PAIRS(PREV1, Y1OUT, FROMB, PF2)                                                                         \
-    MG_LAUNCH((k_smooth2_lds<T, VEC, NW, PREV1, Y1OUT, FROMB, PF2, kPairUnrollNz, S>),                          \
-              dim3(blocks + (FROMB ? extra : 0)), dim3(64 * NW), s, ev0, ev1, n, (T)ih2, x, xp, b, y2, y1, (T)a1, \
-              (T)cd1, (T)a2, (T)cd2, kPairUnrollNz, nyb, (T)cd0, FROMB ? sums : SumsJob{})
+    do {                                                                                                         \
+        if constexpr (kPairXLds)                                                                                 \
+            MG_LAUNCH((k_smooth2x_lds<T, VEC, NW, PREV1, Y1OUT, FROMB, kPairSegNz, S>),                          \
+                      dim3(blocks + (FROMB ? extra : 0)), dim3(64 * NW), s, ev0, ev1, n, (T)ih2, x, xp, b, y2, y1, \
+                      (T)a1, (T)cd1, (T)a2, (T)cd2, nyb, (T)cd0, FROMB ? sums : SumsJob{});                      \
+        else                                                                                                     \
+            MG_LAUNCH((k_smooth2_lds<T, VEC, NW, PREV1, Y1OUT, FROMB, PF2, kPairSegNz, S>),                      \
+                      dim3(blocks + (FROMB ? extra : 0)), dim3(64 * NW), s, ev0, ev1, n, (T)ih2, x, xp, b, y2, y1, \
+                      (T)a1, (T)cd1, (T)a2, (T)cd2, kPairSegNz, nyb, (T)cd0, FROMB ? sums : SumsJob{});          \
+    } while (0)
 template <typename T, int NW, int S>
 hipError_t launch_pair_seg(int n, double ih2, const T* x, const T* xp, const T* b, T* y2, T* y1, double a1,
                            double cd1, double a2, double cd2, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
@@ -1338,8 +1562,8 @@ hipError_t launch_pair_seg(int n, double ih2, const T* x, const T* xp, const T* 
     constexpr int W = NW / S - 2;
     const int extra = sums.count > 0 ? 1 : 0;  // the block that finishes the sums (pass from zero only)
     const int nyb = (n + W - 1) / W;
-    if (n % kPairUnrollNz != 0) return hipErrorInvalidValue;
-    const int blocks = nyb * (n / kPairUnrollNz);
+    if (n % kPairSegNz != 0) return hipErrorInvalidValue;
+    const int blocks = nyb * (n / kPairSegNz);
     const int vec = n / (64 * S);
     auto go = [&](auto vtag) -> hipError_t {
         constexpr int VEC = decltype(vtag)::value;
@@ -1380,8 +1604,8 @@ hipError_t launch_smooth_pair_row(int n, double ih2, const T* x, const T* xp, co
     switch (pair_segments(n, sizeof(T))) {
         case 1: break;
         case 2:
-            return launch_pair_seg<T, 16, 2>(n, ih2, x, xp, b, y2, y1, a1, cd1, a2, cd2, s, ev0, ev1, x0_mode, cd0,
-                                             sums);
+            return launch_pair_seg<T, kPairSegWaves, 2>(n, ih2, x, xp, b, y2, y1, a1, cd1, a2, cd2, s, ev0, ev1,
+                                                        x0_mode, cd0, sums);
         default: return hipErrorInvalidValue;
     }
     int waves = kPairWavesDefault;
@@ -1517,6 +1741,26 @@ hipError_t launch_outer_row(int n, double ih2, const double* phi_in, const TE* e
     })
         MG_OUTER_LDS(kLdsWaves)
 #undef MG_OUTER_LDS
+        return hipGetLastError();
+    }
+    const int S = row_segments(n, sizeof(TA));
+    if (S > 1) {
+        shape(n * S, n, 16, nz, nyb, blocks, 1024);
+#define MG_OUTER_SEG(SS)                                                                                              \
+    DISPATCH_SEG(n, SS, {                                                                                             \
+        if (e)                                                                                                        \
+            MG_LAUNCH((k_outer_row<TA, TR, TE, VEC, true, SS>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (TA)ih2, \
+                      phi_in, e, phi_out, b, bmean, r, x1, (TA)cd0, partials, nz, nyb);                              \
+        else                                                                                                          \
+            MG_LAUNCH((k_outer_row<TA, TR, TE, VEC, false, SS>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (TA)ih2, \
+                      phi_in, e, phi_out, b, bmean, r, x1, (TA)cd0, partials, nz, nyb);                               \
+    })
+        switch (S) {
+            case 2: MG_OUTER_SEG(2); break;
+            case 4: MG_OUTER_SEG(4); break;
+            default: return hipErrorInvalidValue;
+        }
+#undef MG_OUTER_SEG
         return hipGetLastError();
     }
     shape(n, n, 16, nz, nyb, blocks, 1024);
