@@ -1181,27 +1181,40 @@ __global__ __launch_bounds__(64 * W) void k_outer_lds(int n, TA ih2, const doubl
 // fine planes; fine rows 2Y-1, 2Y, 2Y+1 are formed, combined in y, then in x
 // across lanes, then accumulated in z, each with fw3's rounding.
 // =====================================================================================
-template <typename T, int VEC>
+// S > 1: each coarse row's fine rows split into S segments of 64 VEC
+// elements, one wave each (a block of kWaves waves holds kWaves / S coarse
+// rows).  The stencil's x-neighbours across segment ends come from halo
+// elements loaded with each row, and the full weighting in x of a segment's
+// first coarse point takes the previous segment's last fine value from LDS.
+template <typename T, int VEC, int S = 1>
 __global__ __launch_bounds__(kBlock) void k_rr_row(int n, T ih2, const T* __restrict__ x,
                                                    const T* __restrict__ b, T* __restrict__ coarse, int nzc,
                                                    int nyb) {
 #pragma clang fp contract(off)  // full weighting in y, then x, then z, as fw3 rounds it
+    static_assert(S == 1 || VEC >= 2, "split rows hold at least two fine points per lane");
+    static_assert(kWaves % S == 0, "a block holds whole rows");
     constexpr int CV = VEC >= 2 ? VEC / 2 : 1;
-    constexpr int nc = 32 * VEC;
-    const RowGrid g{64 * VEC, 64 * VEC - 1};
+    constexpr int NR = 64 * VEC;
+    constexpr int nc = NR * S / 2;
+    const RowGrid g{NR * S, NR * S - 1};
     const RowGrid gc{nc, nc - 1};
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int yb = lb % nyb, zc = lb / nyb;
     const int lane = threadIdx.x & 63;
-    const int Y = yb * kWaves + wave_id();
+    const int w = wave_id();
+    const int Y = yb * (kWaves / S) + w / S, seg = w % S;
+    const int wprev = (w / S) * S + (seg + S - 1) % S;
     const int Z0 = zc * nzc;
     const int y1 = 2 * Y;
-    const size_t off = (size_t)lane * VEC;
+    const size_t off = (size_t)seg * NR + (size_t)lane * VEC;
+    const int hoff = S > 1 ? seg_halo<VEC, S>(seg, lane) : 0;
+    __shared__ T edge[2][kWaves];  // last fine value of each segment (S > 1)
     // x rows 2Y-2 .. 2Y+2 at plane z (index 0..4) and rows 2Y-1..2Y+1 at z-1, z+1
     T c0[VEC], c1[VEC], c2[VEC];     // rows 2Y-1, 2Y, 2Y+1 at plane z
     T m0[VEC], m1[VEC], m2[VEC];     // same rows at z-1
     T p0[VEC], p1[VEC], p2[VEC];     // same rows at z+1
     T hm[VEC], hp[VEC];              // rows 2Y-2, 2Y+2 at plane z
+    T h0 = T(0), h1 = T(0), h2 = T(0);  // x-halo of c0, c1, c2 (S > 1)
     int z = 2 * Z0 - 1;
     ldrow<T, VEC>(m0, x + g.row(y1 - 1, z - 1) + off);
     ldrow<T, VEC>(m1, x + g.row(y1, z - 1) + off);
@@ -1209,12 +1222,23 @@ __global__ __launch_bounds__(kBlock) void k_rr_row(int n, T ih2, const T* __rest
     ldrow<T, VEC>(c0, x + g.row(y1 - 1, z) + off);
     ldrow<T, VEC>(c1, x + g.row(y1, z) + off);
     ldrow<T, VEC>(c2, x + g.row(y1 + 1, z) + off);
+    if constexpr (S > 1) {
+        h0 = x[g.row(y1 - 1, z) + hoff];
+        h1 = x[g.row(y1, z) + hoff];
+        h2 = x[g.row(y1 + 1, z) + hoff];
+    }
     T acc[CV];
     const int nf = 2 * nzc + 1;
     for (int k = 0; k < nf; ++k, ++z) {
         ldrow<T, VEC>(p0, x + g.row(y1 - 1, z + 1) + off);
         ldrow<T, VEC>(p1, x + g.row(y1, z + 1) + off);
         ldrow<T, VEC>(p2, x + g.row(y1 + 1, z + 1) + off);
+        T q0 = T(0), q1 = T(0), q2 = T(0);
+        if constexpr (S > 1) {
+            q0 = x[g.row(y1 - 1, z + 1) + hoff];
+            q1 = x[g.row(y1, z + 1) + hoff];
+            q2 = x[g.row(y1 + 1, z + 1) + hoff];
+        }
         ldrow<T, VEC>(hm, x + g.row(y1 - 2, z) + off);
         ldrow<T, VEC>(hp, x + g.row(y1 + 2, z) + off);
         T b0[VEC], b1[VEC], b2[VEC];
@@ -1222,16 +1246,21 @@ __global__ __launch_bounds__(kBlock) void k_rr_row(int n, T ih2, const T* __rest
         ldrow<T, VEC>(b1, b + g.row(y1, z) + off);
         ldrow<T, VEC>(b2, b + g.row(y1 + 1, z) + off);
         T M0[VEC], M1[VEC], M2[VEC], s[VEC];
-        flat7_row<T, VEC>(c0, hm, c1, m0, p0, ih2, M0);
-        flat7_row<T, VEC>(c1, c0, c2, m1, p1, ih2, M1);
-        flat7_row<T, VEC>(c2, c1, hp, m2, p2, ih2, M2);
+        flat7_row_seg<T, VEC, S>(c0, hm, c1, m0, p0, ih2, M0, h0);
+        flat7_row_seg<T, VEC, S>(c1, c0, c2, m1, p1, ih2, M1, h1);
+        flat7_row_seg<T, VEC, S>(c2, c1, hp, m2, p2, ih2, M2, h2);
 #pragma unroll
         for (int e = 0; e < VEC; ++e)
             s[e] = fw3<T>(b0[e] - M0[e], b1[e] - M1[e], b2[e] - M2[e]);
         // x: coarse element q <-> fine 2q; needs fine 2q-1 (previous lane's last for q = 0)
         T sx[CV];
         if constexpr (VEC >= 2) {
-            const T lft = lane_rot(s[VEC - 1], -1);
+            T lft = lane_rot(s[VEC - 1], -1);
+            if constexpr (S > 1) {  // lane 0: the previous segment's last fine value
+                if (lane == 63) edge[k & 1][w] = s[VEC - 1];
+                __syncthreads();
+                if (lane == 0) lft = edge[k & 1][wprev];
+            }
 #pragma unroll
             for (int q = 0; q < CV; ++q) {
                 const T l = q > 0 ? s[2 * q - 1] : lft;
@@ -1254,7 +1283,7 @@ __global__ __launch_bounds__(kBlock) void k_rr_row(int n, T ih2, const T* __rest
 #pragma unroll
             for (int q = 0; q < CV; ++q) acc[q] += T(0.25) * sx[q];
             if constexpr (VEC >= 2) {
-                strow<T, CV>(coarse + gc.row(Y, Z) + (size_t)lane * CV, acc);
+                strow<T, CV>(coarse + gc.row(Y, Z) + (size_t)seg * (NR / 2) + (size_t)lane * CV, acc);
             } else {
                 if ((lane & 1) == 0) coarse[gc.row(Y, Z) + (lane >> 1)] = acc[0];
             }
@@ -1267,6 +1296,9 @@ __global__ __launch_bounds__(kBlock) void k_rr_row(int n, T ih2, const T* __rest
         copyrow(c0, p0);
         copyrow(c1, p1);
         copyrow(c2, p2);
+        h0 = q0;
+        h1 = q1;
+        h2 = q2;
     }
 }
 
@@ -1782,7 +1814,18 @@ hipError_t launch_rr_row(int n, double ih2, const T* x, const T* b, T* coarse, h
     int nzc, nyb, blocks;
     // small levels are latency chains: chunks of 2 coarse planes (128^3: 7.7 -> 5.7 us,
     // 64^3: 6.8 -> 4.8 us per launch)
-    shape(nc, nc, n <= 128 ? 2 : 4, nzc, nyb, blocks, n >= 256 ? kRrTarget : 1024);
+    const int S = row_segments(n, sizeof(T));
+    shape(nc * S, nc, n <= 128 ? 2 : 4, nzc, nyb, blocks, n >= 256 ? kRrTarget : 1024);
+    if (S > 1) {
+        switch (S) {
+            case 2: DISPATCH_SEG(n, 2, { MG_LAUNCH((k_rr_row<T, VEC, 2>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n,
+                                                   (T)ih2, x, b, coarse, nzc, nyb); }) break;
+            case 4: DISPATCH_SEG(n, 4, { MG_LAUNCH((k_rr_row<T, VEC, 4>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n,
+                                                   (T)ih2, x, b, coarse, nzc, nyb); }) break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     DISPATCH_VEC(n, {
         MG_LAUNCH((k_rr_row<T, VEC>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (T)ih2, x, b, coarse, nzc, nyb);
     })

@@ -16,6 +16,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 namespace mg {
 namespace {
@@ -364,49 +365,61 @@ __global__ __launch_bounds__(kThreads) void k_coeff_check(int n, const TC* __res
 // =====================================================================================
 // Separable exact solve of the seven-point system: three 1-D basis changes,
 // division by the eigenvalue, three inverse basis changes, all in double in LDS.
-template <typename T>
-__global__ __launch_bounds__(1024) void k_coarse_flat(int nc, const double* __restrict__ Q,
-                                                      const double* __restrict__ lam1, const T* __restrict__ r,
-                                                      T* __restrict__ e) {
-    __shared__ double A[4096];
-    __shared__ double B[4096];
-    __shared__ double q[256];
-    __shared__ double lam[16];
+// The level size NC is a compile-time constant (4, 8 or 16), so the point
+// loops and the basis sums unroll and the index arithmetic is shifts and
+// masks (with a run-time size the 16^3 solve took 53 us per launch).
+template <typename T, int NC>
+__global__ __launch_bounds__(1024) void k_coarse_flat(const double* __restrict__ Q, const double* __restrict__ lam1,
+                                                      const T* __restrict__ r, T* __restrict__ e) {
+    constexpr int N = NC * NC * NC;
+    __shared__ double A[N];
+    __shared__ double B[N];
+    __shared__ double q[NC * NC];
+    __shared__ double lam[NC];
     const int tid = threadIdx.x;
-    const int N = nc * nc * nc;
-    for (int i = tid; i < nc * nc; i += blockDim.x) q[i] = Q[i];
-    for (int i = tid; i < nc; i += blockDim.x) lam[i] = lam1[i];
-    for (int i = tid; i < N; i += blockDim.x) A[i] = (double)r[i];
+    for (int i = tid; i < NC * NC; i += 1024) q[i] = Q[i];
+    if (tid < NC) lam[tid] = lam1[tid];
+    for (int i = tid; i < N; i += 1024) A[i] = (double)r[i];
     __syncthreads();
-    // q[j + nc*k] = basis vector k at point j.  Forward: c_k = sum_j q[j,k] v_j.
-    auto pass = [&](const double* src, double* dst, int axis, bool forward) {
-        for (int i = tid; i < N; i += blockDim.x) {
-            const int x = i % nc, y = (i / nc) % nc, z = i / (nc * nc);
-            const int k = axis == 0 ? x : axis == 1 ? y : z;
-            const int stride = axis == 0 ? 1 : axis == 1 ? nc : nc * nc;
+    // q[j + NC*k] = basis vector k at point j.  Forward: c_k = sum_j q[j,k] v_j.
+    auto pass = [&](const double* src, double* dst, auto axis_tag, auto fwd_tag) {
+        constexpr int axis = decltype(axis_tag)::value;
+        constexpr bool forward = decltype(fwd_tag)::value;
+        constexpr int stride = axis == 0 ? 1 : axis == 1 ? NC : NC * NC;
+#pragma unroll
+        for (int i0 = 0; i0 < N; i0 += 1024) {
+            const int i = i0 + tid;
+            if (N % 1024 != 0 && i >= N) break;
+            const int k = (i / stride) & (NC - 1);
             const int base = i - k * stride;
             double acc = 0.0;
-            for (int j = 0; j < nc; ++j) {
-                const double w = forward ? q[j + nc * k] : q[k + nc * j];
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+                const double w = forward ? q[j + NC * k] : q[k + NC * j];
                 acc += w * src[base + j * stride];
             }
             dst[i] = acc;
         }
         __syncthreads();
     };
-    pass(A, B, 0, true);
-    pass(B, A, 1, true);
-    pass(A, B, 2, true);
-    for (int i = tid; i < N; i += blockDim.x) {
-        const int x = i % nc, y = (i / nc) % nc, z = i / (nc * nc);
+    using X = std::integral_constant<int, 0>;
+    using Y = std::integral_constant<int, 1>;
+    using Z = std::integral_constant<int, 2>;
+    using F = std::true_type;
+    using I = std::false_type;
+    pass(A, B, X{}, F{});
+    pass(B, A, Y{}, F{});
+    pass(A, B, Z{}, F{});
+    for (int i = tid; i < N; i += 1024) {
+        const int x = i & (NC - 1), y = (i / NC) & (NC - 1), z = i / (NC * NC);
         const double l = lam[x] + lam[y] + lam[z];
         B[i] = (x == 0 && y == 0 && z == 0) ? 0.0 : B[i] / l;
     }
     __syncthreads();
-    pass(B, A, 2, false);
-    pass(A, B, 1, false);
-    pass(B, A, 0, false);
-    for (int i = tid; i < N; i += blockDim.x) e[i] = (T)A[i];
+    pass(B, A, Z{}, I{});
+    pass(A, B, Y{}, I{});
+    pass(B, A, X{}, I{});
+    for (int i = tid; i < N; i += 1024) e[i] = (T)A[i];
 }
 
 // e = G r, 8 rows per block, 32 lanes per row, fixed-order sums.
@@ -750,8 +763,12 @@ hipError_t launch_coeff_check(int n, const TC* coeff, double* partials, hipStrea
 
 template <typename T>
 hipError_t launch_coarse_flat(int nc, const double* Q, const double* lam1, const T* r, T* e, hipStream_t s) {
-    if (nc > 16) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_coarse_flat<T>), dim3(1), dim3(1024), 0, s, nc, Q, lam1, r, e);
+    switch (nc) {
+        case 4: hipLaunchKernelGGL((k_coarse_flat<T, 4>), dim3(1), dim3(1024), 0, s, Q, lam1, r, e); break;
+        case 8: hipLaunchKernelGGL((k_coarse_flat<T, 8>), dim3(1), dim3(1024), 0, s, Q, lam1, r, e); break;
+        case 16: hipLaunchKernelGGL((k_coarse_flat<T, 16>), dim3(1), dim3(1024), 0, s, Q, lam1, r, e); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 template <typename T>

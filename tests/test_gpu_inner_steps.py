@@ -283,6 +283,14 @@ def test_smoothing_1024_windows(mgpu, precision):
             print(f"1024^3 {precision} {step} window {starts[k]}: {err:.2e}", flush=True)
             assert err <= bar(precision), (step, starts[k], err)
         del out
+    # residual + restriction (rows split over waves in both precisions at this size)
+    out = mg.inner_step("residual_restrict", 0, x=xd, b=bd)
+    for k, l in enumerate(lo):
+        rc = O.restrict_fw(bw[k] - O.apply_flat(xw[k], 1.0 / n))
+        got = win_t(out, tuple((s + 2 * halo) // 2 for s in l), size // 2)
+        err = maxrel(got, rc[(slice(halo, halo + size // 2),) * 3])
+        print(f"1024^3 {precision} residual_restrict window {starts[k]}: {err:.2e}", flush=True)
+        assert err <= bar(precision), ("residual_restrict", starts[k], err)
 
 
 def win_t(t, start, size):
