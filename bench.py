@@ -71,13 +71,17 @@ def measured_traffic(n, degree, kernel):
 
 def pass_bytes(v, from_zero, pairs, triple, s):
     """Algorithmic bytes per point of one smoothing pass of degree v, following
-    the library's schedule: a pass from zero starts with one kernel for its
+    the library's schedule: a pass from zero of degree 4 is one kernel for
+    steps 0 and 1 (b -> x2) and a pair that forms x_prev = x1 from b
+    (x2, b -> x4); other passes from zero start with one kernel for their
     first three steps (b -> x3, and x2 when a fourth step needs it as x_prev);
     a pass of three steps from a nonzero iterate is one three-step kernel
     (x, b -> x3); otherwise steps pair up from the end of the pass where the
     two-step kernel runs (a pair that is not the last writes its first step)."""
     if not from_zero and triple and v == 3:
         return 3 * s
+    if from_zero and pairs and v == 4:
+        return (2 + 3) * s
     tot, prev, k = 0.0, False, 0
     if from_zero and pairs and v >= 3:
         tot += (2 + (v > 3)) * s

@@ -15,12 +15,22 @@ int row_outer_blocks(int n, bool double_arith);
 template <typename T>
 hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, const T* b, T* out, double a,
                              double cd, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// Step 1 of a pass from zero read from b alone: out = x1 + a1 x1 + cd1 (b - M x1)
+// with x1 = cd0 * b formed on the fly in T (the bits of a single step from
+// zero followed by a single step).  Rows of at most 2 KB; out must differ from b.
+template <typename T>
+hipError_t launch_smooth_fromb_row(int n, double ih2, const T* b, T* out, double a1, double cd1, double cd0,
+                                   hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // Two consecutive smoothing steps in one pass (y2 and optionally y1 written;
 // xp may be nullptr for x_prev = 0).  y2 and y1 must not alias x, xp or b.
-// x0_mode != 0: the first three steps of a pass from zero instead; x and xp
+// x0_mode == 1: the first three steps of a pass from zero instead; x and xp
 // are not read, the first step x = cd0 * b is formed on the fly in T, and
-// (a1, cd1) and (a2, cd2) are steps 1 and 2.  sums (pass from zero only):
-// an extra block also finishes those partial sums (sums.h).
+// (a1, cd1) and (a2, cd2) are steps 1 and 2.
+// x0_mode == 2: steps 2 and 3 of a pass from zero whose step 1 (x) came from
+// launch_smooth_fromb_row: x_prev is the first step cd0 * b, formed on the fly
+// (xp and y1 must be nullptr).
+// sums (x0_mode 1 and 2 only): an extra block also finishes those partial
+// sums (sums.h).
 // pair_kernels_apply tells whether n and the element size are supported.
 bool pair_kernels_apply(int n, size_t elem);
 // Three steps in one pass from x with x_prev = 0 (the start of a smoothing

@@ -129,6 +129,14 @@ __device__ __forceinline__ T cheb_step(T x, T xp, T b, T Mx, T a, T cd) {
     return fma_rn(cd, b - Mx, fma_rn(a, x - xp, x));
 }
 
+// The pointwise first step of a pass from zero, x = cd0 r (cd0 = c0 / D),
+// formed in T; with FROMB false, r itself.
+template <typename T, bool FROMB>
+__device__ __forceinline__ T first_step(T r, T cd0) {
+    if constexpr (FROMB) return cd0 * r;
+    return r;
+}
+
 // =====================================================================================
 // Chebyshev / Jacobi step: out = x + a (x - xprev) + cd (b - M x), cd = c / D
 // =====================================================================================
@@ -136,11 +144,15 @@ __device__ __forceinline__ T cheb_step(T x, T xp, T b, T Mx, T a, T cd) {
 // block of kWaves waves holds kWaves / S rows), so that rows of several KB
 // keep a modest number of values per lane; the x-neighbours across segment
 // ends come from one halo element loaded with each centre row.
-template <typename T, int VEC, bool HASX, bool PREV, int S = 1>
+// FROMB: the second step of a pass from zero, read from b alone: x holds the b
+// rows, the iterate is the pointwise first step cd0 b formed from them, and
+// x_prev = 0.
+template <typename T, int VEC, bool HASX, bool PREV, int S = 1, bool FROMB = false>
 __global__ __launch_bounds__(kBlock) void k_smooth_row(int n, T ih2, const T* x, const T* xprev,
                                                        const T* __restrict__ b, T* out, T a, T cd, int nz,
-                                                       int nyb) {
+                                                       int nyb, T cd0) {
     static_assert(kWaves % S == 0, "a block holds whole rows");
+    static_assert(!FROMB || (HASX && !PREV && S == 1), "a step from b has no x_prev and whole rows");
     constexpr int NR = 64 * VEC;
     const RowGrid g{NR * S, NR * S - 1};
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
@@ -173,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_row(int n, T ih2, const T* x,
         }
         ldrow<T, VEC>(ym, x + g.row(y - 1, z0) + off);
         ldrow<T, VEC>(yp, x + g.row(y + 1, z0) + off);
-        ldrow<T, VEC>(bb, b + g.row(y, z0) + off);
+        if constexpr (!FROMB) ldrow<T, VEC>(bb, b + g.row(y, z0) + off);
         if constexpr (PREV) ldrow<T, VEC>(pp, xprev + g.row(y, z0) + off);
         for (int k = 0; k < nz; ++k) {
             const int z = z0 + k;
@@ -186,13 +198,28 @@ __global__ __launch_bounds__(kBlock) void k_smooth_row(int n, T ih2, const T* x,
                 if constexpr (S > 1) hpp = x[g.row(y, z + 2) + hoff];
                 ldrow<T, VEC>(ymn, x + g.row(y - 1, z + 1) + off);
                 ldrow<T, VEC>(ypn, x + g.row(y + 1, z + 1) + off);
-                ldrow<T, VEC>(bn, b + g.row(y, z + 1) + off);
+                if constexpr (!FROMB) ldrow<T, VEC>(bn, b + g.row(y, z + 1) + off);
                 if constexpr (PREV) ldrow<T, VEC>(pn, xprev + g.row(y, z + 1) + off);
             }
             T Mx[VEC], o[VEC];
-            flat7_row_seg<T, VEC, S>(c, ym, yp, zm, zp, ih2, Mx, hc);
+            if constexpr (FROMB) {  // x = cd0 b on the row and its neighbours; b = the raw centre row
+                T fc[VEC], fym[VEC], fyp[VEC], fzm[VEC], fzp[VEC];
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) o[e] = cheb_step<T>(c[e], PREV ? pp[e] : T(0), bb[e], Mx[e], a, cd);
+                for (int e = 0; e < VEC; ++e) {
+                    fc[e] = first_step<T, true>(c[e], cd0);
+                    fym[e] = first_step<T, true>(ym[e], cd0);
+                    fyp[e] = first_step<T, true>(yp[e], cd0);
+                    fzm[e] = first_step<T, true>(zm[e], cd0);
+                    fzp[e] = first_step<T, true>(zp[e], cd0);
+                }
+                flat7_row<T, VEC>(fc, fym, fyp, fzm, fzp, ih2, Mx);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) o[e] = cheb_step<T>(fc[e], T(0), c[e], Mx[e], a, cd);
+            } else {
+                flat7_row_seg<T, VEC, S>(c, ym, yp, zm, zp, ih2, Mx, hc);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) o[e] = cheb_step<T>(c[e], PREV ? pp[e] : T(0), bb[e], Mx[e], a, cd);
+            }
             strow<T, VEC>(out + g.row(y, z) + off, o);
             if (more) {
                 copyrow(zm, c);
@@ -202,7 +229,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_row(int n, T ih2, const T* x,
                 hp = hpp;
                 copyrow(ym, ymn);
                 copyrow(yp, ypn);
-                copyrow(bb, bn);
+                if constexpr (!FROMB) copyrow(bb, bn);
                 if constexpr (PREV) copyrow(pp, pn);
             }
         }
@@ -370,10 +397,11 @@ __global__ __launch_bounds__(kBlock) void k_outer_row(int n, TA ih2, const doubl
 // so the y-neighbour rows come from LDS instead of L2/HBM.  Used where the
 // 2 (W + 2) rows fit in 80 KB of LDS.
 // =====================================================================================
-template <typename T, int VEC, int W, bool PREV>
+template <typename T, int VEC, int W, bool PREV, bool FROMB = false>
 __global__ __launch_bounds__(64 * W) void k_smooth_lds(int n, T ih2, const T* x, const T* xprev,
                                                        const T* __restrict__ b, T* out, T a, T cd, int nz,
-                                                       int nyb) {
+                                                       int nyb, T cd0) {
+    static_assert(!(FROMB && PREV), "a step from b has no x_prev");
     constexpr int NR = 64 * VEC;
     __shared__ T rows[2][W + 2][NR];
     const RowGrid g{64 * VEC, 64 * VEC - 1};
@@ -391,7 +419,7 @@ __global__ __launch_bounds__(64 * W) void k_smooth_lds(int n, T ih2, const T* x,
     ldrow<T, VEC>(zm, x + g.row(y, z0 - 1) + off);
     ldrow<T, VEC>(c, x + g.row(y, z0) + off);
     ldrow<T, VEC>(zp, x + g.row(y, z0 + 1) + off);
-    ldrow<T, VEC>(bb, b + g.row(y, z0) + off);
+    if constexpr (!FROMB) ldrow<T, VEC>(bb, b + g.row(y, z0) + off);
     if constexpr (PREV) ldrow<T, VEC>(pp, xprev + g.row(y, z0) + off);
     if (lo || hi) ldrow<T, VEC>(h, x + g.row(yh, z0) + off);
     for (int k = 0; k < nz; ++k) {
@@ -401,7 +429,7 @@ __global__ __launch_bounds__(64 * W) void k_smooth_lds(int n, T ih2, const T* x,
         const bool more = k + 1 < nz;
         if (more) {
             ldrow<T, VEC>(zpp, x + g.row(y, z + 2) + off);
-            ldrow<T, VEC>(bn, b + g.row(y, z + 1) + off);
+            if constexpr (!FROMB) ldrow<T, VEC>(bn, b + g.row(y, z + 1) + off);
             if constexpr (PREV) ldrow<T, VEC>(pn, xprev + g.row(y, z + 1) + off);
             if (lo || hi) ldrow<T, VEC>(hn, x + g.row(yh, z + 1) + off);
         }
@@ -413,15 +441,30 @@ __global__ __launch_bounds__(64 * W) void k_smooth_lds(int n, T ih2, const T* x,
         lds_ldrow<T, VEC>(ym, rows[buf][w], lane);
         lds_ldrow<T, VEC>(yp, rows[buf][w + 2], lane);
         T Mx[VEC], o[VEC];
-        flat7_row<T, VEC>(c, ym, yp, zm, zp, ih2, Mx);
+        if constexpr (FROMB) {  // x = cd0 b on the row and its neighbours; b = the raw centre row
+            T fc[VEC], fym[VEC], fyp[VEC], fzm[VEC], fzp[VEC];
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) o[e] = cheb_step<T>(c[e], PREV ? pp[e] : T(0), bb[e], Mx[e], a, cd);
+            for (int e = 0; e < VEC; ++e) {
+                fc[e] = first_step<T, true>(c[e], cd0);
+                fym[e] = first_step<T, true>(ym[e], cd0);
+                fyp[e] = first_step<T, true>(yp[e], cd0);
+                fzm[e] = first_step<T, true>(zm[e], cd0);
+                fzp[e] = first_step<T, true>(zp[e], cd0);
+            }
+            flat7_row<T, VEC>(fc, fym, fyp, fzm, fzp, ih2, Mx);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) o[e] = cheb_step<T>(fc[e], T(0), c[e], Mx[e], a, cd);
+        } else {
+            flat7_row<T, VEC>(c, ym, yp, zm, zp, ih2, Mx);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) o[e] = cheb_step<T>(c[e], PREV ? pp[e] : T(0), bb[e], Mx[e], a, cd);
+        }
         strow<T, VEC>(out + g.row(y, z) + off, o);
         if (more) {
             copyrow(zm, c);
             copyrow(c, zp);
             copyrow(zp, zpp);
-            copyrow(bb, bn);
+            if constexpr (!FROMB) copyrow(bb, bn);
             if constexpr (PREV) copyrow(pp, pn);
             if (lo || hi) copyrow(h, hn);
         }
@@ -444,28 +487,28 @@ __global__ __launch_bounds__(64 * W) void k_smooth_lds(int n, T ih2, const T* x,
 // the pointwise first step x = cd0 b (cd0 = c0 / D), formed from the b rows
 // in T exactly as the single step from zero and the outer residual kernel
 // form it, and xp = 0.  One pass then reads b and writes the third step.
+// PREVB: the third and fourth steps of a pass from zero of degree 4, whose
+// second step (x) a single-step launch formed from b alone.  x_prev is then
+// the pointwise first step cd0 b, formed from the b rows in T like the
+// above, instead of being written and read back.
 // With a sums job (job.count > 0), one extra block (block 0, dispatched first) finishes the
 // partial sums of the outer residual launch that produced b, instead of a
-// launch of its own.
+// launch of its own (FROMB and PREVB only).
 // =====================================================================================
-template <typename T, bool FROMB>
-__device__ __forceinline__ T first_step(T r, T cd0) {
-    if constexpr (FROMB) return cd0 * r;
-    return r;
-}
-
 // S > 1: each row is split into S segments of 64 VEC elements, one per wave
 // (S consecutive waves hold one row), so that long rows keep few values per
 // lane; the x-neighbours across segment ends come from a halo element loaded
 // with each row of the first step's z queue, and from the neighbouring
 // segment's slot in LDS for the second step.
 template <typename T, int VEC, int NW, bool PREV1, bool Y1OUT, bool FROMB = false, bool PF2 = false, int NZC = 0,
-          int S = 1>
+          int S = 1, bool PREVB = false>
 __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* __restrict__ x,
                                                          const T* __restrict__ xp, const T* __restrict__ b,
                                                          T* __restrict__ y2, T* __restrict__ y1o, T a1, T cd1, T a2,
                                                          T cd2, int nz, int nyb, T cd0, SumsJob job) {
     static_assert(!(FROMB && PREV1), "a pass from zero has no x_prev");
+    static_assert(!PREVB || PREV1, "PREVB forms x_prev from b");
+    constexpr bool LDP = PREV1 && !PREVB;  // x_prev is loaded
     static_assert(S == 1 || VEC * sizeof(T) <= 16, "split rows keep the plain LDS row layout");
     static_assert(NW % S == 0, "a block holds whole rows");
     constexpr int NR = 64 * VEC;
@@ -473,7 +516,7 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
     __shared__ T rows[2][NW][NR];
     const RowGrid g{NR * S, NR * S - 1};
     int nb = gridDim.x, bid = blockIdx.x;
-    if constexpr (FROMB) {
+    if constexpr (FROMB || PREVB) {
         if (job.count > 0) {  // block 0 finishes the sums, dispatched first
             nb -= 1;
             bid -= 1;
@@ -517,7 +560,7 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
     ldrow<T, VEC>(ym, src + g.row(y - 1, z1) + off);
     ldrow<T, VEC>(yp, src + g.row(y + 1, z1) + off);
     if constexpr (!FROMB) ldrow<T, VEC>(b1, b + g.row(y, z1) + off);
-    if constexpr (PREV1) ldrow<T, VEC>(p1, xp + g.row(y, z1) + off);
+    if constexpr (LDP) ldrow<T, VEC>(p1, xp + g.row(y, z1) + off);
     // NZC > 0: the chunk height is a compile-time constant and the plane loop
     // unrolls completely, so the row queues are renamed instead of copied and
     // each prefetched row is waited for where it is first used, not at the end
@@ -532,7 +575,7 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
         ldrow<T, VEC>(yma, src + g.row(y - 1, z1 + 1) + off);
         ldrow<T, VEC>(ypa, src + g.row(y + 1, z1 + 1) + off);
         if constexpr (!FROMB) ldrow<T, VEC>(ba, b + g.row(y, z1 + 1) + off);
-        if constexpr (PREV1) ldrow<T, VEC>(pa, xp + g.row(y, z1 + 1) + off);
+        if constexpr (LDP) ldrow<T, VEC>(pa, xp + g.row(y, z1 + 1) + off);
     }
     auto plane = [&](const int j) {
         const bool more = j + 1 < steps;
@@ -546,7 +589,7 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
             ldrow<T, VEC>(ymn, src + g.row(y - 1, z1 + 1 + ahead) + off);
             ldrow<T, VEC>(ypn, src + g.row(y + 1, z1 + 1 + ahead) + off);
             if constexpr (!FROMB) ldrow<T, VEC>(bn, b + g.row(y, z1 + 1 + ahead) + off);
-            if constexpr (PREV1) ldrow<T, VEC>(pn, xp + g.row(y, z1 + 1 + ahead) + off);
+            if constexpr (LDP) ldrow<T, VEC>(pn, xp + g.row(y, z1 + 1 + ahead) + off);
         }
         T M1[VEC], sp[VEC];
         if constexpr (FROMB) {
@@ -565,7 +608,10 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
         } else {
             flat7_row_seg<T, VEC, S>(xc, ym, yp, xm, xq, ih2, M1, hc);
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) sp[e] = cheb_step<T>(xc[e], PREV1 ? p1[e] : T(0), b1[e], M1[e], a1, cd1);
+            for (int e = 0; e < VEC; ++e) {
+                const T xpe = PREVB ? first_step<T, true>(b1[e], cd0) : PREV1 ? p1[e] : T(0);
+                sp[e] = cheb_step<T>(xc[e], xpe, b1[e], M1[e], a1, cd1);
+            }
         }
         if constexpr (Y1OUT) {
             if (outw && j >= 1 && j <= nz) strow<T, VEC>(y1o + g.row(y, z1) + off, sp);
@@ -605,13 +651,13 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
                 copyrow(ym, yma);
                 copyrow(yp, ypa);
                 if constexpr (!FROMB) copyrow(b1, ba);
-                if constexpr (PREV1) copyrow(p1, pa);
+                if constexpr (LDP) copyrow(p1, pa);
                 if (load) {
                     copyrow(xa, xn);
                     copyrow(yma, ymn);
                     copyrow(ypa, ypn);
                     if constexpr (!FROMB) copyrow(ba, bn);
-                    if constexpr (PREV1) copyrow(pa, pn);
+                    if constexpr (LDP) copyrow(pa, pn);
                 }
             } else {
                 hq = hn;
@@ -619,7 +665,7 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
                 copyrow(ym, ymn);
                 copyrow(yp, ypn);
                 if constexpr (!FROMB) copyrow(b1, bn);
-                if constexpr (PREV1) copyrow(p1, pn);
+                if constexpr (LDP) copyrow(p1, pn);
             }
         }
     };
@@ -637,12 +683,14 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
 // split rows, its x-halo) come from LDS instead of the caches; only the two
 // edge rows of the block load their outer neighbour row.  One barrier per
 // plane for both planes; same arithmetic and bits as k_smooth2_lds.
-template <typename T, int VEC, int NW, bool PREV1, bool Y1OUT, bool FROMB, int NZC, int S>
+template <typename T, int VEC, int NW, bool PREV1, bool Y1OUT, bool FROMB, int NZC, int S, bool PREVB = false>
 __global__ __launch_bounds__(64 * NW) void k_smooth2x_lds(int n, T ih2, const T* __restrict__ x,
                                                           const T* __restrict__ xp, const T* __restrict__ b,
                                                           T* __restrict__ y2, T* __restrict__ y1o, T a1, T cd1,
                                                           T a2, T cd2, int nyb, T cd0, SumsJob job) {
     static_assert(!(FROMB && PREV1), "a pass from zero has no x_prev");
+    static_assert(!PREVB || PREV1, "PREVB forms x_prev from b");
+    constexpr bool LDP = PREV1 && !PREVB;  // x_prev is loaded
     static_assert(VEC * sizeof(T) <= 16, "plain LDS row layout");
     static_assert(NW % S == 0 && NW / S >= 3, "a block holds whole rows, at least one output row");
     constexpr int NR = 64 * VEC;
@@ -652,7 +700,7 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2x_lds(int n, T ih2, const T*
     __shared__ T rows[2][NW][NR];  // first-step rows of a plane
     const RowGrid g{NR * S, NR * S - 1};
     int nb = gridDim.x, bid = blockIdx.x;
-    if constexpr (FROMB) {
+    if constexpr (FROMB || PREVB) {
         if (job.count > 0) {  // block 0 finishes the sums, dispatched first
             nb -= 1;
             bid -= 1;
@@ -686,7 +734,7 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2x_lds(int n, T ih2, const T*
     ldrow<T, VEC>(xq, src + g.row(y, z1 + 1) + off);
     if (lo || hi) ldrow<T, VEC>(o1, src + g.row(yo, z1) + off);
     if constexpr (!FROMB) ldrow<T, VEC>(b1, b + g.row(y, z1) + off);
-    if constexpr (PREV1) ldrow<T, VEC>(p1, xp + g.row(y, z1) + off);
+    if constexpr (LDP) ldrow<T, VEC>(p1, xp + g.row(y, z1) + off);
     lds_strow<T, VEC>(xs[0][w], lane, xc);
     __syncthreads();
     constexpr int steps = NZC + 2;
@@ -699,7 +747,7 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2x_lds(int n, T ih2, const T*
             ldrow<T, VEC>(xn, src + g.row(y, z1 + 2) + off);
             if (lo || hi) ldrow<T, VEC>(on, src + g.row(yo, z1 + 1) + off);
             if constexpr (!FROMB) ldrow<T, VEC>(bn, b + g.row(y, z1 + 1) + off);
-            if constexpr (PREV1) ldrow<T, VEC>(pn, xp + g.row(y, z1 + 1) + off);
+            if constexpr (LDP) ldrow<T, VEC>(pn, xp + g.row(y, z1 + 1) + off);
         }
         // first step at z1
         T ym[VEC], yp[VEC], M1[VEC], sp[VEC];
@@ -725,7 +773,10 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2x_lds(int n, T ih2, const T*
         } else {
             flat7_row_seg<T, VEC, S>(xc, ym, yp, xm, xq, ih2, M1, hx);
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) sp[e] = cheb_step<T>(xc[e], PREV1 ? p1[e] : T(0), b1[e], M1[e], a1, cd1);
+            for (int e = 0; e < VEC; ++e) {
+                const T xpe = PREVB ? first_step<T, true>(b1[e], cd0) : PREV1 ? p1[e] : T(0);
+                sp[e] = cheb_step<T>(xc[e], xpe, b1[e], M1[e], a1, cd1);
+            }
         }
         if constexpr (Y1OUT) {
             if (outw && j >= 1 && j <= NZC) strow<T, VEC>(y1o + g.row(y, z1) + off, sp);
@@ -759,7 +810,7 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2x_lds(int n, T ih2, const T*
             copyrow(xq, xn);
             if (lo || hi) copyrow(o1, on);
             if constexpr (!FROMB) copyrow(b1, bn);
-            if constexpr (PREV1) copyrow(p1, pn);
+            if constexpr (LDP) copyrow(p1, pn);
         }
     }
 }
@@ -1440,10 +1491,10 @@ hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, cons
             if constexpr (2ull * (Wv + 2) * 64 * VEC * sizeof(T) <= kLdsBudget) {
                 if (xprev == nullptr)
                     MG_LAUNCH((k_smooth_lds<T, VEC, Wv, false>), dim3(blocks), dim3(64 * Wv), s, ev0, ev1, n,
-                                       (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb);
+                                       (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb, (T)0);
                 else
                     MG_LAUNCH((k_smooth_lds<T, VEC, Wv, true>), dim3(blocks), dim3(64 * Wv), s, ev0, ev1, n,
-                                       (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb);
+                                       (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb, (T)0);
             }
         })
         return hipGetLastError();
@@ -1455,10 +1506,10 @@ hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, cons
     DISPATCH_SEG(n, SS, {                                                                                            \
         if (xprev == nullptr)                                                                                        \
             MG_LAUNCH((k_smooth_row<T, VEC, true, false, SS>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (T)ih2, x, \
-                      xprev, b, out, (T)a, (T)cd, nz, nyb);                                                           \
+                      xprev, b, out, (T)a, (T)cd, nz, nyb, (T)0);                                                     \
         else                                                                                                         \
             MG_LAUNCH((k_smooth_row<T, VEC, true, true, SS>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (T)ih2, x,  \
-                      xprev, b, out, (T)a, (T)cd, nz, nyb);                                                           \
+                      xprev, b, out, (T)a, (T)cd, nz, nyb, (T)0);                                                     \
     })
         switch (S) {
             case 2: MG_SMOOTH_SEG(2); break;
@@ -1472,13 +1523,42 @@ hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, cons
     DISPATCH_VEC(n, {
         if (x == nullptr)
             MG_LAUNCH((k_smooth_row<T, VEC, false, false>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (T)ih2, x,
-                               xprev, b, out, (T)a, (T)cd, nz, nyb);
+                               xprev, b, out, (T)a, (T)cd, nz, nyb, (T)0);
         else if (xprev == nullptr)
             MG_LAUNCH((k_smooth_row<T, VEC, true, false>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (T)ih2, x,
-                               xprev, b, out, (T)a, (T)cd, nz, nyb);
+                               xprev, b, out, (T)a, (T)cd, nz, nyb, (T)0);
         else
             MG_LAUNCH((k_smooth_row<T, VEC, true, true>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (T)ih2, x,
-                               xprev, b, out, (T)a, (T)cd, nz, nyb);
+                               xprev, b, out, (T)a, (T)cd, nz, nyb, (T)0);
+    })
+    return hipGetLastError();
+}
+
+// The second step of a pass from zero from b alone (x_prev = 0, the iterate
+// x1 = cd0 b formed on the fly): out = x1 + a1 x1 + cd1 (b - M x1), in the
+// rounding of the single steps.  Whole rows only (rows of at most 2 KB).
+template <typename T>
+hipError_t launch_smooth_fromb_row(int n, double ih2, const T* b, T* out, double a1, double cd1, double cd0,
+                                   hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (row_segments(n, sizeof(T)) != 1) return hipErrorInvalidValue;
+    int nz, nyb, blocks;
+    if (n >= 512 && lds_rows_fit<T>(n)) {  // the launch shape of the single step
+        constexpr int Wv = kLdsWaves;
+        nyb = n / Wv;
+        nz = n;
+        while (nz > 4 && nyb * (n / nz) < 2048) nz >>= 1;
+        blocks = nyb * (n / nz);
+        DISPATCH_VEC(n, {
+            if constexpr (2ull * (Wv + 2) * 64 * VEC * sizeof(T) <= kLdsBudget)
+                MG_LAUNCH((k_smooth_lds<T, VEC, Wv, false, true>), dim3(blocks), dim3(64 * Wv), s, ev0, ev1, n,
+                          (T)ih2, b, nullptr, b, out, (T)a1, (T)cd1, nz, nyb, (T)cd0);
+        })
+        return hipGetLastError();
+    }
+    shape(n, n, 4, nz, nyb, blocks);
+    DISPATCH_VEC(n, {
+        MG_LAUNCH((k_smooth_row<T, VEC, true, false, 1, true>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (T)ih2,
+                  b, nullptr, b, out, (T)a1, (T)cd1, nz, nyb, (T)cd0);
     })
     return hipGetLastError();
 }
@@ -1507,16 +1587,17 @@ bool pair_kernels_apply(int n, size_t elem) {
 }
 
 // launch of one k_smooth2_lds variant inside launch_pair_nw (VEC from DISPATCH_VEC)
-#define MG_PAIR1(PREV1, Y1OUT, FROMB, PF2, NZC)                                                                 \
-    MG_LAUNCH((k_smooth2_lds<T, VEC, NW, PREV1, Y1OUT, FROMB, PF2, NZC>), dim3(blocks + (FROMB ? extra : 0)),      \
-              dim3(64 * NW), s, ev0, ev1, n, (T)ih2, x, xp, b, y2, y1, (T)a1, (T)cd1, (T)a2, (T)cd2, nz, nyb,     \
-              (T)cd0, FROMB ? sums : SumsJob{})
-#define MG_PAIR(PREV1, Y1OUT, FROMB)                                          \
-    do {                                                                      \
-        if (pf2) MG_PAIR1(PREV1, Y1OUT, FROMB, true, 0);                      \
-        else if (nz == kPairUnrollNz) MG_PAIR1(PREV1, Y1OUT, FROMB, false, kPairUnrollNz); \
-        else MG_PAIR1(PREV1, Y1OUT, FROMB, false, 0);                         \
+#define MG_PAIR1(PREV1, Y1OUT, FROMB, PF2, NZC, PREVB)                                                           \
+    MG_LAUNCH((k_smooth2_lds<T, VEC, NW, PREV1, Y1OUT, FROMB, PF2, NZC, 1, PREVB>),                                 \
+              dim3(blocks + ((FROMB || PREVB) ? extra : 0)), dim3(64 * NW), s, ev0, ev1, n, (T)ih2, x, xp, b, y2, \
+              y1, (T)a1, (T)cd1, (T)a2, (T)cd2, nz, nyb, (T)cd0, (FROMB || PREVB) ? sums : SumsJob{})
+#define MG_PAIRB(PREV1, Y1OUT, FROMB, PREVB)                                                     \
+    do {                                                                                         \
+        if (pf2) MG_PAIR1(PREV1, Y1OUT, FROMB, true, 0, PREVB);                                  \
+        else if (nz == kPairUnrollNz) MG_PAIR1(PREV1, Y1OUT, FROMB, false, kPairUnrollNz, PREVB); \
+        else MG_PAIR1(PREV1, Y1OUT, FROMB, false, 0, PREVB);                                     \
     } while (0)
+#define MG_PAIR(PREV1, Y1OUT, FROMB) MG_PAIRB(PREV1, Y1OUT, FROMB, false)
 
 template <typename T, int NW>
 hipError_t launch_pair_nw(int n, double ih2, const T* x, const T* xp, const T* b, T* y2, T* y1, double a1, double cd1,
@@ -1534,10 +1615,12 @@ hipError_t launch_pair_nw(int n, double ih2, const T* x, const T* xp, const T* b
     const bool pf2 = (size_t)n * sizeof(T) >= 2048;
     DISPATCH_VEC(n, {
         if constexpr (64 * VEC * sizeof(T) <= pair_max_row_bytes(NW) && 2ull * NW * 64 * VEC * sizeof(T) <= kPairLdsBudget) {
-            if (x0_mode != 0) {
+            if (x0_mode == 2) {
+                MG_PAIRB(true, false, false, true);
+            } else if (x0_mode != 0) {
                 if (!pf2 && nz == kPairUnrollNz) {
-                    if (y1 == nullptr) MG_PAIR1(false, false, true, true, kPairUnrollNz);
-                    else MG_PAIR1(false, true, true, true, kPairUnrollNz);
+                    if (y1 == nullptr) MG_PAIR1(false, false, true, true, kPairUnrollNz, false);
+                    else MG_PAIR1(false, true, true, true, kPairUnrollNz, false);
                 } else if (y1 == nullptr) MG_PAIR(false, false, true);
                 else MG_PAIR(false, true, true);
             } else if (xp == nullptr && y1 == nullptr) {
@@ -1556,16 +1639,20 @@ hipError_t launch_pair_nw(int n, double ih2, const T* x, const T* xp, const T* b
     return hipGetLastError();
 }
 #undef MG_PAIR
+#undef MG_PAIRB
 #undef MG_PAIR1
 
 // Rows longer than kPairSegBytes run the two-step kernels split into segments
-// of that many bytes, one wave each, with the block shape and chunk length of
-// the 1 KB rows of 256^3 float (16 waves = 8 rows, chunks of 8 planes): a
-// lane then holds 16 bytes of a row, and the register budget of 16-wave
-// blocks holds the fully unrolled variants.
+// of that many bytes, one wave each, with the block shape of the 1 KB rows of
+// 256^3 float (16 waves = 8 rows): a lane then holds 16 bytes of a row, and
+// the register budget of 16-wave blocks holds the fully unrolled variants.
+// A chunk of NZC output planes reads NZC + 4 planes of x and NZC + 2 of b and
+// x_prev; chunks of 16 planes instead of 8 cut the fetch of the first step's
+// z halo: 512^3 float pairs 4.45 -> 4.63 TB/s, 256^3 double 3.97 -> 4.31 TB/s
+// (32 planes: 4.58 TB/s at 512^3), same bits.
 constexpr size_t kPairSegBytes = 1024;
-constexpr int kPairSegWaves = 16;       // block of the split two-step kernels
-constexpr int kPairSegNz = kPairUnrollNz;  // their (fully unrolled) chunk height
+constexpr int kPairSegWaves = 16;  // block of the split two-step kernels
+constexpr int kPairSegNz = 16;     // their (fully unrolled) chunk height
 // x plane of the split two-step kernels shared through LDS (k_smooth2x_lds):
 // 512^3 float pairs 4.07 -> 4.45 TB/s, 256^3 double 3.74 -> 3.98 TB/s, same
 // bits.  Unsplit 1 KB rows keep k_smooth2_lds: the 256^3 float pass from zero
@@ -1576,16 +1663,17 @@ inline int pair_segments(int n, size_t elem) {
     return row > kPairSegBytes ? (int)(row / kPairSegBytes) : 1;
 }
 
-#define MG_PAIRS(PREV1, Y1OUT, FROMB, PF2)                                                                         \
+#define MG_PAIRS(PREV1, Y1OUT, FROMB, PF2, PREVB)                                                                  \
     do {                                                                                                         \
+        constexpr bool JOB = FROMB || PREVB;                                                                     \
         if constexpr (kPairXLds)                                                                                 \
-            MG_LAUNCH((k_smooth2x_lds<T, VEC, NW, PREV1, Y1OUT, FROMB, kPairSegNz, S>),                          \
-                      dim3(blocks + (FROMB ? extra : 0)), dim3(64 * NW), s, ev0, ev1, n, (T)ih2, x, xp, b, y2, y1, \
-                      (T)a1, (T)cd1, (T)a2, (T)cd2, nyb, (T)cd0, FROMB ? sums : SumsJob{});                      \
+            MG_LAUNCH((k_smooth2x_lds<T, VEC, NW, PREV1, Y1OUT, FROMB, kPairSegNz, S, PREVB>),                   \
+                      dim3(blocks + (JOB ? extra : 0)), dim3(64 * NW), s, ev0, ev1, n, (T)ih2, x, xp, b, y2, y1,   \
+                      (T)a1, (T)cd1, (T)a2, (T)cd2, nyb, (T)cd0, JOB ? sums : SumsJob{});                        \
         else                                                                                                     \
-            MG_LAUNCH((k_smooth2_lds<T, VEC, NW, PREV1, Y1OUT, FROMB, PF2, kPairSegNz, S>),                      \
-                      dim3(blocks + (FROMB ? extra : 0)), dim3(64 * NW), s, ev0, ev1, n, (T)ih2, x, xp, b, y2, y1, \
-                      (T)a1, (T)cd1, (T)a2, (T)cd2, kPairSegNz, nyb, (T)cd0, FROMB ? sums : SumsJob{});          \
+            MG_LAUNCH((k_smooth2_lds<T, VEC, NW, PREV1, Y1OUT, FROMB, PF2, kPairSegNz, S, PREVB>),               \
+                      dim3(blocks + (JOB ? extra : 0)), dim3(64 * NW), s, ev0, ev1, n, (T)ih2, x, xp, b, y2, y1,   \
+                      (T)a1, (T)cd1, (T)a2, (T)cd2, kPairSegNz, nyb, (T)cd0, JOB ? sums : SumsJob{});            \
     } while (0)
 template <typename T, int NW, int S>
 hipError_t launch_pair_seg(int n, double ih2, const T* x, const T* xp, const T* b, T* y2, T* y1, double a1,
@@ -1600,17 +1688,19 @@ hipError_t launch_pair_seg(int n, double ih2, const T* x, const T* xp, const T* 
     auto go = [&](auto vtag) -> hipError_t {
         constexpr int VEC = decltype(vtag)::value;
         if constexpr (VEC * sizeof(T) <= 16 && 2ull * NW * 64 * VEC * sizeof(T) <= kPairLdsBudget) {
-            if (x0_mode != 0) {
-                if (y1 == nullptr) MG_PAIRS(false, false, true, true);
-                else MG_PAIRS(false, true, true, true);
+            if (x0_mode == 2) {
+                MG_PAIRS(true, false, false, false, true);
+            } else if (x0_mode != 0) {
+                if (y1 == nullptr) MG_PAIRS(false, false, true, true, false);
+                else MG_PAIRS(false, true, true, true, false);
             } else if (xp == nullptr && y1 == nullptr) {
-                MG_PAIRS(false, false, false, false);
+                MG_PAIRS(false, false, false, false, false);
             } else if (xp == nullptr) {
-                MG_PAIRS(false, true, false, false);
+                MG_PAIRS(false, true, false, false, false);
             } else if (y1 == nullptr) {
-                MG_PAIRS(true, false, false, false);
+                MG_PAIRS(true, false, false, false, false);
             } else {
-                MG_PAIRS(true, true, false, false);
+                MG_PAIRS(true, true, false, false, false);
             }
             return hipGetLastError();
         }
@@ -1630,9 +1720,11 @@ hipError_t launch_smooth_pair_row(int n, double ih2, const T* x, const T* xp, co
                                   hipEvent_t ev1, int x0_mode, double cd0, const SumsJob* sums_job) {
     if (!pair_kernels_apply(n, sizeof(T))) return hipErrorInvalidValue;
     const SumsJob sums = sums_job ? *sums_job : SumsJob{};
+    if (x0_mode < 0 || x0_mode > 2) return hipErrorInvalidValue;
     if (sums.count > 0 && x0_mode == 0) return hipErrorInvalidValue;
-    if (x0_mode == 0 && x == nullptr) return hipErrorInvalidValue;
+    if (x0_mode != 1 && x == nullptr) return hipErrorInvalidValue;
     if (x0_mode != 0 && xp != nullptr) return hipErrorInvalidValue;
+    if (x0_mode == 2 && y1 != nullptr) return hipErrorInvalidValue;
     switch (pair_segments(n, sizeof(T))) {
         case 1: break;
         case 2:
@@ -1644,7 +1736,7 @@ hipError_t launch_smooth_pair_row(int n, double ih2, const T* x, const T* xp, co
     // The pass from zero (one field read) runs best in larger blocks where the
     // row fits their register budget: 256^3 16 waves 33.8 us (8: 35.4, 12: 38.3),
     // 128^3 12 waves 7.8 us (8: 8.6), 64^3 8 waves.
-    if (x0_mode != 0) {
+    if (x0_mode == 1) {
         const size_t row = (size_t)n * sizeof(T);
         waves = (n >= 256 && row <= pair_max_row_bytes(16)) ? 16 : (n >= 128 && row <= pair_max_row_bytes(12)) ? 12 : 8;
         if (2ull * waves * row > kPairLdsBudget) waves = 8;
@@ -1846,6 +1938,10 @@ template hipError_t launch_smooth_row<float>(int, double, const float*, const fl
                                              double, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_smooth_row<double>(int, double, const double*, const double*, const double*, double*,
                                               double, double, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_smooth_fromb_row<float>(int, double, const float*, float*, double, double, double,
+                                                   hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_smooth_fromb_row<double>(int, double, const double*, double*, double, double, double,
+                                                    hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_smooth_pair_row<float>(int, double, const float*, const float*, const float*, float*,
                                                   float*, double, double, double, double, hipStream_t, hipEvent_t,
                                                   hipEvent_t, int, double, const SumsJob*);

@@ -363,6 +363,7 @@ mg_status smooth_level(mg_ctx* c, int l, bool from_zero) {
     const int v = (int)L.a.size();
     // the last two steps of the pass run as one two-step kernel where it exists
     const bool pairs = c->use_pairs && L.x[2] != nullptr && !c->var;
+    bool prev_b = false;  // x_{k-1} is the pointwise first step c0 D^-1 b, formed by the next kernel
     for (int k = 0; k < v; ++k) {
         double bytes = 0.0;
         if (k == 0 && from_zero && l == 0 && c->x1_ready) {  // formed by the outer residual kernel
@@ -378,16 +379,31 @@ mg_status smooth_level(mg_ctx* c, int l, bool from_zero) {
         const int rem = v - k;
         const bool has_prev = cheb && prev >= 0;
         const bool need_y1 = cheb && rem > 2;
-        const bool triple = k == 0 && from_zero && from_zero_triple(c, l);
+        // a pass from zero of degree 4: steps 0 and 1 from b alone (b -> x_2),
+        // then steps 2 and 3 as a pair whose x_prev = x_1 is formed from b
+        // (b, x_2 -> x_4): 5 field passes instead of 7 for steps 0-2 in one
+        // kernel (b -> x_3, x_2) and step 3 on its own
+        const bool fromb = k == 0 && from_zero && cheb && v == 4 && from_zero_triple(c, l);
+        const bool triple = k == 0 && from_zero && from_zero_triple(c, l) && !fromb;
         // a pass of three steps that does not start from zero: one three-step kernel
         const bool triple3 = k == 0 && !from_zero && cheb && v == 3 && c->use_pairs && !c->var &&
                              triple_kernels_apply(L.n, sizeof(T));
         const bool pair = pairs && rem >= 2 && rem % 2 == 0 && !(k == 0 && from_zero) && !(need_y1 && has_prev);
-        const int kind = triple3 ? MG_TIME_TRIPLE : (pair || triple) ? MG_TIME_PAIR : MG_TIME_STEP;
+        const int kind = triple3 ? MG_TIME_TRIPLE : (pair || triple) && !fromb ? MG_TIME_PAIR : MG_TIME_STEP;
         hipEvent_t ev0, ev1;
         mg_status st = time_events(c, fine, kind, &ev0, &ev1);
         if (st != MG_OK) return st;
-        if (triple3) {
+        if (fromb) {
+            const int out = 1;
+            const double D = -6.0 * L.ih2;
+            HIPCHK(c, launch_smooth_fromb_row<T>(L.n, L.ih2, (const T*)L.b, bufs[out], L.a[1], L.c[1] / D,
+                                                 L.c[0] / D, c->stream, ev0, ev1));
+            bytes = 2.0 * fbytes;  // b; x_2
+            prev = -1;
+            prev_b = true;
+            cur = out;
+            k = 1;  // two steps done
+        } else if (triple3) {
             const int out = other(cur);
             const double D = -6.0 * L.ih2;
             HIPCHK(c, launch_smooth_triple_row<T>(L.n, L.ih2, bufs[cur], (const T*)L.b, bufs[out], L.a[0],
@@ -431,10 +447,20 @@ mg_status smooth_level(mg_ctx* c, int l, bool from_zero) {
                 mid = need_y1 ? f1 : -1;
             }
             const double D = -6.0 * L.ih2;  // c / D rounded as in the single-step launch
+            // after a step from b, level 0 finishes the pending outer sums here
+            const bool sums = prev_b && l == 0 && c->pending_sums;
+            const SumsJob job{c->partials, c->nparts_outer, 3, c->dscal, 1, c->hscal, sums ? c->sums_seq + 1.0 : 0.0};
             HIPCHK(c, launch_smooth_pair_row<T>(L.n, L.ih2, bufs[cur], xp, (const T*)L.b, bufs[out],
                                                 mid >= 0 ? bufs[mid] : nullptr, L.a[k], L.c[k] / D, L.a[k + 1],
-                                                L.c[k + 1] / D, c->stream, ev0, ev1));
+                                                L.c[k + 1] / D, c->stream, ev0, ev1, prev_b ? 2 : 0, L.c[0] / D,
+                                                sums ? &job : nullptr));
+            if (sums) {
+                c->sums_seq += 1.0;
+                c->scal_flag = true;
+                c->pending_sums = false;
+            }
             bytes = (3.0 + (xp ? 1.0 : 0.0) + (mid >= 0 ? 1.0 : 0.0)) * fbytes;  // x, [x_prev], b; y2, [y1]
+            prev_b = false;
             prev = mid;
             cur = out;
             ++k;  // the pair's second step
