@@ -105,8 +105,9 @@ def model_bytes_per_cycle(n, levels, degree, precision):
     """Algorithmic bytes of one outer iteration (inner V-cycle + outer residual/update),
     every field element each kernel reads or writes counted once, following the
     library's schedule: multi-step kernels on levels 64 <= n_l (two-step rows up
-    to 2 KB, three-step rows up to 1 KB; from 128^3 the three-step pass forms
-    x + P e itself, so the prolongation writes nothing), the 32^3 and 64^3
+    to 2 KB, three-step rows up to 1 KB; from 128^3 the three-step pass, and
+    on rows over 1 KB the first pair of an even-degree pass, forms x + P e
+    itself, so the prolongation writes nothing), the 32^3 and 64^3
     levels of a float hierarchy as two fused visits each, the outer kernel
     writing the first step from zero only where the fine level has no
     pass-from-zero kernel."""
@@ -123,7 +124,10 @@ def model_bytes_per_cycle(n, levels, degree, precision):
         x1_outer = l == 0 and not (pairs and degree >= 3)
         pre = pass_bytes(degree, True, pairs, triple, s) - (2 * s if x1_outer else 0)  # step 0 by the outer
         post = pass_bytes(degree, False, pairs, triple, s)
-        fused_prolong = triple and nl >= 128 and degree == 3
+        # the prolongation runs inside the post-smoothing pass's first kernel:
+        # the three-step pass from 128^3 (degree 3), the first pair on split
+        # rows (rows of 1-2 KB, an even degree)
+        fused_prolong = (triple and nl >= 128 and degree == 3) or (pairs and nl * s > 1024 and degree % 2 == 0)
         transfers = 2 * s + s / 8 + (s / 8 if fused_prolong else 2 * s + s / 8)
         tot += nl ** 3 * (pre + post + transfers)
     # outer: read phi, e, b; write phi, r (and the first smoothing step where no pass-from-zero kernel runs)

@@ -31,8 +31,11 @@ hipError_t launch_smooth_fromb_row(int n, double ih2, const T* b, T* out, double
 // (xp and y1 must be nullptr).
 // sums (x0_mode 1 and 2 only): an extra block also finishes those partial
 // sums (sums.h).
+// ec != nullptr (x0_mode 0, no xp, pair_pro_applies): the pair starts from
+// x0 = x + P ec, ec on the (n/2)^3 grid, formed on the fly; x is not changed.
 // pair_kernels_apply tells whether n and the element size are supported.
 bool pair_kernels_apply(int n, size_t elem);
+bool pair_pro_applies(int n, size_t elem);
 // Three steps in one pass from x with x_prev = 0 (the start of a smoothing
 // pass that is not from zero): y3 after steps (a0, cd0), (a1, cd1), (a2, cd2).
 // y3 must differ from x and b.
@@ -52,7 +55,7 @@ template <typename T>
 hipError_t launch_smooth_pair_row(int n, double ih2, const T* x, const T* xp, const T* b, T* y2, T* y1,
                                   double a1, double cd1, double a2, double cd2, hipStream_t s,
                                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, int x0_mode = 0,
-                                  double cd0 = 0.0, const SumsJob* sums = nullptr);
+                                  double cd0 = 0.0, const SumsJob* sums = nullptr, const T* ec = nullptr);
 template <typename TA, typename TR, typename TE>
 hipError_t launch_outer_row(int n, double ih2, const double* phi_in, const TE* e, double* phi_out, const double* b,
                             double bmean, TR* r, TR* x1, double cd0, double* partials, hipStream_t s,

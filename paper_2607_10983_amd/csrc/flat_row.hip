@@ -677,144 +677,6 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
     }
 }
 
-// The same two steps with the x plane (FROMB: the b plane) shared through LDS
-// as well: every wave loads only its own row of x (b, x_prev) and publishes
-// it one plane ahead of its use, so the first step's y-neighbours (and, for
-// split rows, its x-halo) come from LDS instead of the caches; only the two
-// edge rows of the block load their outer neighbour row.  One barrier per
-// plane for both planes; same arithmetic and bits as k_smooth2_lds.
-template <typename T, int VEC, int NW, bool PREV1, bool Y1OUT, bool FROMB, int NZC, int S, bool PREVB = false>
-__global__ __launch_bounds__(64 * NW) void k_smooth2x_lds(int n, T ih2, const T* __restrict__ x,
-                                                          const T* __restrict__ xp, const T* __restrict__ b,
-                                                          T* __restrict__ y2, T* __restrict__ y1o, T a1, T cd1,
-                                                          T a2, T cd2, int nyb, T cd0, SumsJob job) {
-    static_assert(!(FROMB && PREV1), "a pass from zero has no x_prev");
-    static_assert(!PREVB || PREV1, "PREVB forms x_prev from b");
-    constexpr bool LDP = PREV1 && !PREVB;  // x_prev is loaded
-    static_assert(VEC * sizeof(T) <= 16, "plain LDS row layout");
-    static_assert(NW % S == 0 && NW / S >= 3, "a block holds whole rows, at least one output row");
-    constexpr int NR = 64 * VEC;
-    constexpr int R = NW / S;  // rows of the block
-    constexpr int W = R - 2;   // output rows
-    __shared__ T xs[2][NW][NR];    // x (FROMB: b) rows of a plane, one plane ahead
-    __shared__ T rows[2][NW][NR];  // first-step rows of a plane
-    const RowGrid g{NR * S, NR * S - 1};
-    int nb = gridDim.x, bid = blockIdx.x;
-    if constexpr (FROMB || PREVB) {
-        if (job.count > 0) {  // block 0 finishes the sums, dispatched first
-            nb -= 1;
-            bid -= 1;
-            if (bid < 0) {
-                __shared__ double sh[kSumLanes];
-                finish_sums(job, sh);
-                return;
-            }
-        }
-    }
-    const int lb = xcd_logical(bid, nb);
-    const int yb = lb % nyb, zc = lb / nyb;
-    const int w = wave_id();
-    const int wr = w / S, seg = w - wr * S;
-    const int lane = threadIdx.x & 63;
-    const int y = yb * W - 1 + wr;  // rows outside [0, n) wrap for loads
-    const bool outw = wr >= 1 && wr <= W && y < n;
-    const bool lo = wr == 0, hi = wr == R - 1;
-    const int yo = lo ? y - 1 : y + 1;  // outer neighbour row of an edge row
-    const int z0 = zc * NZC;
-    const size_t off = (size_t)seg * NR + (size_t)lane * VEC;
-    const int wprev = wr * S + (seg + S - 1) % S, wnext = wr * S + (seg + 1) % S;
-    const T* src = FROMB ? b : x;
-    int z1 = z0 - 1;
-    // first step at z1: this row at z1-1, z1, z1+1, the outer row (edges) at z1, b and xp at z1
-    T xm[VEC], xc[VEC], xq[VEC], o1[VEC] = {}, b1[VEC], p1[VEC];
-    // second step at z2 = z1 - 1: first-step rows at z2-1, z2; b at z2; x_prev = xm
-    T sm[VEC] = {}, sc[VEC] = {}, b2[VEC] = {};
-    ldrow<T, VEC>(xm, src + g.row(y, z1 - 1) + off);
-    ldrow<T, VEC>(xc, src + g.row(y, z1) + off);
-    ldrow<T, VEC>(xq, src + g.row(y, z1 + 1) + off);
-    if (lo || hi) ldrow<T, VEC>(o1, src + g.row(yo, z1) + off);
-    if constexpr (!FROMB) ldrow<T, VEC>(b1, b + g.row(y, z1) + off);
-    if constexpr (LDP) ldrow<T, VEC>(p1, xp + g.row(y, z1) + off);
-    lds_strow<T, VEC>(xs[0][w], lane, xc);
-    __syncthreads();
-    constexpr int steps = NZC + 2;
-#pragma unroll
-    for (int j = 0; j < steps; ++j, ++z1) {
-        const bool more = j + 1 < steps;
-        const int cb = j & 1;
-        T xn[VEC], bn[VEC], pn[VEC], on[VEC];
-        if (more) {
-            ldrow<T, VEC>(xn, src + g.row(y, z1 + 2) + off);
-            if (lo || hi) ldrow<T, VEC>(on, src + g.row(yo, z1 + 1) + off);
-            if constexpr (!FROMB) ldrow<T, VEC>(bn, b + g.row(y, z1 + 1) + off);
-            if constexpr (LDP) ldrow<T, VEC>(pn, xp + g.row(y, z1 + 1) + off);
-        }
-        // first step at z1
-        T ym[VEC], yp[VEC], M1[VEC], sp[VEC];
-        if (lo) copyrow(ym, o1);
-        else lds_ldrow<T, VEC>(ym, xs[cb][w - S], lane);
-        if (hi) copyrow(yp, o1);
-        else lds_ldrow<T, VEC>(yp, xs[cb][w + S], lane);
-        T hx = T(0);
-        if constexpr (S > 1) hx = lane < 32 ? xs[cb][wprev][NR - 1] : xs[cb][wnext][0];
-        if constexpr (FROMB) {
-            T fc[VEC], fm[VEC], fq[VEC], fym[VEC], fyp[VEC];
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                fc[e] = first_step<T, FROMB>(xc[e], cd0);
-                fm[e] = first_step<T, FROMB>(xm[e], cd0);
-                fq[e] = first_step<T, FROMB>(xq[e], cd0);
-                fym[e] = first_step<T, FROMB>(ym[e], cd0);
-                fyp[e] = first_step<T, FROMB>(yp[e], cd0);
-            }
-            flat7_row_seg<T, VEC, S>(fc, fym, fyp, fm, fq, ih2, M1, first_step<T, FROMB>(hx, cd0));
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) sp[e] = cheb_step<T>(fc[e], T(0), xc[e], M1[e], a1, cd1);
-        } else {
-            flat7_row_seg<T, VEC, S>(xc, ym, yp, xm, xq, ih2, M1, hx);
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                const T xpe = PREVB ? first_step<T, true>(b1[e], cd0) : PREV1 ? p1[e] : T(0);
-                sp[e] = cheb_step<T>(xc[e], xpe, b1[e], M1[e], a1, cd1);
-            }
-        }
-        if constexpr (Y1OUT) {
-            if (outw && j >= 1 && j <= NZC) strow<T, VEC>(y1o + g.row(y, z1) + off, sp);
-        }
-        // publish x at z1+1 (used by the next plane's first step) and the first step at z1-1
-        if (more) lds_strow<T, VEC>(xs[cb ^ 1][w], lane, xq);
-        if (j >= 2) lds_strow<T, VEC>(rows[cb][w], lane, sc);
-        __syncthreads();
-        if (j >= 2 && outw) {  // second step at z1-1
-            T nm[VEC], np[VEC], M2[VEC], o[VEC];
-            lds_ldrow<T, VEC>(nm, rows[cb][w - S], lane);
-            lds_ldrow<T, VEC>(np, rows[cb][w + S], lane);
-            T hs = T(0);
-            if constexpr (S > 1) hs = lane < 32 ? rows[cb][wprev][NR - 1] : rows[cb][wnext][0];
-            flat7_row_seg<T, VEC, S>(sc, nm, np, sm, sp, ih2, M2, hs);
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                if constexpr (FROMB)  // x_prev = first step at z2, b at z2 = the raw queue row
-                    o[e] = cheb_step<T>(sc[e], first_step<T, FROMB>(xm[e], cd0), xm[e], M2[e], a2, cd2);
-                else
-                    o[e] = cheb_step<T>(sc[e], xm[e], b2[e], M2[e], a2, cd2);
-            }
-            strow<T, VEC>(y2 + g.row(y, z1 - 1) + off, o);
-        }
-        copyrow(sm, sc);
-        copyrow(sc, sp);
-        if constexpr (!FROMB) copyrow(b2, b1);
-        if (more) {
-            copyrow(xm, xc);
-            copyrow(xc, xq);
-            copyrow(xq, xn);
-            if (lo || hi) copyrow(o1, on);
-            if constexpr (!FROMB) copyrow(b1, bn);
-            if constexpr (LDP) copyrow(p1, pn);
-        }
-    }
-}
-
 // The coarse rows the trilinear prolongation of fine row (y, z) reads (VEC >= 2):
 // (Y, Z), and (Y+1, Z), (Y, Z+1), (Y+1, Z+1) where y, z are odd; loaded raw so
 // that a prefetch is not waited for until the values are combined.
@@ -899,6 +761,243 @@ __device__ __forceinline__ void prolong_add(T (&xv)[VEC], const CoarseRows<T, VE
         for (int q = 0; q < CV; ++q) {
             xv[2 * q] = xv[2 * q] + w[q];
             xv[2 * q + 1] = xv[2 * q + 1] + T(0.5) * (w[q] + w[q + 1]);
+        }
+    }
+}
+
+// The coarse rows of fine row (y, z) for a row split into S segments of
+// 64 VEC points, one per wave (VEC >= 2): the segment's VEC / 2 coarse values
+// per lane of each row, and the first coarse value after the segment
+// (periodic), which lane 63 needs where an unsplit row takes it from the
+// next lane.
+template <typename T, int VEC>
+struct CoarseSeg {
+    CoarseRows<T, VEC> r;
+    T h00, h01, h10, h11;
+};
+template <typename T, int VEC>
+__device__ __forceinline__ void coarse_load_seg(CoarseSeg<T, VEC>& c, const T* e, const RowGrid& gc, int y, int z,
+                                                int seg, int lane) {
+    constexpr int CV = VEC / 2, NC = 32 * VEC;  // coarse values per lane and per segment
+    const int Y = y >> 1, Z = z >> 1, oy = y & 1, oz = z & 1;
+    const size_t off = (size_t)seg * NC + (size_t)lane * CV;
+    const int hx = ((seg + 1) * NC) & gc.mask;
+    const T* r0 = e + gc.row(Y, Z);
+    ldrow<T, CV>(c.r.t00, r0 + off);
+    c.h00 = r0[hx];
+    if (oy) {
+        const T* r1 = e + gc.row(Y + 1, Z);
+        ldrow<T, CV>(c.r.t01, r1 + off);
+        c.h01 = r1[hx];
+    }
+    if (oz) {
+        const T* r2 = e + gc.row(Y, Z + 1);
+        ldrow<T, CV>(c.r.t10, r2 + off);
+        c.h10 = r2[hx];
+    }
+    if (oy && oz) {
+        const T* r3 = e + gc.row(Y + 1, Z + 1);
+        ldrow<T, CV>(c.r.t11, r3 + off);
+        c.h11 = r3[hx];
+    }
+}
+// prolong_add for a segment: the same interpolation and rounding, with lane
+// 63's coarse value after the segment taken from the halo.
+template <typename T, int VEC>
+__device__ __forceinline__ void prolong_add_seg(T (&xv)[VEC], const CoarseSeg<T, VEC>& c, int y, int z) {
+#pragma clang fp contract(off)
+    static_assert(VEC >= 2, "two fine points per lane at least");
+    const int oy = y & 1, oz = z & 1;
+    const bool last = (threadIdx.x & 63) == 63;
+    constexpr int CV = VEC / 2, CW = CV + 1;
+    T w[CW];
+    auto seg = [&](const T (&t)[CV], T h, int q) {
+        if (q < CV) return t[q];
+        const T r = lane_rot(t[0], 1);
+        return last ? h : r;
+    };
+#pragma unroll
+    for (int q = 0; q < CW; ++q) {
+        const T r00 = seg(c.r.t00, c.h00, q);
+        T a0 = r00;
+        if (oy) a0 = T(0.5) * (r00 + seg(c.r.t01, c.h01, q));
+        if (oz) {
+            const T r10 = seg(c.r.t10, c.h10, q);
+            const T a1 = oy ? T(0.5) * (r10 + seg(c.r.t11, c.h11, q)) : r10;
+            a0 = T(0.5) * (a0 + a1);
+        }
+        w[q] = a0;
+    }
+#pragma unroll
+    for (int q = 0; q < CV; ++q) {
+        xv[2 * q] = xv[2 * q] + w[q];
+        xv[2 * q + 1] = xv[2 * q + 1] + T(0.5) * (w[q] + w[q + 1]);
+    }
+}
+
+// The same two steps with the x plane (FROMB: the b plane) shared through LDS
+// as well: every wave loads only its own row of x (b, x_prev) and publishes
+// it one plane ahead of its use, so the first step's y-neighbours (and, for
+// split rows, its x-halo) come from LDS instead of the caches; only the two
+// edge rows of the block load their outer neighbour row.  One barrier per
+// plane for both planes; same arithmetic and bits as k_smooth2_lds.
+// PRO: the pair starts a post-smoothing pass from x0 = x + P e (ec: the
+// coarse correction on the (n/2)^3 grid), formed row by row as the x rows
+// arrive and never written; the prolongation of k_prolong_row, same bits.
+template <typename T, int VEC, int NW, bool PREV1, bool Y1OUT, bool FROMB, int NZC, int S, bool PREVB = false,
+          bool PRO = false>
+__global__ __launch_bounds__(64 * NW) void k_smooth2x_lds(int n, T ih2, const T* __restrict__ x,
+                                                          const T* __restrict__ xp, const T* __restrict__ b,
+                                                          T* __restrict__ y2, T* __restrict__ y1o, T a1, T cd1,
+                                                          T a2, T cd2, int nyb, T cd0, SumsJob job,
+                                                          const T* __restrict__ ec) {
+    static_assert(!(FROMB && PREV1), "a pass from zero has no x_prev");
+    static_assert(!PREVB || PREV1, "PREVB forms x_prev from b");
+    static_assert(!PRO || (!FROMB && !PREV1 && VEC >= 2), "the prolongation starts a pass from x, x_prev = 0");
+    constexpr bool LDP = PREV1 && !PREVB;  // x_prev is loaded
+    static_assert(VEC * sizeof(T) <= 16, "plain LDS row layout");
+    static_assert(NW % S == 0 && NW / S >= 3, "a block holds whole rows, at least one output row");
+    constexpr int NR = 64 * VEC;
+    constexpr int R = NW / S;  // rows of the block
+    constexpr int W = R - 2;   // output rows
+    __shared__ T xs[2][NW][NR];    // x (FROMB: b) rows of a plane, one plane ahead
+    __shared__ T rows[2][NW][NR];  // first-step rows of a plane
+    const RowGrid g{NR * S, NR * S - 1};
+    const RowGrid gc{NR * S / 2, NR * S / 2 - 1};  // PRO: the coarse grid of ec
+    int nb = gridDim.x, bid = blockIdx.x;
+    if constexpr (FROMB || PREVB) {
+        if (job.count > 0) {  // block 0 finishes the sums, dispatched first
+            nb -= 1;
+            bid -= 1;
+            if (bid < 0) {
+                __shared__ double sh[kSumLanes];
+                finish_sums(job, sh);
+                return;
+            }
+        }
+    }
+    const int lb = xcd_logical(bid, nb);
+    const int yb = lb % nyb, zc = lb / nyb;
+    const int w = wave_id();
+    const int wr = w / S, seg = w - wr * S;
+    const int lane = threadIdx.x & 63;
+    const int y = yb * W - 1 + wr;  // rows outside [0, n) wrap for loads
+    const bool outw = wr >= 1 && wr <= W && y < n;
+    const bool lo = wr == 0, hi = wr == R - 1;
+    const int yo = lo ? y - 1 : y + 1;  // outer neighbour row of an edge row
+    const int z0 = zc * NZC;
+    const size_t off = (size_t)seg * NR + (size_t)lane * VEC;
+    const int wprev = wr * S + (seg + S - 1) % S, wnext = wr * S + (seg + 1) % S;
+    const T* src = FROMB ? b : x;
+    int z1 = z0 - 1;
+    // first step at z1: this row at z1-1, z1, z1+1, the outer row (edges) at z1, b and xp at z1
+    T xm[VEC], xc[VEC], xq[VEC], o1[VEC] = {}, b1[VEC], p1[VEC];
+    // second step at z2 = z1 - 1: first-step rows at z2-1, z2; b at z2; x_prev = xm
+    T sm[VEC] = {}, sc[VEC] = {}, b2[VEC] = {};
+    ldrow<T, VEC>(xm, src + g.row(y, z1 - 1) + off);
+    ldrow<T, VEC>(xc, src + g.row(y, z1) + off);
+    ldrow<T, VEC>(xq, src + g.row(y, z1 + 1) + off);
+    if (lo || hi) ldrow<T, VEC>(o1, src + g.row(yo, z1) + off);
+    if constexpr (!FROMB) ldrow<T, VEC>(b1, b + g.row(y, z1) + off);
+    if constexpr (LDP) ldrow<T, VEC>(p1, xp + g.row(y, z1) + off);
+    if constexpr (PRO) {  // x0 = x + P e on the rows loaded so far
+        CoarseSeg<T, VEC> c;
+        coarse_load_seg<T, VEC>(c, ec, gc, y, z1 - 1, seg, lane);
+        prolong_add_seg<T, VEC>(xm, c, y, z1 - 1);
+        coarse_load_seg<T, VEC>(c, ec, gc, y, z1, seg, lane);
+        prolong_add_seg<T, VEC>(xc, c, y, z1);
+        coarse_load_seg<T, VEC>(c, ec, gc, y, z1 + 1, seg, lane);
+        prolong_add_seg<T, VEC>(xq, c, y, z1 + 1);
+        if (lo || hi) {
+            coarse_load_seg<T, VEC>(c, ec, gc, yo, z1, seg, lane);
+            prolong_add_seg<T, VEC>(o1, c, yo, z1);
+        }
+    }
+    lds_strow<T, VEC>(xs[0][w], lane, xc);
+    __syncthreads();
+    constexpr int steps = NZC + 2;
+#pragma unroll
+    for (int j = 0; j < steps; ++j, ++z1) {
+        const bool more = j + 1 < steps;
+        const int cb = j & 1;
+        T xn[VEC], bn[VEC], pn[VEC], on[VEC];
+        CoarseSeg<T, VEC> cn, con;  // PRO: coarse rows of xn and on
+        if (more) {
+            ldrow<T, VEC>(xn, src + g.row(y, z1 + 2) + off);
+            if (lo || hi) ldrow<T, VEC>(on, src + g.row(yo, z1 + 1) + off);
+            if constexpr (PRO) {
+                coarse_load_seg<T, VEC>(cn, ec, gc, y, z1 + 2, seg, lane);
+                if (lo || hi) coarse_load_seg<T, VEC>(con, ec, gc, yo, z1 + 1, seg, lane);
+            }
+            if constexpr (!FROMB) ldrow<T, VEC>(bn, b + g.row(y, z1 + 1) + off);
+            if constexpr (LDP) ldrow<T, VEC>(pn, xp + g.row(y, z1 + 1) + off);
+        }
+        // first step at z1
+        T ym[VEC], yp[VEC], M1[VEC], sp[VEC];
+        if (lo) copyrow(ym, o1);
+        else lds_ldrow<T, VEC>(ym, xs[cb][w - S], lane);
+        if (hi) copyrow(yp, o1);
+        else lds_ldrow<T, VEC>(yp, xs[cb][w + S], lane);
+        T hx = T(0);
+        if constexpr (S > 1) hx = lane < 32 ? xs[cb][wprev][NR - 1] : xs[cb][wnext][0];
+        if constexpr (FROMB) {
+            T fc[VEC], fm[VEC], fq[VEC], fym[VEC], fyp[VEC];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                fc[e] = first_step<T, FROMB>(xc[e], cd0);
+                fm[e] = first_step<T, FROMB>(xm[e], cd0);
+                fq[e] = first_step<T, FROMB>(xq[e], cd0);
+                fym[e] = first_step<T, FROMB>(ym[e], cd0);
+                fyp[e] = first_step<T, FROMB>(yp[e], cd0);
+            }
+            flat7_row_seg<T, VEC, S>(fc, fym, fyp, fm, fq, ih2, M1, first_step<T, FROMB>(hx, cd0));
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) sp[e] = cheb_step<T>(fc[e], T(0), xc[e], M1[e], a1, cd1);
+        } else {
+            flat7_row_seg<T, VEC, S>(xc, ym, yp, xm, xq, ih2, M1, hx);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                const T xpe = PREVB ? first_step<T, true>(b1[e], cd0) : PREV1 ? p1[e] : T(0);
+                sp[e] = cheb_step<T>(xc[e], xpe, b1[e], M1[e], a1, cd1);
+            }
+        }
+        if constexpr (Y1OUT) {
+            if (outw && j >= 1 && j <= NZC) strow<T, VEC>(y1o + g.row(y, z1) + off, sp);
+        }
+        // publish x at z1+1 (used by the next plane's first step) and the first step at z1-1
+        if (more) lds_strow<T, VEC>(xs[cb ^ 1][w], lane, xq);
+        if (j >= 2) lds_strow<T, VEC>(rows[cb][w], lane, sc);
+        __syncthreads();
+        if (j >= 2 && outw) {  // second step at z1-1
+            T nm[VEC], np[VEC], M2[VEC], o[VEC];
+            lds_ldrow<T, VEC>(nm, rows[cb][w - S], lane);
+            lds_ldrow<T, VEC>(np, rows[cb][w + S], lane);
+            T hs = T(0);
+            if constexpr (S > 1) hs = lane < 32 ? rows[cb][wprev][NR - 1] : rows[cb][wnext][0];
+            flat7_row_seg<T, VEC, S>(sc, nm, np, sm, sp, ih2, M2, hs);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                if constexpr (FROMB)  // x_prev = first step at z2, b at z2 = the raw queue row
+                    o[e] = cheb_step<T>(sc[e], first_step<T, FROMB>(xm[e], cd0), xm[e], M2[e], a2, cd2);
+                else
+                    o[e] = cheb_step<T>(sc[e], xm[e], b2[e], M2[e], a2, cd2);
+            }
+            strow<T, VEC>(y2 + g.row(y, z1 - 1) + off, o);
+        }
+        copyrow(sm, sc);
+        copyrow(sc, sp);
+        if constexpr (!FROMB) copyrow(b2, b1);
+        if (more) {
+            if constexpr (PRO) {  // a whole iteration after their loads were issued
+                prolong_add_seg<T, VEC>(xn, cn, y, z1 + 2);
+                if (lo || hi) prolong_add_seg<T, VEC>(on, con, yo, z1 + 1);
+            }
+            copyrow(xm, xc);
+            copyrow(xc, xq);
+            copyrow(xq, xn);
+            if (lo || hi) copyrow(o1, on);
+            if constexpr (!FROMB) copyrow(b1, bn);
+            if constexpr (LDP) copyrow(p1, pn);
         }
     }
 }
@@ -1663,13 +1762,19 @@ inline int pair_segments(int n, size_t elem) {
     return row > kPairSegBytes ? (int)(row / kPairSegBytes) : 1;
 }
 
-#define MG_PAIRS(PREV1, Y1OUT, FROMB, PF2, PREVB)                                                                  \
+// The prolongation runs fused into the first pair of a post-smoothing pass on
+// split rows (512^3 float, 256^3 double).
+bool pair_pro_applies(int n, size_t elem) {
+    return kPairXLds && pair_kernels_apply(n, elem) && pair_segments(n, elem) == 2;
+}
+
+#define MG_PAIRS(PREV1, Y1OUT, FROMB, PF2, PREVB, PRO)                                                             \
     do {                                                                                                         \
         constexpr bool JOB = FROMB || PREVB;                                                                     \
         if constexpr (kPairXLds)                                                                                 \
-            MG_LAUNCH((k_smooth2x_lds<T, VEC, NW, PREV1, Y1OUT, FROMB, kPairSegNz, S, PREVB>),                   \
+            MG_LAUNCH((k_smooth2x_lds<T, VEC, NW, PREV1, Y1OUT, FROMB, kPairSegNz, S, PREVB, PRO>),              \
                       dim3(blocks + (JOB ? extra : 0)), dim3(64 * NW), s, ev0, ev1, n, (T)ih2, x, xp, b, y2, y1,   \
-                      (T)a1, (T)cd1, (T)a2, (T)cd2, nyb, (T)cd0, JOB ? sums : SumsJob{});                        \
+                      (T)a1, (T)cd1, (T)a2, (T)cd2, nyb, (T)cd0, JOB ? sums : SumsJob{}, ec);                    \
         else                                                                                                     \
             MG_LAUNCH((k_smooth2_lds<T, VEC, NW, PREV1, Y1OUT, FROMB, PF2, kPairSegNz, S, PREVB>),               \
                       dim3(blocks + (JOB ? extra : 0)), dim3(64 * NW), s, ev0, ev1, n, (T)ih2, x, xp, b, y2, y1,   \
@@ -1678,7 +1783,7 @@ inline int pair_segments(int n, size_t elem) {
 template <typename T, int NW, int S>
 hipError_t launch_pair_seg(int n, double ih2, const T* x, const T* xp, const T* b, T* y2, T* y1, double a1,
                            double cd1, double a2, double cd2, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
-                           int x0_mode, double cd0, const SumsJob& sums) {
+                           int x0_mode, double cd0, const SumsJob& sums, const T* ec) {
     constexpr int W = NW / S - 2;
     const int extra = sums.count > 0 ? 1 : 0;  // the block that finishes the sums (pass from zero only)
     const int nyb = (n + W - 1) / W;
@@ -1688,19 +1793,26 @@ hipError_t launch_pair_seg(int n, double ih2, const T* x, const T* xp, const T* 
     auto go = [&](auto vtag) -> hipError_t {
         constexpr int VEC = decltype(vtag)::value;
         if constexpr (VEC * sizeof(T) <= 16 && 2ull * NW * 64 * VEC * sizeof(T) <= kPairLdsBudget) {
-            if (x0_mode == 2) {
-                MG_PAIRS(true, false, false, false, true);
+            if (ec != nullptr) {
+                if constexpr (VEC >= 2) {
+                    if (y1 == nullptr) MG_PAIRS(false, false, false, false, false, true);
+                    else MG_PAIRS(false, true, false, false, false, true);
+                } else {
+                    return hipErrorInvalidValue;
+                }
+            } else if (x0_mode == 2) {
+                MG_PAIRS(true, false, false, false, true, false);
             } else if (x0_mode != 0) {
-                if (y1 == nullptr) MG_PAIRS(false, false, true, true, false);
-                else MG_PAIRS(false, true, true, true, false);
+                if (y1 == nullptr) MG_PAIRS(false, false, true, true, false, false);
+                else MG_PAIRS(false, true, true, true, false, false);
             } else if (xp == nullptr && y1 == nullptr) {
-                MG_PAIRS(false, false, false, false, false);
+                MG_PAIRS(false, false, false, false, false, false);
             } else if (xp == nullptr) {
-                MG_PAIRS(false, true, false, false, false);
+                MG_PAIRS(false, true, false, false, false, false);
             } else if (y1 == nullptr) {
-                MG_PAIRS(true, false, false, false, false);
+                MG_PAIRS(true, false, false, false, false, false);
             } else {
-                MG_PAIRS(true, true, false, false, false);
+                MG_PAIRS(true, true, false, false, false, false);
             }
             return hipGetLastError();
         }
@@ -1717,8 +1829,10 @@ hipError_t launch_pair_seg(int n, double ih2, const T* x, const T* xp, const T* 
 template <typename T>
 hipError_t launch_smooth_pair_row(int n, double ih2, const T* x, const T* xp, const T* b, T* y2, T* y1,
                                   double a1, double cd1, double a2, double cd2, hipStream_t s, hipEvent_t ev0,
-                                  hipEvent_t ev1, int x0_mode, double cd0, const SumsJob* sums_job) {
+                                  hipEvent_t ev1, int x0_mode, double cd0, const SumsJob* sums_job, const T* ec) {
     if (!pair_kernels_apply(n, sizeof(T))) return hipErrorInvalidValue;
+    if (ec != nullptr && (!pair_pro_applies(n, sizeof(T)) || x0_mode != 0 || xp != nullptr || x == nullptr))
+        return hipErrorInvalidValue;
     const SumsJob sums = sums_job ? *sums_job : SumsJob{};
     if (x0_mode < 0 || x0_mode > 2) return hipErrorInvalidValue;
     if (sums.count > 0 && x0_mode == 0) return hipErrorInvalidValue;
@@ -1729,7 +1843,7 @@ hipError_t launch_smooth_pair_row(int n, double ih2, const T* x, const T* xp, co
         case 1: break;
         case 2:
             return launch_pair_seg<T, kPairSegWaves, 2>(n, ih2, x, xp, b, y2, y1, a1, cd1, a2, cd2, s, ev0, ev1,
-                                                        x0_mode, cd0, sums);
+                                                        x0_mode, cd0, sums, ec);
         default: return hipErrorInvalidValue;
     }
     int waves = kPairWavesDefault;
@@ -1944,10 +2058,10 @@ template hipError_t launch_smooth_fromb_row<double>(int, double, const double*, 
                                                     hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_smooth_pair_row<float>(int, double, const float*, const float*, const float*, float*,
                                                   float*, double, double, double, double, hipStream_t, hipEvent_t,
-                                                  hipEvent_t, int, double, const SumsJob*);
+                                                  hipEvent_t, int, double, const SumsJob*, const float*);
 template hipError_t launch_smooth_pair_row<double>(int, double, const double*, const double*, const double*,
                                                    double*, double*, double, double, double, double, hipStream_t,
-                                                   hipEvent_t, hipEvent_t, int, double, const SumsJob*);
+                                                   hipEvent_t, hipEvent_t, int, double, const SumsJob*, const double*);
 template hipError_t launch_rr_row<float>(int, double, const float*, const float*, float*, hipStream_t, hipEvent_t,
                                          hipEvent_t);
 template hipError_t launch_rr_row<double>(int, double, const double*, const double*, double*, hipStream_t, hipEvent_t,

@@ -342,6 +342,15 @@ inline bool post_fused(const mg_ctx* c, int l, size_t elem) {
            triple_pro_applies(L.n, elem);
 }
 
+// Level l's post-smoothing pass (Chebyshev, an even number of steps) starts
+// with a pair that forms x + P e itself: split rows, where the three-step
+// kernels do not run.
+inline bool post_pair_fused(const mg_ctx* c, int l, size_t elem) {
+    const Level& L = c->lev[l];
+    return c->p.smoother == MG_CHEBYSHEV && L.a.size() % 2 == 0 && c->use_pairs && !c->var &&
+           L.x[2] != nullptr && pair_pro_applies(L.n, elem);
+}
+
 // Level l runs its pass from zero as one three-step kernel (first step formed
 // from b on the fly): seven-point operator, two-step kernels available, and
 // at least three steps per pass.
@@ -349,8 +358,10 @@ inline bool from_zero_triple(const mg_ctx* c, int l) {
     return c->use_pairs && !c->var && c->lev[l].x[2] != nullptr && c->lev[l].a.size() >= 3;
 }
 
+// pro_e (not from zero): the pass starts from x + P pro_e, formed by its
+// first kernel (a pair on split rows), instead of a prolongation launch.
 template <typename T>
-mg_status smooth_level(mg_ctx* c, int l, bool from_zero) {
+mg_status smooth_level(mg_ctx* c, int l, bool from_zero, const T* pro_e = nullptr) {
     Level& L = c->lev[l];
     const OpDesc<T> op = op_of<T>(L);
     int cur = L.cur;
@@ -389,6 +400,7 @@ mg_status smooth_level(mg_ctx* c, int l, bool from_zero) {
         const bool triple3 = k == 0 && !from_zero && cheb && v == 3 && c->use_pairs && !c->var &&
                              triple_kernels_apply(L.n, sizeof(T));
         const bool pair = pairs && rem >= 2 && rem % 2 == 0 && !(k == 0 && from_zero) && !(need_y1 && has_prev);
+        if (k == 0 && pro_e != nullptr && !pair) return MG_ERR_INVALID;  // the caller checked that a pair starts
         const int kind = triple3 ? MG_TIME_TRIPLE : (pair || triple) && !fromb ? MG_TIME_PAIR : MG_TIME_STEP;
         hipEvent_t ev0, ev1;
         mg_status st = time_events(c, fine, kind, &ev0, &ev1);
@@ -449,17 +461,19 @@ mg_status smooth_level(mg_ctx* c, int l, bool from_zero) {
             const double D = -6.0 * L.ih2;  // c / D rounded as in the single-step launch
             // after a step from b, level 0 finishes the pending outer sums here
             const bool sums = prev_b && l == 0 && c->pending_sums;
+            const T* ec = k == 0 ? pro_e : nullptr;  // x0 = x + P e formed by this pair
             const SumsJob job{c->partials, c->nparts_outer, 3, c->dscal, 1, c->hscal, sums ? c->sums_seq + 1.0 : 0.0};
             HIPCHK(c, launch_smooth_pair_row<T>(L.n, L.ih2, bufs[cur], xp, (const T*)L.b, bufs[out],
                                                 mid >= 0 ? bufs[mid] : nullptr, L.a[k], L.c[k] / D, L.a[k + 1],
                                                 L.c[k + 1] / D, c->stream, ev0, ev1, prev_b ? 2 : 0, L.c[0] / D,
-                                                sums ? &job : nullptr));
+                                                sums ? &job : nullptr, ec));
             if (sums) {
                 c->sums_seq += 1.0;
                 c->scal_flag = true;
                 c->pending_sums = false;
             }
-            bytes = (3.0 + (xp ? 1.0 : 0.0) + (mid >= 0 ? 1.0 : 0.0)) * fbytes;  // x, [x_prev], b; y2, [y1]
+            // x, [x_prev], b; y2, [y1]; [e once per coarse point]
+            bytes = (3.0 + (xp ? 1.0 : 0.0) + (mid >= 0 ? 1.0 : 0.0) + (ec ? 1.0 / 8.0 : 0.0)) * fbytes;
             prev_b = false;
             prev = mid;
             cur = out;
@@ -570,6 +584,8 @@ mg_status post_level(mg_ctx* c, int l) {
         // x, b read, x_3 written, e read once per coarse point
         return time_end(c, fine, MG_TIME_TRIPLE, (3.0 + 1.0 / 8.0) * (double)L.N * sizeof(T));
     }
+    if (post_pair_fused(c, l, sizeof(T)))  // the prolongation runs inside the pass's first pair
+        return smooth_level<T>(c, l, false, (const T*)Lc.x[Lc.cur]);
     if ((st = time_events(c, fine, MG_TIME_TRANSFER, &ev0, &ev1)) != MG_OK) return st;
     HIPCHK(c, launch_prolong_add<T>(L.n, (const T*)Lc.x[Lc.cur], (T*)L.x[L.cur], c->stream, ev0, ev1));
     if ((st = time_end(c, fine, MG_TIME_TRANSFER, (2.0 + 1.0 / 8.0) * (double)L.N * sizeof(T))) != MG_OK) return st;
