@@ -17,10 +17,15 @@ hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, cons
                              double cd, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // Step 1 of a pass from zero read from b alone: out = x1 + a1 x1 + cd1 (b - M x1)
 // with x1 = cd0 * b formed on the fly in T (the bits of a single step from
-// zero followed by a single step).  Rows of at most 2 KB; out must differ from b.
+// zero followed by a single step).  out must differ from b.
 template <typename T>
 hipError_t launch_smooth_fromb_row(int n, double ih2, const T* b, T* out, double a1, double cd1, double cd0,
                                    hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// Step 2 of that pass: out = x + a2 (x - x1) + cd2 (b - M x) with x_prev
+// x1 = cd0 * b formed from the b rows (not read).  out must differ from x and b.
+template <typename T>
+hipError_t launch_smooth_prevb_row(int n, double ih2, const T* x, const T* b, T* out, double a2, double cd2,
+                                   double cd0, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // Two consecutive smoothing steps in one pass (y2 and optionally y1 written;
 // xp may be nullptr for x_prev = 0).  y2 and y1 must not alias x, xp or b.
 // x0_mode == 1: the first three steps of a pass from zero instead; x and xp

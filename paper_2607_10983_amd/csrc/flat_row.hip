@@ -146,13 +146,16 @@ __device__ __forceinline__ T first_step(T r, T cd0) {
 // ends come from one halo element loaded with each centre row.
 // FROMB: the second step of a pass from zero, read from b alone: x holds the b
 // rows, the iterate is the pointwise first step cd0 b formed from them, and
-// x_prev = 0.
-template <typename T, int VEC, bool HASX, bool PREV, int S = 1, bool FROMB = false>
+// x_prev = 0.  PREVB: the third step of such a pass, whose x_prev is that
+// pointwise first step, formed from the b row instead of being read.
+template <typename T, int VEC, bool HASX, bool PREV, int S = 1, bool FROMB = false, bool PREVB = false>
 __global__ __launch_bounds__(kBlock) void k_smooth_row(int n, T ih2, const T* x, const T* xprev,
                                                        const T* __restrict__ b, T* out, T a, T cd, int nz,
                                                        int nyb, T cd0) {
     static_assert(kWaves % S == 0, "a block holds whole rows");
-    static_assert(!FROMB || (HASX && !PREV && S == 1), "a step from b has no x_prev and whole rows");
+    static_assert(!FROMB || (HASX && !PREV), "a step from b has no x_prev");
+    static_assert(!PREVB || (HASX && PREV && !FROMB), "PREVB forms x_prev from b");
+    constexpr bool LDP = PREV && !PREVB;  // x_prev is loaded
     constexpr int NR = 64 * VEC;
     const RowGrid g{NR * S, NR * S - 1};
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
@@ -186,7 +189,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_row(int n, T ih2, const T* x,
         ldrow<T, VEC>(ym, x + g.row(y - 1, z0) + off);
         ldrow<T, VEC>(yp, x + g.row(y + 1, z0) + off);
         if constexpr (!FROMB) ldrow<T, VEC>(bb, b + g.row(y, z0) + off);
-        if constexpr (PREV) ldrow<T, VEC>(pp, xprev + g.row(y, z0) + off);
+        if constexpr (LDP) ldrow<T, VEC>(pp, xprev + g.row(y, z0) + off);
         for (int k = 0; k < nz; ++k) {
             const int z = z0 + k;
             // prefetch the next plane's operands before any store of this plane
@@ -199,7 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_row(int n, T ih2, const T* x,
                 ldrow<T, VEC>(ymn, x + g.row(y - 1, z + 1) + off);
                 ldrow<T, VEC>(ypn, x + g.row(y + 1, z + 1) + off);
                 if constexpr (!FROMB) ldrow<T, VEC>(bn, b + g.row(y, z + 1) + off);
-                if constexpr (PREV) ldrow<T, VEC>(pn, xprev + g.row(y, z + 1) + off);
+                if constexpr (LDP) ldrow<T, VEC>(pn, xprev + g.row(y, z + 1) + off);
             }
             T Mx[VEC], o[VEC];
             if constexpr (FROMB) {  // x = cd0 b on the row and its neighbours; b = the raw centre row
@@ -212,13 +215,16 @@ __global__ __launch_bounds__(kBlock) void k_smooth_row(int n, T ih2, const T* x,
                     fzm[e] = first_step<T, true>(zm[e], cd0);
                     fzp[e] = first_step<T, true>(zp[e], cd0);
                 }
-                flat7_row<T, VEC>(fc, fym, fyp, fzm, fzp, ih2, Mx);
+                flat7_row_seg<T, VEC, S>(fc, fym, fyp, fzm, fzp, ih2, Mx, first_step<T, true>(hc, cd0));
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) o[e] = cheb_step<T>(fc[e], T(0), c[e], Mx[e], a, cd);
             } else {
                 flat7_row_seg<T, VEC, S>(c, ym, yp, zm, zp, ih2, Mx, hc);
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) o[e] = cheb_step<T>(c[e], PREV ? pp[e] : T(0), bb[e], Mx[e], a, cd);
+                for (int e = 0; e < VEC; ++e) {
+                    const T xpe = PREVB ? first_step<T, true>(bb[e], cd0) : PREV ? pp[e] : T(0);
+                    o[e] = cheb_step<T>(c[e], xpe, bb[e], Mx[e], a, cd);
+                }
             }
             strow<T, VEC>(out + g.row(y, z) + off, o);
             if (more) {
@@ -230,7 +236,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_row(int n, T ih2, const T* x,
                 copyrow(ym, ymn);
                 copyrow(yp, ypn);
                 if constexpr (!FROMB) copyrow(bb, bn);
-                if constexpr (PREV) copyrow(pp, pn);
+                if constexpr (LDP) copyrow(pp, pn);
             }
         }
     }
@@ -397,11 +403,13 @@ __global__ __launch_bounds__(kBlock) void k_outer_row(int n, TA ih2, const doubl
 // so the y-neighbour rows come from LDS instead of L2/HBM.  Used where the
 // 2 (W + 2) rows fit in 80 KB of LDS.
 // =====================================================================================
-template <typename T, int VEC, int W, bool PREV, bool FROMB = false>
+template <typename T, int VEC, int W, bool PREV, bool FROMB = false, bool PREVB = false>
 __global__ __launch_bounds__(64 * W) void k_smooth_lds(int n, T ih2, const T* x, const T* xprev,
                                                        const T* __restrict__ b, T* out, T a, T cd, int nz,
                                                        int nyb, T cd0) {
     static_assert(!(FROMB && PREV), "a step from b has no x_prev");
+    static_assert(!PREVB || (PREV && !FROMB), "PREVB forms x_prev from b");
+    constexpr bool LDP = PREV && !PREVB;  // x_prev is loaded
     constexpr int NR = 64 * VEC;
     __shared__ T rows[2][W + 2][NR];
     const RowGrid g{64 * VEC, 64 * VEC - 1};
@@ -420,7 +428,7 @@ __global__ __launch_bounds__(64 * W) void k_smooth_lds(int n, T ih2, const T* x,
     ldrow<T, VEC>(c, x + g.row(y, z0) + off);
     ldrow<T, VEC>(zp, x + g.row(y, z0 + 1) + off);
     if constexpr (!FROMB) ldrow<T, VEC>(bb, b + g.row(y, z0) + off);
-    if constexpr (PREV) ldrow<T, VEC>(pp, xprev + g.row(y, z0) + off);
+    if constexpr (LDP) ldrow<T, VEC>(pp, xprev + g.row(y, z0) + off);
     if (lo || hi) ldrow<T, VEC>(h, x + g.row(yh, z0) + off);
     for (int k = 0; k < nz; ++k) {
         const int z = z0 + k;
@@ -430,7 +438,7 @@ __global__ __launch_bounds__(64 * W) void k_smooth_lds(int n, T ih2, const T* x,
         if (more) {
             ldrow<T, VEC>(zpp, x + g.row(y, z + 2) + off);
             if constexpr (!FROMB) ldrow<T, VEC>(bn, b + g.row(y, z + 1) + off);
-            if constexpr (PREV) ldrow<T, VEC>(pn, xprev + g.row(y, z + 1) + off);
+            if constexpr (LDP) ldrow<T, VEC>(pn, xprev + g.row(y, z + 1) + off);
             if (lo || hi) ldrow<T, VEC>(hn, x + g.row(yh, z + 1) + off);
         }
         lds_strow<T, VEC>(rows[buf][w + 1], lane, c);
@@ -457,7 +465,10 @@ __global__ __launch_bounds__(64 * W) void k_smooth_lds(int n, T ih2, const T* x,
         } else {
             flat7_row<T, VEC>(c, ym, yp, zm, zp, ih2, Mx);
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) o[e] = cheb_step<T>(c[e], PREV ? pp[e] : T(0), bb[e], Mx[e], a, cd);
+            for (int e = 0; e < VEC; ++e) {
+                const T xpe = PREVB ? first_step<T, true>(bb[e], cd0) : PREV ? pp[e] : T(0);
+                o[e] = cheb_step<T>(c[e], xpe, bb[e], Mx[e], a, cd);
+            }
         }
         strow<T, VEC>(out + g.row(y, z) + off, o);
         if (more) {
@@ -465,7 +476,7 @@ __global__ __launch_bounds__(64 * W) void k_smooth_lds(int n, T ih2, const T* x,
             copyrow(c, zp);
             copyrow(zp, zpp);
             if constexpr (!FROMB) copyrow(bb, bn);
-            if constexpr (PREV) copyrow(pp, pn);
+            if constexpr (LDP) copyrow(pp, pn);
             if (lo || hi) copyrow(h, hn);
         }
     }
@@ -1573,9 +1584,15 @@ int row_outer_blocks(int n, bool double_arith) {
         default: return hipErrorInvalidValue;                 \
     }
 
-template <typename T>
-hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, const T* b, T* out, double a,
-                             double cd, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+// Single smoothing step, in one of three modes: MODE_PLAIN (x, [x_prev], b),
+// MODE_FROMB (step 1 of a pass from zero, from b alone: the iterate is the
+// pointwise first step cd0 b, x_prev = 0) and MODE_PREVB (step 2 of such a
+// pass: x_prev is cd0 b, formed from the b rows).
+enum StepMode { MODE_PLAIN, MODE_FROMB, MODE_PREVB };
+template <typename T, int MODE>
+hipError_t launch_step_mode(int n, double ih2, const T* x, const T* xprev, const T* b, T* out, double a, double cd,
+                            double cd0, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    constexpr bool FB = MODE == MODE_FROMB, PB = MODE == MODE_PREVB;
     int nz, nyb, blocks;
     // Row sharing through LDS pays where the level's fields exceed the 256 MB
     // Infinity Cache (n >= 512); below that the y-halo rows already hit in
@@ -1588,12 +1605,12 @@ hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, cons
         blocks = nyb * (n / nz);
         DISPATCH_VEC(n, {
             if constexpr (2ull * (Wv + 2) * 64 * VEC * sizeof(T) <= kLdsBudget) {
-                if (xprev == nullptr)
-                    MG_LAUNCH((k_smooth_lds<T, VEC, Wv, false>), dim3(blocks), dim3(64 * Wv), s, ev0, ev1, n,
-                                       (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb, (T)0);
-                else
-                    MG_LAUNCH((k_smooth_lds<T, VEC, Wv, true>), dim3(blocks), dim3(64 * Wv), s, ev0, ev1, n,
-                                       (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb, (T)0);
+                if (xprev == nullptr && !PB)
+                    MG_LAUNCH((k_smooth_lds<T, VEC, Wv, false, FB>), dim3(blocks), dim3(64 * Wv), s, ev0, ev1, n,
+                              (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb, (T)cd0);
+                else if constexpr (!FB)
+                    MG_LAUNCH((k_smooth_lds<T, VEC, Wv, true, false, PB>), dim3(blocks), dim3(64 * Wv), s, ev0,
+                              ev1, n, (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb, (T)cd0);
             }
         })
         return hipGetLastError();
@@ -1601,14 +1618,14 @@ hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, cons
     const int S = x != nullptr ? row_segments(n, sizeof(T)) : 1;
     if (S > 1) {
         shape(n * S, n, 4, nz, nyb, blocks);
-#define MG_SMOOTH_SEG(SS)                                                                                            \
-    DISPATCH_SEG(n, SS, {                                                                                            \
-        if (xprev == nullptr)                                                                                        \
-            MG_LAUNCH((k_smooth_row<T, VEC, true, false, SS>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (T)ih2, x, \
-                      xprev, b, out, (T)a, (T)cd, nz, nyb, (T)0);                                                     \
-        else                                                                                                         \
-            MG_LAUNCH((k_smooth_row<T, VEC, true, true, SS>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (T)ih2, x,  \
-                      xprev, b, out, (T)a, (T)cd, nz, nyb, (T)0);                                                     \
+#define MG_SMOOTH_SEG(SS)                                                                                       \
+    DISPATCH_SEG(n, SS, {                                                                                       \
+        if (xprev == nullptr && !PB)                                                                            \
+            MG_LAUNCH((k_smooth_row<T, VEC, true, false, SS, FB>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n,  \
+                      (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb, (T)cd0);                                  \
+        else if constexpr (!FB)                                                                                 \
+            MG_LAUNCH((k_smooth_row<T, VEC, true, true, SS, false, PB>), dim3(blocks), dim3(kBlock), s, ev0,   \
+                      ev1, n, (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb, (T)cd0);                          \
     })
         switch (S) {
             case 2: MG_SMOOTH_SEG(2); break;
@@ -1620,46 +1637,39 @@ hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, cons
     }
     shape(n, n, 4, nz, nyb, blocks);
     DISPATCH_VEC(n, {
-        if (x == nullptr)
-            MG_LAUNCH((k_smooth_row<T, VEC, false, false>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (T)ih2, x,
-                               xprev, b, out, (T)a, (T)cd, nz, nyb, (T)0);
-        else if (xprev == nullptr)
-            MG_LAUNCH((k_smooth_row<T, VEC, true, false>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (T)ih2, x,
-                               xprev, b, out, (T)a, (T)cd, nz, nyb, (T)0);
-        else
-            MG_LAUNCH((k_smooth_row<T, VEC, true, true>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (T)ih2, x,
-                               xprev, b, out, (T)a, (T)cd, nz, nyb, (T)0);
+        if (x == nullptr) {
+            if constexpr (MODE == MODE_PLAIN)
+                MG_LAUNCH((k_smooth_row<T, VEC, false, false>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (T)ih2,
+                          x, xprev, b, out, (T)a, (T)cd, nz, nyb, (T)cd0);
+        } else if (xprev == nullptr && !PB) {
+            MG_LAUNCH((k_smooth_row<T, VEC, true, false, 1, FB>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n,
+                      (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb, (T)cd0);
+        } else if constexpr (!FB) {
+            MG_LAUNCH((k_smooth_row<T, VEC, true, true, 1, false, PB>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n,
+                      (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb, (T)cd0);
+        }
     })
     return hipGetLastError();
 }
 
-// The second step of a pass from zero from b alone (x_prev = 0, the iterate
-// x1 = cd0 b formed on the fly): out = x1 + a1 x1 + cd1 (b - M x1), in the
-// rounding of the single steps.  Whole rows only (rows of at most 2 KB).
+template <typename T>
+hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, const T* b, T* out, double a,
+                             double cd, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    return launch_step_mode<T, MODE_PLAIN>(n, ih2, x, xprev, b, out, a, cd, 0.0, s, ev0, ev1);
+}
+
 template <typename T>
 hipError_t launch_smooth_fromb_row(int n, double ih2, const T* b, T* out, double a1, double cd1, double cd0,
                                    hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-    if (row_segments(n, sizeof(T)) != 1) return hipErrorInvalidValue;
-    int nz, nyb, blocks;
-    if (n >= 512 && lds_rows_fit<T>(n)) {  // the launch shape of the single step
-        constexpr int Wv = kLdsWaves;
-        nyb = n / Wv;
-        nz = n;
-        while (nz > 4 && nyb * (n / nz) < 2048) nz >>= 1;
-        blocks = nyb * (n / nz);
-        DISPATCH_VEC(n, {
-            if constexpr (2ull * (Wv + 2) * 64 * VEC * sizeof(T) <= kLdsBudget)
-                MG_LAUNCH((k_smooth_lds<T, VEC, Wv, false, true>), dim3(blocks), dim3(64 * Wv), s, ev0, ev1, n,
-                          (T)ih2, b, nullptr, b, out, (T)a1, (T)cd1, nz, nyb, (T)cd0);
-        })
-        return hipGetLastError();
-    }
-    shape(n, n, 4, nz, nyb, blocks);
-    DISPATCH_VEC(n, {
-        MG_LAUNCH((k_smooth_row<T, VEC, true, false, 1, true>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, (T)ih2,
-                  b, nullptr, b, out, (T)a1, (T)cd1, nz, nyb, (T)cd0);
-    })
-    return hipGetLastError();
+    if (b == nullptr || out == b) return hipErrorInvalidValue;
+    return launch_step_mode<T, MODE_FROMB>(n, ih2, b, nullptr, b, out, a1, cd1, cd0, s, ev0, ev1);
+}
+
+template <typename T>
+hipError_t launch_smooth_prevb_row(int n, double ih2, const T* x, const T* b, T* out, double a2, double cd2,
+                                   double cd0, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (x == nullptr || b == nullptr || out == x || out == b) return hipErrorInvalidValue;
+    return launch_step_mode<T, MODE_PREVB>(n, ih2, x, nullptr, b, out, a2, cd2, cd0, s, ev0, ev1);
 }
 
 // Waves per block of the two-step kernel (W = waves - 2 output rows): 8
@@ -2056,6 +2066,10 @@ template hipError_t launch_smooth_fromb_row<float>(int, double, const float*, fl
                                                    hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_smooth_fromb_row<double>(int, double, const double*, double*, double, double, double,
                                                     hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_smooth_prevb_row<float>(int, double, const float*, const float*, float*, double, double,
+                                                   double, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_smooth_prevb_row<double>(int, double, const double*, const double*, double*, double,
+                                                    double, double, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_smooth_pair_row<float>(int, double, const float*, const float*, const float*, float*,
                                                   float*, double, double, double, double, hipStream_t, hipEvent_t,
                                                   hipEvent_t, int, double, const SumsJob*, const float*);

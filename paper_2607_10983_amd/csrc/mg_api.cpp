@@ -360,6 +360,16 @@ inline bool from_zero_triple(const mg_ctx* c, int l) {
 
 // pro_e (not from zero): the pass starts from x + P pro_e, formed by its
 // first kernel (a pair on split rows), instead of a prolongation launch.
+// Level l without two-step kernels (rows over 2 KB) starts a pass from zero
+// of at least three Chebyshev steps with one step read from b alone and one
+// step whose x_prev (the pointwise first step) is formed from b, so the
+// first step is never written.
+inline bool from_zero_stepb(const mg_ctx* c, int l) {
+    const Level& L = c->lev[l];
+    return c->use_pairs && !c->var && c->p.smoother == MG_CHEBYSHEV && L.a.size() >= 3 && L.x[2] == nullptr &&
+           row_kernels_apply(L.n) && l + 1 < (int)c->lev.size() && l != c->tail_start && !visit_level(c, l);
+}
+
 template <typename T>
 mg_status smooth_level(mg_ctx* c, int l, bool from_zero, const T* pro_e = nullptr) {
     Level& L = c->lev[l];
@@ -396,6 +406,7 @@ mg_status smooth_level(mg_ctx* c, int l, bool from_zero, const T* pro_e = nullpt
         // kernel (b -> x_3, x_2) and step 3 on its own
         const bool fromb = k == 0 && from_zero && cheb && v == 4 && from_zero_triple(c, l);
         const bool triple = k == 0 && from_zero && from_zero_triple(c, l) && !fromb;
+        const bool stepb = k == 0 && from_zero && from_zero_stepb(c, l);
         // a pass of three steps that does not start from zero: one three-step kernel
         const bool triple3 = k == 0 && !from_zero && cheb && v == 3 && c->use_pairs && !c->var &&
                              triple_kernels_apply(L.n, sizeof(T));
@@ -405,7 +416,25 @@ mg_status smooth_level(mg_ctx* c, int l, bool from_zero, const T* pro_e = nullpt
         hipEvent_t ev0, ev1;
         mg_status st = time_events(c, fine, kind, &ev0, &ev1);
         if (st != MG_OK) return st;
-        if (fromb) {
+        if (stepb) {  // steps 0 and 1 from b alone (b -> x_2); the next step forms x_prev from b
+            const double D = -6.0 * L.ih2;
+            HIPCHK(c, launch_smooth_fromb_row<T>(L.n, L.ih2, (const T*)L.b, bufs[0], L.a[1], L.c[1] / D,
+                                                 L.c[0] / D, c->stream, ev0, ev1));
+            bytes = 2.0 * fbytes;  // b; x_2
+            prev = -1;
+            prev_b = true;
+            cur = 0;
+            k = 1;
+        } else if (prev_b && !pair) {  // x_prev = c0 D^-1 b, formed from the b rows
+            const double D = -6.0 * L.ih2;
+            const int out = other(cur);
+            HIPCHK(c, launch_smooth_prevb_row<T>(L.n, L.ih2, bufs[cur], (const T*)L.b, bufs[out], L.a[k],
+                                                 L.c[k] / D, L.c[0] / D, c->stream, ev0, ev1));
+            bytes = 3.0 * fbytes;  // x, b; out
+            prev_b = false;
+            prev = cur;
+            cur = out;
+        } else if (fromb) {
             const int out = 1;
             const double D = -6.0 * L.ih2;
             HIPCHK(c, launch_smooth_fromb_row<T>(L.n, L.ih2, (const T*)L.b, bufs[out], L.a[1], L.c[1] / D,
@@ -665,7 +694,8 @@ mg_status outer_residual(mg_ctx* c, const double* phi_in, const void* e, double*
     Level& L = c->lev[0];
     const int n = L.n;
     const double ih2 = L.ih2;
-    const bool x1 = next_cycle && x1_fusable(c) && !from_zero_triple(c, 0) && !visit_level(c, 0);
+    const bool x1 = next_cycle && x1_fusable(c) && !from_zero_triple(c, 0) && !from_zero_stepb(c, 0) &&
+                    !visit_level(c, 0);
     const double c0 = L.c.empty() ? 0.0 : L.c[0];
     // x1 goes to a buffer other than the one holding e (the previous cycle's result)
     const int xb = other(L.cur);

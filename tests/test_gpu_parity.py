@@ -455,15 +455,18 @@ def test_graph_replay_matches_eager(mgpu, var):
         assert torch.equal(pe, pg)
 
 
-@pytest.mark.parametrize("n,prec", [(64, "mixed"), (128, "fp64"), (256, "mixed"), (256, "fp64"), (512, "mixed")])
+@pytest.mark.parametrize("n,prec", [(64, "mixed"), (128, "fp64"), (256, "mixed"), (256, "fp64"), (512, "mixed"),
+                                    (512, "fp64")])
 @pytest.mark.parametrize("degree,smoother", [(2, "chebyshev"), (3, "chebyshev"), (4, "chebyshev"), (6, "chebyshev"),
                                              (3, "jacobi")])
 def test_two_step_kernel_matches_single_steps(mgpu, n, prec, degree, smoother):
-    """The two-step smoothing kernel (last two steps of each pass in one
-    pass over memory) computes each step in the same order as the single-step
-    kernel: solves agree bitwise with MG_OPT_NO_PAIR, cycle by cycle.  Rows
-    of more than 1 KB (512^3 float, 256^3 double) run the two-step kernels
-    split over two waves per row."""
+    """The fused smoothing kernels (two or three steps in one pass over
+    memory, steps formed from b, the prolongation inside the first pair)
+    compute each step in the same order as the single-step kernel: solves
+    agree bitwise with MG_OPT_NO_PAIR, cycle by cycle.  Rows of more than
+    1 KB (512^3 float, 256^3 double) run the two-step kernels split over two
+    waves per row; 512^3 double rows take no two-step kernel but start each
+    pass from zero from b."""
     b = dev(flat_source(n, 3))
     levels = int(math.log2(n)) - 1
     kw = dict(levels=levels, degree=degree, precision=prec, smoother=smoother, sweeps=degree)
