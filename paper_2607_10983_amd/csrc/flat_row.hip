@@ -1236,31 +1236,42 @@ __global__ __launch_bounds__(64 * NW) void k_smooth3p_lds(int n, T ih2, const T*
     }
 }
 
-template <typename TA, typename TR, typename TE, int VEC, int W, bool UPDATE>
-__global__ __launch_bounds__(64 * W) void k_outer_lds(int n, TA ih2, const double* __restrict__ phi_in,
-                                                      const TE* __restrict__ e, double* __restrict__ phi_out,
-                                                      const double* __restrict__ b, double bmean,
-                                                      TR* __restrict__ r, TR* __restrict__ x1, TA cd0,
-                                                      double* __restrict__ partials, int nz, int nyb) {
-    constexpr int NR = 64 * VEC;
-    __shared__ TA rows[2][W + 2][NR];
-    __shared__ double sh[3 * W];
-    const RowGrid g{64 * VEC, 64 * VEC - 1};
+// S > 1: rows split into S segments, one per wave (W rows of S waves), for
+// rows whose unsplit queues would not fit a wave's registers; each segment
+// keeps its own slice of the LDS rows, and the x-neighbours across segment
+// ends come from one halo element loaded with each centre row.
+template <typename TA, typename TR, typename TE, int VEC, int W, bool UPDATE, int S = 1>
+__global__ __launch_bounds__(64 * W * S) void k_outer_lds(int n, TA ih2, const double* __restrict__ phi_in,
+                                                          const TE* __restrict__ e, double* __restrict__ phi_out,
+                                                          const double* __restrict__ b, double bmean,
+                                                          TR* __restrict__ r, TR* __restrict__ x1, TA cd0,
+                                                          double* __restrict__ partials, int nz, int nyb) {
+    constexpr int NR = 64 * VEC, NF = NR * S;
+    __shared__ TA rows[2][W + 2][NF];
+    __shared__ double sh[3 * W * S];
+    const RowGrid g{NF, NF - 1};
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int yb = lb % nyb, zc = lb / nyb;
-    const int w = wave_id();
+    const int wv = wave_id();
+    const int w = wv / S, seg = wv - w * S;
     const int y0 = yb * W;
     const int y = y0 + w;
     const int z0 = zc * nz;
     const int lane = threadIdx.x & 63;
-    const size_t off = (size_t)lane * VEC;
+    const size_t off = (size_t)seg * NR + (size_t)lane * VEC;
+    const int hoff = S > 1 ? seg_halo<VEC, S>(seg, lane) : 0;
     const bool lo = w == 0, hi = w == W - 1;
     const int yh = lo ? y0 - 1 : y0 + W;
     TA zm[VEC], c[VEC], zp[VEC], h[VEC];
+    TA hc = TA(0), hp = TA(0);  // x-halo of c and zp (S > 1)
     double bb[VEC];
     ld_value<TA, TR, TE, VEC, UPDATE>(zm, phi_in, e, g.row(y, z0 - 1) + off);
     ld_value<TA, TR, TE, VEC, UPDATE>(c, phi_in, e, g.row(y, z0) + off);
     ld_value<TA, TR, TE, VEC, UPDATE>(zp, phi_in, e, g.row(y, z0 + 1) + off);
+    if constexpr (S > 1) {
+        hc = ld_value1<TA, TE, UPDATE>(phi_in, e, g.row(y, z0) + hoff);
+        hp = ld_value1<TA, TE, UPDATE>(phi_in, e, g.row(y, z0 + 1) + hoff);
+    }
     ldrow<double, VEC>(bb, b + g.row(y, z0) + off);
     if (lo || hi) ld_value<TA, TR, TE, VEC, UPDATE>(h, phi_in, e, g.row(yh, z0) + off);
     double ss = 0.0, sb = 0.0, sp = 0.0;
@@ -1268,23 +1279,25 @@ __global__ __launch_bounds__(64 * W) void k_outer_lds(int n, TA ih2, const doubl
         const int z = z0 + k;
         const int buf = k & 1;
         TA zpp[VEC], hn[VEC];
+        TA hpp = TA(0);
         double bn[VEC];
         const bool more = k + 1 < nz;
         if (more) {
             ld_value<TA, TR, TE, VEC, UPDATE>(zpp, phi_in, e, g.row(y, z + 2) + off);
+            if constexpr (S > 1) hpp = ld_value1<TA, TE, UPDATE>(phi_in, e, g.row(y, z + 2) + hoff);
             ldrow<double, VEC>(bn, b + g.row(y, z + 1) + off);
             if (lo || hi) ld_value<TA, TR, TE, VEC, UPDATE>(hn, phi_in, e, g.row(yh, z + 1) + off);
         }
-        lds_strow<TA, VEC>(rows[buf][w + 1], lane, c);
-        if (lo) lds_strow<TA, VEC>(rows[buf][0], lane, h);
-        if (hi) lds_strow<TA, VEC>(rows[buf][W + 1], lane, h);
+        lds_strow<TA, VEC>(rows[buf][w + 1] + seg * NR, lane, c);
+        if (lo) lds_strow<TA, VEC>(rows[buf][0] + seg * NR, lane, h);
+        if (hi) lds_strow<TA, VEC>(rows[buf][W + 1] + seg * NR, lane, h);
         __syncthreads();
         TA ym[VEC], yp[VEC];
-        lds_ldrow<TA, VEC>(ym, rows[buf][w], lane);
-        lds_ldrow<TA, VEC>(yp, rows[buf][w + 2], lane);
+        lds_ldrow<TA, VEC>(ym, rows[buf][w] + seg * NR, lane);
+        lds_ldrow<TA, VEC>(yp, rows[buf][w + 2] + seg * NR, lane);
         TA Mx[VEC];
         TR ro[VEC];
-        flat7_row<TA, VEC>(c, ym, yp, zm, zp, ih2, Mx);
+        flat7_row_seg<TA, VEC, S>(c, ym, yp, zm, zp, ih2, Mx, hc);
 #pragma unroll
         for (int q = 0; q < VEC; ++q) {
             const double bq = bb[q] - bmean;
@@ -1330,11 +1343,13 @@ __global__ __launch_bounds__(64 * W) void k_outer_lds(int n, TA ih2, const doubl
             copyrow(zm, c);
             copyrow(c, zp);
             copyrow(zp, zpp);
+            hc = hp;
+            hp = hpp;
             copyrow(bb, bn);
             if (lo || hi) copyrow(h, hn);
         }
     }
-    outer_partials(partials, sb, ss, sp, sh, W);
+    outer_partials(partials, sb, ss, sp, sh, W * S);
 }
 
 // =====================================================================================
@@ -1520,6 +1535,7 @@ void shape(int rows, int planes, int min_nz, int& nz, int& nyb, int& blocks, int
 
 constexpr int kLdsWaves = 8;
 constexpr size_t kLdsBudget = 80 * 1024;
+constexpr size_t kOuterSegLdsBudget = 96 * 1024;
 template <typename T>
 bool lds_rows_fit(int n) {
     return 2ull * (kLdsWaves + 2) * (size_t)n * sizeof(T) <= kLdsBudget;
@@ -1556,10 +1572,25 @@ inline int row_segments(int n, size_t elem) {
     return row > kRowSegBytes ? (int)(row / kRowSegBytes) : 1;
 }
 
+// Rows too long for the LDS budget of kLdsWaves rows (1024^3 double): blocks
+// of kOuterSegRows rows, each split into 2 KB segments (S = row / 2 KB waves
+// per row), the rows still shared through LDS (96 KB for 4 rows + 2 halo rows,
+// double-buffered).  1024^3 outer residual against the row kernel without LDS:
+// mixed 3.9 -> 5.4 TB/s, FP64 3.8 -> 5.3 TB/s (2 rows per block: 4.9 TB/s).
+constexpr int kOuterSegRows = 4;
+inline bool outer_seg_lds(int n, size_t elem) {
+    const int S = row_segments(n, elem);
+    return S > 1 && kOuterSegRows * S <= 16 && 2ull * (kOuterSegRows + 2) * n * elem <= kOuterSegLdsBudget;
+}
+
 int row_outer_blocks(int n, bool double_arith) {
     int nz, nyb, blocks;
     if (double_arith ? lds_rows_fit<double>(n) : lds_rows_fit<float>(n)) {
         outer_lds_shape(n, kLdsWaves, nz, nyb, blocks);
+        return blocks;
+    }
+    if (outer_seg_lds(n, double_arith ? sizeof(double) : sizeof(float))) {
+        outer_lds_shape(n, kOuterSegRows, nz, nyb, blocks);
         return blocks;
     }
     shape(n * row_segments(n, double_arith ? sizeof(double) : sizeof(float)), n, 16, nz, nyb, blocks, 1024);
@@ -1992,6 +2023,28 @@ hipError_t launch_outer_row(int n, double ih2, const double* phi_in, const TE* e
         return hipGetLastError();
     }
     const int S = row_segments(n, sizeof(TA));
+    if (outer_seg_lds(n, sizeof(TA))) {
+        constexpr int Wr = kOuterSegRows;
+        outer_lds_shape(n, Wr, nz, nyb, blocks);
+#define MG_OUTER_SEGLDS(SS)                                                                                          \
+    DISPATCH_SEG(n, SS, {                                                                                            \
+        if constexpr (Wr * SS <= 16 && 2ull * (Wr + 2) * 64 * VEC * SS * sizeof(TA) <= kOuterSegLdsBudget) {        \
+            if (e)                                                                                                   \
+                MG_LAUNCH((k_outer_lds<TA, TR, TE, VEC, Wr, true, SS>), dim3(blocks), dim3(64 * Wr * SS), s, ev0,  \
+                          ev1, n, (TA)ih2, phi_in, e, phi_out, b, bmean, r, x1, (TA)cd0, partials, nz, nyb);        \
+            else                                                                                                     \
+                MG_LAUNCH((k_outer_lds<TA, TR, TE, VEC, Wr, false, SS>), dim3(blocks), dim3(64 * Wr * SS), s, ev0, \
+                          ev1, n, (TA)ih2, phi_in, e, phi_out, b, bmean, r, x1, (TA)cd0, partials, nz, nyb);        \
+        }                                                                                                            \
+    })
+        switch (S) {
+            case 2: MG_OUTER_SEGLDS(2); break;
+            case 4: MG_OUTER_SEGLDS(4); break;
+            default: return hipErrorInvalidValue;
+        }
+#undef MG_OUTER_SEGLDS
+        return hipGetLastError();
+    }
     if (S > 1) {
         shape(n * S, n, 16, nz, nyb, blocks, 1024);
 #define MG_OUTER_SEG(SS)                                                                                              \
