@@ -403,30 +403,41 @@ __global__ __launch_bounds__(kBlock) void k_outer_row(int n, TA ih2, const doubl
 // so the y-neighbour rows come from LDS instead of L2/HBM.  Used where the
 // 2 (W + 2) rows fit in 80 KB of LDS.
 // =====================================================================================
-template <typename T, int VEC, int W, bool PREV, bool FROMB = false, bool PREVB = false>
-__global__ __launch_bounds__(64 * W) void k_smooth_lds(int n, T ih2, const T* x, const T* xprev,
-                                                       const T* __restrict__ b, T* out, T a, T cd, int nz,
-                                                       int nyb, T cd0) {
+// S > 1: W rows of S segments each (one wave per segment), for rows whose
+// unsplit queues would not fit a wave's registers; each segment keeps its
+// slice of the LDS rows, and the x-neighbours across segment ends come from
+// one halo element loaded with each centre row, as in k_smooth_row.
+template <typename T, int VEC, int W, bool PREV, bool FROMB = false, bool PREVB = false, int S = 1>
+__global__ __launch_bounds__(64 * W * S) void k_smooth_lds(int n, T ih2, const T* x, const T* xprev,
+                                                           const T* __restrict__ b, T* out, T a, T cd, int nz,
+                                                           int nyb, T cd0) {
     static_assert(!(FROMB && PREV), "a step from b has no x_prev");
     static_assert(!PREVB || (PREV && !FROMB), "PREVB forms x_prev from b");
     constexpr bool LDP = PREV && !PREVB;  // x_prev is loaded
-    constexpr int NR = 64 * VEC;
-    __shared__ T rows[2][W + 2][NR];
-    const RowGrid g{64 * VEC, 64 * VEC - 1};
+    constexpr int NR = 64 * VEC, NF = NR * S;
+    __shared__ T rows[2][W + 2][NF];
+    const RowGrid g{NF, NF - 1};
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int yb = lb % nyb, zc = lb / nyb;
-    const int w = wave_id();
+    const int wv = wave_id();
+    const int w = wv / S, seg = wv - w * S;
     const int y0 = yb * W;
     const int y = y0 + w;
     const int z0 = zc * nz;
     const int lane = threadIdx.x & 63;
-    const size_t off = (size_t)lane * VEC;
+    const size_t off = (size_t)seg * NR + (size_t)lane * VEC;
+    const int hoff = S > 1 ? seg_halo<VEC, S>(seg, lane) : 0;
     const bool lo = w == 0, hi = w == W - 1;
     const int yh = lo ? y0 - 1 : y0 + W;  // halo row of the edge waves
     T zm[VEC], c[VEC], zp[VEC], bb[VEC], pp[VEC], h[VEC];
+    T hc = T(0), hp = T(0);  // x-halo of c and zp (S > 1)
     ldrow<T, VEC>(zm, x + g.row(y, z0 - 1) + off);
     ldrow<T, VEC>(c, x + g.row(y, z0) + off);
     ldrow<T, VEC>(zp, x + g.row(y, z0 + 1) + off);
+    if constexpr (S > 1) {
+        hc = x[g.row(y, z0) + hoff];
+        hp = x[g.row(y, z0 + 1) + hoff];
+    }
     if constexpr (!FROMB) ldrow<T, VEC>(bb, b + g.row(y, z0) + off);
     if constexpr (LDP) ldrow<T, VEC>(pp, xprev + g.row(y, z0) + off);
     if (lo || hi) ldrow<T, VEC>(h, x + g.row(yh, z0) + off);
@@ -434,20 +445,22 @@ __global__ __launch_bounds__(64 * W) void k_smooth_lds(int n, T ih2, const T* x,
         const int z = z0 + k;
         const int buf = k & 1;
         T zpp[VEC], bn[VEC], pn[VEC], hn[VEC];
+        T hpp = T(0);
         const bool more = k + 1 < nz;
         if (more) {
             ldrow<T, VEC>(zpp, x + g.row(y, z + 2) + off);
+            if constexpr (S > 1) hpp = x[g.row(y, z + 2) + hoff];
             if constexpr (!FROMB) ldrow<T, VEC>(bn, b + g.row(y, z + 1) + off);
             if constexpr (LDP) ldrow<T, VEC>(pn, xprev + g.row(y, z + 1) + off);
             if (lo || hi) ldrow<T, VEC>(hn, x + g.row(yh, z + 1) + off);
         }
-        lds_strow<T, VEC>(rows[buf][w + 1], lane, c);
-        if (lo) lds_strow<T, VEC>(rows[buf][0], lane, h);
-        if (hi) lds_strow<T, VEC>(rows[buf][W + 1], lane, h);
+        lds_strow<T, VEC>(rows[buf][w + 1] + seg * NR, lane, c);
+        if (lo) lds_strow<T, VEC>(rows[buf][0] + seg * NR, lane, h);
+        if (hi) lds_strow<T, VEC>(rows[buf][W + 1] + seg * NR, lane, h);
         __syncthreads();
         T ym[VEC], yp[VEC];
-        lds_ldrow<T, VEC>(ym, rows[buf][w], lane);
-        lds_ldrow<T, VEC>(yp, rows[buf][w + 2], lane);
+        lds_ldrow<T, VEC>(ym, rows[buf][w] + seg * NR, lane);
+        lds_ldrow<T, VEC>(yp, rows[buf][w + 2] + seg * NR, lane);
         T Mx[VEC], o[VEC];
         if constexpr (FROMB) {  // x = cd0 b on the row and its neighbours; b = the raw centre row
             T fc[VEC], fym[VEC], fyp[VEC], fzm[VEC], fzp[VEC];
@@ -459,11 +472,11 @@ __global__ __launch_bounds__(64 * W) void k_smooth_lds(int n, T ih2, const T* x,
                 fzm[e] = first_step<T, true>(zm[e], cd0);
                 fzp[e] = first_step<T, true>(zp[e], cd0);
             }
-            flat7_row<T, VEC>(fc, fym, fyp, fzm, fzp, ih2, Mx);
+            flat7_row_seg<T, VEC, S>(fc, fym, fyp, fzm, fzp, ih2, Mx, first_step<T, true>(hc, cd0));
 #pragma unroll
             for (int e = 0; e < VEC; ++e) o[e] = cheb_step<T>(fc[e], T(0), c[e], Mx[e], a, cd);
         } else {
-            flat7_row<T, VEC>(c, ym, yp, zm, zp, ih2, Mx);
+            flat7_row_seg<T, VEC, S>(c, ym, yp, zm, zp, ih2, Mx, hc);
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
                 const T xpe = PREVB ? first_step<T, true>(bb[e], cd0) : PREV ? pp[e] : T(0);
@@ -475,6 +488,8 @@ __global__ __launch_bounds__(64 * W) void k_smooth_lds(int n, T ih2, const T* x,
             copyrow(zm, c);
             copyrow(c, zp);
             copyrow(zp, zpp);
+            hc = hp;
+            hp = hpp;
             if constexpr (!FROMB) copyrow(bb, bn);
             if constexpr (LDP) copyrow(pp, pn);
             if (lo || hi) copyrow(h, hn);
@@ -1615,6 +1630,20 @@ int row_outer_blocks(int n, bool double_arith) {
         default: return hipErrorInvalidValue;                 \
     }
 
+// Single steps on rows over 2 KB (1024^3 float, 512^3 and 1024^3 double):
+// rows split into S segments of 2 KB, one wave each, in blocks of 16 waves
+// (16 / S rows), the rows still shared through LDS; kStepSegTarget blocks per
+// launch at least.  Against the segments without LDS (1024^3 double) or the
+// unsplit LDS rows: 1024^3 double 3.9 -> 4.9 TB/s, 512^3 double 5.0 -> 5.3,
+// 1024^3 float 5.05 -> 5.18 TB/s (blocks of 8 waves: 4.9, 5.2, 5.0 TB/s).
+constexpr int kStepSegWaves = 16;
+constexpr int kStepSegTarget = 1024;
+constexpr size_t kStepSegLdsBudget = 96 * 1024;
+inline bool step_seg_lds(int n, size_t elem) {
+    const int S = row_segments(n, elem);
+    return S > 1 && kStepSegWaves % S == 0 && 2ull * (kStepSegWaves / S + 2) * n * elem <= kStepSegLdsBudget;
+}
+
 // Single smoothing step, in one of three modes: MODE_PLAIN (x, [x_prev], b),
 // MODE_FROMB (step 1 of a pass from zero, from b alone: the iterate is the
 // pointwise first step cd0 b, x_prev = 0) and MODE_PREVB (step 2 of such a
@@ -1625,6 +1654,36 @@ hipError_t launch_step_mode(int n, double ih2, const T* x, const T* xprev, const
                             double cd0, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     constexpr bool FB = MODE == MODE_FROMB, PB = MODE == MODE_PREVB;
     int nz, nyb, blocks;
+    // Rows over 2 KB with LDS room for 16 / S of them: split into 2 KB
+    // segments, one wave each, the rows still shared through LDS.
+    if (x != nullptr && step_seg_lds(n, sizeof(T))) {
+        const int S = row_segments(n, sizeof(T));
+        nyb = n / (kStepSegWaves / S);
+        nz = n;
+        while (nz > 4 && nyb * (n / nz) < kStepSegTarget) nz >>= 1;
+        blocks = nyb * (n / nz);
+#define MG_STEP_SEGLDS(SS)                                                                                        \
+    DISPATCH_SEG(n, SS, {                                                                                         \
+        constexpr int Wr = kStepSegWaves / SS;                                                                    \
+        if constexpr (2ull * (Wr + 2) * 64 * VEC * SS * sizeof(T) <= kStepSegLdsBudget) {                         \
+            if (xprev == nullptr && !PB)                                                                          \
+                MG_LAUNCH((k_smooth_lds<T, VEC, Wr, false, FB, false, SS>), dim3(blocks), dim3(64 * Wr * SS), s,  \
+                          ev0, ev1, n, (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb, (T)cd0);                   \
+            else if constexpr (!FB)                                                                               \
+                MG_LAUNCH((k_smooth_lds<T, VEC, Wr, true, false, PB, SS>), dim3(blocks), dim3(64 * Wr * SS), s,   \
+                          ev0, ev1, n, (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb, (T)cd0);                   \
+        } else {                                                                                                  \
+            return hipErrorInvalidValue;                                                                          \
+        }                                                                                                         \
+    })
+        switch (S) {
+            case 2: MG_STEP_SEGLDS(2); break;
+            case 4: MG_STEP_SEGLDS(4); break;
+            default: return hipErrorInvalidValue;
+        }
+#undef MG_STEP_SEGLDS
+        return hipGetLastError();
+    }
     // Row sharing through LDS pays where the level's fields exceed the 256 MB
     // Infinity Cache (n >= 512); below that the y-halo rows already hit in
     // cache and the per-plane barrier costs more than it saves (measured).
@@ -2035,6 +2094,8 @@ hipError_t launch_outer_row(int n, double ih2, const double* phi_in, const TE* e
             else                                                                                                     \
                 MG_LAUNCH((k_outer_lds<TA, TR, TE, VEC, Wr, false, SS>), dim3(blocks), dim3(64 * Wr * SS), s, ev0, \
                           ev1, n, (TA)ih2, phi_in, e, phi_out, b, bmean, r, x1, (TA)cd0, partials, nz, nyb);        \
+        } else {                                                                                                     \
+            return hipErrorInvalidValue;                                                                             \
         }                                                                                                            \
     })
         switch (S) {
