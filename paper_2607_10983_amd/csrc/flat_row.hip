@@ -11,6 +11,8 @@
 // planes.  Blocks of four
 // waves are renumbered so that consecutive row blocks land on the same XCD
 // and share their halo rows through that XCD's L2.
+#include <type_traits>
+
 #include "flat_row.h"
 
 #include "fma.h"
@@ -1506,26 +1508,43 @@ __device__ __forceinline__ void coarse_seg(T (&v)[VEC / 2 + 1], const T* row, in
     v[CV] = lane_rot(t[0], 1);
 }
 
-template <typename T, int VEC>
+// S > 1: rows split into S segments, one per wave (rows over 2 KB), with the
+// segment-aware coarse loads of the fused pair.  The next plane's x row and
+// coarse rows are loaded before the current plane is combined and stored.
+template <typename T, int VEC, int S = 1>
 __global__ __launch_bounds__(kBlock) void k_prolong_row(int n, const T* __restrict__ e, T* __restrict__ x, int nz,
                                                         int nyb) {
-    constexpr int nc = 32 * VEC;
-    const RowGrid g{64 * VEC, 64 * VEC - 1};
+    static_assert(kWaves % S == 0, "a block holds whole rows");
+    static_assert(S == 1 || VEC >= 2, "split rows hold at least two fine points per lane");
+    constexpr int NR = 64 * VEC, NF = NR * S, nc = NF / 2;
+    using Coarse = typename std::conditional<(S > 1), CoarseSeg<T, VEC>, CoarseRows<T, VEC>>::type;
+    const RowGrid g{NF, NF - 1};
     const RowGrid gc{nc, nc - 1};
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int yb = lb % nyb, zc = lb / nyb;
     const int lane = threadIdx.x & 63;
-    const int y = yb * kWaves + wave_id();
+    const int w = wave_id();
+    const int y = yb * (kWaves / S) + w / S, seg = w % S;
     const int z0 = zc * nz;
-    const size_t off = (size_t)lane * VEC;
+    const size_t off = (size_t)seg * NR + (size_t)lane * VEC;
+    auto load = [&](T (&xv)[VEC], Coarse& c, int z) {
+        ldrow<T, VEC>(xv, x + g.row(y, z) + off);
+        if constexpr (S > 1) coarse_load_seg<T, VEC>(c, e, gc, y, z, seg, lane);
+        else coarse_load<T, VEC>(c, e, gc, y, z, lane);
+    };
+    T xv[VEC];
+    Coarse c;
+    load(xv, c, z0);
     for (int k = 0; k < nz; ++k) {
         const int z = z0 + k;
-        T xv[VEC];
-        ldrow<T, VEC>(xv, x + g.row(y, z) + off);
-        CoarseRows<T, VEC> c;
-        coarse_load<T, VEC>(c, e, gc, y, z, lane);
-        prolong_add<T, VEC>(xv, c, y, z);
+        T xn[VEC];
+        Coarse cn;
+        if (k + 1 < nz) load(xn, cn, z + 1);
+        if constexpr (S > 1) prolong_add_seg<T, VEC>(xv, c, y, z);
+        else prolong_add<T, VEC>(xv, c, y, z);
         strow<T, VEC>(x + g.row(y, z) + off, xv);
+        copyrow(xv, xn);
+        c = cn;
     }
 }
 
@@ -2165,10 +2184,26 @@ hipError_t launch_rr_row(int n, double ih2, const T* x, const T* b, T* coarse, h
 template <typename T>
 hipError_t launch_prolong_row(int n, const T* e, T* x, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     int nz, nyb, blocks;
-    shape(n, n, 4, nz, nyb, blocks);
-    DISPATCH_VEC(n, {
-        MG_LAUNCH((k_prolong_row<T, VEC>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, e, x, nz, nyb);
-    })
+    const int S = row_segments(n, sizeof(T));
+    shape(n * S, n, 4, nz, nyb, blocks);
+    switch (S) {
+        case 1:
+            DISPATCH_VEC(n, {
+                MG_LAUNCH((k_prolong_row<T, VEC>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, e, x, nz, nyb);
+            })
+            break;
+        case 2:
+            DISPATCH_SEG(n, 2, {
+                MG_LAUNCH((k_prolong_row<T, VEC, 2>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, e, x, nz, nyb);
+            })
+            break;
+        case 4:
+            DISPATCH_SEG(n, 4, {
+                MG_LAUNCH((k_prolong_row<T, VEC, 4>), dim3(blocks), dim3(kBlock), s, ev0, ev1, n, e, x, nz, nyb);
+            })
+            break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -251,9 +251,10 @@ def test_inner_step_rejects_bad_arguments(mgpu):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_smoothing_1024_windows(mgpu, precision):
-    """1024^3 (rows of 8 KB in double, split over four waves per row; float
-    rows of 4 KB through the LDS-shared row kernel): one smoothing pass from
-    x and from zero, on periodic windows."""
+    """1024^3 (rows of 8 KB in double, 4 KB in float, split over four and
+    two waves per row): one smoothing pass from x, from zero and from
+    x + P e, the prolongation and residual + restriction, on periodic
+    windows."""
     n, levels, degree = 1024, 7, 4
     free, _ = torch.cuda.mem_get_info()
     if free < 64 * 2**30:
@@ -261,8 +262,9 @@ def test_smoothing_1024_windows(mgpu, precision):
     g = torch.Generator(device="cuda").manual_seed(1024)
     xd = torch.randn((n, n, n), generator=g, device="cuda", dtype=torch.float64)
     bd = torch.randn((n, n, n), generator=g, device="cuda", dtype=torch.float64)
+    ed = torch.randn((n // 2,) * 3, generator=g, device="cuda", dtype=torch.float64)
     if precision != "fp64":
-        xd, bd = xd.float().double(), bd.float().double()
+        xd, bd, ed = xd.float().double(), bd.float().double(), ed.float().double()
     mg = mgpu.Multigrid(n, levels=levels, degree=degree, precision=precision)
     H = O.build_hierarchy(n, 1, degree)
     lev = H.levels[0]
@@ -272,7 +274,18 @@ def test_smoothing_1024_windows(mgpu, precision):
     W_ = size + 4 * halo
     xw = [win_t(xd, l, W_) for l in lo]
     bw = [win_t(bd, l, W_) for l in lo]
+    ew = [win_t(ed, tuple(s // 2 for s in l), W_ // 2) for l in lo]
     inner = (slice(2 * halo, 2 * halo + size),) * 3
+    for step in ("prolong", "prolong_smooth"):
+        out = mg.inner_step(step, 0, x=xd, e=ed, b=bd if step == "prolong_smooth" else None)
+        for k, l in enumerate(lo):
+            got = win_t(out, tuple(s + 2 * halo for s in l), size)
+            x0 = xw[k] + O.prolong(ew[k])
+            ref = (x0 if step == "prolong" else O.smooth(H, lev, x0, bw[k]))[inner]
+            err = maxrel(got, ref)
+            print(f"1024^3 {precision} {step} window {starts[k]}: {err:.2e}", flush=True)
+            assert err <= bar(precision), (step, starts[k], err)
+        del out
     for step in ("smooth", "smooth_zero"):
         out = mg.inner_step(step, 0, x=xd if step == "smooth" else None, b=bd)
         for k, l in enumerate(lo):
