@@ -1606,25 +1606,30 @@ inline int row_segments(int n, size_t elem) {
     return row > kRowSegBytes ? (int)(row / kRowSegBytes) : 1;
 }
 
-// Rows too long for the LDS budget of kLdsWaves rows (1024^3 double): blocks
-// of kOuterSegRows rows, each split into 2 KB segments (S = row / 2 KB waves
-// per row), the rows still shared through LDS (96 KB for 4 rows + 2 halo rows,
-// double-buffered).  1024^3 outer residual against the row kernel without LDS:
-// mixed 3.9 -> 5.4 TB/s, FP64 3.8 -> 5.3 TB/s (2 rows per block: 4.9 TB/s).
-constexpr int kOuterSegRows = 4;
+// Rows of at least kOuterSegMinRow bytes (512^3 and 1024^3 double): blocks
+// of 16 waves, 16 / S rows each split into S segments of 2 KB, the rows still
+// shared through LDS (96 KB for 4 rows + 2 halo rows of 8 KB,
+// double-buffered).  1024^3 outer residual against the row kernel without
+// LDS: mixed 3.9 -> 5.4 TB/s, FP64 3.8 -> 5.3 TB/s (2 rows per block: 4.9);
+// 512^3 against unsplit 4 KB rows in 8-wave blocks: 5.22 -> 5.41 TB/s mixed,
+// 5.14 -> 5.38 TB/s FP64.
+constexpr int kOuterSegWaves = 16;
+constexpr size_t kOuterSegMinRow = 4096;
 inline bool outer_seg_lds(int n, size_t elem) {
     const int S = row_segments(n, elem);
-    return S > 1 && kOuterSegRows * S <= 16 && 2ull * (kOuterSegRows + 2) * n * elem <= kOuterSegLdsBudget;
+    return S > 1 && (size_t)n * elem >= kOuterSegMinRow && kOuterSegWaves % S == 0 &&
+           2ull * (kOuterSegWaves / S + 2) * n * elem <= kOuterSegLdsBudget;
 }
 
 int row_outer_blocks(int n, bool double_arith) {
     int nz, nyb, blocks;
-    if (double_arith ? lds_rows_fit<double>(n) : lds_rows_fit<float>(n)) {
-        outer_lds_shape(n, kLdsWaves, nz, nyb, blocks);
+    const size_t elem = double_arith ? sizeof(double) : sizeof(float);
+    if (outer_seg_lds(n, elem)) {
+        outer_lds_shape(n, kOuterSegWaves / row_segments(n, elem), nz, nyb, blocks);
         return blocks;
     }
-    if (outer_seg_lds(n, double_arith ? sizeof(double) : sizeof(float))) {
-        outer_lds_shape(n, kOuterSegRows, nz, nyb, blocks);
+    if (double_arith ? lds_rows_fit<double>(n) : lds_rows_fit<float>(n)) {
+        outer_lds_shape(n, kLdsWaves, nz, nyb, blocks);
         return blocks;
     }
     shape(n * row_segments(n, double_arith ? sizeof(double) : sizeof(float)), n, 16, nz, nyb, blocks, 1024);
@@ -2083,6 +2088,30 @@ hipError_t launch_outer_row(int n, double ih2, const double* phi_in, const TE* e
                             double bmean, TR* r, TR* x1, double cd0, double* partials, hipStream_t s,
                             hipEvent_t ev0, hipEvent_t ev1) {
     int nz, nyb, blocks;
+    if (outer_seg_lds(n, sizeof(TA))) {
+        outer_lds_shape(n, kOuterSegWaves / row_segments(n, sizeof(TA)), nz, nyb, blocks);
+#define MG_OUTER_SEGLDS(SS)                                                                                          \
+    DISPATCH_SEG(n, SS, {                                                                                            \
+        constexpr int Wr = kOuterSegWaves / SS;                                                                      \
+        if constexpr (2ull * (Wr + 2) * 64 * VEC * SS * sizeof(TA) <= kOuterSegLdsBudget) {                          \
+            if (e)                                                                                                   \
+                MG_LAUNCH((k_outer_lds<TA, TR, TE, VEC, Wr, true, SS>), dim3(blocks), dim3(64 * Wr * SS), s, ev0,  \
+                          ev1, n, (TA)ih2, phi_in, e, phi_out, b, bmean, r, x1, (TA)cd0, partials, nz, nyb);        \
+            else                                                                                                     \
+                MG_LAUNCH((k_outer_lds<TA, TR, TE, VEC, Wr, false, SS>), dim3(blocks), dim3(64 * Wr * SS), s, ev0, \
+                          ev1, n, (TA)ih2, phi_in, e, phi_out, b, bmean, r, x1, (TA)cd0, partials, nz, nyb);        \
+        } else {                                                                                                     \
+            return hipErrorInvalidValue;                                                                             \
+        }                                                                                                            \
+    })
+        switch (row_segments(n, sizeof(TA))) {
+            case 2: MG_OUTER_SEGLDS(2); break;
+            case 4: MG_OUTER_SEGLDS(4); break;
+            default: return hipErrorInvalidValue;
+        }
+#undef MG_OUTER_SEGLDS
+        return hipGetLastError();
+    }
     if (lds_rows_fit<TA>(n)) {
         outer_lds_shape(n, kLdsWaves, nz, nyb, blocks);
 #define MG_OUTER_LDS(Wv)                                                                                           \
@@ -2101,30 +2130,6 @@ hipError_t launch_outer_row(int n, double ih2, const double* phi_in, const TE* e
         return hipGetLastError();
     }
     const int S = row_segments(n, sizeof(TA));
-    if (outer_seg_lds(n, sizeof(TA))) {
-        constexpr int Wr = kOuterSegRows;
-        outer_lds_shape(n, Wr, nz, nyb, blocks);
-#define MG_OUTER_SEGLDS(SS)                                                                                          \
-    DISPATCH_SEG(n, SS, {                                                                                            \
-        if constexpr (Wr * SS <= 16 && 2ull * (Wr + 2) * 64 * VEC * SS * sizeof(TA) <= kOuterSegLdsBudget) {        \
-            if (e)                                                                                                   \
-                MG_LAUNCH((k_outer_lds<TA, TR, TE, VEC, Wr, true, SS>), dim3(blocks), dim3(64 * Wr * SS), s, ev0,  \
-                          ev1, n, (TA)ih2, phi_in, e, phi_out, b, bmean, r, x1, (TA)cd0, partials, nz, nyb);        \
-            else                                                                                                     \
-                MG_LAUNCH((k_outer_lds<TA, TR, TE, VEC, Wr, false, SS>), dim3(blocks), dim3(64 * Wr * SS), s, ev0, \
-                          ev1, n, (TA)ih2, phi_in, e, phi_out, b, bmean, r, x1, (TA)cd0, partials, nz, nyb);        \
-        } else {                                                                                                     \
-            return hipErrorInvalidValue;                                                                             \
-        }                                                                                                            \
-    })
-        switch (S) {
-            case 2: MG_OUTER_SEGLDS(2); break;
-            case 4: MG_OUTER_SEGLDS(4); break;
-            default: return hipErrorInvalidValue;
-        }
-#undef MG_OUTER_SEGLDS
-        return hipGetLastError();
-    }
     if (S > 1) {
         shape(n * S, n, 16, nz, nyb, blocks, 1024);
 #define MG_OUTER_SEG(SS)                                                                                              \
