@@ -37,21 +37,22 @@ sys.path.insert(0, ROOT)
 METRIC = "V-cycle Mpts/s + HBM GB/s; time to rel. residual 1e-10, mixed vs FP64"
 HBM_PEAK_GBPS = 8000.0
 
-# Measured HBM bytes per launch of the fine-level smoothing kernels on the
-# 256^3 / degree-3 workload: rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch
-# (profiles/hbm_bytes_*.md) scaled by the copy-kernel factors 2.0 (fetch) and
-# 1.0 (write), per launch of each kernel.  Reported only while
-# the source of the row kernels and their launch shapes is the one the counters were taken on.
+# Measured HBM bytes per launch of the fine-level kernels, per workload
+# (n, degree; mixed precision) and kernel kind: rocprofv3 FETCH_SIZE and
+# WRITE_SIZE per dispatch (profiles/hbm_bytes_*.md) scaled by the copy-kernel
+# factors 2.0 (fetch) and 1.0 (write), averaged over the launches of the kind.
+# Reported only while the source of the row kernels and their launch shapes
+# is the one the counters were taken on.
 TRAFFIC = {
-    "device_code_sha256": "c8575780fcc42de2a940f660856e12808dd0019bfbf8a5de79169479c8f56455",
-    "n": 256,
-    "degree": 3,
+    "device_code_sha256": "e8d4cc40916f02b8e6b710085bd079dca9eaecf604c9b96b19d4c993e204fcc6",
     "bytes_per_launch": {
-        # pre-smoothing, one pass from zero (b -> x3, two-plane prefetch, 16-wave blocks,
-        # plus the block that finishes the outer sums)
-        "k_smooth2_lds": (79.2 + 64.0) * 1024 * 1024,
-        # prolongation + post-smoothing, three steps in one pass (x, e, b -> x3)
-        "k_smooth3p_lds": (163.1 + 64.0) * 1024 * 1024,
+        # the benchmark step: outer (with the first-cycle variant), pass from
+        # zero (b -> x3), prolongation + three steps, residual + restriction
+        (256, 3): {"k_outer_lds": 536994262, "k_smooth2_lds": 151769617, "k_smooth3p_lds": 238198864,
+                   "k_rr_row": 159442036},
+        # the 512^3 leg: step from b, the three pairs, outer, residual + restriction
+        (512, 4): {"k_smooth_row": 1137125238, "k_smooth2_lds": 2275540746, "k_outer_lds": 4445826031,
+                   "k_rr_row": 1408600711},
     },
 }
 
@@ -59,13 +60,10 @@ TRAFFIC = {
 def measured_traffic(n, degree, kernel):
     import hashlib
     csrc = os.path.join(ROOT, "paper_2607_10983_amd", "csrc")
-    src = open(os.path.join(csrc, "flat_row.hip")).read()
-    dev = src + open(os.path.join(csrc, "fma.h")).read()  # kernels and their launch shapes
+    dev = "".join(open(os.path.join(csrc, f)).read() for f in ("flat_row.hip", "fma.h", "row.h"))
     if hashlib.sha256(dev.encode()).hexdigest() != TRAFFIC["device_code_sha256"]:
         return None
-    if (n, degree) != (TRAFFIC["n"], TRAFFIC["degree"]):
-        return None
-    v = TRAFFIC["bytes_per_launch"].get(kernel)
+    v = TRAFFIC["bytes_per_launch"].get((n, degree), {}).get(kernel)
     return round(v) if v is not None else None
 
 
@@ -332,7 +330,7 @@ def b512_leg(mgpu, torch, flat_source, n=512, levels=6, deg=4, cycles=20, reps=5
             "reference_ms_per_cycle_at_60pct": round(reference_bytes_per_cycle(n, deg, prec)
                                                      / (0.6 * HBM_PEAK_GBPS * 1e9) * 1e3, 3),
             "rel_res_after": rel,
-            "fine_kernels": [kernel_entry(k, kt[k], n, prec, ms, per="call") for k in KINDS if kt[k][0]],
+            "fine_kernels": [kernel_entry(k, kt[k], n, prec, ms, deg=deg, per="call") for k in KINDS if kt[k][0]],
         }
         del mg, phi
         torch.cuda.empty_cache()

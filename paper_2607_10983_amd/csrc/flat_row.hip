@@ -1613,19 +1613,21 @@ inline int row_segments(int n, size_t elem) {
 // LDS: mixed 3.9 -> 5.4 TB/s, FP64 3.8 -> 5.3 TB/s (2 rows per block: 4.9);
 // 512^3 against unsplit 4 KB rows in 8-wave blocks: 5.22 -> 5.41 TB/s mixed,
 // 5.14 -> 5.38 TB/s FP64.
-constexpr int kOuterSegWaves = 16;
+// Float arithmetic (the pure FP32 solver) keeps VEC = 8 per lane and needs
+// more registers than 16-wave blocks leave (it spilled): blocks of 8 waves.
+constexpr int outer_seg_waves(size_t elem) { return elem == sizeof(double) ? 16 : 8; }
 constexpr size_t kOuterSegMinRow = 4096;
 inline bool outer_seg_lds(int n, size_t elem) {
-    const int S = row_segments(n, elem);
-    return S > 1 && (size_t)n * elem >= kOuterSegMinRow && kOuterSegWaves % S == 0 &&
-           2ull * (kOuterSegWaves / S + 2) * n * elem <= kOuterSegLdsBudget;
+    const int S = row_segments(n, elem), waves = outer_seg_waves(elem);
+    return S > 1 && (size_t)n * elem >= kOuterSegMinRow && waves % S == 0 &&
+           2ull * (waves / S + 2) * n * elem <= kOuterSegLdsBudget;
 }
 
 int row_outer_blocks(int n, bool double_arith) {
     int nz, nyb, blocks;
     const size_t elem = double_arith ? sizeof(double) : sizeof(float);
     if (outer_seg_lds(n, elem)) {
-        outer_lds_shape(n, kOuterSegWaves / row_segments(n, elem), nz, nyb, blocks);
+        outer_lds_shape(n, outer_seg_waves(elem) / row_segments(n, elem), nz, nyb, blocks);
         return blocks;
     }
     if (double_arith ? lds_rows_fit<double>(n) : lds_rows_fit<float>(n)) {
@@ -2089,10 +2091,10 @@ hipError_t launch_outer_row(int n, double ih2, const double* phi_in, const TE* e
                             hipEvent_t ev0, hipEvent_t ev1) {
     int nz, nyb, blocks;
     if (outer_seg_lds(n, sizeof(TA))) {
-        outer_lds_shape(n, kOuterSegWaves / row_segments(n, sizeof(TA)), nz, nyb, blocks);
+        outer_lds_shape(n, outer_seg_waves(sizeof(TA)) / row_segments(n, sizeof(TA)), nz, nyb, blocks);
 #define MG_OUTER_SEGLDS(SS)                                                                                          \
     DISPATCH_SEG(n, SS, {                                                                                            \
-        constexpr int Wr = kOuterSegWaves / SS;                                                                      \
+        constexpr int Wr = outer_seg_waves(sizeof(TA)) / SS;                                                         \
         if constexpr (2ull * (Wr + 2) * 64 * VEC * SS * sizeof(TA) <= kOuterSegLdsBudget) {                          \
             if (e)                                                                                                   \
                 MG_LAUNCH((k_outer_lds<TA, TR, TE, VEC, Wr, true, SS>), dim3(blocks), dim3(64 * Wr * SS), s, ev0,  \
