@@ -873,7 +873,7 @@ __device__ __forceinline__ void prolong_add_seg(T (&xv)[VEC], const CoarseSeg<T,
 // coarse correction on the (n/2)^3 grid), formed row by row as the x rows
 // arrive and never written; the prolongation of k_prolong_row, same bits.
 template <typename T, int VEC, int NW, bool PREV1, bool Y1OUT, bool FROMB, int NZC, int S, bool PREVB = false,
-          bool PRO = false>
+          bool PRO = false, bool PFA = false>
 __global__ __launch_bounds__(64 * NW) void k_smooth2x_lds(int n, T ih2, const T* __restrict__ x,
                                                           const T* __restrict__ xp, const T* __restrict__ b,
                                                           T* __restrict__ y2, T* __restrict__ y1o, T a1, T cd1,
@@ -942,23 +942,39 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2x_lds(int n, T ih2, const T*
         }
     }
     lds_strow<T, VEC>(xs[0][w], lane, xc);
-    __syncthreads();
     constexpr int steps = NZC + 2;
+    // PFA: the rows of the next plane are loaded one iteration earlier into a
+    // second register set (xa, oa, ba, pa), i.e. two planes ahead of their use
+    constexpr int ahead = PFA ? 1 : 0;
+    T xa[VEC], oa[VEC] = {}, ba[VEC], pa[VEC];
+    CoarseSeg<T, VEC> ca, coa;
+    if constexpr (PFA) {
+        ldrow<T, VEC>(xa, src + g.row(y, z1 + 2) + off);
+        if (lo || hi) ldrow<T, VEC>(oa, src + g.row(yo, z1 + 1) + off);
+        if constexpr (PRO) {
+            coarse_load_seg<T, VEC>(ca, ec, gc, y, z1 + 2, seg, lane);
+            if (lo || hi) coarse_load_seg<T, VEC>(coa, ec, gc, yo, z1 + 1, seg, lane);
+        }
+        if constexpr (!FROMB) ldrow<T, VEC>(ba, b + g.row(y, z1 + 1) + off);
+        if constexpr (LDP) ldrow<T, VEC>(pa, xp + g.row(y, z1 + 1) + off);
+    }
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < steps; ++j, ++z1) {
         const bool more = j + 1 < steps;
+        const bool load = j + 1 + ahead < steps;
         const int cb = j & 1;
         T xn[VEC], bn[VEC], pn[VEC], on[VEC];
         CoarseSeg<T, VEC> cn, con;  // PRO: coarse rows of xn and on
-        if (more) {
-            ldrow<T, VEC>(xn, src + g.row(y, z1 + 2) + off);
-            if (lo || hi) ldrow<T, VEC>(on, src + g.row(yo, z1 + 1) + off);
+        if (load) {
+            ldrow<T, VEC>(xn, src + g.row(y, z1 + 2 + ahead) + off);
+            if (lo || hi) ldrow<T, VEC>(on, src + g.row(yo, z1 + 1 + ahead) + off);
             if constexpr (PRO) {
-                coarse_load_seg<T, VEC>(cn, ec, gc, y, z1 + 2, seg, lane);
-                if (lo || hi) coarse_load_seg<T, VEC>(con, ec, gc, yo, z1 + 1, seg, lane);
+                coarse_load_seg<T, VEC>(cn, ec, gc, y, z1 + 2 + ahead, seg, lane);
+                if (lo || hi) coarse_load_seg<T, VEC>(con, ec, gc, yo, z1 + 1 + ahead, seg, lane);
             }
-            if constexpr (!FROMB) ldrow<T, VEC>(bn, b + g.row(y, z1 + 1) + off);
-            if constexpr (LDP) ldrow<T, VEC>(pn, xp + g.row(y, z1 + 1) + off);
+            if constexpr (!FROMB) ldrow<T, VEC>(bn, b + g.row(y, z1 + 1 + ahead) + off);
+            if constexpr (LDP) ldrow<T, VEC>(pn, xp + g.row(y, z1 + 1 + ahead) + off);
         }
         // first step at z1
         T ym[VEC], yp[VEC], M1[VEC], sp[VEC];
@@ -1016,16 +1032,39 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2x_lds(int n, T ih2, const T*
         copyrow(sc, sp);
         if constexpr (!FROMB) copyrow(b2, b1);
         if (more) {
-            if constexpr (PRO) {  // a whole iteration after their loads were issued
-                prolong_add_seg<T, VEC>(xn, cn, y, z1 + 2);
-                if (lo || hi) prolong_add_seg<T, VEC>(on, con, yo, z1 + 1);
+            if constexpr (PFA) {
+                if constexpr (PRO) {  // two iterations after their loads were issued
+                    prolong_add_seg<T, VEC>(xa, ca, y, z1 + 2);
+                    if (lo || hi) prolong_add_seg<T, VEC>(oa, coa, yo, z1 + 1);
+                }
+                copyrow(xm, xc);
+                copyrow(xc, xq);
+                copyrow(xq, xa);
+                if (lo || hi) copyrow(o1, oa);
+                if constexpr (!FROMB) copyrow(b1, ba);
+                if constexpr (LDP) copyrow(p1, pa);
+                if (load) {
+                    copyrow(xa, xn);
+                    if (lo || hi) copyrow(oa, on);
+                    if constexpr (PRO) {
+                        ca = cn;
+                        coa = con;
+                    }
+                    if constexpr (!FROMB) copyrow(ba, bn);
+                    if constexpr (LDP) copyrow(pa, pn);
+                }
+            } else {
+                if constexpr (PRO) {  // a whole iteration after their loads were issued
+                    prolong_add_seg<T, VEC>(xn, cn, y, z1 + 2);
+                    if (lo || hi) prolong_add_seg<T, VEC>(on, con, yo, z1 + 1);
+                }
+                copyrow(xm, xc);
+                copyrow(xc, xq);
+                copyrow(xq, xn);
+                if (lo || hi) copyrow(o1, on);
+                if constexpr (!FROMB) copyrow(b1, bn);
+                if constexpr (LDP) copyrow(p1, pn);
             }
-            copyrow(xm, xc);
-            copyrow(xc, xq);
-            copyrow(xq, xn);
-            if (lo || hi) copyrow(o1, on);
-            if constexpr (!FROMB) copyrow(b1, bn);
-            if constexpr (LDP) copyrow(p1, pn);
         }
     }
 }
@@ -1878,6 +1917,9 @@ hipError_t launch_pair_nw(int n, double ih2, const T* x, const T* xp, const T* b
 constexpr size_t kPairSegBytes = 1024;
 constexpr int kPairSegWaves = 16;  // block of the split two-step kernels
 constexpr int kPairSegNz = 16;     // their (fully unrolled) chunk height
+// rows loaded two planes ahead of their use (not with the prolongation in
+// double, where the second register set spilled)
+constexpr bool kPairXPf = true;
 // x plane of the split two-step kernels shared through LDS (k_smooth2x_lds):
 // 512^3 float pairs 4.07 -> 4.45 TB/s, 256^3 double 3.74 -> 3.98 TB/s, same
 // bits.  Unsplit 1 KB rows keep k_smooth2_lds: the 256^3 float pass from zero
@@ -1898,7 +1940,8 @@ bool pair_pro_applies(int n, size_t elem) {
     do {                                                                                                         \
         constexpr bool JOB = FROMB || PREVB;                                                                     \
         if constexpr (kPairXLds)                                                                                 \
-            MG_LAUNCH((k_smooth2x_lds<T, VEC, NW, PREV1, Y1OUT, FROMB, kPairSegNz, S, PREVB, PRO>),              \
+            MG_LAUNCH((k_smooth2x_lds<T, VEC, NW, PREV1, Y1OUT, FROMB, kPairSegNz, S, PREVB, PRO,                \
+                                      kPairXPf && !(PRO && sizeof(T) == sizeof(double))>),                     \
                       dim3(blocks + (JOB ? extra : 0)), dim3(64 * NW), s, ev0, ev1, n, (T)ih2, x, xp, b, y2, y1,   \
                       (T)a1, (T)cd1, (T)a2, (T)cd2, nyb, (T)cd0, JOB ? sums : SumsJob{}, ec);                    \
         else                                                                                                     \
