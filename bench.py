@@ -130,8 +130,13 @@ def model_bytes_per_cycle(n, levels, degree, precision):
         post = pass_bytes(degree, False, pairs, triple, s)
         # the prolongation runs inside the post-smoothing pass's first kernel:
         # the three-step pass from 128^3 (degree 3), the first pair on split
-        # rows (rows of 1-2 KB, an even degree)
-        fused_prolong = (triple and nl >= 128 and degree == 3) or (pairs and nl * s > 1024 and degree % 2 == 0)
+        # rows (rows of 1-2 KB, an even degree), the first two single steps on
+        # rows over 2 KB (x, e, b -> x1; x1, x, e, b -> x2: e read twice)
+        step_pro = rowk and nl * s > 2048 and degree >= 2
+        fused_prolong = ((triple and nl >= 128 and degree == 3) or (pairs and nl * s > 1024 and degree % 2 == 0)
+                         or step_pro)
+        if step_pro:
+            post = (3 + 4 + 4 * (degree - 2)) * s + s / 8
         transfers = 2 * s + s / 8 + (s / 8 if fused_prolong else 2 * s + s / 8)
         tot += nl ** 3 * (pre + post + transfers)
     # outer: read phi, e, b; write phi, r (and the first smoothing step where no pass-from-zero kernel runs)

@@ -21,6 +21,18 @@ hipError_t launch_smooth_row(int n, double ih2, const T* x, const T* xprev, cons
 template <typename T>
 hipError_t launch_smooth_fromb_row(int n, double ih2, const T* b, T* out, double a1, double cd1, double cd0,
                                    hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// Post-smoothing on rows over 2 KB without two-step kernels
+// (step_pro_applies): step 0 from x0 = x + P e formed on the fly (x_prev = 0,
+// out = x1; x is not changed), and step 1 with x_prev = x0 = xold + P e
+// formed pointwise (out may be xold).  e on the (n/2)^3 grid.
+bool step_pro_applies(int n, size_t elem);
+template <typename T>
+hipError_t launch_smooth_pro_row(int n, double ih2, const T* x, const T* e, const T* b, T* out, double a0,
+                                 double cd0, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+template <typename T>
+hipError_t launch_smooth_prevp_row(int n, double ih2, const T* x1, const T* xold, const T* e, const T* b, T* out,
+                                   double a1, double cd1, hipStream_t s, hipEvent_t ev0 = nullptr,
+                                   hipEvent_t ev1 = nullptr);
 // Step 2 of that pass: out = x + a2 (x - x1) + cd2 (b - M x) with x_prev
 // x1 = cd0 * b formed from the b rows (not read).  out must differ from x and b.
 template <typename T>

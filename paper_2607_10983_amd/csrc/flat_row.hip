@@ -65,6 +65,19 @@ __device__ __forceinline__ void lds_ldrow(T (&v)[VEC], const T* row, int lane) {
     }
 }
 
+// Element i (0 <= i < 64 VEC) of a row copy written by lds_strow.
+template <typename T, int VEC>
+__device__ __forceinline__ T lds_elem(const T* row, int i) {
+    constexpr int B = VEC * (int)sizeof(T);
+    if constexpr (B <= 16) {
+        return row[i];
+    } else {
+        constexpr int P = 16 / (int)sizeof(T);
+        const int l = i / VEC, e = i - l * VEC;
+        return row[((e / P) * 64 + l) * P + e % P];
+    }
+}
+
 template <typename T, int VEC>
 __device__ __forceinline__ void copyrow(T (&d)[VEC], const T (&s)[VEC]) {
 #pragma unroll
@@ -122,6 +135,164 @@ template <int VEC, int S>
 __device__ __forceinline__ int seg_halo(int seg, int lane) {
     constexpr int NR = 64 * VEC, NF = NR * S;
     return lane < 32 ? (seg * NR - 1) & (NF - 1) : ((seg + 1) * NR) & (NF - 1);
+}
+
+// The coarse rows the trilinear prolongation of fine row (y, z) reads (VEC >= 2):
+// (Y, Z), and (Y+1, Z), (Y, Z+1), (Y+1, Z+1) where y, z are odd; loaded raw so
+// that a prefetch is not waited for until the values are combined.
+// VEC == 1 (64^3): lane l holds fine x = l, i.e. coarse X = l / 2, and reads
+// the coarse values X and X + 1 of each row itself.
+template <typename T, int VEC>
+struct CoarseRows {
+    T t00[VEC / 2], t01[VEC / 2], t10[VEC / 2], t11[VEC / 2];
+};
+template <typename T>
+struct CoarseRows<T, 1> {
+    T a, a1, b0, b1, c0, c1, d0, d1;  // rows (Y, Z), (Y+1, Z), (Y, Z+1), (Y+1, Z+1) at X, X + 1
+};
+template <typename T, int VEC>
+__device__ __forceinline__ void coarse_load(CoarseRows<T, VEC>& c, const T* e, const RowGrid& gc, int y, int z,
+                                            int lane) {
+    const int Y = y >> 1, Z = z >> 1, oy = y & 1, oz = z & 1;
+    if constexpr (VEC == 1) {
+        const int X = lane >> 1, ox = lane & 1, m = gc.mask;
+        const T* r0 = e + gc.row(Y, Z);
+        c.a = r0[X & m];
+        if (ox) c.a1 = r0[(X + 1) & m];
+        if (oy) {
+            const T* r1 = e + gc.row(Y + 1, Z);
+            c.b0 = r1[X & m];
+            if (ox) c.b1 = r1[(X + 1) & m];
+        }
+        if (oz) {
+            const T* r2 = e + gc.row(Y, Z + 1);
+            c.c0 = r2[X & m];
+            if (ox) c.c1 = r2[(X + 1) & m];
+            if (oy) {
+                const T* r3 = e + gc.row(Y + 1, Z + 1);
+                c.d0 = r3[X & m];
+                if (ox) c.d1 = r3[(X + 1) & m];
+            }
+        }
+    } else {
+        constexpr int CV = VEC / 2;
+        const size_t off = (size_t)lane * CV;
+        ldrow<T, CV>(c.t00, e + gc.row(Y, Z) + off);
+        if (oy) ldrow<T, CV>(c.t01, e + gc.row(Y + 1, Z) + off);
+        if (oz) ldrow<T, CV>(c.t10, e + gc.row(Y, Z + 1) + off);
+        if (oy && oz) ldrow<T, CV>(c.t11, e + gc.row(Y + 1, Z + 1) + off);
+    }
+}
+// xv += P e on fine row (y, z): interpolate in y, then z, then x (the x + 1
+// coarse value from the next lane).  Rounding written out: every kernel that
+// prolongs (the prolongation kernel, the fused post-smoothing pass) gets the
+// same bits.
+template <typename T, int VEC>
+__device__ __forceinline__ void prolong_add(T (&xv)[VEC], const CoarseRows<T, VEC>& c, int y, int z) {
+#pragma clang fp contract(off)
+    const int oy = y & 1, oz = z & 1;
+    if constexpr (VEC == 1) {  // interpolate in x, then y, then z
+        const int ox = threadIdx.x & 1;
+        T v = ox ? T(0.5) * (c.a + c.a1) : c.a;
+        if (oy) v = T(0.5) * (v + (ox ? T(0.5) * (c.b0 + c.b1) : c.b0));
+        if (oz) {
+            T u = ox ? T(0.5) * (c.c0 + c.c1) : c.c0;
+            if (oy) u = T(0.5) * (u + (ox ? T(0.5) * (c.d0 + c.d1) : c.d0));
+            v = T(0.5) * (v + u);
+        }
+        xv[0] = xv[0] + v;
+    } else {
+        constexpr int CV = VEC / 2, CW = CV + 1;
+        T w[CW];
+        auto seg = [&](const T (&t)[CV], int q) { return q < CV ? t[q] : lane_rot(t[0], 1); };
+#pragma unroll
+        for (int q = 0; q < CW; ++q) {
+            const T r00 = seg(c.t00, q);
+            T a0 = r00;
+            if (oy) a0 = T(0.5) * (r00 + seg(c.t01, q));
+            if (oz) {
+                const T r10 = seg(c.t10, q);
+                const T a1 = oy ? T(0.5) * (r10 + seg(c.t11, q)) : r10;
+                a0 = T(0.5) * (a0 + a1);
+            }
+            w[q] = a0;
+        }
+#pragma unroll
+        for (int q = 0; q < CV; ++q) {
+            xv[2 * q] = xv[2 * q] + w[q];
+            xv[2 * q + 1] = xv[2 * q + 1] + T(0.5) * (w[q] + w[q + 1]);
+        }
+    }
+}
+
+// The coarse rows of fine row (y, z) for a row split into S segments of
+// 64 VEC points, one per wave (VEC >= 2): the segment's VEC / 2 coarse values
+// per lane of each row, and the first coarse value after the segment
+// (periodic), which lane 63 needs where an unsplit row takes it from the
+// next lane.
+template <typename T, int VEC>
+struct CoarseSeg {
+    CoarseRows<T, VEC> r;
+    T h00, h01, h10, h11;
+};
+template <typename T, int VEC>
+__device__ __forceinline__ void coarse_load_seg(CoarseSeg<T, VEC>& c, const T* e, const RowGrid& gc, int y, int z,
+                                                int seg, int lane) {
+    constexpr int CV = VEC / 2, NC = 32 * VEC;  // coarse values per lane and per segment
+    const int Y = y >> 1, Z = z >> 1, oy = y & 1, oz = z & 1;
+    const size_t off = (size_t)seg * NC + (size_t)lane * CV;
+    const int hx = ((seg + 1) * NC) & gc.mask;
+    const T* r0 = e + gc.row(Y, Z);
+    ldrow<T, CV>(c.r.t00, r0 + off);
+    c.h00 = r0[hx];
+    if (oy) {
+        const T* r1 = e + gc.row(Y + 1, Z);
+        ldrow<T, CV>(c.r.t01, r1 + off);
+        c.h01 = r1[hx];
+    }
+    if (oz) {
+        const T* r2 = e + gc.row(Y, Z + 1);
+        ldrow<T, CV>(c.r.t10, r2 + off);
+        c.h10 = r2[hx];
+    }
+    if (oy && oz) {
+        const T* r3 = e + gc.row(Y + 1, Z + 1);
+        ldrow<T, CV>(c.r.t11, r3 + off);
+        c.h11 = r3[hx];
+    }
+}
+// prolong_add for a segment: the same interpolation and rounding, with lane
+// 63's coarse value after the segment taken from the halo.
+template <typename T, int VEC>
+__device__ __forceinline__ void prolong_add_seg(T (&xv)[VEC], const CoarseSeg<T, VEC>& c, int y, int z) {
+#pragma clang fp contract(off)
+    static_assert(VEC >= 2, "two fine points per lane at least");
+    const int oy = y & 1, oz = z & 1;
+    const bool last = (threadIdx.x & 63) == 63;
+    constexpr int CV = VEC / 2, CW = CV + 1;
+    T w[CW];
+    auto seg = [&](const T (&t)[CV], T h, int q) {
+        if (q < CV) return t[q];
+        const T r = lane_rot(t[0], 1);
+        return last ? h : r;
+    };
+#pragma unroll
+    for (int q = 0; q < CW; ++q) {
+        const T r00 = seg(c.r.t00, c.h00, q);
+        T a0 = r00;
+        if (oy) a0 = T(0.5) * (r00 + seg(c.r.t01, c.h01, q));
+        if (oz) {
+            const T r10 = seg(c.r.t10, c.h10, q);
+            const T a1 = oy ? T(0.5) * (r10 + seg(c.r.t11, c.h11, q)) : r10;
+            a0 = T(0.5) * (a0 + a1);
+        }
+        w[q] = a0;
+    }
+#pragma unroll
+    for (int q = 0; q < CV; ++q) {
+        xv[2 * q] = xv[2 * q] + w[q];
+        xv[2 * q + 1] = xv[2 * q + 1] + T(0.5) * (w[q] + w[q + 1]);
+    }
 }
 
 // One smoothing step at a point: x + a (x - xp) + cd (b - M x).
@@ -409,16 +580,27 @@ __global__ __launch_bounds__(kBlock) void k_outer_row(int n, TA ih2, const doubl
 // unsplit queues would not fit a wave's registers; each segment keeps its
 // slice of the LDS rows, and the x-neighbours across segment ends come from
 // one halo element loaded with each centre row, as in k_smooth_row.
-template <typename T, int VEC, int W, bool PREV, bool FROMB = false, bool PREVB = false, int S = 1>
+// PRO: the first step of a post-smoothing pass from x0 = x + P e (ec: the
+// coarse correction), x_prev = 0; x0 is formed row by row as the rows arrive
+// and never written, and the x-halo of a segment comes from its neighbour's
+// slot of the LDS row.  PREVP: the second step of that pass, x_prev = x0
+// formed pointwise from the old iterate (xprev) and ec.  Both use the
+// prolongation of k_prolong_row, same bits.
+template <typename T, int VEC, int W, bool PREV, bool FROMB = false, bool PREVB = false, int S = 1, bool PRO = false,
+          bool PREVP = false>
 __global__ __launch_bounds__(64 * W * S) void k_smooth_lds(int n, T ih2, const T* x, const T* xprev,
                                                            const T* __restrict__ b, T* out, T a, T cd, int nz,
-                                                           int nyb, T cd0) {
+                                                           int nyb, T cd0, const T* __restrict__ ec) {
     static_assert(!(FROMB && PREV), "a step from b has no x_prev");
     static_assert(!PREVB || (PREV && !FROMB), "PREVB forms x_prev from b");
-    constexpr bool LDP = PREV && !PREVB;  // x_prev is loaded
+    static_assert(!PRO || (!PREV && !FROMB && VEC >= 2), "the prolongation starts a pass, x_prev = 0");
+    static_assert(!PREVP || (PREV && !PREVB && VEC >= 2), "PREVP forms x_prev from x and e");
+    constexpr bool LDP = PREV && !PREVB && !PREVP;  // x_prev is loaded as it is
     constexpr int NR = 64 * VEC, NF = NR * S;
+    using Coarse = typename std::conditional<(S > 1), CoarseSeg<T, VEC>, CoarseRows<T, VEC>>::type;
     __shared__ T rows[2][W + 2][NF];
     const RowGrid g{NF, NF - 1};
+    const RowGrid gc{NF / 2, NF / 2 - 1};  // PRO / PREVP: the coarse grid of ec
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int yb = lb % nyb, zc = lb / nyb;
     const int wv = wave_id();
@@ -431,30 +613,62 @@ __global__ __launch_bounds__(64 * W * S) void k_smooth_lds(int n, T ih2, const T
     const int hoff = S > 1 ? seg_halo<VEC, S>(seg, lane) : 0;
     const bool lo = w == 0, hi = w == W - 1;
     const int yh = lo ? y0 - 1 : y0 + W;  // halo row of the edge waves
+    auto cload = [&](Coarse& cr, int yy, int zz) {
+        if constexpr (S > 1) coarse_load_seg<T, VEC>(cr, ec, gc, yy, zz, seg, lane);
+        else coarse_load<T, VEC>(cr, ec, gc, yy, zz, lane);
+    };
+    auto padd = [&](T (&v)[VEC], const Coarse& cr, int yy, int zz) {
+        if constexpr (S > 1) prolong_add_seg<T, VEC>(v, cr, yy, zz);
+        else prolong_add<T, VEC>(v, cr, yy, zz);
+    };
     T zm[VEC], c[VEC], zp[VEC], bb[VEC], pp[VEC], h[VEC];
-    T hc = T(0), hp = T(0);  // x-halo of c and zp (S > 1)
+    T hc = T(0), hp = T(0);  // x-halo of c and zp (S > 1, not PRO)
     ldrow<T, VEC>(zm, x + g.row(y, z0 - 1) + off);
     ldrow<T, VEC>(c, x + g.row(y, z0) + off);
     ldrow<T, VEC>(zp, x + g.row(y, z0 + 1) + off);
-    if constexpr (S > 1) {
+    if constexpr (S > 1 && !PRO) {
         hc = x[g.row(y, z0) + hoff];
         hp = x[g.row(y, z0 + 1) + hoff];
     }
     if constexpr (!FROMB) ldrow<T, VEC>(bb, b + g.row(y, z0) + off);
-    if constexpr (LDP) ldrow<T, VEC>(pp, xprev + g.row(y, z0) + off);
+    if constexpr (LDP || PREVP) ldrow<T, VEC>(pp, xprev + g.row(y, z0) + off);
     if (lo || hi) ldrow<T, VEC>(h, x + g.row(yh, z0) + off);
+    if constexpr (PRO) {  // x0 = x + P e on the rows loaded so far
+        Coarse cr;
+        cload(cr, y, z0 - 1);
+        padd(zm, cr, y, z0 - 1);
+        cload(cr, y, z0);
+        padd(c, cr, y, z0);
+        cload(cr, y, z0 + 1);
+        padd(zp, cr, y, z0 + 1);
+        if (lo || hi) {
+            cload(cr, yh, z0);
+            padd(h, cr, yh, z0);
+        }
+    }
+    if constexpr (PREVP) {
+        Coarse cr;
+        cload(cr, y, z0);
+        padd(pp, cr, y, z0);
+    }
     for (int k = 0; k < nz; ++k) {
         const int z = z0 + k;
         const int buf = k & 1;
         T zpp[VEC], bn[VEC], pn[VEC], hn[VEC];
         T hpp = T(0);
+        Coarse cpp, chn, cpn;  // PRO: coarse rows of zpp and hn; PREVP: of pn
         const bool more = k + 1 < nz;
         if (more) {
             ldrow<T, VEC>(zpp, x + g.row(y, z + 2) + off);
-            if constexpr (S > 1) hpp = x[g.row(y, z + 2) + hoff];
+            if constexpr (S > 1 && !PRO) hpp = x[g.row(y, z + 2) + hoff];
             if constexpr (!FROMB) ldrow<T, VEC>(bn, b + g.row(y, z + 1) + off);
-            if constexpr (LDP) ldrow<T, VEC>(pn, xprev + g.row(y, z + 1) + off);
+            if constexpr (LDP || PREVP) ldrow<T, VEC>(pn, xprev + g.row(y, z + 1) + off);
             if (lo || hi) ldrow<T, VEC>(hn, x + g.row(yh, z + 1) + off);
+            if constexpr (PRO) {
+                cload(cpp, y, z + 2);
+                if (lo || hi) cload(chn, yh, z + 1);
+            }
+            if constexpr (PREVP) cload(cpn, y, z + 1);
         }
         lds_strow<T, VEC>(rows[buf][w + 1] + seg * NR, lane, c);
         if (lo) lds_strow<T, VEC>(rows[buf][0] + seg * NR, lane, h);
@@ -463,6 +677,11 @@ __global__ __launch_bounds__(64 * W * S) void k_smooth_lds(int n, T ih2, const T
         T ym[VEC], yp[VEC];
         lds_ldrow<T, VEC>(ym, rows[buf][w] + seg * NR, lane);
         lds_ldrow<T, VEC>(yp, rows[buf][w + 2] + seg * NR, lane);
+        if constexpr (PRO && S > 1) {  // x0 beyond the segment: the neighbour segment's slot
+            const T* row = rows[buf][w + 1];
+            hc = lane < 32 ? lds_elem<T, VEC>(row + ((seg + S - 1) % S) * NR, NR - 1)
+                           : lds_elem<T, VEC>(row + ((seg + 1) % S) * NR, 0);
+        }
         T Mx[VEC], o[VEC];
         if constexpr (FROMB) {  // x = cd0 b on the row and its neighbours; b = the raw centre row
             T fc[VEC], fym[VEC], fyp[VEC], fzm[VEC], fzp[VEC];
@@ -487,13 +706,18 @@ __global__ __launch_bounds__(64 * W * S) void k_smooth_lds(int n, T ih2, const T
         }
         strow<T, VEC>(out + g.row(y, z) + off, o);
         if (more) {
+            if constexpr (PRO) {
+                padd(zpp, cpp, y, z + 2);
+                if (lo || hi) padd(hn, chn, yh, z + 1);
+            }
+            if constexpr (PREVP) padd(pn, cpn, y, z + 1);
             copyrow(zm, c);
             copyrow(c, zp);
             copyrow(zp, zpp);
             hc = hp;
             hp = hpp;
             if constexpr (!FROMB) copyrow(bb, bn);
-            if constexpr (LDP) copyrow(pp, pn);
+            if constexpr (LDP || PREVP) copyrow(pp, pn);
             if (lo || hi) copyrow(h, hn);
         }
     }
@@ -702,164 +926,6 @@ __global__ __launch_bounds__(64 * NW) void k_smooth2_lds(int n, T ih2, const T* 
         for (int j = 0; j < NZC + 2; ++j, ++z1) plane(j);
     } else {
         for (int j = 0; j < steps; ++j, ++z1) plane(j);
-    }
-}
-
-// The coarse rows the trilinear prolongation of fine row (y, z) reads (VEC >= 2):
-// (Y, Z), and (Y+1, Z), (Y, Z+1), (Y+1, Z+1) where y, z are odd; loaded raw so
-// that a prefetch is not waited for until the values are combined.
-// VEC == 1 (64^3): lane l holds fine x = l, i.e. coarse X = l / 2, and reads
-// the coarse values X and X + 1 of each row itself.
-template <typename T, int VEC>
-struct CoarseRows {
-    T t00[VEC / 2], t01[VEC / 2], t10[VEC / 2], t11[VEC / 2];
-};
-template <typename T>
-struct CoarseRows<T, 1> {
-    T a, a1, b0, b1, c0, c1, d0, d1;  // rows (Y, Z), (Y+1, Z), (Y, Z+1), (Y+1, Z+1) at X, X + 1
-};
-template <typename T, int VEC>
-__device__ __forceinline__ void coarse_load(CoarseRows<T, VEC>& c, const T* e, const RowGrid& gc, int y, int z,
-                                            int lane) {
-    const int Y = y >> 1, Z = z >> 1, oy = y & 1, oz = z & 1;
-    if constexpr (VEC == 1) {
-        const int X = lane >> 1, ox = lane & 1, m = gc.mask;
-        const T* r0 = e + gc.row(Y, Z);
-        c.a = r0[X & m];
-        if (ox) c.a1 = r0[(X + 1) & m];
-        if (oy) {
-            const T* r1 = e + gc.row(Y + 1, Z);
-            c.b0 = r1[X & m];
-            if (ox) c.b1 = r1[(X + 1) & m];
-        }
-        if (oz) {
-            const T* r2 = e + gc.row(Y, Z + 1);
-            c.c0 = r2[X & m];
-            if (ox) c.c1 = r2[(X + 1) & m];
-            if (oy) {
-                const T* r3 = e + gc.row(Y + 1, Z + 1);
-                c.d0 = r3[X & m];
-                if (ox) c.d1 = r3[(X + 1) & m];
-            }
-        }
-    } else {
-        constexpr int CV = VEC / 2;
-        const size_t off = (size_t)lane * CV;
-        ldrow<T, CV>(c.t00, e + gc.row(Y, Z) + off);
-        if (oy) ldrow<T, CV>(c.t01, e + gc.row(Y + 1, Z) + off);
-        if (oz) ldrow<T, CV>(c.t10, e + gc.row(Y, Z + 1) + off);
-        if (oy && oz) ldrow<T, CV>(c.t11, e + gc.row(Y + 1, Z + 1) + off);
-    }
-}
-// xv += P e on fine row (y, z): interpolate in y, then z, then x (the x + 1
-// coarse value from the next lane).  Rounding written out: every kernel that
-// prolongs (the prolongation kernel, the fused post-smoothing pass) gets the
-// same bits.
-template <typename T, int VEC>
-__device__ __forceinline__ void prolong_add(T (&xv)[VEC], const CoarseRows<T, VEC>& c, int y, int z) {
-#pragma clang fp contract(off)
-    const int oy = y & 1, oz = z & 1;
-    if constexpr (VEC == 1) {  // interpolate in x, then y, then z
-        const int ox = threadIdx.x & 1;
-        T v = ox ? T(0.5) * (c.a + c.a1) : c.a;
-        if (oy) v = T(0.5) * (v + (ox ? T(0.5) * (c.b0 + c.b1) : c.b0));
-        if (oz) {
-            T u = ox ? T(0.5) * (c.c0 + c.c1) : c.c0;
-            if (oy) u = T(0.5) * (u + (ox ? T(0.5) * (c.d0 + c.d1) : c.d0));
-            v = T(0.5) * (v + u);
-        }
-        xv[0] = xv[0] + v;
-    } else {
-        constexpr int CV = VEC / 2, CW = CV + 1;
-        T w[CW];
-        auto seg = [&](const T (&t)[CV], int q) { return q < CV ? t[q] : lane_rot(t[0], 1); };
-#pragma unroll
-        for (int q = 0; q < CW; ++q) {
-            const T r00 = seg(c.t00, q);
-            T a0 = r00;
-            if (oy) a0 = T(0.5) * (r00 + seg(c.t01, q));
-            if (oz) {
-                const T r10 = seg(c.t10, q);
-                const T a1 = oy ? T(0.5) * (r10 + seg(c.t11, q)) : r10;
-                a0 = T(0.5) * (a0 + a1);
-            }
-            w[q] = a0;
-        }
-#pragma unroll
-        for (int q = 0; q < CV; ++q) {
-            xv[2 * q] = xv[2 * q] + w[q];
-            xv[2 * q + 1] = xv[2 * q + 1] + T(0.5) * (w[q] + w[q + 1]);
-        }
-    }
-}
-
-// The coarse rows of fine row (y, z) for a row split into S segments of
-// 64 VEC points, one per wave (VEC >= 2): the segment's VEC / 2 coarse values
-// per lane of each row, and the first coarse value after the segment
-// (periodic), which lane 63 needs where an unsplit row takes it from the
-// next lane.
-template <typename T, int VEC>
-struct CoarseSeg {
-    CoarseRows<T, VEC> r;
-    T h00, h01, h10, h11;
-};
-template <typename T, int VEC>
-__device__ __forceinline__ void coarse_load_seg(CoarseSeg<T, VEC>& c, const T* e, const RowGrid& gc, int y, int z,
-                                                int seg, int lane) {
-    constexpr int CV = VEC / 2, NC = 32 * VEC;  // coarse values per lane and per segment
-    const int Y = y >> 1, Z = z >> 1, oy = y & 1, oz = z & 1;
-    const size_t off = (size_t)seg * NC + (size_t)lane * CV;
-    const int hx = ((seg + 1) * NC) & gc.mask;
-    const T* r0 = e + gc.row(Y, Z);
-    ldrow<T, CV>(c.r.t00, r0 + off);
-    c.h00 = r0[hx];
-    if (oy) {
-        const T* r1 = e + gc.row(Y + 1, Z);
-        ldrow<T, CV>(c.r.t01, r1 + off);
-        c.h01 = r1[hx];
-    }
-    if (oz) {
-        const T* r2 = e + gc.row(Y, Z + 1);
-        ldrow<T, CV>(c.r.t10, r2 + off);
-        c.h10 = r2[hx];
-    }
-    if (oy && oz) {
-        const T* r3 = e + gc.row(Y + 1, Z + 1);
-        ldrow<T, CV>(c.r.t11, r3 + off);
-        c.h11 = r3[hx];
-    }
-}
-// prolong_add for a segment: the same interpolation and rounding, with lane
-// 63's coarse value after the segment taken from the halo.
-template <typename T, int VEC>
-__device__ __forceinline__ void prolong_add_seg(T (&xv)[VEC], const CoarseSeg<T, VEC>& c, int y, int z) {
-#pragma clang fp contract(off)
-    static_assert(VEC >= 2, "two fine points per lane at least");
-    const int oy = y & 1, oz = z & 1;
-    const bool last = (threadIdx.x & 63) == 63;
-    constexpr int CV = VEC / 2, CW = CV + 1;
-    T w[CW];
-    auto seg = [&](const T (&t)[CV], T h, int q) {
-        if (q < CV) return t[q];
-        const T r = lane_rot(t[0], 1);
-        return last ? h : r;
-    };
-#pragma unroll
-    for (int q = 0; q < CW; ++q) {
-        const T r00 = seg(c.r.t00, c.h00, q);
-        T a0 = r00;
-        if (oy) a0 = T(0.5) * (r00 + seg(c.r.t01, c.h01, q));
-        if (oz) {
-            const T r10 = seg(c.r.t10, c.h10, q);
-            const T a1 = oy ? T(0.5) * (r10 + seg(c.r.t11, c.h11, q)) : r10;
-            a0 = T(0.5) * (a0 + a1);
-        }
-        w[q] = a0;
-    }
-#pragma unroll
-    for (int q = 0; q < CV; ++q) {
-        xv[2 * q] = xv[2 * q] + w[q];
-        xv[2 * q + 1] = xv[2 * q + 1] + T(0.5) * (w[q] + w[q + 1]);
     }
 }
 
@@ -1708,35 +1774,55 @@ inline bool step_seg_lds(int n, size_t elem) {
     const int S = row_segments(n, elem);
     return S > 1 && kStepSegWaves % S == 0 && 2ull * (kStepSegWaves / S + 2) * n * elem <= kStepSegLdsBudget;
 }
+// The first two post-smoothing steps with the prolongation formed on the fly
+// (steps of the split LDS kernel with the coarse rows as well): blocks of 8
+// waves, where the coarse rows fit the registers without spilling.
+constexpr int kStepProWaves = 8;
+bool step_pro_applies(int n, size_t elem) {
+    return step_seg_lds(n, elem) && kStepProWaves % row_segments(n, elem) == 0;
+}
 
-// Single smoothing step, in one of three modes: MODE_PLAIN (x, [x_prev], b),
+// Single smoothing step, in one of five modes: MODE_PLAIN (x, [x_prev], b),
 // MODE_FROMB (step 1 of a pass from zero, from b alone: the iterate is the
-// pointwise first step cd0 b, x_prev = 0) and MODE_PREVB (step 2 of such a
-// pass: x_prev is cd0 b, formed from the b rows).
-enum StepMode { MODE_PLAIN, MODE_FROMB, MODE_PREVB };
+// pointwise first step cd0 b, x_prev = 0), MODE_PREVB (step 2 of such a
+// pass: x_prev is cd0 b, formed from the b rows), MODE_PRO (step 0 of a
+// post-smoothing pass from x + P e, formed on the fly) and MODE_PREVP (step
+// 1 of that pass: x_prev = x + P e formed pointwise from the old iterate).
+enum StepMode { MODE_PLAIN, MODE_FROMB, MODE_PREVB, MODE_PRO, MODE_PREVP };
 template <typename T, int MODE>
 hipError_t launch_step_mode(int n, double ih2, const T* x, const T* xprev, const T* b, T* out, double a, double cd,
-                            double cd0, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-    constexpr bool FB = MODE == MODE_FROMB, PB = MODE == MODE_PREVB;
+                            double cd0, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, const T* ec = nullptr) {
+    constexpr bool FB = MODE == MODE_FROMB, PB = MODE == MODE_PREVB, PR = MODE == MODE_PRO,
+                   PP = MODE == MODE_PREVP;
     int nz, nyb, blocks;
     // Rows over 2 KB with LDS room for 16 / S of them: split into 2 KB
-    // segments, one wave each, the rows still shared through LDS.
+    // segments, one wave each, the rows still shared through LDS.  The steps
+    // that prolong on the fly hold the coarse rows as well: blocks of 8 waves.
     if (x != nullptr && step_seg_lds(n, sizeof(T))) {
         const int S = row_segments(n, sizeof(T));
-        nyb = n / (kStepSegWaves / S);
+        const int waves = (PR || PP) ? kStepProWaves : kStepSegWaves;
+        nyb = n / (waves / S);
         nz = n;
         while (nz > 4 && nyb * (n / nz) < kStepSegTarget) nz >>= 1;
         blocks = nyb * (n / nz);
 #define MG_STEP_SEGLDS(SS)                                                                                        \
     DISPATCH_SEG(n, SS, {                                                                                         \
-        constexpr int Wr = kStepSegWaves / SS;                                                                    \
+        constexpr int Wr = ((PR || PP) ? kStepProWaves : kStepSegWaves) / SS;                                     \
         if constexpr (2ull * (Wr + 2) * 64 * VEC * SS * sizeof(T) <= kStepSegLdsBudget) {                         \
-            if (xprev == nullptr && !PB)                                                                          \
+            if constexpr (PR)                                                                                     \
+                MG_LAUNCH((k_smooth_lds<T, VEC, Wr, false, false, false, SS, true>), dim3(blocks),                \
+                          dim3(64 * Wr * SS), s, ev0, ev1, n, (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb,     \
+                          (T)cd0, ec);                                                                            \
+            else if constexpr (PP)                                                                                \
+                MG_LAUNCH((k_smooth_lds<T, VEC, Wr, true, false, false, SS, false, true>), dim3(blocks),          \
+                          dim3(64 * Wr * SS), s, ev0, ev1, n, (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb,     \
+                          (T)cd0, ec);                                                                            \
+            else if (xprev == nullptr && !PB)                                                                     \
                 MG_LAUNCH((k_smooth_lds<T, VEC, Wr, false, FB, false, SS>), dim3(blocks), dim3(64 * Wr * SS), s,  \
-                          ev0, ev1, n, (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb, (T)cd0);                   \
+                          ev0, ev1, n, (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb, (T)cd0, ec);               \
             else if constexpr (!FB)                                                                               \
                 MG_LAUNCH((k_smooth_lds<T, VEC, Wr, true, false, PB, SS>), dim3(blocks), dim3(64 * Wr * SS), s,   \
-                          ev0, ev1, n, (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb, (T)cd0);                   \
+                          ev0, ev1, n, (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb, (T)cd0, ec);               \
         } else {                                                                                                  \
             return hipErrorInvalidValue;                                                                          \
         }                                                                                                         \
@@ -1749,6 +1835,7 @@ hipError_t launch_step_mode(int n, double ih2, const T* x, const T* xprev, const
 #undef MG_STEP_SEGLDS
         return hipGetLastError();
     }
+    if constexpr (PR || PP) return hipErrorInvalidValue;  // split rows with LDS only
     // Row sharing through LDS pays where the level's fields exceed the 256 MB
     // Infinity Cache (n >= 512); below that the y-halo rows already hit in
     // cache and the per-plane barrier costs more than it saves (measured).
@@ -1762,10 +1849,10 @@ hipError_t launch_step_mode(int n, double ih2, const T* x, const T* xprev, const
             if constexpr (2ull * (Wv + 2) * 64 * VEC * sizeof(T) <= kLdsBudget) {
                 if (xprev == nullptr && !PB)
                     MG_LAUNCH((k_smooth_lds<T, VEC, Wv, false, FB>), dim3(blocks), dim3(64 * Wv), s, ev0, ev1, n,
-                              (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb, (T)cd0);
+                              (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb, (T)cd0, ec);
                 else if constexpr (!FB)
                     MG_LAUNCH((k_smooth_lds<T, VEC, Wv, true, false, PB>), dim3(blocks), dim3(64 * Wv), s, ev0,
-                              ev1, n, (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb, (T)cd0);
+                              ev1, n, (T)ih2, x, xprev, b, out, (T)a, (T)cd, nz, nyb, (T)cd0, ec);
             }
         })
         return hipGetLastError();
@@ -1825,6 +1912,24 @@ hipError_t launch_smooth_prevb_row(int n, double ih2, const T* x, const T* b, T*
                                    double cd0, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (x == nullptr || b == nullptr || out == x || out == b) return hipErrorInvalidValue;
     return launch_step_mode<T, MODE_PREVB>(n, ih2, x, nullptr, b, out, a2, cd2, cd0, s, ev0, ev1);
+}
+
+// Step 0 of a post-smoothing pass from x0 = x + P e (x_prev = 0), x0 formed
+// on the fly: out = x1.  Rows over 2 KB only (step_pro_applies).
+template <typename T>
+hipError_t launch_smooth_pro_row(int n, double ih2, const T* x, const T* e, const T* b, T* out, double a0,
+                                 double cd0, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (!step_pro_applies(n, sizeof(T)) || !x || !e || !b || out == x || out == b) return hipErrorInvalidValue;
+    return launch_step_mode<T, MODE_PRO>(n, ih2, x, nullptr, b, out, a0, cd0, 0.0, s, ev0, ev1, e);
+}
+
+// Step 1 of that pass: x_prev = x0 = xold + P e formed pointwise; out may be xold.
+template <typename T>
+hipError_t launch_smooth_prevp_row(int n, double ih2, const T* x1, const T* xold, const T* e, const T* b, T* out,
+                                   double a1, double cd1, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (!step_pro_applies(n, sizeof(T)) || !x1 || !xold || !e || !b || out == x1 || out == b)
+        return hipErrorInvalidValue;
+    return launch_step_mode<T, MODE_PREVP>(n, ih2, x1, xold, b, out, a1, cd1, 0.0, s, ev0, ev1, e);
 }
 
 // Waves per block of the two-step kernel (W = waves - 2 output rows): 8
@@ -2265,6 +2370,16 @@ template hipError_t launch_smooth_fromb_row<float>(int, double, const float*, fl
                                                    hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_smooth_fromb_row<double>(int, double, const double*, double*, double, double, double,
                                                     hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_smooth_pro_row<float>(int, double, const float*, const float*, const float*, float*,
+                                                 double, double, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_smooth_pro_row<double>(int, double, const double*, const double*, const double*, double*,
+                                                  double, double, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_smooth_prevp_row<float>(int, double, const float*, const float*, const float*,
+                                                   const float*, float*, double, double, hipStream_t, hipEvent_t,
+                                                   hipEvent_t);
+template hipError_t launch_smooth_prevp_row<double>(int, double, const double*, const double*, const double*,
+                                                    const double*, double*, double, double, hipStream_t, hipEvent_t,
+                                                    hipEvent_t);
 template hipError_t launch_smooth_prevb_row<float>(int, double, const float*, const float*, float*, double, double,
                                                    double, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_smooth_prevb_row<double>(int, double, const double*, const double*, double*, double,

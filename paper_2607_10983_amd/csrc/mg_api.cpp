@@ -360,6 +360,16 @@ inline bool from_zero_triple(const mg_ctx* c, int l) {
 
 // pro_e (not from zero): the pass starts from x + P pro_e, formed by its
 // first kernel (a pair on split rows), instead of a prolongation launch.
+// Level l without two-step kernels (rows over 2 KB, row kernels with LDS)
+// starts its post-smoothing pass (Chebyshev, at least two steps) with a step
+// that forms x + P e itself and a step that forms that x_prev pointwise, in
+// place of a prolongation launch.
+inline bool post_step_fused(const mg_ctx* c, int l, size_t elem) {
+    const Level& L = c->lev[l];
+    return c->use_pairs && !c->var && c->p.smoother == MG_CHEBYSHEV && L.a.size() >= 2 && L.x[2] == nullptr &&
+           step_pro_applies(L.n, elem);
+}
+
 // Level l without two-step kernels (rows over 2 KB) starts a pass from zero
 // of at least three Chebyshev steps with one step read from b alone and one
 // step whose x_prev (the pointwise first step) is formed from b, so the
@@ -385,6 +395,7 @@ mg_status smooth_level(mg_ctx* c, int l, bool from_zero, const T* pro_e = nullpt
     // the last two steps of the pass run as one two-step kernel where it exists
     const bool pairs = c->use_pairs && L.x[2] != nullptr && !c->var;
     bool prev_b = false;  // x_{k-1} is the pointwise first step c0 D^-1 b, formed by the next kernel
+    bool prev_p = false;  // x_{k-1} is x_old + P pro_e (x_old in bufs[prev]), formed by the next kernel
     for (int k = 0; k < v; ++k) {
         double bytes = 0.0;
         if (k == 0 && from_zero && l == 0 && c->x1_ready) {  // formed by the outer residual kernel
@@ -411,12 +422,32 @@ mg_status smooth_level(mg_ctx* c, int l, bool from_zero, const T* pro_e = nullpt
         const bool triple3 = k == 0 && !from_zero && cheb && v == 3 && c->use_pairs && !c->var &&
                              triple_kernels_apply(L.n, sizeof(T));
         const bool pair = pairs && rem >= 2 && rem % 2 == 0 && !(k == 0 && from_zero) && !(need_y1 && has_prev);
-        if (k == 0 && pro_e != nullptr && !pair) return MG_ERR_INVALID;  // the caller checked that a pair starts
+        // pro_e: a pair starts the pass (split rows), or a step that prolongs on the fly (rows over 2 KB)
+        const bool pro_step = k == 0 && pro_e != nullptr && !pair;
+        if (pro_step && !post_step_fused(c, l, sizeof(T))) return MG_ERR_INVALID;
         const int kind = triple3 ? MG_TIME_TRIPLE : (pair || triple) && !fromb ? MG_TIME_PAIR : MG_TIME_STEP;
         hipEvent_t ev0, ev1;
         mg_status st = time_events(c, fine, kind, &ev0, &ev1);
         if (st != MG_OK) return st;
-        if (stepb) {  // steps 0 and 1 from b alone (b -> x_2); the next step forms x_prev from b
+        if (pro_step) {  // step 0 from x0 = x + P e formed on the fly; x (the old iterate) is kept
+            const double D = -6.0 * L.ih2;
+            const int out = other(cur);
+            HIPCHK(c, launch_smooth_pro_row<T>(L.n, L.ih2, bufs[cur], pro_e, (const T*)L.b, bufs[out], L.a[0],
+                                               L.c[0] / D, c->stream, ev0, ev1));
+            bytes = (3.0 + 1.0 / 8.0) * fbytes;  // x, e, b; x_1
+            prev = cur;
+            prev_p = true;
+            cur = out;
+        } else if (prev_p) {  // step 1, x_prev = x0 formed from the old iterate and e; out replaces the old iterate
+            const double D = -6.0 * L.ih2;
+            const int out = prev;
+            HIPCHK(c, launch_smooth_prevp_row<T>(L.n, L.ih2, bufs[cur], bufs[prev], pro_e, (const T*)L.b,
+                                                 bufs[out], L.a[k], L.c[k] / D, c->stream, ev0, ev1));
+            bytes = (4.0 + 1.0 / 8.0) * fbytes;  // x_1, x, e, b; x_2
+            prev_p = false;
+            prev = cur;
+            cur = out;
+        } else if (stepb) {  // steps 0 and 1 from b alone (b -> x_2); the next step forms x_prev from b
             const double D = -6.0 * L.ih2;
             HIPCHK(c, launch_smooth_fromb_row<T>(L.n, L.ih2, (const T*)L.b, bufs[0], L.a[1], L.c[1] / D,
                                                  L.c[0] / D, c->stream, ev0, ev1));
@@ -613,7 +644,8 @@ mg_status post_level(mg_ctx* c, int l) {
         // x, b read, x_3 written, e read once per coarse point
         return time_end(c, fine, MG_TIME_TRIPLE, (3.0 + 1.0 / 8.0) * (double)L.N * sizeof(T));
     }
-    if (post_pair_fused(c, l, sizeof(T)))  // the prolongation runs inside the pass's first pair
+    // the prolongation runs inside the pass's first pair, or its first two steps
+    if (post_pair_fused(c, l, sizeof(T)) || post_step_fused(c, l, sizeof(T)))
         return smooth_level<T>(c, l, false, (const T*)Lc.x[Lc.cur]);
     if ((st = time_events(c, fine, MG_TIME_TRANSFER, &ev0, &ev1)) != MG_OK) return st;
     HIPCHK(c, launch_prolong_add<T>(L.n, (const T*)Lc.x[Lc.cur], (T*)L.x[L.cur], c->stream, ev0, ev1));
