@@ -1775,11 +1775,15 @@ inline bool step_seg_lds(int n, size_t elem) {
     return S > 1 && kStepSegWaves % S == 0 && 2ull * (kStepSegWaves / S + 2) * n * elem <= kStepSegLdsBudget;
 }
 // The first two post-smoothing steps with the prolongation formed on the fly
-// (steps of the split LDS kernel with the coarse rows as well): blocks of 8
-// waves, where the coarse rows fit the registers without spilling.
-constexpr int kStepProWaves = 8;
+// (steps of the split LDS kernel with the coarse rows as well).  The step
+// that prolongs fits 128 VGPRs and takes 16-wave blocks like the plain steps
+// (1024^3 FP64 65.9 -> 65.2 ms per cycle against 8 waves); the step that
+// forms x_prev = x + P e needs more and takes blocks of 8 waves (16 spilled).
+constexpr int kStepProWaves = 16;
+constexpr int kStepPrevpWaves = 8;
 bool step_pro_applies(int n, size_t elem) {
-    return step_seg_lds(n, elem) && kStepProWaves % row_segments(n, elem) == 0;
+    const int S = row_segments(n, elem);
+    return step_seg_lds(n, elem) && kStepProWaves % S == 0 && kStepPrevpWaves % S == 0;
 }
 
 // Single smoothing step, in one of five modes: MODE_PLAIN (x, [x_prev], b),
@@ -1800,14 +1804,14 @@ hipError_t launch_step_mode(int n, double ih2, const T* x, const T* xprev, const
     // that prolong on the fly hold the coarse rows as well: blocks of 8 waves.
     if (x != nullptr && step_seg_lds(n, sizeof(T))) {
         const int S = row_segments(n, sizeof(T));
-        const int waves = (PR || PP) ? kStepProWaves : kStepSegWaves;
+        const int waves = PR ? kStepProWaves : PP ? kStepPrevpWaves : kStepSegWaves;
         nyb = n / (waves / S);
         nz = n;
         while (nz > 4 && nyb * (n / nz) < kStepSegTarget) nz >>= 1;
         blocks = nyb * (n / nz);
 #define MG_STEP_SEGLDS(SS)                                                                                        \
     DISPATCH_SEG(n, SS, {                                                                                         \
-        constexpr int Wr = ((PR || PP) ? kStepProWaves : kStepSegWaves) / SS;                                     \
+        constexpr int Wr = (PR ? kStepProWaves : PP ? kStepPrevpWaves : kStepSegWaves) / SS;                      \
         if constexpr (2ull * (Wr + 2) * 64 * VEC * SS * sizeof(T) <= kStepSegLdsBudget) {                         \
             if constexpr (PR)                                                                                     \
                 MG_LAUNCH((k_smooth_lds<T, VEC, Wr, false, false, false, SS, true>), dim3(blocks),                \
