@@ -44,15 +44,15 @@ HBM_PEAK_GBPS = 8000.0
 # Reported only while the source of the row kernels and their launch shapes
 # is the one the counters were taken on.
 TRAFFIC = {
-    "device_code_sha256": "e8d4cc40916f02b8e6b710085bd079dca9eaecf604c9b96b19d4c993e204fcc6",
+    "device_code_sha256": "773a150b201bd5065fa9ba3e160732336956a75b12d2175b3bec45019a109d0d",
     "bytes_per_launch": {
         # the benchmark step: outer (with the first-cycle variant), pass from
         # zero (b -> x3), prolongation + three steps, residual + restriction
-        (256, 3): {"k_outer_lds": 536994262, "k_smooth2_lds": 151769617, "k_smooth3p_lds": 238198864,
-                   "k_rr_row": 159442036},
+        (256, 3): {"k_outer_lds": 536997728, "k_smooth2_lds": 152094815, "k_smooth3p_lds": 238171692,
+                   "k_rr_row": 159438088},
         # the 512^3 leg: step from b, the three pairs, outer, residual + restriction
-        (512, 4): {"k_smooth_row": 1137125238, "k_smooth2_lds": 2275540746, "k_outer_lds": 4445826031,
-                   "k_rr_row": 1408600711},
+        (512, 4): {"k_smooth_row": 1137134872, "k_smooth2_lds": 2278263824, "k_outer_lds": 4445412712,
+                   "k_rr_row": 1406540835},
     },
 }
 
