@@ -44,7 +44,7 @@ HBM_PEAK_GBPS = 8000.0
 # Reported only while the source of the row kernels and their launch shapes
 # is the one the counters were taken on.
 TRAFFIC = {
-    "device_code_sha256": "773a150b201bd5065fa9ba3e160732336956a75b12d2175b3bec45019a109d0d",
+    "device_code_sha256": "e149ac085bc5783ea82aeca18837be13dc423d055496993fae93aba8b2cb8eed",
     "bytes_per_launch": {
         # the benchmark step: outer (with the first-cycle variant), pass from
         # zero (b -> x3), prolongation + three steps, residual + restriction

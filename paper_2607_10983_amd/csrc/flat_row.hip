@@ -29,42 +29,6 @@ namespace {
 constexpr int kWaves = 4;
 constexpr int kBlock = 64 * kWaves;
 
-// A row's copy in LDS.  Rows of at most 16 bytes per lane keep the global
-// layout (lane l at element l * VEC).  Longer rows are stored in 16-byte
-// pieces with piece j of every lane together (lane l's piece j at element
-// (j * 64 + l) * P), so that every 16-byte LDS access of a wave covers
-// consecutive addresses instead of a lane stride of VEC elements, which
-// conflicts on the LDS banks.
-template <typename T, int VEC>
-__device__ __forceinline__ void lds_strow(T* row, int lane, const T (&v)[VEC]) {
-    constexpr int B = VEC * (int)sizeof(T);
-    if constexpr (B <= 16) {
-        strow<T, VEC>(row + (size_t)lane * VEC, v);
-    } else {
-        constexpr int P = 16 / (int)sizeof(T);
-#pragma unroll
-        for (int j = 0; j < VEC / P; ++j) {
-            v4i t;
-            __builtin_memcpy(&t, &v[j * P], 16);
-            *reinterpret_cast<v4i*>(row + (size_t)(j * 64 + lane) * P) = t;
-        }
-    }
-}
-template <typename T, int VEC>
-__device__ __forceinline__ void lds_ldrow(T (&v)[VEC], const T* row, int lane) {
-    constexpr int B = VEC * (int)sizeof(T);
-    if constexpr (B <= 16) {
-        ldrow<T, VEC>(v, row + (size_t)lane * VEC);
-    } else {
-        constexpr int P = 16 / (int)sizeof(T);
-#pragma unroll
-        for (int j = 0; j < VEC / P; ++j) {
-            const v4i t = *reinterpret_cast<const v4i*>(row + (size_t)(j * 64 + lane) * P);
-            __builtin_memcpy(&v[j * P], &t, 16);
-        }
-    }
-}
-
 // Element i (0 <= i < 64 VEC) of a row copy written by lds_strow.
 template <typename T, int VEC>
 __device__ __forceinline__ T lds_elem(const T* row, int i) {

@@ -26,6 +26,7 @@ namespace {
 
 constexpr int kWaves = 4;
 constexpr int kBlock = 64 * kWaves;
+constexpr bool kVarLds = true;  // smoothing steps share the iterate's rows through LDS (n >= 128)
 
 // coefficient row in compute precision T
 template <typename T, typename TC, int VEC>
@@ -313,6 +314,91 @@ __global__ __launch_bounds__(kBlock) void k_var_smooth_row(int n, T ih2, const T
     }
 }
 
+// The same step with the y-neighbour rows of the iterate shared through LDS:
+// a block of W waves owns rows y0 .. y0+W-1; every wave loads only its own row
+// of x (the edge waves also the block's halo rows), publishes it in a ring of
+// four planes one plane ahead of its use, and takes the rows y +- 1 at z-1,
+// z, z+1 from the ring.  One barrier per plane: a plane is written two
+// iterations after its slot was last read.  Same arithmetic as
+// k_var_smooth_row (var19_row on the same 3 x 3 rows), same bits.
+template <typename T, typename TC, int VEC, int W, bool PREV, bool ZQ>
+__global__ __launch_bounds__(64 * W) void k_var_smooth_lds(int n, T ih2, const TC* __restrict__ C, const T* x,
+                                                           const T* xprev, const T* __restrict__ b, T* out, T a,
+                                                           T c, int nz, int nyb) {
+    constexpr int NR = 64 * VEC;
+    constexpr size_t N = (size_t)NR * NR * NR;
+    __shared__ T ring[4][W + 2][NR];
+    const RowGrid g{NR, NR - 1};
+    const int lb = xcd_logical(blockIdx.x, gridDim.x);
+    const int yb = lb % nyb, zc = lb / nyb;
+    const int w = wave_id();
+    const int y0 = yb * W, y = y0 + w;
+    const int z0 = zc * nz;
+    const int lane = threadIdx.x & 63;
+    const size_t off = (size_t)lane * VEC;
+    const bool lo = w == 0, hi = w == W - 1;
+    const int yh = lo ? y0 - 1 : y0 + W;  // halo row of the edge waves
+    const int hs = lo ? 0 : W + 1;        // its ring row
+    auto slot = [](int zz) { return zz & 3; };
+    T U[3][3][VEC];   // [dy][dz]: the own row (dy = 1) rides in registers
+    T xn[VEC], hn[VEC];  // own and halo row of the plane after next, loaded one iteration early
+    T hr[VEC];
+    ldrow<T, VEC>(U[1][0], x + g.row(y, z0 - 1) + off);
+    ldrow<T, VEC>(U[1][1], x + g.row(y, z0) + off);
+    ldrow<T, VEC>(U[1][2], x + g.row(y, z0 + 1) + off);
+    lds_strow<T, VEC>(ring[slot(z0 - 1)][w + 1], lane, U[1][0]);
+    lds_strow<T, VEC>(ring[slot(z0)][w + 1], lane, U[1][1]);
+    if (lo || hi) {
+        ldrow<T, VEC>(hr, x + g.row(yh, z0 - 1) + off);
+        lds_strow<T, VEC>(ring[slot(z0 - 1)][hs], lane, hr);
+        ldrow<T, VEC>(hr, x + g.row(yh, z0) + off);
+        lds_strow<T, VEC>(ring[slot(z0)][hs], lane, hr);
+        ldrow<T, VEC>(hr, x + g.row(yh, z0 + 1) + off);
+    }
+    CQueue<T, VEC> q;
+    cq_load<ZQ, T, TC, VEC>(q, 0, C, N, g, y, z0 - 1, off);
+    cq_load<ZQ, T, TC, VEC>(q, 1, C, N, g, y, z0, off);
+    for (int k = 0; k < nz; ++k) {
+        const int z = z0 + k;
+        const bool more = k + 1 < nz;
+        if (more) {
+            ldrow<T, VEC>(xn, x + g.row(y, z + 2) + off);
+            if (lo || hi) ldrow<T, VEC>(hn, x + g.row(yh, z + 2) + off);
+        }
+        lds_strow<T, VEC>(ring[slot(z + 1)][w + 1], lane, U[1][2]);
+        if (lo || hi) lds_strow<T, VEC>(ring[slot(z + 1)][hs], lane, hr);
+        cq_load<ZQ, T, TC, VEC>(q, 2, C, N, g, y, z + 1, off);
+        T bb[VEC], pp[VEC], Mu[VEC], D[VEC], o[VEC];
+        const size_t r = g.row(y, z) + off;
+        ldrow<T, VEC>(bb, b + r);
+        if constexpr (PREV) ldrow<T, VEC>(pp, xprev + r);
+        __syncthreads();
+#pragma unroll
+        for (int dz = 0; dz < 3; ++dz) {
+            lds_ldrow<T, VEC>(U[0][dz], ring[slot(z - 1 + dz)][w], lane);
+            lds_ldrow<T, VEC>(U[2][dz], ring[slot(z - 1 + dz)][w + 2], lane);
+        }
+        var19_row<ZQ, T, TC, VEC>(U, q, C, N, g, y, z, off, ih2, Mu, D);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const T xc = U[1][1][e];
+            const T xp = PREV ? pp[e] : T(0);
+            o[e] = xc + a * (xc - xp) + c * (bb[e] - Mu[e]) / D[e];
+        }
+        strow<T, VEC>(out + r, o);
+        if (more) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                U[1][0][e] = U[1][1][e];
+                U[1][1][e] = U[1][2][e];
+                U[1][2][e] = xn[e];
+                if (lo || hi) hr[e] = hn[e];
+            }
+        }
+        cq_shift<ZQ, T, VEC>(q);
+    }
+}
+
 // =====================================================================================
 // residual r = b - M x (scratch of the two-pass residual restriction) / apply
 // =====================================================================================
@@ -480,10 +566,36 @@ int var_row_blocks(int n) {
         default: return hipErrorInvalidValue;                      \
     }
 
+// Smoothing with the iterate's y-neighbour rows through LDS: kVarLdsWaves
+// rows per block, chunks giving at least 1024 blocks, where a ring of four
+// planes fits 80 KB (float n <= 512, double n <= 256).
+constexpr int kVarLdsWaves = 8;
+
 template <typename T, typename TC>
 hipError_t launch_var_smooth_row(int n, double ih2, const TC* C, const T* x, const T* xprev, const T* b, T* out,
                                  double a, double c, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     int nz, nyb, blocks;
+    if (kVarLds && x != nullptr && n >= 128 && 4ull * (kVarLdsWaves + 2) * n * sizeof(T) <= 80 * 1024) {
+        constexpr int Wv = kVarLdsWaves;
+        nyb = n / Wv;
+        nz = n;
+        while (nz > 4 && nyb * (n / nz) < 1024) nz >>= 1;
+        blocks = nyb * (n / nz);
+        DISPATCH_VEC(n, {
+            constexpr bool ZQ = VEC * sizeof(T) <= 16;
+            if constexpr (4ull * (Wv + 2) * 64 * VEC * sizeof(T) <= 80 * 1024) {
+                if (xprev == nullptr)
+                    MG_LAUNCH((k_var_smooth_lds<T, TC, VEC, Wv, false, ZQ>), dim3(blocks), dim3(64 * Wv), s, ev0, ev1,
+                              n, (T)ih2, C, x, xprev, b, out, (T)a, (T)c, nz, nyb);
+                else
+                    MG_LAUNCH((k_var_smooth_lds<T, TC, VEC, Wv, true, ZQ>), dim3(blocks), dim3(64 * Wv), s, ev0, ev1,
+                              n, (T)ih2, C, x, xprev, b, out, (T)a, (T)c, nz, nyb);
+            } else {
+                return hipErrorInvalidValue;
+            }
+        })
+        return hipGetLastError();
+    }
     shape(n, nz, nyb, blocks);
     DISPATCH_VEC(n, {
         if (x == nullptr)
