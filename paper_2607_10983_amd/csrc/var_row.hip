@@ -26,7 +26,7 @@ namespace {
 
 constexpr int kWaves = 4;
 constexpr int kBlock = 64 * kWaves;
-constexpr bool kVarLds = true;  // smoothing steps share the iterate's rows through LDS (n >= 128)
+constexpr bool kVarLds = true;  // smoothing steps and the residual share the iterate's rows through LDS (n >= 128)
 
 // coefficient row in compute precision T
 template <typename T, typename TC, int VEC>
@@ -260,6 +260,66 @@ __device__ __forceinline__ void shift_queue(T (&U)[3][3][VEC]) {
         }
 }
 
+// Iterate rows of a block of W waves (rows y0 .. y0+W-1) through a ring of
+// four LDS planes: every wave loads only its own row (the edge waves also the
+// block's halo row), publishes it one plane ahead of its use, and takes the
+// rows y +- 1 at z-1, z, z+1 from the ring.  One barrier per plane (by the
+// kernel, between ring_publish and ring_gather): a slot is written two
+// iterations after it was last read.
+template <typename T, int VEC, int W>
+struct Ring {
+    T (*r)[W + 2][64 * VEC];  // the kernel's __shared__ T [4][W + 2][64 VEC]
+    int w, hs, lane;          // own ring row w + 1; the edge wave's halo ring row hs
+    bool edge;
+    __device__ __forceinline__ T* row(int z, int i) const { return r[z & 3][i]; }
+};
+// prologue: U[1][0..2] = own row at z0-1, z0, z0+1; planes z0-1, z0 published;
+// hr = the halo row at z0+1
+template <typename T, int VEC, int W, typename Src>
+__device__ __forceinline__ void ring_start(const Ring<T, VEC, W>& rg, T (&U)[3][3][VEC], T (&hr)[VEC], const Src& src,
+                                           const RowGrid& g, int y, int yh, int z0, size_t off) {
+    src.load(U[1][0], g.row(y, z0 - 1) + off);
+    src.load(U[1][1], g.row(y, z0) + off);
+    src.load(U[1][2], g.row(y, z0 + 1) + off);
+    lds_strow<T, VEC>(rg.row(z0 - 1, rg.w + 1), rg.lane, U[1][0]);
+    lds_strow<T, VEC>(rg.row(z0, rg.w + 1), rg.lane, U[1][1]);
+    if (rg.edge) {
+        src.load(hr, g.row(yh, z0 - 1) + off);
+        lds_strow<T, VEC>(rg.row(z0 - 1, rg.hs), rg.lane, hr);
+        src.load(hr, g.row(yh, z0) + off);
+        lds_strow<T, VEC>(rg.row(z0, rg.hs), rg.lane, hr);
+        src.load(hr, g.row(yh, z0 + 1) + off);
+    }
+}
+// publish plane z + 1 (own row U[1][2], halo row hr)
+template <typename T, int VEC, int W>
+__device__ __forceinline__ void ring_publish(const Ring<T, VEC, W>& rg, const T (&U)[3][3][VEC], const T (&hr)[VEC],
+                                             int z) {
+    lds_strow<T, VEC>(rg.row(z + 1, rg.w + 1), rg.lane, U[1][2]);
+    if (rg.edge) lds_strow<T, VEC>(rg.row(z + 1, rg.hs), rg.lane, hr);
+}
+// after the barrier: the rows y -+ 1 at z-1, z, z+1
+template <typename T, int VEC, int W>
+__device__ __forceinline__ void ring_gather(const Ring<T, VEC, W>& rg, T (&U)[3][3][VEC], int z) {
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz) {
+        lds_ldrow<T, VEC>(U[0][dz], rg.row(z - 1 + dz, rg.w), rg.lane);
+        lds_ldrow<T, VEC>(U[2][dz], rg.row(z - 1 + dz, rg.w + 2), rg.lane);
+    }
+}
+// advance the own queue and the halo row by one plane (xn, hn: plane z + 2)
+template <typename T, int VEC, int W>
+__device__ __forceinline__ void ring_shift(const Ring<T, VEC, W>& rg, T (&U)[3][3][VEC], T (&hr)[VEC],
+                                           const T (&xn)[VEC], const T (&hn)[VEC]) {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        U[1][0][e] = U[1][1][e];
+        U[1][1][e] = U[1][2][e];
+        U[1][2][e] = xn[e];
+        if (rg.edge) hr[e] = hn[e];
+    }
+}
+
 // =====================================================================================
 // smoothing step: out = x + a (x - xprev) + c D^-1 (b - M x)
 // =====================================================================================
@@ -314,12 +374,8 @@ __global__ __launch_bounds__(kBlock) void k_var_smooth_row(int n, T ih2, const T
     }
 }
 
-// The same step with the y-neighbour rows of the iterate shared through LDS:
-// a block of W waves owns rows y0 .. y0+W-1; every wave loads only its own row
-// of x (the edge waves also the block's halo rows), publishes it in a ring of
-// four planes one plane ahead of its use, and takes the rows y +- 1 at z-1,
-// z, z+1 from the ring.  One barrier per plane: a plane is written two
-// iterations after its slot was last read.  Same arithmetic as
+// The same step with the y-neighbour rows of the iterate shared through LDS
+// (Ring): a block of W waves owns rows y0 .. y0+W-1.  Same arithmetic as
 // k_var_smooth_row (var19_row on the same 3 x 3 rows), same bits.
 template <typename T, typename TC, int VEC, int W, bool PREV, bool ZQ>
 __global__ __launch_bounds__(64 * W) void k_var_smooth_lds(int n, T ih2, const TC* __restrict__ C, const T* x,
@@ -338,46 +394,28 @@ __global__ __launch_bounds__(64 * W) void k_var_smooth_lds(int n, T ih2, const T
     const size_t off = (size_t)lane * VEC;
     const bool lo = w == 0, hi = w == W - 1;
     const int yh = lo ? y0 - 1 : y0 + W;  // halo row of the edge waves
-    const int hs = lo ? 0 : W + 1;        // its ring row
-    auto slot = [](int zz) { return zz & 3; };
-    T U[3][3][VEC];   // [dy][dz]: the own row (dy = 1) rides in registers
-    T xn[VEC], hn[VEC];  // own and halo row of the plane after next, loaded one iteration early
-    T hr[VEC];
-    ldrow<T, VEC>(U[1][0], x + g.row(y, z0 - 1) + off);
-    ldrow<T, VEC>(U[1][1], x + g.row(y, z0) + off);
-    ldrow<T, VEC>(U[1][2], x + g.row(y, z0 + 1) + off);
-    lds_strow<T, VEC>(ring[slot(z0 - 1)][w + 1], lane, U[1][0]);
-    lds_strow<T, VEC>(ring[slot(z0)][w + 1], lane, U[1][1]);
-    if (lo || hi) {
-        ldrow<T, VEC>(hr, x + g.row(yh, z0 - 1) + off);
-        lds_strow<T, VEC>(ring[slot(z0 - 1)][hs], lane, hr);
-        ldrow<T, VEC>(hr, x + g.row(yh, z0) + off);
-        lds_strow<T, VEC>(ring[slot(z0)][hs], lane, hr);
-        ldrow<T, VEC>(hr, x + g.row(yh, z0 + 1) + off);
-    }
+    const Ring<T, VEC, W> rg{ring, w, lo ? 0 : W + 1, lane, lo || hi};
+    const PlainRows<T, T, VEC> src{x};
+    T U[3][3][VEC], hr[VEC], xn[VEC], hn[VEC];
+    ring_start<T, VEC, W>(rg, U, hr, src, g, y, yh, z0, off);
     CQueue<T, VEC> q;
     cq_load<ZQ, T, TC, VEC>(q, 0, C, N, g, y, z0 - 1, off);
     cq_load<ZQ, T, TC, VEC>(q, 1, C, N, g, y, z0, off);
     for (int k = 0; k < nz; ++k) {
         const int z = z0 + k;
         const bool more = k + 1 < nz;
-        if (more) {
-            ldrow<T, VEC>(xn, x + g.row(y, z + 2) + off);
-            if (lo || hi) ldrow<T, VEC>(hn, x + g.row(yh, z + 2) + off);
+        if (more) {  // the plane after next, one iteration early
+            src.load(xn, g.row(y, z + 2) + off);
+            if (rg.edge) src.load(hn, g.row(yh, z + 2) + off);
         }
-        lds_strow<T, VEC>(ring[slot(z + 1)][w + 1], lane, U[1][2]);
-        if (lo || hi) lds_strow<T, VEC>(ring[slot(z + 1)][hs], lane, hr);
+        ring_publish<T, VEC, W>(rg, U, hr, z);
         cq_load<ZQ, T, TC, VEC>(q, 2, C, N, g, y, z + 1, off);
         T bb[VEC], pp[VEC], Mu[VEC], D[VEC], o[VEC];
         const size_t r = g.row(y, z) + off;
         ldrow<T, VEC>(bb, b + r);
         if constexpr (PREV) ldrow<T, VEC>(pp, xprev + r);
         __syncthreads();
-#pragma unroll
-        for (int dz = 0; dz < 3; ++dz) {
-            lds_ldrow<T, VEC>(U[0][dz], ring[slot(z - 1 + dz)][w], lane);
-            lds_ldrow<T, VEC>(U[2][dz], ring[slot(z - 1 + dz)][w + 2], lane);
-        }
+        ring_gather<T, VEC, W>(rg, U, z);
         var19_row<ZQ, T, TC, VEC>(U, q, C, N, g, y, z, off, ih2, Mu, D);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
@@ -386,15 +424,7 @@ __global__ __launch_bounds__(64 * W) void k_var_smooth_lds(int n, T ih2, const T
             o[e] = xc + a * (xc - xp) + c * (bb[e] - Mu[e]) / D[e];
         }
         strow<T, VEC>(out + r, o);
-        if (more) {
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                U[1][0][e] = U[1][1][e];
-                U[1][1][e] = U[1][2][e];
-                U[1][2][e] = xn[e];
-                if (lo || hi) hr[e] = hn[e];
-            }
-        }
+        if (more) ring_shift<T, VEC, W>(rg, U, hr, xn, hn);
         cq_shift<ZQ, T, VEC>(q);
     }
 }
@@ -438,6 +468,54 @@ __global__ __launch_bounds__(kBlock) void k_var_resid_row(int n, T ih2, const TC
         }
         strow<T, VEC>(out + r, o);
         shift_queue<T, VEC>(U);
+        cq_shift<ZQ, T, VEC>(q);
+    }
+}
+
+// The residual (apply) with the iterate's y-neighbour rows through LDS (Ring).
+template <typename T, typename TC, int VEC, int W, bool WITHB, bool ZQ>
+__global__ __launch_bounds__(64 * W) void k_var_resid_lds(int n, T ih2, const TC* __restrict__ C,
+                                                          const T* __restrict__ x, const T* __restrict__ b,
+                                                          T* __restrict__ out, int nz, int nyb) {
+    constexpr int NR = 64 * VEC;
+    constexpr size_t N = (size_t)NR * NR * NR;
+    __shared__ T ring[4][W + 2][NR];
+    const RowGrid g{NR, NR - 1};
+    const int lb = xcd_logical(blockIdx.x, gridDim.x);
+    const int yb = lb % nyb, zc = lb / nyb;
+    const int w = wave_id();
+    const int y0 = yb * W, y = y0 + w;
+    const int z0 = zc * nz;
+    const int lane = threadIdx.x & 63;
+    const size_t off = (size_t)lane * VEC;
+    const bool lo = w == 0, hi = w == W - 1;
+    const int yh = lo ? y0 - 1 : y0 + W;
+    const Ring<T, VEC, W> rg{ring, w, lo ? 0 : W + 1, lane, lo || hi};
+    const PlainRows<T, T, VEC> src{x};
+    T U[3][3][VEC], hr[VEC], xn[VEC], hn[VEC];
+    ring_start<T, VEC, W>(rg, U, hr, src, g, y, yh, z0, off);
+    CQueue<T, VEC> q;
+    cq_load<ZQ, T, TC, VEC>(q, 0, C, N, g, y, z0 - 1, off);
+    cq_load<ZQ, T, TC, VEC>(q, 1, C, N, g, y, z0, off);
+    for (int k = 0; k < nz; ++k) {
+        const int z = z0 + k;
+        const bool more = k + 1 < nz;
+        if (more) {
+            src.load(xn, g.row(y, z + 2) + off);
+            if (rg.edge) src.load(hn, g.row(yh, z + 2) + off);
+        }
+        ring_publish<T, VEC, W>(rg, U, hr, z);
+        cq_load<ZQ, T, TC, VEC>(q, 2, C, N, g, y, z + 1, off);
+        const size_t r = g.row(y, z) + off;
+        T bb[VEC], Mu[VEC], D[VEC], o[VEC];
+        if constexpr (WITHB) ldrow<T, VEC>(bb, b + r);
+        __syncthreads();
+        ring_gather<T, VEC, W>(rg, U, z);
+        var19_row<ZQ, T, TC, VEC>(U, q, C, N, g, y, z, off, ih2, Mu, D);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) o[e] = WITHB ? bb[e] - Mu[e] : Mu[e];
+        strow<T, VEC>(out + r, o);
+        if (more) ring_shift<T, VEC, W>(rg, U, hr, xn, hn);
         cq_shift<ZQ, T, VEC>(q);
     }
 }
@@ -550,6 +628,20 @@ void shape(int n, int& nz, int& nyb, int& blocks) {
 
 bool var_row_kernels_apply(int n) { return n >= 64 && n <= 1024 && (n & (n - 1)) == 0; }
 
+// The kernels with the iterate's y-neighbour rows through LDS (Ring):
+// kVarLdsWaves rows per block, chunks giving at least 1024 blocks, where a
+// ring of four planes fits 80 KB (float n <= 512, double n <= 256).
+constexpr int kVarLdsWaves = 8;
+inline bool var_lds_applies(int n, size_t elem) {
+    return kVarLds && n >= 128 && 4ull * (kVarLdsWaves + 2) * n * elem <= 80 * 1024;
+}
+inline void var_lds_shape(int n, int& nz, int& nyb, int& blocks) {
+    nyb = n / kVarLdsWaves;
+    nz = n;
+    while (nz > 4 && nyb * (n / nz) < 1024) nz >>= 1;
+    blocks = nyb * (n / nz);
+}
+
 int var_row_blocks(int n) {
     int nz, nyb, blocks;
     shape(n, nz, nyb, blocks);
@@ -566,21 +658,13 @@ int var_row_blocks(int n) {
         default: return hipErrorInvalidValue;                      \
     }
 
-// Smoothing with the iterate's y-neighbour rows through LDS: kVarLdsWaves
-// rows per block, chunks giving at least 1024 blocks, where a ring of four
-// planes fits 80 KB (float n <= 512, double n <= 256).
-constexpr int kVarLdsWaves = 8;
-
 template <typename T, typename TC>
 hipError_t launch_var_smooth_row(int n, double ih2, const TC* C, const T* x, const T* xprev, const T* b, T* out,
                                  double a, double c, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     int nz, nyb, blocks;
-    if (kVarLds && x != nullptr && n >= 128 && 4ull * (kVarLdsWaves + 2) * n * sizeof(T) <= 80 * 1024) {
+    if (x != nullptr && var_lds_applies(n, sizeof(T))) {
         constexpr int Wv = kVarLdsWaves;
-        nyb = n / Wv;
-        nz = n;
-        while (nz > 4 && nyb * (n / nz) < 1024) nz >>= 1;
-        blocks = nyb * (n / nz);
+        var_lds_shape(n, nz, nyb, blocks);
         DISPATCH_VEC(n, {
             constexpr bool ZQ = VEC * sizeof(T) <= 16;
             if constexpr (4ull * (Wv + 2) * 64 * VEC * sizeof(T) <= 80 * 1024) {
@@ -612,6 +696,24 @@ template <typename T, typename TC>
 hipError_t launch_var_resid_row(int n, double ih2, const TC* C, const T* x, const T* b, T* out, hipStream_t s,
                                 hipEvent_t ev0, hipEvent_t ev1) {
     int nz, nyb, blocks;
+    if (var_lds_applies(n, sizeof(T))) {
+        constexpr int Wv = kVarLdsWaves;
+        var_lds_shape(n, nz, nyb, blocks);
+        DISPATCH_VEC(n, {
+            constexpr bool ZQ = VEC <= 4;
+            if constexpr (4ull * (Wv + 2) * 64 * VEC * sizeof(T) <= 80 * 1024) {
+                if (b)
+                    MG_LAUNCH((k_var_resid_lds<T, TC, VEC, Wv, true, ZQ>), dim3(blocks), dim3(64 * Wv), s, ev0, ev1,
+                              n, (T)ih2, C, x, b, out, nz, nyb);
+                else
+                    MG_LAUNCH((k_var_resid_lds<T, TC, VEC, Wv, false, ZQ>), dim3(blocks), dim3(64 * Wv), s, ev0, ev1,
+                              n, (T)ih2, C, x, b, out, nz, nyb);
+            } else {
+                return hipErrorInvalidValue;
+            }
+        })
+        return hipGetLastError();
+    }
     shape(n, nz, nyb, blocks);
     DISPATCH_VEC(n, {
         if (b)
