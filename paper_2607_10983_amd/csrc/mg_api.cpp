@@ -326,12 +326,15 @@ inline int other(int cur) { return cur == 0 ? 1 : 0; }
 // level 0 is not itself run by the tail kernel).
 inline bool x1_fusable(const mg_ctx* c) { return c->tail_start != 0 && c->lev.size() > 1; }
 
-// Level l (not the coarsest, not run by the tail kernel) is visited by the two
-// fused visit kernels: float hierarchy, seven-point operator, 32^3 points.
-inline bool visit_level(const mg_ctx* c, int l) {
-    return c->use_visits && !c->var && !c->inner_double && c->p.smoother == MG_CHEBYSHEV &&
-           l + 1 < (int)c->lev.size() && l != c->tail_start &&
-           visit_applies(c->lev[l].n, (int)c->lev[l].a.size());
+// Level l (not the coarsest, not run by the tail kernel) is visited by the
+// fused visit kernels: float hierarchy, seven-point operator, 32^3 or 64^3
+// points; pre (post) selects the visit before (after) the coarse correction.
+inline bool visit_level(const mg_ctx* c, int l, bool pre) {
+    if (!(c->use_visits && !c->var && !c->inner_double && c->p.smoother == MG_CHEBYSHEV &&
+          l + 1 < (int)c->lev.size() && l != c->tail_start))
+        return false;
+    const int n = c->lev[l].n, v = (int)c->lev[l].a.size();
+    return pre ? visit_pre_applies(n, v) : visit_post_applies(n, v);
 }
 
 // Level l's post-smoothing pass (three Chebyshev steps) runs fused with the
@@ -377,7 +380,7 @@ inline bool post_step_fused(const mg_ctx* c, int l, size_t elem) {
 inline bool from_zero_stepb(const mg_ctx* c, int l) {
     const Level& L = c->lev[l];
     return c->use_pairs && !c->var && c->p.smoother == MG_CHEBYSHEV && L.a.size() >= 3 && L.x[2] == nullptr &&
-           row_kernels_apply(L.n) && l + 1 < (int)c->lev.size() && l != c->tail_start && !visit_level(c, l);
+           row_kernels_apply(L.n) && l + 1 < (int)c->lev.size() && l != c->tail_start && !visit_level(c, l, true);
 }
 
 template <typename T>
@@ -694,26 +697,25 @@ mg_status vcycle_from_zero(mg_ctx* c, int l) {
     if (l == last) return coarse_level<T>(c, l);
     Level& L = c->lev[l];
     Level& Lc = c->lev[l + 1];
-    if constexpr (std::is_same<T, float>::value) {
-        if (visit_level(c, l)) {  // two launches for the whole visit of the 32^3 level
-            const int v = (int)L.a.size();
-            if (l == 0) c->x1_ready = false;
-            HIPCHK(c, launch_visit_pre(L.n, L.ih2, (const float*)L.b, (float*)L.x[0], (float*)Lc.b, L.a.data(),
-                                       L.c.data(), v, c->stream));
-            L.cur = 0;
-            mg_status st = vcycle_from_zero<T>(c, l + 1);
-            if (st != MG_OK) return st;
-            HIPCHK(c, launch_visit_post(L.n, L.ih2, (const float*)L.x[0], (const float*)Lc.x[Lc.cur],
-                                        (const float*)L.b, (float*)L.x[1], L.a.data(), L.c.data(), v, c->stream));
-            L.cur = 1;
-            return MG_OK;
-        }
+    mg_status st = MG_OK;
+    const int v = (int)L.a.size();
+    if (std::is_same<T, float>::value && visit_level(c, l, true)) {  // one launch before the coarse level
+        if (l == 0) c->x1_ready = false;
+        HIPCHK(c, launch_visit_pre(L.n, L.ih2, (const float*)L.b, (float*)L.x[0], (float*)Lc.b, L.a.data(),
+                                   L.c.data(), v, c->stream));
+        L.cur = 0;
+    } else {
+        if ((st = smooth_level<T>(c, l, true)) != MG_OK) return st;
+        if ((st = residual_restrict_level<T>(c, l)) != MG_OK) return st;
     }
-    mg_status st = smooth_level<T>(c, l, true);
-    if (st != MG_OK) return st;
-    if ((st = residual_restrict_level<T>(c, l)) != MG_OK) return st;
-    st = vcycle_from_zero<T>(c, l + 1);
-    if (st != MG_OK) return st;
+    if ((st = vcycle_from_zero<T>(c, l + 1)) != MG_OK) return st;
+    if (std::is_same<T, float>::value && visit_level(c, l, false)) {  // and one after it
+        const int nx = other(L.cur);
+        HIPCHK(c, launch_visit_post(L.n, L.ih2, (const float*)L.x[L.cur], (const float*)Lc.x[Lc.cur],
+                                    (const float*)L.b, (float*)L.x[nx], L.a.data(), L.c.data(), v, c->stream));
+        L.cur = nx;
+        return MG_OK;
+    }
     return post_level<T>(c, l);
 }
 
@@ -727,7 +729,7 @@ mg_status outer_residual(mg_ctx* c, const double* phi_in, const void* e, double*
     const int n = L.n;
     const double ih2 = L.ih2;
     const bool x1 = next_cycle && x1_fusable(c) && !from_zero_triple(c, 0) && !from_zero_stepb(c, 0) &&
-                    !visit_level(c, 0);
+                    !visit_level(c, 0, true);
     const double c0 = L.c.empty() ? 0.0 : L.c[0];
     // x1 goes to a buffer other than the one holding e (the previous cycle's result)
     const int xb = other(L.cur);
@@ -1114,7 +1116,8 @@ static mg_status post_outer_sums(mg_ctx* c) {
 // Level 0's inner V-cycle starts with the pass-from-zero kernel, which can
 // finish the outer sums in an extra block.
 static bool sums_in_pass_from_zero(const mg_ctx* c) {
-    return c->fuse_sums && c->lev.size() > 1 && c->tail_start != 0 && !visit_level(c, 0) && from_zero_triple(c, 0);
+    return c->fuse_sums && c->lev.size() > 1 && c->tail_start != 0 && !visit_level(c, 0, true) &&
+           from_zero_triple(c, 0);
 }
 // Outer residual of the solve loop and its three sums.  When a V-cycle is
 // enqueued right after it (cycle_follows) and starts with the pass from zero,

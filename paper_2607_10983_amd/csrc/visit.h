@@ -6,11 +6,13 @@
 namespace mg {
 
 // Largest smoothing degree a fused visit handles (its plane stacks must fit LDS).
-constexpr int kVisitMaxDegree = 3;
+constexpr int kVisitMaxDegree = 4;
 
-// True when the level (n^3 points, n = 32 or 64, smoothing degree) can be
-// visited fused.
-bool visit_applies(int n, int degree);
+// True when the pre (post) visit of the level (n^3 points, n = 32 or 64,
+// smoothing degree) can run fused.  The 64^3 pre visit's tile halo of four
+// rows covers at most three steps.
+bool visit_pre_applies(int n, int degree);
+bool visit_post_applies(int n, int degree);
 
 // Pre-smoothing from zero, residual and full weighting in one launch:
 // xout (n^3) = `degree` steps from zero on b; coarse_b ((n/2)^3) = R(b - M xout).

@@ -1,11 +1,12 @@
 // Fused level visits for the 32^3 and 64^3 levels of the seven-point hierarchy.
 //
 // On a 32^3 level every kernel of a V-cycle visit is far too small to fill the
-// chip, and the visit costs its launch latencies (nine launches).  Here the
-// visit takes two launches.  Each workgroup (1024 threads, one per (x, y)
-// point of a 32 x 32 plane) owns one coarse plane Z, i.e. fine planes 2Z and
-// 2Z + 1, and recomputes what it needs of the neighbouring planes (a halo of
-// v + 1 planes shrinking by one per step), all of it in LDS:
+// chip, and the visit costs its launch latencies (2v + 3 launches for v
+// smoothing steps).  Here the visit takes two launches.  Each workgroup (1024
+// threads, one per (x, y) point of a 32 x 32 plane) owns one coarse plane Z,
+// i.e. fine planes 2Z and 2Z + 1, and recomputes what it needs of the
+// neighbouring planes (a halo of v + 1 planes shrinking by one per step), all
+// of it in LDS:
 //
 //   pre:  x_1 = c_0 D^-1 b (pointwise), v - 1 further steps, r = b - M x_v,
 //         coarse rhs = R r; writes x_v on the owned planes and the coarse plane;
@@ -28,9 +29,9 @@ constexpr int kN = 32;                // points per side
 constexpr int kP = kN * kN;           // points per plane = threads per workgroup
 constexpr int kMaxDeg = kVisitMaxDegree;
 constexpr int kPrePlanes = 2 * kMaxDeg + 3;   // planes of x_1 in the pre visit
-// b and three rotating iterate stacks of kPrePlanes planes: 144 KB of the 160 KB
-// a gfx950 workgroup may use
-constexpr int kLdsFloats = 4 * kPrePlanes * kP;
+// b and two iterate stacks of kPrePlanes planes, and the three residual planes
+// of the pre visit: 144 KB of the 160 KB a gfx950 workgroup may use
+constexpr int kLdsFloats = (3 * kPrePlanes + 3) * kP;
 
 struct VisitCoef {
     float a[kMaxDeg], cd[kMaxDeg];  // step k: x + a_k (x - x_prev) + cd_k (b - M x)
@@ -47,10 +48,11 @@ __device__ __forceinline__ float M_at(const float* st, int p, int x, int y, floa
                            c[wrap(y + 1) * kN + x], m[y * kN + x], q[y * kN + x], c[y * kN + x], ih2);
 }
 
-// Plane stacks: every stack holds the planes [lo, lo + NP) of a field, and
-// the three iterate stacks rotate so that x_k, x_{k-1} and a free one are at
-// hand.  V (the step count) is a template parameter so that every plane loop
-// unrolls and the global loads of the staging loops are all in flight at once.
+// Plane stacks: every stack holds the planes [lo, lo + NP) of a field.  Two
+// iterate stacks alternate: a step reads x_{k-1} only at the point it writes,
+// so x_{k+1} overwrites x_{k-1} in place.  V (the step count) is a template
+// parameter so that every plane loop unrolls and the global loads of the
+// staging loops are all in flight at once.
 template <int V>
 __global__ __launch_bounds__(kP) void k_visit_pre(const float* __restrict__ b, float* __restrict__ xout,
                                                   float* __restrict__ coarse_b, float ih2, VisitCoef coef) {
@@ -62,7 +64,9 @@ __global__ __launch_bounds__(kP) void k_visit_pre(const float* __restrict__ b, f
     const int z0 = 2 * Z;
     const int lo = z0 - 1 - V;
     float* sb = lds;  // b on the x_1 planes
-    float* buf[3] = {lds + NP * kP, lds + 2 * NP * kP, lds + 3 * NP * kP};
+    float* buf[2] = {lds + NP * kP, lds + 2 * NP * kP};
+    float* rs = lds + 3 * NP * kP;  // residual on planes z0 - 1 .. z0 + 1
+    static_assert(3 * NP * kP + 3 * kP <= kLdsFloats, "pre visit stacks exceed LDS");
     // b and x_1 = c_0 D^-1 b on every plane of the stack
     float bv[NP];
 #pragma unroll
@@ -89,10 +93,9 @@ __global__ __launch_bounds__(kP) void k_visit_pre(const float* __restrict__ b, f
         prv = cur;
         cur = out;
     }
-    // residual on planes z0 - 1 .. z0 + 1 (stack planes V .. V + 2) into the free buffer
-    const int rb = prv >= 0 ? 3 - cur - prv : 1;
+    // residual on planes z0 - 1 .. z0 + 1 (stack planes V .. V + 2)
 #pragma unroll
-    for (int p = V; p <= V + 2; ++p) buf[rb][p * kP + t] = sb[p * kP + t] - M_at(buf[cur], p, x, y, ih2);
+    for (int p = V; p <= V + 2; ++p) rs[(p - V) * kP + t] = sb[p * kP + t] - M_at(buf[cur], p, x, y, ih2);
     // the smoothed iterate on the owned planes
 #pragma unroll
     for (int p = V + 1; p <= V + 2; ++p) xout[(size_t)(lo + p) * kP + t] = buf[cur][p * kP + t];
@@ -107,7 +110,7 @@ __global__ __launch_bounds__(kP) void k_visit_pre(const float* __restrict__ b, f
             for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
                 for (int dx = 0; dx < 3; ++dx)
-                    vv[dz][dy][dx] = buf[rb][(V + dz) * kP + wrap(2 * Y + dy - 1) * kN + wrap(2 * X + dx - 1)];
+                    vv[dz][dy][dx] = rs[dz * kP + wrap(2 * Y + dy - 1) * kN + wrap(2 * X + dx - 1)];
         coarse_b[(size_t)Z * (kP / 4) + t] = fw_pt<float>(vv);
     }
 }
@@ -127,9 +130,9 @@ __global__ __launch_bounds__(kP) void k_visit_post(const float* __restrict__ xin
     const int lo = z0 - V;
     const int zlo = Z - (V + 1) / 2;  // first staged coarse plane
     float* sb = lds;
-    float* buf[3] = {lds + NP * kP, lds + 2 * NP * kP, lds + 3 * NP * kP};
-    float* se = lds + 4 * NP * kP;  // coarse planes zlo .. zlo + NC - 1
-    static_assert(4 * NP * kP + NC * pc <= kLdsFloats, "post visit stacks exceed LDS");
+    float* buf[2] = {lds + NP * kP, lds + 2 * NP * kP};
+    float* se = lds + 3 * NP * kP;  // coarse planes zlo .. zlo + NC - 1
+    static_assert(3 * NP * kP + NC * pc <= kLdsFloats, "post visit stacks exceed LDS");
     float bv[NP], xv[NP], ev[(NC * pc + kP - 1) / kP];
 #pragma unroll
     for (int j = 0; j < (NC * pc + kP - 1) / kP; ++j) {
@@ -218,7 +221,10 @@ __global__ __launch_bounds__(kP) void k_visit64_pre(const float* __restrict__ b,
     const int y = wrap64(y0 - kHY + r);
     const int lo = z0 - 1 - V;
     float* sb = lds;
-    float* buf[3] = {lds + NP * kP, lds + 2 * NP * kP, lds + 3 * NP * kP};
+    float* buf[2] = {lds + NP * kP, lds + 2 * NP * kP};
+    float* rs = lds + 3 * NP * kP;  // residual on planes z0 - 1 .. z0 + 1
+    static_assert(3 * NP * kP + 3 * kP <= kLdsFloats, "pre visit stacks exceed LDS");
+    static_assert(V + 1 <= kHY, "the tile halo covers the steps, the residual and the restriction");
     float bv[NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) bv[p] = b[((size_t)wrap64(lo + p) * kN64 + y) * kN64 + x];
@@ -245,11 +251,10 @@ __global__ __launch_bounds__(kP) void k_visit64_pre(const float* __restrict__ b,
         prv = cur;
         cur = out;
     }
-    // residual on rows 3 .. 11 (fine rows y0-1 .. y0+7), planes V .. V+2, into the free buffer
-    const int rb = prv >= 0 ? 3 - cur - prv : 1;
+    // residual on rows 3 .. 11 (fine rows y0-1 .. y0+7), planes V .. V+2
     if (r >= kHY - 1 && r <= kHY + kTY - 1) {
 #pragma unroll
-        for (int p = V; p <= V + 2; ++p) buf[rb][p * kP + t] = sb[p * kP + t] - M_tile(buf[cur], p, x, r, ih2);
+        for (int p = V; p <= V + 2; ++p) rs[(p - V) * kP + t] = sb[p * kP + t] - M_tile(buf[cur], p, x, r, ih2);
     }
     // the smoothed iterate on the owned rows and planes
     if (r >= kHY && r < kHY + kTY) {
@@ -260,7 +265,7 @@ __global__ __launch_bounds__(kP) void k_visit64_pre(const float* __restrict__ b,
     // full weighting onto the tile's 4 coarse rows of coarse plane Z: y, then x, then z
     if (t < (kN64 / 2) * (kTY / 2)) {
         const int X = t & (kN64 / 2 - 1), Yl = t >> 5;
-        const float* rr = buf[rb];
+        const float* rr = rs;
         float sz[3];
 #pragma unroll
         for (int dz = 0; dz < 3; ++dz) {
@@ -268,7 +273,7 @@ __global__ __launch_bounds__(kP) void k_visit64_pre(const float* __restrict__ b,
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx) {
                 const int xx = wrap64(2 * X + dx - 1);
-                const float* col = rr + (V + dz) * kP + xx;
+                const float* col = rr + dz * kP + xx;
                 const int r0 = kHY - 1 + 2 * Yl;  // tile row of fine row 2Y - 1
                 sx[dx] = fw3<float>(col[r0 * kN64], col[(r0 + 1) * kN64], col[(r0 + 2) * kN64]);
             }
@@ -297,9 +302,10 @@ __global__ __launch_bounds__(kP) void k_visit64_post(const float* __restrict__ x
     const int lo = z0 - V;
     const int zlo = Z - (V + 1) / 2, ylo = (y0 - kHY) / 2 - 1;  // first staged coarse plane / row
     float* sb = lds;
-    float* buf[3] = {lds + NP * kP, lds + 2 * NP * kP, lds + 3 * NP * kP};
-    float* se = lds + 4 * NP * kP;  // coarse planes zlo .. zlo+NC-1, rows ylo .. ylo+CR-1
-    static_assert(4 * NP * kP + NC * CR * nc <= kLdsFloats, "post visit stacks exceed LDS");
+    float* buf[2] = {lds + NP * kP, lds + 2 * NP * kP};
+    float* se = lds + 3 * NP * kP;  // coarse planes zlo .. zlo+NC-1, rows ylo .. ylo+CR-1
+    static_assert(3 * NP * kP + NC * CR * nc <= kLdsFloats, "post visit stacks exceed LDS");
+    static_assert(V <= kHY, "the tile halo covers the steps");
     constexpr int NE = (NC * CR * nc + kP - 1) / kP;
     float ev[NE], bv[NP], xv[NP];
 #pragma unroll
@@ -353,11 +359,16 @@ __global__ __launch_bounds__(kP) void k_visit64_post(const float* __restrict__ x
 
 }  // namespace
 
-bool visit_applies(int n, int degree) { return (n == kN || n == kN64) && degree >= 1 && degree <= kMaxDeg; }
+bool visit_pre_applies(int n, int degree) {
+    return degree >= 1 && ((n == kN && degree <= kMaxDeg) || (n == kN64 && degree <= kHY - 1));
+}
+bool visit_post_applies(int n, int degree) {
+    return degree >= 1 && ((n == kN && degree <= kMaxDeg) || (n == kN64 && degree <= kHY && degree <= kMaxDeg));
+}
 
 hipError_t launch_visit_pre(int n, double ih2, const float* b, float* xout, float* coarse_b, const double* a,
                             const double* c, int degree, hipStream_t s) {
-    if (!visit_applies(n, degree)) return hipErrorInvalidValue;
+    if (!visit_pre_applies(n, degree)) return hipErrorInvalidValue;
     const VisitCoef coef = visit_coef(ih2, a, c, degree);
     const float fih2 = (float)ih2;
     if (n == kN64) {
@@ -373,14 +384,15 @@ hipError_t launch_visit_pre(int n, double ih2, const float* b, float* xout, floa
     switch (degree) {
     case 1: hipLaunchKernelGGL(k_visit_pre<1>, grid, block, 0, s, b, xout, coarse_b, fih2, coef); break;
     case 2: hipLaunchKernelGGL(k_visit_pre<2>, grid, block, 0, s, b, xout, coarse_b, fih2, coef); break;
-    default: hipLaunchKernelGGL(k_visit_pre<3>, grid, block, 0, s, b, xout, coarse_b, fih2, coef); break;
+    case 3: hipLaunchKernelGGL(k_visit_pre<3>, grid, block, 0, s, b, xout, coarse_b, fih2, coef); break;
+    default: hipLaunchKernelGGL(k_visit_pre<4>, grid, block, 0, s, b, xout, coarse_b, fih2, coef); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_visit_post(int n, double ih2, const float* xin, const float* e, const float* b, float* xout,
                              const double* a, const double* c, int degree, hipStream_t s) {
-    if (!visit_applies(n, degree) || xout == xin) return hipErrorInvalidValue;
+    if (!visit_post_applies(n, degree) || xout == xin) return hipErrorInvalidValue;
     const VisitCoef coef = visit_coef(ih2, a, c, degree);
     const float fih2 = (float)ih2;
     if (n == kN64) {
@@ -388,7 +400,8 @@ hipError_t launch_visit_post(int n, double ih2, const float* xin, const float* e
         switch (degree) {
         case 1: hipLaunchKernelGGL(k_visit64_post<1>, grid, block, 0, s, xin, e, b, xout, fih2, coef); break;
         case 2: hipLaunchKernelGGL(k_visit64_post<2>, grid, block, 0, s, xin, e, b, xout, fih2, coef); break;
-        default: hipLaunchKernelGGL(k_visit64_post<3>, grid, block, 0, s, xin, e, b, xout, fih2, coef); break;
+        case 3: hipLaunchKernelGGL(k_visit64_post<3>, grid, block, 0, s, xin, e, b, xout, fih2, coef); break;
+        default: hipLaunchKernelGGL(k_visit64_post<4>, grid, block, 0, s, xin, e, b, xout, fih2, coef); break;
         }
         return hipGetLastError();
     }
@@ -396,7 +409,8 @@ hipError_t launch_visit_post(int n, double ih2, const float* xin, const float* e
     switch (degree) {
     case 1: hipLaunchKernelGGL(k_visit_post<1>, grid, block, 0, s, xin, e, b, xout, fih2, coef); break;
     case 2: hipLaunchKernelGGL(k_visit_post<2>, grid, block, 0, s, xin, e, b, xout, fih2, coef); break;
-    default: hipLaunchKernelGGL(k_visit_post<3>, grid, block, 0, s, xin, e, b, xout, fih2, coef); break;
+    case 3: hipLaunchKernelGGL(k_visit_post<3>, grid, block, 0, s, xin, e, b, xout, fih2, coef); break;
+    default: hipLaunchKernelGGL(k_visit_post<4>, grid, block, 0, s, xin, e, b, xout, fih2, coef); break;
     }
     return hipGetLastError();
 }

@@ -482,12 +482,13 @@ def test_two_step_kernel_matches_single_steps(mgpu, n, prec, degree, smoother):
 
 
 @pytest.mark.parametrize("n,levels", [(32, 4), (32, 2), (64, 5), (64, 3), (128, 6), (256, 7)])
-@pytest.mark.parametrize("degree", [1, 2, 3])
+@pytest.mark.parametrize("degree", [1, 2, 3, 4])
 def test_level_visit_matches_unfused(mgpu, n, levels, degree):
     """The fused visits of the 32^3 and 64^3 levels (smoothing from zero,
     residual and full weighting in one launch; prolongation and smoothing in
     another) use the point formulas of the separate kernels: mixed-precision
-    solves agree bitwise with MG_OPT_NO_VISIT, cycle by cycle."""
+    solves agree bitwise with MG_OPT_NO_VISIT, cycle by cycle.  Degree 4 runs
+    the 64^3 level's pre-smoothing unfused and its post visit fused."""
     b = dev(flat_source(n, 5))
     kw = dict(levels=levels, degree=degree, precision="mixed")
     plain = mgpu.Multigrid(n, options=mgpu._lib.MG_OPT_NO_VISIT, **kw)
