@@ -364,62 +364,91 @@ __global__ __launch_bounds__(kThreads) void k_coeff_check(int n, const TC* __res
 // coarsest level
 // =====================================================================================
 // Separable exact solve of the seven-point system: three 1-D basis changes,
-// division by the eigenvalue, three inverse basis changes, all in double in LDS.
-// The level size NC is a compile-time constant (4, 8 or 16), so the point
-// loops and the basis sums unroll and the index arithmetic is shifts and
-// masks (with a run-time size the 16^3 solve took 53 us per launch).
+// division by the eigenvalue, three inverse basis changes, all in double.
+// Every basis change is a set of independent lines (NC^2 lines of NC points
+// along one axis): one thread holds a whole line in registers, forms all NC
+// outputs and writes them back over the line, so each value crosses LDS once
+// per change and the basis matrix, the same for every line, is read with
+// uniform loads.  The z change, the division and the inverse z change run on
+// the same line in one pass.  LDS rows are padded to NC + 1 values and planes
+// to NC (NC + 1), so the lanes of a wave fall on different banks along every
+// axis.  Each output is the same sum, in the same order, as a plain basis
+// change (acc = 0, then q_j v_j added for j = 0 .. NC-1).  NC (4, 8 or 16) is
+// a compile-time constant, so every loop unrolls.  One workgroup of
+// coarse_threads(NC) threads (one per line).
+constexpr int coarse_threads(int nc) { return nc * nc < 64 ? 64 : nc * nc; }
 template <typename T, int NC>
-__global__ __launch_bounds__(1024) void k_coarse_flat(const double* __restrict__ Q, const double* __restrict__ lam1,
-                                                      const T* __restrict__ r, T* __restrict__ e) {
+__global__ __launch_bounds__(coarse_threads(NC)) void k_coarse_flat(const double* __restrict__ Q,
+                                                                    const double* __restrict__ lam1,
+                                                                    const T* __restrict__ r, T* __restrict__ e) {
     constexpr int N = NC * NC * NC;
-    __shared__ double A[N];
-    __shared__ double B[N];
-    __shared__ double q[NC * NC];
-    __shared__ double lam[NC];
+    constexpr int RP = NC + 1, PP = NC * RP;  // padded row and plane pitches
+    constexpr int LINES = NC * NC, NT = coarse_threads(NC);
+    __shared__ double A[NC * PP];
     const int tid = threadIdx.x;
-    for (int i = tid; i < NC * NC; i += 1024) q[i] = Q[i];
-    if (tid < NC) lam[tid] = lam1[tid];
-    for (int i = tid; i < N; i += 1024) A[i] = (double)r[i];
+    auto at = [](int x, int y, int z) { return x + RP * y + PP * z; };
+    for (int i = tid; i < N; i += NT) A[at(i & (NC - 1), (i / NC) & (NC - 1), i / (NC * NC))] = (double)r[i];
     __syncthreads();
-    // q[j + NC*k] = basis vector k at point j.  Forward: c_k = sum_j q[j,k] v_j.
-    auto pass = [&](const double* src, double* dst, auto axis_tag, auto fwd_tag) {
-        constexpr int axis = decltype(axis_tag)::value;
-        constexpr bool forward = decltype(fwd_tag)::value;
-        constexpr int stride = axis == 0 ? 1 : axis == 1 ? NC : NC * NC;
-#pragma unroll
-        for (int i0 = 0; i0 < N; i0 += 1024) {
-            const int i = i0 + tid;
-            if (N % 1024 != 0 && i >= N) break;
-            const int k = (i / stride) & (NC - 1);
-            const int base = i - k * stride;
+    // q[j + NC*k] = basis vector k at point j.  Forward: c_k = sum_j q[j,k] v_j;
+    // inverse: v_k = sum_j q[k,j] c_j.  The line's values are all in registers
+    // before output k is stored over point k (the thread owns the line), and
+    // f(k, c_k) is what is stored.
+    auto change = [&](const double(&v)[NC], int base, int stride, bool forward, auto f) {
+#pragma unroll 4
+        for (int k = 0; k < NC; ++k) {
             double acc = 0.0;
 #pragma unroll
             for (int j = 0; j < NC; ++j) {
-                const double w = forward ? q[j + NC * k] : q[k + NC * j];
-                acc += w * src[base + j * stride];
+                const double w = forward ? Q[j + NC * k] : Q[k + NC * j];
+                acc += w * v[j];
             }
-            dst[i] = acc;
+            A[base + k * stride] = f(k, acc);
         }
-        __syncthreads();
     };
-    using X = std::integral_constant<int, 0>;
-    using Y = std::integral_constant<int, 1>;
-    using Z = std::integral_constant<int, 2>;
-    using F = std::true_type;
-    using I = std::false_type;
-    pass(A, B, X{}, F{});
-    pass(B, A, Y{}, F{});
-    pass(A, B, Z{}, F{});
-    for (int i = tid; i < N; i += 1024) {
-        const int x = i & (NC - 1), y = (i / NC) & (NC - 1), z = i / (NC * NC);
-        const double l = lam[x] + lam[y] + lam[z];
-        B[i] = (x == 0 && y == 0 && z == 0) ? 0.0 : B[i] / l;
+    auto load = [&](double(&v)[NC], int base, int stride) {
+#pragma unroll
+        for (int j = 0; j < NC; ++j) v[j] = A[base + j * stride];
+    };
+    auto same = [](int, double c) { return c; };
+    const int u = tid & (NC - 1), w = tid / NC;  // line tid: the two other coordinates
+    const int bx = at(0, u, w), by = at(u, 0, w), bz = at(u, w, 0);
+    double v[NC];
+    // forward x and y changes
+    if (tid < LINES) {
+        load(v, bx, 1);
+        change(v, bx, 1, true, same);
     }
     __syncthreads();
-    pass(B, A, Z{}, I{});
-    pass(A, B, Y{}, I{});
-    pass(B, A, X{}, I{});
-    for (int i = tid; i < N; i += 1024) e[i] = (T)A[i];
+    if (tid < LINES) {
+        load(v, by, RP);
+        change(v, by, RP, true, same);
+    }
+    __syncthreads();
+    // z line of wavenumbers (kx, ky) = (u, w): forward change divided by the
+    // eigenvalue (the constant mode set to zero), then the inverse change
+    if (tid < LINES) {
+        const double lxy = lam1[u] + lam1[w];
+        load(v, bz, PP);
+        change(v, bz, PP, true, [&](int k, double c) {
+            const double l = lxy + lam1[k];
+            return (u == 0 && w == 0 && k == 0) ? 0.0 : c / l;
+        });
+        load(v, bz, PP);
+        change(v, bz, PP, false, same);
+    }
+    __syncthreads();
+    // inverse y and x changes
+    if (tid < LINES) {
+        load(v, by, RP);
+        change(v, by, RP, false, same);
+    }
+    __syncthreads();
+    if (tid < LINES) {
+        load(v, bx, 1);
+        change(v, bx, 1, false, same);
+    }
+    __syncthreads();
+    for (int i = tid; i < N; i += NT) e[i] = (T)A[at(i & (NC - 1), (i / NC) & (NC - 1), i / (NC * NC))];
 }
 
 // e = G r, 8 rows per block, 32 lanes per row, fixed-order sums.
@@ -764,9 +793,11 @@ hipError_t launch_coeff_check(int n, const TC* coeff, double* partials, hipStrea
 template <typename T>
 hipError_t launch_coarse_flat(int nc, const double* Q, const double* lam1, const T* r, T* e, hipStream_t s) {
     switch (nc) {
-        case 4: hipLaunchKernelGGL((k_coarse_flat<T, 4>), dim3(1), dim3(1024), 0, s, Q, lam1, r, e); break;
-        case 8: hipLaunchKernelGGL((k_coarse_flat<T, 8>), dim3(1), dim3(1024), 0, s, Q, lam1, r, e); break;
-        case 16: hipLaunchKernelGGL((k_coarse_flat<T, 16>), dim3(1), dim3(1024), 0, s, Q, lam1, r, e); break;
+        case 4: hipLaunchKernelGGL((k_coarse_flat<T, 4>), dim3(1), dim3(coarse_threads(4)), 0, s, Q, lam1, r, e); break;
+        case 8: hipLaunchKernelGGL((k_coarse_flat<T, 8>), dim3(1), dim3(coarse_threads(8)), 0, s, Q, lam1, r, e); break;
+        case 16:
+            hipLaunchKernelGGL((k_coarse_flat<T, 16>), dim3(1), dim3(coarse_threads(16)), 0, s, Q, lam1, r, e);
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
