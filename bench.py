@@ -42,7 +42,8 @@ HBM_PEAK_GBPS = 8000.0
 # WRITE_SIZE per dispatch (profiles/hbm_bytes_*.md) scaled by the copy-kernel
 # factors 2.0 (fetch) and 1.0 (write), averaged over the launches of the kind.
 # Reported only while the source of the row kernels and their launch shapes
-# is the one the counters were taken on.
+# is the one the counters were taken on.  Keys are the first name of each
+# kind's label (kernel_name).
 TRAFFIC = {
     "device_code_sha256": "e149ac085bc5783ea82aeca18837be13dc423d055496993fae93aba8b2cb8eed",
     "bytes_per_launch": {
@@ -176,9 +177,10 @@ KINDS = (MG_TIME_STEP, MG_TIME_PAIR, MG_TIME_TRIPLE, MG_TIME_OUTER, MG_TIME_TRAN
 def kernel_name(kind, n, precision, var=False):
     t = "double" if precision == "fp64" else "float"
     if var:
-        return {MG_TIME_STEP: f"k_var_smooth_row (fine-level 19-point Chebyshev step, {t})",
+        return {MG_TIME_STEP: f"k_var_smooth_row / k_var_smooth_lds (fine-level 19-point Chebyshev step, {t})",
                 MG_TIME_OUTER: "k_var_outer_row (19-point outer defect correction: phi += e, FP64 residual, norms)",
-                MG_TIME_TRANSFER: f"k_var_resid_row / k_prolong_row (fine-level 19-point residual, prolongation, {t})",
+                MG_TIME_TRANSFER: f"k_var_resid_row / k_var_resid_lds / k_prolong_row (fine-level 19-point "
+                                  f"residual, prolongation, {t})",
                 }.get(kind, f"kind {kind}")
     return {MG_TIME_STEP: f"k_smooth_row / k_smooth_lds (fine-level single Chebyshev step, {t})",
             MG_TIME_PAIR: f"k_smooth2_lds (fine-level two-step pass and pass from zero, {t})",
@@ -186,7 +188,8 @@ def kernel_name(kind, n, precision, var=False):
                              else f"k_smooth3_lds (fine-level three-step pass, {t})"),
             MG_TIME_OUTER: "k_outer_lds (outer defect correction: phi += e, FP64 residual r, norms, r cast "
                            "to the inner precision)",
-            MG_TIME_TRANSFER: f"k_rr_row / k_prolong_row (fine-level residual + restriction, prolongation, {t})",
+            MG_TIME_TRANSFER: f"k_rr_row / k_rr_lds / k_prolong_row (fine-level residual + restriction, "
+                              f"prolongation, {t})",
             }[kind]
 
 
