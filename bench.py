@@ -178,6 +178,7 @@ def kernel_name(kind, n, precision, var=False):
     t = "double" if precision == "fp64" else "float"
     if var:
         return {MG_TIME_STEP: f"k_var_smooth_row / k_var_smooth_lds (fine-level 19-point Chebyshev step, {t})",
+                MG_TIME_PAIR: f"k_var_smooth2_lds (fine-level 19-point two-step pass, {t})",
                 MG_TIME_OUTER: "k_var_outer_row (19-point outer defect correction: phi += e, FP64 residual, norms)",
                 MG_TIME_TRANSFER: f"k_var_resid_row / k_var_resid_lds / k_prolong_row (fine-level 19-point "
                                   f"residual, prolongation, {t})",

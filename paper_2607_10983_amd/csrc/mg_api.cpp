@@ -19,6 +19,7 @@
 #include "flat_row.h"
 #include "kernels.h"
 #include "tail.h"
+#include "var_row.h"
 #include "visit.h"
 
 #include <type_traits>
@@ -397,6 +398,8 @@ mg_status smooth_level(mg_ctx* c, int l, bool from_zero, const T* pro_e = nullpt
     const int v = (int)L.a.size();
     // the last two steps of the pass run as one two-step kernel where it exists
     const bool pairs = c->use_pairs && L.x[2] != nullptr && !c->var;
+    // 19-point: the last two Chebyshev steps of the pass run as one kernel
+    const bool vpairs = c->use_pairs && c->var && cheb && L.x[2] != nullptr;
     bool prev_b = false;  // x_{k-1} is the pointwise first step c0 D^-1 b, formed by the next kernel
     bool prev_p = false;  // x_{k-1} is x_old + P pro_e (x_old in bufs[prev]), formed by the next kernel
     for (int k = 0; k < v; ++k) {
@@ -425,10 +428,13 @@ mg_status smooth_level(mg_ctx* c, int l, bool from_zero, const T* pro_e = nullpt
         const bool triple3 = k == 0 && !from_zero && cheb && v == 3 && c->use_pairs && !c->var &&
                              triple_kernels_apply(L.n, sizeof(T));
         const bool pair = pairs && rem >= 2 && rem % 2 == 0 && !(k == 0 && from_zero) && !(need_y1 && has_prev);
+        const bool vpair = vpairs && rem == 2 && !(k == 0 && from_zero);
         // pro_e: a pair starts the pass (split rows), or a step that prolongs on the fly (rows over 2 KB)
         const bool pro_step = k == 0 && pro_e != nullptr && !pair;
         if (pro_step && !post_step_fused(c, l, sizeof(T))) return MG_ERR_INVALID;
-        const int kind = triple3 ? MG_TIME_TRIPLE : (pair || triple) && !fromb ? MG_TIME_PAIR : MG_TIME_STEP;
+        const int kind = triple3                               ? MG_TIME_TRIPLE
+                         : (pair || triple || vpair) && !fromb ? MG_TIME_PAIR
+                                                               : MG_TIME_STEP;
         hipEvent_t ev0, ev1;
         mg_status st = time_events(c, fine, kind, &ev0, &ev1);
         if (st != MG_OK) return st;
@@ -510,6 +516,15 @@ mg_status smooth_level(mg_ctx* c, int l, bool from_zero, const T* pro_e = nullpt
             prev = mid;
             cur = out;
             k = 2;  // three steps done
+        } else if (vpair) {  // x, x_prev -> y2 in the third buffer (the kernel reads both on halo rows)
+            const T* xp = has_prev ? bufs[prev] : nullptr;
+            const int out = has_prev ? 3 - cur - prev : other(cur);
+            HIPCHK(c, launch_var_smooth_pair<T, T>(L.n, L.ih2, op.coeff, bufs[cur], xp, (const T*)L.b, bufs[out],
+                                                   L.a[k], L.c[k], L.a[k + 1], L.c[k + 1], c->stream, ev0, ev1));
+            bytes = (3.0 + (xp ? 1.0 : 0.0)) * fbytes + cbytes;  // x, [x_prev], b, C; y2
+            prev = -1;
+            cur = out;
+            ++k;  // the pair's second step
         } else if (pair) {
             const T* xp = has_prev ? bufs[prev] : nullptr;
             int out, mid = -1;
@@ -903,8 +918,10 @@ static mg_status create_impl(mg_ctx* c, const void* coeff, int coeff_dtype, cons
         mg_status st;
         if ((st = dalloc(c, &L.x[0], L.N * Tsz)) != MG_OK) return st;
         if ((st = dalloc(c, &L.x[1], L.N * Tsz)) != MG_OK) return st;
-        if (!c->var && c->use_pairs && pair_kernels_apply(L.n, Tsz) && (st = dalloc(c, &L.x[2], L.N * Tsz)) != MG_OK)
-            return st;
+        const bool third = c->use_pairs && (c->var ? var_pair_applies(L.n, Tsz) && p.smoother == MG_CHEBYSHEV &&
+                                                         p.cheb_degree >= 2
+                                                   : pair_kernels_apply(L.n, Tsz));
+        if (third && (st = dalloc(c, &L.x[2], L.N * Tsz)) != MG_OK) return st;
         if ((st = dalloc(c, &L.b, L.N * Tsz)) != MG_OK) return st;
     }
     const size_t N0 = c->lev[0].N;

@@ -429,6 +429,112 @@ __global__ __launch_bounds__(64 * W) void k_var_smooth_lds(int n, T ih2, const T
     }
 }
 
+// Two consecutive smoothing steps in one pass:
+//   y1 = x  + a1 (x - xp) + c1 D^-1 (b - M x)    (xp = 0 without PREV1)
+//   y2 = y1 + a2 (y1 - x) + c2 D^-1 (b - M y1)
+// Only y2 is written, and C is read once for both steps.  A block of NW waves
+// owns rows y0-1 .. y0+W (W = NW - 2 outputs): every wave forms y1 on its row
+// (x rows through Ring) one plane ahead of the second step and publishes it
+// into a second ring of four planes, from which waves 1 .. W gather the 3 x 3
+// (y, z) neighbourhood of their y1 row; the two edge waves only supply the
+// halo rows of y1.  The second step's z rows of C^{zz}, C^{xz}, C^{yz} come
+// from the first step's queue one plane earlier.  Two barriers per plane.
+// Each step is the arithmetic of k_var_smooth_row, so the result is bitwise
+// that of two single steps.
+template <typename T, typename TC, int VEC, int NW, bool PREV1, bool ZQ>
+__global__ __launch_bounds__(64 * NW) void k_var_smooth2_lds(int n, T ih2, const TC* __restrict__ C,
+                                                             const T* __restrict__ x, const T* __restrict__ xp,
+                                                             const T* __restrict__ b, T* __restrict__ y2, T a1,
+                                                             T c1, T a2, T c2, int nz, int nyb) {
+    constexpr int NR = 64 * VEC;
+    constexpr size_t N = (size_t)NR * NR * NR;
+    constexpr int W = NW - 2;
+    __shared__ T ring[4][NW + 2][NR];  // x rows y0-2 .. y0+W+1
+    __shared__ T yr[4][NW][NR];        // y1 rows y0-1 .. y0+W
+    const RowGrid g{NR, NR - 1};
+    const int lb = xcd_logical(blockIdx.x, gridDim.x);
+    const int yb = lb % nyb, zc = lb / nyb;
+    const int w = wave_id();
+    const int yr0 = yb * W - 1, y = yr0 + w;  // rows outside [0, n) wrap in g.row
+    const int z0 = zc * nz;
+    const int lane = threadIdx.x & 63;
+    const size_t off = (size_t)lane * VEC;
+    const bool lo = w == 0, hi = w == NW - 1, outw = !lo && !hi && y < n;  // the last block is ragged
+    const int yh = lo ? yr0 - 1 : yr0 + NW;
+    const Ring<T, VEC, NW> rg{ring, w, lo ? 0 : NW + 1, lane, lo || hi};
+    const PlainRows<T, T, VEC> src{x};
+    T U[3][3][VEC], hr[VEC], xn[VEC], hn[VEC];
+    int z1 = z0 - 1;  // plane of the first step; the second step is at z1 - 1
+    ring_start<T, VEC, NW>(rg, U, hr, src, g, y, yh, z1, off);
+    CQueue<T, VEC> q;     // planes z1-1, z1, z1+1
+    CQueue<T, VEC> q2{};  // planes z1-2, z1-1, z1 (the second step's)
+    cq_load<ZQ, T, TC, VEC>(q, 0, C, N, g, y, z1 - 1, off);
+    cq_load<ZQ, T, TC, VEC>(q, 1, C, N, g, y, z1, off);
+    T bo[VEC] = {};  // b at z1 - 1
+    for (int j = 0; j < nz + 2; ++j, ++z1) {
+        const bool more = j + 1 < nz + 2;
+        if (more) {  // the plane after next, one iteration early
+            src.load(xn, g.row(y, z1 + 2) + off);
+            if (rg.edge) src.load(hn, g.row(yh, z1 + 2) + off);
+        }
+        ring_publish<T, VEC, NW>(rg, U, hr, z1);
+        cq_load<ZQ, T, TC, VEC>(q, 2, C, N, g, y, z1 + 1, off);
+        T bb[VEC], pp[VEC], Mu[VEC], D[VEC], o[VEC];
+        const size_t r = g.row(y, z1) + off;
+        ldrow<T, VEC>(bb, b + r);
+        if constexpr (PREV1) ldrow<T, VEC>(pp, xp + r);
+        __syncthreads();
+        ring_gather<T, VEC, NW>(rg, U, z1);
+        var19_row<ZQ, T, TC, VEC>(U, q, C, N, g, y, z1, off, ih2, Mu, D);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const T xc = U[1][1][e];
+            const T xpe = PREV1 ? pp[e] : T(0);
+            o[e] = xc + a1 * (xc - xpe) + c1 * (bb[e] - Mu[e]) / D[e];
+        }
+        lds_strow<T, VEC>(yr[z1 & 3][w], lane, o);
+        if constexpr (ZQ) {  // the second step's queue: planes z1-2 (kept), z1-1, z1
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                q2.zz[1][e] = q.zz[0][e];
+                q2.zz[2][e] = q.zz[1][e];
+                q2.xz[1][e] = q.xz[0][e];
+                q2.xz[2][e] = q.xz[1][e];
+                q2.yz[1][e] = q.yz[0][e];
+                q2.yz[2][e] = q.yz[1][e];
+            }
+        }
+        __syncthreads();
+        if (j >= 2 && outw) {  // second step at z2 = z1 - 1: y1 planes z1-2 .. z1
+            const int z2 = z1 - 1;
+            T Y[3][3][VEC], M2[VEC], D2[VEC], o2[VEC];
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dz = 0; dz < 3; ++dz) lds_ldrow<T, VEC>(Y[dy][dz], yr[(z2 - 1 + dz) & 3][w - 1 + dy], lane);
+            var19_row<ZQ, T, TC, VEC>(Y, q2, C, N, g, y, z2, off, ih2, M2, D2);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                const T yc = Y[1][1][e];
+                o2[e] = yc + a2 * (yc - U[1][0][e]) + c2 * (bo[e] - M2[e]) / D2[e];
+            }
+            strow<T, VEC>(y2 + g.row(y, z2) + off, o2);
+        }
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) bo[e] = bb[e];
+        if constexpr (ZQ) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                q2.zz[0][e] = q.zz[0][e];
+                q2.xz[0][e] = q.xz[0][e];
+                q2.yz[0][e] = q.yz[0][e];
+            }
+        }
+        if (more) ring_shift<T, VEC, NW>(rg, U, hr, xn, hn);
+        cq_shift<ZQ, T, VEC>(q);
+    }
+}
+
 // =====================================================================================
 // residual r = b - M x (scratch of the two-pass residual restriction) / apply
 // =====================================================================================
@@ -692,6 +798,44 @@ hipError_t launch_var_smooth_row(int n, double ih2, const TC* C, const T* x, con
     return hipGetLastError();
 }
 
+// The two-step kernel: float rows of up to 1 KB (n = 128, 256), blocks of
+// kVarPairWaves waves (kVarPairWaves - 2 output rows; a last block that
+// overhangs the grid is ragged), chunks of at most kVarPairNz planes giving
+// at least 256 blocks.  At 256^3 (A/B, mixed moving mesh): 8-wave blocks
+// with 16-plane chunks 246 us per pair, 10 waves 207 us, 12 waves 236 us,
+// 10 waves with 32-plane chunks 200 us; four waves per SIMD forced (two
+// blocks per CU) spilled and took 483 us.
+constexpr int kVarPairWaves = 10;
+constexpr int kVarPairNz = 32;
+bool var_pair_applies(int n, size_t elem) {
+    return kVarLds && elem == sizeof(float) && n >= 128 && (size_t)n * elem <= 1024;
+}
+
+template <typename T, typename TC>
+hipError_t launch_var_smooth_pair(int n, double ih2, const TC* C, const T* x, const T* xp, const T* b, T* y2,
+                                  double a1, double c1, double a2, double c2, hipStream_t s, hipEvent_t ev0,
+                                  hipEvent_t ev1) {
+    if (!var_pair_applies(n, sizeof(T)) || x == nullptr || y2 == x || y2 == xp) return hipErrorInvalidValue;
+    constexpr int NW = kVarPairWaves, W = NW - 2;
+    const int nyb = (n + W - 1) / W;
+    int nz = kVarPairNz;
+    while (nz > 4 && nyb * (n / nz) < 256) nz >>= 1;
+    const int blocks = nyb * (n / nz);
+    DISPATCH_VEC(n, {
+        if constexpr (sizeof(T) == sizeof(float) && VEC >= 2 && VEC <= 4) {
+            if (xp)
+                MG_LAUNCH((k_var_smooth2_lds<T, TC, VEC, NW, true, true>), dim3(blocks), dim3(64 * NW), s, ev0, ev1,
+                          n, (T)ih2, C, x, xp, b, y2, (T)a1, (T)c1, (T)a2, (T)c2, nz, nyb);
+            else
+                MG_LAUNCH((k_var_smooth2_lds<T, TC, VEC, NW, false, true>), dim3(blocks), dim3(64 * NW), s, ev0,
+                          ev1, n, (T)ih2, C, x, xp, b, y2, (T)a1, (T)c1, (T)a2, (T)c2, nz, nyb);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    })
+    return hipGetLastError();
+}
+
 template <typename T, typename TC>
 hipError_t launch_var_resid_row(int n, double ih2, const TC* C, const T* x, const T* b, T* out, hipStream_t s,
                                 hipEvent_t ev0, hipEvent_t ev1) {
@@ -746,6 +890,9 @@ hipError_t launch_var_outer_row(int n, double ih2, const TC* C, const double* ph
 #define INST_VAR(T, TC)                                                                                            \
     template hipError_t launch_var_smooth_row<T, TC>(int, double, const TC*, const T*, const T*, const T*, T*,     \
                                                      double, double, hipStream_t, hipEvent_t, hipEvent_t);         \
+    template hipError_t launch_var_smooth_pair<T, TC>(int, double, const TC*, const T*, const T*, const T*, T*,    \
+                                                      double, double, double, double, hipStream_t, hipEvent_t,     \
+                                                      hipEvent_t);                                                 \
     template hipError_t launch_var_resid_row<T, TC>(int, double, const TC*, const T*, const T*, T*, hipStream_t,   \
                                                     hipEvent_t, hipEvent_t);
 INST_VAR(float, float)

@@ -481,6 +481,30 @@ def test_two_step_kernel_matches_single_steps(mgpu, n, prec, degree, smoother):
     assert torch.equal(ps, pf)
 
 
+@pytest.mark.parametrize("n", [128, 256])
+@pytest.mark.parametrize("degree", [2, 3, 4])
+def test_19_point_pair_matches_single_steps(mgpu, n, degree):
+    """The 19-point two-step kernel (float rows of up to 1 KB: the last two
+    Chebyshev steps of every pass on those levels) forms each step as the
+    single-step kernel: moving-mesh mixed solves (float32 coefficients from the
+    GPU geometry) agree bitwise with MG_OPT_NO_PAIR, cycle by cycle."""
+    psi = PSI_SCALE[str(n)] * psi_unit(n)
+    C32, sg = mgpu.geometry(dev(psi), dtype=torch.float32)
+    g = dev(moving_mesh_field(n, 0))
+    b = sg * (g - (g * sg).sum() / sg.sum())
+    kw = dict(levels=int(math.log2(n)) - 1, degree=degree, coeff=C32, precision="mixed")
+    single = mgpu.Multigrid(n, options=mgpu._lib.MG_OPT_NO_PAIR, **kw)
+    fused = mgpu.Multigrid(n, **kw)
+    out = []
+    for mg in (single, fused):
+        phi, info = mg.solve(b, tol=1e-10, max_cycles=8, raise_on_error=False)
+        out.append((phi, info))
+    (ps, is_), (pf, if_) = out
+    print(f"19-point n={n} degree {degree}: {if_.cycles} cycles, rel_res {if_.rel_res:.2e}", flush=True)
+    assert is_.cycles == if_.cycles and is_.history == if_.history
+    assert torch.equal(ps, pf)
+
+
 @pytest.mark.parametrize("n,levels", [(32, 4), (32, 2), (64, 5), (64, 3), (128, 6), (256, 7)])
 @pytest.mark.parametrize("degree", [1, 2, 3, 4])
 def test_level_visit_matches_unfused(mgpu, n, levels, degree):
