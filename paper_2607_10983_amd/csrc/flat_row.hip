@@ -1565,41 +1565,60 @@ __global__ __launch_bounds__(kBlock) void k_rr_row(int n, T ih2, const T* __rest
 }
 
 // The same residual + restriction with the fine rows shared through LDS
-// (unsplit rows, VEC >= 2): a block of W + 1 waves owns coarse rows
-// Y0 .. Y0+W-1.  Wave w loads fine rows fa = 2Y-1 and fb = 2Y (Y = Y0 + w;
-// wave W: rows 2Y0+2W-1 and 2Y0+2W, wave 0 also row 2Y0-2) one plane ahead
-// and publishes them, so each x and b row is read once per block and each
-// residual row is formed once (k_rr_row forms rows 2Y+-1 twice and reads x
-// rows 2.5 times).  Wave w < W combines r(2Y-1), r(2Y) with r(2Y+1) of wave
-// w + 1 (through LDS); wave W only forms r(2Y0+2W-1).  One barrier per plane:
-// the x plane and the shared residual row are double-buffered by plane
-// parity.  Same point formulas and the same fw3 order as k_rr_row, same bits.
-template <typename T, int VEC, int W>
-__global__ __launch_bounds__(64 * (W + 1)) void k_rr_lds(int n, T ih2, const T* __restrict__ x,
-                                                         const T* __restrict__ b, T* __restrict__ coarse, int nzc,
-                                                         int nyb) {
+// (VEC >= 2): a block of (W + 1) S waves owns coarse rows Y0 .. Y0+W-1.
+// Wave w (row slot wr = w / S, segment w mod S of S) loads fine rows
+// fa = 2Y-1 and fb = 2Y (Y = Y0 + wr; slot W: rows 2Y0+2W-1 and 2Y0+2W, slot
+// 0 also row 2Y0-2) one plane ahead and publishes them, so each x and b row
+// is read once per block and each residual row is formed once (k_rr_row
+// forms rows 2Y+-1 twice and reads x rows 2.5 times).  Slot wr < W combines
+// r(2Y-1), r(2Y) with r(2Y+1) of slot wr + 1 (through LDS); slot W only forms
+// r(2Y0+2W-1).  Split rows (S > 1) take the stencil's x-halo from the
+// neighbouring segment in LDS, and the full weighting in x of a segment's
+// first coarse point re-forms the previous segment's last y-weighted value
+// from the shared residual rows and the published last element of its
+// r(2Y).  One barrier per plane: the x plane, the shared residual row and
+// the edge values are double-buffered by plane parity.  Same point formulas
+// and the same fw3 order as k_rr_row, same bits.
+template <typename T, int VEC, int W, int S>
+__global__ __launch_bounds__(64 * (W + 1) * S) void k_rr_lds(int n, T ih2, const T* __restrict__ x,
+                                                             const T* __restrict__ b, T* __restrict__ coarse,
+                                                             int nzc, int nyb) {
 #pragma clang fp contract(off)  // full weighting in y, then x, then z, as fw3 rounds it
     static_assert(VEC >= 2, "two fine points per lane at least");
     constexpr int CV = VEC / 2;
-    constexpr int NR = 64 * VEC;
-    constexpr int nc = NR / 2;
-    __shared__ T xs[2][2 * W + 3][NR];  // fine rows 2Y0-2 .. 2Y0+2W of a plane
-    __shared__ T rs[2][W + 1][NR];      // r(2Y-1) of each wave
-    const RowGrid g{NR, NR - 1};
+    constexpr int NR = 64 * VEC;  // a segment
+    constexpr int NF = NR * S;    // a fine row
+    constexpr int nc = NF / 2;
+    __shared__ T xs[2][2 * W + 3][NF];  // fine rows 2Y0-2 .. 2Y0+2W of a plane
+    __shared__ T rs[2][W + 1][NF];      // r(2Y-1) of each row slot
+    __shared__ T eb[2][W + 1][S];       // last element of each segment of r(2Y)
+    const RowGrid g{NF, NF - 1};
     const RowGrid gc{nc, nc - 1};
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int yb = lb % nyb, zc = lb / nyb;
     const int lane = threadIdx.x & 63;
     const int w = wave_id();
-    const bool comb = w < W;
-    const int Y = yb * W + w;
+    const int wr = w / S, seg = w - wr * S;
+    const int ps = (seg + S - 1) % S, ns = (seg + 1) % S;  // neighbouring segments (periodic)
+    const bool comb = wr < W;
+    const int Y = yb * W + wr;
     const int fa = 2 * Y - 1, fb = 2 * Y;  // rows outside [0, n) wrap in g.row
-    const int ia = 2 * w + 1, ib = 2 * w + 2;  // their rows in xs
-    const size_t off = (size_t)lane * VEC;
+    const int ia = 2 * wr + 1, ib = 2 * wr + 2;  // their rows in xs
+    const size_t off = (size_t)seg * NR + (size_t)lane * VEC;
+    const int so = seg * NR;  // the segment in an LDS row
     const int Z0 = zc * nzc;
     const int nf = 2 * nzc + 1;
     int z = 2 * Z0 - 1;
-    // x rows at z-1, z, z+1 and the prefetched z+2 (a: fa, b: fb); wave 0's row
+    // x-halo of a row segment (lane 0: the previous segment's last element,
+    // lane 63: the next segment's first)
+    auto halo = [&](const T* row) -> T {
+        if constexpr (S == 1) {
+            return T(0);
+        } else {
+            return lane < 32 ? lds_elem<T, VEC>(row + ps * NR, NR - 1) : lds_elem<T, VEC>(row + ns * NR, 0);
+        }
+    };
+    // x rows at z-1, z, z+1 and the prefetched z+2 (a: fa, b: fb); slot 0's row
     // 2Y0-2 at z+1 (tp, published next) and the prefetched one (tq)
     T am[VEC], ac[VEC], ap[VEC], an[VEC], bm[VEC], bc[VEC], bp[VEC], bn[VEC], tp[VEC] = {}, tq[VEC] = {};
     // b rows at z and the prefetched z+1
@@ -1612,13 +1631,13 @@ __global__ __launch_bounds__(64 * (W + 1)) void k_rr_lds(int n, T ih2, const T* 
     ldrow<T, VEC>(bp, x + g.row(fb, z + 1) + off);
     ldrow<T, VEC>(ga, b + g.row(fa, z) + off);
     if (comb) ldrow<T, VEC>(gb, b + g.row(fb, z) + off);
-    if (w == 0) {
+    if (wr == 0) {
         ldrow<T, VEC>(tq, x + g.row(fa - 1, z) + off);
         ldrow<T, VEC>(tp, x + g.row(fa - 1, z + 1) + off);
     }
-    lds_strow<T, VEC>(xs[z & 1][ia], lane, ac);
-    lds_strow<T, VEC>(xs[z & 1][ib], lane, bc);
-    if (w == 0) lds_strow<T, VEC>(xs[z & 1][0], lane, tq);
+    lds_strow<T, VEC>(xs[z & 1][ia] + so, lane, ac);
+    lds_strow<T, VEC>(xs[z & 1][ib] + so, lane, bc);
+    if (wr == 0) lds_strow<T, VEC>(xs[z & 1][0] + so, lane, tq);
     __syncthreads();
     T acc[CV];
     for (int k = 0; k < nf; ++k, ++z) {
@@ -1629,36 +1648,45 @@ __global__ __launch_bounds__(64 * (W + 1)) void k_rr_lds(int n, T ih2, const T* 
             ldrow<T, VEC>(bn, x + g.row(fb, z + 2) + off);
             ldrow<T, VEC>(gan, b + g.row(fa, z + 1) + off);
             if (comb) ldrow<T, VEC>(gbn, b + g.row(fb, z + 1) + off);
-            if (w == 0) ldrow<T, VEC>(tq, x + g.row(fa - 1, z + 2) + off);
+            if (wr == 0) ldrow<T, VEC>(tq, x + g.row(fa - 1, z + 2) + off);
             // publish plane z + 1 (its slot was last read before the previous barrier)
-            lds_strow<T, VEC>(xs[cb ^ 1][ia], lane, ap);
-            lds_strow<T, VEC>(xs[cb ^ 1][ib], lane, bp);
-            if (w == 0) lds_strow<T, VEC>(xs[cb ^ 1][0], lane, tp);
+            lds_strow<T, VEC>(xs[cb ^ 1][ia] + so, lane, ap);
+            lds_strow<T, VEC>(xs[cb ^ 1][ib] + so, lane, bp);
+            if (wr == 0) lds_strow<T, VEC>(xs[cb ^ 1][0] + so, lane, tp);
         }
         // r(fa) = b - M x: y-neighbours row fa-1 (xs) and fb (own)
         T ym[VEC], Ma[VEC], ra[VEC];
-        lds_ldrow<T, VEC>(ym, xs[cb][ia - 1], lane);
-        flat7_row_seg<T, VEC, 1>(ac, ym, bc, am, ap, ih2, Ma, T(0));
+        lds_ldrow<T, VEC>(ym, xs[cb][ia - 1] + so, lane);
+        flat7_row_seg<T, VEC, S>(ac, ym, bc, am, ap, ih2, Ma, halo(xs[cb][ia]));
 #pragma unroll
         for (int e = 0; e < VEC; ++e) ra[e] = ga[e] - Ma[e];
-        lds_strow<T, VEC>(rs[cb][w], lane, ra);
+        lds_strow<T, VEC>(rs[cb][wr] + so, lane, ra);
         T rb[VEC];
         if (comb) {  // r(fb): y-neighbours fa (own) and fb+1 (xs)
             T yp[VEC], Mb[VEC];
-            lds_ldrow<T, VEC>(yp, xs[cb][ib + 1], lane);
-            flat7_row_seg<T, VEC, 1>(bc, ac, yp, bm, bp, ih2, Mb, T(0));
+            lds_ldrow<T, VEC>(yp, xs[cb][ib + 1] + so, lane);
+            flat7_row_seg<T, VEC, S>(bc, ac, yp, bm, bp, ih2, Mb, halo(xs[cb][ib]));
 #pragma unroll
             for (int e = 0; e < VEC; ++e) rb[e] = gb[e] - Mb[e];
+            if constexpr (S > 1) {
+                if (lane == 63) eb[cb][wr][seg] = rb[VEC - 1];
+            }
         }
         __syncthreads();
         if (comb) {
             T rc[VEC], s[VEC];
-            lds_ldrow<T, VEC>(rc, rs[cb][w + 1], lane);
+            lds_ldrow<T, VEC>(rc, rs[cb][wr + 1] + so, lane);
 #pragma unroll
             for (int e = 0; e < VEC; ++e) s[e] = fw3<T>(ra[e], rb[e], rc[e]);
-            // x: coarse element q <-> fine 2q; needs fine 2q-1 (previous lane's last for q = 0)
+            // x: coarse element q <-> fine 2q; needs fine 2q-1 (previous lane's last for q = 0;
+            // for lane 0 of a split row, the previous segment's last, formed again from LDS)
+            T lft = lane_rot(s[VEC - 1], -1);
+            if constexpr (S > 1) {
+                if (lane == 0)
+                    lft = fw3<T>(lds_elem<T, VEC>(rs[cb][wr] + ps * NR, NR - 1), eb[cb][wr][ps],
+                                 lds_elem<T, VEC>(rs[cb][wr + 1] + ps * NR, NR - 1));
+            }
             T sx[CV];
-            const T lft = lane_rot(s[VEC - 1], -1);
 #pragma unroll
             for (int q = 0; q < CV; ++q) {
                 const T l = q > 0 ? s[2 * q - 1] : lft;
@@ -1676,7 +1704,7 @@ __global__ __launch_bounds__(64 * (W + 1)) void k_rr_lds(int n, T ih2, const T* 
                 const int Zc = (z - 1) >> 1;
 #pragma unroll
                 for (int q = 0; q < CV; ++q) acc[q] += T(0.25) * sx[q];
-                strow<T, CV>(coarse + gc.row(Y, Zc) + (size_t)lane * CV, acc);
+                strow<T, CV>(coarse + gc.row(Y, Zc) + (size_t)seg * (NR / 2) + (size_t)lane * CV, acc);
 #pragma unroll
                 for (int q = 0; q < CV; ++q) acc[q] = T(0.25) * sx[q];
             }
@@ -1690,7 +1718,7 @@ __global__ __launch_bounds__(64 * (W + 1)) void k_rr_lds(int n, T ih2, const T* 
             copyrow(bp, bn);
             copyrow(ga, gan);
             if (comb) copyrow(gb, gbn);
-            if (w == 0) copyrow(tp, tq);
+            if (wr == 0) copyrow(tp, tq);
         }
     }
 }
@@ -2410,33 +2438,46 @@ hipError_t launch_outer_row(int n, double ih2, const double* phi_in, const TE* e
     return hipGetLastError();
 }
 
-// Fine rows of kRrLdsRowBytes (512^3 float, 256^3 double) take the LDS kernel,
-// kRrLdsRows coarse rows per block.
+// Fine rows of 2 KB (512^3 float, 256^3 double) take the LDS kernel with 8
+// coarse rows per block; rows of 4 KB (1024^3 float, 512^3 double) with 4
+// coarse rows of two 2 KB segments (10 waves, 128 KB of LDS).
 constexpr bool kRrLds = true;
-constexpr size_t kRrLdsRowBytes = 2048;
-constexpr int kRrLdsRows = 8;
-inline bool rr_lds_applies(int n, size_t elem) { return kRrLds && (size_t)n * elem == kRrLdsRowBytes; }
+constexpr size_t kRrLdsSegBytes = 2048;
+inline int rr_lds_segments(int n, size_t elem) {
+    const size_t row = (size_t)n * elem;
+    return kRrLds && (row == kRrLdsSegBytes || row == 2 * kRrLdsSegBytes) ? (int)(row / kRrLdsSegBytes) : 0;
+}
+constexpr int rr_lds_rows(int S) { return S == 1 ? 8 : 4; }
+
+template <typename T, int S>
+hipError_t launch_rr_lds(int n, double ih2, const T* x, const T* b, T* coarse, hipStream_t s, hipEvent_t ev0,
+                         hipEvent_t ev1) {
+    constexpr int W = rr_lds_rows(S);
+    const int nc = n / 2;
+    const int nyb = nc / W;
+    int nzc = nc;
+    while (nzc > 4 && nyb * (nc / nzc) < kRrTarget) nzc >>= 1;
+    const int blocks = nyb * (nc / nzc);
+    DISPATCH_SEG(n, S, {
+        if constexpr (64 * VEC * sizeof(T) == kRrLdsSegBytes) {
+            MG_LAUNCH((k_rr_lds<T, VEC, W, S>), dim3(blocks), dim3(64 * (W + 1) * S), s, ev0, ev1, n, (T)ih2, x, b,
+                      coarse, nzc, nyb);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    })
+    return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_rr_row(int n, double ih2, const T* x, const T* b, T* coarse, hipStream_t s, hipEvent_t ev0,
                          hipEvent_t ev1) {
     const int nc = n / 2;
     int nzc, nyb, blocks;
-    if (rr_lds_applies(n, sizeof(T))) {
-        constexpr int W = kRrLdsRows;
-        nyb = nc / W;
-        nzc = nc;
-        while (nzc > 4 && nyb * (nc / nzc) < kRrTarget) nzc >>= 1;
-        blocks = nyb * (nc / nzc);
-        DISPATCH_VEC(n, {
-            if constexpr (64 * VEC * sizeof(T) == kRrLdsRowBytes) {
-                MG_LAUNCH((k_rr_lds<T, VEC, W>), dim3(blocks), dim3(64 * (W + 1)), s, ev0, ev1, n, (T)ih2, x, b,
-                          coarse, nzc, nyb);
-            } else {
-                return hipErrorInvalidValue;
-            }
-        })
-        return hipGetLastError();
+    switch (rr_lds_segments(n, sizeof(T))) {
+        case 1: return launch_rr_lds<T, 1>(n, ih2, x, b, coarse, s, ev0, ev1);
+        case 2: return launch_rr_lds<T, 2>(n, ih2, x, b, coarse, s, ev0, ev1);
+        default: break;
     }
     // small levels are latency chains: chunks of 2 coarse planes (128^3: 7.7 -> 5.7 us,
     // 64^3: 6.8 -> 4.8 us per launch)
