@@ -45,15 +45,15 @@ HBM_PEAK_GBPS = 8000.0
 # is the one the counters were taken on.  Keys are the first name of each
 # kind's label (kernel_name).
 TRAFFIC = {
-    "device_code_sha256": "e149ac085bc5783ea82aeca18837be13dc423d055496993fae93aba8b2cb8eed",
+    "device_code_sha256": "d54b7c1db8381bea087ed9da4386c84b2e3358a5ea13b709a8386296b1ca3cd6",
     "bytes_per_launch": {
         # the benchmark step: outer (with the first-cycle variant), pass from
         # zero (b -> x3), prolongation + three steps, residual + restriction
-        (256, 3): {"k_outer_lds": 536997728, "k_smooth2_lds": 152094815, "k_smooth3p_lds": 238171692,
-                   "k_rr_row": 159438088},
-        # the 512^3 leg: step from b, the three pairs, outer, residual + restriction
-        (512, 4): {"k_smooth_row": 1137134872, "k_smooth2_lds": 2278263824, "k_outer_lds": 4445412712,
-                   "k_rr_row": 1406540835},
+        (256, 3): {"k_outer_lds": 536855684, "k_smooth2_lds": 151742958, "k_smooth3p_lds": 238153913,
+                   "k_rr_row": 159429926},
+        # the 512^3 leg: step from b, the three pairs, outer, residual + restriction (k_rr_lds)
+        (512, 4): {"k_smooth_row": 1137164769, "k_smooth2_lds": 2278180068, "k_outer_lds": 4445624636,
+                   "k_rr_row": 1196833543},
     },
 }
 
