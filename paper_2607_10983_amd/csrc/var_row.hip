@@ -27,6 +27,11 @@ namespace {
 constexpr int kWaves = 4;
 constexpr int kBlock = 64 * kWaves;
 constexpr bool kVarLds = true;  // smoothing steps and the residual share the iterate's rows through LDS (n >= 128)
+// The LDS kernels load the plane's C rows (CRows) before its barrier, so their
+// latency overlaps the wait, at the cost of registers live across it (float
+// smoothing step 3 instead of 4 waves per SIMD).  256^3 moving mesh: single
+// step 131 -> 127 us mixed, 319 -> 308 us FP64; float residual 77 -> 76 us.
+constexpr bool kVarCrowsEarly = true;
 
 // coefficient row in compute precision T
 template <typename T, typename TC, int VEC>
@@ -77,16 +82,37 @@ __device__ __forceinline__ void cq_shift(CQueue<T, VEC>& q) {
     }
 }
 
+// The rows of C in the plane of row (y, z) that the 19-point formula reads
+// besides the z queue: C^{xx} at y; C^{yy} and C^{xy} at y, y + 1, y - 1;
+// C^{yz} at y + 1, y - 1 (converted to T).  Loaded ahead of the plane's
+// barrier, their latency overlaps the wait.
+template <typename T, int VEC>
+struct CRows {
+    T xx[VEC], yy[VEC], yyp[VEC], yym[VEC], xy[VEC], xyp[VEC], xym[VEC], yzp[VEC], yzm[VEC];
+};
+template <typename T, typename TC, int VEC>
+__device__ __forceinline__ void cr_load(CRows<T, VEC>& c, const TC* __restrict__ C, size_t N, const RowGrid& g,
+                                        int y, int z, size_t off) {
+    const size_t r0 = g.row(y, z) + off, rp = g.row(y + 1, z) + off, rm = g.row(y - 1, z) + off;
+    ldcrow<T, TC, VEC>(c.xx, C + r0);
+    ldcrow<T, TC, VEC>(c.yy, C + N + r0);
+    ldcrow<T, TC, VEC>(c.yyp, C + N + rp);
+    ldcrow<T, TC, VEC>(c.yym, C + N + rm);
+    ldcrow<T, TC, VEC>(c.xy, C + 3 * N + r0);
+    ldcrow<T, TC, VEC>(c.xyp, C + 3 * N + rp);
+    ldcrow<T, TC, VEC>(c.xym, C + 3 * N + rm);
+    ldcrow<T, TC, VEC>(c.yzp, C + 5 * N + rp);
+    ldcrow<T, TC, VEC>(c.yzm, C + 5 * N + rm);
+}
+
 // U[dy + 1][dz + 1] = iterate rows (y + dy, z + dz), q the z queue of the row
-// (unused without ZQ); returns M u and D of row (y, z).
+// (unused without ZQ), cr the plane's other C rows; returns M u and D of row (y, z).
 template <bool ZQ, typename T, typename TC, int VEC>
-__device__ __forceinline__ void var19_row(const T (&U)[3][3][VEC], const CQueue<T, VEC>& q,
-                                          const TC* __restrict__ C, size_t N, const RowGrid& g, int y, int z,
-                                          size_t off, T ih2, T (&Mu)[VEC], T (&D)[VEC]) {
-    const TC* Cxx = C;
-    const TC* Cyy = C + N;
+__device__ __forceinline__ void var19_row_c(const T (&U)[3][3][VEC], const CQueue<T, VEC>& q,
+                                            const CRows<T, VEC>& cr, const TC* __restrict__ C, size_t N,
+                                            const RowGrid& g, int y, int z, size_t off, T ih2, T (&Mu)[VEC],
+                                            T (&D)[VEC]) {
     const TC* Czz = C + 2 * N;
-    const TC* Cxy = C + 3 * N;
     const TC* Cxz = C + 4 * N;
     const TC* Cyz = C + 5 * N;
     const size_t r0 = g.row(y, z) + off;
@@ -109,8 +135,8 @@ __device__ __forceinline__ void var19_row(const T (&U)[3][3][VEC], const CQueue<
     T up[VEC], um[VEC];
     shifts<T, VEC>(U[1][1], up, um);
     {   // x faces
-        T c[VEC], cp[VEC], cm[VEC];
-        ldcrow<T, TC, VEC>(c, Cxx + r0);
+        const T(&c)[VEC] = cr.xx;
+        T cp[VEC], cm[VEC];
         shifts<T, VEC>(c, cp, cm);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
@@ -121,10 +147,9 @@ __device__ __forceinline__ void var19_row(const T (&U)[3][3][VEC], const CQueue<
         }
     }
     {   // y faces
-        T c[VEC], cp[VEC], cm[VEC];
-        ldcrow<T, TC, VEC>(c, Cyy + r0);
-        ldcrow<T, TC, VEC>(cp, Cyy + g.row(y + 1, z) + off);
-        ldcrow<T, TC, VEC>(cm, Cyy + g.row(y - 1, z) + off);
+        const T(&c)[VEC] = cr.yy;
+        const T(&cp)[VEC] = cr.yyp;
+        const T(&cm)[VEC] = cr.yym;
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
             const T uc = U[1][1][e];
@@ -146,11 +171,11 @@ __device__ __forceinline__ void var19_row(const T (&U)[3][3][VEC], const CQueue<
         }
     }
     {   // pairs (x,y) and (y,x): C^{xy} at x+-1 (row y) and at y+-1
-        T c[VEC], cxp[VEC], cxm[VEC], cyp[VEC], cym[VEC];
-        ldcrow<T, TC, VEC>(c, Cxy + r0);
+        const T(&c)[VEC] = cr.xy;
+        T cxp[VEC], cxm[VEC];
         shifts<T, VEC>(c, cxp, cxm);
-        ldcrow<T, TC, VEC>(cyp, Cxy + g.row(y + 1, z) + off);
-        ldcrow<T, TC, VEC>(cym, Cxy + g.row(y - 1, z) + off);
+        const T(&cyp)[VEC] = cr.xyp;
+        const T(&cym)[VEC] = cr.xym;
         T ypp[VEC], ypm[VEC], ymp[VEC], ymm[VEC];  // u(y+1, x+-1), u(y-1, x+-1)
         shifts<T, VEC>(U[2][1], ypp, ypm);
         shifts<T, VEC>(U[0][1], ymp, ymm);
@@ -176,9 +201,8 @@ __device__ __forceinline__ void var19_row(const T (&U)[3][3][VEC], const CQueue<
         }
     }
     {   // pairs (y,z) and (z,y)
-        T cyp[VEC], cym[VEC];
-        ldcrow<T, TC, VEC>(cyp, Cyz + g.row(y + 1, z) + off);
-        ldcrow<T, TC, VEC>(cym, Cyz + g.row(y - 1, z) + off);
+        const T(&cyp)[VEC] = cr.yzp;
+        const T(&cym)[VEC] = cr.yzm;
         const T(&czp)[VEC] = yz[2];
         const T(&czm)[VEC] = yz[0];
 #pragma unroll
@@ -193,6 +217,16 @@ __device__ __forceinline__ void var19_row(const T (&U)[3][3][VEC], const CQueue<
         Mu[e] = (acc[e] + T(0.25) * cross[e]) * ih2;
         D[e] = -dsum[e] * ih2;
     }
+}
+
+// The same with the plane's C rows loaded here.
+template <bool ZQ, typename T, typename TC, int VEC>
+__device__ __forceinline__ void var19_row(const T (&U)[3][3][VEC], const CQueue<T, VEC>& q,
+                                          const TC* __restrict__ C, size_t N, const RowGrid& g, int y, int z,
+                                          size_t off, T ih2, T (&Mu)[VEC], T (&D)[VEC]) {
+    CRows<T, VEC> cr;
+    cr_load<T, TC, VEC>(cr, C, N, g, y, z, off);
+    var19_row_c<ZQ, T, TC, VEC>(U, q, cr, C, N, g, y, z, off, ih2, Mu, D);
 }
 
 // diagonal only (first smoothing step from zero)
@@ -410,13 +444,16 @@ __global__ __launch_bounds__(64 * W) void k_var_smooth_lds(int n, T ih2, const T
         }
         ring_publish<T, VEC, W>(rg, U, hr, z);
         cq_load<ZQ, T, TC, VEC>(q, 2, C, N, g, y, z + 1, off);
+        CRows<T, VEC> cr;
+        if constexpr (kVarCrowsEarly) cr_load<T, TC, VEC>(cr, C, N, g, y, z, off);
         T bb[VEC], pp[VEC], Mu[VEC], D[VEC], o[VEC];
         const size_t r = g.row(y, z) + off;
         ldrow<T, VEC>(bb, b + r);
         if constexpr (PREV) ldrow<T, VEC>(pp, xprev + r);
         __syncthreads();
         ring_gather<T, VEC, W>(rg, U, z);
-        var19_row<ZQ, T, TC, VEC>(U, q, C, N, g, y, z, off, ih2, Mu, D);
+        if constexpr (!kVarCrowsEarly) cr_load<T, TC, VEC>(cr, C, N, g, y, z, off);
+        var19_row_c<ZQ, T, TC, VEC>(U, q, cr, C, N, g, y, z, off, ih2, Mu, D);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
             const T xc = U[1][1][e];
@@ -613,11 +650,16 @@ __global__ __launch_bounds__(64 * W) void k_var_resid_lds(int n, T ih2, const TC
         ring_publish<T, VEC, W>(rg, U, hr, z);
         cq_load<ZQ, T, TC, VEC>(q, 2, C, N, g, y, z + 1, off);
         const size_t r = g.row(y, z) + off;
+        // (the double residual measured slower with its C rows loaded early: 157 -> 161 us at 256^3)
+        constexpr bool EARLY = kVarCrowsEarly && sizeof(T) == sizeof(float);
+        CRows<T, VEC> cr;
+        if constexpr (EARLY) cr_load<T, TC, VEC>(cr, C, N, g, y, z, off);
         T bb[VEC], Mu[VEC], D[VEC], o[VEC];
         if constexpr (WITHB) ldrow<T, VEC>(bb, b + r);
         __syncthreads();
         ring_gather<T, VEC, W>(rg, U, z);
-        var19_row<ZQ, T, TC, VEC>(U, q, C, N, g, y, z, off, ih2, Mu, D);
+        if constexpr (!EARLY) cr_load<T, TC, VEC>(cr, C, N, g, y, z, off);
+        var19_row_c<ZQ, T, TC, VEC>(U, q, cr, C, N, g, y, z, off, ih2, Mu, D);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) o[e] = WITHB ? bb[e] - Mu[e] : Mu[e];
         strow<T, VEC>(out + r, o);
